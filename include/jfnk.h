@@ -1,0 +1,193 @@
+/*
+ * jfnk.h - C ABI of the MI355X (gfx950) symmetry-preserving Jacobian-free
+ * Newton-Krylov hot path for the dry nonhydrostatic model.
+ *
+ * Problem statement followed (section 2.5): find u with L(u) = f(u^n) where
+ * L(u) = 2u/dt - F(u) and f(u^n) = 2u^n/dt + F(u^n) (trapezoidal step, eq. 5),
+ * F the spatially discrete operator of equations 1-3 (eq. 4).  Newton solves
+ * J(u) du = -R(u), R(u) = L(u) - f (eq. 8), by GMRES with the Jacobian applied
+ * matrix-free as the Frechet derivative of R (eq. 9), right-preconditioned by the
+ * physics-based field-block preconditioner (section 2.5.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller, allocated on the
+ *   device that was current when the context was created.  Host-side structs
+ *   (options, info) are plain host memory owned by the caller.
+ * - A state vector holds n_f fields, field-major and x fastest:
+ *   index = ((f * nz + k) * ny + j) * nx + i.  2D problems have ny = 1 and fields
+ *   (u, w, p', theta'); 3D problems fields (u, v, w, p', theta').  p' is the Exner
+ *   perturbation c_p pi' and theta' the potential-temperature perturbation.
+ *   Cell-centred grid x_i = (i + 1/2) dx; walls lie on the domain faces.
+ * - Precision: JFNK_F64 arrays are double, JFNK_F32 arrays are float.  Reductions
+ *   (norms, Arnoldi dot products) accumulate in FP64 in both cases; the Givens /
+ *   least-squares step of GMRES is FP64.
+ * - Calls enqueue work on the context's HIP stream.  Calls that must take a
+ *   convergence decision (jfnk_gmres, jfnk_newton_step) synchronise that stream
+ *   before they return; the others return without synchronising.
+ * - A context is not thread safe; use one context per host thread.
+ * - No entry point allocates device memory except jfnk_create (and frees it in
+ *   jfnk_destroy).
+ *
+ * Return codes: JFNK_OK (0); JFNK_NOT_CONVERGED (1, soft: outputs hold the last
+ * iterate and the info struct is filled); JFNK_ERR_ARG (-1, invalid argument:
+ * null pointer, a dimension below 8, dt <= 0, m > max_m, unsupported option);
+ * JFNK_ERR_HIP (-2, a HIP runtime error); JFNK_ERR_NONFINITE (-3, a residual or
+ * Krylov norm is NaN or infinite).  jfnk_last_error() returns a message for the
+ * last failing call on the calling thread.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    JFNK_OK = 0,
+    JFNK_NOT_CONVERGED = 1,
+    JFNK_ERR_ARG = -1,
+    JFNK_ERR_HIP = -2,
+    JFNK_ERR_NONFINITE = -3
+};
+
+typedef enum { JFNK_F64 = 0, JFNK_F32 = 1 } jfnk_dtype;
+typedef enum { JFNK_PC_NONE = 0, JFNK_PC_PHYSICS = 1, JFNK_PC_LEARNED = 2 } jfnk_pc_kind;
+/* STABLE: [R(u+eps v) - R(u)]/eps with every bilinear term expanded (equal to the
+ *         literal quotient in exact arithmetic, no cancellation);
+ * LITERAL: the quotient evaluated as written;  ANALYTIC: the eps -> 0 limit.   */
+typedef enum { JFNK_JV_STABLE = 0, JFNK_JV_LITERAL = 1, JFNK_JV_ANALYTIC = 2 } jfnk_jv_mode;
+typedef enum { JFNK_CLOSURE_CONST_K = 0, JFNK_CLOSURE_SMAGORINSKY = 1, JFNK_CLOSURE_NONE = 2 } jfnk_closure;
+typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIODIC = 2 } jfnk_bc;
+
+/* Physical problem (equations 1-3 with the constants of section 2.1).
+ * Background: theta_bar = theta0 + beta z with beta = n_bv^2 theta0 / g, Exner
+ * background p_bar with dp_bar/dz = -g/theta_bar and p_bar(0) = cp.  kappa_div is
+ * the coefficient of (p_bar + p') div u in the Exner equation (<= 0: R/cv).
+ * Closure (section 2.4): Smagorinsky nu = (cs Delta)^2 sqrt(2 S:S), Delta the
+ * geometric mean spacing, heat diffusivity nu/pr_t; or constant k_m, k_h.
+ * Surface heat flux (section 3.2): h0 [W m^-2] over a strip of width strip_width
+ * centred at x = strip_center, top-hat (strip_shape 0) or tanh profile (1, with
+ * half-width units and steepness strip_xi); converted with rho0 = p_ref/(R theta0)
+ * to Q = H/(rho0 cp) and applied as Q/dz in the lowest cell.
+ * convection = 0 drops the convective terms; energy_test = 1 replaces
+ * kappa (p_bar + p') by kappa cp and drops w dp_bar/dz (a frozen-coefficient
+ * operator that conserves a quadratic energy).  dd_p must be 2 (5-point
+ * Deslauriers-Dubuc derivative, section 2.3).                                   */
+typedef struct {
+    int32_t dim, nx, ny, nz;          /* 2 or 3; grid points per direction (ny = 1 in 2D) */
+    double lx, ly, lz, dt;            /* domain [m], time step [s]                       */
+    double theta0, g, cp, cv, rgas, p_ref;
+    double kappa_div;
+    double n_bv;
+    int32_t closure;                  /* jfnk_closure */
+    double cs, pr_t, k_m, k_h;
+    int32_t bc_lateral;               /* JFNK_BC_FREE_SLIP or JFNK_BC_PERIODIC */
+    int32_t bc_vertical;              /* jfnk_bc */
+    double h0, strip_width, strip_center;
+    int32_t strip_shape;
+    double strip_xi;
+    int32_t convection;
+    int32_t energy_test;
+    int32_t dd_p;
+} jfnk_problem;
+
+typedef struct {
+    int32_t m;                 /* restart length (<= max_m of the context)              */
+    int32_t max_restarts;      /* total iterations <= m * max_restarts                   */
+    double tol;                /* stop when the least-squares residual <= tol * ||rhs||  */
+    int32_t pc;                /* jfnk_pc_kind                                           */
+    int32_t jv;                /* jfnk_jv_mode                                           */
+    int32_t sweeps;            /* physics preconditioner Jacobi sweeps (>= 0)            */
+    int32_t max_iters;         /* hard cap on iterations (<= 0: m * max_restarts)        */
+} jfnk_gmres_opts;
+
+typedef struct {
+    int32_t iters, restarts, converged;
+    double res0, res_est;
+    double* h_out;             /* optional HOST buffer of (m+1)*m doubles, row-major:
+                                  receives the Hessenberg of the last cycle before the
+                                  Givens rotations (NULL: not returned)                  */
+} jfnk_gmres_info;
+
+typedef struct {
+    double rtol;               /* stop when ||R|| <= max(rtol ||R(u0)||, atol)           */
+    double atol_factor;        /* atol = atol_factor * ||2 u^n / dt||                     */
+    int32_t max_newton;
+    int32_t inner;             /* jfnk_dtype of the Krylov solve and Jv (F32 = mixed)     */
+    jfnk_gmres_opts gm;        /* gm.tol is ignored: the forcing term sets it            */
+    int32_t forcing;           /* 0: Eisenstat-Walker choice 2, 1: fixed eta            */
+    double eta;                /* fixed forcing term                                     */
+    double eta_floor;          /* lower bound on the forcing term                        */
+} jfnk_newton_opts;
+
+typedef struct {
+    int32_t newton_iters, gmres_iters_total, converged, fallbacks;
+    double res0, res_final;
+} jfnk_newton_info;
+
+typedef struct jfnk_ctx jfnk_ctx;
+
+/* Create a context for one problem on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL: the null stream).  max_m bounds the GMRES restart length;
+ * the workspace (Krylov bases V and Z of max_m+1 vectors in both precisions,
+ * temporaries, background profiles) is allocated here, sized for the grid.
+ * Sets up the background state and surface flux (section 2.1, section 3.2).      */
+int jfnk_create(const jfnk_problem* prob, int32_t max_m, void* hip_stream, jfnk_ctx** out);
+int jfnk_destroy(jfnk_ctx* ctx);
+const char* jfnk_last_error(void);
+/* Rebind the stream a context enqueues on.                                       */
+int jfnk_set_stream(jfnk_ctx* ctx, void* hip_stream);
+
+/* f = 2 u^n / dt + F(u^n)   (equation 5, right-hand side).  FP64.               */
+int jfnk_rhs(jfnk_ctx* ctx, const double* u_n, double* f);
+
+/* R = 2 u / dt - F(u) - f   (section 2.5.1, R = L(u) - f).  FP64.  f may be NULL
+ * (treated as zero).                                                             */
+int jfnk_residual(jfnk_ctx* ctx, const double* u, const double* f, double* R);
+
+/* Same operators in either precision: out = F(u) (what = 0), 2u/dt + F(u)
+ * (what = 1) or 2u/dt - F(u) - f (what = 2).                                      */
+int jfnk_apply_F(jfnk_ctx* ctx, jfnk_dtype dt, int32_t what, const void* u, const void* f, void* out);
+
+/* Jv = J(u) v, the Frechet derivative of R at u in direction v (equation 9).
+ * eps <= 0 selects eps = sqrt(eps_mach) max(||u||, sqrt(N)) / ||v|| with eps_mach
+ * of the dtype (2^-52 or 2^-23); ignored by ANALYTIC.  u, v, Jv share the dtype.  */
+int jfnk_jv(jfnk_ctx* ctx, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v,
+            double eps, void* Jv);
+
+/* z ~ P(u)^{-1} r, the physics-based preconditioner (section 2.5.1): field-block
+ * diagonal of L with u frozen, 2/dt + C(u; .) - D.(K D .), applied by Jacobi
+ * sweeps (z0 = r/d, z <- z + (r - P z)/d).  JFNK_PC_NONE copies r.  u, r, z share
+ * the dtype; r and z must not alias.                                             */
+int jfnk_precond_apply(jfnk_ctx* ctx, jfnk_pc_kind pc, jfnk_dtype dt, const void* u,
+                       const void* r, void* z, int32_t sweeps);
+
+/* Right-preconditioned flexible restarted GMRES(m) (Saad and Schultz) for
+ * J(u) x = rhs with x0 = 0, classical Gram-Schmidt applied twice, Givens
+ * rotations and back substitution in FP64.  x is output only.                    */
+int jfnk_gmres(jfnk_ctx* ctx, jfnk_dtype dt, const void* u, const void* rhs, void* x,
+               const jfnk_gmres_opts* opts, jfnk_gmres_info* info);
+
+/* One trapezoidal step by inexact Newton (equation 8): u_np1 holds the initial
+ * guess on entry (usually a copy of u_n) and the solution on return.  FP64 outer
+ * residual, update and norms; inner Krylov solve in opts->inner.                  */
+int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
+                     const jfnk_newton_opts* opts, jfnk_newton_info* info);
+
+/* 2-norm of a vector of n values (FP64 accumulation), result to a host double.   */
+int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* out);
+
+/* Kernel timing with HIP events on the context stream.  Kernel classes:
+ * 0 Jv, 1 residual/rhs, 2 physics preconditioner sweep, 3 Arnoldi passes,
+ * 4 other vector kernels.  enable = 1 starts recording (clears the counters).    */
+int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
+int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JFNK_H */

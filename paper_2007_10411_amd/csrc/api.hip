@@ -1,0 +1,700 @@
+// C ABI of the JFNK library: context set-up, operator entry points, flexible
+// restarted GMRES and the inexact Newton step (section 2.5 of the paper,
+// equations 5, 8 and 9).  Host orchestration only; every arithmetic step on the
+// state runs in the kernels of stencil2d.hip and vec.hip.
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "jfnk_internal.hpp"
+
+namespace jfnk {
+
+namespace {
+thread_local std::string g_err;
+
+// device-scalar layout (doubles)
+constexpr int M = kMaxDots;
+constexpr int O_H = 0;
+constexpr int O_HRAW = O_H + (M + 1) * M;
+constexpr int O_CS = O_HRAW + (M + 1) * M;
+constexpr int O_SN = O_CS + M;
+constexpr int O_G = O_SN + M;
+constexpr int O_Y = O_G + M + 1;
+constexpr int O_H1 = O_Y + M;
+constexpr int O_H2 = O_H1 + M;
+constexpr int O_S = O_H2 + M;         // misc scalars
+enum { S_UNORM2 = 0, S_VNORM2, S_EPS, S_WNORM2, S_WNORM, S_RES, S_BETA2, S_BETA, S_TMP, S_COUNT = 16 };
+constexpr int kScal = O_S + S_COUNT;
+
+double* ds(jfnk_ctx* c, int off) { return c->dscal + off; }
+double* sc(jfnk_ctx* c, int which) { return c->dscal + O_S + which; }
+
+template <typename T> T* Vb(jfnk_ctx* c);
+template <> double* Vb<double>(jfnk_ctx* c) { return c->V64; }
+template <> float* Vb<float>(jfnk_ctx* c) { return c->V32; }
+template <typename T> T* Zb(jfnk_ctx* c);
+template <> double* Zb<double>(jfnk_ctx* c) { return c->Z64; }
+template <> float* Zb<float>(jfnk_ctx* c) { return c->Z32; }
+template <typename T> T* NUb(jfnk_ctx* c);
+template <> double* NUb<double>(jfnk_ctx* c) { return c->nu64; }
+template <> float* NUb<float>(jfnk_ctx* c) { return c->nu32; }
+template <typename T> T* TA(jfnk_ctx* c);
+template <> double* TA<double>(jfnk_ctx* c) { return c->t64a; }
+template <> float* TA<float>(jfnk_ctx* c) { return c->t32a; }
+template <typename T> T* TB(jfnk_ctx* c);
+template <> double* TB<double>(jfnk_ctx* c) { return c->t64b; }
+template <> float* TB<float>(jfnk_ctx* c) { return c->t32b; }
+template <typename T> constexpr double eps_mach();
+template <> constexpr double eps_mach<double>() { return 2.220446049250313e-16; }   // 2^-52
+template <> constexpr double eps_mach<float>() { return 1.1920928955078125e-07; }   // 2^-23
+
+// ---- timing ----
+struct TimedLaunch {
+    jfnk_ctx* c;
+    int cls;
+    bool active;
+    TimedLaunch(jfnk_ctx* c_, int cls_) : c(c_), cls(cls_), active(c_->timing.on) {
+        if (!active) return;
+        auto& T = c->timing;
+        if ((int)T.ev[cls].size() < 2 * (T.used[cls] + 1)) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                active = false;
+                return;
+            }
+            T.ev[cls].push_back(a);
+            T.ev[cls].push_back(b);
+        }
+        (void)hipEventRecord(T.ev[cls][2 * T.used[cls]], c->stream);
+    }
+    ~TimedLaunch() {
+        if (!active) return;
+        auto& T = c->timing;
+        (void)hipEventRecord(T.ev[cls][2 * T.used[cls] + 1], c->stream);
+        T.used[cls]++;
+        T.launches[cls]++;
+    }
+};
+
+void resolve_timing(jfnk_ctx* c) {
+    auto& T = c->timing;
+    for (int k = 0; k < KC_COUNT; ++k) {
+        for (int i = 0; i < T.used[k]; ++i) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(T.ev[k][2 * i + 1]);
+            if (hipEventElapsedTime(&ms, T.ev[k][2 * i], T.ev[k][2 * i + 1]) == hipSuccess) T.ms[k] += ms;
+        }
+        T.used[k] = 0;
+    }
+}
+
+// ---- background and surface flux set-up (section 2.1, section 3.2) ----
+__global__ void k_background(Geo g, jfnk_problem p, double* pbar, double* dpbar, double* sflux, float* pbar32,
+                             float* dpbar32, float* sflux32) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < g.nz) {
+        const double z = (t + 0.5) * g.dz;
+        const double thb = p.theta0 + g.beta * z;
+        double pb;
+        if (g.beta > 0.0)
+            pb = p.cp - (p.g / g.beta) * log1p(g.beta * z / p.theta0);
+        else
+            pb = p.cp - p.g * z / p.theta0;
+        const double dpb = -p.g / thb;
+        pbar[t] = pb;
+        dpbar[t] = dpb;
+        pbar32[t] = (float)pb;
+        dpbar32[t] = (float)dpb;
+    }
+    const int nxy = g.nx * g.ny;
+    if (t < nxy) {
+        const int i = t % g.nx;
+        const double x = (i + 0.5) * g.dx;
+        double H = 0.0;
+        if (p.h0 != 0.0 && p.bc_vertical != JFNK_BC_PERIODIC) {
+            const double half = 0.5 * p.strip_width;
+            if (p.strip_shape == 0) {
+                H = fabs(x - p.strip_center) <= half ? p.h0 : 0.0;
+            } else {
+                const double xp = (x - p.strip_center) / half;
+                H = 0.5 * p.h0 * (tanh((xp + 1.0) / p.strip_xi) - tanh((xp - 1.0) / p.strip_xi));
+            }
+        }
+        const double rho0 = p.p_ref / (p.rgas * p.theta0);
+        const double q = H / (rho0 * p.cp) / g.dz;
+        sflux[t] = q;
+        sflux32[t] = (float)q;
+    }
+}
+
+template <typename T>
+int norm2_to(jfnk_ctx* c, const T* x, long long n, double* out_dev) {
+    const int nb = red_blocks(n);
+    JFNK_HIP(launch_norm2_partial<T>(x, n, c->partials, nb, c->stream));
+    JFNK_HIP(launch_reduce_partials(c->partials, nb, 1, 1, out_dev, 0, c->stream));
+    return JFNK_OK;
+}
+
+int read_scalars(jfnk_ctx* c, int first, int count) {
+    JFNK_HIP(hipMemcpyAsync(c->hscal + first, sc(c, first), count * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    JFNK_HIP(hipStreamSynchronize(c->stream));
+    return JFNK_OK;
+}
+
+// Jv with eps from the device scalar (stable / literal) or eps = 0 (analytic)
+template <typename T>
+int apply_jv(jfnk_ctx* c, int mode, const T* u, const T* v, const double* eps_dev, double eps_host, T* out) {
+    if (mode == JFNK_JV_LITERAL) {
+        double e = eps_host;
+        if (eps_dev) {
+            JFNK_HIP(hipMemcpyAsync(&c->hscal[S_TMP], eps_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            JFNK_HIP(hipStreamSynchronize(c->stream));
+            e = c->hscal[S_TMP];
+        }
+        T* w1 = TA<T>(c);
+        T* w2 = TB<T>(c);
+        JFNK_HIP(launch_lincomb<T>(w1, u, v, c->n, 1.0, e, c->stream));
+        {
+            TimedLaunch tl(c, KC_RESIDUAL);
+            JFNK_HIP(launch_apply_F<T>(c->geo, w1, nullptr, w2, 2, c->stream));
+        }
+        {
+            TimedLaunch tl(c, KC_RESIDUAL);
+            JFNK_HIP(launch_apply_F<T>(c->geo, u, nullptr, w1, 2, c->stream));
+        }
+        JFNK_HIP(launch_lincomb<T>(out, w2, w1, c->n, 1.0 / e, -1.0 / e, c->stream));
+        return JFNK_OK;
+    }
+    TimedLaunch tl(c, KC_JV);
+    if (mode == JFNK_JV_ANALYTIC)
+        JFNK_HIP(launch_jv<T>(c->geo, u, v, 0.0, nullptr, out, c->stream));
+    else
+        JFNK_HIP(launch_jv<T>(c->geo, u, v, eps_host, eps_dev, out, c->stream));
+    return JFNK_OK;
+}
+
+// eps for direction v at state u: needs ||u||^2 already in S_UNORM2
+template <typename T>
+int fd_eps_dev(jfnk_ctx* c, const T* v) {
+    int rc = norm2_to<T>(c, v, c->n, sc(c, S_VNORM2));
+    if (rc) return rc;
+    JFNK_HIP(launch_fd_eps(sc(c, S_UNORM2), sc(c, S_VNORM2), std::sqrt(eps_mach<T>()), std::sqrt((double)c->n),
+                           sc(c, S_EPS), c->stream));
+    return JFNK_OK;
+}
+
+// z = P^{-1} r by the physics preconditioner (nu frozen beforehand), or copy
+template <typename T>
+int apply_pc(jfnk_ctx* c, int pc, const T* u, const T* r, T* z, int sweeps, T* scratch) {
+    if (pc == JFNK_PC_NONE) {
+        JFNK_HIP(hipMemcpyAsync(z, r, c->n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        return JFNK_OK;
+    }
+    if (pc != JFNK_PC_PHYSICS) {
+        set_error("unsupported preconditioner kind");
+        return JFNK_ERR_ARG;
+    }
+    const T* nu = NUb<T>(c);
+    // ping-pong so that the last sweep lands in z
+    T* bufs[2] = {z, scratch};
+    int cur = (sweeps % 2 == 0) ? 0 : 1;
+    {
+        TimedLaunch tl(c, KC_PC);
+        JFNK_HIP(launch_pc_diag<T>(c->geo, nu, r, bufs[cur], c->stream));
+    }
+    for (int s = 0; s < sweeps; ++s) {
+        TimedLaunch tl(c, KC_PC);
+        JFNK_HIP(launch_pc_sweep<T>(c->geo, u, nu, r, bufs[cur], bufs[1 - cur], c->stream));
+        cur = 1 - cur;
+    }
+    return JFNK_OK;
+}
+
+template <typename T>
+int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o, jfnk_gmres_info* info) {
+    const long long n = c->n;
+    const int m = o.m;
+    const int max_iters = o.max_iters > 0 ? o.max_iters : m * o.max_restarts;
+    T* V = Vb<T>(c);
+    T* Z = Zb<T>(c);
+    hipStream_t s = c->stream;
+    int rc;
+    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(launch_frozen_nu<T>(c->geo, u, NUb<T>(c), s));
+    if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
+    JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
+    JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
+    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+    const double bnorm = c->hscal[S_BETA];
+    if (info) {
+        info->res0 = bnorm;
+        info->res_est = bnorm;
+        info->iters = 0;
+        info->restarts = 0;
+        info->converged = 0;
+    }
+    if (!std::isfinite(bnorm)) {
+        set_error("non-finite right-hand side norm");
+        return JFNK_ERR_NONFINITE;
+    }
+    if (bnorm == 0.0) {
+        if (info) info->converged = 1;
+        return JFNK_OK;
+    }
+    const int nb = red_blocks(n);
+    int total = 0, restarts = 0;
+    bool converged = false;
+    double res_est = bnorm;
+    while (true) {
+        JFNK_HIP(launch_scale<T>(V, n, sc(c, S_BETA), s));
+        int k = 0;
+        bool done = false;
+        for (int j = 0; j < m; ++j) {
+            T* Vj = V + (long long)j * n;
+            T* Vn = V + (long long)(j + 1) * n;
+            T* Zj = Z + (long long)j * n;
+            if ((rc = apply_pc<T>(c, o.pc, u, Vj, Zj, o.sweeps, Vn))) return rc;
+            if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, Zj))) return rc;
+            if ((rc = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return rc;
+            {
+                TimedLaunch tl(c, KC_ARNOLDI);
+                // classical Gram-Schmidt, twice
+                JFNK_HIP(launch_multidot<T>(V, n, j + 1, Vn, c->partials, nb, s));
+                JFNK_HIP(launch_reduce_partials(c->partials, nb, kMaxDots, j + 1, ds(c, O_H1), 0, s));
+                JFNK_HIP(launch_update_dot<T>(V, n, j + 1, ds(c, O_H1), Vn, c->partials, nb, 0, s));
+                JFNK_HIP(launch_multidot<T>(V, n, j + 1, Vn, c->partials, nb, s));
+                JFNK_HIP(launch_reduce_partials(c->partials, nb, kMaxDots, j + 1, ds(c, O_H2), 0, s));
+                JFNK_HIP(launch_update_dot<T>(V, n, j + 1, ds(c, O_H2), Vn, c->partials, nb, 1, s));
+                JFNK_HIP(launch_reduce_partials(c->partials, nb, 1, 1, sc(c, S_WNORM2), 0, s));
+            }
+            JFNK_HIP(launch_givens(ds(c, O_H), ds(c, O_HRAW), ds(c, O_CS), ds(c, O_SN), ds(c, O_G), j, m, ds(c, O_H1),
+                                   ds(c, O_H2), sc(c, S_WNORM2), sc(c, S_WNORM), sc(c, S_RES), s));
+            if ((rc = read_scalars(c, S_WNORM, 2))) return rc;
+            const double wn = c->hscal[S_WNORM];
+            res_est = c->hscal[S_RES];
+            if (!std::isfinite(wn) || !std::isfinite(res_est)) {
+                set_error("non-finite Krylov norm");
+                return JFNK_ERR_NONFINITE;
+            }
+            if (wn > 0.0) JFNK_HIP(launch_scale<T>(Vn, n, sc(c, S_WNORM), s));
+            k = j + 1;
+            ++total;
+            if (res_est <= o.tol * bnorm || wn == 0.0 || total >= max_iters) {
+                done = true;
+                break;
+            }
+        }
+        JFNK_HIP(launch_backsolve(ds(c, O_H), ds(c, O_G), k, m, ds(c, O_Y), s));
+        JFNK_HIP(launch_axpy_basis<T>(x, Z, n, k, ds(c, O_Y), s));
+        if (done) {
+            converged = res_est <= o.tol * bnorm;
+            break;
+        }
+        ++restarts;
+        // true residual r = b - J x
+        if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
+        if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
+        JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
+        if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+        JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
+        if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+        if (c->hscal[S_BETA] == 0.0) {
+            converged = true;
+            break;
+        }
+    }
+    if (info) {
+        info->iters = total;
+        info->restarts = restarts;
+        info->converged = converged ? 1 : 0;
+        info->res_est = res_est;
+        if (info->h_out) {
+            JFNK_HIP(hipMemcpyAsync(info->h_out, ds(c, O_HRAW), (size_t)(m + 1) * m * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+        }
+    }
+    JFNK_HIP(hipStreamSynchronize(s));
+    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+bool valid_problem(const jfnk_problem* p, std::string& why) {
+    if (!p) return why = "null problem", false;
+    if (p->dim != 2) return why = "only dim = 2 is supported by this build", false;
+    if (p->nx < 8 || p->nz < 8 || p->ny != 1) return why = "grid below 8 points in a direction (or ny != 1 in 2D)", false;
+    if (!(p->dt > 0) || !(p->lx > 0) || !(p->lz > 0)) return why = "non-positive dt or domain size", false;
+    if (p->dd_p != 2) return why = "only dd_p = 2 is supported", false;
+    if (p->bc_lateral != JFNK_BC_FREE_SLIP && p->bc_lateral != JFNK_BC_PERIODIC)
+        return why = "bc_lateral must be free-slip or periodic", false;
+    if (p->bc_vertical < 0 || p->bc_vertical > 2) return why = "invalid bc_vertical", false;
+    if (p->closure < 0 || p->closure > 2) return why = "invalid closure", false;
+    if (p->closure == JFNK_CLOSURE_SMAGORINSKY && !(p->pr_t > 0)) return why = "pr_t must be positive", false;
+    return true;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+    return JFNK_ERR_HIP;
+}
+
+}  // namespace jfnk
+
+using namespace jfnk;
+
+extern "C" {
+
+const char* jfnk_last_error(void) { return g_err.c_str(); }
+
+int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** out) {
+    std::string why;
+    if (!out) {
+        set_error("null output pointer");
+        return JFNK_ERR_ARG;
+    }
+    *out = nullptr;
+    if (!valid_problem(p, why)) {
+        set_error(why);
+        return JFNK_ERR_ARG;
+    }
+    if (max_m < 1 || max_m + 1 > kMaxDots) {
+        set_error("max_m must be in [1, 63]");
+        return JFNK_ERR_ARG;
+    }
+    jfnk_ctx* c = new jfnk_ctx();
+    c->prob = *p;
+    c->stream = (hipStream_t)stream;
+    c->max_m = max_m;
+    JFNK_HIP(hipGetDevice(&c->device));
+    Geo& g = c->geo;
+    g.dim = p->dim;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.npts = (long long)p->nx * p->ny * p->nz;
+    g.bcl = p->bc_lateral;
+    g.bcv = p->bc_vertical;
+    g.dx = p->lx / p->nx;
+    g.dy = p->ly / p->ny;
+    g.dz = p->lz / p->nz;
+    g.idx = 1.0 / g.dx;
+    g.idy = 1.0 / g.dy;
+    g.idz = 1.0 / g.dz;
+    g.two_dt = 2.0 / p->dt;
+    g.theta0 = p->theta0;
+    g.g_theta0 = p->g / p->theta0;
+    g.kappa = p->kappa_div > 0 ? p->kappa_div : p->rgas / p->cv;
+    g.kappa_cp = g.kappa * p->cp;
+    g.beta = p->n_bv * p->n_bv * p->theta0 / p->g;
+    g.closure = p->closure;
+    const double delta = p->dim == 2 ? std::sqrt(g.dx * g.dz) : std::cbrt(g.dx * g.dy * g.dz);
+    g.smag = (p->cs * delta) * (p->cs * delta);
+    g.inv_pr = p->pr_t > 0 ? 1.0 / p->pr_t : 0.0;
+    g.k_m = p->k_m;
+    g.k_h = p->k_h;
+    g.convection = p->convection;
+    g.energy_test = p->energy_test;
+    c->nf = p->dim == 2 ? 4 : 5;
+    c->n = c->nf * g.npts;
+    const long long n = c->n;
+    const size_t nb64 = n * sizeof(double), nb32 = n * sizeof(float);
+    auto fail = [&](hipError_t e, const char* what) {
+        jfnk_destroy(c);
+        return hip_fail(e, what);
+    };
+#define ALLOC(ptr, bytes)                                         \
+    do {                                                          \
+        hipError_t e_ = hipMalloc((void**)&(ptr), (bytes));       \
+        if (e_ != hipSuccess) return fail(e_, "hipMalloc " #ptr); \
+    } while (0)
+    ALLOC(c->V64, (size_t)(max_m + 1) * nb64);
+    ALLOC(c->Z64, (size_t)max_m * nb64);
+    ALLOC(c->V32, (size_t)(max_m + 1) * nb32);
+    ALLOC(c->Z32, (size_t)max_m * nb32);
+    ALLOC(c->f64, nb64);
+    ALLOC(c->R64, nb64);
+    ALLOC(c->t64a, nb64);
+    ALLOC(c->t64b, nb64);
+    ALLOC(c->b64, nb64);
+    ALLOC(c->x64, nb64);
+    const size_t next = (size_t)(g.nx + 4) * (g.nz + 4) * (g.dim == 3 ? (g.ny + 4) : 1);
+    ALLOC(c->nu64, next * sizeof(double));
+    ALLOC(c->u32, nb32);
+    ALLOC(c->b32, nb32);
+    ALLOC(c->x32, nb32);
+    ALLOC(c->t32a, nb32);
+    ALLOC(c->t32b, nb32);
+    ALLOC(c->nu32, next * sizeof(float));
+    const size_t nbg = (size_t)2 * g.nz + (size_t)g.nx * g.ny;
+    ALLOC(c->bg64, nbg * sizeof(double));
+    ALLOC(c->bg32, nbg * sizeof(float));
+    ALLOC(c->partials, (size_t)kMaxPartials * kMaxDots * sizeof(double));
+    ALLOC(c->dscal, kScal * sizeof(double));
+#undef ALLOC
+    {
+        hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return fail(e, "hipHostMalloc");
+    }
+    g.pbar64 = c->bg64;
+    g.dpbar64 = c->bg64 + g.nz;
+    g.sflux64 = c->bg64 + 2 * g.nz;
+    g.pbar32 = c->bg32;
+    g.dpbar32 = c->bg32 + g.nz;
+    g.sflux32 = c->bg32 + 2 * g.nz;
+    {
+        hipError_t e = hipMemsetAsync(c->dscal, 0, kScal * sizeof(double), c->stream);
+        if (e != hipSuccess) return fail(e, "hipMemsetAsync");
+        const int cnt = std::max(g.nz, g.nx * g.ny);
+        hipLaunchKernelGGL(k_background, dim3((cnt + 255) / 256), dim3(256), 0, c->stream, g, *p,
+                           (double*)g.pbar64, (double*)g.dpbar64, (double*)g.sflux64, (float*)g.pbar32,
+                           (float*)g.dpbar32, (float*)g.sflux32);
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail(e, "k_background");
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(e, "hipStreamSynchronize");
+    }
+    *out = c;
+    return JFNK_OK;
+}
+
+int jfnk_destroy(jfnk_ctx* c) {
+    if (!c) return JFNK_OK;
+    (void)hipStreamSynchronize(c->stream);
+    void* ptrs[] = {c->V64, c->Z64, c->V32, c->Z32, c->f64, c->R64, c->t64a, c->t64b, c->b64, c->x64, c->nu64, c->u32, c->b32,
+                    c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    for (int k = 0; k < KC_COUNT; ++k)
+        for (auto e : c->timing.ev[k]) (void)hipEventDestroy(e);
+    delete c;
+    return JFNK_OK;
+}
+
+int jfnk_set_stream(jfnk_ctx* c, void* stream) {
+    if (!c) {
+        set_error("null context");
+        return JFNK_ERR_ARG;
+    }
+    c->stream = (hipStream_t)stream;
+    return JFNK_OK;
+}
+
+int jfnk_apply_F(jfnk_ctx* c, jfnk_dtype dt, int32_t what, const void* u, const void* f, void* out) {
+    if (!c || !u || !out || what < 0 || what > 2) {
+        set_error("invalid argument to jfnk_apply_F");
+        return JFNK_ERR_ARG;
+    }
+    TimedLaunch tl(c, KC_RESIDUAL);
+    if (dt == JFNK_F64)
+        JFNK_HIP(launch_apply_F<double>(c->geo, (const double*)u, (const double*)f, (double*)out, what, c->stream));
+    else if (dt == JFNK_F32)
+        JFNK_HIP(launch_apply_F<float>(c->geo, (const float*)u, (const float*)f, (float*)out, what, c->stream));
+    else {
+        set_error("invalid dtype");
+        return JFNK_ERR_ARG;
+    }
+    return JFNK_OK;
+}
+
+int jfnk_rhs(jfnk_ctx* c, const double* u_n, double* f) { return jfnk_apply_F(c, JFNK_F64, 1, u_n, nullptr, f); }
+
+int jfnk_residual(jfnk_ctx* c, const double* u, const double* f, double* R) {
+    return jfnk_apply_F(c, JFNK_F64, 2, u, f, R);
+}
+
+int jfnk_jv(jfnk_ctx* c, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v, double eps, void* Jv) {
+    if (!c || !u || !v || !Jv || mode < 0 || mode > 2) {
+        set_error("invalid argument to jfnk_jv");
+        return JFNK_ERR_ARG;
+    }
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        const double* edev = nullptr;
+        if (mode != JFNK_JV_ANALYTIC && !(eps > 0)) {
+            int rc = norm2_to<T>(c, (const T*)u, c->n, sc(c, S_UNORM2));
+            if (rc) return rc;
+            if ((rc = fd_eps_dev<T>(c, (const T*)v))) return rc;
+            edev = sc(c, S_EPS);
+        }
+        return apply_jv<T>(c, mode, (const T*)u, (const T*)v, edev, eps, (T*)Jv);
+    };
+    if (dt == JFNK_F64) return run(double(0));
+    if (dt == JFNK_F32) return run(float(0));
+    set_error("invalid dtype");
+    return JFNK_ERR_ARG;
+}
+
+int jfnk_precond_apply(jfnk_ctx* c, jfnk_pc_kind pc, jfnk_dtype dt, const void* u, const void* r, void* z,
+                       int32_t sweeps) {
+    if (!c || !u || !r || !z || r == z || sweeps < 0) {
+        set_error("invalid argument to jfnk_precond_apply");
+        return JFNK_ERR_ARG;
+    }
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        if (pc == JFNK_PC_PHYSICS) JFNK_HIP(launch_frozen_nu<T>(c->geo, (const T*)u, NUb<T>(c), c->stream));
+        return apply_pc<T>(c, pc, (const T*)u, (const T*)r, (T*)z, sweeps, TA<T>(c));
+    };
+    if (dt == JFNK_F64) return run(double(0));
+    if (dt == JFNK_F32) return run(float(0));
+    set_error("invalid dtype");
+    return JFNK_ERR_ARG;
+}
+
+static bool valid_gmres_opts(jfnk_ctx* c, const jfnk_gmres_opts* o) {
+    if (!o || o->m < 1 || o->m > c->max_m || o->max_restarts < 1 || o->sweeps < 0 || o->jv < 0 || o->jv > 2) {
+        set_error("invalid GMRES options (m must be in [1, max_m])");
+        return false;
+    }
+    if (o->pc != JFNK_PC_NONE && o->pc != JFNK_PC_PHYSICS) {
+        set_error("preconditioner kind not available in this build");
+        return false;
+    }
+    return true;
+}
+
+int jfnk_gmres(jfnk_ctx* c, jfnk_dtype dt, const void* u, const void* rhs, void* x, const jfnk_gmres_opts* o,
+               jfnk_gmres_info* info) {
+    if (!c || !u || !rhs || !x || !valid_gmres_opts(c, o)) {
+        if (c && o) set_error(std::string("invalid argument to jfnk_gmres: ") + jfnk_last_error());
+        return JFNK_ERR_ARG;
+    }
+    if (dt == JFNK_F64) return gmres_impl<double>(c, (const double*)u, (const double*)rhs, (double*)x, *o, info);
+    if (dt == JFNK_F32) return gmres_impl<float>(c, (const float*)u, (const float*)rhs, (float*)x, *o, info);
+    set_error("invalid dtype");
+    return JFNK_ERR_ARG;
+}
+
+int jfnk_norm(jfnk_ctx* c, jfnk_dtype dt, const void* x, int64_t n, double* out) {
+    if (!c || !x || !out || n < 0) {
+        set_error("invalid argument to jfnk_norm");
+        return JFNK_ERR_ARG;
+    }
+    int rc = dt == JFNK_F64 ? norm2_to<double>(c, (const double*)x, n, sc(c, S_TMP))
+                            : norm2_to<float>(c, (const float*)x, n, sc(c, S_TMP));
+    if (rc) return rc;
+    if ((rc = read_scalars(c, S_TMP, 1))) return rc;
+    *out = std::sqrt(c->hscal[S_TMP]);
+    return JFNK_OK;
+}
+
+int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newton_opts* o, jfnk_newton_info* info) {
+    if (!c || !u_n || !u || !o || !valid_gmres_opts(c, &o->gm) || o->max_newton < 0 ||
+        (o->inner != JFNK_F64 && o->inner != JFNK_F32)) {
+        set_error(std::string("invalid argument to jfnk_newton_step"));
+        return JFNK_ERR_ARG;
+    }
+    const long long n = c->n;
+    hipStream_t s = c->stream;
+    int rc;
+    {
+        TimedLaunch tl(c, KC_RESIDUAL);
+        JFNK_HIP(launch_apply_F<double>(c->geo, u_n, nullptr, c->f64, 1, s));
+    }
+    auto resid_norm = [&](double& out) -> int {
+        {
+            TimedLaunch tl(c, KC_RESIDUAL);
+            JFNK_HIP(launch_apply_F<double>(c->geo, u, c->f64, c->R64, 2, s));
+        }
+        int r2 = norm2_to<double>(c, c->R64, n, sc(c, S_TMP));
+        if (r2) return r2;
+        if ((r2 = read_scalars(c, S_TMP, 1))) return r2;
+        out = std::sqrt(c->hscal[S_TMP]);
+        return JFNK_OK;
+    };
+    double unorm;
+    if ((rc = jfnk_norm(c, JFNK_F64, u_n, n, &unorm))) return rc;
+    double rn;
+    if ((rc = resid_norm(rn))) return rc;
+    const double r0 = rn;
+    const double tol = std::max(o->rtol * r0, o->atol_factor * (2.0 / c->prob.dt) * unorm);
+    jfnk_newton_info inf{};
+    inf.res0 = r0;
+    double rprev = r0, eta = 0.5;
+    bool converged = false;
+    int k = 0;
+    for (;; ++k) {
+        if (!std::isfinite(rn)) {
+            set_error("non-finite Newton residual");
+            return JFNK_ERR_NONFINITE;
+        }
+        if (rn <= tol) {
+            converged = true;
+            break;
+        }
+        if (k >= o->max_newton) break;
+        if (o->forcing == 0) {
+            // Eisenstat-Walker choice 2 with the standard safeguards
+            const double gamma = 0.9, alpha = 2.0, eta_max = 0.9;
+            if (k == 0) {
+                eta = 0.5;
+            } else {
+                double e = gamma * std::pow(rn / rprev, alpha);
+                const double sg = gamma * std::pow(eta, alpha);
+                if (sg > 0.1) e = std::max(e, sg);
+                eta = std::min(e, eta_max);
+            }
+            eta = std::min(std::max(eta, 0.5 * tol / rn), eta_max);
+        } else {
+            eta = o->eta;
+        }
+        eta = std::max(eta, o->eta_floor);
+        jfnk_gmres_opts go = o->gm;
+        go.tol = eta;
+        jfnk_gmres_info gi{};
+        if (o->inner == JFNK_F64) {
+            JFNK_HIP(launch_cast<double, double>(c->b64, c->R64, n, -1.0, s));
+            rc = gmres_impl<double>(c, u, c->b64, c->x64, go, &gi);
+            if (rc < 0) return rc;
+            JFNK_HIP(launch_add_to64<double>(u, c->x64, n, s));
+        } else {
+            JFNK_HIP(launch_cast<float, double>(c->u32, u, n, 1.0, s));
+            JFNK_HIP(launch_cast<float, double>(c->b32, c->R64, n, -1.0, s));
+            rc = gmres_impl<float>(c, c->u32, c->b32, c->x32, go, &gi);
+            if (rc < 0) return rc;
+            JFNK_HIP(launch_add_to64<float>(u, c->x32, n, s));
+        }
+        inf.gmres_iters_total += gi.iters;
+        rprev = rn;
+        if ((rc = resid_norm(rn))) return rc;
+    }
+    inf.newton_iters = k;
+    inf.converged = converged ? 1 : 0;
+    inf.res_final = rn;
+    if (info) *info = inf;
+    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+int jfnk_timing_enable(jfnk_ctx* c, int32_t enable) {
+    if (!c) {
+        set_error("null context");
+        return JFNK_ERR_ARG;
+    }
+    resolve_timing(c);
+    for (int k = 0; k < KC_COUNT; ++k) {
+        c->timing.ms[k] = 0.0;
+        c->timing.launches[k] = 0;
+    }
+    c->timing.on = enable != 0;
+    return JFNK_OK;
+}
+
+int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launches) {
+    if (!c || cls < 0 || cls >= KC_COUNT) {
+        set_error("invalid argument to jfnk_timing_read");
+        return JFNK_ERR_ARG;
+    }
+    resolve_timing(c);
+    if (total_ms) *total_ms = c->timing.ms[cls];
+    if (launches) *launches = c->timing.launches[cls];
+    return JFNK_OK;
+}
+
+}  // extern "C"

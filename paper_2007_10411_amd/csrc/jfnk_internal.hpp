@@ -1,0 +1,172 @@
+// Internal declarations of the JFNK HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/jfnk.h"
+
+namespace jfnk {
+
+// Kernel-side view of a problem: constants and device pointers, passed by value.
+struct Geo {
+    int dim, nx, ny, nz;
+    long long npts;
+    int bcl, bcv;               // lateral / vertical boundary kind
+    double dx, dy, dz;
+    double idx, idy, idz;       // inverse spacings
+    double two_dt;              // 2 / dt
+    double theta0, g_theta0;    // theta0, g / theta0
+    double kappa, kappa_cp;     // kappa, kappa * cp (energy-test coefficient)
+    double beta;
+    int closure;
+    double smag;                // (cs * Delta)^2
+    double inv_pr;              // 1 / Pr_t
+    double k_m, k_h;
+    int convection, energy_test;
+    const double* pbar64;       // p_bar(z), [nz]
+    const double* dpbar64;      // dp_bar/dz(z), [nz]
+    const double* sflux64;      // Q(x, y) / dz, [ny * nx]
+    const float* pbar32;
+    const float* dpbar32;
+    const float* sflux32;
+};
+
+template <typename T> struct Bg;
+template <> struct Bg<double> {
+    static __device__ __forceinline__ const double* pbar(const Geo& g) { return g.pbar64; }
+    static __device__ __forceinline__ const double* dpbar(const Geo& g) { return g.dpbar64; }
+    static __device__ __forceinline__ const double* sflux(const Geo& g) { return g.sflux64; }
+};
+template <> struct Bg<float> {
+    static __device__ __forceinline__ const float* pbar(const Geo& g) { return g.pbar32; }
+    static __device__ __forceinline__ const float* dpbar(const Geo& g) { return g.dpbar32; }
+    static __device__ __forceinline__ const float* sflux(const Geo& g) { return g.sflux32; }
+};
+
+enum KernelClass { KC_JV = 0, KC_RESIDUAL = 1, KC_PC = 2, KC_ARNOLDI = 3, KC_VEC = 4, KC_COUNT = 5 };
+
+constexpr int kMaxPartials = 2048;   // blocks of a reduction grid
+constexpr int kMaxDots = 64;         // vectors per fused dot pass (>= max_m + 1)
+
+// Event pairs recorded around kernel launches of each class while timing is on;
+// elapsed times are resolved lazily (no host synchronisation per launch).
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev[KC_COUNT];   // 2 per launch
+    int used[KC_COUNT] = {0};
+    double ms[KC_COUNT] = {0};
+    long long launches[KC_COUNT] = {0};
+};
+
+}  // namespace jfnk
+
+struct jfnk_ctx {
+    jfnk_problem prob;
+    jfnk::Geo geo;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int max_m = 0;
+    int nf = 0;
+    long long n = 0;            // nf * npts
+    // Krylov bases
+    double* V64 = nullptr;      // (max_m + 1) * n
+    double* Z64 = nullptr;      // max_m * n
+    float* V32 = nullptr;
+    float* Z32 = nullptr;
+    // FP64 temporaries
+    double* f64 = nullptr;      // f(u^n)
+    double* R64 = nullptr;      // residual
+    double* t64a = nullptr;
+    double* t64b = nullptr;
+    double* b64 = nullptr;      // Newton right-hand side -R
+    double* x64 = nullptr;      // Newton correction
+    double* nu64 = nullptr;     // frozen eddy viscosity [npts]
+    // FP32 temporaries
+    float* u32 = nullptr;
+    float* b32 = nullptr;
+    float* x32 = nullptr;
+    float* t32a = nullptr;
+    float* t32b = nullptr;
+    float* nu32 = nullptr;
+    // background
+    double* bg64 = nullptr;     // pbar | dpbar | sflux
+    float* bg32 = nullptr;
+    // reductions and small device state
+    double* partials = nullptr; // kMaxPartials * kMaxDots
+    double* dscal = nullptr;    // device scalars (see solver)
+    double* hscal = nullptr;    // pinned host mirror
+    jfnk::Timing timing;
+};
+
+namespace jfnk {
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define JFNK_HIP(...)                                                     \
+    do {                                                                  \
+        hipError_t e_ = (__VA_ARGS__);                                    \
+        if (e_ != hipSuccess) return ::jfnk::hip_fail(e_, #__VA_ARGS__);  \
+    } while (0)
+
+// ---- kernel launchers (stencil.hip) ----
+// out = F(u) (what 0), 2u/dt + F(u) (what 1), 2u/dt - F(u) - f (what 2)
+template <typename T>
+hipError_t launch_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, hipStream_t s);
+// Jv = 2v/dt - [F(u + eps v) - F(u)]/eps, expanded; eps read from *eps_dev if non-null
+template <typename T>
+hipError_t launch_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* jv,
+                     hipStream_t s);
+// frozen eddy viscosity nu(u) at the grid points
+template <typename T>
+hipError_t launch_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
+// one Jacobi sweep of the physics preconditioner: zout = zin + (r - P zin)/d
+// (zin == nullptr: zin = r/d)
+template <typename T>
+hipError_t launch_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_pc_diag(const Geo& g, const T* nu, const T* r, T* z, hipStream_t s);
+
+// ---- vector kernels (vec.hip) ----
+int red_blocks(long long n);
+template <typename T>
+hipError_t launch_norm2_partial(const T* x, long long n, double* partials, int nblk, hipStream_t s);
+// out[k] = sum of partials[b * stride + k] over b < nblk, k < cnt (fixed order)
+hipError_t launch_reduce_partials(const double* partials, int nblk, int stride, int cnt, double* out,
+                                  int accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_multidot(const T* V, long long n, int nv, const T* w, double* partials, int nblk,
+                           hipStream_t s);
+// w -= sum_i h[i] V_i ; then partial dots of V_i with the new w (dots != 0) or partial ||w||^2
+template <typename T>
+hipError_t launch_update_dot(const T* V, long long n, int nv, const double* h, T* w, double* partials,
+                             int nblk, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_scale(T* x, long long n, const double* inv_scale_dev, hipStream_t s);  // x /= *dev
+template <typename T>
+hipError_t launch_axpy_basis(T* x, const T* Z, long long n, int k, const double* y, hipStream_t s);
+template <typename Td, typename Ts>
+hipError_t launch_cast(Td* d, const Ts* s_, long long n, double alpha, hipStream_t s);   // d = alpha*s
+template <typename Ts>
+hipError_t launch_add_to64(double* u, const Ts* d, long long n, hipStream_t s);          // u += d
+template <typename T>
+hipError_t launch_axpby(T* y, const T* x, long long n, double a, double b, hipStream_t s); // y = a x + b y
+template <typename T>
+hipError_t launch_lincomb(T* out, const T* x, const T* y, long long n, double a, double b,
+                          hipStream_t s);                                                 // out = a x + b y
+// small single-thread kernels on the device scalars
+hipError_t launch_fd_eps(const double* unorm2, const double* vnorm2, double sqrt_eps_mach, double sqrt_n,
+                         double* eps, hipStream_t s);
+hipError_t launch_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
+                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
+                         double* res_est, hipStream_t s);
+hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s);
+hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m, hipStream_t s);
+
+}  // namespace jfnk

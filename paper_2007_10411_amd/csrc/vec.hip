@@ -1,0 +1,347 @@
+// Vector kernels of the Krylov solver: FP64-accumulated dot products and norms
+// with a fixed reduction order (deterministic across runs), Gram-Schmidt basis
+// updates, casts and the FP64 Givens / back-substitution steps of GMRES
+// (Saad and Schultz 1986).
+
+#include "jfnk_internal.hpp"
+
+namespace jfnk {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kGroup = 8;        // basis vectors per register group of a dot pass
+
+// Sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Block-wide sum of one value per thread (256 threads = 4 wavefronts); the
+// result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_norm2_partial(const T* __restrict__ x, long long n,
+                                                          double* __restrict__ partials) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const double v = (double)x[i];
+        acc += v * v;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ partials, int nblk,
+                                                            int stride, double* __restrict__ out,
+                                                            int accumulate) {
+    __shared__ double red[4];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(long long)b * stride + k];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
+}
+
+// partials[b * kMaxDots + v] = partial dot of V_v with w, v < nv
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_multidot(const T* __restrict__ V, long long n, int nv,
+                                                     const T* __restrict__ w, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (int g0 = 0; g0 < nv; g0 += kGroup) {
+        double acc[kGroup];
+#pragma unroll
+        for (int v = 0; v < kGroup; ++v) acc[v] = 0.0;
+        const int cnt = nv - g0 < kGroup ? nv - g0 : kGroup;
+        for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+            const double wv = (double)w[i];
+#pragma unroll
+            for (int v = 0; v < kGroup; ++v)
+                if (v < cnt) acc[v] += (double)V[(long long)(g0 + v) * n + i] * wv;
+        }
+#pragma unroll
+        for (int v = 0; v < kGroup; ++v) {
+            if (v < cnt) {
+                const double s = block_sum(acc[v], red);
+                if (threadIdx.x == 0) partials[(long long)blockIdx.x * kMaxDots + g0 + v] = s;
+            }
+        }
+    }
+}
+
+// w -= sum_v h[v] V_v; mode 1: also partial ||w||^2 into partials[b]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(const T* __restrict__ V, long long n, int nv,
+                                                   const double* __restrict__ h, T* __restrict__ w,
+                                                   double* __restrict__ partials, int mode) {
+    __shared__ double red[4];
+    __shared__ double hs[kMaxDots];
+    for (int v = threadIdx.x; v < nv; v += kBlock) hs[v] = h[v];
+    __syncthreads();
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double s = (double)w[i];
+        for (int v = 0; v < nv; ++v) s -= hs[v] * (double)V[(long long)v * n + i];
+        const T o = (T)s;
+        w[i] = o;
+        acc += (double)o * (double)o;
+    }
+    if (mode == 1) {
+        const double t = block_sum(acc, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_div(T* __restrict__ x, long long n,
+                                                      const double* __restrict__ d) {
+    const double den = *d;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        x[i] = (T)((double)x[i] / den);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_basis(T* __restrict__ x, const T* __restrict__ Z, long long n,
+                                                       int k, const double* __restrict__ y) {
+    __shared__ double ys[kMaxDots];
+    for (int v = threadIdx.x; v < k; v += kBlock) ys[v] = y[v];
+    __syncthreads();
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double s = (double)x[i];
+        for (int v = 0; v < k; ++v) s += ys[v] * (double)Z[(long long)v * n + i];
+        x[i] = (T)s;
+    }
+}
+
+template <typename Td, typename Ts>
+__global__ __launch_bounds__(kBlock) void k_cast(Td* __restrict__ d, const Ts* __restrict__ s, long long n,
+                                                 double alpha) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        d[i] = (Td)(alpha * (double)s[i]);
+}
+
+template <typename Ts>
+__global__ __launch_bounds__(kBlock) void k_add_to64(double* __restrict__ u, const Ts* __restrict__ d,
+                                                     long long n) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        u[i] = u[i] + (double)d[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpby(T* __restrict__ y, const T* __restrict__ x, long long n,
+                                                  double a, double b) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lincomb(T* __restrict__ o, const T* __restrict__ x,
+                                                    const T* __restrict__ y, long long n, double a, double b) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        o[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+// eps = sqrt(eps_mach) max(||u||, sqrt(N)) / ||v||   (0 when v = 0)
+__global__ void k_fd_eps(const double* unorm2, const double* vnorm2, double sqrt_eps, double sqrt_n,
+                         double* eps) {
+    const double nv = sqrt(*vnorm2);
+    const double nu = sqrt(*unorm2);
+    *eps = nv > 0.0 ? sqrt_eps * (nu > sqrt_n ? nu : sqrt_n) / nv : 0.0;
+}
+
+// Column j of the Hessenberg: h1 + h2 above the diagonal, ||w|| below; apply the
+// previous rotations, form the new one, update g and the residual estimate.
+// Hraw (row-major (m+1) x m) keeps the unrotated column.
+__global__ void k_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
+                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
+                         double* res_est) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i <= j; ++i) {
+        const double h = h1[i] + h2[i];
+        H[i * m + j] = h;
+        Hraw[i * m + j] = h;
+    }
+    const double nw = sqrt(*wnorm2);
+    H[(j + 1) * m + j] = nw;
+    Hraw[(j + 1) * m + j] = nw;
+    *wnorm = nw;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double r = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (r > 0.0) {
+        c = a / r;
+        s = b / r;
+    }
+    cs[j] = c;
+    sn[j] = s;
+    H[j * m + j] = r;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    *res_est = fabs(g[j + 1]);
+}
+
+__global__ void k_backsolve(const double* H, const double* g, int k, int m, double* y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
+        y[i] = s / H[i * m + i];
+    }
+}
+
+__global__ void k_set_start(const double* beta2, double* g, double* beta, int m) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double b = sqrt(*beta2);
+    *beta = b;
+    g[0] = b;
+    for (int i = 1; i <= m; ++i) g[i] = 0.0;
+}
+
+int grid_for(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+int red_blocks(long long n) {
+    long long b = (n + 4LL * kBlock - 1) / (4LL * kBlock);
+    if (b > kMaxPartials) b = kMaxPartials;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename T>
+hipError_t launch_norm2_partial(const T* x, long long n, double* partials, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_norm2_partial<T>), dim3(nblk), dim3(kBlock), 0, s, x, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partials, int nblk, int stride, int cnt, double* out,
+                                  int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(cnt), dim3(kBlock), 0, s, partials, nblk, stride, out, accumulate);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_multidot(const T* V, long long n, int nv, const T* w, double* partials, int nblk,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk), dim3(kBlock), 0, s, V, n, nv, w, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update_dot(const T* V, long long n, int nv, const double* h, T* w, double* partials,
+                             int nblk, int mode, hipStream_t s) {
+    hipLaunchKernelGGL((k_update<T>), dim3(nblk), dim3(kBlock), 0, s, V, n, nv, h, w, partials, mode);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(T* x, long long n, const double* d, hipStream_t s) {
+    hipLaunchKernelGGL((k_scale_div<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, n, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_basis(T* x, const T* Z, long long n, int k, const double* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpy_basis<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, Z, n, k, y);
+    return hipGetLastError();
+}
+
+template <typename Td, typename Ts>
+hipError_t launch_cast(Td* d, const Ts* s_, long long n, double alpha, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<Td, Ts>), dim3(grid_for(n)), dim3(kBlock), 0, s, d, s_, n, alpha);
+    return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t launch_add_to64(double* u, const Ts* d, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((k_add_to64<Ts>), dim3(grid_for(n)), dim3(kBlock), 0, s, u, d, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpby(T* y, const T* x, long long n, double a, double b, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpby<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, y, x, n, a, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lincomb(T* out, const T* x, const T* y, long long n, double a, double b, hipStream_t s) {
+    hipLaunchKernelGGL((k_lincomb<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, out, x, y, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_eps(const double* unorm2, const double* vnorm2, double sqrt_eps_mach, double sqrt_n,
+                         double* eps, hipStream_t s) {
+    hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, unorm2, vnorm2, sqrt_eps_mach, sqrt_n, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
+                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
+                         double* res_est, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, H, Hraw, cs, sn, g, j, m, h1, h2, wnorm2, wnorm, res_est);
+    return hipGetLastError();
+}
+
+hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, s, H, g, k, m, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_start, dim3(1), dim3(1), 0, s, beta2, g, beta, m);
+    return hipGetLastError();
+}
+
+#define JFNK_VINST(T)                                                                                          \
+    template hipError_t launch_norm2_partial<T>(const T*, long long, double*, int, hipStream_t);               \
+    template hipError_t launch_multidot<T>(const T*, long long, int, const T*, double*, int, hipStream_t);      \
+    template hipError_t launch_update_dot<T>(const T*, long long, int, const double*, T*, double*, int, int,   \
+                                             hipStream_t);                                                     \
+    template hipError_t launch_scale<T>(T*, long long, const double*, hipStream_t);                            \
+    template hipError_t launch_axpy_basis<T>(T*, const T*, long long, int, const double*, hipStream_t);        \
+    template hipError_t launch_add_to64<T>(double*, const T*, long long, hipStream_t);                         \
+    template hipError_t launch_axpby<T>(T*, const T*, long long, double, double, hipStream_t);                 \
+    template hipError_t launch_lincomb<T>(T*, const T*, const T*, long long, double, double, hipStream_t);
+JFNK_VINST(double)
+JFNK_VINST(float)
+#undef JFNK_VINST
+template hipError_t launch_cast<float, double>(float*, const double*, long long, double, hipStream_t);
+template hipError_t launch_cast<double, float>(double*, const float*, long long, double, hipStream_t);
+template hipError_t launch_cast<double, double>(double*, const double*, long long, double, hipStream_t);
+template hipError_t launch_cast<float, float>(float*, const float*, long long, double, hipStream_t);
+
+}  // namespace jfnk

@@ -1,0 +1,168 @@
+"""Python view of the JFNK C ABI with the same entry-point names.
+
+Arrays are torch CUDA (HIP) tensors of shape ``(n_f, nz, ny, nx)`` (or any shape
+with that many contiguous elements); torch supplies device memory and the
+stream.  Argument marshalling only: every step runs in ``libjfnk.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+DTYPES = {"f64": L.F64, "f32": L.F32}
+PCS = {"none": L.PC_NONE, "physics": L.PC_PHYSICS, "learned": L.PC_LEARNED}
+JVS = {"stable": L.JV_STABLE, "literal": L.JV_LITERAL, "analytic": L.JV_ANALYTIC}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dcode(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return L.F64
+    if t.dtype == torch.float32:
+        return L.F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("arrays must be contiguous device tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class GmresResult:
+    iters: int
+    restarts: int
+    converged: bool
+    res0: float
+    res_est: float
+    H: np.ndarray = None
+
+
+@dataclass
+class NewtonResult:
+    newton_iters: int
+    gmres_iters_total: int
+    converged: bool
+    res0: float
+    res_final: float
+
+
+class Context:
+    """One problem on the current device (``jfnk_create`` / ``jfnk_destroy``)."""
+
+    def __init__(self, prob, max_m: int = 30, stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.prob = prob
+        self.n = prob.n
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._stream = s
+        h = C.c_void_p()
+        ps = L.problem_struct(prob)
+        L.check(self.lib.jfnk_create(C.byref(ps), int(max_m), C.c_void_p(s.cuda_stream), C.byref(h)),
+                "jfnk_create", soft_ok=False)
+        self.h = h
+        self.max_m = max_m
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.jfnk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_size(self, *ts):
+        for t in ts:
+            if t is not None and t.numel() != self.n:
+                raise ValueError(f"expected {self.n} elements, got {t.numel()}")
+
+    # -- operators ------------------------------------------------------------
+    def rhs(self, u_n, f):
+        self._check_size(u_n, f)
+        L.check(self.lib.jfnk_rhs(self.h, _ptr(u_n), _ptr(f)), "jfnk_rhs", soft_ok=False)
+        return f
+
+    def residual(self, u, f, R):
+        self._check_size(u, f, R)
+        L.check(self.lib.jfnk_residual(self.h, _ptr(u), _ptr(f), _ptr(R)), "jfnk_residual", soft_ok=False)
+        return R
+
+    def apply_F(self, u, out, what=0, f=None):
+        self._check_size(u, f, out)
+        L.check(self.lib.jfnk_apply_F(self.h, _dcode(u), int(what), _ptr(u), _ptr(f), _ptr(out)),
+                "jfnk_apply_F", soft_ok=False)
+        return out
+
+    def jv(self, u, v, out, mode="stable", eps=0.0):
+        self._check_size(u, v, out)
+        L.check(self.lib.jfnk_jv(self.h, _dcode(u), JVS[mode], _ptr(u), _ptr(v), float(eps), _ptr(out)),
+                "jfnk_jv", soft_ok=False)
+        return out
+
+    def precond_apply(self, u, r, z, pc="physics", sweeps=2):
+        self._check_size(u, r, z)
+        L.check(self.lib.jfnk_precond_apply(self.h, PCS[pc], _dcode(u), _ptr(u), _ptr(r), _ptr(z), int(sweeps)),
+                "jfnk_precond_apply", soft_ok=False)
+        return z
+
+    def gmres(self, u, b, x, m=30, max_restarts=20, tol=1e-6, pc="physics", jv="stable", sweeps=2,
+              max_iters=0, want_H=False):
+        self._check_size(u, b, x)
+        o = L.GmresOpts(m=m, max_restarts=max_restarts, tol=tol, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
+                        max_iters=max_iters)
+        info = L.GmresInfo()
+        Hbuf = None
+        if want_H:
+            Hbuf = (C.c_double * ((m + 1) * m))()
+            info.h_out = C.cast(Hbuf, C.POINTER(C.c_double))
+        L.check(self.lib.jfnk_gmres(self.h, _dcode(u), _ptr(u), _ptr(b), _ptr(x), C.byref(o), C.byref(info)),
+                "jfnk_gmres")
+        H = np.ctypeslib.as_array(Hbuf).reshape(m + 1, m).copy() if want_H else None
+        return GmresResult(info.iters, info.restarts, bool(info.converged), info.res0, info.res_est, H)
+
+    def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, inner="f64",
+                    m=30, max_restarts=20, pc="physics", jv="stable", sweeps=2, forcing="ew", eta=1e-2,
+                    eta_floor=0.0):
+        self._check_size(u_n, u_np1)
+        gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
+                         max_iters=0)
+        o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=DTYPES[inner],
+                         gm=gm, forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
+        info = L.NewtonInfo()
+        L.check(self.lib.jfnk_newton_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), C.byref(info)),
+                "jfnk_newton_step")
+        return NewtonResult(info.newton_iters, info.gmres_iters_total, bool(info.converged), info.res0,
+                            info.res_final)
+
+    def norm(self, x):
+        out = C.c_double()
+        L.check(self.lib.jfnk_norm(self.h, _dcode(x), _ptr(x), x.numel(), C.byref(out)), "jfnk_norm",
+                soft_ok=False)
+        return out.value
+
+    # -- timing ----------------------------------------------------------------
+    def timing(self, on: bool):
+        L.check(self.lib.jfnk_timing_enable(self.h, 1 if on else 0), "jfnk_timing_enable", soft_ok=False)
+
+    def timing_read(self, cls):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        L.check(self.lib.jfnk_timing_read(self.h, int(cls), C.byref(ms), C.byref(cnt)), "jfnk_timing_read",
+                soft_ok=False)
+        return ms.value, cnt.value
