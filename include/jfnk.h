@@ -181,11 +181,16 @@ int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
 /* 2-norm of a vector of n values (FP64 accumulation), result to a host double.   */
 int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* out);
 
-/* Kernel timing with HIP events on the context stream.  Kernel classes:
- * 0 Jv, 1 residual/rhs, 2 physics preconditioner sweep, 3 Arnoldi passes,
- * 4 other vector kernels.  enable = 1 starts recording (clears the counters).    */
+/* Kernel timing with HIP events recorded on the context stream around each
+ * launch (resolved lazily, no synchronisation per launch).  Kernel classes:
+ * 0 Jv, 1 residual/rhs, 2 physics preconditioner (diagonal start and sweeps),
+ * 3 Arnoldi (the three Gram-Schmidt passes of one iteration with their
+ * finishing reductions and the Givens step), 4 other.  enable = 1 starts
+ * recording and clears the counters.  bytes receives the algorithmic HBM bytes
+ * of the recorded launches (each array element moved once per launch).         */
 int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
-int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
+int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches,
+                     double* bytes);
 
 #ifdef __cplusplus
 }

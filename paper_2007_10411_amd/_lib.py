@@ -85,7 +85,8 @@ def load():
     L.jfnk_newton_step.argtypes = [vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)]
     L.jfnk_norm.argtypes = [vp, C.c_int, vp, C.c_int64, C.POINTER(C.c_double)]
     L.jfnk_timing_enable.argtypes = [vp, C.c_int32]
-    L.jfnk_timing_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.jfnk_timing_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name != "jfnk_last_error":
             getattr(L, name).restype = C.c_int

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "jfnk_internal.hpp"
+#include "reduce.hpp"
 
 namespace jfnk {
 
@@ -25,7 +26,7 @@ constexpr int O_Y = O_G + M + 1;
 constexpr int O_H1 = O_Y + M;
 constexpr int O_H2 = O_H1 + M;
 constexpr int O_S = O_H2 + M;         // misc scalars
-enum { S_UNORM2 = 0, S_VNORM2, S_EPS, S_WNORM2, S_WNORM, S_RES, S_BETA2, S_BETA, S_TMP, S_COUNT = 16 };
+enum { S_UNORM2 = 0, S_VNORM2, S_EPS, S_WNORM2, S_WNORM, S_RES, S_BETA2, S_BETA, S_TMP, S_SLOT0 = 10, S_COUNT = 16 };
 constexpr int kScal = O_S + S_COUNT;
 
 double* ds(jfnk_ctx* c, int off) { return c->dscal + off; }
@@ -55,8 +56,9 @@ struct TimedLaunch {
     jfnk_ctx* c;
     int cls;
     bool active;
-    TimedLaunch(jfnk_ctx* c_, int cls_) : c(c_), cls(cls_), active(c_->timing.on) {
+    TimedLaunch(jfnk_ctx* c_, int cls_, double bytes = 0.0) : c(c_), cls(cls_), active(c_->timing.on) {
         if (!active) return;
+        c->timing.bytes[cls] += bytes;
         auto& T = c->timing;
         if ((int)T.ev[cls].size() < 2 * (T.used[cls] + 1)) {
             hipEvent_t a, b;
@@ -168,7 +170,7 @@ int apply_jv(jfnk_ctx* c, int mode, const T* u, const T* v, const double* eps_de
         JFNK_HIP(launch_lincomb<T>(out, w2, w1, c->n, 1.0 / e, -1.0 / e, c->stream));
         return JFNK_OK;
     }
-    TimedLaunch tl(c, KC_JV);
+    TimedLaunch tl(c, KC_JV, 3.0 * c->n * sizeof(T));
     if (mode == JFNK_JV_ANALYTIC)
         JFNK_HIP(launch_jv<T>(c->geo, u, v, 0.0, nullptr, out, c->stream));
     else
@@ -186,11 +188,26 @@ int fd_eps_dev(jfnk_ctx* c, const T* v) {
     return JFNK_OK;
 }
 
-// z = P^{-1} r by the physics preconditioner (nu frozen beforehand), or copy
+EpsArgs eps_args(jfnk_ctx* c, double eps_mach_v) {
+    EpsArgs a;
+    a.partials = c->epart;
+    a.unorm2 = sc(c, S_UNORM2);
+    a.vnorm2 = sc(c, S_VNORM2);
+    a.eps = sc(c, S_EPS);
+    a.sqrt_eps = std::sqrt(eps_mach_v);
+    a.sqrt_n = std::sqrt((double)c->n);
+    return a;
+}
+
+// z = P^{-1} v by the physics preconditioner (nu frozen beforehand) or z = v,
+// where v = V_j / *div is first written back into V_j (div may be null).  When
+// ea.partials is set, the FD step for direction z is formed on the way.
 template <typename T>
-int apply_pc(jfnk_ctx* c, int pc, const T* u, const T* r, T* z, int sweeps, T* scratch) {
+int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, int sweeps, T* scratch,
+             const EpsArgs& ea) {
     if (pc == JFNK_PC_NONE) {
-        JFNK_HIP(hipMemcpyAsync(z, r, c->n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        TimedLaunch tl(c, KC_PC);
+        JFNK_HIP(launch_normalize_copy<T>(vj, c->n, div, z, ea, c->stream));
         return JFNK_OK;
     }
     if (pc != JFNK_PC_PHYSICS) {
@@ -198,16 +215,19 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, const T* r, T* z, int sweeps, T* s
         return JFNK_ERR_ARG;
     }
     const T* nu = NUb<T>(c);
+    EpsArgs none;
     // ping-pong so that the last sweep lands in z
     T* bufs[2] = {z, scratch};
     int cur = (sweeps % 2 == 0) ? 0 : 1;
+    const double npts = (double)c->geo.npts;
     {
-        TimedLaunch tl(c, KC_PC);
-        JFNK_HIP(launch_pc_diag<T>(c->geo, nu, r, bufs[cur], c->stream));
+        TimedLaunch tl(c, KC_PC, ((div ? 3.0 : 2.0) * c->n + npts) * sizeof(T));
+        JFNK_HIP(launch_pc_diag<T>(c->geo, nu, vj, div, bufs[cur], sweeps == 0 ? ea : none, c->stream));
     }
     for (int s = 0; s < sweeps; ++s) {
-        TimedLaunch tl(c, KC_PC);
-        JFNK_HIP(launch_pc_sweep<T>(c->geo, u, nu, r, bufs[cur], bufs[1 - cur], c->stream));
+        TimedLaunch tl(c, KC_PC, (3.0 * c->n + (c->geo.dim + 1) * npts) * sizeof(T));
+        JFNK_HIP(launch_pc_sweep<T>(c->geo, u, nu, vj, bufs[cur], bufs[1 - cur], s == sweeps - 1 ? ea : none,
+                                    c->stream));
         cur = 1 - cur;
     }
     return JFNK_OK;
@@ -245,45 +265,77 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
         if (info) info->converged = 1;
         return JFNK_OK;
     }
-    const int nb = red_blocks(n);
-    int total = 0, restarts = 0;
+    const EpsArgs ea = o.jv == JFNK_JV_ANALYTIC ? EpsArgs() : eps_args(c, eps_mach<T>());
+    GivensArgs ga;
+    ga.H = ds(c, O_H);
+    ga.Hraw = ds(c, O_HRAW);
+    ga.cs = ds(c, O_CS);
+    ga.sn = ds(c, O_SN);
+    ga.g = ds(c, O_G);
+    ga.h1 = ds(c, O_H1);
+    ga.h2 = ds(c, O_H2);
+    ga.wnorm = sc(c, S_WNORM);
+    ga.res_est = sc(c, S_RES);
+    ga.m = m;
+    GivensArgs gnone;
+    int total = 0, restarts = 0, enqueued = 0;
     bool converged = false;
     double res_est = bnorm;
+    // Iteration j+1 is enqueued before the host tests iteration j (two pinned
+    // result slots); when j has converged the speculative j+1 is discarded: it
+    // only wrote column j+1 of H, g[j+1] and V_{j+2}, Z_{j+1}, none of which the
+    // back substitution over the first j+1 columns reads.
+    auto enqueue_iter = [&](int j) -> int {
+        T* Vj = V + (long long)j * n;
+        T* Vn = V + (long long)(j + 1) * n;
+        T* Zj = Z + (long long)j * n;
+        // v_j = w_j / ||w_j|| (beta at the start of a cycle), z_j = M^-1 v_j, FD step for z_j
+        const double* div = j == 0 ? sc(c, S_BETA) : sc(c, S_WNORM);
+        int r;
+        if ((r = apply_pc<T>(c, o.pc, u, Vj, div, Zj, o.sweeps, Vn, ea))) return r;
+        if ((r = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return r;
+        {
+            // classical Gram-Schmidt, twice; the Givens step of column j rides on the last pass
+            // dot pass reads V_0..V_j and w; each update pass also writes w
+            TimedLaunch tl(c, KC_ARNOLDI, (3.0 * (j + 1) + 5.0) * n * sizeof(T));
+            ga.j = j;
+            JFNK_HIP(launch_cgs<T>(V, n, j + 1, nullptr, Vn, c->partials, ds(c, O_H1), CGS_DOT, gnone, s));
+            JFNK_HIP(launch_cgs<T>(V, n, j + 1, ds(c, O_H1), Vn, c->partials, ds(c, O_H2), CGS_UPD_DOT, gnone, s));
+            JFNK_HIP(launch_cgs<T>(V, n, j + 1, ds(c, O_H2), Vn, c->partials, sc(c, S_WNORM2), CGS_UPD_NORM, ga,
+                                   s));
+        }
+        const int slot = j & 1;
+        JFNK_HIP(hipMemcpyAsync(c->hscal + S_SLOT0 + 2 * slot, sc(c, S_WNORM), 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        JFNK_HIP(hipEventRecord(c->slot_ev[slot], s));
+        ++enqueued;
+        return JFNK_OK;
+    };
+    // wait for iteration j and decide whether the cycle stops after it
+    auto finish_iter = [&](int j, bool& stop) -> int {
+        const int slot = j & 1;
+        JFNK_HIP(hipEventSynchronize(c->slot_ev[slot]));
+        const double wn = c->hscal[S_SLOT0 + 2 * slot];
+        res_est = c->hscal[S_SLOT0 + 2 * slot + 1];
+        if (!std::isfinite(wn) || !std::isfinite(res_est)) {
+            set_error("non-finite Krylov norm");
+            return JFNK_ERR_NONFINITE;
+        }
+        ++total;
+        stop = res_est <= o.tol * bnorm || wn == 0.0 || total >= max_iters;
+        return JFNK_OK;
+    };
     while (true) {
-        JFNK_HIP(launch_scale<T>(V, n, sc(c, S_BETA), s));
         int k = 0;
         bool done = false;
+        if ((rc = enqueue_iter(0))) return rc;
         for (int j = 0; j < m; ++j) {
-            T* Vj = V + (long long)j * n;
-            T* Vn = V + (long long)(j + 1) * n;
-            T* Zj = Z + (long long)j * n;
-            if ((rc = apply_pc<T>(c, o.pc, u, Vj, Zj, o.sweeps, Vn))) return rc;
-            if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, Zj))) return rc;
-            if ((rc = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return rc;
-            {
-                TimedLaunch tl(c, KC_ARNOLDI);
-                // classical Gram-Schmidt, twice
-                JFNK_HIP(launch_multidot<T>(V, n, j + 1, Vn, c->partials, nb, s));
-                JFNK_HIP(launch_reduce_partials(c->partials, nb, kMaxDots, j + 1, ds(c, O_H1), 0, s));
-                JFNK_HIP(launch_update_dot<T>(V, n, j + 1, ds(c, O_H1), Vn, c->partials, nb, 0, s));
-                JFNK_HIP(launch_multidot<T>(V, n, j + 1, Vn, c->partials, nb, s));
-                JFNK_HIP(launch_reduce_partials(c->partials, nb, kMaxDots, j + 1, ds(c, O_H2), 0, s));
-                JFNK_HIP(launch_update_dot<T>(V, n, j + 1, ds(c, O_H2), Vn, c->partials, nb, 1, s));
-                JFNK_HIP(launch_reduce_partials(c->partials, nb, 1, 1, sc(c, S_WNORM2), 0, s));
-            }
-            JFNK_HIP(launch_givens(ds(c, O_H), ds(c, O_HRAW), ds(c, O_CS), ds(c, O_SN), ds(c, O_G), j, m, ds(c, O_H1),
-                                   ds(c, O_H2), sc(c, S_WNORM2), sc(c, S_WNORM), sc(c, S_RES), s));
-            if ((rc = read_scalars(c, S_WNORM, 2))) return rc;
-            const double wn = c->hscal[S_WNORM];
-            res_est = c->hscal[S_RES];
-            if (!std::isfinite(wn) || !std::isfinite(res_est)) {
-                set_error("non-finite Krylov norm");
-                return JFNK_ERR_NONFINITE;
-            }
-            if (wn > 0.0) JFNK_HIP(launch_scale<T>(Vn, n, sc(c, S_WNORM), s));
+            if (j + 1 < m && enqueued < max_iters)
+                if ((rc = enqueue_iter(j + 1))) return rc;
+            bool stop = false;
+            if ((rc = finish_iter(j, stop))) return rc;
             k = j + 1;
-            ++total;
-            if (res_est <= o.tol * bnorm || wn == 0.0 || total >= max_iters) {
+            if (stop) {
                 done = true;
                 break;
             }
@@ -436,10 +488,19 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     ALLOC(c->bg32, nbg * sizeof(float));
     ALLOC(c->partials, (size_t)kMaxPartials * kMaxDots * sizeof(double));
     ALLOC(c->dscal, kScal * sizeof(double));
+    {
+        const long long tiles = (long long)((g.nx + 63) / 64) * ((g.nz + 7) / 8) * (g.dim == 3 ? g.ny : 1);
+        const long long ne = std::max(tiles, (g.npts + 255) / 256) + 1024;
+        ALLOC(c->epart, (size_t)ne * sizeof(double));
+    }
 #undef ALLOC
     {
         hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return fail(e, "hipHostMalloc");
+        for (int k = 0; k < 2; ++k) {
+            e = hipEventCreateWithFlags(&c->slot_ev[k], hipEventDisableTiming);
+            if (e != hipSuccess) return fail(e, "hipEventCreate");
+        }
     }
     g.pbar64 = c->bg64;
     g.dpbar64 = c->bg64 + g.nz;
@@ -467,10 +528,12 @@ int jfnk_destroy(jfnk_ctx* c) {
     if (!c) return JFNK_OK;
     (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->V64, c->Z64, c->V32, c->Z32, c->f64, c->R64, c->t64a, c->t64b, c->b64, c->x64, c->nu64, c->u32, c->b32,
-                    c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal};
+                    c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal, c->epart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (c->hscal) (void)hipHostFree(c->hscal);
+    for (int k = 0; k < 2; ++k)
+        if (c->slot_ev[k]) (void)hipEventDestroy(c->slot_ev[k]);
     for (int k = 0; k < KC_COUNT; ++k)
         for (auto e : c->timing.ev[k]) (void)hipEventDestroy(e);
     delete c;
@@ -540,7 +603,8 @@ int jfnk_precond_apply(jfnk_ctx* c, jfnk_pc_kind pc, jfnk_dtype dt, const void* 
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         if (pc == JFNK_PC_PHYSICS) JFNK_HIP(launch_frozen_nu<T>(c->geo, (const T*)u, NUb<T>(c), c->stream));
-        return apply_pc<T>(c, pc, (const T*)u, (const T*)r, (T*)z, sweeps, TA<T>(c));
+        // div = null: r is read, never written
+        return apply_pc<T>(c, pc, (const T*)u, (T*)r, nullptr, (T*)z, sweeps, TA<T>(c), EpsArgs());
     };
     if (dt == JFNK_F64) return run(double(0));
     if (dt == JFNK_F32) return run(float(0));
@@ -681,12 +745,13 @@ int jfnk_timing_enable(jfnk_ctx* c, int32_t enable) {
     for (int k = 0; k < KC_COUNT; ++k) {
         c->timing.ms[k] = 0.0;
         c->timing.launches[k] = 0;
+        c->timing.bytes[k] = 0.0;
     }
     c->timing.on = enable != 0;
     return JFNK_OK;
 }
 
-int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launches) {
+int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launches, double* bytes) {
     if (!c || cls < 0 || cls >= KC_COUNT) {
         set_error("invalid argument to jfnk_timing_read");
         return JFNK_ERR_ARG;
@@ -694,6 +759,7 @@ int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launch
     resolve_timing(c);
     if (total_ms) *total_ms = c->timing.ms[cls];
     if (launches) *launches = c->timing.launches[cls];
+    if (bytes) *bytes = c->timing.bytes[cls];
     return JFNK_OK;
 }
 

@@ -48,6 +48,36 @@ template <> struct Bg<float> {
     static __device__ __forceinline__ const float* sflux(const Geo& g) { return g.sflux32; }
 };
 
+// Arguments of the FP64 Givens step of GMRES column j (device pointers;
+// host = optional pinned mirror receiving (||w||, |g_{j+1}|)).
+struct GivensArgs {
+    double* H = nullptr;
+    double* Hraw = nullptr;
+    double* cs = nullptr;
+    double* sn = nullptr;
+    double* g = nullptr;
+    const double* h1 = nullptr;
+    const double* h2 = nullptr;
+    double* wnorm = nullptr;
+    double* res_est = nullptr;
+    double* host = nullptr;
+    int j = 0;
+    int m = 0;
+};
+
+// Finite-difference step of the Jacobian-vector product from squared norms:
+// eps = sqrt(eps_mach) max(||u||, sqrt(N)) / ||v||  (0 when v = 0).
+struct EpsArgs {
+    double* partials = nullptr;   // null: no norm requested
+    const double* unorm2 = nullptr;
+    double* vnorm2 = nullptr;
+    double* eps = nullptr;
+    double sqrt_eps = 0.0;
+    double sqrt_n = 0.0;
+};
+
+enum CgsMode { CGS_DOT = 0, CGS_UPD_DOT = 1, CGS_UPD_NORM = 2 };
+
 enum KernelClass { KC_JV = 0, KC_RESIDUAL = 1, KC_PC = 2, KC_ARNOLDI = 3, KC_VEC = 4, KC_COUNT = 5 };
 
 constexpr int kMaxPartials = 2048;   // blocks of a reduction grid
@@ -61,6 +91,7 @@ struct Timing {
     int used[KC_COUNT] = {0};
     double ms[KC_COUNT] = {0};
     long long launches[KC_COUNT] = {0};
+    double bytes[KC_COUNT] = {0};           // algorithmic HBM bytes of the timed launches
 };
 
 }  // namespace jfnk
@@ -98,8 +129,10 @@ struct jfnk_ctx {
     float* bg32 = nullptr;
     // reductions and small device state
     double* partials = nullptr; // kMaxPartials * kMaxDots
+    double* epart = nullptr;    // per-block partials of the FD-step norm
     double* dscal = nullptr;    // device scalars (see solver)
     double* hscal = nullptr;    // pinned host mirror
+    hipEvent_t slot_ev[2] = {nullptr, nullptr};  // GMRES result slots in flight
     jfnk::Timing timing;
 };
 
@@ -129,9 +162,12 @@ hipError_t launch_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
 // (zin == nullptr: zin = r/d)
 template <typename T>
 hipError_t launch_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
-                           hipStream_t s);
+                           const EpsArgs& ea, hipStream_t s);
+// z = v / d with v = V_j / *div written back into V_j when div != null; the norm of
+// z (for the FD step) when ea.partials != null
 template <typename T>
-hipError_t launch_pc_diag(const Geo& g, const T* nu, const T* r, T* z, hipStream_t s);
+hipError_t launch_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
+                          hipStream_t s);
 
 // ---- vector kernels (vec.hip) ----
 int red_blocks(long long n);
@@ -163,9 +199,14 @@ hipError_t launch_lincomb(T* out, const T* x, const T* y, long long n, double a,
 // small single-thread kernels on the device scalars
 hipError_t launch_fd_eps(const double* unorm2, const double* vnorm2, double sqrt_eps_mach, double sqrt_n,
                          double* eps, hipStream_t s);
-hipError_t launch_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
-                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
-                         double* res_est, hipStream_t s);
+hipError_t launch_givens(const GivensArgs& a, const double* wnorm2, hipStream_t s);
+int cgs_blocks(long long n);
+template <typename T>
+hipError_t launch_cgs(const T* V, long long n, int nv, const double* hin, T* w, double* partials,
+                      double* hout, int mode, const GivensArgs& ga, hipStream_t s);
+hipError_t launch_eps_finish(int nblk, const EpsArgs& ea, hipStream_t s);
+template <typename T>
+hipError_t launch_normalize_copy(T* v, long long n, const double* div, T* z, const EpsArgs& ea, hipStream_t s);
 hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s);
 hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m, hipStream_t s);
 

@@ -19,6 +19,7 @@
 // wavefront reads 64 consecutive points of a row (coalesced).
 
 #include "jfnk_internal.hpp"
+#include "reduce.hpp"
 
 namespace jfnk {
 
@@ -388,36 +389,53 @@ __device__ __forceinline__ void pc_coeffs(const Geo& g, T nu_pt, T& kmom, T& kth
     }
 }
 
+// Start of the Jacobi iteration, z0 = v / d, fused with the normalisation of
+// the incoming Krylov vector (v = V_j / *div written back) and, when no sweep
+// follows, the norm of z for the finite-difference step.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pc_diag_2d(Geo g, const T* __restrict__ nu, const T* __restrict__ r,
-                                                    T* __restrict__ z) {
+__global__ __launch_bounds__(256) void k_pc_diag_2d(Geo g, const T* __restrict__ nu, T* __restrict__ vj,
+                                                    const double* __restrict__ div, T* __restrict__ z,
+                                                    EpsArgs ea) {
+    __shared__ double red[4];
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.npts) return;
-    const long long ie = (i / g.nx + 2) * (long long)(g.nx + 4) + (i % g.nx) + 2;
-    T km, kt;
-    pc_coeffs(g, nu[ie], km, kt);
-    const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
-    const T cD = T(65.0 / 72.0);
-    const T dm = T(g.two_dt) + cD * km * ih2;
-    const T dt_ = T(g.two_dt) + cD * kt * ih2;
-    const T dp = T(g.two_dt);
-    const long long np = g.npts;
-    z[i] = r[i] / dm;
-    z[np + i] = r[np + i] / dm;
-    z[2 * np + i] = r[2 * np + i] / dp;
-    z[3 * np + i] = r[3 * np + i] / dt_;
+    double acc = 0.0;
+    if (i < g.npts) {
+        const long long ie = (i / g.nx + 2) * (long long)(g.nx + 4) + (i % g.nx) + 2;
+        T km, kt;
+        pc_coeffs(g, nu[ie], km, kt);
+        const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
+        const T cD = T(65.0 / 72.0);
+        const T dd[4] = {T(g.two_dt) + cD * km * ih2, T(g.two_dt) + cD * km * ih2, T(g.two_dt),
+                         T(g.two_dt) + cD * kt * ih2};
+        const long long np = g.npts;
+        const double dv = div ? *div : 1.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T v = vj[k * np + i];
+            if (div) {
+                v = (T)((double)v / dv);
+                vj[k * np + i] = v;
+            }
+            const T zz = v / dd[k];
+            z[k * np + i] = zz;
+            acc += (double)zz * (double)zz;
+        }
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
 }
 
 template <typename T, int TX, int TZ>
 __global__ __launch_bounds__(256) void k_pc_sweep_2d(Geo g, const T* __restrict__ u, const T* __restrict__ nu,
                                                      const T* __restrict__ r, const T* __restrict__ zin,
-                                                     T* __restrict__ zout) {
+                                                     T* __restrict__ zout, EpsArgs ea) {
     constexpr int SX = TX + 2 * kHalo, SZ = TZ + 2 * kHalo, PS = SZ * SX;
     constexpr int DX = TX + 4, DZ = TZ + 4, DS = DZ * DX;
     __shared__ T sz_[4 * PS];   // z, halo 4
     __shared__ T sv[2 * DS];    // frozen velocity, halo 2
     __shared__ T sn[DS];        // frozen viscosity, halo 2
     __shared__ T sf[6 * DS];    // K D_x z, K D_z z for u, w, theta on ring 2
+    __shared__ double red[4];
+    double zacc = 0.0;
     const int x0 = blockIdx.x * TX, z0 = blockIdx.y * TZ;
     const T ihx = T(g.idx), ihz = T(g.idz);
     const long long np = g.npts;
@@ -491,9 +509,12 @@ __global__ __launch_bounds__(256) void k_pc_sweep_2d(Geo g, const T* __restrict_
             }
             const T Pz = T(g.two_dt) * zc + (cv - diff);
             const T d = T(g.two_dt) + cD * kk * ih2;
-            zout[k * np + off] = zc + (r[k * np + off] - Pz) / d;
+            const T zn = zc + (r[k * np + off] - Pz) / d;
+            zout[k * np + off] = zn;
+            zacc += (double)zn * (double)zn;
         }
     }
+    if (ea.partials) partial_eps(ea, zacc, red);
 }
 
 }  // namespace
@@ -528,26 +549,33 @@ hipError_t launch_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_pc_diag(const Geo& g, const T* nu, const T* r, T* z, hipStream_t s) {
+hipError_t launch_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
+                          hipStream_t s) {
     const int nb = (int)((g.npts + 255) / 256);
-    hipLaunchKernelGGL((k_pc_diag_2d<T>), dim3(nb), dim3(256), 0, s, g, nu, r, z);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_pc_diag_2d<T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ea.partials) return e;
+    return launch_eps_finish(nb, ea, s);
 }
 
 template <typename T>
 hipError_t launch_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
-                           hipStream_t s) {
+                           const EpsArgs& ea, hipStream_t s) {
     dim3 grid((g.nx + kTX - 1) / kTX, (g.nz + kTZ - 1) / kTZ);
-    hipLaunchKernelGGL((k_pc_sweep_2d<T, kTX, kTZ>), grid, dim3(256), 0, s, g, u, nu, r, zin, zout);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_pc_sweep_2d<T, kTX, kTZ>), grid, dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ea.partials) return e;
+    return launch_eps_finish((int)(grid.x * grid.y), ea, s);
 }
 
 #define JFNK_INST(T)                                                                                        \
     template hipError_t launch_apply_F<T>(const Geo&, const T*, const T*, T*, int, hipStream_t);             \
     template hipError_t launch_jv<T>(const Geo&, const T*, const T*, double, const double*, T*, hipStream_t); \
     template hipError_t launch_frozen_nu<T>(const Geo&, const T*, T*, hipStream_t);                          \
-    template hipError_t launch_pc_diag<T>(const Geo&, const T*, const T*, T*, hipStream_t);                  \
-    template hipError_t launch_pc_sweep<T>(const Geo&, const T*, const T*, const T*, const T*, T*, hipStream_t);
+    template hipError_t launch_pc_diag<T>(const Geo&, const T*, T*, const double*, T*, const EpsArgs&,       \
+                                          hipStream_t);                                                      \
+    template hipError_t launch_pc_sweep<T>(const Geo&, const T*, const T*, const T*, const T*, T*,            \
+                                           const EpsArgs&, hipStream_t);
 JFNK_INST(double)
 JFNK_INST(float)
 #undef JFNK_INST

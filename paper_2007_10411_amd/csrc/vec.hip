@@ -4,6 +4,7 @@
 // (Saad and Schultz 1986).
 
 #include "jfnk_internal.hpp"
+#include "reduce.hpp"
 
 namespace jfnk {
 
@@ -174,38 +175,46 @@ __global__ void k_fd_eps(const double* unorm2, const double* vnorm2, double sqrt
 // Column j of the Hessenberg: h1 + h2 above the diagonal, ||w|| below; apply the
 // previous rotations, form the new one, update g and the residual estimate.
 // Hraw (row-major (m+1) x m) keeps the unrotated column.
-__global__ void k_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
-                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
-                         double* res_est) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void givens_column(const GivensArgs& a, double wnorm2) {
+    const int j = a.j, m = a.m;
+    double* H = a.H;
     for (int i = 0; i <= j; ++i) {
-        const double h = h1[i] + h2[i];
+        const double h = a.h1[i] + a.h2[i];
         H[i * m + j] = h;
-        Hraw[i * m + j] = h;
+        a.Hraw[i * m + j] = h;
     }
-    const double nw = sqrt(*wnorm2);
+    const double nw = sqrt(wnorm2);
     H[(j + 1) * m + j] = nw;
-    Hraw[(j + 1) * m + j] = nw;
-    *wnorm = nw;
+    a.Hraw[(j + 1) * m + j] = nw;
+    *a.wnorm = nw;
     for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * b;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+        const double x = H[i * m + j], y = H[(i + 1) * m + j];
+        H[i * m + j] = a.cs[i] * x + a.sn[i] * y;
+        H[(i + 1) * m + j] = -a.sn[i] * x + a.cs[i] * y;
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j];
-    const double r = hypot(a, b);
-    double c = 1.0, s = 0.0;
+    const double x = H[j * m + j], y = H[(j + 1) * m + j];
+    const double r = hypot(x, y);
+    double c = 1.0, sn = 0.0;
     if (r > 0.0) {
-        c = a / r;
-        s = b / r;
+        c = x / r;
+        sn = y / r;
     }
-    cs[j] = c;
-    sn[j] = s;
+    a.cs[j] = c;
+    a.sn[j] = sn;
     H[j * m + j] = r;
     H[(j + 1) * m + j] = 0.0;
-    g[j + 1] = -s * g[j];
-    g[j] = c * g[j];
-    *res_est = fabs(g[j + 1]);
+    a.g[j + 1] = -sn * a.g[j];
+    a.g[j] = c * a.g[j];
+    *a.res_est = fabs(a.g[j + 1]);
+    if (a.host) {                       // mirror for the host's convergence test
+        a.host[0] = nw;
+        a.host[1] = *a.res_est;
+    }
+}
+
+__global__ void k_givens(GivensArgs a, const double* wnorm2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    givens_column(a, *wnorm2);
 }
 
 __global__ void k_backsolve(const double* H, const double* g, int k, int m, double* y) {
@@ -223,6 +232,172 @@ __global__ void k_set_start(const double* beta2, double* g, double* beta, int m)
     *beta = b;
     g[0] = b;
     for (int i = 1; i <= m; ++i) g[i] = 0.0;
+}
+
+
+// ---------------------------------------------------------------------------
+// Fused classical Gram-Schmidt passes over the basis V_0..V_{nv-1}:
+//   CGS_DOT       hout = V^T w
+//   CGS_UPD_DOT   w <- w - V hin, hout = V^T w          (basis values reused from registers)
+//   CGS_UPD_NORM  w <- w - V hin, ||w||^2, then the Givens step of column j
+// Partial sums per block are finished by the last block of the same launch.
+// ---------------------------------------------------------------------------
+// Chunks of kChunk consecutive elements: V_0..V_{nv-1} of the chunk are staged
+// in LDS once; each thread updates its own element of w, then wavefront k forms
+// the dots of basis vectors k, k+4, ... with the chunk of w (FP64 accumulation).
+constexpr int kChunk = 256;
+
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_cgs(const T* __restrict__ V, long long n, int nv,
+                                                const double* __restrict__ hin, T* __restrict__ w,
+                                                double* __restrict__ partials, int mode) {
+    __shared__ T sV[NV][kChunk];
+    __shared__ T sW[kChunk];
+    __shared__ double hs[NV];
+    __shared__ double red[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int v = tid; v < NV; v += kBlock) hs[v] = (mode != CGS_DOT && v < nv) ? hin[v] : 0.0;
+    __syncthreads();
+    constexpr int KPW = NV / 4;               // basis vectors per wavefront
+    double acc[KPW];
+#pragma unroll
+    for (int k = 0; k < KPW; ++k) acc[k] = 0.0;
+    double nacc = 0.0;
+    const long long step = (long long)gridDim.x * kChunk;
+    for (long long c0 = (long long)blockIdx.x * kChunk; c0 < n; c0 += step) {
+        const long long i = c0 + tid;
+        const bool ok = i < n;
+        T wv = ok ? w[i] : T(0);
+        double sacc = (double)wv;
+        // groups of 8 independent loads in flight (row index clamped: always in bounds)
+        for (int v0 = 0; v0 < nv; v0 += 8) {
+            T x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int v = v0 + u < nv ? v0 + u : nv - 1;
+                x[u] = ok ? V[(long long)v * n + i] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (v0 + u < nv) {
+                    sV[v0 + u][tid] = x[u];
+                    sacc -= hs[v0 + u] * (double)x[u];
+                }
+            }
+        }
+        if (mode != CGS_DOT) {
+            wv = (T)sacc;
+            if (ok) w[i] = wv;
+        }
+        if (mode == CGS_UPD_NORM) {
+            nacc += (double)wv * (double)wv;
+            continue;
+        }
+        sW[tid] = wv;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) {
+            const int v = wid + 4 * k;
+            if (v < nv) {
+                double a = 0.0;
+#pragma unroll
+                for (int t = lane; t < kChunk; t += 64) a += (double)sV[v][t] * (double)sW[t];
+                acc[k] += a;
+            }
+        }
+        __syncthreads();
+    }
+    if (mode == CGS_UPD_NORM) {
+        const double t = block_sum256(nacc, red);
+        if (tid == 0) partials[blockIdx.x] = t;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < KPW; ++k) {
+        const int v = wid + 4 * k;
+        if (v < nv) {
+            const double t = wave_sum64(acc[k]);
+            if (lane == 0) partials[(long long)v * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+// Block v: hout[v] = sum of the pass partials (fixed order).  The last pass has
+// a single value (||w||^2) and its block also takes the Givens step of column j.
+__global__ __launch_bounds__(kBlock) void k_cgs_finish(const double* __restrict__ partials, int nblk,
+                                                       double* __restrict__ hout, int mode, GivensArgs ga) {
+    __shared__ double red[4];
+    __shared__ double col[kMaxDots + 1], scs[kMaxDots], ssn[kMaxDots];
+    const int v = blockIdx.x;
+    const double t = sum_partials(partials + (long long)v * nblk, nblk, 1, 0, red);   // layout [v][block]
+    if (threadIdx.x == 0) hout[v] = t;
+    if (mode != CGS_UPD_NORM) return;
+    // Givens step of column j: stage the column and the previous rotations in LDS
+    const int j = ga.j, m = ga.m;
+    for (int i = threadIdx.x; i <= j; i += kBlock) {
+        col[i] = ga.h1[i] + ga.h2[i];
+        ga.Hraw[i * m + j] = col[i];
+        if (i < j) {
+            scs[i] = ga.cs[i];
+            ssn[i] = ga.sn[i];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double nw = sqrt(t);
+        ga.Hraw[(j + 1) * m + j] = nw;
+        *ga.wnorm = nw;
+        col[j + 1] = nw;
+        for (int i = 0; i < j; ++i) {
+            const double x = col[i], y = col[i + 1];
+            col[i] = scs[i] * x + ssn[i] * y;
+            col[i + 1] = -ssn[i] * x + scs[i] * y;
+        }
+        const double x = col[j], y = col[j + 1];
+        const double r = hypot(x, y);
+        double c = 1.0, sn = 0.0;
+        if (r > 0.0) {
+            c = x / r;
+            sn = y / r;
+        }
+        ga.cs[j] = c;
+        ga.sn[j] = sn;
+        col[j] = r;
+        col[j + 1] = 0.0;
+        const double gj = ga.g[j];
+        ga.g[j + 1] = -sn * gj;
+        ga.g[j] = c * gj;
+        *ga.res_est = fabs(sn * gj);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += kBlock) ga.H[i * m + j] = col[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_eps_finish(int nblk, EpsArgs ea) {
+    __shared__ double red[4];
+    const double t = sum_partials(ea.partials, nblk, 1, 0, red);
+    if (threadIdx.x == 0) finish_eps(ea, t);
+}
+
+// v <- v / *div (if div), z = v; partial ||z||^2 for the FD step
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_normalize_copy(T* __restrict__ v, long long n,
+                                                           const double* __restrict__ div, T* __restrict__ z,
+                                                           EpsArgs ea) {
+    __shared__ double red[4];
+    const double d = div ? *div : 1.0;
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        T o = v[i];
+        if (div) {
+            o = (T)((double)o / d);
+            v[i] = o;
+        }
+        z[i] = o;
+        acc += (double)o * (double)o;
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
 }
 
 int grid_for(long long n) {
@@ -309,11 +484,48 @@ hipError_t launch_fd_eps(const double* unorm2, const double* vnorm2, double sqrt
     return hipGetLastError();
 }
 
-hipError_t launch_givens(double* H, double* Hraw, double* cs, double* sn, double* g, int j, int m,
-                         const double* h1, const double* h2, const double* wnorm2, double* wnorm,
-                         double* res_est, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, H, Hraw, cs, sn, g, j, m, h1, h2, wnorm2, wnorm, res_est);
+hipError_t launch_givens(const GivensArgs& a, const double* wnorm2, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, a, wnorm2);
     return hipGetLastError();
+}
+
+int cgs_blocks(long long n) {
+    long long b = (n + 8LL * kChunk - 1) / (8LL * kChunk);
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename T>
+hipError_t launch_cgs(const T* V, long long n, int nv, const double* hin, T* w, double* partials,
+                      double* hout, int mode, const GivensArgs& ga, hipStream_t s) {
+    const int nb = cgs_blocks(n);
+    if (nv <= 8)
+        hipLaunchKernelGGL((k_cgs<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((k_cgs<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
+    else if (nv <= 32)
+        hipLaunchKernelGGL((k_cgs<T, 32>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
+    else
+        hipLaunchKernelGGL((k_cgs<T, 64>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nacc = mode == CGS_UPD_NORM ? 1 : nv;
+    hipLaunchKernelGGL(k_cgs_finish, dim3(nacc), dim3(kBlock), 0, s, partials, nb, hout, mode, ga);
+    return hipGetLastError();
+}
+
+hipError_t launch_eps_finish(int nblk, const EpsArgs& ea, hipStream_t s) {
+    hipLaunchKernelGGL(k_eps_finish, dim3(1), dim3(kBlock), 0, s, nblk, ea);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_normalize_copy(T* v, long long n, const double* div, T* z, const EpsArgs& ea, hipStream_t s) {
+    hipLaunchKernelGGL((k_normalize_copy<T>), dim3(cgs_blocks(n)), dim3(kBlock), 0, s, v, n, div, z, ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ea.partials) return e;
+    return launch_eps_finish(cgs_blocks(n), ea, s);
 }
 
 hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s) {
@@ -335,7 +547,10 @@ hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m,
     template hipError_t launch_axpy_basis<T>(T*, const T*, long long, int, const double*, hipStream_t);        \
     template hipError_t launch_add_to64<T>(double*, const T*, long long, hipStream_t);                         \
     template hipError_t launch_axpby<T>(T*, const T*, long long, double, double, hipStream_t);                 \
-    template hipError_t launch_lincomb<T>(T*, const T*, const T*, long long, double, double, hipStream_t);
+    template hipError_t launch_lincomb<T>(T*, const T*, const T*, long long, double, double, hipStream_t); \
+    template hipError_t launch_cgs<T>(const T*, long long, int, const double*, T*, double*, double*, int,      \
+                                      const GivensArgs&, hipStream_t);                                         \
+    template hipError_t launch_normalize_copy<T>(T*, long long, const double*, T*, const EpsArgs&, hipStream_t);
 JFNK_VINST(double)
 JFNK_VINST(float)
 #undef JFNK_VINST

@@ -161,8 +161,10 @@ class Context:
         L.check(self.lib.jfnk_timing_enable(self.h, 1 if on else 0), "jfnk_timing_enable", soft_ok=False)
 
     def timing_read(self, cls):
+        """(total ms, launches, algorithmic bytes) of one kernel class."""
         ms = C.c_double()
         cnt = C.c_int64()
-        L.check(self.lib.jfnk_timing_read(self.h, int(cls), C.byref(ms), C.byref(cnt)), "jfnk_timing_read",
-                soft_ok=False)
-        return ms.value, cnt.value
+        by = C.c_double()
+        L.check(self.lib.jfnk_timing_read(self.h, int(cls), C.byref(ms), C.byref(cnt), C.byref(by)),
+                "jfnk_timing_read", soft_ok=False)
+        return ms.value, cnt.value, by.value
