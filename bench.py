@@ -1,19 +1,24 @@
 """Benchmark of the JFNK hot path on one MI355X.
 
-Workload (default): the 2D dry thermal in a stably stratified atmosphere,
-1024 x 512 grid over 20 x 10 km, N = 0.01 1/s, +2 K bubble, dt = 1 s,
-Smagorinsky closure.  One step = one trapezoidal implicit step solved by inexact
-Newton to a relative residual of 1e-8 (FP64 outer residual / update / norms),
-with GMRES(30) right-preconditioned by the physics-based field-block
-preconditioner.  The timed leg runs the mixed form (FP32 Krylov and Jv inside the
-FP64 Newton); the plain FP64 form is timed beside it for the ms/step comparison.
+Workload: the 2D dry thermal in a stably stratified atmosphere, 1024 x 512 grid
+over 20 x 10 km, N = 0.01 1/s, +2 K bubble, dt = 1 s, Smagorinsky closure.  One
+step = one trapezoidal implicit step solved by inexact Newton (Eisenstat-Walker
+forcing) to a relative residual of 1e-8, FGMRES(30).
 
-Printed JSON line:
+Legs, all from the same state after the warm-up steps:
+  learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton
+            (the network is trained first on pairs the solver generates on this
+            workload; training time is reported, not timed with the steps)
+  mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton
+  plain     FP64 everywhere, physics-based preconditioner
+
+Printed JSON line (the timed leg is `learned`, or `mixed` with --no-learned):
   value          whole-job Jv throughput: grid points x Jv evaluations during the
                  timed steps / wall time of those steps [Gpoint-residuals/s]
-  ms_per_step    wall time per implicit step of the timed (mixed) leg
-  roofline       the Jv kernel: algorithmic bytes 3 n_f w per point and launch
-                 over its average HIP-event duration, against 8 TB/s HBM
+  ms_per_step    wall time per implicit step of the timed leg
+  roofline       dominant kernel class of the timed leg (algorithmic bytes over
+                 summed HIP-event time) against 8 TB/s HBM; roofline_jv and
+                 roofline_net for the Jv kernel and the network (vs 2.5 PFLOP/s BF16)
   cpu_baseline   the FP64 oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -29,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def parse():
@@ -39,9 +45,15 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def run_steps(ctx, u, k, torch, **opts):
@@ -58,11 +70,24 @@ def run_steps(ctx, u, k, torch, **opts):
     return infos
 
 
+def timed_leg(ctx, u0, k, torch, L, **opts):
+    u = u0.clone()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    infos = run_steps(ctx, u, k, torch, **opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cls = {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI, "residual": L.KC_RESIDUAL, "net": L.KC_NET}
+    tm = {name: ctx.timing_read(c) for name, c in cls.items()}    # (ms, launches, bytes or flops)
+    ctx.timing(False)
+    return {"wall": wall, "infos": infos, "tm": tm, "u": u}
+
+
 def cpu_baseline(prob, U0, seconds):
     """Oracle (FP64 numpy) on a bounded sample of the same workload: GMRES
     iterations of the first Newton iteration of the first step (physics
     preconditioner, stable-FD Jv, CGS2 Arnoldi), stopped after `seconds`."""
-    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import krylov as K
@@ -103,61 +128,81 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
 
     from paper_2007_10411_amd import _lib as L
     from paper_2007_10411_amd import inputs as I
+    from paper_2007_10411_amd import learned as LRN
     from paper_2007_10411_amd.jfnk import Context
 
     torch.cuda.set_device(0)
     prob = I.thermal_stable_2d(args.nx, args.nz)
     U0 = I.bubble_state(prob)
     ctx = Context(prob, max_m=30)
-    mixed = dict(rtol=1e-8, inner="f32", eta_floor=1e-4, m=30, max_restarts=20, pc="physics")
-    plain = dict(rtol=1e-8, inner="f64", m=30, max_restarts=20, pc="physics")
+    common = dict(rtol=1e-8, m=30, max_restarts=20)
+    mixed = dict(common, inner="f32", eta_floor=1e-4, pc="physics")
+    plain = dict(common, inner="f64", pc="physics")
+    learned = dict(common, inner="f32", eta_floor=1e-4, pc="learned")
 
     u = torch.from_numpy(U0).cuda()
-    print(f"[bench] warmup {args.warmup} mixed steps", file=sys.stderr, flush=True)
+    log(f"warmup {args.warmup} mixed steps")
     run_steps(ctx, u, args.warmup, torch, **mixed)
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    print(f"[bench] timing {args.steps} mixed steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = run_steps(ctx, u, args.steps, torch, **mixed)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cls = {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI, "residual": L.KC_RESIDUAL}
-    tm = {k: ctx.timing_read(v) for k, v in cls.items()}      # (ms, launches, algorithmic bytes)
-    ctx.timing(False)
-
-    # plain FP64 leg from the same state, for the ms/step comparison
-    print(f"[bench] timing {args.plain_steps} plain FP64 steps", file=sys.stderr, flush=True)
-    u64 = u.clone()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pinfos = run_steps(ctx, u64, args.plain_steps, torch, **plain)
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t1
-
+    train_info = None
+    if not args.no_learned:
+        log("recording solver pairs and training the learned preconditioner")
+        t0 = time.perf_counter()
+        R, DU, u = LRN.collect_pairs(ctx, u, steps=2, cap=96)
+        t1 = time.perf_counter()
+        theta, losses = LRN.train_mixed(ctx, R, DU, u, iters=args.train_iters, lr=2e-3, batch=8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        train_info = {"pairs": int(R.shape[0]), "collect_s": t1 - t0, "train_s": t2 - t1,
+                      "adam_steps": args.train_iters, "loss_first": losses[0],
+                      "loss_last": float(np.mean(losses[-20:]))}
+        del R, DU
+        torch.cuda.empty_cache()
+    legs = {}
+    if not args.no_learned:
+        log(f"timing {args.steps} learned steps")
+        legs["learned"] = timed_leg(ctx, u, args.steps, torch, L, **learned)
+    log(f"timing {args.steps} mixed steps")
+    legs["mixed"] = timed_leg(ctx, u, args.steps, torch, L, **mixed)
+    log(f"timing {args.plain_steps} plain FP64 steps")
+    legs["plain"] = timed_leg(ctx, u, args.plain_steps, torch, L, **plain)
+    main_leg = "learned" if "learned" in legs else "mixed"
+    T = legs[main_leg]
+    tm = T["tm"]
     npts = prob.npts
-    gm_total = sum(r.gmres_iters_total for r in infos)
-    jv_ms, jv_launches, jv_bytes_total = tm["jv"]
-    # Jv evaluations: one per GMRES iteration plus one per restart (true residual)
-    value = npts * jv_launches / wall / 1e9
 
-    def roof(name, kernel):
-        ms, launches, nbytes = tm[name]
-        achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    def per_step(leg):
+        k = len(legs[leg]["infos"])
+        return {"ms_per_step": legs[leg]["wall"] / k * 1e3,
+                "newton_iters_per_step": sum(r.newton_iters for r in legs[leg]["infos"]) / k,
+                "gmres_iters_per_step": sum(r.gmres_iters_total for r in legs[leg]["infos"]) / k,
+                "fallbacks": sum(r.fallbacks for r in legs[leg]["infos"])}
+
+    def roof(name, kernel, bound="hbm"):
+        ms, launches, amount = tm[name]
+        rate = amount / (ms / 1e3) if ms > 0 else 0.0
+        if bound == "mfma":
+            achieved = rate / 1e12
+            return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                    "flops_per_launch": amount / max(launches, 1), "avg_launch_us": ms / max(launches, 1) * 1e3,
+                    "launches": launches}
+        achieved = rate / 1e9
         return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": nbytes / max(launches, 1), "avg_launch_us": ms / max(launches, 1) * 1e3,
+                "bytes_per_launch": amount / max(launches, 1), "avg_launch_us": ms / max(launches, 1) * 1e3,
                 "launches": launches}
 
     kernels = {"arnoldi": "k_cgs<float> x3 + k_cgs_finish x3 (CGS2 passes of one GMRES iteration)",
                "pc": "k_pc_diag_2d<float> + k_pc_sweep_2d<float,64,8> (physics preconditioner)",
                "jv": "k_jv_2d<float,64,8> (stable finite-difference Jv)"}
     dominant = max(kernels, key=lambda k: tm[k][0])
+    jv_ms, jv_launches, _ = tm["jv"]
+    value = npts * jv_launches / T["wall"] / 1e9
     out = {
         "metric": "Gpoint-residuals/s (Jv) and ms per implicit step at 1e-8 Newton tol, plain vs learned",
         "value": value,
@@ -165,29 +210,30 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": T["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 Krylov/Jv, f64 Newton",
+        "dtype": ("f32 Krylov/Jv, bf16 MFMA learned PC, f64 Newton" if main_leg == "learned"
+                  else "f32 Krylov/Jv, f64 Newton"),
         "data": "synthetic",
         "config": {
             "workload": f"stable 2D dry thermal {prob.nx}x{prob.nz} (20x10 km, N=0.01/s, +2 K bubble, "
-                        f"dt={prob.dt} s, Smagorinsky), mixed FP32-inner/FP64-outer JFNK, physics PC, "
-                        f"GMRES(30), Newton rtol 1e-8",
+                        f"dt={prob.dt} s, Smagorinsky), {main_leg} JFNK: FGMRES(30), Newton rtol 1e-8",
             "grid": [prob.nx, prob.nz],
-            "newton_iters_per_step": sum(r.newton_iters for r in infos) / len(infos),
-            "gmres_iters_per_step": gm_total / len(infos),
-            "plain_f64_ms_per_step": plain_wall / args.plain_steps * 1e3,
-            "plain_f64_gmres_iters_per_step": sum(r.gmres_iters_total for r in pinfos) / len(pinfos),
+            "timed_leg": main_leg,
+            "legs": {k: per_step(k) for k in legs},
+            "training": train_info,
             "jv_kernel_gpts": npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0,
             "kernel_ms_per_step": {k: v[0] / args.steps for k, v in tm.items()},
         },
         "roofline": roof(dominant, kernels[dominant]),
         "roofline_jv": roof("jv", kernels["jv"]),
     }
+    if tm["net"][1] > 0:
+        out["roofline_net"] = roof("net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)", "mfma")
     if not args.no_cpu:
-        print(f"[bench] cpu baseline ({args.cpu_seconds} s)", file=sys.stderr, flush=True)
+        log(f"cpu baseline ({args.cpu_seconds} s)")
         out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

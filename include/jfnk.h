@@ -26,8 +26,8 @@
  *   convergence decision (jfnk_gmres, jfnk_newton_step) synchronise that stream
  *   before they return; the others return without synchronising.
  * - A context is not thread safe; use one context per host thread.
- * - No entry point allocates device memory except jfnk_create (and frees it in
- *   jfnk_destroy).
+ * - No entry point allocates device memory except jfnk_create and jfnk_net_init
+ *   (both freed by jfnk_destroy).
  *
  * Return codes: JFNK_OK (0); JFNK_NOT_CONVERGED (1, soft: outputs hold the last
  * iterate and the info struct is filled); JFNK_ERR_ARG (-1, invalid argument:
@@ -122,6 +122,14 @@ typedef struct {
     int32_t forcing;           /* 0: Eisenstat-Walker choice 2, 1: fixed eta            */
     double eta;                /* fixed forcing term                                     */
     double eta_floor;          /* lower bound on the forcing term                        */
+    float* rec_r;              /* optional DEVICE buffers of rec_cap FP32 state vectors:  */
+    float* rec_du;             /* the rhs -R and Krylov solution du of each Newton       */
+    int32_t rec_cap;           /* iteration are appended (training pairs of the learned  */
+    int32_t* rec_count;        /* preconditioner); rec_count (HOST) counts them.  NULL /  */
+                               /* 0 disables recording.                                   */
+    int32_t rec_krylov;        /* 1: record instead, for every FGMRES iteration of an FP32 */
+                               /* solve, the pair (J z_j, z_j) of a preconditioned Krylov */
+                               /* direction z_j and its image                             */
 } jfnk_newton_opts;
 
 typedef struct {
@@ -185,12 +193,43 @@ int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* ou
  * launch (resolved lazily, no synchronisation per launch).  Kernel classes:
  * 0 Jv, 1 residual/rhs, 2 physics preconditioner (diagonal start and sweeps),
  * 3 Arnoldi (the three Gram-Schmidt passes of one iteration with their
- * finishing reductions and the Givens step), 4 other.  enable = 1 starts
- * recording and clears the counters.  bytes receives the algorithmic HBM bytes
- * of the recorded launches (each array element moved once per launch).         */
+ * finishing reductions and the Givens step), 4 other, 5 learned preconditioner
+ * (network application).  enable = 1 starts recording and clears the counters.
+ * bytes receives the algorithmic HBM bytes of the recorded launches (each array
+ * element moved once per launch); for class 5 it receives the algorithmic flops
+ * (2 per weight and grid point) instead.                                        */
 int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
 int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches,
                      double* bytes);
+
+/* ---- learned right preconditioner (2D) ------------------------------------
+ * z = (dt/2) r + s N(r / s), s the RMS of r over all fields and points (1 for
+ * r = 0), N = conv(n_f->16) GELU conv(16->16) GELU conv(16->16) GELU
+ * conv(16->n_f), 3x3 kernels, zero padding, exact (erf) GELU.  An approximate
+ * inverse of J in the spirit of the paper's cheap preconditioners (section 2.5.1);
+ * nonlinear in r, hence used inside the flexible GMRES.  Parameters: one flat
+ * FP32 vector, per layer W[co][ci][kz][kx] (tap offset (kz-1, kx-1)) then b[co].
+ * Inference (JFNK_PC_LEARNED, jfnk_net_apply with bf16 = 1) runs in BF16 on the
+ * matrix cores with FP32 accumulation; training in FP32 with FP32 Adam moments.
+ * Vectors r, z, du are FP32 device arrays in the state layout.                  */
+/* Allocate the network workspace (the only allocating call besides
+ * jfnk_create); n_params receives the parameter count.  2D problems only.       */
+int jfnk_net_init(jfnk_ctx* ctx, int64_t* n_params);
+/* Copy FP32 parameters from / to HOST memory (n must equal the count); setting
+ * resets the Adam state.                                                         */
+int jfnk_net_set_params(jfnk_ctx* ctx, const float* theta_host, int64_t n);
+int jfnk_net_get_params(jfnk_ctx* ctx, float* theta_host, int64_t n);
+/* z = learned preconditioner applied to r; bf16 = 1: BF16 MFMA, 0: FP32.       */
+int jfnk_net_apply(jfnk_ctx* ctx, int32_t bf16, const float* r, float* z);
+/* Mean over a batch of pairs (r_b, du_b) (batch consecutive state vectors) of
+ * ||z(r_b) - du_b||^2 / ||du_b||^2 (to a host double) and its gradient (to a HOST
+ * float array of n_params, or NULL), FP32 forward and backward.                  */
+int jfnk_net_loss_grad(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, double* loss,
+                       float* grad_host);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on that loss;
+ * loss receives the loss before the step (host double, may be NULL).            */
+int jfnk_net_train_step(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, float lr,
+                        double* loss);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,169 @@
+"""Learned right preconditioner for the Krylov solve: a small convolutional
+network, its exact gradient and one Adam step, in FP64.
+
+ORACLE - test infrastructure only.  Plain numpy loops over the 3 x 3 taps.
+
+The paper's preconditioning discussion (section 2.5.1) motivates approximating
+J^{-1} cheaply; the network form follows the design of this project:
+
+    z = (dt/2) r + s N(r / s),       s = RMS of r over all fields and points
+                                      (s = 1 for r = 0)
+    N = conv(n_f -> 16) - GELU - conv(16 -> 16) - GELU - conv(16 -> 16) - GELU
+        - conv(16 -> n_f),   3 x 3 kernels, zero padding ("same"), with bias,
+    GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
+
+Loss of a pair (r, du): ||z(r) - du||^2 / ||du||^2, averaged over a batch.
+Adam (Kingma and Ba 2015): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+w <- w - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+
+Parameters are one flat vector: for each layer l, W_l[co][ci][kz][kx]
+(offsets dz = kz - 1, dx = kx - 1), then b_l[co].
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+HIDDEN = 16
+NLAYER = 4
+
+
+def channels(nf):
+    return [nf, HIDDEN, HIDDEN, HIDDEN, nf]
+
+
+def param_shapes(nf):
+    ch = channels(nf)
+    out = []
+    for l in range(NLAYER):
+        out.append(((ch[l + 1], ch[l], 3, 3), (ch[l + 1],)))
+    return out
+
+
+def param_count(nf):
+    return sum(int(np.prod(w)) + int(np.prod(b)) for w, b in param_shapes(nf))
+
+
+def unpack(theta, nf):
+    layers = []
+    o = 0
+    for ws, bs in param_shapes(nf):
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        layers.append((theta[o:o + nw].reshape(ws), theta[o + nw:o + nw + nb]))
+        o += nw + nb
+    return layers
+
+
+def pack(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def conv(x, W, b):
+    """out[co, z, x] = b[co] + sum_ci sum_taps W[co, ci, kz, kx] x[ci, z+kz-1, x+kx-1],
+    zero outside the grid.  x: (C_in, Z, X)."""
+    cin, Z, X = x.shape
+    xp = np.zeros((cin, Z + 2, X + 2))
+    xp[:, 1:-1, 1:-1] = x
+    out = np.zeros((W.shape[0], Z, X)) + b[:, None, None]
+    for kz in range(3):
+        for kx in range(3):
+            patch = xp[:, kz:kz + Z, kx:kx + X]
+            out += np.einsum("oc,czx->ozx", W[:, :, kz, kx], patch)
+    return out
+
+
+def conv_grad_input(g, W, shape_in):
+    """d/dx of sum(g * conv(x)) for zero padding (the transposed convolution)."""
+    cin, Z, X = shape_in
+    gx = np.zeros((cin, Z + 2, X + 2))
+    for kz in range(3):
+        for kx in range(3):
+            gx[:, kz:kz + Z, kx:kx + X] += np.einsum("oc,ozx->czx", W[:, :, kz, kx], g)
+    return gx[:, 1:-1, 1:-1]
+
+
+def conv_grad_weight(g, x):
+    cin, Z, X = x.shape
+    xp = np.zeros((cin, Z + 2, X + 2))
+    xp[:, 1:-1, 1:-1] = x
+    gW = np.zeros((g.shape[0], cin, 3, 3))
+    for kz in range(3):
+        for kx in range(3):
+            gW[:, :, kz, kx] = np.einsum("ozx,czx->oc", g, xp[:, kz:kz + Z, kx:kx + X])
+    return gW, g.sum(axis=(1, 2))
+
+
+def field_scale(r):
+    """One scale for every field: the RMS of r over all fields and points (1 when
+    r = 0).  A single scale keeps the cross-field part of the inverse
+    representable: a residual in one field needs a correction in the others."""
+    s = float(np.sqrt(np.mean(r ** 2)))
+    return np.full(r.shape[0], s if s > 0 else 1.0)
+
+
+def _grid(r):
+    """(n_f, nz, 1, nx) state -> (n_f, nz, nx) image."""
+    return r[:, :, 0, :] if r.ndim == 4 else r
+
+
+def forward(theta, r, dt, keep=False):
+    """z = (dt/2) r + s * N(r/s) for one 2D state-shaped r."""
+    img = _grid(r)
+    nf = img.shape[0]
+    layers = unpack(theta, nf)
+    s = field_scale(img)
+    a = img / s[:, None, None]
+    acts, pres = [a], []
+    for l, (W, b) in enumerate(layers):
+        h = conv(a, W, b)
+        pres.append(h)
+        a = gelu(h) if l < NLAYER - 1 else h
+        acts.append(a)
+    z = 0.5 * dt * img + s[:, None, None] * a
+    z = z.reshape(r.shape)
+    if keep:
+        return z, (s, acts, pres)
+    return z
+
+
+def loss_and_grad(theta, R, DU, dt):
+    """Mean over the batch of ||z(r) - du||^2 / ||du||^2 and its gradient."""
+    nf = _grid(R[0]).shape[0]
+    layers = unpack(theta, nf)
+    total = 0.0
+    grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
+    B = len(R)
+    for r, du in zip(R, DU):
+        z, (s, acts, pres) = forward(theta, r, dt, keep=True)
+        d = _grid(z) - _grid(du)
+        nd = float(np.sum(_grid(du) ** 2))
+        total += float(np.sum(d * d)) / nd / B
+        g = (2.0 / nd / B) * d * s[:, None, None]          # dL / d(network output)
+        for l in range(NLAYER - 1, -1, -1):
+            if l < NLAYER - 1:
+                g = g * gelu_grad(pres[l])
+            W, _ = layers[l]
+            gW, gb = conv_grad_weight(g, acts[l])
+            grads[l] = (grads[l][0] + gW, grads[l][1] + gb)
+            if l > 0:
+                g = conv_grad_input(g, W, acts[l].shape)
+    return total, pack(grads)
+
+
+def adam_step(theta, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (t counts from 1); returns new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

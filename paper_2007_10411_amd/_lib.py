@@ -16,11 +16,13 @@ JFNK_OK, JFNK_NOT_CONVERGED, JFNK_ERR_ARG, JFNK_ERR_HIP, JFNK_ERR_NONFINITE = 0,
 F64, F32 = 0, 1
 PC_NONE, PC_PHYSICS, PC_LEARNED = 0, 1, 2
 JV_STABLE, JV_LITERAL, JV_ANALYTIC = 0, 1, 2
-KC_JV, KC_RESIDUAL, KC_PC, KC_ARNOLDI, KC_VEC = range(5)
+KC_JV, KC_RESIDUAL, KC_PC, KC_ARNOLDI, KC_VEC, KC_NET = range(6)
 
 EXPORTS = ["jfnk_create", "jfnk_destroy", "jfnk_last_error", "jfnk_set_stream", "jfnk_rhs",
            "jfnk_residual", "jfnk_apply_F", "jfnk_jv", "jfnk_precond_apply", "jfnk_gmres",
-           "jfnk_newton_step", "jfnk_norm", "jfnk_timing_enable", "jfnk_timing_read"]
+           "jfnk_newton_step", "jfnk_norm", "jfnk_timing_enable", "jfnk_timing_read",
+           "jfnk_net_init", "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_apply",
+           "jfnk_net_loss_grad", "jfnk_net_train_step"]
 
 
 class Problem(C.Structure):
@@ -48,7 +50,8 @@ class GmresInfo(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_factor", C.c_double), ("max_newton", C.c_int32),
                 ("inner", C.c_int32), ("gm", GmresOpts), ("forcing", C.c_int32), ("eta", C.c_double),
-                ("eta_floor", C.c_double)]
+                ("eta_floor", C.c_double), ("rec_r", C.c_void_p), ("rec_du", C.c_void_p),
+                ("rec_cap", C.c_int32), ("rec_count", C.POINTER(C.c_int32)), ("rec_krylov", C.c_int32)]
 
 
 class NewtonInfo(C.Structure):
@@ -87,6 +90,12 @@ def load():
     L.jfnk_timing_enable.argtypes = [vp, C.c_int32]
     L.jfnk_timing_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
+    L.jfnk_net_init.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.jfnk_net_set_params.argtypes = [vp, vp, C.c_int64]
+    L.jfnk_net_get_params.argtypes = [vp, vp, C.c_int64]
+    L.jfnk_net_apply.argtypes = [vp, C.c_int32, vp, vp]
+    L.jfnk_net_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]
+    L.jfnk_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name != "jfnk_last_error":
             getattr(L, name).restype = C.c_int

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
@@ -210,6 +212,25 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
         JFNK_HIP(launch_normalize_copy<T>(vj, c->n, div, z, ea, c->stream));
         return JFNK_OK;
     }
+    if (pc == JFNK_PC_LEARNED) {
+        if (!std::is_same<T, float>::value || !c->net.ready) {
+            set_error("the learned preconditioner needs FP32 vectors and parameters set by jfnk_net_set_params");
+            return JFNK_ERR_ARG;
+        }
+        if (div) JFNK_HIP(launch_scale<T>(vj, c->n, div, c->stream));
+        {
+            // counted in flops: 2 multiply-adds per weight and point
+            TimedLaunch tl(c, KC_NET, 2.0 * (c->net.nparam) * c->geo.npts);
+            JFNK_HIP(net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), (const float*)vj,
+                               (float*)z, true, c->stream));
+        }
+        if (ea.partials) {
+            int r = norm2_to<T>(c, z, c->n, sc(c, S_VNORM2));
+            if (r) return r;
+            JFNK_HIP(launch_fd_eps(sc(c, S_UNORM2), sc(c, S_VNORM2), ea.sqrt_eps, ea.sqrt_n, sc(c, S_EPS), c->stream));
+        }
+        return JFNK_OK;
+    }
     if (pc != JFNK_PC_PHYSICS) {
         set_error("unsupported preconditioner kind");
         return JFNK_ERR_ARG;
@@ -294,6 +315,12 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
         int r;
         if ((r = apply_pc<T>(c, o.pc, u, Vj, div, Zj, o.sweeps, Vn, ea))) return r;
         if ((r = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return r;
+        if (std::is_same<T, float>::value && c->rec_count && *c->rec_count < c->rec_cap) {
+            const long long off = (long long)(*c->rec_count) * n;
+            JFNK_HIP(hipMemcpyAsync(c->rec_r + off, Vn, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+            JFNK_HIP(hipMemcpyAsync(c->rec_du + off, Zj, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+            ++*c->rec_count;
+        }
         {
             // classical Gram-Schmidt, twice; the Givens step of column j rides on the last pass
             // dot pass reads V_0..V_j and w; each update pass also writes w
@@ -531,6 +558,13 @@ int jfnk_destroy(jfnk_ctx* c) {
                     c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal, c->epart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    {
+        NetBuffers& nb = c->net;
+        void* np_[] = {nb.theta, nb.grad, nb.m, nb.v, nb.wt, nb.wbf, nb.s, nb.partials, nb.scal, nb.loss,
+                       nb.act, nb.pre, nb.a0, nb.z, nb.g0, nb.g1, nb.wpart, nb.abf};
+        for (void* q : np_)
+            if (q) (void)hipFree(q);
+    }
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (int k = 0; k < 2; ++k)
         if (c->slot_ev[k]) (void)hipEventDestroy(c->slot_ev[k]);
@@ -617,8 +651,8 @@ static bool valid_gmres_opts(jfnk_ctx* c, const jfnk_gmres_opts* o) {
         set_error("invalid GMRES options (m must be in [1, max_m])");
         return false;
     }
-    if (o->pc != JFNK_PC_NONE && o->pc != JFNK_PC_PHYSICS) {
-        set_error("preconditioner kind not available in this build");
+    if (o->pc != JFNK_PC_NONE && o->pc != JFNK_PC_PHYSICS && o->pc != JFNK_PC_LEARNED) {
+        set_error("unknown preconditioner kind");
         return false;
     }
     return true;
@@ -651,7 +685,7 @@ int jfnk_norm(jfnk_ctx* c, jfnk_dtype dt, const void* x, int64_t n, double* out)
 
 int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newton_opts* o, jfnk_newton_info* info) {
     if (!c || !u_n || !u || !o || !valid_gmres_opts(c, &o->gm) || o->max_newton < 0 ||
-        (o->inner != JFNK_F64 && o->inner != JFNK_F32)) {
+        (o->inner != JFNK_F64 && o->inner != JFNK_F32) || (o->gm.pc == JFNK_PC_LEARNED && o->inner != JFNK_F32)) {
         set_error(std::string("invalid argument to jfnk_newton_step"));
         return JFNK_ERR_ARG;
     }
@@ -681,6 +715,21 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
     const double tol = std::max(o->rtol * r0, o->atol_factor * (2.0 / c->prob.dt) * unorm);
     jfnk_newton_info inf{};
     inf.res0 = r0;
+    const bool rec_sys = o->rec_r && o->rec_du && o->rec_count && !o->rec_krylov;
+    struct RecGuard {
+        jfnk_ctx* c;
+        ~RecGuard() {
+            c->rec_r = c->rec_du = nullptr;
+            c->rec_count = nullptr;
+            c->rec_cap = 0;
+        }
+    } rec_guard{c};
+    if (o->rec_krylov && o->rec_r && o->rec_du && o->rec_count) {
+        c->rec_r = o->rec_r;
+        c->rec_du = o->rec_du;
+        c->rec_cap = o->rec_cap;
+        c->rec_count = o->rec_count;
+    }
     double rprev = r0, eta = 0.5;
     bool converged = false;
     int k = 0;
@@ -717,12 +766,31 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
             JFNK_HIP(launch_cast<double, double>(c->b64, c->R64, n, -1.0, s));
             rc = gmres_impl<double>(c, u, c->b64, c->x64, go, &gi);
             if (rc < 0) return rc;
+            if (rec_sys && *o->rec_count < o->rec_cap) {
+                const long long off = (long long)(*o->rec_count) * n;
+                JFNK_HIP(launch_cast<float, double>(o->rec_r + off, c->b64, n, 1.0, s));
+                JFNK_HIP(launch_cast<float, double>(o->rec_du + off, c->x64, n, 1.0, s));
+                ++*o->rec_count;
+            }
             JFNK_HIP(launch_add_to64<double>(u, c->x64, n, s));
         } else {
             JFNK_HIP(launch_cast<float, double>(c->u32, u, n, 1.0, s));
             JFNK_HIP(launch_cast<float, double>(c->b32, c->R64, n, -1.0, s));
             rc = gmres_impl<float>(c, c->u32, c->b32, c->x32, go, &gi);
+            if (go.pc == JFNK_PC_LEARNED && rc != JFNK_OK) {
+                // the learned preconditioner failed this solve: redo it with the physics-based one
+                inf.fallbacks++;
+                inf.gmres_iters_total += gi.iters;
+                go.pc = JFNK_PC_PHYSICS;
+                rc = gmres_impl<float>(c, c->u32, c->b32, c->x32, go, &gi);
+            }
             if (rc < 0) return rc;
+            if (rec_sys && *o->rec_count < o->rec_cap) {
+                const long long off = (long long)(*o->rec_count) * n;
+                JFNK_HIP(hipMemcpyAsync(o->rec_r + off, c->b32, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+                JFNK_HIP(hipMemcpyAsync(o->rec_du + off, c->x32, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+                ++*o->rec_count;
+            }
             JFNK_HIP(launch_add_to64<float>(u, c->x32, n, s));
         }
         inf.gmres_iters_total += gi.iters;
@@ -760,6 +828,130 @@ int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launch
     if (total_ms) *total_ms = c->timing.ms[cls];
     if (launches) *launches = c->timing.launches[cls];
     if (bytes) *bytes = c->timing.bytes[cls];
+    return JFNK_OK;
+}
+
+
+int jfnk_net_init(jfnk_ctx* c, int64_t* n_params) {
+    if (!c || c->prob.dim != 2) {
+        set_error("the learned preconditioner is available for 2D problems");
+        return JFNK_ERR_ARG;
+    }
+    NetBuffers& nb = c->net;
+    const int np = net_param_count(c->nf);
+    if (n_params) *n_params = np;
+    if (nb.theta) return JFNK_OK;
+    const long long npts = c->geo.npts;
+    const long long tiles = (long long)((c->geo.nx + 63) / 64) * ((c->geo.nz + 3) / 4);
+    nb.nparam = np;
+#define NALLOC(ptr, count)                                                   \
+    do {                                                                     \
+        hipError_t e_ = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (count)); \
+        if (e_ != hipSuccess) return hip_fail(e_, "hipMalloc " #ptr);        \
+    } while (0)
+    NALLOC(nb.theta, np);
+    NALLOC(nb.grad, np);
+    NALLOC(nb.m, np);
+    NALLOC(nb.v, np);
+    NALLOC(nb.wt, np);
+    NALLOC(nb.wbf, 4 * 9 * 16 * 16);
+    NALLOC(nb.s, 16);
+    NALLOC(nb.partials, 8192);
+    NALLOC(nb.scal, 4);
+    NALLOC(nb.loss, 4);
+    NALLOC(nb.act, 4 * 16 * npts);
+    NALLOC(nb.pre, 4 * 16 * npts);
+    NALLOC(nb.a0, (long long)c->nf * npts);
+    NALLOC(nb.z, (long long)c->nf * npts);
+    NALLOC(nb.g0, 16 * npts);
+    NALLOC(nb.g1, 16 * npts);
+    NALLOC(nb.wpart, tiles * (16 * 16 * 9 + 16));
+    NALLOC(nb.abf, 2 * 16 * npts);
+#undef NALLOC
+    JFNK_HIP(hipMemsetAsync(nb.theta, 0, np * sizeof(float), c->stream));
+    JFNK_HIP(hipMemsetAsync(nb.m, 0, np * sizeof(float), c->stream));
+    JFNK_HIP(hipMemsetAsync(nb.v, 0, np * sizeof(float), c->stream));
+    JFNK_HIP(hipStreamSynchronize(c->stream));
+    nb.adam_t = 0;
+    return JFNK_OK;
+}
+
+static bool net_ok(jfnk_ctx* c) {
+    if (!c || !c->net.theta) {
+        set_error("call jfnk_net_init first");
+        return false;
+    }
+    return true;
+}
+
+int jfnk_net_set_params(jfnk_ctx* c, const float* theta, int64_t n) {
+    if (!net_ok(c) || !theta || n != c->net.nparam) {
+        if (c && c->net.theta) set_error("parameter count mismatch");
+        return JFNK_ERR_ARG;
+    }
+    JFNK_HIP(hipMemcpyAsync(c->net.theta, theta, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    JFNK_HIP(hipMemsetAsync(c->net.m, 0, n * sizeof(float), c->stream));
+    JFNK_HIP(hipMemsetAsync(c->net.v, 0, n * sizeof(float), c->stream));
+    c->net.adam_t = 0;
+    JFNK_HIP(net_prep_weights(c->net, c->nf, c->stream));
+    JFNK_HIP(hipStreamSynchronize(c->stream));
+    c->net.ready = true;
+    return JFNK_OK;
+}
+
+int jfnk_net_get_params(jfnk_ctx* c, float* theta, int64_t n) {
+    if (!net_ok(c) || !theta || n != c->net.nparam) return JFNK_ERR_ARG;
+    JFNK_HIP(hipMemcpyAsync(theta, c->net.theta, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    JFNK_HIP(hipStreamSynchronize(c->stream));
+    return JFNK_OK;
+}
+
+int jfnk_net_apply(jfnk_ctx* c, int32_t bf16, const float* r, float* z) {
+    if (!net_ok(c) || !r || !z || !c->net.ready) {
+        set_error("invalid argument to jfnk_net_apply (parameters set?)");
+        return JFNK_ERR_ARG;
+    }
+    TimedLaunch tl(c, KC_NET, 2.0 * c->net.nparam * c->geo.npts);
+    JFNK_HIP(net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), r, z, bf16 != 0, c->stream));
+    return JFNK_OK;
+}
+
+static int net_batch_grad(jfnk_ctx* c, const float* r, const float* du, int32_t batch, double* loss) {
+    NetBuffers& nb = c->net;
+    for (int b = 0; b < batch; ++b)
+        JFNK_HIP(net_pair_grad(nb, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), r + (long long)b * c->n,
+                               du + (long long)b * c->n, 1.0 / batch, b == 0, c->stream));
+    if (loss) {
+        JFNK_HIP(hipMemcpyAsync(loss, nb.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        JFNK_HIP(hipStreamSynchronize(c->stream));
+    }
+    return JFNK_OK;
+}
+
+int jfnk_net_loss_grad(jfnk_ctx* c, const float* r, const float* du, int32_t batch, double* loss, float* grad) {
+    if (!net_ok(c) || !r || !du || batch < 1 || !c->net.ready) {
+        set_error("invalid argument to jfnk_net_loss_grad");
+        return JFNK_ERR_ARG;
+    }
+    int rc = net_batch_grad(c, r, du, batch, loss);
+    if (rc) return rc;
+    if (grad) {
+        JFNK_HIP(hipMemcpyAsync(grad, c->net.grad, c->net.nparam * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        JFNK_HIP(hipStreamSynchronize(c->stream));
+    }
+    return JFNK_OK;
+}
+
+int jfnk_net_train_step(jfnk_ctx* c, const float* r, const float* du, int32_t batch, float lr, double* loss) {
+    if (!net_ok(c) || !r || !du || batch < 1 || !(lr > 0) || !c->net.ready) {
+        set_error("invalid argument to jfnk_net_train_step");
+        return JFNK_ERR_ARG;
+    }
+    int rc = net_batch_grad(c, r, du, batch, loss);
+    if (rc) return rc;
+    c->net.adam_t++;
+    JFNK_HIP(net_adam(c->net, c->net.nparam, c->net.adam_t, lr, c->stream));
+    JFNK_HIP(net_prep_weights(c->net, c->nf, c->stream));
     return JFNK_OK;
 }
 

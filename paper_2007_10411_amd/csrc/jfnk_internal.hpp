@@ -78,7 +78,7 @@ struct EpsArgs {
 
 enum CgsMode { CGS_DOT = 0, CGS_UPD_DOT = 1, CGS_UPD_NORM = 2 };
 
-enum KernelClass { KC_JV = 0, KC_RESIDUAL = 1, KC_PC = 2, KC_ARNOLDI = 3, KC_VEC = 4, KC_COUNT = 5 };
+enum KernelClass { KC_JV = 0, KC_RESIDUAL = 1, KC_PC = 2, KC_ARNOLDI = 3, KC_VEC = 4, KC_NET = 5, KC_COUNT = 6 };
 
 constexpr int kMaxPartials = 2048;   // blocks of a reduction grid
 constexpr int kMaxDots = 64;         // vectors per fused dot pass (>= max_m + 1)
@@ -93,6 +93,39 @@ struct Timing {
     long long launches[KC_COUNT] = {0};
     double bytes[KC_COUNT] = {0};           // algorithmic HBM bytes of the timed launches
 };
+
+// Workspace of the learned preconditioner (allocated by jfnk_net_init).
+struct NetBuffers {
+    float* theta = nullptr;          // FP32 master parameters
+    float* grad = nullptr;
+    float* m = nullptr;              // Adam moments
+    float* v = nullptr;
+    float* wt = nullptr;             // transposed, flipped weights (backward data)
+    unsigned short* wbf = nullptr;   // bf16 weights [layer][tap][co][ci], 16 x 16 padded
+    float* s = nullptr;              // per-field scales
+    double* partials = nullptr;
+    double* scal = nullptr;
+    double* loss = nullptr;
+    float* act = nullptr;            // 4 x 16 x npts post-activations
+    float* pre = nullptr;            // 4 x 16 x npts pre-activations
+    float* a0 = nullptr;             // nf x npts scaled input
+    float* z = nullptr;              // nf x npts output
+    float* g0 = nullptr;             // 16 x npts gradients
+    float* g1 = nullptr;
+    float* wpart = nullptr;          // per-tile weight-gradient partials
+    unsigned short* abf = nullptr;   // 2 x 16 x npts bf16 activations
+    int nparam = 0;
+    int adam_t = 0;
+    bool ready = false;              // parameters set
+};
+
+int net_param_count(int nf);
+hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s);
+hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r, float* z,
+                     bool bf16, hipStream_t st);
+hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
+                         const float* du, double inv_batch, bool first_pair, hipStream_t st);
+hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st);
 
 }  // namespace jfnk
 
@@ -134,6 +167,13 @@ struct jfnk_ctx {
     double* hscal = nullptr;    // pinned host mirror
     hipEvent_t slot_ev[2] = {nullptr, nullptr};  // GMRES result slots in flight
     jfnk::Timing timing;
+    jfnk::NetBuffers net;
+    int fallbacks = 0;
+    // Krylov-pair recording (J z_j, z_j) during FP32 solves
+    float* rec_r = nullptr;
+    float* rec_du = nullptr;
+    int rec_cap = 0;
+    int* rec_count = nullptr;
 };
 
 namespace jfnk {

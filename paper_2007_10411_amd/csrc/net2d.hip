@@ -1,0 +1,494 @@
+// Learned right preconditioner for the Krylov solve (2D): a 4-layer 3x3
+// convolutional network applied as
+//     z = (dt/2) r + s N(r / s),     s = RMS of r over all fields (1 if r = 0),
+//     N = conv(nf->16) GELU conv(16->16) GELU conv(16->16) GELU conv(16->nf),
+// zero padding, exact erf GELU.  Inference runs in BF16 on MFMA
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one 3x3 tap per instruction);
+// training (forward, backward, Adam on FP32 master weights) runs in FP32.
+//
+// Activations are channel-major [c][nz][nx] like the state vectors.  Parameters
+// are one flat FP32 vector: per layer W[co][ci][kz][kx] (tap offsets kz-1, kx-1)
+// followed by b[co].
+
+#include "jfnk_internal.hpp"
+#include "reduce.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace jfnk {
+
+namespace {
+
+constexpr int kHid = 16;
+constexpr int kTX = 64, kTZ = 4;            // output tile per 256-thread block
+constexpr int kSX = kTX + 2, kSZ = kTZ + 2; // input tile with a halo of 1
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.3989422804014327f;
+}
+
+enum { L_FIRST = 0, L_MID = 1, L_LAST = 2 };
+
+// ---------------------------------------------------------------------------
+// scale s = sqrt(mean r^2) over all fields (stored once per field channel)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_field_sumsq(const float* __restrict__ r, long long npts,
+                                                     double* __restrict__ partials) {
+    __shared__ double red[4];
+    const int f = blockIdx.y;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < npts; i += (long long)gridDim.x * 256) {
+        const double v = r[f * npts + i];
+        acc += v * v;
+    }
+    const double t = block_sum256(acc, red);
+    if (threadIdx.x == 0) partials[(long long)f * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_field_scale(const double* __restrict__ partials, int nblk, long long npts,
+                                                     int nf, float* __restrict__ s) {
+    __shared__ double red[4];
+    double tot = 0.0;
+    for (int f = 0; f < nf; ++f) tot += sum_partials(partials + (long long)f * nblk, nblk, 1, 0, red);
+    if (threadIdx.x == 0) {
+        const double v = sqrt(tot / ((double)npts * nf));
+        for (int f = 0; f < nf; ++f) s[f] = v > 0.0 ? (float)v : 1.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 convolution (training forward, backward-data via transposed weights)
+// out_pre[co] = b[co] + sum_ci sum_taps W[co][ci][t] in[ci](p + off_t)
+// FIRST: in = r / s;  MID: in = act;  LAST: z = (dt/2) r + s (out_pre)
+// post = GELU(out_pre) for FIRST/MID (or, with gmul, out_pre * gelu'(gmul))
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_f32(int nx, int nz, const float* __restrict__ in, int cin,
+                                                  const float* __restrict__ W, const float* __restrict__ b, int cout,
+                                                  float* __restrict__ pre, float* __restrict__ post,
+                                                  const float* __restrict__ r, const float* __restrict__ s,
+                                                  float half_dt, float* __restrict__ z,
+                                                  const float* __restrict__ gmul) {
+    __shared__ float sin_[kHid][kSZ][kSX];
+    __shared__ float sw[kHid * kHid * 9];
+    __shared__ float sb[kHid];
+    const long long np = (long long)nx * nz;
+    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+    for (int i = threadIdx.x; i < cout * cin * 9; i += 256) sw[i] = W[i];
+    for (int i = threadIdx.x; i < cout; i += 256) sb[i] = b ? b[i] : 0.0f;
+    for (int idx = threadIdx.x; idx < cin * kSZ * kSX; idx += 256) {
+        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
+        const int lz = rem / kSX, lx = rem - lz * kSX;
+        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
+        float v = 0.0f;
+        if (gx >= 0 && gx < nx && gz >= 0 && gz < nz) {
+            const long long o = (long long)c * np + (long long)gz * nx + gx;
+            v = (MODE == L_FIRST) ? r[o] / s[c] : in[o];
+        }
+        sin_[c][lz][lx] = v;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 63, lz = threadIdx.x >> 6;
+    const int gx = x0 + lx, gz = z0 + lz;
+    if (gx >= nx || gz >= nz) return;
+    float acc[kHid];
+#pragma unroll
+    for (int co = 0; co < kHid; ++co) acc[co] = co < cout ? sb[co] : 0.0f;
+    for (int ci = 0; ci < cin; ++ci) {
+        float xv[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) xv[t] = sin_[ci][lz + t / 3][lx + t % 3];
+#pragma unroll
+        for (int co = 0; co < kHid; ++co) {
+            if (co < cout) {
+                const float* w = sw + (co * cin + ci) * 9;
+                float a = acc[co];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) a += w[t] * xv[t];
+                acc[co] = a;
+            }
+        }
+    }
+    const long long o = (long long)gz * nx + gx;
+#pragma unroll
+    for (int co = 0; co < kHid; ++co) {
+        if (co >= cout) continue;
+        const float h = acc[co];
+        if (MODE == L_LAST) {
+            if (pre) pre[co * np + o] = h;
+            if (z) z[co * np + o] = half_dt * r[co * np + o] + s[co] * h;
+        } else {
+            if (pre) pre[co * np + o] = h;
+            if (post) post[co * np + o] = gmul ? h * gelu_grad(gmul[co * np + o]) : gelu(h);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA convolution for inference.  Wave w of the block computes output row
+// z0 + w, 64 pixels as four 16-pixel MFMA tiles; per tile 9 instructions
+// (one per tap), A = 16 pixels x 16 input channels, B = 16 input x 16 output
+// channels, FP32 accumulation.  Operand layout of v_mfma_f32_16x16x16_bf16:
+// lane l holds A[row l%16][k 4(l/16)..+3], B[k 4(l/16)..+3][col l%16] and
+// D[row 4(l/16)..+3][col l%16].
+// Wf: bf16 weights [tap][co][ci] padded to 16 x 16.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigned short* __restrict__ in, int cin,
+                                                   const unsigned short* __restrict__ Wf,
+                                                   const float* __restrict__ b, int cout,
+                                                   unsigned short* __restrict__ post, const float* __restrict__ r,
+                                                   const float* __restrict__ s, float half_dt,
+                                                   float* __restrict__ z) {
+    __shared__ unsigned short sin_[kSZ][kSX][kHid];   // pixel-major, channel-innermost
+    const long long np = (long long)nx * nz;
+    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+    for (int idx = threadIdx.x; idx < kHid * kSZ * kSX; idx += 256) {
+        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
+        const int lz = rem / kSX, lx = rem - lz * kSX;
+        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
+        unsigned short v = 0;
+        if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz) {
+            const long long o = (long long)c * np + (long long)gz * nx + gx;
+            v = (MODE == L_FIRST) ? f2bf(r[o] / s[c]) : in[o];
+        }
+        sin_[lz][lx][c] = v;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;          // k group of 4 channels
+    // B fragments of the 9 taps: W[t][co = col][ci = 4 kg .. 4 kg + 3]
+    bf16x4_t bfrag[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
+        bfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
+    }
+    const float bias = col < cout ? b[col] : 0.0f;
+    __syncthreads();
+    const int gz = z0 + wv;
+    if (gz >= nz) return;
+#pragma unroll
+    for (int st = 0; st < kTX / 16; ++st) {
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int px = st * 16 + col;                   // A row: pixel of this lane
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dz = t / 3, dx = t % 3;
+            const unsigned short* ap = &sin_[wv + dz][px + dx][4 * kg];
+            const bf16x4_t a = bf16x4_t{(short)ap[0], (short)ap[1], (short)ap[2], (short)ap[3]};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
+        }
+        // D: rows (pixels) 4 kg + i, column (output channel) col
+        if (col >= cout) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gx = x0 + st * 16 + 4 * kg + i;
+            if (gx >= nx) continue;
+            const long long o = (long long)col * np + (long long)gz * nx + gx;
+            const float h = acc[i] + bias;
+            if (MODE == L_LAST)
+                z[o] = half_dt * r[o] + s[col] * h;
+            else
+                post[o] = f2bf(gelu(h));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// g = 2 (z - du) s / (||du||^2 B), and the partial loss sum (z - du)^2 / ||du||^2
+__global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ z, const float* __restrict__ du,
+                                                   long long npts, int nf, const float* __restrict__ s,
+                                                   const double* __restrict__ du2, double inv_batch,
+                                                   float* __restrict__ g, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const double nd = *du2;
+    const long long n = npts * nf;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const double d = (double)z[i] - (double)du[i];
+        acc += d * d;
+        const int f = (int)(i / npts);
+        g[i] = (float)(2.0 * d * (double)s[f] / nd * inv_batch);
+    }
+    const double t = block_sum256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t / nd * inv_batch;
+}
+
+// dW[co][ci][t] and db[co] partial sums over one 64 x 4 tile of pixels
+__global__ __launch_bounds__(256) void k_conv_wgrad(int nx, int nz, const float* __restrict__ g, int cout,
+                                                    const float* __restrict__ a, int cin,
+                                                    float* __restrict__ partials, int nw) {
+    __shared__ float sg[kHid][kTZ][kTX];
+    __shared__ float sa[kHid][kSZ][kSX];
+    const long long np = (long long)nx * nz;
+    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+    for (int idx = threadIdx.x; idx < cout * kTZ * kTX; idx += 256) {
+        const int c = idx / (kTZ * kTX), rem = idx - c * (kTZ * kTX);
+        const int lz = rem / kTX, lx = rem - lz * kTX;
+        const int gx = x0 + lx, gz = z0 + lz;
+        sg[c][lz][lx] = (gx < nx && gz < nz) ? g[(long long)c * np + (long long)gz * nx + gx] : 0.0f;
+    }
+    for (int idx = threadIdx.x; idx < cin * kSZ * kSX; idx += 256) {
+        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
+        const int lz = rem / kSX, lx = rem - lz * kSX;
+        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
+        sa[c][lz][lx] = (gx >= 0 && gx < nx && gz >= 0 && gz < nz) ? a[(long long)c * np + (long long)gz * nx + gx] : 0.0f;
+    }
+    __syncthreads();
+    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int k = threadIdx.x; k < nw + cout; k += 256) {
+        float acc = 0.0f;
+        if (k < nw) {
+            const int co = k / (cin * 9), rem = k - co * (cin * 9);
+            const int ci = rem / 9, t = rem - ci * 9;
+            const int dz = t / 3, dx = t % 3;
+            for (int lz = 0; lz < kTZ; ++lz)
+                for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx] * sa[ci][lz + dz][lx + dx];
+        } else {
+            const int co = k - nw;
+            for (int lz = 0; lz < kTZ; ++lz)
+                for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx];
+        }
+        partials[blk * (nw + cout) + k] = acc;
+    }
+}
+
+// grad[k] (+)= sum over blocks of partials[b][k] (fixed order, FP64)
+__global__ __launch_bounds__(256) void k_wgrad_finish(const float* __restrict__ partials, int nblk, int cnt,
+                                                      float* __restrict__ grad, int accumulate) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= cnt) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partials[(long long)b * cnt + k];
+    grad[k] = accumulate ? grad[k] + (float)acc : (float)acc;
+}
+
+__global__ __launch_bounds__(256) void k_cast_scaled_input(const float* __restrict__ r, long long np, int nf,
+                                                           const float* __restrict__ s, float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < np * nf) out[i] = r[i] / s[i / np];
+}
+
+// transposed, flipped weights for the backward-data convolution:
+// Wt[ci][co][t] = W[co][ci][8 - t]; also the padded bf16 inference weights
+// Wf[t][co][ci] (zero beyond cout / cin)
+__global__ void k_prep_weights(const float* __restrict__ W, int cout, int cin, float* __restrict__ Wt,
+                               unsigned short* __restrict__ Wf) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cout * cin * 9) {
+        const int co = k / (cin * 9), rem = k - co * (cin * 9);
+        const int ci = rem / 9, t = rem - ci * 9;
+        Wt[(ci * cout + co) * 9 + (8 - t)] = W[k];
+    }
+    if (k < 9 * kHid * kHid) {
+        const int t = k / (kHid * kHid), rem = k - t * (kHid * kHid);
+        const int co = rem / kHid, ci = rem - co * kHid;
+        Wf[k] = (co < cout && ci < cin) ? f2bf(W[(co * cin + ci) * 9 + t]) : (unsigned short)0;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct NetLayer {
+    int cin, cout, woff, boff;
+};
+
+static void layers_of(int nf, NetLayer L[4]) {
+    const int ch[5] = {nf, kHid, kHid, kHid, nf};
+    int o = 0;
+    for (int l = 0; l < 4; ++l) {
+        L[l].cin = ch[l];
+        L[l].cout = ch[l + 1];
+        L[l].woff = o;
+        o += ch[l + 1] * ch[l] * 9;
+        L[l].boff = o;
+        o += ch[l + 1];
+    }
+}
+
+int net_param_count(int nf) {
+    NetLayer L[4];
+    layers_of(nf, L);
+    return L[3].boff + L[3].cout;
+}
+
+static dim3 tiles(int nx, int nz) { return dim3((nx + kTX - 1) / kTX, (nz + kTZ - 1) / kTZ); }
+
+hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s) {
+    NetLayer L[4];
+    layers_of(nf, L);
+    for (int l = 0; l < 4; ++l) {
+        hipLaunchKernelGGL(k_prep_weights, dim3((9 * kHid * kHid + 255) / 256), dim3(256), 0, s, nb.theta + L[l].woff,
+                           L[l].cout, L[l].cin, nb.wt + L[l].woff, nb.wbf + l * 9 * kHid * kHid);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t net_field_scale(const float* r, int nx, int nz, int nf, double* partials, float* s, hipStream_t st) {
+    const long long np = (long long)nx * nz;
+    int nblk = (int)std::min<long long>(512, (np + 1023) / 1024);
+    if (nblk < 1) nblk = 1;
+    hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, nf), dim3(256), 0, st, r, np, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_field_scale, dim3(1), dim3(256), 0, st, partials, nblk, np, nf, s);
+    return hipGetLastError();
+}
+
+// inference: z = (dt/2) r + s N(r/s), BF16 MFMA (bf16 = true) or FP32
+hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r, float* z,
+                     bool bf16, hipStream_t st) {
+    NetLayer L[4];
+    layers_of(nf, L);
+    hipError_t e = net_field_scale(r, nx, nz, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
+    const dim3 grid = tiles(nx, nz);
+    const long long np = (long long)nx * nz;
+    if (bf16) {
+        unsigned short* a0 = nb.abf;
+        unsigned short* a1 = nb.abf + kHid * np;
+        hipLaunchKernelGGL((k_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)nullptr,
+                           L[0].cin, nb.wbf + 0 * 9 * kHid * kHid, nb.theta + L[0].boff, L[0].cout, a0, r, nb.s,
+                           half_dt, (float*)nullptr);
+        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[1].cin,
+                           nb.wbf + 1 * 9 * kHid * kHid, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
+                           (float*)nullptr);
+        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a1, L[2].cin,
+                           nb.wbf + 2 * 9 * kHid * kHid, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
+                           (float*)nullptr);
+        hipLaunchKernelGGL((k_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[3].cin,
+                           nb.wbf + 3 * 9 * kHid * kHid, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
+                           nb.s, half_dt, z);
+        return hipGetLastError();
+    }
+    float* a0 = nb.act;                 // reuse the training buffers
+    float* a1 = nb.act + kHid * np;
+    hipLaunchKernelGGL((k_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const float*)nullptr, L[0].cin,
+                       nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, (float*)nullptr, a0, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)a0, L[1].cin,
+                       nb.theta + L[1].woff, nb.theta + L[1].boff, L[1].cout, (float*)nullptr, a1, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)a1, L[2].cin,
+                       nb.theta + L[2].woff, nb.theta + L[2].boff, L[2].cout, (float*)nullptr, a0, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const float*)a0, L[3].cin,
+                       nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, (float*)nullptr, (float*)nullptr, r,
+                       nb.s, half_dt, z, (const float*)nullptr);
+    return hipGetLastError();
+}
+
+// loss and gradient (accumulated into nb.grad) of one pair, FP32 forward/backward;
+// returns the loss contribution in nb.loss (device double, accumulated)
+hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
+                         const float* du, double inv_batch, bool first_pair, hipStream_t st) {
+    NetLayer L[4];
+    layers_of(nf, L);
+    const long long np = (long long)nx * nz;
+    const dim3 grid = tiles(nx, nz);
+    hipError_t e = net_field_scale(r, nx, nz, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
+    // forward, keeping pre-activations h_l and post-activations a_l
+    float* act[4];
+    float* pre[4];
+    for (int l = 0; l < 4; ++l) {
+        act[l] = nb.act + (long long)l * kHid * np;   // input of layer l+1 (a_{l+1})
+        pre[l] = nb.pre + (long long)l * kHid * np;
+    }
+    hipLaunchKernelGGL((k_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const float*)nullptr, L[0].cin,
+                       nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, pre[0], act[0], r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    for (int l = 1; l < 3; ++l)
+        hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)act[l - 1], L[l].cin,
+                           nb.theta + L[l].woff, nb.theta + L[l].boff, L[l].cout, pre[l], act[l], r, nb.s, half_dt,
+                           (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const float*)act[2], L[3].cin,
+                       nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, pre[3], (float*)nullptr, r, nb.s,
+                       half_dt, nb.z, (const float*)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // ||du||^2, then g = dL/d(network output) and the loss
+    {
+        const long long n = np * nf;
+        int nblk = (int)std::min<long long>(1024, (n + 1023) / 1024);
+        hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, 1), dim3(256), 0, st, du, n, nb.partials);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_reduce_partials(nb.partials, nblk, 1, 1, nb.scal, 0, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_loss_grad, dim3(nblk), dim3(256), 0, st, nb.z, du, np, nf, nb.s, nb.scal, inv_batch,
+                           nb.g0, nb.partials + 4096);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_reduce_partials(nb.partials + 4096, nblk, 1, 1, nb.loss, first_pair ? 0 : 1, st)) !=
+            hipSuccess)
+            return e;
+    }
+    // backward through the layers
+    float* g = nb.g0;
+    float* gnext = nb.g1;
+    const int nt = (int)(grid.x * grid.y);
+    for (int l = 3; l >= 0; --l) {
+        const float* a_in = l == 0 ? nb.a0 : act[l - 1];
+        if (l == 0) {
+            // the scaled input r / s of the first layer
+            hipLaunchKernelGGL(k_cast_scaled_input, dim3((unsigned)((np * nf + 255) / 256)), dim3(256), 0, st, r,
+                               np, nf, nb.s, nb.a0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int nw = L[l].cout * L[l].cin * 9;
+        hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout, a_in, L[l].cin,
+                           nb.wpart, nw);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_wgrad_finish, dim3((nw + L[l].cout + 255) / 256), dim3(256), 0, st,
+                           (const float*)nb.wpart, nt, nw + L[l].cout, nb.grad + L[l].woff, first_pair ? 0 : 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (l > 0) {
+            // g_in = conv(g, W transposed and flipped) * gelu'(h_{l-1})
+            hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout,
+                               nb.wt + L[l].woff, (const float*)nullptr, L[l].cin, (float*)nullptr, gnext, r, nb.s,
+                               half_dt, (float*)nullptr, (const float*)pre[l - 1]);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            std::swap(g, gnext);
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, nb.theta, (const float*)nb.grad, nb.m, nb.v, n,
+                       lr, b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace jfnk

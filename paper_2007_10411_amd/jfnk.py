@@ -57,6 +57,7 @@ class NewtonResult:
     converged: bool
     res0: float
     res_final: float
+    fallbacks: int = 0
 
 
 class Context:
@@ -138,23 +139,78 @@ class Context:
 
     def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, inner="f64",
                     m=30, max_restarts=20, pc="physics", jv="stable", sweeps=2, forcing="ew", eta=1e-2,
-                    eta_floor=0.0):
+                    eta_floor=0.0, record=None, record_krylov=False):
+        """record: optional (R, DU, count) with R, DU float32 device tensors of
+        shape (cap, n) receiving the Newton linear systems; count is a one-element
+        list updated in place."""
         self._check_size(u_n, u_np1)
         gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
                          max_iters=0)
         o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=DTYPES[inner],
                          gm=gm, forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
+        cnt = C.c_int32(0)
+        if record is not None:
+            Rr, Dr, count = record
+            cnt.value = count[0]
+            o.rec_r = Rr.data_ptr()
+            o.rec_du = Dr.data_ptr()
+            o.rec_cap = Rr.shape[0]
+            o.rec_count = C.pointer(cnt)
+            o.rec_krylov = 1 if record_krylov else 0
         info = L.NewtonInfo()
         L.check(self.lib.jfnk_newton_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), C.byref(info)),
                 "jfnk_newton_step")
+        if record is not None:
+            record[2][0] = cnt.value
         return NewtonResult(info.newton_iters, info.gmres_iters_total, bool(info.converged), info.res0,
-                            info.res_final)
+                            info.res_final, info.fallbacks)
 
     def norm(self, x):
         out = C.c_double()
         L.check(self.lib.jfnk_norm(self.h, _dcode(x), _ptr(x), x.numel(), C.byref(out)), "jfnk_norm",
                 soft_ok=False)
         return out.value
+
+    # -- learned preconditioner -----------------------------------------------
+    def net_init(self):
+        n = C.c_int64()
+        L.check(self.lib.jfnk_net_init(self.h, C.byref(n)), "jfnk_net_init", soft_ok=False)
+        self.n_params = n.value
+        return n.value
+
+    def net_set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        L.check(self.lib.jfnk_net_set_params(self.h, th.ctypes.data_as(C.c_void_p), th.size),
+                "jfnk_net_set_params", soft_ok=False)
+
+    def net_get_params(self):
+        th = np.empty(self.n_params, dtype=np.float32)
+        L.check(self.lib.jfnk_net_get_params(self.h, th.ctypes.data_as(C.c_void_p), th.size),
+                "jfnk_net_get_params", soft_ok=False)
+        return th
+
+    def net_apply(self, r, z, bf16=True):
+        self._check_size(r, z)
+        L.check(self.lib.jfnk_net_apply(self.h, 1 if bf16 else 0, _ptr(r), _ptr(z)), "jfnk_net_apply",
+                soft_ok=False)
+        return z
+
+    def net_loss_grad(self, R, DU, want_grad=True):
+        """R, DU: float32 device tensors holding `batch` state vectors back to back."""
+        batch = R.numel() // self.n
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        L.check(self.lib.jfnk_net_loss_grad(self.h, _ptr(R), _ptr(DU), batch, C.byref(loss),
+                                            g.ctypes.data_as(C.c_void_p) if want_grad else None),
+                "jfnk_net_loss_grad", soft_ok=False)
+        return loss.value, g
+
+    def net_train_step(self, R, DU, lr):
+        batch = R.numel() // self.n
+        loss = C.c_double()
+        L.check(self.lib.jfnk_net_train_step(self.h, _ptr(R), _ptr(DU), batch, float(lr), C.byref(loss)),
+                "jfnk_net_train_step", soft_ok=False)
+        return loss.value
 
     # -- timing ----------------------------------------------------------------
     def timing(self, on: bool):

@@ -1,0 +1,157 @@
+"""GPU parity of the learned preconditioner against the FP64 oracle network:
+FP32 forward (1e-5), BF16 MFMA forward (within the BF16 rounding bound), FP32
+loss and gradient, the Adam step, FGMRES with the learned preconditioner, and
+what the trained network gains over the untrained (diagonal-only) form."""
+import numpy as np
+import pytest
+
+from oracle import net as N
+from paper_2007_10411_amd import inputs as I
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(prob, max_m=30):
+    from paper_2007_10411_amd.jfnk import Context
+    c = Context(prob, max_m=max_m)
+    c.net_init()
+    return c
+
+
+def _theta(nf, seed=1):
+    th = I.net_init_params(nf, seed=seed, out_scale=1.0)
+    th = th + np.random.Generator(np.random.PCG64(seed + 50)).normal(scale=0.05, size=th.size)
+    return th.astype(np.float32).astype(np.float64)
+
+
+def _r(prob, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = rng.normal(size=prob.shape) * np.array([1.0, 0.5, 1e-3, 2.0])[:, None, None, None]
+    return r.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("nx,nz", [(100, 40), (64, 4), (200, 9)])
+def test_net_forward_f32_and_bf16(nx, nz):
+    prob = I.thermal_stable_2d(nx, max(nz, 8)) if nz >= 8 else I.thermal_stable_2d(nx, 8)
+    c = _ctx(prob)
+    th = _theta(prob.nf)
+    c.net_set_params(th)
+    r = _r(prob, 2)
+    ref = N.forward(th, r, prob.dt)
+    netpart = ref - 0.5 * prob.dt * r
+    z = dev(np.zeros(prob.shape), "f32")
+    c.net_apply(dev(r, "f32"), z, bf16=False)
+    gp = host(z) - 0.5 * prob.dt * r
+    for k in range(prob.nf):
+        e = np.linalg.norm(gp[k] - netpart[k]) / np.linalg.norm(netpart[k])
+        assert e < 1e-5, ("f32", k, e)
+    c.net_apply(dev(r, "f32"), z, bf16=True)
+    gp = host(z) - 0.5 * prob.dt * r
+    for k in range(prob.nf):
+        e = np.linalg.norm(gp[k] - netpart[k]) / np.linalg.norm(netpart[k])
+        # four layers of BF16 operands (8-bit significands) with FP32 accumulation
+        assert e < 3e-2, ("bf16", k, e)
+
+
+def test_net_loss_gradient_matches_oracle():
+    prob = I.thermal_stable_2d(70, 20)
+    c = _ctx(prob)
+    th = _theta(prob.nf, seed=3)
+    c.net_set_params(th)
+    R = [_r(prob, 4), _r(prob, 5)]
+    DU = [_r(prob, 6), _r(prob, 7)]
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    Rd = dev(np.stack(R), "f32")
+    Dd = dev(np.stack(DU), "f32")
+    lg, gg = c.net_loss_grad(Rd, Dd)
+    assert abs(lg - lo) <= 1e-5 * lo
+    assert np.linalg.norm(gg - go) <= 1e-4 * np.linalg.norm(go)
+    # per layer as well (the small first / last layers must not hide in the norm)
+    o = 0
+    for ws, bs in I.net_layer_shapes(prob.nf):
+        nw = int(np.prod(ws)) + int(np.prod(bs))
+        sl = slice(o, o + nw)
+        assert np.linalg.norm(gg[sl] - go[sl]) <= 1e-4 * np.linalg.norm(go[sl])
+        o += nw
+
+
+def test_net_adam_step_matches_oracle():
+    prob = I.thermal_stable_2d(64, 16)
+    c = _ctx(prob)
+    th = _theta(prob.nf, seed=8)
+    c.net_set_params(th)
+    R = [_r(prob, 9)]
+    DU = [_r(prob, 10)]
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    lr = 1e-3
+    ref, _, _ = N.adam_step(th, go, np.zeros_like(th), np.zeros_like(th), 1, lr)
+    loss = c.net_train_step(dev(R[0], "f32"), dev(DU[0], "f32"), lr)
+    assert abs(loss - lo) <= 1e-5 * lo
+    got = c.net_get_params().astype(np.float64)
+    # first Adam step moves each weight by lr * g / (|g| + eps): compare the moves
+    dg, dr = got - th, ref - th
+    big = np.abs(go) > 1e-3 * np.abs(go).max()
+    assert np.abs(dg[big] - dr[big]).max() <= 1e-3 * lr
+    assert np.abs(dg).max() <= 1.0001 * lr
+
+
+def test_learned_pc_in_fgmres_converges_and_falls_back():
+    prob = I.thermal_stable_2d(128, 64)
+    c = _ctx(prob)
+    th = I.net_init_params(prob.nf, seed=0)
+    c.net_set_params(th)
+    U0 = I.bubble_state(prob)
+    un = dev(U0)
+    u = un.clone()
+    r = c.newton_step(un, u, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4)
+    assert r.converged
+    # two iterations cannot reach a forcing term of 1e-10: the learned solve fails
+    # and is redone with the physics-based preconditioner
+    u2 = un.clone()
+    r2 = c.newton_step(un, u2, rtol=1e-8, inner="f32", pc="learned", forcing="fixed", eta=1e-10,
+                       max_restarts=1, m=2, max_newton=1)
+    assert r2.fallbacks == 1 and not r2.converged
+
+
+def test_trained_network_beats_untrained_form():
+    """Train on pairs the solver generates on the stable thermal (Krylov
+    directions and their images, noise directions through the solver's Jv); the
+    trained preconditioner needs fewer Krylov iterations per step than the same
+    form with N = 0 (z = (dt/2) r, its starting point) and than the physics-based
+    preconditioner."""
+    from paper_2007_10411_amd import learned as LRN
+    prob = I.thermal_stable_2d(256, 128)
+    c = _ctx(prob)
+    u0 = dev(I.bubble_state(prob))
+    R, DU, u_end = LRN.collect_pairs(c, u0, steps=4, cap=256)
+    assert R.shape[0] >= 64
+    ntest = 16
+    theta, losses = LRN.train_mixed(c, R[:-ntest], DU[:-ntest], u_end, iters=1500, lr=2e-3, batch=8)
+    held = LRN.held_out_loss(c, R[-ntest:], DU[-ntest:])
+    zero = np.zeros(c.n_params, dtype=np.float32)
+    c.net_set_params(zero)
+    held0 = LRN.held_out_loss(c, R[-ntest:], DU[-ntest:])
+    assert held < 0.1 * held0
+
+    def iters(pc, params):
+        if params is not None:
+            c.net_set_params(params)
+        u = u_end.clone()
+        tot = 0
+        for _ in range(2):
+            nxt = u.clone()
+            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc=pc, eta_floor=1e-4)
+            assert res.converged and res.fallbacks == 0
+            tot += res.gmres_iters_total
+            u.copy_(nxt)
+        return tot
+
+    it_zero = iters("learned", zero)
+    it_trained = iters("learned", theta)
+    it_phys = iters("physics", None)
+    print(f"GMRES iterations over 2 steps: N=0 {it_zero}, trained {it_trained}, physics {it_phys}; "
+          f"held-out loss {held:.3e} (N=0 {held0:.3e}), train loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
+    assert it_trained < it_zero
+    assert it_trained < it_phys
