@@ -189,6 +189,14 @@ int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
 /* 2-norm of a vector of n values (FP64 accumulation), result to a host double.   */
 int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* out);
 
+/* Autotuner: times every compiled tile shape (64 x 4, 64 x 8, 64 x 16 points)
+ * of the residual, Jv and preconditioner-sweep kernels in both precisions on
+ * this context's grid (HIP events, one warm-up and five timed launches each) and
+ * keeps the fastest for the context; tile_rows (HOST, 6 entries, may be NULL)
+ * receives the chosen tile heights for (F64 residual, F32 residual, F64 Jv,
+ * F32 Jv, F64 sweep, F32 sweep).  Overwrites the Krylov workspace; synchronises. */
+int jfnk_tune(jfnk_ctx* ctx, int32_t* tile_rows);
+
 /* Kernel timing with HIP events recorded on the context stream around each
  * launch (resolved lazily, no synchronisation per launch).  Kernel classes:
  * 0 Jv, 1 residual/rhs, 2 physics preconditioner (diagonal start and sweeps),
@@ -230,6 +238,31 @@ int jfnk_net_loss_grad(jfnk_ctx* ctx, const float* r, const float* du, int32_t b
  * loss receives the loss before the step (host double, may be NULL).            */
 int jfnk_net_train_step(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, float lr,
                         double* loss);
+
+/* ---- batched ensemble (2D) ------------------------------------------------
+ * Independent problems of uneven grid sizes solved together: every stage of the
+ * Newton-Krylov iteration (residual, preconditioner, Jv, Gram-Schmidt passes,
+ * Givens step) is one launch over all instances, instances that have converged
+ * drop out through a device mask.  Batch state vectors hold the instances'
+ * vectors back to back (instance i at element offsets[i], each in the layout of a
+ * single problem).  The inner solve is FP32 FGMRES with the physics-based (or no)
+ * preconditioner; the Newton residual, update and norms are FP64.              */
+typedef struct jfnk_batch jfnk_batch;
+/* Allocates the batch workspace for ninst problems (host array).                 */
+int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, void* hip_stream,
+                      jfnk_batch** out);
+int jfnk_batch_destroy(jfnk_batch* batch);
+/* total: elements of a batch state vector; offsets (HOST, ninst + 1, or NULL).   */
+int jfnk_batch_size(jfnk_batch* batch, int64_t* total, int64_t* offsets);
+/* F / rhs / residual of every instance (what as in jfnk_apply_F), FP64.          */
+int jfnk_batch_apply_F(jfnk_batch* batch, int32_t what, const double* u, const double* f, double* out);
+/* One trapezoidal step of every instance (opts->inner must be JFNK_F32; the
+ * recording fields are ignored); infos: HOST array of ninst results.            */
+int jfnk_batch_newton_step(jfnk_batch* batch, const double* u_n, double* u_np1, const jfnk_newton_opts* opts,
+                           jfnk_newton_info* infos);
+/* Autotuner of the batched residual, Jv and sweep kernels (tile heights 4, 8,
+ * 16); tile_rows (HOST, 3 entries, may be NULL) receives the choices.           */
+int jfnk_batch_tune(jfnk_batch* batch, int32_t* tile_rows);
 
 #ifdef __cplusplus
 }

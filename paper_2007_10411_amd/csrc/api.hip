@@ -49,6 +49,9 @@ template <> float* TA<float>(jfnk_ctx* c) { return c->t32a; }
 template <typename T> T* TB(jfnk_ctx* c);
 template <> double* TB<double>(jfnk_ctx* c) { return c->t64b; }
 template <> float* TB<float>(jfnk_ctx* c) { return c->t32b; }
+template <typename T> constexpr int is32() { return sizeof(T) == 4 ? 1 : 0; }
+int tv(jfnk_ctx* c, int stage, int f32) { return c->tune[stage * 2 + f32]; }
+
 template <typename T> constexpr double eps_mach();
 template <> constexpr double eps_mach<double>() { return 2.220446049250313e-16; }   // 2^-52
 template <> constexpr double eps_mach<float>() { return 1.1920928955078125e-07; }   // 2^-23
@@ -163,20 +166,20 @@ int apply_jv(jfnk_ctx* c, int mode, const T* u, const T* v, const double* eps_de
         JFNK_HIP(launch_lincomb<T>(w1, u, v, c->n, 1.0, e, c->stream));
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<T>(c->geo, w1, nullptr, w2, 2, c->stream));
+            JFNK_HIP(launch_apply_F<T>(c->geo, w1, nullptr, w2, 2, c->stream, tv(c, 0, is32<T>())));
         }
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<T>(c->geo, u, nullptr, w1, 2, c->stream));
+            JFNK_HIP(launch_apply_F<T>(c->geo, u, nullptr, w1, 2, c->stream, tv(c, 0, is32<T>())));
         }
         JFNK_HIP(launch_lincomb<T>(out, w2, w1, c->n, 1.0 / e, -1.0 / e, c->stream));
         return JFNK_OK;
     }
     TimedLaunch tl(c, KC_JV, 3.0 * c->n * sizeof(T));
     if (mode == JFNK_JV_ANALYTIC)
-        JFNK_HIP(launch_jv<T>(c->geo, u, v, 0.0, nullptr, out, c->stream));
+        JFNK_HIP(launch_jv<T>(c->geo, u, v, 0.0, nullptr, out, c->stream, tv(c, 1, is32<T>())));
     else
-        JFNK_HIP(launch_jv<T>(c->geo, u, v, eps_host, eps_dev, out, c->stream));
+        JFNK_HIP(launch_jv<T>(c->geo, u, v, eps_host, eps_dev, out, c->stream, tv(c, 1, is32<T>())));
     return JFNK_OK;
 }
 
@@ -248,7 +251,7 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
     for (int s = 0; s < sweeps; ++s) {
         TimedLaunch tl(c, KC_PC, (3.0 * c->n + (c->geo.dim + 1) * npts) * sizeof(T));
         JFNK_HIP(launch_pc_sweep<T>(c->geo, u, nu, vj, bufs[cur], bufs[1 - cur], s == sweeps - 1 ? ea : none,
-                                    c->stream));
+                                    c->stream, tv(c, 2, is32<T>())));
         cur = 1 - cur;
     }
     return JFNK_OK;
@@ -398,6 +401,46 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
     }
     JFNK_HIP(hipStreamSynchronize(s));
     return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+// Autotuner: every compiled tile height (4, 8, 16 rows of 64 points) of the
+// three stencil stages in both precisions is timed with HIP events on this
+// context's grid (one warm-up and five timed launches on the workspace
+// vectors); the fastest is kept for the context.
+template <typename T>
+int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
+    T* V = Vb<T>(c);
+    T* Z = Zb<T>(c);
+    const long long n = c->n;
+    hipStream_t s = c->stream;
+    JFNK_HIP(hipMemsetAsync(V, 0, 2 * n * sizeof(T), s));
+    JFNK_HIP(launch_frozen_nu<T>(c->geo, V, NUb<T>(c), s));
+    EpsArgs none;
+    for (int stage = 0; stage < 3; ++stage) {
+        float best = 1e30f;
+        int bestv = 1;
+        for (int var = 0; var < 3; ++var) {
+            if (stage == 1 && sizeof(T) == 8 && var == 2) continue;   // exceeds the LDS of a CU
+            auto launch = [&]() -> hipError_t {
+                if (stage == 0) return launch_apply_F<T>(c->geo, V, nullptr, Z, 0, s, var);
+                if (stage == 1) return launch_jv<T>(c->geo, V, V + n, 1e-6, nullptr, Z, s, var);
+                return launch_pc_sweep<T>(c->geo, V, NUb<T>(c), V + n, V, Z, none, s, var);
+            };
+            JFNK_HIP(launch());
+            JFNK_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < 5; ++k) JFNK_HIP(launch());
+            JFNK_HIP(hipEventRecord(e1, s));
+            JFNK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            JFNK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bestv = var;
+            }
+        }
+        c->tune[stage * 2 + is32<T>()] = bestv;
+    }
+    return JFNK_OK;
 }
 
 bool valid_problem(const jfnk_problem* p, std::string& why) {
@@ -590,9 +633,11 @@ int jfnk_apply_F(jfnk_ctx* c, jfnk_dtype dt, int32_t what, const void* u, const 
     }
     TimedLaunch tl(c, KC_RESIDUAL);
     if (dt == JFNK_F64)
-        JFNK_HIP(launch_apply_F<double>(c->geo, (const double*)u, (const double*)f, (double*)out, what, c->stream));
+        JFNK_HIP(launch_apply_F<double>(c->geo, (const double*)u, (const double*)f, (double*)out, what, c->stream,
+                                        tv(c, 0, 0)));
     else if (dt == JFNK_F32)
-        JFNK_HIP(launch_apply_F<float>(c->geo, (const float*)u, (const float*)f, (float*)out, what, c->stream));
+        JFNK_HIP(launch_apply_F<float>(c->geo, (const float*)u, (const float*)f, (float*)out, what, c->stream,
+                                       tv(c, 0, 1)));
     else {
         set_error("invalid dtype");
         return JFNK_ERR_ARG;
@@ -694,12 +739,12 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
     int rc;
     {
         TimedLaunch tl(c, KC_RESIDUAL);
-        JFNK_HIP(launch_apply_F<double>(c->geo, u_n, nullptr, c->f64, 1, s));
+        JFNK_HIP(launch_apply_F<double>(c->geo, u_n, nullptr, c->f64, 1, s, tv(c, 0, 0)));
     }
     auto resid_norm = [&](double& out) -> int {
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<double>(c->geo, u, c->f64, c->R64, 2, s));
+            JFNK_HIP(launch_apply_F<double>(c->geo, u, c->f64, c->R64, 2, s, tv(c, 0, 0)));
         }
         int r2 = norm2_to<double>(c, c->R64, n, sc(c, S_TMP));
         if (r2) return r2;
@@ -802,6 +847,24 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
     inf.res_final = rn;
     if (info) *info = inf;
     return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+int jfnk_tune(jfnk_ctx* c, int32_t* tile_rows) {
+    if (!c) {
+        set_error("null context");
+        return JFNK_ERR_ARG;
+    }
+    hipEvent_t e0, e1;
+    JFNK_HIP(hipEventCreate(&e0));
+    JFNK_HIP(hipEventCreate(&e1));
+    int rc = tune_precision<double>(c, e0, e1);
+    if (!rc) rc = tune_precision<float>(c, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (tile_rows)
+        for (int k = 0; k < 6; ++k) tile_rows[k] = tile_tz(c->tune[k]);
+    return JFNK_OK;
 }
 
 int jfnk_timing_enable(jfnk_ctx* c, int32_t enable) {

@@ -76,6 +76,10 @@ struct EpsArgs {
     double sqrt_n = 0.0;
 };
 
+// per-instance scalar block of a batch (doubles)
+constexpr int S_STRIDE = 16;
+enum { SB_UNORM2 = 0, SB_VNORM2 = 1, SB_EPS = 2, SB_WNORM = 3, SB_RES = 4, SB_BETA = 5, SB_SQRTN = 6 };
+
 enum CgsMode { CGS_DOT = 0, CGS_UPD_DOT = 1, CGS_UPD_NORM = 2 };
 
 enum KernelClass { KC_JV = 0, KC_RESIDUAL = 1, KC_PC = 2, KC_ARNOLDI = 3, KC_VEC = 4, KC_NET = 5, KC_COUNT = 6 };
@@ -169,6 +173,9 @@ struct jfnk_ctx {
     jfnk::Timing timing;
     jfnk::NetBuffers net;
     int fallbacks = 0;
+    // tile variant per stencil stage, chosen by jfnk_tune (index: stage * 2 + (FP32 ? 1 : 0);
+    // stages 0 residual / F, 1 Jv, 2 preconditioner sweep)
+    int tune[6] = {1, 1, 1, 1, 1, 1};
     // Krylov-pair recording (J z_j, z_j) during FP32 solves
     float* rec_r = nullptr;
     float* rec_du = nullptr;
@@ -189,12 +196,14 @@ int hip_fail(hipError_t e, const char* what);
 
 // ---- kernel launchers (stencil.hip) ----
 // out = F(u) (what 0), 2u/dt + F(u) (what 1), 2u/dt - F(u) - f (what 2)
+// var: tile variant chosen by the autotuner (tile height 4 << var)
+int tile_tz(int variant);
 template <typename T>
-hipError_t launch_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, hipStream_t s);
+hipError_t launch_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, hipStream_t s, int var = 1);
 // Jv = 2v/dt - [F(u + eps v) - F(u)]/eps, expanded; eps read from *eps_dev if non-null
 template <typename T>
 hipError_t launch_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* jv,
-                     hipStream_t s);
+                     hipStream_t s, int var = 1);
 // frozen eddy viscosity nu(u) at the grid points
 template <typename T>
 hipError_t launch_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
@@ -202,7 +211,7 @@ hipError_t launch_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
 // (zin == nullptr: zin = r/d)
 template <typename T>
 hipError_t launch_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
-                           const EpsArgs& ea, hipStream_t s);
+                           const EpsArgs& ea, hipStream_t s, int var = 1);
 // z = v / d with v = V_j / *div written back into V_j when div != null; the norm of
 // z (for the FD step) when ea.partials != null
 template <typename T>

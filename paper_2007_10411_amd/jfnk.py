@@ -212,6 +212,13 @@ class Context:
                 "jfnk_net_train_step", soft_ok=False)
         return loss.value
 
+    def tune(self):
+        """Autotune the stencil tile shapes; returns the chosen tile heights."""
+        rows = (C.c_int32 * 6)()
+        L.check(self.lib.jfnk_tune(self.h, rows), "jfnk_tune", soft_ok=False)
+        keys = ["f64_residual", "f32_residual", "f64_jv", "f32_jv", "f64_pc_sweep", "f32_pc_sweep"]
+        return dict(zip(keys, list(rows)))
+
     # -- timing ----------------------------------------------------------------
     def timing(self, on: bool):
         L.check(self.lib.jfnk_timing_enable(self.h, 1 if on else 0), "jfnk_timing_enable", soft_ok=False)
@@ -224,3 +231,67 @@ class Context:
         L.check(self.lib.jfnk_timing_read(self.h, int(cls), C.byref(ms), C.byref(cnt), C.byref(by)),
                 "jfnk_timing_read", soft_ok=False)
         return ms.value, cnt.value, by.value
+
+
+class Batch:
+    """Ensemble of independent 2D problems solved together (``jfnk_batch_*``).
+    Batch vectors are the instances' state vectors back to back."""
+
+    def __init__(self, probs, max_m: int = 30, stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.probs = list(probs)
+        arr = (L.Problem * len(self.probs))(*[L.problem_struct(p) for p in self.probs])
+        s = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        L.check(self.lib.jfnk_batch_create(arr, len(self.probs), int(max_m), C.c_void_p(s.cuda_stream), C.byref(h)),
+                "jfnk_batch_create", soft_ok=False)
+        self.h = h
+        tot = C.c_int64()
+        offs = (C.c_int64 * (len(self.probs) + 1))()
+        L.check(self.lib.jfnk_batch_size(self.h, C.byref(tot), offs), "jfnk_batch_size", soft_ok=False)
+        self.n = tot.value
+        self.offsets = list(offs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.jfnk_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, states):
+        """List of (n_f, nz, 1, nx) numpy states -> one FP64 device vector."""
+        torch = _torch()
+        flat = np.concatenate([np.ascontiguousarray(s, dtype=np.float64).ravel() for s in states])
+        return torch.from_numpy(flat).cuda()
+
+    def unpack(self, t):
+        h = t.detach().double().cpu().numpy()
+        return [h[self.offsets[i]:self.offsets[i + 1]].reshape(p.shape) for i, p in enumerate(self.probs)]
+
+    def apply_F(self, u, out, what=0, f=None):
+        L.check(self.lib.jfnk_batch_apply_F(self.h, int(what), _ptr(u), _ptr(f), _ptr(out)), "jfnk_batch_apply_F",
+                soft_ok=False)
+        return out
+
+    def tune(self):
+        rows = (C.c_int32 * 3)()
+        L.check(self.lib.jfnk_batch_tune(self.h, rows), "jfnk_batch_tune", soft_ok=False)
+        return dict(zip(["f64_residual", "f32_jv", "f32_pc_sweep"], list(rows)))
+
+    def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, m=30, max_restarts=20,
+                    pc="physics", sweeps=2, forcing="ew", eta=1e-2, eta_floor=1e-4):
+        gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=L.JV_STABLE, sweeps=sweeps,
+                         max_iters=0)
+        o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=L.F32, gm=gm,
+                         forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
+        infos = (L.NewtonInfo * len(self.probs))()
+        L.check(self.lib.jfnk_batch_newton_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), infos),
+                "jfnk_batch_newton_step")
+        return [NewtonResult(i.newton_iters, i.gmres_iters_total, bool(i.converged), i.res0, i.res_final,
+                             i.fallbacks) for i in infos]
