@@ -52,6 +52,38 @@ template <> float* TB<float>(jfnk_ctx* c) { return c->t32b; }
 template <typename T> constexpr int is32() { return sizeof(T) == 4 ? 1 : 0; }
 int tv(jfnk_ctx* c, int stage, int f32) { return c->tune[stage * 2 + f32]; }
 
+template <typename T> T* DB(jfnk_ctx* c);
+template <> double* DB<double>(jfnk_ctx* c) { return c->d64; }
+template <> float* DB<float>(jfnk_ctx* c) { return c->d32; }
+
+// operator dispatch: 2D tiled kernels (tuned tile height) or the 3D two-pass kernels
+template <typename T>
+hipError_t op_F(jfnk_ctx* c, const T* u, const T* f, T* out, int what) {
+    if (c->geo.dim == 3) return launch3_apply_F<T>(c->geo, u, f, out, what, DB<T>(c), c->stream);
+    return launch_apply_F<T>(c->geo, u, f, out, what, c->stream, tv(c, 0, is32<T>()));
+}
+template <typename T>
+hipError_t op_jv(jfnk_ctx* c, const T* u, const T* v, double eps, const double* eps_dev, T* out) {
+    if (c->geo.dim == 3) return launch3_jv<T>(c->geo, u, v, eps, eps_dev, out, DB<T>(c), c->stream);
+    return launch_jv<T>(c->geo, u, v, eps, eps_dev, out, c->stream, tv(c, 1, is32<T>()));
+}
+template <typename T>
+hipError_t op_frozen_nu(jfnk_ctx* c, const T* u, T* nu) {
+    if (c->geo.dim == 3) return launch3_frozen_nu<T>(c->geo, u, nu, c->stream);
+    return launch_frozen_nu<T>(c->geo, u, nu, c->stream);
+}
+template <typename T>
+hipError_t op_pc_diag(jfnk_ctx* c, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea) {
+    if (c->geo.dim == 3) return launch3_pc_diag<T>(c->geo, nu, vj, div, z, ea, c->stream);
+    return launch_pc_diag<T>(c->geo, nu, vj, div, z, ea, c->stream);
+}
+template <typename T>
+hipError_t op_pc_sweep(jfnk_ctx* c, const T* u, const T* nu, const T* r, const T* zin, T* zout,
+                       const EpsArgs& ea) {
+    if (c->geo.dim == 3) return launch3_pc_sweep<T>(c->geo, u, nu, r, zin, zout, ea, c->stream);
+    return launch_pc_sweep<T>(c->geo, u, nu, r, zin, zout, ea, c->stream, tv(c, 2, is32<T>()));
+}
+
 template <typename T> constexpr double eps_mach();
 template <> constexpr double eps_mach<double>() { return 2.220446049250313e-16; }   // 2^-52
 template <> constexpr double eps_mach<float>() { return 1.1920928955078125e-07; }   // 2^-23
@@ -166,20 +198,20 @@ int apply_jv(jfnk_ctx* c, int mode, const T* u, const T* v, const double* eps_de
         JFNK_HIP(launch_lincomb<T>(w1, u, v, c->n, 1.0, e, c->stream));
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<T>(c->geo, w1, nullptr, w2, 2, c->stream, tv(c, 0, is32<T>())));
+            JFNK_HIP(op_F<T>(c, w1, nullptr, w2, 2));
         }
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<T>(c->geo, u, nullptr, w1, 2, c->stream, tv(c, 0, is32<T>())));
+            JFNK_HIP(op_F<T>(c, u, nullptr, w1, 2));
         }
         JFNK_HIP(launch_lincomb<T>(out, w2, w1, c->n, 1.0 / e, -1.0 / e, c->stream));
         return JFNK_OK;
     }
     TimedLaunch tl(c, KC_JV, 3.0 * c->n * sizeof(T));
     if (mode == JFNK_JV_ANALYTIC)
-        JFNK_HIP(launch_jv<T>(c->geo, u, v, 0.0, nullptr, out, c->stream, tv(c, 1, is32<T>())));
+        JFNK_HIP(op_jv<T>(c, u, v, 0.0, nullptr, out));
     else
-        JFNK_HIP(launch_jv<T>(c->geo, u, v, eps_host, eps_dev, out, c->stream, tv(c, 1, is32<T>())));
+        JFNK_HIP(op_jv<T>(c, u, v, eps_host, eps_dev, out));
     return JFNK_OK;
 }
 
@@ -246,12 +278,11 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
     const double npts = (double)c->geo.npts;
     {
         TimedLaunch tl(c, KC_PC, ((div ? 3.0 : 2.0) * c->n + npts) * sizeof(T));
-        JFNK_HIP(launch_pc_diag<T>(c->geo, nu, vj, div, bufs[cur], sweeps == 0 ? ea : none, c->stream));
+        JFNK_HIP(op_pc_diag<T>(c, nu, vj, div, bufs[cur], sweeps == 0 ? ea : none));
     }
     for (int s = 0; s < sweeps; ++s) {
         TimedLaunch tl(c, KC_PC, (3.0 * c->n + (c->geo.dim + 1) * npts) * sizeof(T));
-        JFNK_HIP(launch_pc_sweep<T>(c->geo, u, nu, vj, bufs[cur], bufs[1 - cur], s == sweeps - 1 ? ea : none,
-                                    c->stream, tv(c, 2, is32<T>())));
+        JFNK_HIP(op_pc_sweep<T>(c, u, nu, vj, bufs[cur], bufs[1 - cur], s == sweeps - 1 ? ea : none));
         cur = 1 - cur;
     }
     return JFNK_OK;
@@ -266,7 +297,7 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
     T* Z = Zb<T>(c);
     hipStream_t s = c->stream;
     int rc;
-    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(launch_frozen_nu<T>(c->geo, u, NUb<T>(c), s));
+    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, u, NUb<T>(c)));
     if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
     JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
     JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
@@ -445,8 +476,10 @@ int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
 
 bool valid_problem(const jfnk_problem* p, std::string& why) {
     if (!p) return why = "null problem", false;
-    if (p->dim != 2) return why = "only dim = 2 is supported by this build", false;
-    if (p->nx < 8 || p->nz < 8 || p->ny != 1) return why = "grid below 8 points in a direction (or ny != 1 in 2D)", false;
+    if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", false;
+    if (p->nx < 8 || p->nz < 8 || (p->dim == 2 && p->ny != 1) || (p->dim == 3 && p->ny < 8))
+        return why = "grid below 8 points in a direction (or ny != 1 in 2D)", false;
+    if (p->dim == 3 && !(p->ly > 0)) return why = "non-positive domain size", false;
     if (!(p->dt > 0) || !(p->lx > 0) || !(p->lz > 0)) return why = "non-positive dt or domain size", false;
     if (p->dd_p != 2) return why = "only dd_p = 2 is supported", false;
     if (p->bc_lateral != JFNK_BC_FREE_SLIP && p->bc_lateral != JFNK_BC_PERIODIC)
@@ -553,6 +586,10 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     ALLOC(c->t32a, nb32);
     ALLOC(c->t32b, nb32);
     ALLOC(c->nu32, next * sizeof(float));
+    if (g.dim == 3) {
+        ALLOC(c->d64, 9 * next * sizeof(double));
+        ALLOC(c->d32, 9 * next * sizeof(float));
+    }
     const size_t nbg = (size_t)2 * g.nz + (size_t)g.nx * g.ny;
     ALLOC(c->bg64, nbg * sizeof(double));
     ALLOC(c->bg32, nbg * sizeof(float));
@@ -597,7 +634,7 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
 int jfnk_destroy(jfnk_ctx* c) {
     if (!c) return JFNK_OK;
     (void)hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->V64, c->Z64, c->V32, c->Z32, c->f64, c->R64, c->t64a, c->t64b, c->b64, c->x64, c->nu64, c->u32, c->b32,
+    void* ptrs[] = {c->V64, c->Z64, c->V32, c->Z32, c->f64, c->R64, c->t64a, c->t64b, c->b64, c->x64, c->nu64, c->d64, c->d32, c->u32, c->b32,
                     c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal, c->epart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -633,11 +670,9 @@ int jfnk_apply_F(jfnk_ctx* c, jfnk_dtype dt, int32_t what, const void* u, const 
     }
     TimedLaunch tl(c, KC_RESIDUAL);
     if (dt == JFNK_F64)
-        JFNK_HIP(launch_apply_F<double>(c->geo, (const double*)u, (const double*)f, (double*)out, what, c->stream,
-                                        tv(c, 0, 0)));
+        JFNK_HIP(op_F<double>(c, (const double*)u, (const double*)f, (double*)out, what));
     else if (dt == JFNK_F32)
-        JFNK_HIP(launch_apply_F<float>(c->geo, (const float*)u, (const float*)f, (float*)out, what, c->stream,
-                                       tv(c, 0, 1)));
+        JFNK_HIP(op_F<float>(c, (const float*)u, (const float*)f, (float*)out, what));
     else {
         set_error("invalid dtype");
         return JFNK_ERR_ARG;
@@ -681,7 +716,7 @@ int jfnk_precond_apply(jfnk_ctx* c, jfnk_pc_kind pc, jfnk_dtype dt, const void* 
     }
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
-        if (pc == JFNK_PC_PHYSICS) JFNK_HIP(launch_frozen_nu<T>(c->geo, (const T*)u, NUb<T>(c), c->stream));
+        if (pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, (const T*)u, NUb<T>(c)));
         // div = null: r is read, never written
         return apply_pc<T>(c, pc, (const T*)u, (T*)r, nullptr, (T*)z, sweeps, TA<T>(c), EpsArgs());
     };
@@ -739,12 +774,12 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
     int rc;
     {
         TimedLaunch tl(c, KC_RESIDUAL);
-        JFNK_HIP(launch_apply_F<double>(c->geo, u_n, nullptr, c->f64, 1, s, tv(c, 0, 0)));
+        JFNK_HIP(op_F<double>(c, u_n, nullptr, c->f64, 1));
     }
     auto resid_norm = [&](double& out) -> int {
         {
             TimedLaunch tl(c, KC_RESIDUAL);
-            JFNK_HIP(launch_apply_F<double>(c->geo, u, c->f64, c->R64, 2, s, tv(c, 0, 0)));
+            JFNK_HIP(op_F<double>(c, u, c->f64, c->R64, 2));
         }
         int r2 = norm2_to<double>(c, c->R64, n, sc(c, S_TMP));
         if (r2) return r2;
@@ -853,6 +888,11 @@ int jfnk_tune(jfnk_ctx* c, int32_t* tile_rows) {
     if (!c) {
         set_error("null context");
         return JFNK_ERR_ARG;
+    }
+    if (c->geo.dim == 3) {               // the 3D kernels have a single launch shape
+        if (tile_rows)
+            for (int k = 0; k < 6; ++k) tile_rows[k] = 0;
+        return JFNK_OK;
     }
     hipEvent_t e0, e1;
     JFNK_HIP(hipEventCreate(&e0));

@@ -153,7 +153,9 @@ struct jfnk_ctx {
     double* t64b = nullptr;
     double* b64 = nullptr;      // Newton right-hand side -R
     double* x64 = nullptr;      // Newton correction
-    double* nu64 = nullptr;     // frozen eddy viscosity [npts]
+    double* nu64 = nullptr;     // frozen eddy viscosity on the ring-2 extended grid
+    double* d64 = nullptr;      // 3D: stress / heat-flux buffer [9][ext]
+    float* d32 = nullptr;
     // FP32 temporaries
     float* u32 = nullptr;
     float* b32 = nullptr;
@@ -217,6 +219,21 @@ hipError_t launch_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, co
 template <typename T>
 hipError_t launch_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
                           hipStream_t s);
+
+// ---- 3D kernels (stencil3d.hip); dbuf: [9][nz+4][ny+4][nx+4] scratch ----
+template <typename T>
+hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, T* dbuf, hipStream_t s);
+template <typename T>
+hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
+                      hipStream_t s);
+template <typename T>
+hipError_t launch3_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
+template <typename T>
+hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch3_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
+                            const EpsArgs& ea, hipStream_t s);
 
 // ---- vector kernels (vec.hip) ----
 int red_blocks(long long n);

@@ -1,0 +1,527 @@
+// 3D stencil kernels of the JFNK hot path (gfx950).  Same discretisation as the
+// 2D kernels (sections 2.1-2.4, equations 1-5 and 9): 5-point DD derivative,
+// skew-symmetric convection, Smagorinsky stress, mirror-parity ghosts.  Fields
+// (u, v, w, p', theta').
+//
+// The composite stencil D(tau(D u)) reaches 4 points along each axis and 2 x 2
+// across axes, so each operator runs as two passes:
+//   pass 1  the stress tau (6 components) and heat flux q (3) -- or their
+//           finite-difference differences for Jv -- on the grid extended by a
+//           ring of 2, written to an HBM buffer [9][nz+4][ny+4][nx+4];
+//   pass 2  per grid point: convection, pressure gradient, divergence, buoyancy
+//           and the divergences of tau and q.
+// Neighbour values are loaded through the caches with the parity mapping; one
+// thread per point, x fastest (coalesced rows).
+
+#include "jfnk_internal.hpp"
+#include "reduce.hpp"
+
+namespace jfnk {
+
+namespace {
+
+__device__ __forceinline__ int map3(int e, int n, bool periodic, int& side) {
+    side = 0;
+    if (periodic) {
+        int r = e % n;
+        return r < 0 ? r + n : r;
+    }
+    if (e < 0) {
+        side = 1;
+        e = -1 - e;
+    } else if (e >= n) {
+        side = 2;
+        e = 2 * n - 1 - e;
+    }
+    return e < 0 ? 0 : (e >= n ? n - 1 : e);
+}
+
+// Reflection sign of 3D field f (0 u, 1 v, 2 w, 3 p, 4 theta).
+__device__ __forceinline__ bool odd3(int f, int sx, int sy, int sz, int bcv) {
+    bool o = false;
+    if (sx && f == 0) o = !o;
+    if (sy && f == 1) o = !o;
+    if (sz) {
+        if (f == 2) o = !o;
+        else if ((f == 0 || f == 1) && bcv == JFNK_BC_NO_SLIP_BOTTOM && sz == 1) o = !o;
+    }
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ T d5(T m2, T m1, T p1, T p2, T ih) {
+    return (T(2.0 / 3.0) * (p1 - m1) - T(1.0 / 12.0) * (p2 - m2)) * ih;
+}
+
+// field f of a state at (possibly ghost) position (x, y, z)
+template <typename T>
+__device__ __forceinline__ T ld(const Geo& g, const T* __restrict__ u, int f, int x, int y, int z) {
+    int sx, sy, sz;
+    const bool lat = g.bcl == JFNK_BC_PERIODIC;
+    const int mx = map3(x, g.nx, lat, sx), my = map3(y, g.ny, lat, sy);
+    const int mz = map3(z, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+    const T v = u[(long long)f * g.npts + ((long long)mz * g.ny + my) * g.nx + mx];
+    return odd3(f, sx, sy, sz, g.bcv) ? -v : v;
+}
+
+// derivative of field f along axis a (0 x, 1 y, 2 z) at (x, y, z)
+template <typename T>
+__device__ __forceinline__ T dfield(const Geo& g, const T* __restrict__ u, int f, int a, int x, int y, int z) {
+    const int ex = a == 0, ey = a == 1, ez = a == 2;
+    const T ih = T(a == 0 ? g.idx : (a == 1 ? g.idy : g.idz));
+    return d5(ld(g, u, f, x - 2 * ex, y - 2 * ey, z - 2 * ez), ld(g, u, f, x - ex, y - ey, z - ez),
+              ld(g, u, f, x + ex, y + ey, z + ez), ld(g, u, f, x + 2 * ex, y + 2 * ey, z + 2 * ez), ih);
+}
+
+// extended-buffer access: component c at grid position (x, y, z), |offset| <= 2
+template <typename T>
+__device__ __forceinline__ T ldx(const Geo& g, const T* __restrict__ d, int c, int x, int y, int z) {
+    const long long ex = g.nx + 4, ey = g.ny + 4, ez = g.nz + 4;
+    return d[(long long)c * ex * ey * ez + ((long long)(z + 2) * ey + (y + 2)) * ex + (x + 2)];
+}
+
+template <typename T>
+__device__ __forceinline__ T dext(const Geo& g, const T* __restrict__ d, int c, int a, int x, int y, int z) {
+    const int ex = a == 0, ey = a == 1, ez = a == 2;
+    const T ih = T(a == 0 ? g.idx : (a == 1 ? g.idy : g.idz));
+    return d5(ldx(g, d, c, x - 2 * ex, y - 2 * ey, z - 2 * ez), ldx(g, d, c, x - ex, y - ey, z - ez),
+              ldx(g, d, c, x + ex, y + ey, z + ez), ldx(g, d, c, x + 2 * ex, y + 2 * ey, z + 2 * ez), ih);
+}
+
+template <typename T>
+__device__ __forceinline__ void closure3(const Geo& g, T s2, T& nu, T& kth) {
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+        nu = T(g.smag) * sqrt(T(2) * s2);
+        kth = nu * T(g.inv_pr);
+    } else if (g.closure == JFNK_CLOSURE_CONST_K) {
+        nu = T(g.k_m);
+        kth = T(g.k_h);
+    } else {
+        nu = T(0);
+        kth = T(0);
+    }
+}
+
+// symmetric strain (xx, yy, zz, xy, xz, yz) of the velocity of a state
+template <typename T>
+__device__ __forceinline__ void strain3(const Geo& g, const T* __restrict__ u, int x, int y, int z, T S[6],
+                                        T th[3]) {
+    T gr[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] = dfield(g, u, i, j, x, y, z);
+    S[0] = gr[0][0];
+    S[1] = gr[1][1];
+    S[2] = gr[2][2];
+    S[3] = T(0.5) * (gr[0][1] + gr[1][0]);
+    S[4] = T(0.5) * (gr[0][2] + gr[2][0]);
+    S[5] = T(0.5) * (gr[1][2] + gr[2][1]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) th[j] = dfield(g, u, 4, j, x, y, z);
+}
+
+template <typename T>
+__device__ __forceinline__ T frob3(const T a[6], const T b[6]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + T(2) * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]);
+}
+
+__device__ __forceinline__ bool ext_point(const Geo& g, long long i, int& x, int& y, int& z) {
+    const long long ex = g.nx + 4, ey = g.ny + 4, ez = g.nz + 4;
+    if (i >= ex * ey * ez) return false;
+    x = (int)(i % ex) - 2;
+    y = (int)((i / ex) % ey) - 2;
+    z = (int)(i / (ex * ey)) - 2;
+    return true;
+}
+
+// pass 1 of F: tau (6) and q (3) on the ring-2 extended grid
+template <typename T>
+__global__ __launch_bounds__(256) void k3_derived(Geo g, const T* __restrict__ u, T* __restrict__ d) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_point(g, i, x, y, z)) return;
+    T S[6], th[3];
+    strain3(g, u, x, y, z, S, th);
+    T nu, kth;
+    closure3(g, frob3(S, S), nu, kth);
+    const T third = (S[0] + S[1] + S[2]) / T(3);
+    const long long ne = (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4);
+    d[0 * ne + i] = T(2) * nu * (S[0] - third);
+    d[1 * ne + i] = T(2) * nu * (S[1] - third);
+    d[2 * ne + i] = T(2) * nu * (S[2] - third);
+    d[3 * ne + i] = T(2) * nu * S[3];
+    d[4 * ne + i] = T(2) * nu * S[4];
+    d[5 * ne + i] = T(2) * nu * S[5];
+    d[6 * ne + i] = kth * th[0];
+    d[7 * ne + i] = kth * th[1];
+    d[8 * ne + i] = kth * th[2];
+}
+
+// stress component index of (i, j)
+__device__ __forceinline__ int tix(int i, int j) {
+    if (i == j) return i;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a == 0 ? (b == 1 ? 3 : 4) : 5;
+}
+
+// pass 2 of F: out = F (what 0), 2u/dt + F (1), 2u/dt - F - f (2)
+template <typename T>
+__global__ __launch_bounds__(256) void k3_apply_F(Geo g, const T* __restrict__ u, const T* __restrict__ d,
+                                                  const T* __restrict__ f, T* __restrict__ out, int what) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.npts) return;
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+    const long long np = g.npts;
+    T a[3], val[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) val[k] = u[k * np + i];
+    a[0] = val[0];
+    a[1] = val[1];
+    a[2] = val[2];
+    T Fv[5] = {0, 0, 0, 0, 0};
+    if (g.convection) {
+        // C(a; phi) = 1/2 sum_j [D_j(a_j phi) + a_j D_j phi] for all fields
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int ex = j == 0, ey = j == 1, ez = j == 2;
+            const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
+            T am2 = ld(g, u, j, x - 2 * ex, y - 2 * ey, z - 2 * ez), am1 = ld(g, u, j, x - ex, y - ey, z - ez);
+            T ap1 = ld(g, u, j, x + ex, y + ey, z + ez), ap2 = ld(g, u, j, x + 2 * ex, y + 2 * ey, z + 2 * ez);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const T pm2 = ld(g, u, k, x - 2 * ex, y - 2 * ey, z - 2 * ez);
+                const T pm1 = ld(g, u, k, x - ex, y - ey, z - ez);
+                const T pp1 = ld(g, u, k, x + ex, y + ey, z + ez);
+                const T pp2 = ld(g, u, k, x + 2 * ex, y + 2 * ey, z + 2 * ez);
+                const T flux = d5(am2 * pm2, am1 * pm1, ap1 * pp1, ap2 * pp2, ih);
+                const T adv = a[j] * d5(pm2, pm1, pp1, pp2, ih);
+                Fv[k] -= T(0.5) * (flux + adv);
+            }
+        }
+    }
+    const T th0 = T(g.theta0);
+    T div = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Fv[c] -= th0 * dfield(g, u, 3, c, x, y, z);
+        div += dfield(g, u, c, c, x, y, z);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Fv[c] += dext(g, d, tix(c, j), j, x, y, z);
+    }
+    Fv[2] += T(g.g_theta0) * val[4];
+    const T* pb = Bg<T>::pbar(g);
+    const T* dpb = Bg<T>::dpbar(g);
+    if (g.energy_test)
+        Fv[3] -= T(g.kappa_cp) * div;
+    else
+        Fv[3] -= val[2] * dpb[z] + T(g.kappa) * (pb[z] + val[3]) * div;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Fv[4] += dext(g, d, 6 + j, j, x, y, z);
+    Fv[4] -= T(g.beta) * val[2];
+    if (z == 0 && !g.energy_test) Fv[4] += Bg<T>::sflux(g)[(long long)y * g.nx + x];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        T r;
+        if (what == 0) r = Fv[k];
+        else if (what == 1) r = T(g.two_dt) * val[k] + Fv[k];
+        else r = T(g.two_dt) * val[k] - Fv[k] - (f ? f[k * np + i] : T(0));
+        out[k * np + i] = r;
+    }
+}
+
+// pass 1 of Jv: stress and heat-flux differences [tau(u + e v) - tau(u)]/e, etc.
+template <typename T>
+__global__ __launch_bounds__(256) void k3_jv_derived(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                                     double eps_in, const double* __restrict__ eps_dev,
+                                                     T* __restrict__ d) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_point(g, i, x, y, z)) return;
+    const T e = T(eps_dev ? *eps_dev : eps_in);
+    T SU[6], SV[6], tU[3], tV[3];
+    strain3(g, u, x, y, z, SU, tU);
+    strain3(g, v, x, y, z, SV, tV);
+    T nua, ktha;
+    closure3(g, frob3(SU, SU), nua, ktha);
+    T SW[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) SW[k] = SU[k] + e * SV[k];
+    T dnu = T(0), dkth = T(0);
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+        const T den = sqrt(frob3(SU, SU)) + sqrt(frob3(SW, SW));
+        const T num = T(2) * frob3(SU, SV) + e * frob3(SV, SV);
+        dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+        dkth = dnu * T(g.inv_pr);
+    }
+    const T trw = (SW[0] + SW[1] + SW[2]) / T(3), trv = (SV[0] + SV[1] + SV[2]) / T(3);
+    const long long ne = (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const T dw = k < 3 ? SW[k] - trw : SW[k];
+        const T dv = k < 3 ? SV[k] - trv : SV[k];
+        d[k * ne + i] = T(2) * dnu * dw + T(2) * nua * dv;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d[(6 + j) * ne + i] = dkth * (tU[j] + e * tV[j]) + ktha * tV[j];
+}
+
+// pass 2 of Jv: 2v/dt - [F(u + e v) - F(u)]/e with bilinear terms expanded
+template <typename T>
+__global__ __launch_bounds__(256) void k3_jv(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                             double eps_in, const double* __restrict__ eps_dev,
+                                             const T* __restrict__ d, T* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.npts) return;
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+    const long long np = g.npts;
+    const T e = T(eps_dev ? *eps_dev : eps_in);
+    T A[5], B[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        A[k] = u[k * np + i];
+        B[k] = v[k * np + i];
+    }
+    T dF[5] = {0, 0, 0, 0, 0};
+    if (g.convection) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int ex = j == 0, ey = j == 1, ez = j == 2;
+            const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
+            const int ox[4] = {-2, -1, 1, 2};
+            T au[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                au[q] = ld(g, u, j, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
+                bv[q] = ld(g, v, j, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                T pa[4], pbv[4], pr[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    pa[q] = ld(g, u, k, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
+                    pbv[q] = ld(g, v, k, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
+                    pr[q] = au[q] * pbv[q] + bv[q] * (pa[q] + e * pbv[q]);
+                }
+                const T flux = d5(pr[0], pr[1], pr[2], pr[3], ih);
+                const T dA = d5(pa[0], pa[1], pa[2], pa[3], ih), dB = d5(pbv[0], pbv[1], pbv[2], pbv[3], ih);
+                const T adv = A[j] * dB + B[j] * (dA + e * dB);
+                dF[k] -= T(0.5) * (flux + adv);
+            }
+        }
+    }
+    const T th0 = T(g.theta0);
+    T divA = T(0), divB = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dF[c] -= th0 * dfield(g, v, 3, c, x, y, z);
+        divA += dfield(g, u, c, c, x, y, z);
+        divB += dfield(g, v, c, c, x, y, z);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dF[c] += dext(g, d, tix(c, j), j, x, y, z);
+    }
+    dF[2] += T(g.g_theta0) * B[4];
+    const T* pb = Bg<T>::pbar(g);
+    const T* dpb = Bg<T>::dpbar(g);
+    if (g.energy_test)
+        dF[3] -= T(g.kappa_cp) * divB;
+    else
+        dF[3] -= B[2] * dpb[z] + T(g.kappa) * ((pb[z] + A[3]) * divB + B[3] * divA + e * B[3] * divB);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dF[4] += dext(g, d, 6 + j, j, x, y, z);
+    dF[4] -= T(g.beta) * B[2];
+    const T tdt = T(g.two_dt);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[k * np + i] = tdt * B[k] - dF[k];
+}
+
+// frozen eddy viscosity on the ring-2 extended grid
+template <typename T>
+__global__ __launch_bounds__(256) void k3_frozen_nu(Geo g, const T* __restrict__ u, T* __restrict__ nu) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_point(g, i, x, y, z)) return;
+    T S[6], th[3];
+    strain3(g, u, x, y, z, S, th);
+    T n, k;
+    closure3(g, frob3(S, S), n, k);
+    nu[i] = n;
+}
+
+template <typename T>
+__device__ __forceinline__ void pc_k3(const Geo& g, T nu_pt, T& kmom, T& kth) {
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+        kmom = nu_pt;
+        kth = nu_pt * T(g.inv_pr);
+    } else if (g.closure == JFNK_CLOSURE_CONST_K) {
+        kmom = T(g.k_m);
+        kth = T(g.k_h);
+    } else {
+        kmom = T(0);
+        kth = T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T nuext(const Geo& g, const T* __restrict__ nu, int x, int y, int z) {
+    const long long ex = g.nx + 4, ey = g.ny + 4;
+    return nu[((long long)(z + 2) * ey + (y + 2)) * ex + (x + 2)];
+}
+
+// z0 = v / d (v = V_j / div written back); returns the thread's ||z||^2
+template <typename T>
+__global__ __launch_bounds__(256) void k3_pc_diag(Geo g, const T* __restrict__ nu, T* __restrict__ vj,
+                                                  const double* __restrict__ div, T* __restrict__ z, EpsArgs ea) {
+    __shared__ double red[4];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (i < g.npts) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zz = (int)(i / ((long long)g.nx * g.ny));
+        T km, kt;
+        pc_k3(g, nuext(g, nu, x, y, zz), km, kt);
+        const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
+        const T cD = T(65.0 / 72.0);
+        const T dm = T(g.two_dt) + cD * km * ih2, dt_ = T(g.two_dt) + cD * kt * ih2;
+        const T dd[5] = {dm, dm, dm, T(g.two_dt), dt_};
+        const double dv = div ? *div : 1.0;
+        const long long np = g.npts;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            T vv = vj[k * np + i];
+            if (div) {
+                vv = (T)((double)vv / dv);
+                vj[k * np + i] = vv;
+            }
+            const T zv = vv / dd[k];
+            z[k * np + i] = zv;
+            acc += (double)zv * (double)zv;
+        }
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
+}
+
+// one Jacobi sweep of the field-block preconditioner
+template <typename T>
+__global__ __launch_bounds__(256) void k3_pc_sweep(Geo g, const T* __restrict__ u, const T* __restrict__ nu,
+                                                   const T* __restrict__ r, const T* __restrict__ zin,
+                                                   T* __restrict__ zout, EpsArgs ea) {
+    __shared__ double red[4];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (i < g.npts) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+        const long long np = g.npts;
+        T km0, kt0;
+        pc_k3(g, nuext(g, nu, x, y, z), km0, kt0);
+        const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
+        const T cD = T(65.0 / 72.0);
+        const T a[3] = {u[i], u[np + i], u[2 * np + i]};
+        const int ox[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const T zc = zin[k * np + i];
+            T diff = T(0), cv = T(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int ex = j == 0, ey = j == 1, ez = j == 2;
+                const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
+                if (k != 3) {
+                    // D_j(K D_j z): fluxes at the four neighbours along j
+                    T fl[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int xq = x + ox[q] * ex, yq = y + ox[q] * ey, zq = z + ox[q] * ez;
+                        T kmq, ktq;
+                        pc_k3(g, nuext(g, nu, xq, yq, zq), kmq, ktq);
+                        fl[q] = (k == 4 ? ktq : kmq) * dfield(g, zin, k, j, xq, yq, zq);
+                    }
+                    diff += d5(fl[0], fl[1], fl[2], fl[3], ih);
+                }
+                if (g.convection) {
+                    T pa[4], pz[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int xq = x + ox[q] * ex, yq = y + ox[q] * ey, zq = z + ox[q] * ez;
+                        pa[q] = ld(g, u, j, xq, yq, zq);
+                        pz[q] = ld(g, zin, k, xq, yq, zq);
+                    }
+                    cv += T(0.5) * (d5(pa[0] * pz[0], pa[1] * pz[1], pa[2] * pz[2], pa[3] * pz[3], ih) +
+                                    a[j] * d5(pz[0], pz[1], pz[2], pz[3], ih));
+                }
+            }
+            const T kk = k == 3 ? T(0) : (k == 4 ? kt0 : km0);
+            const T Pz = T(g.two_dt) * zc + (cv - diff);
+            const T dd = T(g.two_dt) + cD * kk * ih2;
+            const T zn = zc + (r[k * np + i] - Pz) / dd;
+            zout[k * np + i] = zn;
+            acc += (double)zn * (double)zn;
+        }
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
+}
+
+inline int blocks(long long n) { return (int)((n + 255) / 256); }
+inline long long next3(const Geo& g) { return (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, T* dbuf, hipStream_t s) {
+    hipLaunchKernelGGL((k3_derived<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, dbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k3_apply_F<T>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, (const T*)dbuf, f, out, what);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k3_jv_derived<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, v, eps, eps_dev, dbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k3_jv<T>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, v, eps, eps_dev, (const T*)dbuf, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s) {
+    hipLaunchKernelGGL((k3_frozen_nu<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, nu);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
+                           hipStream_t s) {
+    const int nb = blocks(g.npts);
+    hipLaunchKernelGGL((k3_pc_diag<T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ea.partials) return e;
+    return launch_eps_finish(nb, ea, s);
+}
+
+template <typename T>
+hipError_t launch3_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
+                            const EpsArgs& ea, hipStream_t s) {
+    const int nb = blocks(g.npts);
+    hipLaunchKernelGGL((k3_pc_sweep<T>), dim3(nb), dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ea.partials) return e;
+    return launch_eps_finish(nb, ea, s);
+}
+
+#define JFNK_INST3(T)                                                                                          \
+    template hipError_t launch3_apply_F<T>(const Geo&, const T*, const T*, T*, int, T*, hipStream_t);          \
+    template hipError_t launch3_jv<T>(const Geo&, const T*, const T*, double, const double*, T*, T*,            \
+                                      hipStream_t);                                                            \
+    template hipError_t launch3_frozen_nu<T>(const Geo&, const T*, T*, hipStream_t);                           \
+    template hipError_t launch3_pc_diag<T>(const Geo&, const T*, T*, const double*, T*, const EpsArgs&,        \
+                                           hipStream_t);                                                       \
+    template hipError_t launch3_pc_sweep<T>(const Geo&, const T*, const T*, const T*, const T*, T*,             \
+                                            const EpsArgs&, hipStream_t);
+JFNK_INST3(double)
+JFNK_INST3(float)
+#undef JFNK_INST3
+
+}  // namespace jfnk
