@@ -9,7 +9,8 @@ J^{-1} cheaply; the network form follows the design of this project:
     z = (dt/2) r + s N(r / s),       s = RMS of r over all fields and points
                                       (s = 1 for r = 0)
     N = conv(n_f -> 16) - GELU - conv(16 -> 16) - GELU - conv(16 -> 16) - GELU
-        - conv(16 -> n_f),   3 x 3 kernels, zero padding ("same"), with bias,
+        - conv(16 -> n_f),   3 x 3 kernels with dilation d_l (taps at offsets
+        d_l * (-1, 0, 1)), zero padding ("same"), with bias,
     GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
 
 Loss of a pair (r, du): ||z(r) - du||^2 / ||du||^2, averaged over a batch.
@@ -68,38 +69,43 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
-def conv(x, W, b):
-    """out[co, z, x] = b[co] + sum_ci sum_taps W[co, ci, kz, kx] x[ci, z+kz-1, x+kx-1],
+def _pad(x, d):
+    cin, Z, X = x.shape
+    xp = np.zeros((cin, Z + 2 * d, X + 2 * d))
+    xp[:, d:d + Z, d:d + X] = x
+    return xp
+
+
+def conv(x, W, b, d=1):
+    """out[co, z, x] = b[co] + sum_ci sum_taps W[co, ci, kz, kx] x[ci, z+d(kz-1), x+d(kx-1)],
     zero outside the grid.  x: (C_in, Z, X)."""
     cin, Z, X = x.shape
-    xp = np.zeros((cin, Z + 2, X + 2))
-    xp[:, 1:-1, 1:-1] = x
+    xp = _pad(x, d)
     out = np.zeros((W.shape[0], Z, X)) + b[:, None, None]
     for kz in range(3):
         for kx in range(3):
-            patch = xp[:, kz:kz + Z, kx:kx + X]
+            patch = xp[:, kz * d:kz * d + Z, kx * d:kx * d + X]
             out += np.einsum("oc,czx->ozx", W[:, :, kz, kx], patch)
     return out
 
 
-def conv_grad_input(g, W, shape_in):
+def conv_grad_input(g, W, shape_in, d=1):
     """d/dx of sum(g * conv(x)) for zero padding (the transposed convolution)."""
     cin, Z, X = shape_in
-    gx = np.zeros((cin, Z + 2, X + 2))
+    gx = np.zeros((cin, Z + 2 * d, X + 2 * d))
     for kz in range(3):
         for kx in range(3):
-            gx[:, kz:kz + Z, kx:kx + X] += np.einsum("oc,ozx->czx", W[:, :, kz, kx], g)
-    return gx[:, 1:-1, 1:-1]
+            gx[:, kz * d:kz * d + Z, kx * d:kx * d + X] += np.einsum("oc,ozx->czx", W[:, :, kz, kx], g)
+    return gx[:, d:d + Z, d:d + X]
 
 
-def conv_grad_weight(g, x):
+def conv_grad_weight(g, x, d=1):
     cin, Z, X = x.shape
-    xp = np.zeros((cin, Z + 2, X + 2))
-    xp[:, 1:-1, 1:-1] = x
+    xp = _pad(x, d)
     gW = np.zeros((g.shape[0], cin, 3, 3))
     for kz in range(3):
         for kx in range(3):
-            gW[:, :, kz, kx] = np.einsum("ozx,czx->oc", g, xp[:, kz:kz + Z, kx:kx + X])
+            gW[:, :, kz, kx] = np.einsum("ozx,czx->oc", g, xp[:, kz * d:kz * d + Z, kx * d:kx * d + X])
     return gW, g.sum(axis=(1, 2))
 
 
@@ -116,7 +122,7 @@ def _grid(r):
     return r[:, :, 0, :] if r.ndim == 4 else r
 
 
-def forward(theta, r, dt, keep=False):
+def forward(theta, r, dt, keep=False, dils=(1, 1, 1, 1)):
     """z = (dt/2) r + s * N(r/s) for one 2D state-shaped r."""
     img = _grid(r)
     nf = img.shape[0]
@@ -125,7 +131,7 @@ def forward(theta, r, dt, keep=False):
     a = img / s[:, None, None]
     acts, pres = [a], []
     for l, (W, b) in enumerate(layers):
-        h = conv(a, W, b)
+        h = conv(a, W, b, dils[l])
         pres.append(h)
         a = gelu(h) if l < NLAYER - 1 else h
         acts.append(a)
@@ -136,7 +142,7 @@ def forward(theta, r, dt, keep=False):
     return z
 
 
-def loss_and_grad(theta, R, DU, dt):
+def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1)):
     """Mean over the batch of ||z(r) - du||^2 / ||du||^2 and its gradient."""
     nf = _grid(R[0]).shape[0]
     layers = unpack(theta, nf)
@@ -144,7 +150,7 @@ def loss_and_grad(theta, R, DU, dt):
     grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     B = len(R)
     for r, du in zip(R, DU):
-        z, (s, acts, pres) = forward(theta, r, dt, keep=True)
+        z, (s, acts, pres) = forward(theta, r, dt, keep=True, dils=dils)
         d = _grid(z) - _grid(du)
         nd = float(np.sum(_grid(du) ** 2))
         total += float(np.sum(d * d)) / nd / B
@@ -153,10 +159,10 @@ def loss_and_grad(theta, R, DU, dt):
             if l < NLAYER - 1:
                 g = g * gelu_grad(pres[l])
             W, _ = layers[l]
-            gW, gb = conv_grad_weight(g, acts[l])
+            gW, gb = conv_grad_weight(g, acts[l], dils[l])
             grads[l] = (grads[l][0] + gW, grads[l][1] + gb)
             if l > 0:
-                g = conv_grad_input(g, W, acts[l].shape)
+                g = conv_grad_input(g, W, acts[l].shape, dils[l])
     return total, pack(grads)
 
 

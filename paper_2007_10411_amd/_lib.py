@@ -92,7 +92,7 @@ def load():
     L.jfnk_timing_enable.argtypes = [vp, C.c_int32]
     L.jfnk_timing_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
-    L.jfnk_net_init.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.jfnk_net_init.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     L.jfnk_net_set_params.argtypes = [vp, vp, C.c_int64]
     L.jfnk_net_get_params.argtypes = [vp, vp, C.c_int64]
     L.jfnk_net_apply.argtypes = [vp, C.c_int32, vp, vp]

@@ -935,12 +935,20 @@ int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launch
 }
 
 
-int jfnk_net_init(jfnk_ctx* c, int64_t* n_params) {
+int jfnk_net_init(jfnk_ctx* c, const int32_t* dilations, int64_t* n_params) {
     if (!c || c->prob.dim != 2) {
         set_error("the learned preconditioner is available for 2D problems");
         return JFNK_ERR_ARG;
     }
     NetBuffers& nb = c->net;
+    for (int l = 0; l < 4; ++l) {
+        const int d = dilations ? dilations[l] : 1;
+        if (d < 1 || d > 8) {
+            set_error("dilations must be in [1, 8]");
+            return JFNK_ERR_ARG;
+        }
+        nb.dil[l] = d;
+    }
     const int np = net_param_count(c->nf);
     if (n_params) *n_params = np;
     if (nb.theta) return JFNK_OK;

@@ -120,6 +120,7 @@ struct NetBuffers {
     unsigned short* abf = nullptr;   // 2 x 16 x npts bf16 activations
     int nparam = 0;
     int adam_t = 0;
+    int dil[4] = {1, 1, 1, 1};       // per-layer dilation of the 3x3 kernels
     bool ready = false;              // parameters set
 };
 

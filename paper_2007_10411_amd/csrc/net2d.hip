@@ -2,6 +2,7 @@
 // convolutional network applied as
 //     z = (dt/2) r + s N(r / s),     s = RMS of r over all fields (1 if r = 0),
 //     N = conv(nf->16) GELU conv(16->16) GELU conv(16->16) GELU conv(16->nf),
+// 3x3 kernels with a dilation d_l per layer (taps at d_l * (-1, 0, 1), d_l <= 8),
 // zero padding, exact erf GELU.  Inference runs in BF16 on MFMA
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one 3x3 tap per instruction);
 // training (forward, backward, Adam on FP32 master weights) runs in FP32.
@@ -22,7 +23,8 @@ namespace {
 
 constexpr int kHid = 16;
 constexpr int kTX = 64, kTZ = 4;            // output tile per 256-thread block
-constexpr int kSX = kTX + 2, kSZ = kTZ + 2; // input tile with a halo of 1
+constexpr int kMaxDil = 8;
+constexpr int kSX = kTX + 2 * kMaxDil, kSZ = kTZ + 2 * kMaxDil;   // input tile with the largest halo
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -81,36 +83,33 @@ __global__ __launch_bounds__(256) void k_conv_f32(int nx, int nz, const float* _
                                                   float* __restrict__ pre, float* __restrict__ post,
                                                   const float* __restrict__ r, const float* __restrict__ s,
                                                   float half_dt, float* __restrict__ z,
-                                                  const float* __restrict__ gmul) {
-    __shared__ float sin_[kHid][kSZ][kSX];
+                                                  const float* __restrict__ gmul, int dil) {
     __shared__ float sw[kHid * kHid * 9];
     __shared__ float sb[kHid];
     const long long np = (long long)nx * nz;
-    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
     for (int i = threadIdx.x; i < cout * cin * 9; i += 256) sw[i] = W[i];
     for (int i = threadIdx.x; i < cout; i += 256) sb[i] = b ? b[i] : 0.0f;
-    for (int idx = threadIdx.x; idx < cin * kSZ * kSX; idx += 256) {
-        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
-        const int lz = rem / kSX, lx = rem - lz * kSX;
-        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
-        float v = 0.0f;
-        if (gx >= 0 && gx < nx && gz >= 0 && gz < nz) {
-            const long long o = (long long)c * np + (long long)gz * nx + gx;
-            v = (MODE == L_FIRST) ? r[o] / s[c] : in[o];
-        }
-        sin_[c][lz][lx] = v;
-    }
     __syncthreads();
     const int lx = threadIdx.x & 63, lz = threadIdx.x >> 6;
-    const int gx = x0 + lx, gz = z0 + lz;
+    const int gx = blockIdx.x * kTX + lx, gz = blockIdx.y * kTZ + lz;
     if (gx >= nx || gz >= nz) return;
     float acc[kHid];
 #pragma unroll
     for (int co = 0; co < kHid; ++co) acc[co] = co < cout ? sb[co] : 0.0f;
     for (int ci = 0; ci < cin; ++ci) {
+        // inputs at the 9 dilated taps, read through the caches (zero outside the grid)
         float xv[9];
+        const float inv_s = (MODE == L_FIRST) ? 1.0f / s[ci] : 1.0f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) xv[t] = sin_[ci][lz + t / 3][lx + t % 3];
+        for (int t = 0; t < 9; ++t) {
+            const int xx = gx + dil * (t % 3 - 1), zz = gz + dil * (t / 3 - 1);
+            float v = 0.0f;
+            if (xx >= 0 && xx < nx && zz >= 0 && zz < nz) {
+                const long long o = (long long)ci * np + (long long)zz * nx + xx;
+                v = (MODE == L_FIRST) ? r[o] * inv_s : in[o];
+            }
+            xv[t] = v;
+        }
 #pragma unroll
         for (int co = 0; co < kHid; ++co) {
             if (co < cout) {
@@ -152,14 +151,15 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
                                                    const float* __restrict__ b, int cout,
                                                    unsigned short* __restrict__ post, const float* __restrict__ r,
                                                    const float* __restrict__ s, float half_dt,
-                                                   float* __restrict__ z) {
+                                                   float* __restrict__ z, int dil) {
     __shared__ unsigned short sin_[kSZ][kSX][kHid];   // pixel-major, channel-innermost
     const long long np = (long long)nx * nz;
     const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
-    for (int idx = threadIdx.x; idx < kHid * kSZ * kSX; idx += 256) {
-        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
-        const int lz = rem / kSX, lx = rem - lz * kSX;
-        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
+    const int SZ = kTZ + 2 * dil, SX = kTX + 2 * dil;   // staged region for this dilation
+    for (int idx = threadIdx.x; idx < kHid * SZ * SX; idx += 256) {
+        const int c = idx / (SZ * SX), rem = idx - c * (SZ * SX);
+        const int lz = rem / SX, lx = rem - lz * SX;
+        const int gx = x0 + lx - dil, gz = z0 + lz - dil;
         unsigned short v = 0;
         if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz) {
             const long long o = (long long)c * np + (long long)gz * nx + gx;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
         const int px = st * 16 + col;                   // A row: pixel of this lane
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int dz = t / 3, dx = t % 3;
+            const int dz = (t / 3) * dil, dx = (t % 3) * dil;
             const unsigned short* ap = &sin_[wv + dz][px + dx][4 * kg];
             const bf16x4_t a = bf16x4_t{(short)ap[0], (short)ap[1], (short)ap[2], (short)ap[3]};
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
@@ -229,42 +229,49 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ z, 
     if (threadIdx.x == 0) partials[blockIdx.x] = t / nd * inv_batch;
 }
 
-// dW[co][ci][t] and db[co] partial sums over one 64 x 4 tile of pixels
+// dW[co][ci][t] and db[co] partial sums over one 64 x 4 tile of pixels; the
+// input is staged one channel at a time with the halo of the layer's dilation
 __global__ __launch_bounds__(256) void k_conv_wgrad(int nx, int nz, const float* __restrict__ g, int cout,
                                                     const float* __restrict__ a, int cin,
-                                                    float* __restrict__ partials, int nw) {
+                                                    float* __restrict__ partials, int nw, int dil) {
     __shared__ float sg[kHid][kTZ][kTX];
-    __shared__ float sa[kHid][kSZ][kSX];
+    __shared__ float sa[kSZ][kSX];
     const long long np = (long long)nx * nz;
     const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    float* out = partials + blk * (nw + cout);
     for (int idx = threadIdx.x; idx < cout * kTZ * kTX; idx += 256) {
         const int c = idx / (kTZ * kTX), rem = idx - c * (kTZ * kTX);
         const int lz = rem / kTX, lx = rem - lz * kTX;
         const int gx = x0 + lx, gz = z0 + lz;
         sg[c][lz][lx] = (gx < nx && gz < nz) ? g[(long long)c * np + (long long)gz * nx + gx] : 0.0f;
     }
-    for (int idx = threadIdx.x; idx < cin * kSZ * kSX; idx += 256) {
-        const int c = idx / (kSZ * kSX), rem = idx - c * (kSZ * kSX);
-        const int lz = rem / kSX, lx = rem - lz * kSX;
-        const int gx = x0 + lx - 1, gz = z0 + lz - 1;
-        sa[c][lz][lx] = (gx >= 0 && gx < nx && gz >= 0 && gz < nz) ? a[(long long)c * np + (long long)gz * nx + gx] : 0.0f;
-    }
     __syncthreads();
-    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-    for (int k = threadIdx.x; k < nw + cout; k += 256) {
+    if (threadIdx.x < cout) {                        // bias gradient
+        const int co = threadIdx.x;
         float acc = 0.0f;
-        if (k < nw) {
-            const int co = k / (cin * 9), rem = k - co * (cin * 9);
-            const int ci = rem / 9, t = rem - ci * 9;
-            const int dz = t / 3, dx = t % 3;
-            for (int lz = 0; lz < kTZ; ++lz)
-                for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx] * sa[ci][lz + dz][lx + dx];
-        } else {
-            const int co = k - nw;
-            for (int lz = 0; lz < kTZ; ++lz)
-                for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx];
+        for (int lz = 0; lz < kTZ; ++lz)
+            for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx];
+        out[nw + co] = acc;
+    }
+    const int SZ = kTZ + 2 * dil, SX = kTX + 2 * dil;
+    for (int ci = 0; ci < cin; ++ci) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < SZ * SX; idx += 256) {
+            const int lz = idx / SX, lx = idx - lz * SX;
+            const int gx = x0 + lx - dil, gz = z0 + lz - dil;
+            sa[lz][lx] = (gx >= 0 && gx < nx && gz >= 0 && gz < nz) ? a[(long long)ci * np + (long long)gz * nx + gx]
+                                                                     : 0.0f;
         }
-        partials[blk * (nw + cout) + k] = acc;
+        __syncthreads();
+        for (int k = threadIdx.x; k < cout * 9; k += 256) {
+            const int co = k / 9, t = k - co * 9;
+            const int dz = (t / 3) * dil, dx = (t % 3) * dil;
+            float acc = 0.0f;
+            for (int lz = 0; lz < kTZ; ++lz)
+                for (int lx = 0; lx < kTX; ++lx) acc += sg[co][lz][lx] * sa[lz + dz][lx + dx];
+            out[(co * cin + ci) * 9 + t] = acc;
+        }
     }
 }
 
@@ -381,32 +388,32 @@ hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt
         unsigned short* a1 = nb.abf + kHid * np;
         hipLaunchKernelGGL((k_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)nullptr,
                            L[0].cin, nb.wbf + 0 * 9 * kHid * kHid, nb.theta + L[0].boff, L[0].cout, a0, r, nb.s,
-                           half_dt, (float*)nullptr);
+                           half_dt, (float*)nullptr, nb.dil[0]);
         hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[1].cin,
                            nb.wbf + 1 * 9 * kHid * kHid, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
-                           (float*)nullptr);
+                           (float*)nullptr, nb.dil[1]);
         hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a1, L[2].cin,
                            nb.wbf + 2 * 9 * kHid * kHid, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
-                           (float*)nullptr);
+                           (float*)nullptr, nb.dil[2]);
         hipLaunchKernelGGL((k_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[3].cin,
                            nb.wbf + 3 * 9 * kHid * kHid, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
-                           nb.s, half_dt, z);
+                           nb.s, half_dt, z, nb.dil[3]);
         return hipGetLastError();
     }
     float* a0 = nb.act;                 // reuse the training buffers
     float* a1 = nb.act + kHid * np;
     hipLaunchKernelGGL((k_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const float*)nullptr, L[0].cin,
                        nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, (float*)nullptr, a0, r, nb.s, half_dt,
-                       (float*)nullptr, (const float*)nullptr);
+                       (float*)nullptr, (const float*)nullptr, nb.dil[0]);
     hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)a0, L[1].cin,
                        nb.theta + L[1].woff, nb.theta + L[1].boff, L[1].cout, (float*)nullptr, a1, r, nb.s, half_dt,
-                       (float*)nullptr, (const float*)nullptr);
+                       (float*)nullptr, (const float*)nullptr, nb.dil[1]);
     hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)a1, L[2].cin,
                        nb.theta + L[2].woff, nb.theta + L[2].boff, L[2].cout, (float*)nullptr, a0, r, nb.s, half_dt,
-                       (float*)nullptr, (const float*)nullptr);
+                       (float*)nullptr, (const float*)nullptr, nb.dil[2]);
     hipLaunchKernelGGL((k_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const float*)a0, L[3].cin,
                        nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, (float*)nullptr, (float*)nullptr, r,
-                       nb.s, half_dt, z, (const float*)nullptr);
+                       nb.s, half_dt, z, (const float*)nullptr, nb.dil[3]);
     return hipGetLastError();
 }
 
@@ -429,14 +436,14 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
     }
     hipLaunchKernelGGL((k_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const float*)nullptr, L[0].cin,
                        nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, pre[0], act[0], r, nb.s, half_dt,
-                       (float*)nullptr, (const float*)nullptr);
+                       (float*)nullptr, (const float*)nullptr, nb.dil[0]);
     for (int l = 1; l < 3; ++l)
         hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)act[l - 1], L[l].cin,
                            nb.theta + L[l].woff, nb.theta + L[l].boff, L[l].cout, pre[l], act[l], r, nb.s, half_dt,
-                           (float*)nullptr, (const float*)nullptr);
+                           (float*)nullptr, (const float*)nullptr, nb.dil[l]);
     hipLaunchKernelGGL((k_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const float*)act[2], L[3].cin,
                        nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, pre[3], (float*)nullptr, r, nb.s,
-                       half_dt, nb.z, (const float*)nullptr);
+                       half_dt, nb.z, (const float*)nullptr, nb.dil[3]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // ||du||^2, then g = dL/d(network output) and the loss
     {
@@ -466,7 +473,7 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
         }
         const int nw = L[l].cout * L[l].cin * 9;
         hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout, a_in, L[l].cin,
-                           nb.wpart, nw);
+                           nb.wpart, nw, nb.dil[l]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_wgrad_finish, dim3((nw + L[l].cout + 255) / 256), dim3(256), 0, st,
                            (const float*)nb.wpart, nt, nw + L[l].cout, nb.grad + L[l].woff, first_pair ? 0 : 1);
@@ -475,7 +482,7 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
             // g_in = conv(g, W transposed and flipped) * gelu'(h_{l-1})
             hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout,
                                nb.wt + L[l].woff, (const float*)nullptr, L[l].cin, (float*)nullptr, gnext, r, nb.s,
-                               half_dt, (float*)nullptr, (const float*)pre[l - 1]);
+                               half_dt, (float*)nullptr, (const float*)pre[l - 1], nb.dil[l]);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             std::swap(g, gnext);
         }

@@ -172,10 +172,12 @@ class Context:
         return out.value
 
     # -- learned preconditioner -----------------------------------------------
-    def net_init(self):
+    def net_init(self, dilations=(1, 1, 1, 1)):
         n = C.c_int64()
-        L.check(self.lib.jfnk_net_init(self.h, C.byref(n)), "jfnk_net_init", soft_ok=False)
+        d = (C.c_int32 * 4)(*[int(x) for x in dilations])
+        L.check(self.lib.jfnk_net_init(self.h, d, C.byref(n)), "jfnk_net_init", soft_ok=False)
         self.n_params = n.value
+        self.dilations = tuple(int(x) for x in dilations)
         return n.value
 
     def net_set_params(self, theta):

@@ -21,6 +21,10 @@ import numpy as np
 
 from . import inputs as I
 
+# Per-layer dilations of the 3 x 3 kernels: 1, 2, 4, 8 give every output a dense
+# 31 x 31 receptive field with the parameters and flops of four plain layers.
+DILATIONS = (1, 2, 4, 8)
+
 
 def collect_pairs(ctx, u0, steps, cap, eta=1e-3, pc="physics", inner="f32", krylov=True, **kw):
     """Advance ``steps`` implicit steps from u0 (FP64 device tensor), recording
@@ -73,12 +77,13 @@ def field_rms(DU, nf):
     return DU.reshape(DU.shape[0], nf, -1).pow(2).mean(dim=(0, 2)).sqrt().cpu().numpy()
 
 
-def train_mixed(ctx, R, DU, u, iters=2000, lr=2e-3, batch=8, seed=0, theta0=None, noise_every=2):
+def train_mixed(ctx, R, DU, u, iters=2000, lr=2e-3, batch=8, seed=0, theta0=None, noise_every=2,
+                dilations=DILATIONS):
     """The recipe used by the benchmark and tests: noise pairs at the state u on
     every step but one in ``noise_every``, recorded Krylov pairs on the others."""
     import torch
     nf = ctx.prob.nf
-    ctx.net_init()
+    ctx.net_init(dilations)
     theta = I.net_init_params(nf, seed=seed) if theta0 is None else np.asarray(theta0)
     ctx.net_set_params(theta.astype(np.float32))
     noise = NoisePairs(ctx, u, field_rms(DU, nf), seed=seed + 1)
@@ -96,11 +101,11 @@ def train_mixed(ctx, R, DU, u, iters=2000, lr=2e-3, batch=8, seed=0, theta0=None
     return ctx.net_get_params(), losses
 
 
-def train(ctx, R, DU, iters, lr=2e-3, batch=4, seed=0, theta0=None, lr_decay=True):
+def train(ctx, R, DU, iters, lr=2e-3, batch=4, seed=0, theta0=None, lr_decay=True, dilations=DILATIONS):
     """Adam on mini-batches of recorded pairs only; returns (theta, per-step losses)."""
     import torch
     nf = ctx.prob.nf
-    ctx.net_init()
+    ctx.net_init(dilations)
     theta = I.net_init_params(nf, seed=seed) if theta0 is None else np.asarray(theta0)
     ctx.net_set_params(theta.astype(np.float32))
     rng = np.random.Generator(np.random.PCG64(seed + 17))

@@ -13,10 +13,10 @@ from gpu_util import dev, host
 pytestmark = pytest.mark.gpu
 
 
-def _ctx(prob, max_m=30):
+def _ctx(prob, max_m=30, dils=(1, 1, 1, 1)):
     from paper_2007_10411_amd.jfnk import Context
     c = Context(prob, max_m=max_m)
-    c.net_init()
+    c.net_init(dils)
     return c
 
 
@@ -32,14 +32,15 @@ def _r(prob, seed):
     return r.astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("nx,nz", [(100, 40), (64, 4), (200, 9)])
-def test_net_forward_f32_and_bf16(nx, nz):
-    prob = I.thermal_stable_2d(nx, max(nz, 8)) if nz >= 8 else I.thermal_stable_2d(nx, 8)
-    c = _ctx(prob)
+@pytest.mark.parametrize("dils", [(1, 1, 1, 1), (1, 2, 4, 8), (3, 8, 1, 5)])
+@pytest.mark.parametrize("nx,nz", [(100, 40), (64, 8), (200, 9)])
+def test_net_forward_f32_and_bf16(nx, nz, dils):
+    prob = I.thermal_stable_2d(nx, nz)
+    c = _ctx(prob, dils=dils)
     th = _theta(prob.nf)
     c.net_set_params(th)
     r = _r(prob, 2)
-    ref = N.forward(th, r, prob.dt)
+    ref = N.forward(th, r, prob.dt, dils=dils)
     netpart = ref - 0.5 * prob.dt * r
     z = dev(np.zeros(prob.shape), "f32")
     c.net_apply(dev(r, "f32"), z, bf16=False)
@@ -55,14 +56,15 @@ def test_net_forward_f32_and_bf16(nx, nz):
         assert e < 3e-2, ("bf16", k, e)
 
 
-def test_net_loss_gradient_matches_oracle():
+@pytest.mark.parametrize("dils", [(1, 1, 1, 1), (1, 2, 4, 8), (8, 3, 1, 2)])
+def test_net_loss_gradient_matches_oracle(dils):
     prob = I.thermal_stable_2d(70, 20)
-    c = _ctx(prob)
+    c = _ctx(prob, dils=dils)
     th = _theta(prob.nf, seed=3)
     c.net_set_params(th)
     R = [_r(prob, 4), _r(prob, 5)]
     DU = [_r(prob, 6), _r(prob, 7)]
-    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt, dils=dils)
     Rd = dev(np.stack(R), "f32")
     Dd = dev(np.stack(DU), "f32")
     lg, gg = c.net_loss_grad(Rd, Dd)
@@ -78,13 +80,14 @@ def test_net_loss_gradient_matches_oracle():
 
 
 def test_net_adam_step_matches_oracle():
+    dils = (1, 2, 4, 8)
     prob = I.thermal_stable_2d(64, 16)
-    c = _ctx(prob)
+    c = _ctx(prob, dils=dils)
     th = _theta(prob.nf, seed=8)
     c.net_set_params(th)
     R = [_r(prob, 9)]
     DU = [_r(prob, 10)]
-    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt, dils=dils)
     lr = 1e-3
     ref, _, _ = N.adam_step(th, go, np.zeros_like(th), np.zeros_like(th), 1, lr)
     loss = c.net_train_step(dev(R[0], "f32"), dev(DU[0], "f32"), lr)
@@ -95,6 +98,15 @@ def test_net_adam_step_matches_oracle():
     big = np.abs(go) > 1e-3 * np.abs(go).max()
     assert np.abs(dg[big] - dr[big]).max() <= 1e-3 * lr
     assert np.abs(dg).max() <= 1.0001 * lr
+
+
+def test_net_rejects_bad_dilation():
+    from paper_2007_10411_amd._lib import JfnkError
+    from paper_2007_10411_amd.jfnk import Context
+    c = Context(I.thermal_stable_2d(64, 8))
+    for bad in [(0, 1, 1, 1), (1, 9, 1, 1)]:
+        with pytest.raises(JfnkError):
+            c.net_init(bad)
 
 
 def test_learned_pc_in_fgmres_converges_and_falls_back():

@@ -21,15 +21,20 @@ def test_param_layout_matches_input_generator():
     assert [W.shape for W, _ in layers] == [s[0] for s in I.net_layer_shapes(nf)]
 
 
-def test_conv_equals_scipy_correlate_with_zero_padding():
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_conv_equals_scipy_correlate_with_zero_padding(d):
+    """A dilated 3x3 kernel is the (2d+1) x (2d+1) kernel with zeros between taps."""
     rng = np.random.Generator(np.random.PCG64(1))
-    x = rng.normal(size=(3, 7, 9))
+    x = rng.normal(size=(3, 9, 11))
     W = rng.normal(size=(5, 3, 3, 3))
     b = rng.normal(size=5)
-    out = N.conv(x, W, b)
+    out = N.conv(x, W, b, d)
     for co in range(5):
-        ref = b[co] + sum(correlate2d(x[ci], W[co, ci], mode="same", boundary="fill", fillvalue=0.0)
-                          for ci in range(3))
+        ref = b[co]
+        for ci in range(3):
+            Kd = np.zeros((2 * d + 1, 2 * d + 1))
+            Kd[::d, ::d] = W[co, ci]
+            ref = ref + correlate2d(x[ci], Kd, mode="same", boundary="fill", fillvalue=0.0)
         assert np.allclose(out[co], ref, rtol=1e-13, atol=1e-13)
 
 
@@ -44,18 +49,19 @@ def test_gelu_definition_and_values():
     assert np.allclose(N.gelu_grad(xs), fd, atol=1e-8)
 
 
-def test_transposed_convolution_is_the_adjoint():
+@pytest.mark.parametrize("d", [1, 4])
+def test_transposed_convolution_is_the_adjoint(d):
     rng = np.random.Generator(np.random.PCG64(2))
-    x = rng.normal(size=(4, 6, 8))
+    x = rng.normal(size=(4, 6, 11))
     W = rng.normal(size=(16, 4, 3, 3))
-    g = rng.normal(size=(16, 6, 8))
-    lhs = float(np.sum(g * (N.conv(x, W, np.zeros(16)))))
-    rhs = float(np.sum(N.conv_grad_input(g, W, x.shape) * x))
+    g = rng.normal(size=(16, 6, 11))
+    lhs = float(np.sum(g * (N.conv(x, W, np.zeros(16), d))))
+    rhs = float(np.sum(N.conv_grad_input(g, W, x.shape, d) * x))
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
-    gW, gb = N.conv_grad_weight(g, x)
+    gW, gb = N.conv_grad_weight(g, x, d)
     # <g, conv_W(x)> is linear in W: its gradient is gW
     dW = rng.normal(size=W.shape)
-    assert abs(float(np.sum(g * N.conv(x, dW, np.zeros(16)))) - float(np.sum(gW * dW))) <= 1e-12 * abs(lhs)
+    assert abs(float(np.sum(g * N.conv(x, dW, np.zeros(16), d))) - float(np.sum(gW * dW))) <= 1e-12 * abs(lhs)
 
 
 def _pairs(nf=4, nz=5, nx=6, B=2, seed=4):
@@ -65,12 +71,13 @@ def _pairs(nf=4, nz=5, nx=6, B=2, seed=4):
     return R, DU
 
 
-def test_loss_gradient_matches_central_differences():
+@pytest.mark.parametrize("dils", [(1, 1, 1, 1), (1, 2, 3, 1)])
+def test_loss_gradient_matches_central_differences(dils):
     nf, dt = 4, 2.0
     th = I.net_init_params(nf, seed=5, out_scale=1.0)
     th = th + np.random.Generator(np.random.PCG64(6)).normal(scale=0.05, size=th.size)   # nonzero biases
     R, DU = _pairs()
-    loss, g = N.loss_and_grad(th, R, DU, dt)
+    loss, g = N.loss_and_grad(th, R, DU, dt, dils)
     rng = np.random.Generator(np.random.PCG64(7))
     idx = rng.choice(th.size, size=60, replace=False)
     for k in idx:
@@ -78,7 +85,7 @@ def test_loss_gradient_matches_central_differences():
         tp, tm = th.copy(), th.copy()
         tp[k] += h
         tm[k] -= h
-        fd = (N.loss_and_grad(tp, R, DU, dt)[0] - N.loss_and_grad(tm, R, DU, dt)[0]) / (2 * h)
+        fd = (N.loss_and_grad(tp, R, DU, dt, dils)[0] - N.loss_and_grad(tm, R, DU, dt, dils)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(abs(g).max(), 1e-12) + 1e-7 * abs(g[k]), (k, fd, g[k])
 
 
