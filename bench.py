@@ -6,26 +6,33 @@ step = one trapezoidal implicit step solved by inexact Newton (Eisenstat-Walker
 forcing) to a relative residual of 1e-8, FGMRES(30).
 
 Legs, all from the same state after the warm-up steps:
-  learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton
-            (the network is trained first on pairs the solver generates on this
-            workload; training time is reported, not timed with the steps)
-  mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton
+  mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton   (timed leg)
   plain     FP64 everywhere, physics-based preconditioner
+  learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
+            the network is trained first on pairs the solver generates on this
+            workload (training time reported, not timed with the steps)
+A second learned comparison runs on the same thermal at 256 x 128, where the
+acoustic CFL number is a quarter of the full grid's.
 
-Printed JSON line (the timed leg is `learned`, or `mixed` with --no-learned):
-  value          whole-job Jv throughput: grid points x Jv evaluations during the
-                 timed steps / wall time of those steps [Gpoint-residuals/s]
+Printed JSON line:
+  value          whole-job Jv throughput of the timed leg: grid points x Jv
+                 evaluations / wall time of the timed steps [Gpoint-residuals/s]
   ms_per_step    wall time per implicit step of the timed leg
-  roofline       dominant kernel class of the timed leg (algorithmic bytes over
-                 summed HIP-event time) against 8 TB/s HBM; roofline_jv and
-                 roofline_net for the Jv kernel and the network (vs 2.5 PFLOP/s BF16)
+  roofline       the dominant kernel class of the timed leg (algorithmic bytes over
+                 the summed HIP-event time of its launches) against 8 TB/s HBM;
+                 roofline_jv for the Jv kernel, roofline_net for the network
   cpu_baseline   the FP64 oracle on a bounded sample of the same workload
+
+--copy-probe GIB runs only a device-to-device copy of GIB GiB (the calibration
+kernel for the hardware byte counters) and prints its size and time.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,12 +50,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--legs", default="mixed,plain,learned")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
+    ap.add_argument("--copy-probe", type=float, default=0.0)
     return ap.parse_args()
 
 
@@ -70,18 +80,29 @@ def run_steps(ctx, u, k, torch, **opts):
     return infos
 
 
-def timed_leg(ctx, u0, k, torch, L, **opts):
+def timed_leg(ctx, u0, k, torch, L, classes, **opts):
+    """k steps from u0; HIP events record the launches of the given classes."""
     u = u0.clone()
+    mask = 0
+    for c in classes.values():
+        mask |= 1 << c
     torch.cuda.synchronize()
-    ctx.timing(True)
+    ctx.timing(mask)
     t0 = time.perf_counter()
     infos = run_steps(ctx, u, k, torch, **opts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    cls = {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI, "residual": L.KC_RESIDUAL, "net": L.KC_NET}
-    tm = {name: ctx.timing_read(c) for name, c in cls.items()}    # (ms, launches, bytes or flops)
-    ctx.timing(False)
+    tm = {name: ctx.timing_read(c) for name, c in classes.items()}    # (ms, launches, bytes or flops)
+    ctx.timing(0)
     return {"wall": wall, "infos": infos, "tm": tm, "u": u}
+
+
+def per_step(leg):
+    k = len(leg["infos"])
+    return {"ms_per_step": leg["wall"] / k * 1e3,
+            "newton_iters_per_step": sum(r.newton_iters for r in leg["infos"]) / k,
+            "gmres_iters_per_step": sum(r.gmres_iters_total for r in leg["infos"]) / k,
+            "fallbacks": sum(r.fallbacks for r in leg["infos"])}
 
 
 def cpu_baseline(prob, U0, seconds):
@@ -122,12 +143,82 @@ def cpu_baseline(prob, U0, seconds):
                       f"iteration of step 1 on the same {prob.nx}x{prob.nz} grid, {el:.1f} s, 1 thread"}
 
 
+def sources_sha256(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(name):
+    """HBM bytes per launch of a kernel class from the committed hardware-counter
+    summary profiles/<name>.md (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    factor), or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"^sources: (.+)$", text, re.M)
+    m_sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    m_val = re.search(r"^hbm_bytes_per_launch: ([0-9.eE+]+)$", text, re.M)
+    if not (m_src and m_sha and m_val):
+        return None
+    if sources_sha256(m_src.group(1).split()) != m_sha.group(1):
+        return None
+    return float(m_val.group(1))
+
+
+def copy_probe(gib):
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                      "GBps_read_plus_write": 8 * n / ms / 1e6}), flush=True)
+
+
+def learned_small(torch, I, LRN, Context, train_iters):
+    """Trained network vs the physics preconditioner vs the untrained form on the
+    stable thermal at 256 x 128 (two steps each from the same state)."""
+    import numpy as np
+    prob = I.thermal_stable_2d(256, 128)
+    ctx = Context(prob, max_m=30)
+    u = torch.from_numpy(I.bubble_state(prob)).cuda()
+    R, DU, u_end = LRN.collect_pairs(ctx, u, steps=4, cap=256)
+    t0 = time.perf_counter()
+    theta, losses = LRN.train_mixed(ctx, R, DU, u_end, iters=train_iters, lr=2e-3, batch=8)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0])}
+    for name, pc, params in [("physics", "physics", None), ("learned", "learned", theta),
+                             ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32))]:
+        if params is not None:
+            ctx.net_set_params(params)
+        leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner="f32",
+                        eta_floor=1e-4, pc=pc)
+        out[name] = per_step(leg)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     import numpy as np
     import torch
 
@@ -136,71 +227,83 @@ def main():
     from paper_2007_10411_amd import learned as LRN
     from paper_2007_10411_amd.jfnk import Context
 
+    legs_wanted = [x for x in args.legs.split(",") if x]
+    if args.no_learned and "learned" in legs_wanted:
+        legs_wanted.remove("learned")
+    if "mixed" not in legs_wanted:
+        legs_wanted.insert(0, "mixed")
     torch.cuda.set_device(0)
     prob = I.thermal_stable_2d(args.nx, args.nz)
     U0 = I.bubble_state(prob)
     ctx = Context(prob, max_m=30)
     common = dict(rtol=1e-8, m=30, max_restarts=20)
-    mixed = dict(common, inner="f32", eta_floor=1e-4, pc="physics")
-    plain = dict(common, inner="f64", pc="physics")
-    learned = dict(common, inner="f32", eta_floor=1e-4, pc="learned")
+    opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics"),
+            "plain": dict(common, inner="f64", pc="physics"),
+            "learned": dict(common, inner="f32", eta_floor=1e-4, pc="learned")}
+    steps = {"mixed": args.steps, "plain": args.plain_steps, "learned": args.learned_steps}
+    classes = {"mixed": {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI},
+               "plain": {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI},
+               "learned": {"jv": L.KC_JV, "arnoldi": L.KC_ARNOLDI, "net": L.KC_NET}}
 
     u = torch.from_numpy(U0).cuda()
     log(f"warmup {args.warmup} mixed steps")
-    run_steps(ctx, u, args.warmup, torch, **mixed)
+    run_steps(ctx, u, args.warmup, torch, **opts["mixed"])
+    legs = {}
+    log(f"timing {steps['mixed']} mixed steps")
+    legs["mixed"] = timed_leg(ctx, u, steps["mixed"], torch, L, classes["mixed"], **opts["mixed"])
+    if "plain" in legs_wanted:
+        log(f"timing {steps['plain']} plain FP64 steps")
+        legs["plain"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["plain"], **opts["plain"])
     train_info = None
-    if not args.no_learned:
+    small = None
+    if "learned" in legs_wanted:
         log("recording solver pairs and training the learned preconditioner")
         t0 = time.perf_counter()
-        R, DU, u = LRN.collect_pairs(ctx, u, steps=2, cap=96)
+        R, DU, u_tr = LRN.collect_pairs(ctx, u, steps=2, cap=96)
         t1 = time.perf_counter()
-        theta, losses = LRN.train_mixed(ctx, R, DU, u, iters=args.train_iters, lr=2e-3, batch=8)
+        theta, losses = LRN.train_mixed(ctx, R, DU, u_tr, iters=args.train_iters, lr=2e-3, batch=8)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         train_info = {"pairs": int(R.shape[0]), "collect_s": t1 - t0, "train_s": t2 - t1,
-                      "adam_steps": args.train_iters, "loss_first": losses[0],
-                      "loss_last": float(np.mean(losses[-20:]))}
+                      "adam_steps": args.train_iters, "dilations": list(LRN.DILATIONS),
+                      "loss_first": losses[0], "loss_last": float(np.mean(losses[-20:]))}
         del R, DU
         torch.cuda.empty_cache()
-    legs = {}
-    if not args.no_learned:
-        log(f"timing {args.steps} learned steps")
-        legs["learned"] = timed_leg(ctx, u, args.steps, torch, L, **learned)
-    log(f"timing {args.steps} mixed steps")
-    legs["mixed"] = timed_leg(ctx, u, args.steps, torch, L, **mixed)
-    log(f"timing {args.plain_steps} plain FP64 steps")
-    legs["plain"] = timed_leg(ctx, u, args.plain_steps, torch, L, **plain)
-    main_leg = "learned" if "learned" in legs else "mixed"
-    T = legs[main_leg]
+        log(f"timing {steps['learned']} learned steps")
+        legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
+        log("learned vs physics preconditioner at 256 x 128")
+        small = learned_small(torch, I, LRN, Context, args.train_iters)
+
+    T = legs["mixed"]
     tm = T["tm"]
     npts = prob.npts
 
-    def per_step(leg):
-        k = len(legs[leg]["infos"])
-        return {"ms_per_step": legs[leg]["wall"] / k * 1e3,
-                "newton_iters_per_step": sum(r.newton_iters for r in legs[leg]["infos"]) / k,
-                "gmres_iters_per_step": sum(r.gmres_iters_total for r in legs[leg]["infos"]) / k,
-                "fallbacks": sum(r.fallbacks for r in legs[leg]["infos"])}
-
-    def roof(name, kernel, bound="hbm"):
-        ms, launches, amount = tm[name]
+    def roof(leg, name, kernel, bound="hbm", traffic=None):
+        ms, launches, amount = legs[leg]["tm"][name]
         rate = amount / (ms / 1e3) if ms > 0 else 0.0
+        per = amount / max(launches, 1)
         if bound == "mfma":
             achieved = rate / 1e12
             return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
-                    "flops_per_launch": amount / max(launches, 1), "avg_launch_us": ms / max(launches, 1) * 1e3,
-                    "launches": launches}
+                    "flops_per_launch": per, "avg_launch_us": ms / max(launches, 1) * 1e3, "launches": launches}
         achieved = rate / 1e9
         return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": amount / max(launches, 1), "avg_launch_us": ms / max(launches, 1) * 1e3,
-                "launches": launches}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_launch": per, "avg_launch_us": ms / max(launches, 1) * 1e3, "launches": launches}
 
-    kernels = {"arnoldi": "k_cgs<float> x3 + k_cgs_finish x3 (CGS2 passes of one GMRES iteration)",
-               "pc": "k_pc_diag_2d<float> + k_pc_sweep_2d<float,64,8> (physics preconditioner)",
-               "jv": "k_jv_2d<float,64,8> (stable finite-difference Jv)"}
+    kernels = {"arnoldi": "k_cgs<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
+               "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner)",
+               "jv": "k_jv_2d<float> (stable finite-difference Jv)"}
+    traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_stable_1024x512",
+                    "pc": "pc_f32_counters_thermal_stable_1024x512",
+                    "jv": "jv_f32_counters_thermal_stable_1024x512"}
     dominant = max(kernels, key=lambda k: tm[k][0])
+    full = (prob.nx, prob.nz) == (1024, 512)
+
+    def traffic_of(k):
+        return counter_traffic(traffic_name[k]) if full else None
+
     jv_ms, jv_launches, _ = tm["jv"]
     value = npts * jv_launches / T["wall"] / 1e9
     out = {
@@ -208,30 +311,35 @@ def main():
         "value": value,
         "unit": "Gpoint-residuals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps["mixed"],
         "warmup": args.warmup,
-        "ms_per_step": T["wall"] / args.steps * 1e3,
+        "ms_per_step": T["wall"] / steps["mixed"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32 Krylov/Jv, bf16 MFMA learned PC, f64 Newton" if main_leg == "learned"
-                  else "f32 Krylov/Jv, f64 Newton"),
+        "dtype": "f32 Krylov/Jv, f64 Newton",
         "data": "synthetic",
         "config": {
             "workload": f"stable 2D dry thermal {prob.nx}x{prob.nz} (20x10 km, N=0.01/s, +2 K bubble, "
-                        f"dt={prob.dt} s, Smagorinsky), {main_leg} JFNK: FGMRES(30), Newton rtol 1e-8",
+                        f"dt={prob.dt} s, Smagorinsky), mixed-precision JFNK with the physics-based "
+                        f"preconditioner: FGMRES(30), Newton rtol 1e-8",
             "grid": [prob.nx, prob.nz],
-            "timed_leg": main_leg,
-            "legs": {k: per_step(k) for k in legs},
+            "timed_leg": "mixed",
+            "legs": {k: per_step(v) for k, v in legs.items()},
+            "plain_over_mixed_time": (per_step(legs["plain"])["ms_per_step"] / per_step(T)["ms_per_step"]
+                                      if "plain" in legs else None),
             "training": train_info,
+            "learned_256x128": small,
             "jv_kernel_gpts": npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0,
-            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in tm.items()},
+            "kernel_ms_per_step": {k: v[0] / steps["mixed"] for k, v in tm.items()},
         },
-        "roofline": roof(dominant, kernels[dominant]),
-        "roofline_jv": roof("jv", kernels["jv"]),
+        "roofline": roof("mixed", dominant, kernels[dominant], traffic=traffic_of(dominant)),
+        "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=traffic_of("jv")),
+        "roofline_pc": roof("mixed", "pc", kernels["pc"], traffic=traffic_of("pc")),
     }
-    if tm["net"][1] > 0:
-        out["roofline_net"] = roof("net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)", "mfma")
+    if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
+        out["roofline_net"] = roof("learned", "net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)",
+                                   "mfma")
     if not args.no_cpu:
         log(f"cpu baseline ({args.cpu_seconds} s)")
         out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds)

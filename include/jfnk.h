@@ -202,7 +202,8 @@ int jfnk_tune(jfnk_ctx* ctx, int32_t* tile_rows);
  * 0 Jv, 1 residual/rhs, 2 physics preconditioner (diagonal start and sweeps),
  * 3 Arnoldi (the three Gram-Schmidt passes of one iteration with their
  * finishing reductions and the Givens step), 4 other, 5 learned preconditioner
- * (network application).  enable = 1 starts recording and clears the counters.
+ * (network application).  enable != 0 starts recording and clears the counters:
+ * a bit mask of the classes recorded (bit k: class k; -1 all), 0 stops.
  * bytes receives the algorithmic HBM bytes of the recorded launches (each array
  * element moved once per launch); for class 5 it receives the algorithmic flops
  * (2 per weight and grid point) instead.                                        */
@@ -232,9 +233,20 @@ int jfnk_net_set_params(jfnk_ctx* ctx, const float* theta_host, int64_t n);
 int jfnk_net_get_params(jfnk_ctx* ctx, float* theta_host, int64_t n);
 /* z = learned preconditioner applied to r; bf16 = 1: BF16 MFMA, 0: FP32.       */
 int jfnk_net_apply(jfnk_ctx* ctx, int32_t bf16, const float* r, float* z);
-/* Mean over a batch of pairs (r_b, du_b) (batch consecutive state vectors) of
- * ||z(r_b) - du_b||^2 / ||du_b||^2 (to a host double) and its gradient (to a HOST
- * float array of n_params, or NULL), FP32 forward and backward.                  */
+/* Training loss of a pair (r, du) with J du = r:
+ *   JFNK_NET_LOSS_SOLUTION        ||z(r) - du||^2 / ||du||^2 (default)
+ *   JFNK_NET_LOSS_REST_JACOBIAN   ||J0 (z(r) - du)||^2 / ||J0 du||^2, J0 the
+ *       Jacobian of R (eq. 5) at the state of rest with the closure off: the
+ *       acoustic-gravity terms of eqs. 1-3 about the hydrostatic background.  It
+ *       weighs the error as the residual J z - r that right-preconditioned GMRES
+ *       sees; its gradient uses the exact transpose of J0 (with mirror walls the
+ *       transpose of a derivative is minus the derivative of the opposite
+ *       parity).  Needs energy_test = 0.  Errors: JFNK_ERR_ARG.                   */
+typedef enum { JFNK_NET_LOSS_SOLUTION = 0, JFNK_NET_LOSS_REST_JACOBIAN = 1 } jfnk_net_loss;
+int jfnk_net_set_loss(jfnk_ctx* ctx, int32_t kind);
+/* Mean over a batch of pairs (r_b, du_b) (batch consecutive state vectors) of the
+ * selected loss (to a host double) and its gradient (to a HOST float array of
+ * n_params, or NULL), FP32 forward and backward.                                 */
 int jfnk_net_loss_grad(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, double* loss,
                        float* grad_host);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on that loss;

@@ -392,6 +392,68 @@ def jv(prob, U, V, eps):
 
 
 # --------------------------------------------------------------------------- #
+# Jacobian at the state of rest without closure (acoustic-gravity operator)
+# --------------------------------------------------------------------------- #
+def rest_jacobian(prob, V):
+    """J0 v: the Jacobian of R (eq. 5) at the state of rest (u = 0, p' = 0,
+    theta' = 0) with the turbulence closure off.  There every convective
+    product and the surface source drop out, leaving the acoustic-gravity
+    terms of eqs. 1-3 about the hydrostatic background:
+        (J0 v)_i     = 2 v_i / dt + theta0 D_i p  - delta_iz (g/theta0) theta
+        (J0 v)_p     = 2 p / dt + w dp_bar/dz + kappa p_bar div v
+        (J0 v)_theta = 2 theta / dt + beta w
+    (v_i, p, theta the components of v)."""
+    assert not prob.energy_test
+    ops = _Ops(prob)
+    nd = prob.dim
+    names = field_names(prob)
+    I = lambda a: interior(prob, a)
+    _, pb, dpb = background(prob)
+    k = kappa(prob)
+    out = 2.0 * V / prob.dt
+    pe = extend(prob, V[nd], names[nd])
+    for i in range(nd):
+        out[i] = out[i] + prob.theta0 * I(ops.D(pe, i))
+    out[nd - 1] = out[nd - 1] - (prob.g / prob.theta0) * V[nd + 1]
+    div = 0.0
+    for j in range(nd):
+        div = div + I(ops.D(extend(prob, V[j], names[j]), j))
+    out[nd] = out[nd] + V[nd - 1] * _zcol(prob, dpb) + k * _zcol(prob, pb) * div
+    out[nd + 1] = out[nd + 1] + beta(prob) * V[nd - 1]
+    return out
+
+
+def rest_jacobian_transpose(prob, Y):
+    """J0^T y.  With mirror extension, the transpose of the derivative of a field
+    of one parity is minus the derivative of a field of the opposite parity
+    (fold the ghost rows back onto their sources); for the terms of J0 this is
+    every field's own parity, so
+        (J0^T y)_i     = 2 y_i / dt - D_i(kappa p_bar y_p) + delta_iz (dp_bar/dz y_p + beta y_theta)
+        (J0^T y)_p     = 2 y_p / dt - theta0 div(y_vel)
+        (J0^T y)_theta = 2 y_theta / dt - (g/theta0) y_w
+    with kappa p_bar y_p extended like p (the product formed at the interior
+    points, then reflected)."""
+    assert not prob.energy_test
+    ops = _Ops(prob)
+    nd = prob.dim
+    names = field_names(prob)
+    I = lambda a: interior(prob, a)
+    _, pb, dpb = background(prob)
+    k = kappa(prob)
+    out = 2.0 * Y / prob.dt
+    q = extend(prob, k * _zcol(prob, pb) * Y[nd], names[nd])
+    for i in range(nd):
+        out[i] = out[i] - I(ops.D(q, i))
+    out[nd - 1] = out[nd - 1] + _zcol(prob, dpb) * Y[nd] + beta(prob) * Y[nd + 1]
+    div = 0.0
+    for j in range(nd):
+        div = div + I(ops.D(extend(prob, Y[j], names[j]), j))
+    out[nd] = out[nd] - prob.theta0 * div
+    out[nd + 1] = out[nd + 1] - (prob.g / prob.theta0) * Y[nd - 1]
+    return out
+
+
+# --------------------------------------------------------------------------- #
 # diagnostics (section 3.1.3)
 # --------------------------------------------------------------------------- #
 def energies(prob, U):

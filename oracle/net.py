@@ -13,7 +13,11 @@ J^{-1} cheaply; the network form follows the design of this project:
         d_l * (-1, 0, 1)), zero padding ("same"), with bias,
     GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
 
-Loss of a pair (r, du): ||z(r) - du||^2 / ||du||^2, averaged over a batch.
+Loss of a pair (r, du), averaged over a batch, in one of two norms:
+  solution space   ||z(r) - du||^2 / ||du||^2
+  weighted by A    ||A (z(r) - du)||^2 / ||A du||^2, A a fixed linear operator
+                   (the Jacobian at rest, so that the loss measures the residual
+                   J z - r that right-preconditioned GMRES sees).
 Adam (Kingma and Ba 2015): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
 w <- w - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
@@ -142,8 +146,10 @@ def forward(theta, r, dt, keep=False, dils=(1, 1, 1, 1)):
     return z
 
 
-def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1)):
-    """Mean over the batch of ||z(r) - du||^2 / ||du||^2 and its gradient."""
+def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1), op=None):
+    """Mean over the batch of the pair loss and its gradient.  op = None: the
+    solution-space loss; op = (A, AT): the loss weighted by A, with AT its
+    transpose (both map state-shaped arrays)."""
     nf = _grid(R[0]).shape[0]
     layers = unpack(theta, nf)
     total = 0.0
@@ -151,10 +157,18 @@ def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1)):
     B = len(R)
     for r, du in zip(R, DU):
         z, (s, acts, pres) = forward(theta, r, dt, keep=True, dils=dils)
-        d = _grid(z) - _grid(du)
-        nd = float(np.sum(_grid(du) ** 2))
-        total += float(np.sum(d * d)) / nd / B
-        g = (2.0 / nd / B) * d * s[:, None, None]          # dL / d(network output)
+        if op is None:
+            d = _grid(z) - _grid(du)
+            nd = float(np.sum(_grid(du) ** 2))
+            total += float(np.sum(d * d)) / nd / B
+            gz = d
+        else:
+            A, AT = op
+            t = A(z - du)
+            nd = float(np.sum(A(du) ** 2))
+            total += float(np.sum(t * t)) / nd / B
+            gz = _grid(AT(t))
+        g = (2.0 / nd / B) * gz * s[:, None, None]         # dL / d(network output)
         for l in range(NLAYER - 1, -1, -1):
             if l < NLAYER - 1:
                 g = g * gelu_grad(pres[l])

@@ -16,13 +16,14 @@ JFNK_OK, JFNK_NOT_CONVERGED, JFNK_ERR_ARG, JFNK_ERR_HIP, JFNK_ERR_NONFINITE = 0,
 F64, F32 = 0, 1
 PC_NONE, PC_PHYSICS, PC_LEARNED = 0, 1, 2
 JV_STABLE, JV_LITERAL, JV_ANALYTIC = 0, 1, 2
+NET_LOSS_SOLUTION, NET_LOSS_REST_JACOBIAN = 0, 1
 KC_JV, KC_RESIDUAL, KC_PC, KC_ARNOLDI, KC_VEC, KC_NET = range(6)
 
 EXPORTS = ["jfnk_create", "jfnk_destroy", "jfnk_last_error", "jfnk_set_stream", "jfnk_rhs",
            "jfnk_residual", "jfnk_apply_F", "jfnk_jv", "jfnk_precond_apply", "jfnk_gmres",
            "jfnk_newton_step", "jfnk_norm", "jfnk_timing_enable", "jfnk_timing_read",
            "jfnk_net_init", "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_apply",
-           "jfnk_net_loss_grad", "jfnk_net_train_step", "jfnk_tune",
+           "jfnk_net_set_loss", "jfnk_net_loss_grad", "jfnk_net_train_step", "jfnk_tune",
            "jfnk_batch_create", "jfnk_batch_destroy", "jfnk_batch_size", "jfnk_batch_apply_F",
            "jfnk_batch_newton_step", "jfnk_batch_tune"]
 
@@ -96,6 +97,7 @@ def load():
     L.jfnk_net_set_params.argtypes = [vp, vp, C.c_int64]
     L.jfnk_net_get_params.argtypes = [vp, vp, C.c_int64]
     L.jfnk_net_apply.argtypes = [vp, C.c_int32, vp, vp]
+    L.jfnk_net_set_loss.argtypes = [vp, C.c_int32]
     L.jfnk_net_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]
     L.jfnk_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.POINTER(C.c_double)]
     L.jfnk_tune.argtypes = [vp, C.POINTER(C.c_int32)]

@@ -93,7 +93,8 @@ struct TimedLaunch {
     jfnk_ctx* c;
     int cls;
     bool active;
-    TimedLaunch(jfnk_ctx* c_, int cls_, double bytes = 0.0) : c(c_), cls(cls_), active(c_->timing.on) {
+    TimedLaunch(jfnk_ctx* c_, int cls_, double bytes = 0.0)
+        : c(c_), cls(cls_), active(c_->timing.on && ((c_->timing.mask >> cls_) & 1u)) {
         if (!active) return;
         c->timing.bytes[cls] += bytes;
         auto& T = c->timing;
@@ -360,15 +361,13 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
             // dot pass reads V_0..V_j and w; each update pass also writes w
             TimedLaunch tl(c, KC_ARNOLDI, (3.0 * (j + 1) + 5.0) * n * sizeof(T));
             ga.j = j;
+            ga.host = c->hscal + S_SLOT0 + 2 * (j & 1);   // (||w||, |g_{j+1}|) for the host's test
             JFNK_HIP(launch_cgs<T>(V, n, j + 1, nullptr, Vn, c->partials, ds(c, O_H1), CGS_DOT, gnone, s));
             JFNK_HIP(launch_cgs<T>(V, n, j + 1, ds(c, O_H1), Vn, c->partials, ds(c, O_H2), CGS_UPD_DOT, gnone, s));
             JFNK_HIP(launch_cgs<T>(V, n, j + 1, ds(c, O_H2), Vn, c->partials, sc(c, S_WNORM2), CGS_UPD_NORM, ga,
                                    s));
         }
-        const int slot = j & 1;
-        JFNK_HIP(hipMemcpyAsync(c->hscal + S_SLOT0 + 2 * slot, sc(c, S_WNORM), 2 * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-        JFNK_HIP(hipEventRecord(c->slot_ev[slot], s));
+        JFNK_HIP(hipEventRecord(c->slot_ev[j & 1], s));
         ++enqueued;
         return JFNK_OK;
     };
@@ -602,7 +601,9 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     }
 #undef ALLOC
     {
-        hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault);
+        // fine-grained (coherent) so that kernels can write the convergence
+        // scalars straight to the host
+        hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocCoherent);
         if (e != hipSuccess) return fail(e, "hipHostMalloc");
         for (int k = 0; k < 2; ++k) {
             e = hipEventCreateWithFlags(&c->slot_ev[k], hipEventDisableTiming);
@@ -919,6 +920,7 @@ int jfnk_timing_enable(jfnk_ctx* c, int32_t enable) {
         c->timing.bytes[k] = 0.0;
     }
     c->timing.on = enable != 0;
+    c->timing.mask = enable < 0 ? ~0u : (unsigned)enable;
     return JFNK_OK;
 }
 
@@ -1031,11 +1033,24 @@ static int net_batch_grad(jfnk_ctx* c, const float* r, const float* du, int32_t 
     NetBuffers& nb = c->net;
     for (int b = 0; b < batch; ++b)
         JFNK_HIP(net_pair_grad(nb, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), r + (long long)b * c->n,
-                               du + (long long)b * c->n, 1.0 / batch, b == 0, c->stream));
+                               du + (long long)b * c->n, 1.0 / batch, b == 0, c->geo, c->stream));
     if (loss) {
         JFNK_HIP(hipMemcpyAsync(loss, nb.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         JFNK_HIP(hipStreamSynchronize(c->stream));
     }
+    return JFNK_OK;
+}
+
+int jfnk_net_set_loss(jfnk_ctx* c, int32_t kind) {
+    if (!net_ok(c) || (kind != JFNK_NET_LOSS_SOLUTION && kind != JFNK_NET_LOSS_REST_JACOBIAN)) {
+        set_error("invalid argument to jfnk_net_set_loss");
+        return JFNK_ERR_ARG;
+    }
+    if (kind == JFNK_NET_LOSS_REST_JACOBIAN && c->prob.energy_test) {
+        set_error("the rest-Jacobian loss needs the physical Exner coefficient (energy_test = 0)");
+        return JFNK_ERR_ARG;
+    }
+    c->net.loss_kind = kind;
     return JFNK_OK;
 }
 

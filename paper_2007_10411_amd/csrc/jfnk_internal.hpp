@@ -91,6 +91,7 @@ constexpr int kMaxDots = 64;         // vectors per fused dot pass (>= max_m + 1
 // elapsed times are resolved lazily (no host synchronisation per launch).
 struct Timing {
     bool on = false;
+    unsigned mask = 0;                      // classes recorded (bit k: class k)
     std::vector<hipEvent_t> ev[KC_COUNT];   // 2 per launch
     int used[KC_COUNT] = {0};
     double ms[KC_COUNT] = {0};
@@ -121,15 +122,17 @@ struct NetBuffers {
     int nparam = 0;
     int adam_t = 0;
     int dil[4] = {1, 1, 1, 1};       // per-layer dilation of the 3x3 kernels
+    int loss_kind = 0;               // NET_LOSS_SOLUTION or NET_LOSS_REST_JACOBIAN
     bool ready = false;              // parameters set
 };
+enum { NET_LOSS_SOLUTION = 0, NET_LOSS_REST_JACOBIAN = 1 };
 
 int net_param_count(int nf);
 hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s);
 hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r, float* z,
                      bool bf16, hipStream_t st);
 hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
-                         const float* du, double inv_batch, bool first_pair, hipStream_t st);
+                         const float* du, double inv_batch, bool first_pair, const Geo& geo, hipStream_t st);
 hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st);
 
 }  // namespace jfnk

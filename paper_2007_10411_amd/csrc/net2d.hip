@@ -13,6 +13,7 @@
 
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
+#include "stencil2d_impl.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -229,6 +230,99 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ z, 
     if (threadIdx.x == 0) partials[blockIdx.x] = t / nd * inv_batch;
 }
 
+// Jacobian at rest J0 (acoustic-gravity terms about the hydrostatic background,
+// closure off) and its transpose, FP32, one thread per point with the taps read
+// through the caches under each field's own reflection parity:
+//   (J0 v)_u = 2u/dt + theta0 Dx p         (J0^T y)_u = 2y_u/dt - Dx(kappa p_bar y_p)
+//   (J0 v)_w = 2w/dt + theta0 Dz p         (J0^T y)_w = 2y_w/dt - Dz(kappa p_bar y_p)
+//              - (g/theta0) theta                       + dp_bar/dz y_p + beta y_theta
+//   (J0 v)_p = 2p/dt + dp_bar/dz w         (J0^T y)_p = 2y_p/dt - theta0 (Dx y_u + Dz y_w)
+//              + kappa p_bar (Dx u + Dz w)
+//   (J0 v)_theta = 2theta/dt + beta w      (J0^T y)_theta = 2y_theta/dt - (g/theta0) y_w
+// (kappa p_bar y_p is formed at the source point of a reflected tap, i.e.
+// extended like p).  partials[block] = sum of the squared outputs.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_rest_jac(Geo g, const float* __restrict__ in, float* __restrict__ out,
+                                                  double* __restrict__ partials) {
+    __shared__ double red[4];
+    const long long np = g.npts;
+    const int nx = g.nx, nz = g.nz;
+    const bool perx = g.bcl == JFNK_BC_PERIODIC, perz = g.bcv == JFNK_BC_PERIODIC;
+    const float ihx = (float)g.idx, ihz = (float)g.idz, tdt = (float)g.two_dt;
+    const float th0 = (float)g.theta0, gth = (float)g.g_theta0, kap = (float)g.kappa, bet = (float)g.beta;
+    const float* pb = g.pbar32;
+    const float* dpb = g.dpbar32;
+    // field f at the extended position (ex, ez), with its reflection sign; with
+    // TRANS and f == 2 the product kappa p_bar y_p at the source point
+    auto tap = [&](int f, int ex, int ez) -> float {
+        int sx, sz;
+        const int xs = s2d::map_axis(ex, nx, perx, sx);
+        const int zs = s2d::map_axis(ez, nz, perz, sz);
+        float v = in[(long long)f * np + (long long)zs * nx + xs];
+        if (TRANS && f == 2) v *= kap * pb[zs];
+        return s2d::sign2d(f, sx, sz, g.bcv) < 0 ? -v : v;
+    };
+    auto ddx = [&](int f, int x, int z) {
+        return s2d::d5(tap(f, x - 2, z), tap(f, x - 1, z), tap(f, x + 1, z), tap(f, x + 2, z), ihx);
+    };
+    auto ddz = [&](int f, int x, int z) {
+        return s2d::d5(tap(f, x, z - 2), tap(f, x, z - 1), tap(f, x, z + 1), tap(f, x, z + 2), ihz);
+    };
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < np; i += (long long)gridDim.x * 256) {
+        const int gz = (int)(i / nx), gx = (int)(i - (long long)gz * nx);
+        const float u = in[i], w = in[np + i], p = in[2 * np + i], t = in[3 * np + i];
+        float ou, ow, op, ot;
+        if (!TRANS) {
+            ou = tdt * u + th0 * ddx(2, gx, gz);
+            ow = tdt * w + th0 * ddz(2, gx, gz) - gth * t;
+            op = tdt * p + dpb[gz] * w + kap * pb[gz] * (ddx(0, gx, gz) + ddz(1, gx, gz));
+            ot = tdt * t + bet * w;
+        } else {
+            ou = tdt * u - ddx(2, gx, gz);
+            ow = tdt * w - ddz(2, gx, gz) + dpb[gz] * p + bet * t;
+            op = tdt * p - th0 * (ddx(0, gx, gz) + ddz(1, gx, gz));
+            ot = tdt * t - gth * w;
+        }
+        out[i] = ou;
+        out[np + i] = ow;
+        out[2 * np + i] = op;
+        out[3 * np + i] = ot;
+        acc += (double)ou * ou + (double)ow * ow + (double)op * op + (double)ot * ot;
+    }
+    const double tot = block_sum256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// e = z - du (elementwise)
+__global__ __launch_bounds__(256) void k_sub(const float* __restrict__ a, const float* __restrict__ b, long long n,
+                                             float* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        out[i] = a[i] - b[i];
+}
+
+// loss (+)= sum(partials) / ||A du||^2 * inv_batch; g *= 2 s / (||A du||^2 B)
+__global__ __launch_bounds__(256) void k_weighted_loss(const double* __restrict__ partials, int nblk,
+                                                       const double* __restrict__ du2, double inv_batch,
+                                                       double* __restrict__ loss, int accumulate) {
+    __shared__ double red[4];
+    const double t = sum_partials(partials, nblk, 1, 0, red);
+    if (threadIdx.x == 0) {
+        const double v = t / *du2 * inv_batch;
+        *loss = accumulate ? *loss + v : v;
+    }
+}
+__global__ __launch_bounds__(256) void k_scale_grad(float* __restrict__ g, long long npts, int nf,
+                                                    const float* __restrict__ s, const double* __restrict__ du2,
+                                                    double inv_batch) {
+    const double c = 2.0 / *du2 * inv_batch;
+    const long long n = npts * nf;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const int f = (int)(i / npts);
+        g[i] = (float)((double)g[i] * (double)s[f] * c);
+    }
+}
+
 // dW[co][ci][t] and db[co] partial sums over one 64 x 4 tile of pixels; the
 // input is staged one channel at a time with the halo of the layer's dilation
 __global__ __launch_bounds__(256) void k_conv_wgrad(int nx, int nz, const float* __restrict__ g, int cout,
@@ -420,7 +514,7 @@ hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt
 // loss and gradient (accumulated into nb.grad) of one pair, FP32 forward/backward;
 // returns the loss contribution in nb.loss (device double, accumulated)
 hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
-                         const float* du, double inv_batch, bool first_pair, hipStream_t st) {
+                         const float* du, double inv_batch, bool first_pair, const Geo& geo, hipStream_t st) {
     NetLayer L[4];
     layers_of(nf, L);
     const long long np = (long long)nx * nz;
@@ -445,8 +539,26 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
                        nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, pre[3], (float*)nullptr, r, nb.s,
                        half_dt, nb.z, (const float*)nullptr, nb.dil[3]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // ||du||^2, then g = dL/d(network output) and the loss
-    {
+    if (nb.loss_kind == NET_LOSS_REST_JACOBIAN) {
+        // ||J0 du||^2; t = J0 (z - du) and its squared norm; g = J0^T t scaled
+        const int nblk = (int)std::min<long long>(1024, (np + 255) / 256);
+        float* ebuf = nb.g0;
+        float* tbuf = nb.g1;
+        hipLaunchKernelGGL(k_rest_jac<false>, dim3(nblk), dim3(256), 0, st, geo, du, tbuf, nb.partials);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_reduce_partials(nb.partials, nblk, 1, 1, nb.scal, 0, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, st, (const float*)nb.z, du, np * nf, ebuf);
+        hipLaunchKernelGGL(k_rest_jac<false>, dim3(nblk), dim3(256), 0, st, geo, (const float*)ebuf, tbuf,
+                           nb.partials + 4096);
+        hipLaunchKernelGGL(k_weighted_loss, dim3(1), dim3(256), 0, st, (const double*)(nb.partials + 4096), nblk,
+                           (const double*)nb.scal, inv_batch, nb.loss, first_pair ? 0 : 1);
+        hipLaunchKernelGGL(k_rest_jac<true>, dim3(nblk), dim3(256), 0, st, geo, (const float*)tbuf, ebuf,
+                           nb.partials);
+        hipLaunchKernelGGL(k_scale_grad, dim3(nblk), dim3(256), 0, st, ebuf, np, nf, (const float*)nb.s,
+                           (const double*)nb.scal, inv_batch);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        // ||du||^2, then g = dL/d(network output) and the loss
         const long long n = np * nf;
         int nblk = (int)std::min<long long>(1024, (n + 1023) / 1024);
         hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, 1), dim3(256), 0, st, du, n, nb.partials);

@@ -217,13 +217,26 @@ __global__ void k_givens(GivensArgs a, const double* wnorm2) {
     givens_column(a, *wnorm2);
 }
 
-__global__ void k_backsolve(const double* H, const double* g, int k, int m, double* y) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
-        y[i] = s / H[i * m + i];
+// Back substitution of the k x k upper triangle of H (row-major, row stride m)
+// by columns: y_i = s_i / H_ii, then every row above subtracts H_li y_i.  One
+// wavefront, H and g staged in LDS (k <= kMaxDots).
+__global__ __launch_bounds__(64) void k_backsolve(const double* H, const double* g, int k, int m, double* y) {
+    __shared__ double sH[kMaxDots][kMaxDots + 1];
+    __shared__ double sy[kMaxDots];
+    const int t = threadIdx.x;
+    for (int idx = t; idx < k * k; idx += 64) {
+        const int i = idx / k, l = idx - i * k;
+        sH[i][l] = H[i * m + l];
     }
+    double s = t < k ? g[t] : 0.0;
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+        if (t == i) sy[i] = s / sH[i][i];
+        __syncthreads();
+        if (t < i) s -= sH[t][i] * sy[i];
+    }
+    __syncthreads();
+    if (t < k) y[t] = sy[t];
 }
 
 __global__ void k_set_start(const double* beta2, double* g, double* beta, int m) {
@@ -368,6 +381,10 @@ __global__ __launch_bounds__(kBlock) void k_cgs_finish(const double* __restrict_
         ga.g[j + 1] = -sn * gj;
         ga.g[j] = c * gj;
         *ga.res_est = fabs(sn * gj);
+        if (ga.host) {                   // pinned host mirror for the convergence test
+            ga.host[0] = nw;
+            ga.host[1] = fabs(sn * gj);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= j + 1; i += kBlock) ga.H[i * m + j] = col[i];
@@ -529,7 +546,8 @@ hipError_t launch_normalize_copy(T* v, long long n, const double* div, T* z, con
 }
 
 hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, s, H, g, k, m, y);
+    if (k < 1 || k > kMaxDots) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, g, k, m, y);
     return hipGetLastError();
 }
 

@@ -180,6 +180,12 @@ class Context:
         self.dilations = tuple(int(x) for x in dilations)
         return n.value
 
+    def net_set_loss(self, kind):
+        """kind: "solution" (||z - du||^2 / ||du||^2) or "rest_jacobian"
+        (||J0 (z - du)||^2 / ||J0 du||^2, J0 the Jacobian at rest)."""
+        code = {"solution": L.NET_LOSS_SOLUTION, "rest_jacobian": L.NET_LOSS_REST_JACOBIAN}[kind]
+        L.check(self.lib.jfnk_net_set_loss(self.h, code), "jfnk_net_set_loss", soft_ok=False)
+
     def net_set_params(self, theta):
         th = np.ascontiguousarray(theta, dtype=np.float32)
         L.check(self.lib.jfnk_net_set_params(self.h, th.ctypes.data_as(C.c_void_p), th.size),
@@ -222,8 +228,11 @@ class Context:
         return dict(zip(keys, list(rows)))
 
     # -- timing ----------------------------------------------------------------
-    def timing(self, on: bool):
-        L.check(self.lib.jfnk_timing_enable(self.h, 1 if on else 0), "jfnk_timing_enable", soft_ok=False)
+    def timing(self, on):
+        """Start (clearing the counters) or stop HIP-event timing: True records
+        every kernel class, an int is a bit mask of classes (bit k: class k)."""
+        mask = -1 if on is True else (0 if on is False else int(on))
+        L.check(self.lib.jfnk_timing_enable(self.h, mask), "jfnk_timing_enable", soft_ok=False)
 
     def timing_read(self, cls):
         """(total ms, launches, algorithmic bytes) of one kernel class."""

@@ -78,12 +78,14 @@ def field_rms(DU, nf):
 
 
 def train_mixed(ctx, R, DU, u, iters=2000, lr=2e-3, batch=8, seed=0, theta0=None, noise_every=2,
-                dilations=DILATIONS):
+                dilations=DILATIONS, loss="solution"):
     """The recipe used by the benchmark and tests: noise pairs at the state u on
-    every step but one in ``noise_every``, recorded Krylov pairs on the others."""
+    every step but one in ``noise_every``, recorded Krylov pairs on the others;
+    ``loss`` selects the training norm (see ``Context.net_set_loss``)."""
     import torch
     nf = ctx.prob.nf
     ctx.net_init(dilations)
+    ctx.net_set_loss(loss)
     theta = I.net_init_params(nf, seed=seed) if theta0 is None else np.asarray(theta0)
     ctx.net_set_params(theta.astype(np.float32))
     noise = NoisePairs(ctx, u, field_rms(DU, nf), seed=seed + 1)

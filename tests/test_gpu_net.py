@@ -79,6 +79,35 @@ def test_net_loss_gradient_matches_oracle(dils):
         o += nw
 
 
+@pytest.mark.parametrize("case", ["stable", "heat_island", "periodic"])
+def test_rest_jacobian_loss_gradient_matches_oracle(case):
+    from oracle import model as M
+    prob = {"stable": I.thermal_stable_2d(70, 20),
+            "heat_island": I.heat_island_2d(96, 16),
+            "periodic": I.thermal_stable_2d(64, 12).replace(bc_lateral=2)}[case]
+    dils = (1, 2, 4, 1)
+    c = _ctx(prob, dils=dils)
+    c.net_set_loss("rest_jacobian")
+    th = _theta(prob.nf, seed=3)
+    c.net_set_params(th)
+    R = [_r(prob, 14), _r(prob, 15)]
+    DU = [_r(prob, 16), _r(prob, 17)]
+    op = (lambda a: M.rest_jacobian(prob, a), lambda a: M.rest_jacobian_transpose(prob, a))
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt, dils=dils, op=op)
+    lg, gg = c.net_loss_grad(dev(np.stack(R), "f32"), dev(np.stack(DU), "f32"))
+    assert abs(lg - lo) <= 1e-5 * lo, (lg, lo)
+    o = 0
+    for ws, bs in I.net_layer_shapes(prob.nf):
+        nw = int(np.prod(ws)) + int(np.prod(bs))
+        sl = slice(o, o + nw)
+        assert np.linalg.norm(gg[sl] - go[sl]) <= 1e-4 * np.linalg.norm(go[sl])
+        o += nw
+    # switching back restores the solution-space loss
+    c.net_set_loss("solution")
+    ls, _ = c.net_loss_grad(dev(np.stack(R), "f32"), dev(np.stack(DU), "f32"))
+    assert abs(ls - N.loss_and_grad(th, R, DU, prob.dt, dils=dils)[0]) <= 1e-5 * ls
+
+
 def test_net_adam_step_matches_oracle():
     dils = (1, 2, 4, 8)
     prob = I.thermal_stable_2d(64, 16)
