@@ -211,21 +211,22 @@ int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
 int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches,
                      double* bytes);
 
-/* ---- learned right preconditioner (2D) ------------------------------------
+/* ---- learned right preconditioner ------------------------------------------
  * z = (dt/2) r + s N(r / s), s the RMS of r over all fields and points (1 for
  * r = 0), N = conv(n_f->16) GELU conv(16->16) GELU conv(16->16) GELU
- * conv(16->n_f), 3x3 kernels with a dilation d_l per layer (taps at
- * d_l (-1, 0, 1); dilations 1, 2, 4, 8 give a dense 31 x 31 receptive field),
- * zero padding, exact (erf) GELU.  An approximate
+ * conv(16->n_f), zero padding, exact (erf) GELU.  2D: 3x3 kernels with a
+ * dilation d_l per layer (taps at d_l (-1, 0, 1); dilations 1, 2, 4, 8 give a
+ * dense 31 x 31 receptive field).  3D: 3x3x3 kernels, dilation 1.  An approximate
  * inverse of J in the spirit of the paper's cheap preconditioners (section 2.5.1);
  * nonlinear in r, hence used inside the flexible GMRES.  Parameters: one flat
- * FP32 vector, per layer W[co][ci][kz][kx] (tap offset (kz-1, kx-1)) then b[co].
+ * FP32 vector, per layer W[co][ci][kz][kx] (2D) or W[co][ci][kz][ky][kx] (3D),
+ * tap offset (kz-1, ...), then b[co].
  * Inference (JFNK_PC_LEARNED, jfnk_net_apply with bf16 = 1) runs in BF16 on the
  * matrix cores with FP32 accumulation; training in FP32 with FP32 Adam moments.
  * Vectors r, z, du are FP32 device arrays in the state layout.                  */
 /* Allocate the network workspace (the only allocating call besides
  * jfnk_create) and set the per-layer dilations (HOST, 4 entries in [1, 8], NULL:
- * all 1); n_params receives the parameter count.  2D problems only.             */
+ * all 1; 3D problems accept only 1); n_params receives the parameter count.     */
 int jfnk_net_init(jfnk_ctx* ctx, const int32_t* dilations, int64_t* n_params);
 /* Copy FP32 parameters from / to HOST memory (n must equal the count); setting
  * resets the Adam state.                                                         */

@@ -1,7 +1,8 @@
 """Learned right preconditioner for the Krylov solve: a small convolutional
 network, its exact gradient and one Adam step, in FP64.
 
-ORACLE - test infrastructure only.  Plain numpy loops over the 3 x 3 taps.
+ORACLE - test infrastructure only.  Plain numpy loops over the 3 x 3 (2D) or
+3 x 3 x 3 (3D) taps.
 
 The paper's preconditioning discussion (section 2.5.1) motivates approximating
 J^{-1} cheaply; the network form follows the design of this project:
@@ -9,8 +10,9 @@ J^{-1} cheaply; the network form follows the design of this project:
     z = (dt/2) r + s N(r / s),       s = RMS of r over all fields and points
                                       (s = 1 for r = 0)
     N = conv(n_f -> 16) - GELU - conv(16 -> 16) - GELU - conv(16 -> 16) - GELU
-        - conv(16 -> n_f),   3 x 3 kernels with dilation d_l (taps at offsets
-        d_l * (-1, 0, 1)), zero padding ("same"), with bias,
+        - conv(16 -> n_f),   3 x 3 kernels in 2D, 3 x 3 x 3 in 3D, with
+        dilation d_l (taps at offsets d_l * (-1, 0, 1) along each axis), zero
+        padding ("same"), with bias,
     GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
 
 Loss of a pair (r, du), averaged over a batch, in one of two norms:
@@ -21,11 +23,12 @@ Loss of a pair (r, du), averaged over a batch, in one of two norms:
 Adam (Kingma and Ba 2015): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
 w <- w - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
-Parameters are one flat vector: for each layer l, W_l[co][ci][kz][kx]
-(offsets dz = kz - 1, dx = kx - 1), then b_l[co].
+Parameters are one flat vector: for each layer l, W_l[co][ci][kz][kx] in 2D,
+W_l[co][ci][kz][ky][kx] in 3D (offsets dz = kz - 1, ...), then b_l[co].
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -39,22 +42,23 @@ def channels(nf):
     return [nf, HIDDEN, HIDDEN, HIDDEN, nf]
 
 
-def param_shapes(nf):
+def param_shapes(nf, dim=2):
     ch = channels(nf)
+    k = (3,) * dim
     out = []
     for l in range(NLAYER):
-        out.append(((ch[l + 1], ch[l], 3, 3), (ch[l + 1],)))
+        out.append(((ch[l + 1], ch[l]) + k, (ch[l + 1],)))
     return out
 
 
-def param_count(nf):
-    return sum(int(np.prod(w)) + int(np.prod(b)) for w, b in param_shapes(nf))
+def param_count(nf, dim=2):
+    return sum(int(np.prod(w)) + int(np.prod(b)) for w, b in param_shapes(nf, dim))
 
 
-def unpack(theta, nf):
+def unpack(theta, nf, dim=2):
     layers = []
     o = 0
-    for ws, bs in param_shapes(nf):
+    for ws, bs in param_shapes(nf, dim):
         nw, nb = int(np.prod(ws)), int(np.prod(bs))
         layers.append((theta[o:o + nw].reshape(ws), theta[o + nw:o + nw + nb]))
         o += nw + nb
@@ -74,43 +78,46 @@ def gelu_grad(x):
 
 
 def _pad(x, d):
-    cin, Z, X = x.shape
-    xp = np.zeros((cin, Z + 2 * d, X + 2 * d))
-    xp[:, d:d + Z, d:d + X] = x
-    return xp
+    return np.pad(x, [(0, 0)] + [(d, d)] * (x.ndim - 1))
+
+
+def _taps(nsp):
+    return list(itertools.product(range(3), repeat=nsp))
+
+
+def _window(k, d, shape):
+    """Slices of the padded array seen by tap k (one index per spatial axis)."""
+    return (slice(None),) + tuple(slice(kk * d, kk * d + S) for kk, S in zip(k, shape))
 
 
 def conv(x, W, b, d=1):
-    """out[co, z, x] = b[co] + sum_ci sum_taps W[co, ci, kz, kx] x[ci, z+d(kz-1), x+d(kx-1)],
-    zero outside the grid.  x: (C_in, Z, X)."""
-    cin, Z, X = x.shape
+    """out[co, p] = b[co] + sum_ci sum_taps W[co, ci, k] x[ci, p + d(k - 1)],
+    zero outside the grid.  x: (C_in, Z, X) or (C_in, Z, Y, X)."""
+    S = x.shape[1:]
     xp = _pad(x, d)
-    out = np.zeros((W.shape[0], Z, X)) + b[:, None, None]
-    for kz in range(3):
-        for kx in range(3):
-            patch = xp[:, kz * d:kz * d + Z, kx * d:kx * d + X]
-            out += np.einsum("oc,czx->ozx", W[:, :, kz, kx], patch)
+    out = np.zeros((W.shape[0],) + S) + b.reshape((-1,) + (1,) * len(S))
+    for k in _taps(len(S)):
+        out += np.einsum("oc,c...->o...", W[(slice(None), slice(None)) + k], xp[_window(k, d, S)])
     return out
 
 
 def conv_grad_input(g, W, shape_in, d=1):
     """d/dx of sum(g * conv(x)) for zero padding (the transposed convolution)."""
-    cin, Z, X = shape_in
-    gx = np.zeros((cin, Z + 2 * d, X + 2 * d))
-    for kz in range(3):
-        for kx in range(3):
-            gx[:, kz * d:kz * d + Z, kx * d:kx * d + X] += np.einsum("oc,ozx->czx", W[:, :, kz, kx], g)
-    return gx[:, d:d + Z, d:d + X]
+    S = tuple(shape_in[1:])
+    gx = np.zeros((shape_in[0],) + tuple(n + 2 * d for n in S))
+    for k in _taps(len(S)):
+        gx[_window(k, d, S)] += np.einsum("oc,o...->c...", W[(slice(None), slice(None)) + k], g)
+    return gx[(slice(None),) + tuple(slice(d, d + n) for n in S)]
 
 
 def conv_grad_weight(g, x, d=1):
-    cin, Z, X = x.shape
+    S = x.shape[1:]
     xp = _pad(x, d)
-    gW = np.zeros((g.shape[0], cin, 3, 3))
-    for kz in range(3):
-        for kx in range(3):
-            gW[:, :, kz, kx] = np.einsum("ozx,czx->oc", g, xp[:, kz * d:kz * d + Z, kx * d:kx * d + X])
-    return gW, g.sum(axis=(1, 2))
+    gW = np.zeros((g.shape[0], x.shape[0]) + (3,) * len(S))
+    axes = "".join("zyx"[-len(S):])
+    for k in _taps(len(S)):
+        gW[(slice(None), slice(None)) + k] = np.einsum(f"o{axes},c{axes}->oc", g, xp[_window(k, d, S)])
+    return gW, g.sum(axis=tuple(range(1, 1 + len(S))))
 
 
 def field_scale(r):
@@ -122,24 +129,31 @@ def field_scale(r):
 
 
 def _grid(r):
-    """(n_f, nz, 1, nx) state -> (n_f, nz, nx) image."""
-    return r[:, :, 0, :] if r.ndim == 4 else r
+    """(n_f, nz, 1, nx) state -> (n_f, nz, nx) image; a 3D state (n_f, nz, ny,
+    nx) is its own volume."""
+    if r.ndim == 4 and r.shape[2] == 1:
+        return r[:, :, 0, :]
+    return r
+
+
+def _bcast(s, nsp):
+    return s.reshape((-1,) + (1,) * nsp)
 
 
 def forward(theta, r, dt, keep=False, dils=(1, 1, 1, 1)):
     """z = (dt/2) r + s * N(r/s) for one 2D state-shaped r."""
     img = _grid(r)
-    nf = img.shape[0]
-    layers = unpack(theta, nf)
+    nf, nsp = img.shape[0], img.ndim - 1
+    layers = unpack(theta, nf, nsp)
     s = field_scale(img)
-    a = img / s[:, None, None]
+    a = img / _bcast(s, nsp)
     acts, pres = [a], []
     for l, (W, b) in enumerate(layers):
         h = conv(a, W, b, dils[l])
         pres.append(h)
         a = gelu(h) if l < NLAYER - 1 else h
         acts.append(a)
-    z = 0.5 * dt * img + s[:, None, None] * a
+    z = 0.5 * dt * img + _bcast(s, nsp) * a
     z = z.reshape(r.shape)
     if keep:
         return z, (s, acts, pres)
@@ -150,8 +164,9 @@ def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1), op=None):
     """Mean over the batch of the pair loss and its gradient.  op = None: the
     solution-space loss; op = (A, AT): the loss weighted by A, with AT its
     transpose (both map state-shaped arrays)."""
-    nf = _grid(R[0]).shape[0]
-    layers = unpack(theta, nf)
+    img0 = _grid(R[0])
+    nf, nsp = img0.shape[0], img0.ndim - 1
+    layers = unpack(theta, nf, nsp)
     total = 0.0
     grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     B = len(R)
@@ -168,7 +183,7 @@ def loss_and_grad(theta, R, DU, dt, dils=(1, 1, 1, 1), op=None):
             nd = float(np.sum(A(du) ** 2))
             total += float(np.sum(t * t)) / nd / B
             gz = _grid(AT(t))
-        g = (2.0 / nd / B) * gz * s[:, None, None]         # dL / d(network output)
+        g = (2.0 / nd / B) * gz * _bcast(s, nsp)           # dL / d(network output)
         for l in range(NLAYER - 1, -1, -1):
             if l < NLAYER - 1:
                 g = g * gelu_grad(pres[l])

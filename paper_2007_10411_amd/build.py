@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjfnk.so")
-SOURCES = ["api.hip", "stencil2d.hip", "stencil3d.hip", "vec.hip", "net2d.hip", "batch.hip"]
+SOURCES = ["api.hip", "stencil2d.hip", "stencil3d.hip", "vec.hip", "net2d.hip", "net3d.hip", "batch.hip"]
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

@@ -118,6 +118,14 @@ struct TimedLaunch {
     }
 };
 
+// learned preconditioner of the context's dimension
+hipError_t net_run(jfnk_ctx* c, const float* r, float* z, bool bf16) {
+    const float hdt = (float)(0.5 * c->prob.dt);
+    if (c->net.dim == 3)
+        return net3_apply(c->net, c->geo.nx, c->geo.ny, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream);
+    return net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream);
+}
+
 void resolve_timing(jfnk_ctx* c) {
     auto& T = c->timing;
     for (int k = 0; k < KC_COUNT; ++k) {
@@ -257,8 +265,7 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
         {
             // counted in flops: 2 multiply-adds per weight and point
             TimedLaunch tl(c, KC_NET, 2.0 * (c->net.nparam) * c->geo.npts);
-            JFNK_HIP(net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), (const float*)vj,
-                               (float*)z, true, c->stream));
+            JFNK_HIP(net_run(c, (const float*)vj, (float*)z, true));
         }
         if (ea.partials) {
             int r = norm2_to<T>(c, z, c->n, sc(c, S_VNORM2));
@@ -938,24 +945,28 @@ int jfnk_timing_read(jfnk_ctx* c, int32_t cls, double* total_ms, int64_t* launch
 
 
 int jfnk_net_init(jfnk_ctx* c, const int32_t* dilations, int64_t* n_params) {
-    if (!c || c->prob.dim != 2) {
-        set_error("the learned preconditioner is available for 2D problems");
+    if (!c) {
+        set_error("null context");
         return JFNK_ERR_ARG;
     }
     NetBuffers& nb = c->net;
+    const int dim = c->prob.dim;
     for (int l = 0; l < 4; ++l) {
         const int d = dilations ? dilations[l] : 1;
-        if (d < 1 || d > 8) {
-            set_error("dilations must be in [1, 8]");
+        if (d < 1 || d > 8 || (dim == 3 && d != 1)) {
+            set_error(dim == 3 ? "the 3D network has dilation 1" : "dilations must be in [1, 8]");
             return JFNK_ERR_ARG;
         }
         nb.dil[l] = d;
     }
-    const int np = net_param_count(c->nf);
+    const int taps = dim == 3 ? 27 : 9;
+    const int np = dim == 3 ? net3_param_count(c->nf) : net_param_count(c->nf);
     if (n_params) *n_params = np;
     if (nb.theta) return JFNK_OK;
+    nb.dim = dim;
     const long long npts = c->geo.npts;
-    const long long tiles = (long long)((c->geo.nx + 63) / 64) * ((c->geo.nz + 3) / 4);
+    const long long tiles = dim == 3 ? net3_wgrad_tiles(c->geo.nx, c->geo.ny, c->geo.nz)
+                                     : (long long)((c->geo.nx + 63) / 64) * ((c->geo.nz + 3) / 4);
     nb.nparam = np;
 #define NALLOC(ptr, count)                                                   \
     do {                                                                     \
@@ -967,7 +978,7 @@ int jfnk_net_init(jfnk_ctx* c, const int32_t* dilations, int64_t* n_params) {
     NALLOC(nb.m, np);
     NALLOC(nb.v, np);
     NALLOC(nb.wt, np);
-    NALLOC(nb.wbf, 4 * 9 * 16 * 16);
+    NALLOC(nb.wbf, 4 * taps * 16 * 16);
     NALLOC(nb.s, 16);
     NALLOC(nb.partials, 8192);
     NALLOC(nb.scal, 4);
@@ -978,7 +989,7 @@ int jfnk_net_init(jfnk_ctx* c, const int32_t* dilations, int64_t* n_params) {
     NALLOC(nb.z, (long long)c->nf * npts);
     NALLOC(nb.g0, 16 * npts);
     NALLOC(nb.g1, 16 * npts);
-    NALLOC(nb.wpart, tiles * (16 * 16 * 9 + 16));
+    NALLOC(nb.wpart, tiles * (16 * 16 * taps + 16));
     NALLOC(nb.abf, 2 * 16 * npts);
 #undef NALLOC
     JFNK_HIP(hipMemsetAsync(nb.theta, 0, np * sizeof(float), c->stream));
@@ -987,6 +998,10 @@ int jfnk_net_init(jfnk_ctx* c, const int32_t* dilations, int64_t* n_params) {
     JFNK_HIP(hipStreamSynchronize(c->stream));
     nb.adam_t = 0;
     return JFNK_OK;
+}
+
+static hipError_t net_prep(jfnk_ctx* c) {
+    return c->net.dim == 3 ? net3_prep_weights(c->net, c->nf, c->stream) : net_prep_weights(c->net, c->nf, c->stream);
 }
 
 static bool net_ok(jfnk_ctx* c) {
@@ -1006,7 +1021,7 @@ int jfnk_net_set_params(jfnk_ctx* c, const float* theta, int64_t n) {
     JFNK_HIP(hipMemsetAsync(c->net.m, 0, n * sizeof(float), c->stream));
     JFNK_HIP(hipMemsetAsync(c->net.v, 0, n * sizeof(float), c->stream));
     c->net.adam_t = 0;
-    JFNK_HIP(net_prep_weights(c->net, c->nf, c->stream));
+    JFNK_HIP(net_prep(c));
     JFNK_HIP(hipStreamSynchronize(c->stream));
     c->net.ready = true;
     return JFNK_OK;
@@ -1025,15 +1040,23 @@ int jfnk_net_apply(jfnk_ctx* c, int32_t bf16, const float* r, float* z) {
         return JFNK_ERR_ARG;
     }
     TimedLaunch tl(c, KC_NET, 2.0 * c->net.nparam * c->geo.npts);
-    JFNK_HIP(net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), r, z, bf16 != 0, c->stream));
+    JFNK_HIP(net_run(c, r, z, bf16 != 0));
     return JFNK_OK;
 }
 
 static int net_batch_grad(jfnk_ctx* c, const float* r, const float* du, int32_t batch, double* loss) {
     NetBuffers& nb = c->net;
-    for (int b = 0; b < batch; ++b)
-        JFNK_HIP(net_pair_grad(nb, c->geo.nx, c->geo.nz, c->nf, (float)(0.5 * c->prob.dt), r + (long long)b * c->n,
-                               du + (long long)b * c->n, 1.0 / batch, b == 0, c->geo, c->stream));
+    const float hdt = (float)(0.5 * c->prob.dt);
+    for (int b = 0; b < batch; ++b) {
+        const float* rb = r + (long long)b * c->n;
+        const float* db = du + (long long)b * c->n;
+        if (nb.dim == 3)
+            JFNK_HIP(net3_pair_grad(nb, c->geo.nx, c->geo.ny, c->geo.nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0,
+                                    c->stream));
+        else
+            JFNK_HIP(net_pair_grad(nb, c->geo.nx, c->geo.nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0, c->geo,
+                                   c->stream));
+    }
     if (loss) {
         JFNK_HIP(hipMemcpyAsync(loss, nb.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         JFNK_HIP(hipStreamSynchronize(c->stream));
@@ -1046,8 +1069,8 @@ int jfnk_net_set_loss(jfnk_ctx* c, int32_t kind) {
         set_error("invalid argument to jfnk_net_set_loss");
         return JFNK_ERR_ARG;
     }
-    if (kind == JFNK_NET_LOSS_REST_JACOBIAN && c->prob.energy_test) {
-        set_error("the rest-Jacobian loss needs the physical Exner coefficient (energy_test = 0)");
+    if (kind == JFNK_NET_LOSS_REST_JACOBIAN && (c->prob.energy_test || c->prob.dim != 2)) {
+        set_error("the rest-Jacobian loss is available for 2D problems with energy_test = 0");
         return JFNK_ERR_ARG;
     }
     c->net.loss_kind = kind;
@@ -1077,7 +1100,7 @@ int jfnk_net_train_step(jfnk_ctx* c, const float* r, const float* du, int32_t ba
     if (rc) return rc;
     c->net.adam_t++;
     JFNK_HIP(net_adam(c->net, c->net.nparam, c->net.adam_t, lr, c->stream));
-    JFNK_HIP(net_prep_weights(c->net, c->nf, c->stream));
+    JFNK_HIP(net_prep(c));
     return JFNK_OK;
 }
 

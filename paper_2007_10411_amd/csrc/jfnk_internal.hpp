@@ -106,7 +106,7 @@ struct NetBuffers {
     float* m = nullptr;              // Adam moments
     float* v = nullptr;
     float* wt = nullptr;             // transposed, flipped weights (backward data)
-    unsigned short* wbf = nullptr;   // bf16 weights [layer][tap][co][ci], 16 x 16 padded
+    unsigned short* wbf = nullptr;   // bf16 weights [layer][tap][co][ci], 16 x 16 padded (9 or 27 taps)
     float* s = nullptr;              // per-field scales
     double* partials = nullptr;
     double* scal = nullptr;
@@ -123,6 +123,7 @@ struct NetBuffers {
     int adam_t = 0;
     int dil[4] = {1, 1, 1, 1};       // per-layer dilation of the 3x3 kernels
     int loss_kind = 0;               // NET_LOSS_SOLUTION or NET_LOSS_REST_JACOBIAN
+    int dim = 2;                     // 2: 3x3 kernels, 3: 3x3x3 kernels
     bool ready = false;              // parameters set
 };
 enum { NET_LOSS_SOLUTION = 0, NET_LOSS_REST_JACOBIAN = 1 };
@@ -134,6 +135,19 @@ hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt
 hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
                          const float* du, double inv_batch, bool first_pair, const Geo& geo, hipStream_t st);
 hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st);
+hipError_t net_field_scale(const float* r, long long np, int nf, double* partials, float* s, hipStream_t st);
+hipError_t net_solution_loss(const NetBuffers& nb, long long np, int nf, const float* du, double inv_batch,
+                             bool first_pair, hipStream_t st);
+hipError_t net_cast_scaled(const float* r, long long np, int nf, const float* s, float* out, hipStream_t st);
+hipError_t net_wgrad_finish(const float* partials, int nblk, int cnt, float* grad, bool accumulate, hipStream_t st);
+// 3D network (3 x 3 x 3 kernels, dilation 1)
+int net3_param_count(int nf);
+long long net3_wgrad_tiles(int nx, int ny, int nz);
+hipError_t net3_prep_weights(const NetBuffers& nb, int nf, hipStream_t s);
+hipError_t net3_apply(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r, float* z,
+                      bool bf16, hipStream_t st);
+hipError_t net3_pair_grad(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r,
+                          const float* du, double inv_batch, bool first_pair, hipStream_t st);
 
 }  // namespace jfnk
 

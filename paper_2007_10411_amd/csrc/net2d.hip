@@ -457,8 +457,7 @@ hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t net_field_scale(const float* r, int nx, int nz, int nf, double* partials, float* s, hipStream_t st) {
-    const long long np = (long long)nx * nz;
+hipError_t net_field_scale(const float* r, long long np, int nf, double* partials, float* s, hipStream_t st) {
     int nblk = (int)std::min<long long>(512, (np + 1023) / 1024);
     if (nblk < 1) nblk = 1;
     hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, nf), dim3(256), 0, st, r, np, partials);
@@ -473,7 +472,7 @@ hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt
                      bool bf16, hipStream_t st) {
     NetLayer L[4];
     layers_of(nf, L);
-    hipError_t e = net_field_scale(r, nx, nz, nf, nb.partials, nb.s, st);
+    hipError_t e = net_field_scale(r, (long long)nx * nz, nf, nb.partials, nb.s, st);
     if (e != hipSuccess) return e;
     const dim3 grid = tiles(nx, nz);
     const long long np = (long long)nx * nz;
@@ -519,7 +518,7 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
     layers_of(nf, L);
     const long long np = (long long)nx * nz;
     const dim3 grid = tiles(nx, nz);
-    hipError_t e = net_field_scale(r, nx, nz, nf, nb.partials, nb.s, st);
+    hipError_t e = net_field_scale(r, (long long)nx * nz, nf, nb.partials, nb.s, st);
     if (e != hipSuccess) return e;
     // forward, keeping pre-activations h_l and post-activations a_l
     float* act[4];
@@ -558,18 +557,7 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
                            (const double*)nb.scal, inv_batch);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
-        // ||du||^2, then g = dL/d(network output) and the loss
-        const long long n = np * nf;
-        int nblk = (int)std::min<long long>(1024, (n + 1023) / 1024);
-        hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, 1), dim3(256), 0, st, du, n, nb.partials);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_reduce_partials(nb.partials, nblk, 1, 1, nb.scal, 0, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_loss_grad, dim3(nblk), dim3(256), 0, st, nb.z, du, np, nf, nb.s, nb.scal, inv_batch,
-                           nb.g0, nb.partials + 4096);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_reduce_partials(nb.partials + 4096, nblk, 1, 1, nb.loss, first_pair ? 0 : 1, st)) !=
-            hipSuccess)
-            return e;
+        if ((e = net_solution_loss(nb, np, nf, du, inv_batch, first_pair, st)) != hipSuccess) return e;
     }
     // backward through the layers
     float* g = nb.g0;
@@ -579,17 +567,15 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
         const float* a_in = l == 0 ? nb.a0 : act[l - 1];
         if (l == 0) {
             // the scaled input r / s of the first layer
-            hipLaunchKernelGGL(k_cast_scaled_input, dim3((unsigned)((np * nf + 255) / 256)), dim3(256), 0, st, r,
-                               np, nf, nb.s, nb.a0);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = net_cast_scaled(r, np, nf, nb.s, nb.a0, st)) != hipSuccess) return e;
         }
         const int nw = L[l].cout * L[l].cin * 9;
         hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout, a_in, L[l].cin,
                            nb.wpart, nw, nb.dil[l]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_wgrad_finish, dim3((nw + L[l].cout + 255) / 256), dim3(256), 0, st,
-                           (const float*)nb.wpart, nt, nw + L[l].cout, nb.grad + L[l].woff, first_pair ? 0 : 1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = net_wgrad_finish(nb.wpart, nt, nw + L[l].cout, nb.grad + L[l].woff, !first_pair, st)) !=
+            hipSuccess)
+            return e;
         if (l > 0) {
             // g_in = conv(g, W transposed and flipped) * gelu'(h_{l-1})
             hipLaunchKernelGGL((k_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, nz, (const float*)g, L[l].cout,
@@ -600,6 +586,33 @@ hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float hal
         }
     }
     return hipSuccess;
+}
+
+// g0 = dL/d(network output) and the loss for the solution-space norm, from nb.z
+hipError_t net_solution_loss(const NetBuffers& nb, long long np, int nf, const float* du, double inv_batch,
+                             bool first_pair, hipStream_t st) {
+    const long long n = np * nf;
+    const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, (n + 1023) / 1024));
+    hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, 1), dim3(256), 0, st, du, n, nb.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_reduce_partials(nb.partials, nblk, 1, 1, nb.scal, 0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_grad, dim3(nblk), dim3(256), 0, st, nb.z, du, np, nf, nb.s, nb.scal, inv_batch, nb.g0,
+                       nb.partials + 4096);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_reduce_partials(nb.partials + 4096, nblk, 1, 1, nb.loss, first_pair ? 0 : 1, st);
+}
+
+hipError_t net_cast_scaled(const float* r, long long np, int nf, const float* s, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_scaled_input, dim3((unsigned)((np * nf + 255) / 256)), dim3(256), 0, st, r, np, nf, s,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t net_wgrad_finish(const float* partials, int nblk, int cnt, float* grad, bool accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_wgrad_finish, dim3((cnt + 255) / 256), dim3(256), 0, st, partials, nblk, cnt, grad,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st) {

@@ -1,0 +1,390 @@
+// Learned right preconditioner for 3D problems: the network of the 2D path with
+// 3 x 3 x 3 kernels (taps at (-1, 0, 1) along z, y and x, dilation 1):
+//     z = (dt/2) r + s N(r / s),     s = RMS of r over all fields (1 if r = 0),
+//     N = conv(nf->16) GELU conv(16->16) GELU conv(16->16) GELU conv(16->nf),
+// zero padding, exact erf GELU.  Inference runs in BF16 on MFMA
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one tap per instruction, 27
+// per 16-point subtile); training (forward, backward, Adam) runs in FP32.
+//
+// Activations are channel-major [c][nz][ny][nx] like the state vectors.
+// Parameters: one flat FP32 vector, per layer W[co][ci][kz][ky][kx] then b[co].
+
+#include "jfnk_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace jfnk {
+
+namespace {
+
+constexpr int kHid = 16;
+constexpr int kTaps = 27;
+constexpr int kTX = 64, kTY = 4;      // output points per 256-thread block (one z plane)
+constexpr int kWZ = 4;                // z planes per weight-gradient block
+constexpr int kSX = kTX + 2, kSY = kTY + 2, kSZ = 3;
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.3989422804014327f;
+}
+
+enum { L_FIRST = 0, L_MID = 1, L_LAST = 2 };
+
+__device__ __forceinline__ void tap_offsets(int t, int& dz, int& dy, int& dx) {
+    dz = t / 9 - 1;
+    dy = (t / 3) % 3 - 1;
+    dx = t % 3 - 1;
+}
+
+// FP32 convolution, one thread per point, taps read through the caches
+// FIRST: in = r / s;  MID: in = act;  LAST: z = (dt/2) r + s (out_pre)
+// post = GELU(out_pre), or with gmul out_pre * gelu'(gmul) (backward data)
+template <int MODE>
+__global__ __launch_bounds__(256) void k3_conv_f32(int nx, int ny, int nz, const float* __restrict__ in, int cin,
+                                                   const float* __restrict__ W, const float* __restrict__ b, int cout,
+                                                   float* __restrict__ pre, float* __restrict__ post,
+                                                   const float* __restrict__ r, const float* __restrict__ s,
+                                                   float half_dt, float* __restrict__ z,
+                                                   const float* __restrict__ gmul) {
+    __shared__ float sw[kHid * kHid * kTaps];
+    __shared__ float sb[kHid];
+    const long long np = (long long)nx * ny * nz;
+    for (int i = threadIdx.x; i < cout * cin * kTaps; i += 256) sw[i] = W[i];
+    for (int i = threadIdx.x; i < cout; i += 256) sb[i] = b ? b[i] : 0.0f;
+    __syncthreads();
+    const int gx = blockIdx.x * kTX + (threadIdx.x & 63);
+    const int gy = blockIdx.y * kTY + (threadIdx.x >> 6);
+    const int gz = blockIdx.z;
+    if (gx >= nx || gy >= ny) return;
+    float acc[kHid];
+#pragma unroll
+    for (int co = 0; co < kHid; ++co) acc[co] = co < cout ? sb[co] : 0.0f;
+    for (int ci = 0; ci < cin; ++ci) {
+        const float inv_s = (MODE == L_FIRST) ? 1.0f / s[ci] : 1.0f;
+        float xv[kTaps];
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            int dz, dy, dx;
+            tap_offsets(t, dz, dy, dx);
+            const int xx = gx + dx, yy = gy + dy, zz = gz + dz;
+            float v = 0.0f;
+            if (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
+                const long long o = (long long)ci * np + ((long long)zz * ny + yy) * nx + xx;
+                v = (MODE == L_FIRST) ? r[o] * inv_s : in[o];
+            }
+            xv[t] = v;
+        }
+#pragma unroll
+        for (int co = 0; co < kHid; ++co) {
+            if (co < cout) {
+                const float* w = sw + (co * cin + ci) * kTaps;
+                float a = acc[co];
+#pragma unroll
+                for (int t = 0; t < kTaps; ++t) a += w[t] * xv[t];
+                acc[co] = a;
+            }
+        }
+    }
+    const long long o = ((long long)gz * ny + gy) * nx + gx;
+#pragma unroll
+    for (int co = 0; co < kHid; ++co) {
+        if (co >= cout) continue;
+        const float h = acc[co];
+        if (pre) pre[co * np + o] = h;
+        if (MODE == L_LAST) {
+            if (z) z[co * np + o] = half_dt * r[co * np + o] + s[co] * h;
+        } else if (post) {
+            post[co * np + o] = gmul ? h * gelu_grad(gmul[co * np + o]) : gelu(h);
+        }
+    }
+}
+
+// BF16 MFMA convolution for inference.  Block: 64 x 4 points of one z plane,
+// wavefront w computes row y0 + w as four 16-point subtiles; the input (3 x 6 x
+// 66 points, 16 channels, channel innermost) is staged in LDS once.
+template <int MODE>
+__global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, const unsigned short* __restrict__ in,
+                                                    int cin, const unsigned short* __restrict__ Wf,
+                                                    const float* __restrict__ b, int cout,
+                                                    unsigned short* __restrict__ post, const float* __restrict__ r,
+                                                    const float* __restrict__ s, float half_dt,
+                                                    float* __restrict__ z) {
+    __shared__ unsigned short sin_[kSZ][kSY][kSX][kHid];
+    const long long np = (long long)nx * ny * nz;
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, gz = blockIdx.z;
+    constexpr int plane = kSZ * kSY * kSX;
+    for (int idx = threadIdx.x; idx < kHid * plane; idx += 256) {
+        const int c = idx / plane, rem = idx - c * plane;
+        const int lz = rem / (kSY * kSX), rem2 = rem - lz * (kSY * kSX);
+        const int ly = rem2 / kSX, lx = rem2 - ly * kSX;
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
+        unsigned short v = 0;
+        if (c < cin && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz) {
+            const long long o = (long long)c * np + ((long long)zz * ny + gy) * nx + gx;
+            v = (MODE == L_FIRST) ? f2bf(r[o] / s[c]) : in[o];
+        }
+        sin_[lz][ly][lx][c] = v;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    bf16x4_t bfrag[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+        const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
+        bfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
+    }
+    const float bias = col < cout ? b[col] : 0.0f;
+    __syncthreads();
+    const int gy = y0 + wv;
+    if (gy >= ny) return;
+#pragma unroll
+    for (int st = 0; st < kTX / 16; ++st) {
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int px = st * 16 + col;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const unsigned short* ap = &sin_[dz][wv + dy][px + dx][4 * kg];
+            const bf16x4_t a = bf16x4_t{(short)ap[0], (short)ap[1], (short)ap[2], (short)ap[3]};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
+        }
+        if (col >= cout) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gx = x0 + st * 16 + 4 * kg + i;
+            if (gx >= nx) continue;
+            const long long o = (long long)col * np + ((long long)gz * ny + gy) * nx + gx;
+            const float h = acc[i] + bias;
+            if (MODE == L_LAST)
+                z[o] = half_dt * r[o] + s[col] * h;
+            else
+                post[o] = f2bf(gelu(h));
+        }
+    }
+}
+
+// dW[co][ci][t] and db[co] partial sums over a 64 x 4 x kWZ block of points:
+// per z plane the output gradient is staged once, the input one channel at a
+// time (3 x 6 x 66 points); sums collect in LDS, one slot per thread.
+__global__ __launch_bounds__(256) void k3_conv_wgrad(int nx, int ny, int nz, const float* __restrict__ g, int cout,
+                                                     const float* __restrict__ a, int cin,
+                                                     float* __restrict__ partials, int nw) {
+    __shared__ float sg[kHid][kTY][kTX];
+    __shared__ float sa[kSZ][kSY][kSX];
+    __shared__ float sp[kHid * kHid * kTaps + kHid];
+    const long long np = (long long)nx * ny * nz;
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kWZ;
+    const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    for (int k = threadIdx.x; k < nw + cout; k += 256) sp[k] = 0.0f;
+    for (int pz = 0; pz < kWZ; ++pz) {
+        const int gz = z0 + pz;
+        if (gz >= nz) break;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cout * kTY * kTX; idx += 256) {
+            const int c = idx / (kTY * kTX), rem = idx - c * (kTY * kTX);
+            const int ly = rem / kTX, lx = rem - ly * kTX;
+            const int gx = x0 + lx, gy = y0 + ly;
+            sg[c][ly][lx] = (gx < nx && gy < ny) ? g[(long long)c * np + ((long long)gz * ny + gy) * nx + gx] : 0.0f;
+        }
+        __syncthreads();
+        if (threadIdx.x < cout) {
+            float acc = 0.0f;
+            for (int ly = 0; ly < kTY; ++ly)
+                for (int lx = 0; lx < kTX; ++lx) acc += sg[threadIdx.x][ly][lx];
+            sp[nw + threadIdx.x] += acc;
+        }
+        for (int ci = 0; ci < cin; ++ci) {
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < kSZ * kSY * kSX; idx += 256) {
+                const int lz = idx / (kSY * kSX), rem = idx - lz * (kSY * kSX);
+                const int ly = rem / kSX, lx = rem - ly * kSX;
+                const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
+                sa[lz][ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz)
+                                     ? a[(long long)ci * np + ((long long)zz * ny + gy) * nx + gx]
+                                     : 0.0f;
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < cout * kTaps; k += 256) {
+                const int co = k / kTaps, t = k - co * kTaps;
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                float acc = 0.0f;
+                for (int ly = 0; ly < kTY; ++ly)
+                    for (int lx = 0; lx < kTX; ++lx) acc += sg[co][ly][lx] * sa[dz][ly + dy][lx + dx];
+                sp[(co * cin + ci) * kTaps + t] += acc;
+            }
+        }
+    }
+    __syncthreads();
+    float* out = partials + blk * (nw + cout);
+    for (int k = threadIdx.x; k < nw + cout; k += 256) out[k] = sp[k];
+}
+
+// Wt[ci][co][26 - t] = W[co][ci][t] (transposed, flipped: backward data) and
+// the padded bf16 inference weights Wf[t][co][ci]
+__global__ void k3_prep_weights(const float* __restrict__ W, int cout, int cin, float* __restrict__ Wt,
+                                unsigned short* __restrict__ Wf) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cout * cin * kTaps) {
+        const int co = k / (cin * kTaps), rem = k - co * (cin * kTaps);
+        const int ci = rem / kTaps, t = rem - ci * kTaps;
+        Wt[(ci * cout + co) * kTaps + (kTaps - 1 - t)] = W[k];
+    }
+    if (k < kTaps * kHid * kHid) {
+        const int t = k / (kHid * kHid), rem = k - t * (kHid * kHid);
+        const int co = rem / kHid, ci = rem - co * kHid;
+        Wf[k] = (co < cout && ci < cin) ? f2bf(W[(co * cin + ci) * kTaps + t]) : (unsigned short)0;
+    }
+}
+
+struct Layer3 {
+    int cin, cout, woff, boff;
+};
+
+void layers3(int nf, Layer3 L[4]) {
+    const int ch[5] = {nf, kHid, kHid, kHid, nf};
+    int o = 0;
+    for (int l = 0; l < 4; ++l) {
+        L[l].cin = ch[l];
+        L[l].cout = ch[l + 1];
+        L[l].woff = o;
+        o += ch[l + 1] * ch[l] * kTaps;
+        L[l].boff = o;
+        o += ch[l + 1];
+    }
+}
+
+dim3 grid3(int nx, int ny, int nz) { return dim3((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, nz); }
+
+}  // namespace
+
+int net3_param_count(int nf) {
+    Layer3 L[4];
+    layers3(nf, L);
+    return L[3].boff + L[3].cout;
+}
+
+long long net3_wgrad_tiles(int nx, int ny, int nz) {
+    return (long long)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kWZ - 1) / kWZ);
+}
+
+hipError_t net3_prep_weights(const NetBuffers& nb, int nf, hipStream_t s) {
+    Layer3 L[4];
+    layers3(nf, L);
+    for (int l = 0; l < 4; ++l) {
+        hipLaunchKernelGGL(k3_prep_weights, dim3((kTaps * kHid * kHid + 255) / 256), dim3(256), 0, s,
+                           nb.theta + L[l].woff, L[l].cout, L[l].cin, nb.wt + L[l].woff,
+                           nb.wbf + l * kTaps * kHid * kHid);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t net3_apply(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r, float* z,
+                      bool bf16, hipStream_t st) {
+    Layer3 L[4];
+    layers3(nf, L);
+    const long long np = (long long)nx * ny * nz;
+    const dim3 grid = grid3(nx, ny, nz);
+    hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
+    if (bf16) {
+        unsigned short* a0 = nb.abf;
+        unsigned short* a1 = nb.abf + kHid * np;
+        const int wl = kTaps * kHid * kHid;
+        hipLaunchKernelGGL((k3_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz,
+                           (const unsigned short*)nullptr, L[0].cin, nb.wbf + 0 * wl, nb.theta + L[0].boff, L[0].cout,
+                           a0, r, nb.s, half_dt, (float*)nullptr);
+        hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
+                           L[1].cin, nb.wbf + 1 * wl, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
+                           (float*)nullptr);
+        hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a1,
+                           L[2].cin, nb.wbf + 2 * wl, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
+                           (float*)nullptr);
+        hipLaunchKernelGGL((k3_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
+                           L[3].cin, nb.wbf + 3 * wl, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
+                           nb.s, half_dt, z);
+        return hipGetLastError();
+    }
+    float* a0 = nb.act;
+    float* a1 = nb.act + kHid * np;
+    hipLaunchKernelGGL((k3_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)nullptr, L[0].cin,
+                       nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, (float*)nullptr, a0, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k3_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)a0, L[1].cin,
+                       nb.theta + L[1].woff, nb.theta + L[1].boff, L[1].cout, (float*)nullptr, a1, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k3_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)a1, L[2].cin,
+                       nb.theta + L[2].woff, nb.theta + L[2].boff, L[2].cout, (float*)nullptr, a0, r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k3_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)a0, L[3].cin,
+                       nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, (float*)nullptr, (float*)nullptr, r,
+                       nb.s, half_dt, z, (const float*)nullptr);
+    return hipGetLastError();
+}
+
+// Loss of one pair (solution-space norm) and its gradient, added into nb.grad
+// unless first_pair.
+hipError_t net3_pair_grad(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r,
+                          const float* du, double inv_batch, bool first_pair, hipStream_t st) {
+    Layer3 L[4];
+    layers3(nf, L);
+    const long long np = (long long)nx * ny * nz;
+    const dim3 grid = grid3(nx, ny, nz);
+    hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
+    float* act[4];
+    float* pre[4];
+    for (int l = 0; l < 4; ++l) {
+        act[l] = nb.act + (long long)l * kHid * np;
+        pre[l] = nb.pre + (long long)l * kHid * np;
+    }
+    hipLaunchKernelGGL((k3_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)nullptr, L[0].cin,
+                       nb.theta + L[0].woff, nb.theta + L[0].boff, L[0].cout, pre[0], act[0], r, nb.s, half_dt,
+                       (float*)nullptr, (const float*)nullptr);
+    for (int l = 1; l < 3; ++l)
+        hipLaunchKernelGGL((k3_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)act[l - 1],
+                           L[l].cin, nb.theta + L[l].woff, nb.theta + L[l].boff, L[l].cout, pre[l], act[l], r, nb.s,
+                           half_dt, (float*)nullptr, (const float*)nullptr);
+    hipLaunchKernelGGL((k3_conv_f32<L_LAST>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)act[2], L[3].cin,
+                       nb.theta + L[3].woff, nb.theta + L[3].boff, L[3].cout, pre[3], (float*)nullptr, r, nb.s,
+                       half_dt, nb.z, (const float*)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = net_solution_loss(nb, np, nf, du, inv_batch, first_pair, st)) != hipSuccess) return e;
+    float* g = nb.g0;
+    float* gnext = nb.g1;
+    const dim3 wgrid((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, (nz + kWZ - 1) / kWZ);
+    const int nt = (int)net3_wgrad_tiles(nx, ny, nz);
+    for (int l = 3; l >= 0; --l) {
+        const float* a_in = l == 0 ? nb.a0 : act[l - 1];
+        if (l == 0 && (e = net_cast_scaled(r, np, nf, nb.s, nb.a0, st)) != hipSuccess) return e;
+        const int nw = L[l].cout * L[l].cin * kTaps;
+        hipLaunchKernelGGL(k3_conv_wgrad, wgrid, dim3(256), 0, st, nx, ny, nz, (const float*)g, L[l].cout, a_in,
+                           L[l].cin, nb.wpart, nw);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = net_wgrad_finish(nb.wpart, nt, nw + L[l].cout, nb.grad + L[l].woff, !first_pair, st)) != hipSuccess)
+            return e;
+        if (l > 0) {
+            // g_in = conv(g, W transposed and flipped) * gelu'(h_{l-1})
+            hipLaunchKernelGGL((k3_conv_f32<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)g, L[l].cout,
+                               nb.wt + L[l].woff, (const float*)nullptr, L[l].cin, (float*)nullptr, gnext, r, nb.s,
+                               half_dt, (float*)nullptr, (const float*)pre[l - 1]);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            std::swap(g, gnext);
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace jfnk

@@ -251,20 +251,21 @@ def random_smooth_vector(prob: Problem, seed=2) -> np.ndarray:
 NET_HIDDEN = 16
 
 
-def net_layer_shapes(nf: int):
-    """(W shape, b shape) per layer of the 4-layer 3x3 network nf->16->16->16->nf."""
+def net_layer_shapes(nf: int, dim: int = 2):
+    """(W shape, b shape) per layer of the 4-layer network nf->16->16->16->nf
+    (3 x 3 kernels in 2D, 3 x 3 x 3 in 3D)."""
     ch = [nf, NET_HIDDEN, NET_HIDDEN, NET_HIDDEN, nf]
-    return [((ch[l + 1], ch[l], 3, 3), (ch[l + 1],)) for l in range(4)]
+    return [((ch[l + 1], ch[l]) + (3,) * dim, (ch[l + 1],)) for l in range(4)]
 
 
-def net_init_params(nf: int, seed: int = 0, out_scale: float = 0.1) -> np.ndarray:
+def net_init_params(nf: int, seed: int = 0, out_scale: float = 0.1, dim: int = 2) -> np.ndarray:
     """Seeded He-normal initial weights, zero biases, last layer scaled by
-    out_scale; one flat float64 vector (per layer W[co][ci][kz][kx], then b)."""
+    out_scale; one flat float64 vector (per layer W[co][ci][taps], then b)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
-    shapes = net_layer_shapes(nf)
+    shapes = net_layer_shapes(nf, dim)
     for l, (ws, bs) in enumerate(shapes):
-        W = rng.normal(scale=math.sqrt(2.0 / (ws[1] * 9)), size=ws)
+        W = rng.normal(scale=math.sqrt(2.0 / (ws[1] * 3 ** dim)), size=ws)
         if l == len(shapes) - 1:
             W = W * out_scale
         parts += [W.ravel(), np.zeros(bs)]

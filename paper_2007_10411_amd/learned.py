@@ -86,7 +86,7 @@ def train_mixed(ctx, R, DU, u, iters=2000, lr=2e-3, batch=8, seed=0, theta0=None
     nf = ctx.prob.nf
     ctx.net_init(dilations)
     ctx.net_set_loss(loss)
-    theta = I.net_init_params(nf, seed=seed) if theta0 is None else np.asarray(theta0)
+    theta = I.net_init_params(nf, seed=seed, dim=ctx.prob.dim) if theta0 is None else np.asarray(theta0)
     ctx.net_set_params(theta.astype(np.float32))
     noise = NoisePairs(ctx, u, field_rms(DU, nf), seed=seed + 1)
     rng = np.random.Generator(np.random.PCG64(seed + 17))
@@ -108,7 +108,7 @@ def train(ctx, R, DU, iters, lr=2e-3, batch=4, seed=0, theta0=None, lr_decay=Tru
     import torch
     nf = ctx.prob.nf
     ctx.net_init(dilations)
-    theta = I.net_init_params(nf, seed=seed) if theta0 is None else np.asarray(theta0)
+    theta = I.net_init_params(nf, seed=seed, dim=ctx.prob.dim) if theta0 is None else np.asarray(theta0)
     ctx.net_set_params(theta.astype(np.float32))
     rng = np.random.Generator(np.random.PCG64(seed + 17))
     npairs = R.shape[0]

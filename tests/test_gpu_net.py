@@ -196,3 +196,93 @@ def test_trained_network_beats_untrained_form():
           f"held-out loss {held:.3e} (N=0 {held0:.3e}), train loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
     assert it_trained < it_zero
     assert it_trained < it_phys
+
+
+# ---- 3D network (3 x 3 x 3 kernels) ---------------------------------------- #
+def _r3(prob, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = rng.normal(size=prob.shape) * np.array([1.0, 0.7, 0.5, 1e-3, 2.0])[:, None, None, None]
+    return r.astype(np.float32).astype(np.float64)
+
+
+def _theta3(nf, seed=1):
+    th = I.net_init_params(nf, seed=seed, out_scale=1.0, dim=3)
+    th = th + np.random.Generator(np.random.PCG64(seed + 50)).normal(scale=0.05, size=th.size)
+    return th.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(70, 9, 8), (64, 8, 8), (17, 10, 9)])
+def test_net3d_forward_f32_and_bf16(nx, ny, nz):
+    prob = I.thermal_neutral_3d(nx, ny, nz)
+    c = _ctx(prob)
+    th = _theta3(prob.nf)
+    c.net_set_params(th)
+    r = _r3(prob, 2)
+    ref = N.forward(th, r, prob.dt)
+    netpart = ref - 0.5 * prob.dt * r
+    z = dev(np.zeros(prob.shape), "f32")
+    for bf16, tol in [(False, 1e-5), (True, 3e-2)]:
+        c.net_apply(dev(r, "f32"), z, bf16=bf16)
+        gp = host(z) - 0.5 * prob.dt * r
+        for k in range(prob.nf):
+            e = np.linalg.norm(gp[k] - netpart[k]) / np.linalg.norm(netpart[k])
+            assert e < tol, (bf16, k, e)
+
+
+def test_net3d_loss_gradient_matches_oracle():
+    prob = I.thermal_neutral_3d(40, 9, 8)
+    c = _ctx(prob)
+    th = _theta3(prob.nf, seed=3)
+    c.net_set_params(th)
+    R = [_r3(prob, 4), _r3(prob, 5)]
+    DU = [_r3(prob, 6), _r3(prob, 7)]
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    lg, gg = c.net_loss_grad(dev(np.stack(R), "f32"), dev(np.stack(DU), "f32"))
+    assert abs(lg - lo) <= 1e-5 * lo
+    o = 0
+    for ws, bs in I.net_layer_shapes(prob.nf, 3):
+        nw = int(np.prod(ws)) + int(np.prod(bs))
+        sl = slice(o, o + nw)
+        assert np.linalg.norm(gg[sl] - go[sl]) <= 1e-4 * np.linalg.norm(go[sl])
+        o += nw
+
+
+def test_net3d_rejects_dilation_and_rest_jacobian_loss():
+    from paper_2007_10411_amd._lib import JfnkError
+    from paper_2007_10411_amd.jfnk import Context
+    c = Context(I.thermal_neutral_3d(16, 8, 8))
+    with pytest.raises(JfnkError):
+        c.net_init((1, 2, 1, 1))
+    c.net_init()
+    with pytest.raises(JfnkError):
+        c.net_set_loss("rest_jacobian")
+
+
+def test_trained_network_3d_beats_untrained_form():
+    """3D thermal on a coarse grid: the trained 3x3x3 network needs fewer Krylov
+    iterations per step than its untrained form z = (dt/2) r."""
+    from paper_2007_10411_amd import learned as LRN
+    prob = I.thermal_neutral_3d(48, 48, 24)
+    c = _ctx(prob)
+    u0 = dev(I.bubble_state(prob))
+    R, DU, u_end = LRN.collect_pairs(c, u0, steps=3, cap=96)
+    assert R.shape[0] >= 32
+    theta, losses = LRN.train_mixed(c, R, DU, u_end, iters=600, lr=2e-3, batch=4, dilations=(1, 1, 1, 1))
+    zero = np.zeros(c.n_params, dtype=np.float32)
+
+    def iters(params):
+        c.net_set_params(params)
+        u = u_end.clone()
+        tot = 0
+        for _ in range(2):
+            nxt = u.clone()
+            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4)
+            assert res.converged and res.fallbacks == 0
+            tot += res.gmres_iters_total
+            u.copy_(nxt)
+        return tot
+
+    it_zero, it_trained = iters(zero), iters(theta)
+    print(f"3D GMRES iterations over 2 steps: N=0 {it_zero}, trained {it_trained}; "
+          f"train loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
+    assert it_trained < it_zero

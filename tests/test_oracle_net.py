@@ -115,3 +115,55 @@ def test_first_adam_step_is_lr_times_sign():
     g = rng.normal(size=50)
     new, m, v = N.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3)
     assert np.allclose(th - new, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# ---- 3D network (3 x 3 x 3 kernels) ---------------------------------------- #
+def test_param_layout_3d():
+    nf = 5
+    th = I.net_init_params(nf, seed=3, dim=3)
+    assert th.size == N.param_count(nf, 3) == (5 * 16 + 16 * 16 * 2 + 16 * 5) * 27 + 16 * 3 + 5
+    assert [W.shape for W, _ in N.unpack(th, nf, 3)] == [s[0] for s in I.net_layer_shapes(nf, 3)]
+
+
+def test_conv3d_equals_scipy_correlate_with_zero_padding():
+    from scipy.signal import correlate
+    rng = np.random.Generator(np.random.PCG64(21))
+    x = rng.normal(size=(3, 5, 6, 7))
+    W = rng.normal(size=(4, 3, 3, 3, 3))
+    b = rng.normal(size=4)
+    out = N.conv(x, W, b)
+    for co in range(4):
+        ref = b[co] + sum(correlate(x[ci], W[co, ci], mode="same") for ci in range(3))
+        assert np.allclose(out[co], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_conv3d_transpose_adjoint_identity():
+    rng = np.random.Generator(np.random.PCG64(22))
+    x = rng.normal(size=(3, 4, 5, 6))
+    W = rng.normal(size=(2, 3, 3, 3, 3))
+    g = rng.normal(size=(2, 4, 5, 6))
+    lhs = float(np.sum(N.conv(x, W, np.zeros(2)) * g))
+    rhs = float(np.sum(x * N.conv_grad_input(g, W, x.shape)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_loss_gradient_3d_matches_central_differences():
+    from paper_2007_10411_amd.inputs import thermal_neutral_3d
+    prob = thermal_neutral_3d(6, 5, 4)
+    nf = prob.nf
+    rng = np.random.Generator(np.random.PCG64(23))
+    th = I.net_init_params(nf, seed=4, out_scale=1.0, dim=3) + rng.normal(scale=0.05, size=N.param_count(nf, 3))
+    R = [rng.normal(size=prob.shape)]
+    DU = [rng.normal(size=prob.shape)]
+    lo, go = N.loss_and_grad(th, R, DU, prob.dt)
+    o = 0
+    for ws, bs in N.param_shapes(nf, 3):          # one weight and one bias of every layer
+        nw = int(np.prod(ws))
+        for idx in (o + int(rng.integers(nw)), o + nw + int(rng.integers(bs[0]))):
+            h = 1e-6
+            tp, tm = th.copy(), th.copy()
+            tp[idx] += h
+            tm[idx] -= h
+            fd = (N.loss_and_grad(tp, R, DU, prob.dt)[0] - N.loss_and_grad(tm, R, DU, prob.dt)[0]) / (2 * h)
+            assert abs(fd - go[idx]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(go).max()), (idx, fd, go[idx])
+        o += nw + bs[0]
