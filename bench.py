@@ -23,14 +23,21 @@ Printed JSON line:
                  roofline_jv for the Jv kernel, roofline_net for the network
   cpu_baseline   the FP64 oracle on a bounded sample of the same workload
 
+kernel_micro   the residual and Jv kernels alone on grids whose vectors exceed the
+               256 MB Infinity Cache (2D 8192 x 8192, 3D 256 x 256 x 128), FP32
+               and FP64: per-launch HIP-event time, algorithmic bytes (read u and
+               v or f, write the result: 3 n_f w per point) and the HBM fraction
+
 --copy-probe GIB runs only a device-to-device copy of GIB GiB (the calibration
 kernel for the hardware byte counters) and prints its size and time.
+--micro-only runs only the kernel micro-benchmark.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -59,6 +66,9 @@ def parse():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--copy-probe", type=float, default=0.0)
+    ap.add_argument("--micro-only", action="store_true")
+    ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--micro-reps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -187,6 +197,78 @@ def copy_probe(gib):
                       "GBps_read_plus_write": 8 * n / ms / 1e6}), flush=True)
 
 
+def synth_state(torch, prob, seed=0):
+    """Timing input on the device: smooth velocities (a few sine modes of a
+    streamfunction in x-z, scaled to 10 m/s), the +2 K bubble and Gaussian
+    pressure noise of standard deviation 0.01."""
+    dev = "cuda"
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    nf, nz, ny, nx = prob.shape
+    x = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * (prob.lx / nx)
+    y = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * (prob.ly / ny)
+    z = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * (prob.lz / nz)
+    Z, Y, X = torch.meshgrid(z, y, x, indexing="ij")
+    U = torch.zeros(prob.shape, dtype=torch.float64, device=dev)
+    amp = torch.randn((4, 4), generator=g, device=dev, dtype=torch.float64)
+    for m in range(1, 5):
+        for n in range(1, 5):
+            a = float(amp[m - 1, n - 1]) / (m * m + n * n)
+            ax, az = m * math.pi / prob.lx, n * math.pi / prob.lz
+            U[0] += -a * az * torch.sin(ax * X) * torch.cos(az * Z)
+            U[prob.dim - 1] += a * ax * torch.cos(ax * X) * torch.sin(az * Z)
+    if prob.dim == 3:
+        U[1] = 0.5 * U[0] * torch.cos(math.pi * Y / prob.ly)
+    vmax = U[:prob.dim].abs().max()
+    U[:prob.dim] *= 10.0 / vmax
+    r = torch.sqrt((X - prob.lx / 2) ** 2 + (Z - 2000.0) ** 2 + ((Y - prob.ly / 2) ** 2 if prob.dim == 3 else 0.0))
+    U[-1] = torch.where(r <= 2000.0, 2.0 * torch.cos(math.pi * r / 4000.0) ** 2, torch.zeros_like(r))
+    U[prob.dim] = 0.01 * torch.randn(U[prob.dim].shape, generator=g, device=dev, dtype=torch.float64)
+    return U.reshape(-1)
+
+
+def kernel_micro(torch, I, L, Context, reps):
+    """Residual and Jv kernels alone at sizes beyond the Infinity Cache."""
+    out = {}
+    cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d())]
+    for name, prob in cases:
+        ctx = Context(prob, max_m=1)
+        u64 = synth_state(torch, prob)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        v64 = torch.randn(prob.n, generator=g, device="cuda", dtype=torch.float64)
+        v64 /= v64.norm()
+        res = {}
+        for dt in ("f32", "f64"):
+            u = u64 if dt == "f64" else u64.float()
+            v = v64 if dt == "f64" else v64.float()
+            f = torch.zeros_like(u)
+            o = torch.empty_like(u)
+            w = u.element_size()
+            for _ in range(3):
+                ctx.jv(u, v, o, mode="stable", eps=1e-3)
+                ctx.apply_F(u, o, what=2, f=f)
+            torch.cuda.synchronize()
+            for kname, call, cls in [("jv", lambda: ctx.jv(u, v, o, mode="stable", eps=1e-3), L.KC_JV),
+                                     ("residual", lambda: ctx.apply_F(u, o, what=2, f=f), L.KC_RESIDUAL)]:
+                ctx.timing(1 << cls)
+                for _ in range(reps):
+                    call()
+                torch.cuda.synchronize()
+                ms, launches, _ = ctx.timing_read(cls)
+                ctx.timing(0)
+                per = ms / launches * 1e3
+                by = 3.0 * prob.n * w
+                gbs = by / (per * 1e-6) / 1e9
+                res[f"{kname}_{dt}"] = {"avg_launch_us": per, "bytes_per_launch": by, "GBps": gbs,
+                                        "frac": gbs / HBM_PEAK_GBS,
+                                        "gpts": prob.npts / (per * 1e-6) / 1e9}
+        out[name] = res
+        del ctx, u64, v64
+        torch.cuda.empty_cache()
+    return out
+
+
 def learned_small(torch, I, LRN, Context, train_iters):
     """Trained network vs the physics preconditioner vs the untrained form on the
     stable thermal at 256 x 128 (two steps each from the same state)."""
@@ -218,6 +300,15 @@ def main():
         sys.exit(2)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.micro_only:
+        import torch
+
+        from paper_2007_10411_amd import _lib as L
+        from paper_2007_10411_amd import inputs as I
+        from paper_2007_10411_amd.jfnk import Context
+        torch.cuda.set_device(0)
+        print(json.dumps({"kernel_micro": kernel_micro(torch, I, L, Context, args.micro_reps)}), flush=True)
         return
     import numpy as np
     import torch
@@ -340,6 +431,19 @@ def main():
     if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
         out["roofline_net"] = roof("learned", "net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)",
                                    "mfma")
+    if not args.no_micro:
+        del legs
+        torch.cuda.empty_cache()
+        log("kernel micro-benchmark (2D 8192x8192, 3D 256x256x128)")
+        micro = kernel_micro(torch, I, L, Context, args.micro_reps)
+        out["kernel_micro"] = micro
+        best = micro["2d_8192x8192"]["jv_f32"]
+        out["roofline_jv_micro"] = {"kernel": "k_jv_2d<float> at 8192x8192 (vectors beyond the Infinity Cache)",
+                                    "bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": best["frac"],
+                                    "traffic": counter_traffic("jv_f32_counters_8192x8192"),
+                                    "bytes_per_launch": best["bytes_per_launch"],
+                                    "avg_launch_us": best["avg_launch_us"]}
     if not args.no_cpu:
         log(f"cpu baseline ({args.cpu_seconds} s)")
         out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds)
