@@ -211,6 +211,27 @@ int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
 int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches,
                      double* bytes);
 
+/* ---- nonlinear physics-based preconditioning (section 2.5.1) ----------------
+ * The preconditioned system R~(u) = u - P^{-1}(u)[f - L(u) + P(u)u], with the
+ * preconditioning operator acting on u inside the bracket, is
+ * R~(u) = P^{-1}(u) R(u): P^{-1}(u) is the physics-based field-block
+ * preconditioner of jfnk_precond_apply with its coefficients frozen at u
+ * (`sweeps` Jacobi sweeps).  Its roots are those of R.  FP64, 2D and 3D.       */
+/* out = R~(u) for the right-hand side f (DEVICE FP64 state vectors; out must not
+ * alias u or f).                                                                */
+int jfnk_nlpc_residual(jfnk_ctx* ctx, const double* u, const double* f, double* out, int32_t sweeps);
+/* One trapezoidal step on the preconditioned system: method 0 the fixed-point
+ * iteration u <- u - R~(u) (at most o->max_newton iterations); method 1 inexact
+ * Newton-GMRES on R~ without further preconditioning, Jacobian-vector products
+ * [R~(u + eps v) - R~(u)]/eps (eps as for jfnk_jv), Eisenstat-Walker forcing on
+ * ||R~|| (o->forcing = 0) or fixed o->eta.  Options used: rtol, atol_factor,
+ * max_newton, forcing, eta, eta_floor, gm.m, gm.max_restarts, gm.sweeps.  Both
+ * stop on the unpreconditioned residual, ||R(u)|| <= max(rtol ||R(u^n)||,
+ * atol_factor ||2u^n/dt||).  u_np1 holds the initial guess on entry.  Returns
+ * JFNK_NOT_CONVERGED (soft) when the iteration limit is reached.                */
+int jfnk_nlpc_step(jfnk_ctx* ctx, const double* u_n, double* u_np1, const jfnk_newton_opts* o, int32_t method,
+                   jfnk_newton_info* info);
+
 /* ---- learned right preconditioner ------------------------------------------
  * z = (dt/2) r + s N(r / s), s the RMS of r over all fields and points (1 for
  * r = 0), N = conv(n_f->16) GELU conv(16->16) GELU conv(16->16) GELU

@@ -676,6 +676,9 @@ __global__ void k_background_batch(Geo g, jfnk_problem p, double* pbar, double* 
         dpbar32[t] = (float)(-p.g / thb);
     }
     if (t < g.nx * g.ny) {
+        // the cell centre is rounded on its own, as the strip definition reads
+        // (no multiply-add fused into the strip test)
+#pragma clang fp contract(off)
         const double x = (t % g.nx + 0.5) * g.dx;
         double H = 0.0;
         if (p.h0 != 0.0 && p.bc_vertical != JFNK_BC_PERIODIC) {

@@ -167,6 +167,9 @@ struct jfnk_ctx {
     // FP64 temporaries
     double* f64 = nullptr;      // f(u^n)
     double* R64 = nullptr;      // residual
+    double* nl64 = nullptr;     // R~(u) of the nonlinear preconditioning (cached for its FD Jacobian)
+    double* nls64 = nullptr;    // preconditioner scratch of the nonlinear preconditioning
+    int nl_sweeps = 2;
     double* t64a = nullptr;
     double* t64b = nullptr;
     double* b64 = nullptr;      // Newton right-hand side -R

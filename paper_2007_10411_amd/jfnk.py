@@ -165,6 +165,29 @@ class Context:
         return NewtonResult(info.newton_iters, info.gmres_iters_total, bool(info.converged), info.res0,
                             info.res_final, info.fallbacks)
 
+    def nlpc_residual(self, u, f, out, sweeps=2):
+        """out = R~(u) = P^{-1}(u) R(u) (FP64)."""
+        self._check_size(u, f, out)
+        L.check(self.lib.jfnk_nlpc_residual(self.h, _ptr(u), _ptr(f), _ptr(out), int(sweeps)),
+                "jfnk_nlpc_residual", soft_ok=False)
+        return out
+
+    def nlpc_step(self, u_n, u_np1, method="newton", rtol=1e-8, atol_factor=1e-13, max_iter=20, m=30,
+                  max_restarts=20, sweeps=2, forcing="ew", eta=1e-2, eta_floor=0.0):
+        """One step on the nonlinearly preconditioned system: method "newton"
+        (Newton-Krylov on R~) or "fixed_point" (u <- u - R~(u))."""
+        self._check_size(u_n, u_np1)
+        gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS["none"], jv=L.JV_STABLE,
+                         sweeps=sweeps, max_iters=0)
+        o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_iter, inner=L.F64, gm=gm,
+                         forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
+        info = L.NewtonInfo()
+        code = {"fixed_point": 0, "newton": 1}[method]
+        L.check(self.lib.jfnk_nlpc_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), code, C.byref(info)),
+                "jfnk_nlpc_step")
+        return NewtonResult(info.newton_iters, info.gmres_iters_total, bool(info.converged), info.res0,
+                            info.res_final, info.fallbacks)
+
     def norm(self, x):
         out = C.c_double()
         L.check(self.lib.jfnk_norm(self.h, _dcode(x), _ptr(x), x.numel(), C.byref(out)), "jfnk_norm",
