@@ -24,7 +24,8 @@ Readings of points the paper leaves open (each also listed in the design notes):
   heat flux q_j = (nu / Pr_t) D_j theta.  Divergences use the same D.
 * Grid: cell centres x_i = (i + 1/2) dx; walls on the faces; fields extended by
   mirror reflection with a parity (wall-normal velocity odd; at a no-slip bottom
-  the tangential velocity is odd too; p, theta even).  Ghost depth 4; derived
+  the tangential velocity is odd too; p, theta even).  Ghost depth twice the
+  stencil's half-width (4 for p = 2, 8 for the 9-point p = 3 stencil); derived
   quantities are formed from the extended primitives and then differentiated.
 * Surface heat flux H(x) enters the first cell as Q / dz with
   Q = H / (rho0 c_p), rho0 = p_ref / (R theta0).
@@ -35,9 +36,17 @@ import math
 
 import numpy as np
 
-from .stencil import deriv
+from .stencil import deriv, stencil
 
-G = 4  # ghost depth: D(2 nu S(u)) reaches 4 points
+
+def half_width(p: int) -> int:
+    """Reach of the derivative stencil of order parameter p (2 for p = 2, 4 for p = 3)."""
+    return len(stencil(p)[0]) // 2
+
+
+def ghost(prob) -> int:
+    """Ghost depth: D(2 nu S(u)) reaches twice the stencil's half-width."""
+    return 2 * half_width(prob.dd_p)
 
 
 # --------------------------------------------------------------------------- #
@@ -103,9 +112,9 @@ def les_width(prob) -> float:
 # --------------------------------------------------------------------------- #
 # ghost extension
 # --------------------------------------------------------------------------- #
-def _axis_map(n, kind, s_lo, s_hi):
-    """Source index and sign of every extended position -G..n+G-1."""
-    e = np.arange(-G, n + G)
+def _axis_map(n, kind, s_lo, s_hi, g=4):
+    """Source index and sign of every extended position -g..n+g-1."""
+    e = np.arange(-g, n + g)
     if kind == 2:                               # periodic
         return e % n, np.ones(e.shape)
     src = e.copy()
@@ -139,10 +148,11 @@ def parities(prob, name):
 def extend(prob, a, name):
     """Ghost-extended copy of one (nz, ny, nx) field; y is not extended in 2D."""
     px, py, pz = parities(prob, name)
-    ix, sx = _axis_map(prob.nx, prob.bc_lateral, *px)
-    iz, sz = _axis_map(prob.nz, prob.bc_vertical, *pz)
+    g = ghost(prob)
+    ix, sx = _axis_map(prob.nx, prob.bc_lateral, *px, g)
+    iz, sz = _axis_map(prob.nz, prob.bc_vertical, *pz, g)
     if prob.dim == 3:
-        iy, sy = _axis_map(prob.ny, prob.bc_lateral, *py)
+        iy, sy = _axis_map(prob.ny, prob.bc_lateral, *py, g)
     else:
         iy, sy = np.arange(prob.ny), np.ones(prob.ny)
     out = a[np.ix_(iz, iy, ix)]
@@ -150,8 +160,9 @@ def extend(prob, a, name):
 
 
 def interior(prob, a):
-    ys = slice(G, -G) if prob.dim == 3 else slice(None)
-    return a[G:-G, ys, G:-G]
+    g = ghost(prob)
+    ys = slice(g, -g) if prob.dim == 3 else slice(None)
+    return a[g:-g, ys, g:-g]
 
 
 class _Ops:

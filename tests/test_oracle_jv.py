@@ -18,6 +18,8 @@ def _cases():
         ("island-noslip", I.heat_island_2d(32, 12, h0=400.0, width=8000.0)),
         ("constK-periodic", I.Problem(nx=20, nz=12, closure=0, bc_lateral=2, bc_vertical=2, n_bv=0.01)),
         ("3d", I.thermal_neutral_3d(12, 10, 8)),
+        ("stable-smag-p3", I.thermal_stable_2d(24, 16).replace(dd_p=3)),
+        ("island-noslip-p3", I.heat_island_2d(32, 12, h0=400.0, width=8000.0).replace(dd_p=3)),
     ]
 
 

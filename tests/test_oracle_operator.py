@@ -29,12 +29,13 @@ def _inner(a, b):
 BCS = [(0, 0), (0, 1), (2, 2), (0, 2)]
 
 
+@pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("bcl,bcv", BCS)
 @pytest.mark.parametrize("dim", [2, 3])
-def test_skew_symmetry_for_any_velocity(dim, bcl, bcv):
-    """<phi, C(a; phi)> = 0 for every field phi and any velocity a."""
-    prob = _prob(dim=dim, nx=12, ny=(10 if dim == 3 else 1), nz=8, ly=15000.0,
-                 bc_lateral=bcl, bc_vertical=bcv)
+def test_skew_symmetry_for_any_velocity(dim, bcl, bcv, p):
+    """<phi, C(a; phi)> = 0 for every field phi and any velocity a (both stencils)."""
+    prob = _prob(dim=dim, nx=12, ny=(10 if dim == 3 else 1), nz=(8 if p == 2 else 9), ly=15000.0,
+                 bc_lateral=bcl, bc_vertical=bcv, dd_p=p)
     U = _rand(prob, 1)
     ops = M._Ops(prob)
     vel, p, th = M._ext_state(prob, U)
@@ -52,17 +53,18 @@ def _streamfunction_velocity(prob, seed):
     ops = M._Ops(prob)
     psi = np.random.Generator(np.random.PCG64(seed)).normal(size=(prob.nz, prob.ny, prob.nx))
     # extend psi as odd in x and z (same parity as a normal velocity in both)
-    ix, sx = M._axis_map(prob.nx, prob.bc_lateral, -1, -1)
-    iz, sz = M._axis_map(prob.nz, prob.bc_vertical, -1, -1)
+    ix, sx = M._axis_map(prob.nx, prob.bc_lateral, -1, -1, M.ghost(prob))
+    iz, sz = M._axis_map(prob.nz, prob.bc_vertical, -1, -1, M.ghost(prob))
     pe = psi[np.ix_(iz, np.arange(prob.ny), ix)] * sz[:, None, None] * sx[None, None, :]
     u = -M.interior(prob, ops.D(pe, 1))
     w = M.interior(prob, ops.D(pe, 0))
     return u, w
 
 
+@pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("bcl,bcv", [(0, 0), (2, 2), (0, 1)])
-def test_mass_conservation_and_divergence_free_convection(bcl, bcv):
-    prob = _prob(bc_lateral=bcl, bc_vertical=bcv)
+def test_mass_conservation_and_divergence_free_convection(bcl, bcv, p):
+    prob = _prob(bc_lateral=bcl, bc_vertical=bcv, dd_p=p)
     ops = M._Ops(prob)
     U = _rand(prob, 3)
     vel, p, th = M._ext_state(prob, U)
@@ -112,10 +114,11 @@ def test_heat_budget_equals_surface_flux():
     assert abs(expect - 0.214392 * 4000.0 * (Hx > 0).sum() * dx / 4000.0) < 1e-5 * expect
 
 
+@pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("bcl,bcv", [(0, 0), (2, 2)])
-def test_symmetric_dissipative_diffusion(bcl, bcv):
+def test_symmetric_dissipative_diffusion(bcl, bcv, p):
     """<u, D.tau> = -sum tau:S <= 0 and <theta, D.q> = -sum K_theta |D theta|^2 <= 0."""
-    prob = _prob(bc_lateral=bcl, bc_vertical=bcv, convection=0, n_bv=0.0)
+    prob = _prob(bc_lateral=bcl, bc_vertical=bcv, convection=0, n_bv=0.0, dd_p=p)
     ops = M._Ops(prob)
     U = _rand(prob, 7)
     U[2] = 0.0                                       # no pressure gradient
@@ -180,24 +183,34 @@ def test_background_profile_is_hydrostatic():
 
 @pytest.mark.parametrize("bcl,bcv", [(0, 0), (2, 2)])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_inviscid_operator_conserves_wave_energy(dim, bcl, bcv):
+@pytest.mark.parametrize("p", [2, 3])
+def test_inviscid_operator_conserves_wave_energy(dim, bcl, bcv, p):
     """Energy-test form (no closure, frozen Exner coefficient): <grad E_W, F(u)> = 0
     for any u, convection included."""
-    prob = _prob(dim=dim, nx=12, ny=(10 if dim == 3 else 1), nz=8, ly=15000.0,
-                 bc_lateral=bcl, bc_vertical=bcv, closure=2, energy_test=1, n_bv=0.012)
+    prob = _prob(dim=dim, nx=12, ny=(10 if dim == 3 else 1), nz=(8 if p == 2 else 9), ly=15000.0,
+                 bc_lateral=bcl, bc_vertical=bcv, closure=2, energy_test=1, n_bv=0.012, dd_p=p)
     U = _rand(prob, 11)
     Fv = M.F(prob, U)
     Gr = M.wave_energy_gradient(prob, U)
     assert abs(_inner(Gr, Fv)) <= 1e-13 * float(np.sum(np.abs(Gr * Fv)))
 
 
-def _dispersion_setup(mx=2, mz=1):
+# modified-wavenumber weights: k~ dx = 2 sum_m c_m sin(m k dx), c_m the stencil's
+# one-sided coefficients (p = 2: 2/3, -1/12; p = 3: 272/365, -53/365, 16/1095, 1/2920)
+_KW = {2: (2 / 3, -1 / 12), 3: (272 / 365, -53 / 365, 16 / 1095, 1 / 2920)}
+
+
+def _ktilde(k, h, p):
+    return 2.0 * sum(c * np.sin((m + 1) * k * h) for m, c in enumerate(_KW[p])) / h
+
+
+def _dispersion_setup(mx=2, mz=1, p=2):
     prob = _prob(nx=32, nz=16, bc_lateral=2, bc_vertical=2, closure=2, energy_test=1,
-                 convection=0, n_bv=0.01)
+                 convection=0, n_bv=0.01, dd_p=p)
     dx, _, dz = M.spacings(prob)
     kx, kz = 2 * np.pi * mx / prob.lx, 2 * np.pi * mz / prob.lz
-    ktx = ((4 / 3) * np.sin(kx * dx) - (1 / 6) * np.sin(2 * kx * dx)) / dx
-    ktz = ((4 / 3) * np.sin(kz * dz) - (1 / 6) * np.sin(2 * kz * dz)) / dz
+    ktx = _ktilde(kx, dx, p)
+    ktz = _ktilde(kz, dz, p)
     c2 = (287.0 / 717.0) * 1004.0 * 300.0
     N2 = 0.01 ** 2
     kt2 = ktx ** 2 + ktz ** 2
@@ -225,11 +238,12 @@ def _mode(prob, lam, ktx, ktz, ph, beta):
     return U
 
 
+@pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("branch", ["gravity", "acoustic"])
-def test_internal_wave_dispersion(branch):
+def test_internal_wave_dispersion(branch, p):
     """Single Fourier mode on a doubly periodic grid is an eigenvector of the linear
     operator with eigenvalue i omega, omega^4 - omega^2 (N^2 + c^2 k~^2) + c^2 N^2 k~_x^2 = 0."""
-    prob, ktx, ktz, om_g, om_a, ph, beta = _dispersion_setup()
+    prob, ktx, ktz, om_g, om_a, ph, beta = _dispersion_setup(p=p)
     om = om_g if branch == "gravity" else om_a
     lam = 1j * om
     U = _mode(prob, lam, ktx, ktz, ph, beta)
