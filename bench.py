@@ -11,6 +11,7 @@ Legs, all from the same state after the warm-up steps:
   learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
             the network is trained first on pairs the solver generates on this
             workload (training time reported, not timed with the steps)
+  mixed_p3  the mixed leg with the 9-point (p = 3) derivative
 A second learned comparison runs on the same thermal at 256 x 128, where the
 acoustic CFL number is a quarter of the full grid's.
 
@@ -61,7 +62,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,learned")
+    ap.add_argument("--legs", default="mixed,plain,learned,p3")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
@@ -230,7 +231,8 @@ def synth_state(torch, prob, seed=0):
 def kernel_micro(torch, I, L, Context, reps):
     """Residual and Jv kernels alone at sizes beyond the Infinity Cache."""
     out = {}
-    cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d())]
+    cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d()),
+             ("2d_8192x8192_p3", I.thermal_stable_2d(8192, 8192).replace(dd_p=3))]
     for name, prob in cases:
         ctx = Context(prob, max_m=1)
         u64 = synth_state(torch, prob)
@@ -364,6 +366,15 @@ def main():
         legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
         log("learned vs physics preconditioner at 256 x 128")
         small = learned_small(torch, I, LRN, Context, args.train_iters)
+    if "p3" in legs_wanted:
+        # the same workload with the 9-point (p = 3) derivative
+        prob3 = prob.replace(dd_p=3)
+        ctx3 = Context(prob3, max_m=30)
+        u3 = torch.from_numpy(U0).cuda()
+        log("mixed steps with the 9-point stencil")
+        run_steps(ctx3, u3, args.warmup, torch, **opts["mixed"])
+        legs["mixed_p3"] = timed_leg(ctx3, u3, args.plain_steps, torch, L, classes["mixed"], **opts["mixed"])
+        del ctx3
 
     T = legs["mixed"]
     tm = T["tm"]

@@ -75,8 +75,9 @@ typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIOD
  * to Q = H/(rho0 cp) and applied as Q/dz in the lowest cell.
  * convection = 0 drops the convective terms; energy_test = 1 replaces
  * kappa (p_bar + p') by kappa cp and drops w dp_bar/dz (a frozen-coefficient
- * operator that conserves a quadratic energy).  dd_p must be 2 (5-point
- * Deslauriers-Dubuc derivative, section 2.3).                                   */
+ * operator that conserves a quadratic energy).  dd_p is the order parameter of
+ * the Deslauriers-Dubuc derivative (section 2.3): 2 (5 points) or, for 2D
+ * problems outside a batch, 3 (9 points; halos twice as deep).                  */
 typedef struct {
     int32_t dim, nx, ny, nz;          /* 2 or 3; grid points per direction (ny = 1 in 2D) */
     double lx, ly, lz, dt;            /* domain [m], time step [s]                       */

@@ -533,7 +533,8 @@ bool valid_problem(const jfnk_problem* p, std::string& why) {
         return why = "grid below 8 points in a direction (or ny != 1 in 2D)", false;
     if (p->dim == 3 && !(p->ly > 0)) return why = "non-positive domain size", false;
     if (!(p->dt > 0) || !(p->lx > 0) || !(p->lz > 0)) return why = "non-positive dt or domain size", false;
-    if (p->dd_p != 2) return why = "only dd_p = 2 is supported", false;
+    if (p->dd_p != 2 && !(p->dd_p == 3 && p->dim == 2))
+        return why = "dd_p must be 2 (or 3 for 2D problems)", false;
     if (p->bc_lateral != JFNK_BC_FREE_SLIP && p->bc_lateral != JFNK_BC_PERIODIC)
         return why = "bc_lateral must be free-slip or periodic", false;
     if (p->bc_vertical < 0 || p->bc_vertical > 2) return why = "invalid bc_vertical", false;
@@ -587,6 +588,7 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     g.npts = (long long)p->nx * p->ny * p->nz;
     g.bcl = p->bc_lateral;
     g.bcv = p->bc_vertical;
+    g.W = p->dd_p == 3 ? 4 : 2;
     g.dx = p->lx / p->nx;
     g.dy = p->ly / p->ny;
     g.dz = p->lz / p->nz;
@@ -632,7 +634,7 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     ALLOC(c->t64b, nb64);
     ALLOC(c->b64, nb64);
     ALLOC(c->x64, nb64);
-    const size_t next = (size_t)(g.nx + 4) * (g.nz + 4) * (g.dim == 3 ? (g.ny + 4) : 1);
+    const size_t next = (size_t)(g.nx + 2 * g.W) * (g.nz + 2 * g.W) * (g.dim == 3 ? (g.ny + 4) : 1);
     ALLOC(c->nu64, next * sizeof(double));
     ALLOC(c->u32, nb32);
     ALLOC(c->b32, nb32);
@@ -1233,8 +1235,8 @@ int jfnk_net_set_loss(jfnk_ctx* c, int32_t kind) {
         set_error("invalid argument to jfnk_net_set_loss");
         return JFNK_ERR_ARG;
     }
-    if (kind == JFNK_NET_LOSS_REST_JACOBIAN && (c->prob.energy_test || c->prob.dim != 2)) {
-        set_error("the rest-Jacobian loss is available for 2D problems with energy_test = 0");
+    if (kind == JFNK_NET_LOSS_REST_JACOBIAN && (c->prob.energy_test || c->prob.dim != 2 || c->prob.dd_p != 2)) {
+        set_error("the rest-Jacobian loss is available for 2D problems with energy_test = 0 and dd_p = 2");
         return JFNK_ERR_ARG;
     }
     c->net.loss_kind = kind;

@@ -15,6 +15,7 @@ namespace jfnk {
 // Kernel-side view of a problem: constants and device pointers, passed by value.
 struct Geo {
     int dim, nx, ny, nz;
+    int W = 2;                  // half-width of the derivative stencil (2: p = 2, 4: p = 3)
     long long npts;
     int bcl, bcv;               // lateral / vertical boundary kind
     double dx, dy, dz;

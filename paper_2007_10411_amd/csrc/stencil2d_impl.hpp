@@ -2,8 +2,10 @@
 // (shared by the single-grid kernels and the batched ensemble kernels).
 //
 // Discretisation (sections 2.1-2.4 of the paper, equations 1-5 and 9):
-//   D      5-point Deslauriers-Dubuc collocation derivative (order 2p = 4):
-//          (D a)_i = [ 2/3 (a_{i+1} - a_{i-1}) - 1/12 (a_{i+2} - a_{i-2}) ] / h
+//   D      Deslauriers-Dubuc collocation derivative of order 2p with half-width W:
+//          (D a)_i = sum_{m=1..W} c_m (a_{i+m} - a_{i-m}) / h, p = 2 (W = 2, 5 points):
+//          c = 2/3, -1/12; p = 3 (W = 4, 9 points): c = 272/365, -53/365, 16/1095,
+//          1/2920
 //   C      skew-symmetric convection 1/2 sum_j [ D_j(a_j phi) + a_j D_j phi ]
 //   tau    2 nu (S - tr(S)/3 I), S = sym(grad u), nu = (cs Delta)^2 sqrt(2 S:S)
 //   q      (nu / Pr_t) D theta
@@ -12,9 +14,10 @@
 //   F_th   = -C(u; theta) - beta w + D_j q_j + [k = 0] Q / dz
 // Walls sit on the cell faces; fields are extended by mirror reflection with a
 // parity (normal velocity odd, tangential velocity odd at a no-slip bottom,
-// everything else even) or periodically.  The composite D(tau(D u)) reaches 4
-// points, so every tile stages its primitives with a halo of 4 in LDS, forms the
-// stress and heat flux on a ring of 2 and differentiates those.
+// everything else even) or periodically.  The composite D(tau(D u)) reaches 2W
+// points, so every tile stages its primitives with a halo of 2W in LDS, forms
+// the stress and heat flux on a ring of W and differentiates those.  W is a
+// template parameter of every tile body (default 2).
 //
 // Tile: TX x TZ output points per 256-thread workgroup, x fastest so that each
 // wavefront reads 64 consecutive points of a row (coalesced).
@@ -65,43 +68,68 @@ __device__ __forceinline__ T d5(T m2, T m1, T p1, T p2, T ih) {
     return (T(2.0 / 3.0) * (p1 - m1) - T(1.0 / 12.0) * (p2 - m2)) * ih;
 }
 
+// One-sided weights c_m of the derivative of half-width W, and 2 sum_m c_m^2
+// (the diagonal of D(K D .) per unit K / h^2).
+template <int W> struct DW;
+template <> struct DW<2> {
+    static constexpr double c[2] = {2.0 / 3.0, -1.0 / 12.0};
+    static constexpr double sumsq2 = 65.0 / 72.0;
+};
+template <> struct DW<4> {
+    static constexpr double c[4] = {272.0 / 365.0, -53.0 / 365.0, 16.0 / 1095.0, 1.0 / 2920.0};
+    static constexpr double sumsq2 = 2.0 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3]);
+};
+
+// sum_m c_m (f(m) - f(-m)) * ih for a tap functor f(offset)
+template <int W, typename T, typename F>
+__device__ __forceinline__ T dtaps(F f, T ih) {
+    if constexpr (W == 2) {
+        return d5(f(-2), f(-1), f(1), f(2), ih);
+    } else {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < W; ++m) acc += T(DW<W>::c[m]) * (f(m + 1) - f(-m - 1));
+        return acc * ih;
+    }
+}
+
 // x- and z-derivative of an LDS array at (z, x) with row stride S
-template <typename T, int S>
+template <typename T, int S, int W = 2>
 __device__ __forceinline__ T dx_s(const T* a, int z, int x, T ih) {
     const T* r = a + z * S + x;
-    return d5(r[-2], r[-1], r[1], r[2], ih);
+    return dtaps<W>([&](int o) { return r[o]; }, ih);
 }
-template <typename T, int S>
+template <typename T, int S, int W = 2>
 __device__ __forceinline__ T dz_s(const T* a, int z, int x, T ih) {
     const T* r = a + z * S + x;
-    return d5(r[-2 * S], r[-S], r[S], r[2 * S], ih);
+    return dtaps<W>([&](int o) { return r[o * S]; }, ih);
 }
 
 // Derivatives of a product a*b stored in two LDS arrays
-template <typename T, int S>
+template <typename T, int S, int W = 2>
 __device__ __forceinline__ T dx_prod(const T* a, const T* b, int z, int x, T ih) {
     const T* ra = a + z * S + x;
     const T* rb = b + z * S + x;
-    return d5(ra[-2] * rb[-2], ra[-1] * rb[-1], ra[1] * rb[1], ra[2] * rb[2], ih);
+    return dtaps<W>([&](int o) { return ra[o] * rb[o]; }, ih);
 }
-template <typename T, int S>
+template <typename T, int S, int W = 2>
 __device__ __forceinline__ T dz_prod(const T* a, const T* b, int z, int x, T ih) {
     const T* ra = a + z * S + x;
     const T* rb = b + z * S + x;
-    return d5(ra[-2 * S] * rb[-2 * S], ra[-S] * rb[-S], ra[S] * rb[S], ra[2 * S] * rb[2 * S], ih);
+    return dtaps<W>([&](int o) { return ra[o * S] * rb[o * S]; }, ih);
 }
 
-// Stage the n-field state (field stride np) with halo 4 into LDS s[f][SZ][SX].
-template <typename T, int TX, int TZ, int NFL>
+// Stage the n-field state (field stride np) with halo H into LDS s[f][SZ][SX].
+template <typename T, int TX, int TZ, int NFL, int H = kHalo>
 __device__ __forceinline__ void stage_fields(const Geo& g, const T* __restrict__ u, T* s, int x0, int z0,
                                              int f_first) {
-    constexpr int SX = TX + 2 * kHalo, SZ = TZ + 2 * kHalo;
+    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
     const long long np = g.npts;
     for (int idx = threadIdx.x; idx < SZ * SX; idx += blockDim.x) {
         const int lz = idx / SX, lx = idx - (idx / SX) * SX;
         int sx, sz;
-        const int gx = map_axis(x0 + lx - kHalo, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
-        const int gz = map_axis(z0 + lz - kHalo, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+        const int gx = map_axis(x0 + lx - H, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
+        const int gz = map_axis(z0 + lz - H, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
         const long long off = (long long)gz * g.nx + gx;
 #pragma unroll
         for (int f = 0; f < NFL; ++f) {
@@ -128,16 +156,17 @@ __device__ __forceinline__ void closure_coeffs(const Geo& g, T s2, T& nu, T& kth
 // ---------------------------------------------------------------------------
 // F(u) and the residual
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TZ>
+template <typename T, int TX, int TZ, int W = 2>
 __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const T* __restrict__ u,
                                              const T* __restrict__ f, T* __restrict__ out, int what) {
-    constexpr int SX = TX + 2 * kHalo, SZ = TZ + 2 * kHalo;
-    constexpr int DX = TX + 4, DZ = TZ + 4;
+    constexpr int H = 2 * W;
+    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
+    constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W;
     __shared__ T sp[4 * SZ * SX];
     __shared__ T sd[5 * DZ * DX];
     const T ihx = T(g.idx), ihz = T(g.idz);
 
-    stage_fields<T, TX, TZ, 4>(g, u, sp, x0, z0, 0);
+    stage_fields<T, TX, TZ, 4, H>(g, u, sp, x0, z0, 0);
     __syncthreads();
 
     const T* su = sp;
@@ -145,13 +174,13 @@ __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const
     const T* spp = sp + 2 * SZ * SX;
     const T* sth = sp + 3 * SZ * SX;
 
-    // stress and heat flux on the ring-2 extended tile
+    // stress and heat flux on the ring-W extended tile
     for (int idx = threadIdx.x; idx < DZ * DX; idx += blockDim.x) {
         const int dzi = idx / DX, dxi = idx - (idx / DX) * DX;
-        const int z = dzi + 2, x = dxi + 2;
-        const T ux = dx_s<T, SX>(su, z, x, ihx), uz = dz_s<T, SX>(su, z, x, ihz);
-        const T wx = dx_s<T, SX>(sw, z, x, ihx), wz = dz_s<T, SX>(sw, z, x, ihz);
-        const T tx = dx_s<T, SX>(sth, z, x, ihx), tz = dz_s<T, SX>(sth, z, x, ihz);
+        const int z = dzi + W, x = dxi + W;
+        const T ux = dx_s<T, SX, W>(su, z, x, ihx), uz = dz_s<T, SX, W>(su, z, x, ihz);
+        const T wx = dx_s<T, SX, W>(sw, z, x, ihx), wz = dz_s<T, SX, W>(sw, z, x, ihz);
+        const T tx = dx_s<T, SX, W>(sth, z, x, ihx), tz = dz_s<T, SX, W>(sth, z, x, ihz);
         const T sxz = T(0.5) * (uz + wx);
         const T div = ux + wz;
         const T s2 = ux * ux + wz * wz + T(2) * sxz * sxz;
@@ -175,20 +204,20 @@ __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= g.nx || gz >= g.nz) continue;
-        const int z = lz + kHalo, x = lx + kHalo;      // primitive coordinates
-        const int dz_ = lz + 2, dx_ = lx + 2;          // derived coordinates
+        const int z = lz + H, x = lx + H;              // primitive coordinates
+        const int dz_ = lz + W, dx_ = lx + W;          // derived coordinates
         const T uu = su[z * SX + x], ww = sw[z * SX + x], pp = spp[z * SX + x], th = sth[z * SX + x];
-        const T ux = dx_s<T, SX>(su, z, x, ihx), wz = dz_s<T, SX>(sw, z, x, ihz);
+        const T ux = dx_s<T, SX, W>(su, z, x, ihx), wz = dz_s<T, SX, W>(sw, z, x, ihz);
         const T div = ux + wz;
         T cu = 0, cw = 0, cp = 0, ct = 0;
         if (conv) {
-            const T uz = dz_s<T, SX>(su, z, x, ihz), wx = dx_s<T, SX>(sw, z, x, ihx);
-            const T px = dx_s<T, SX>(spp, z, x, ihx), pz = dz_s<T, SX>(spp, z, x, ihz);
-            const T tx = dx_s<T, SX>(sth, z, x, ihx), tz = dz_s<T, SX>(sth, z, x, ihz);
-            cu = T(0.5) * (dx_prod<T, SX>(su, su, z, x, ihx) + dz_prod<T, SX>(sw, su, z, x, ihz) + uu * ux + ww * uz);
-            cw = T(0.5) * (dx_prod<T, SX>(su, sw, z, x, ihx) + dz_prod<T, SX>(sw, sw, z, x, ihz) + uu * wx + ww * wz);
-            cp = T(0.5) * (dx_prod<T, SX>(su, spp, z, x, ihx) + dz_prod<T, SX>(sw, spp, z, x, ihz) + uu * px + ww * pz);
-            ct = T(0.5) * (dx_prod<T, SX>(su, sth, z, x, ihx) + dz_prod<T, SX>(sw, sth, z, x, ihz) + uu * tx + ww * tz);
+            const T uz = dz_s<T, SX, W>(su, z, x, ihz), wx = dx_s<T, SX, W>(sw, z, x, ihx);
+            const T px = dx_s<T, SX, W>(spp, z, x, ihx), pz = dz_s<T, SX, W>(spp, z, x, ihz);
+            const T tx = dx_s<T, SX, W>(sth, z, x, ihx), tz = dz_s<T, SX, W>(sth, z, x, ihz);
+            cu = T(0.5) * (dx_prod<T, SX, W>(su, su, z, x, ihx) + dz_prod<T, SX, W>(sw, su, z, x, ihz) + uu * ux + ww * uz);
+            cw = T(0.5) * (dx_prod<T, SX, W>(su, sw, z, x, ihx) + dz_prod<T, SX, W>(sw, sw, z, x, ihz) + uu * wx + ww * wz);
+            cp = T(0.5) * (dx_prod<T, SX, W>(su, spp, z, x, ihx) + dz_prod<T, SX, W>(sw, spp, z, x, ihz) + uu * px + ww * pz);
+            ct = T(0.5) * (dx_prod<T, SX, W>(su, sth, z, x, ihx) + dz_prod<T, SX, W>(sw, sth, z, x, ihz) + uu * tx + ww * tz);
         }
         const T* txx = sd;
         const T* txz = sd + DZ * DX;
@@ -196,15 +225,15 @@ __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const
         const T* qx = sd + 3 * DZ * DX;
         const T* qz = sd + 4 * DZ * DX;
         const T th0 = T(g.theta0);
-        T Fu = -th0 * dx_s<T, SX>(spp, z, x, ihx) + dx_s<T, DX>(txx, dz_, dx_, ihx) + dz_s<T, DX>(txz, dz_, dx_, ihz) - cu;
-        T Fw = -th0 * dz_s<T, SX>(spp, z, x, ihz) + dx_s<T, DX>(txz, dz_, dx_, ihx) + dz_s<T, DX>(tzz, dz_, dx_, ihz) - cw +
+        T Fu = -th0 * dx_s<T, SX, W>(spp, z, x, ihx) + dx_s<T, DX, W>(txx, dz_, dx_, ihx) + dz_s<T, DX, W>(txz, dz_, dx_, ihz) - cu;
+        T Fw = -th0 * dz_s<T, SX, W>(spp, z, x, ihz) + dx_s<T, DX, W>(txz, dz_, dx_, ihx) + dz_s<T, DX, W>(tzz, dz_, dx_, ihz) - cw +
                T(g.g_theta0) * th;
         T Fp;
         if (g.energy_test)
             Fp = -cp - T(g.kappa_cp) * div;
         else
             Fp = -cp - ww * dpb[gz] - T(g.kappa) * (pb[gz] + pp) * div;
-        T Ft = dx_s<T, DX>(qx, dz_, dx_, ihx) + dz_s<T, DX>(qz, dz_, dx_, ihz) - ct - T(g.beta) * ww;
+        T Ft = dx_s<T, DX, W>(qx, dz_, dx_, ihx) + dz_s<T, DX, W>(qz, dz_, dx_, ihz) - ct - T(g.beta) * ww;
         if (gz == 0 && !g.energy_test) Ft += sfl[gx];
         const long long off = (long long)gz * g.nx + gx;
         T Fv[4] = {Fu, Fw, Fp, Ft};
@@ -225,12 +254,13 @@ __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const
 //   [B(a + e b, c + e d) - B(a, c)] / e = B(a, d) + B(b, c) + e B(b, d)
 //   nu difference: (cs Delta)^2 sqrt2 (2 S:T + e T:T) / (|S + e T| + |S|)
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TZ>
+template <typename T, int TX, int TZ, int W = 2>
 __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* __restrict__ u,
                                         const T* __restrict__ v, double eps_in, const double* __restrict__ eps_dev,
                                         T* __restrict__ out) {
-    constexpr int SX = TX + 2 * kHalo, SZ = TZ + 2 * kHalo;
-    constexpr int DX = TX + 4, DZ = TZ + 4;
+    constexpr int H = 2 * W;
+    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
+    constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W;
     constexpr int PS = SZ * SX, DS = DZ * DX;
     __shared__ T sa[4 * PS];
     __shared__ T sb[4 * PS];
@@ -238,21 +268,21 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
     const T ihx = T(g.idx), ihz = T(g.idz);
     const T e = T(eps_dev ? *eps_dev : eps_in);
 
-    stage_fields<T, TX, TZ, 4>(g, u, sa, x0, z0, 0);
-    stage_fields<T, TX, TZ, 4>(g, v, sb, x0, z0, 0);
+    stage_fields<T, TX, TZ, 4, H>(g, u, sa, x0, z0, 0);
+    stage_fields<T, TX, TZ, 4, H>(g, v, sb, x0, z0, 0);
     __syncthreads();
 
     const T *ua = sa, *wa = sa + PS, *pa = sa + 2 * PS, *ta = sa + 3 * PS;
     const T *ub = sb, *wb = sb + PS, *pbv = sb + 2 * PS, *tb = sb + 3 * PS;
 
     for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
-        const int z = idx / DX + 2, x = idx - (idx / DX) * DX + 2;
-        const T uxa = dx_s<T, SX>(ua, z, x, ihx), uza = dz_s<T, SX>(ua, z, x, ihz);
-        const T wxa = dx_s<T, SX>(wa, z, x, ihx), wza = dz_s<T, SX>(wa, z, x, ihz);
-        const T uxb = dx_s<T, SX>(ub, z, x, ihx), uzb = dz_s<T, SX>(ub, z, x, ihz);
-        const T wxb = dx_s<T, SX>(wb, z, x, ihx), wzb = dz_s<T, SX>(wb, z, x, ihz);
-        const T txa = dx_s<T, SX>(ta, z, x, ihx), tza = dz_s<T, SX>(ta, z, x, ihz);
-        const T txb = dx_s<T, SX>(tb, z, x, ihx), tzb = dz_s<T, SX>(tb, z, x, ihz);
+        const int z = idx / DX + W, x = idx - (idx / DX) * DX + W;
+        const T uxa = dx_s<T, SX, W>(ua, z, x, ihx), uza = dz_s<T, SX, W>(ua, z, x, ihz);
+        const T wxa = dx_s<T, SX, W>(wa, z, x, ihx), wza = dz_s<T, SX, W>(wa, z, x, ihz);
+        const T uxb = dx_s<T, SX, W>(ub, z, x, ihx), uzb = dz_s<T, SX, W>(ub, z, x, ihz);
+        const T wxb = dx_s<T, SX, W>(wb, z, x, ihx), wzb = dz_s<T, SX, W>(wb, z, x, ihz);
+        const T txa = dx_s<T, SX, W>(ta, z, x, ihx), tza = dz_s<T, SX, W>(ta, z, x, ihz);
+        const T txb = dx_s<T, SX, W>(tb, z, x, ihx), tzb = dz_s<T, SX, W>(tb, z, x, ihz);
         // strain of u (a) and of v (b)
         const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
         const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
@@ -290,13 +320,13 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= g.nx || gz >= g.nz) continue;
-        const int z = lz + kHalo, x = lx + kHalo;
-        const int dz_ = lz + 2, dx_ = lx + 2;
+        const int z = lz + H, x = lx + H;
+        const int dz_ = lz + W, dx_ = lx + W;
         const int c = z * SX + x;
         const T uA = ua[c], wA = wa[c], pA = pa[c];
         const T uB = ub[c], wB = wb[c], pB = pbv[c], tB = tb[c];
-        const T divA = dx_s<T, SX>(ua, z, x, ihx) + dz_s<T, SX>(wa, z, x, ihz);
-        const T divB = dx_s<T, SX>(ub, z, x, ihx) + dz_s<T, SX>(wb, z, x, ihz);
+        const T divA = dx_s<T, SX, W>(ua, z, x, ihx) + dz_s<T, SX, W>(wa, z, x, ihz);
+        const T divB = dx_s<T, SX, W>(ub, z, x, ihx) + dz_s<T, SX, W>(wb, z, x, ihz);
         T cu = 0, cw = 0, cp = 0, ct = 0;
         if (conv) {
             // 1/2 [ D_j(a_j phi_b + b_j phi_a + e b_j phi_b) + a_j D_j phi_b + b_j D_j phi_a + e b_j D_j phi_b ]
@@ -309,10 +339,10 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
                 const T* B = fb[k];
                 auto px = [&](int o) { return ua[c + o] * B[c + o] + ub[c + o] * (A[c + o] + e * B[c + o]); };
                 auto pz = [&](int o) { return wa[c + o] * B[c + o] + wb[c + o] * (A[c + o] + e * B[c + o]); };
-                const T fx = d5(px(-2), px(-1), px(1), px(2), ihx);
-                const T fz = d5(pz(-2 * SX), pz(-SX), pz(SX), pz(2 * SX), ihz);
-                const T dAx = dx_s<T, SX>(A, z, x, ihx), dAz = dz_s<T, SX>(A, z, x, ihz);
-                const T dBx = dx_s<T, SX>(B, z, x, ihx), dBz = dz_s<T, SX>(B, z, x, ihz);
+                const T fx = dtaps<W>(px, ihx);
+                const T fz = dtaps<W>([&](int o) { return pz(o * SX); }, ihz);
+                const T dAx = dx_s<T, SX, W>(A, z, x, ihx), dAz = dz_s<T, SX, W>(A, z, x, ihz);
+                const T dBx = dx_s<T, SX, W>(B, z, x, ihx), dBz = dz_s<T, SX, W>(B, z, x, ihz);
                 const T ad = uA * dBx + wA * dBz + uB * (dAx + e * dBx) + wB * (dAz + e * dBz);
                 cc[k] = T(0.5) * (fx + fz + ad);
             }
@@ -323,16 +353,16 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
         }
         const T *txx = sd, *txz = sd + DS, *tzz = sd + 2 * DS, *qx = sd + 3 * DS, *qz = sd + 4 * DS;
         const T th0 = T(g.theta0);
-        const T dFu = -th0 * dx_s<T, SX>(pbv, z, x, ihx) + dx_s<T, DX>(txx, dz_, dx_, ihx) +
-                      dz_s<T, DX>(txz, dz_, dx_, ihz) - cu;
-        const T dFw = -th0 * dz_s<T, SX>(pbv, z, x, ihz) + dx_s<T, DX>(txz, dz_, dx_, ihx) +
-                      dz_s<T, DX>(tzz, dz_, dx_, ihz) - cw + T(g.g_theta0) * tB;
+        const T dFu = -th0 * dx_s<T, SX, W>(pbv, z, x, ihx) + dx_s<T, DX, W>(txx, dz_, dx_, ihx) +
+                      dz_s<T, DX, W>(txz, dz_, dx_, ihz) - cu;
+        const T dFw = -th0 * dz_s<T, SX, W>(pbv, z, x, ihz) + dx_s<T, DX, W>(txz, dz_, dx_, ihx) +
+                      dz_s<T, DX, W>(tzz, dz_, dx_, ihz) - cw + T(g.g_theta0) * tB;
         T dFp;
         if (g.energy_test)
             dFp = -cp - T(g.kappa_cp) * divB;
         else
             dFp = -cp - wB * dpb[gz] - T(g.kappa) * ((pbar[gz] + pA) * divB + pB * divA + e * pB * divB);
-        const T dFt = dx_s<T, DX>(qx, dz_, dx_, ihx) + dz_s<T, DX>(qz, dz_, dx_, ihz) - ct - T(g.beta) * wB;
+        const T dFt = dx_s<T, DX, W>(qx, dz_, dx_, ihx) + dz_s<T, DX, W>(qz, dz_, dx_, ihz) - ct - T(g.beta) * wB;
         const long long off = (long long)gz * g.nx + gx;
         const T tdt = T(g.two_dt);
         out[off] = tdt * uB - dFu;
@@ -345,16 +375,16 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
 // ---------------------------------------------------------------------------
 // Physics-based preconditioner
 // ---------------------------------------------------------------------------
-// Frozen eddy viscosity on the grid extended by a ring of 2, stored with row
-// stride nx + 4: ghost values are formed from the mirrored velocity, like every
+// Frozen eddy viscosity on the grid extended by a ring of W, stored with row
+// stride nx + 2W: ghost values are formed from the mirrored velocity, like every
 // derived quantity (at a no-slip bottom they are not a mirror image of the
 // interior values).
-template <typename T>
+template <typename T, int W = 2>
 __device__ __forceinline__ void frozen_nu_point(const Geo& g, long long i, const T* __restrict__ u,
                                                 T* __restrict__ nu) {
-    const int ex = g.nx + 4, ez = g.nz + 4;
+    const int ex = g.nx + 2 * W, ez = g.nz + 2 * W;
     if (i >= (long long)ex * ez) return;
-    const int gx = (int)(i % ex) - 2, gz = (int)(i / ex) - 2;
+    const int gx = (int)(i % ex) - W, gz = (int)(i / ex) - W;
     const long long np = g.npts;
     auto val = [&](int f, int x, int z) {
         int sx, sz;
@@ -364,10 +394,10 @@ __device__ __forceinline__ void frozen_nu_point(const Geo& g, long long i, const
         return sign2d(f, sx, sz, g.bcv) < 0 ? -v : v;
     };
     const T ihx = T(g.idx), ihz = T(g.idz);
-    const T ux = d5(val(0, gx - 2, gz), val(0, gx - 1, gz), val(0, gx + 1, gz), val(0, gx + 2, gz), ihx);
-    const T uz = d5(val(0, gx, gz - 2), val(0, gx, gz - 1), val(0, gx, gz + 1), val(0, gx, gz + 2), ihz);
-    const T wx = d5(val(1, gx - 2, gz), val(1, gx - 1, gz), val(1, gx + 1, gz), val(1, gx + 2, gz), ihx);
-    const T wz = d5(val(1, gx, gz - 2), val(1, gx, gz - 1), val(1, gx, gz + 1), val(1, gx, gz + 2), ihz);
+    const T ux = dtaps<W>([&](int o) { return val(0, gx + o, gz); }, ihx);
+    const T uz = dtaps<W>([&](int o) { return val(0, gx, gz + o); }, ihz);
+    const T wx = dtaps<W>([&](int o) { return val(1, gx + o, gz); }, ihx);
+    const T wz = dtaps<W>([&](int o) { return val(1, gx, gz + o); }, ihz);
     const T sxz = T(0.5) * (uz + wx);
     const T s2 = ux * ux + wz * wz + T(2) * sxz * sxz;
     T n, k;
@@ -375,8 +405,8 @@ __device__ __forceinline__ void frozen_nu_point(const Geo& g, long long i, const
     nu[i] = n;
 }
 
-// Diagonal of the field block: 2/dt + (65/72) K (1/dx^2 + 1/dz^2); 65/72 is the
-// sum of the squared derivative weights 2 ((2/3)^2 + (1/12)^2).
+// Diagonal of the field block: 2/dt + 2 sum_m c_m^2 K (1/dx^2 + 1/dz^2) (65/72
+// for the 5-point stencil).
 template <typename T>
 __device__ __forceinline__ void pc_coeffs(const Geo& g, T nu_pt, T& kmom, T& kth) {
     if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
@@ -395,17 +425,17 @@ __device__ __forceinline__ void pc_coeffs(const Geo& g, T nu_pt, T& kmom, T& kth
 // the incoming Krylov vector (v = V_j / *div written back) and, when no sweep
 // follows, the norm of z for the finite-difference step.
 // Returns this thread's contribution to ||z||^2.
-template <typename T>
+template <typename T, int W = 2>
 __device__ __forceinline__ double pc_diag_point(const Geo& g, long long i, const T* __restrict__ nu,
                                                 T* __restrict__ vj, const double* __restrict__ div,
                                                 T* __restrict__ z) {
     double acc = 0.0;
     if (i < g.npts) {
-        const long long ie = (i / g.nx + 2) * (long long)(g.nx + 4) + (i % g.nx) + 2;
+        const long long ie = (i / g.nx + W) * (long long)(g.nx + 2 * W) + (i % g.nx) + W;
         T km, kt;
         pc_coeffs(g, nu[ie], km, kt);
         const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
-        const T cD = T(65.0 / 72.0);
+        const T cD = T(DW<W>::sumsq2);
         const T dd[4] = {T(g.two_dt) + cD * km * ih2, T(g.two_dt) + cD * km * ih2, T(g.two_dt),
                          T(g.two_dt) + cD * kt * ih2};
         const long long np = g.npts;
@@ -426,61 +456,62 @@ __device__ __forceinline__ double pc_diag_point(const Geo& g, long long i, const
 }
 
 // Returns this thread's contribution to ||zout||^2.
-template <typename T, int TX, int TZ>
+template <typename T, int TX, int TZ, int W = 2>
 __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, const T* __restrict__ u,
                                                 const T* __restrict__ nu, const T* __restrict__ r,
                                                 const T* __restrict__ zin, T* __restrict__ zout) {
-    constexpr int SX = TX + 2 * kHalo, SZ = TZ + 2 * kHalo, PS = SZ * SX;
-    constexpr int DX = TX + 4, DZ = TZ + 4, DS = DZ * DX;
-    __shared__ T sz_[4 * PS];   // z, halo 4
-    __shared__ T sv[2 * DS];    // frozen velocity, halo 2
-    __shared__ T sn[DS];        // frozen viscosity, halo 2
-    __shared__ T sf[6 * DS];    // K D_x z, K D_z z for u, w, theta on ring 2
+    constexpr int H = 2 * W;
+    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H, PS = SZ * SX;
+    constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W, DS = DZ * DX;
+    __shared__ T sz_[4 * PS];   // z, halo 2W
+    __shared__ T sv[2 * DS];    // frozen velocity, halo W
+    __shared__ T sn[DS];        // frozen viscosity, halo W
+    __shared__ T sf[6 * DS];    // K D_x z, K D_z z for u, w, theta on ring W
     double zacc = 0.0;
     const T ihx = T(g.idx), ihz = T(g.idz);
     const long long np = g.npts;
 
-    stage_fields<T, TX, TZ, 4>(g, zin, sz_, x0, z0, 0);
+    stage_fields<T, TX, TZ, 4, H>(g, zin, sz_, x0, z0, 0);
     for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
         const int lz = idx / DX, lx = idx - (idx / DX) * DX;
         int sx, szd;
-        const int gx = map_axis(x0 + lx - 2, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
-        const int gz = map_axis(z0 + lz - 2, g.nz, g.bcv == JFNK_BC_PERIODIC, szd);
+        const int gx = map_axis(x0 + lx - W, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
+        const int gz = map_axis(z0 + lz - W, g.nz, g.bcv == JFNK_BC_PERIODIC, szd);
         const long long off = (long long)gz * g.nx + gx;
         const T a0 = u[off], a1 = u[np + off];
         sv[idx] = sign2d(0, sx, szd, g.bcv) < 0 ? -a0 : a0;
         sv[DS + idx] = sign2d(1, sx, szd, g.bcv) < 0 ? -a1 : a1;
-        // extended viscosity: row gz + 2 of the (nz + 4) x (nx + 4) ring-2 grid
-        const int ex = min(max(x0 + lx, 0), g.nx + 3), ez = min(max(z0 + lz, 0), g.nz + 3);
-        sn[idx] = nu[(long long)ez * (g.nx + 4) + ex];
+        // extended viscosity: row gz + W of the (nz + 2W) x (nx + 2W) ring-W grid
+        const int ex = min(max(x0 + lx, 0), g.nx + 2 * W - 1), ez = min(max(z0 + lz, 0), g.nz + 2 * W - 1);
+        sn[idx] = nu[(long long)ez * (g.nx + 2 * W) + ex];
     }
     __syncthreads();
 
     for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
-        const int z = idx / DX + 2, x = idx - (idx / DX) * DX + 2;
+        const int z = idx / DX + W, x = idx - (idx / DX) * DX + W;
         T km, kt;
         pc_coeffs(g, sn[idx], km, kt);
         const T* zu = sz_;
         const T* zw = sz_ + PS;
         const T* zt = sz_ + 3 * PS;
-        sf[0 * DS + idx] = km * dx_s<T, SX>(zu, z, x, ihx);
-        sf[1 * DS + idx] = km * dz_s<T, SX>(zu, z, x, ihz);
-        sf[2 * DS + idx] = km * dx_s<T, SX>(zw, z, x, ihx);
-        sf[3 * DS + idx] = km * dz_s<T, SX>(zw, z, x, ihz);
-        sf[4 * DS + idx] = kt * dx_s<T, SX>(zt, z, x, ihx);
-        sf[5 * DS + idx] = kt * dz_s<T, SX>(zt, z, x, ihz);
+        sf[0 * DS + idx] = km * dx_s<T, SX, W>(zu, z, x, ihx);
+        sf[1 * DS + idx] = km * dz_s<T, SX, W>(zu, z, x, ihz);
+        sf[2 * DS + idx] = km * dx_s<T, SX, W>(zw, z, x, ihx);
+        sf[3 * DS + idx] = km * dz_s<T, SX, W>(zw, z, x, ihz);
+        sf[4 * DS + idx] = kt * dx_s<T, SX, W>(zt, z, x, ihx);
+        sf[5 * DS + idx] = kt * dz_s<T, SX, W>(zt, z, x, ihz);
     }
     __syncthreads();
 
     const bool conv = g.convection != 0;
     const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
-    const T cD = T(65.0 / 72.0);
+    const T cD = T(DW<W>::sumsq2);
     for (int idx = threadIdx.x; idx < TZ * TX; idx += blockDim.x) {
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= g.nx || gz >= g.nz) continue;
-        const int z = lz + kHalo, x = lx + kHalo;
-        const int dzi = lz + 2, dxi = lx + 2;
+        const int z = lz + H, x = lx + H;
+        const int dzi = lz + W, dxi = lx + W;
         const int dc = dzi * DX + dxi;
         const T a = sv[dc], w = sv[DS + dc];
         T km, kt;
@@ -494,7 +525,7 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
             T kk = (k == 2) ? T(0) : (k == 3 ? kt : km);
             if (k != 2) {
                 const int fi = (k == 3) ? 4 : 2 * k;
-                diff = dx_s<T, DX>(sf + fi * DS, dzi, dxi, ihx) + dz_s<T, DX>(sf + (fi + 1) * DS, dzi, dxi, ihz);
+                diff = dx_s<T, DX, W>(sf + fi * DS, dzi, dxi, ihx) + dz_s<T, DX, W>(sf + (fi + 1) * DS, dzi, dxi, ihz);
             }
             T cv = T(0);
             if (conv) {
@@ -503,9 +534,9 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
                 // D_x(a z): products over the ring-2 velocity and halo-4 z
                 auto pxv = [&](int o) { return va[dc + o] * Z[z * SX + x + o]; };
                 auto pzv = [&](int o) { return vw[dc + o * DX] * Z[(z + o) * SX + x]; };
-                const T fx = d5(pxv(-2), pxv(-1), pxv(1), pxv(2), ihx);
-                const T fz = d5(pzv(-2), pzv(-1), pzv(1), pzv(2), ihz);
-                cv = T(0.5) * (fx + fz + a * dx_s<T, SX>(Z, z, x, ihx) + w * dz_s<T, SX>(Z, z, x, ihz));
+                const T fx = dtaps<W>(pxv, ihx);
+                const T fz = dtaps<W>(pzv, ihz);
+                cv = T(0.5) * (fx + fz + a * dx_s<T, SX, W>(Z, z, x, ihx) + w * dz_s<T, SX, W>(Z, z, x, ihz));
             }
             const T Pz = T(g.two_dt) * zc + (cv - diff);
             const T d = T(g.two_dt) + cD * kk * ih2;

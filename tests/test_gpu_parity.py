@@ -38,6 +38,12 @@ def _cases():
         "energy-test-64x16": (I.Problem(nx=64, nz=16, closure=2, energy_test=1, n_bv=0.012), 5),
         "minimal-8x8": (I.thermal_stable_2d(8, 8), 6),
         "inviscid-lin-33x9": (I.Problem(nx=33, nz=9, closure=2, convection=0, n_bv=0.01), 7),
+        # 9-point stencil (p = 3): halo 8 in LDS, stress on a ring of 4
+        "stable-p3-200x100": (I.thermal_stable_2d(200, 100).replace(dd_p=3), 8),
+        "island-noslip-p3-130x36": (I.heat_island_2d(130, 36, h0=400.0, width=8000.0).replace(dd_p=3), 9),
+        "constK-periodic-p3-72x24": (I.Problem(nx=72, nz=24, closure=0, bc_lateral=2, bc_vertical=2, n_bv=0.01,
+                                               dd_p=3), 10),
+        "minimal-p3-8x9": (I.thermal_stable_2d(8, 9).replace(dd_p=3), 11),
     }
 
 
@@ -121,6 +127,8 @@ def test_jv_literal_within_rounding_bound():
 
 
 @pytest.mark.parametrize("name", ["neutral-130x70", "stable-200x100", "island-noslip-260x36",
+                                  "stable-p3-200x100", "island-noslip-p3-130x36", "constK-periodic-p3-72x24",
+                                  "minimal-p3-8x9",
                                   "constK-periodic-72x24", "minimal-8x8"])
 @pytest.mark.parametrize("sweeps", [0, 1, 2])
 def test_physics_pc(name, sweeps):
@@ -140,9 +148,10 @@ def test_physics_pc(name, sweeps):
     assert_fields_close(host(z32), ref32, F32_TOL, f"{name} pc{sweeps} f32")
 
 
+@pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("pc", ["physics", "none"])
-def test_gmres_fixed_iterations_f64(pc):
-    prob = I.thermal_stable_2d(96, 40)
+def test_gmres_fixed_iterations_f64(pc, p):
+    prob = I.thermal_stable_2d(96, 40).replace(dd_p=p)
     U = _state(prob, 21)
     b = I.random_vector(prob, seed=22)
     mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
@@ -175,8 +184,9 @@ def test_gmres_converges_and_estimate_is_true_residual():
     assert true <= 2e-8 * np.linalg.norm(b)
 
 
-def test_newton_step_f64_matches_oracle():
-    prob = I.thermal_neutral_2d(128, 64)
+@pytest.mark.parametrize("p", [2, 3])
+def test_newton_step_f64_matches_oracle(p):
+    prob = I.thermal_neutral_2d(128, 64).replace(dd_p=p)
     U0 = I.bubble_state(prob)
     ref, info = K.newton_step(prob, U0, K.NewtonOpts(rtol=1e-13))
     assert info.converged
