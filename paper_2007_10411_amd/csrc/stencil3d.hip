@@ -10,8 +10,9 @@
 //           ring of 2, written to an HBM buffer [9][nz+4][ny+4][nx+4];
 //   pass 2  per grid point: convection, pressure gradient, divergence, buoyancy
 //           and the divergences of tau and q.
-// Neighbour values are loaded through the caches with the parity mapping; one
-// thread per point, x fastest (coalesced rows).
+// Both passes march along z through LDS windows of 5 planes (k3m_*).  The
+// preconditioner kernels load their neighbour values through the caches with
+// the parity mapping, one thread per point, x fastest (coalesced rows).
 
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
@@ -23,8 +24,12 @@ namespace {
 __device__ __forceinline__ int map3(int e, int n, bool periodic, int& side) {
     side = 0;
     if (periodic) {
-        int r = e % n;
-        return r < 0 ? r + n : r;
+        int r = e < 0 ? e + n : (e >= n ? e - n : e);
+        if (r < 0 || r >= n) {
+            r = e % n;
+            r = r < 0 ? r + n : r;
+        }
+        return r;
     }
     if (e < 0) {
         side = 1;
@@ -135,29 +140,6 @@ __device__ __forceinline__ bool ext_point(const Geo& g, long long i, int& x, int
     return true;
 }
 
-// pass 1 of F: tau (6) and q (3) on the ring-2 extended grid
-template <typename T>
-__global__ __launch_bounds__(256) void k3_derived(Geo g, const T* __restrict__ u, T* __restrict__ d) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    int x, y, z;
-    if (!ext_point(g, i, x, y, z)) return;
-    T S[6], th[3];
-    strain3(g, u, x, y, z, S, th);
-    T nu, kth;
-    closure3(g, frob3(S, S), nu, kth);
-    const T third = (S[0] + S[1] + S[2]) / T(3);
-    const long long ne = (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4);
-    d[0 * ne + i] = T(2) * nu * (S[0] - third);
-    d[1 * ne + i] = T(2) * nu * (S[1] - third);
-    d[2 * ne + i] = T(2) * nu * (S[2] - third);
-    d[3 * ne + i] = T(2) * nu * S[3];
-    d[4 * ne + i] = T(2) * nu * S[4];
-    d[5 * ne + i] = T(2) * nu * S[5];
-    d[6 * ne + i] = kth * th[0];
-    d[7 * ne + i] = kth * th[1];
-    d[8 * ne + i] = kth * th[2];
-}
-
 // stress component index of (i, j)
 __device__ __forceinline__ int tix(int i, int j) {
     if (i == j) return i;
@@ -165,175 +147,410 @@ __device__ __forceinline__ int tix(int i, int j) {
     return a == 0 ? (b == 1 ? 3 : 4) : 5;
 }
 
-// pass 2 of F: out = F (what 0), 2u/dt + F (1), 2u/dt - F - f (2)
-template <typename T>
-__global__ __launch_bounds__(256) void k3_apply_F(Geo g, const T* __restrict__ u, const T* __restrict__ d,
-                                                  const T* __restrict__ f, T* __restrict__ out, int what) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= g.npts) return;
-    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    const long long np = g.npts;
-    T a[3], val[5];
+// ---------------------------------------------------------------------------
+// z-marching operator kernels.  A workgroup owns a TX x TY column of points and
+// walks through a chunk of kZC planes; a ring of 5 planes of the staged fields
+// (the tile grown by 2 in x and y, reflected ghosts included) lives in LDS, so
+// every neighbour along x, y and z of the 5-point derivative is an LDS read and
+// every state value is fetched from HBM once per workgroup (plus the x-y halo).
+// ---------------------------------------------------------------------------
+constexpr int kMTX = 32;       // points per workgroup along x
+constexpr int kZC = 16;        // planes per workgroup
+
+template <int TY> struct MarchGeom {
+    static constexpr int SX = kMTX + 4, SY = TY + 4, P = SX * SY;
+};
+
+// Register-staged copy of one plane of NF fields over the window region whose
+// (0, 0) is grid point (xa, ya): load() issues every global load of the plane
+// (reflected ghosts via the parity mapping, signs kept as bits), store() writes
+// them to LDS.  Issued one plane ahead, the loads run under the compute of the
+// current plane.  Fields 0..NS-1 come from state a, NS..2NS-1 from state b;
+// with SKIP_P the pressure is left out (field k is state field k < 3 ? k : 4).
+template <typename T, int NF, int TY, int NTHR, int NS, bool SKIP_P>
+struct Stager {
+    using MG = MarchGeom<TY>;
+    static constexpr int N = NF * MG::P;
+    static constexpr int IT = (N + NTHR - 1) / NTHR;
+    static_assert(IT <= 32, "sign bits");
+    T r[IT];
+    unsigned neg;
+    __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ a, const T* __restrict__ b, int xa,
+                                         int ya, int z) {
+        const bool lat = g.bcl == JFNK_BC_PERIODIC;
+        int sz;
+        const int mz = map3(z, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+        neg = 0u;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) val[k] = u[k * np + i];
-    a[0] = val[0];
-    a[1] = val[1];
-    a[2] = val[2];
-    T Fv[5] = {0, 0, 0, 0, 0};
-    if (g.convection) {
-        // C(a; phi) = 1/2 sum_j [D_j(a_j phi) + a_j D_j phi] for all fields
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int ex = j == 0, ey = j == 1, ez = j == 2;
-            const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
-            T am2 = ld(g, u, j, x - 2 * ex, y - 2 * ey, z - 2 * ez), am1 = ld(g, u, j, x - ex, y - ey, z - ez);
-            T ap1 = ld(g, u, j, x + ex, y + ey, z + ez), ap2 = ld(g, u, j, x + 2 * ex, y + 2 * ey, z + 2 * ez);
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const T pm2 = ld(g, u, k, x - 2 * ex, y - 2 * ey, z - 2 * ez);
-                const T pm1 = ld(g, u, k, x - ex, y - ey, z - ez);
-                const T pp1 = ld(g, u, k, x + ex, y + ey, z + ez);
-                const T pp2 = ld(g, u, k, x + 2 * ex, y + 2 * ey, z + 2 * ez);
-                const T flux = d5(am2 * pm2, am1 * pm1, ap1 * pp1, ap2 * pp2, ih);
-                const T adv = a[j] * d5(pm2, pm1, pp1, pp2, ih);
-                Fv[k] -= T(0.5) * (flux + adv);
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + it * NTHR;
+            if (idx < N) {
+                const int f = idx / MG::P, rr = idx - f * MG::P;
+                const int ly = rr / MG::SX, lx = rr - ly * MG::SX;
+                const int k = f < NS ? f : f - NS;
+                const int sf = SKIP_P && k == 3 ? 4 : k;
+                int sx, sy;
+                const int mx = map3(xa + lx, g.nx, lat, sx), my = map3(ya + ly, g.ny, lat, sy);
+                const T* src = f < NS ? a : b;
+                r[it] = src[(long long)sf * g.npts + ((long long)mz * g.ny + my) * g.nx + mx];
+                if (odd3(sf, sx, sy, sz, g.bcv)) neg |= 1u << it;
             }
         }
     }
-    const T th0 = T(g.theta0);
-    T div = T(0);
+    __device__ __forceinline__ void store(T* dst) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Fv[c] -= th0 * dfield(g, u, 3, c, x, y, z);
-        div += dfield(g, u, c, c, x, y, z);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Fv[c] += dext(g, d, tix(c, j), j, x, y, z);
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + it * NTHR;
+            if (idx < N) dst[idx] = (neg >> it) & 1u ? -r[it] : r[it];
+        }
     }
-    Fv[2] += T(g.g_theta0) * val[4];
-    const T* pb = Bg<T>::pbar(g);
-    const T* dpb = Bg<T>::dpbar(g);
-    if (g.energy_test)
-        Fv[3] -= T(g.kappa_cp) * div;
-    else
-        Fv[3] -= val[2] * dpb[z] + T(g.kappa) * (pb[z] + val[3]) * div;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Fv[4] += dext(g, d, 6 + j, j, x, y, z);
-    Fv[4] -= T(g.beta) * val[2];
-    if (z == 0 && !g.energy_test) Fv[4] += Bg<T>::sflux(g)[(long long)y * g.nx + x];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        T r;
-        if (what == 0) r = Fv[k];
-        else if (what == 1) r = T(g.two_dt) * val[k] + Fv[k];
-        else r = T(g.two_dt) * val[k] - Fv[k] - (f ? f[k * np + i] : T(0));
-        out[k * np + i] = r;
+};
+
+// Window accessor: field f at offset (ox, oy, oz) from the thread's point
+template <typename T, int TY>
+struct Win {
+    const T* slot[5];   // planes z-2 .. z+2
+    int c;              // in-plane index of the thread's point
+    __device__ __forceinline__ T at(int f, int ox, int oy, int oz) const {
+        using MG = MarchGeom<TY>;
+        return slot[oz + 2][f * MG::P + c + oy * MG::SX + ox];
     }
+    __device__ __forceinline__ T d(int f, int a, T ih) const {   // derivative along axis a
+        const int ex = a == 0, ey = a == 1, ez = a == 2;
+        return d5(at(f, -2 * ex, -2 * ey, -2 * ez), at(f, -ex, -ey, -ez), at(f, ex, ey, ez),
+                  at(f, 2 * ex, 2 * ey, 2 * ez), ih);
+    }
+};
+
+// gradient of the velocity (window fields 0..2) and of theta (window field 3)
+template <typename T, int TY>
+__device__ __forceinline__ void strain_win(const Geo& g, const Win<T, TY>& w, int f0, T S[6], T th[3]) {
+    const T ih[3] = {T(g.idx), T(g.idy), T(g.idz)};
+    T gr[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] = w.d(f0 + i, j, ih[j]);
+    S[0] = gr[0][0];
+    S[1] = gr[1][1];
+    S[2] = gr[2][2];
+    S[3] = T(0.5) * (gr[0][1] + gr[1][0]);
+    S[4] = T(0.5) * (gr[0][2] + gr[2][0]);
+    S[5] = T(0.5) * (gr[1][2] + gr[2][1]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) th[j] = w.d(f0 + 3, j, ih[j]);
 }
 
-// pass 1 of Jv: stress and heat-flux differences [tau(u + e v) - tau(u)]/e, etc.
-template <typename T>
-__global__ __launch_bounds__(256) void k3_jv_derived(Geo g, const T* __restrict__ u, const T* __restrict__ v,
-                                                     double eps_in, const double* __restrict__ eps_dev,
-                                                     T* __restrict__ d) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    int x, y, z;
-    if (!ext_point(g, i, x, y, z)) return;
-    const T e = T(eps_dev ? *eps_dev : eps_in);
-    T SU[6], SV[6], tU[3], tV[3];
-    strain3(g, u, x, y, z, SU, tU);
-    strain3(g, v, x, y, z, SV, tV);
-    T nua, ktha;
-    closure3(g, frob3(SU, SU), nua, ktha);
-    T SW[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) SW[k] = SU[k] + e * SV[k];
-    T dnu = T(0), dkth = T(0);
-    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-        const T den = sqrt(frob3(SU, SU)) + sqrt(frob3(SW, SW));
-        const T num = T(2) * frob3(SU, SV) + e * frob3(SV, SV);
-        dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
-        dkth = dnu * T(g.inv_pr);
+// Pass 1: tau (6) and q (3) on the ring-2 extended grid [9][nz+4][ny+4][nx+4],
+// or with PAIR their finite-difference differences for (u, v):
+// [tau(u + e v) - tau(u)] / e with the stable nu difference.
+template <typename T, bool PAIR>
+__global__ __launch_bounds__(256) void k3m_derived(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                                   double eps_in, const double* __restrict__ eps_dev,
+                                                   T* __restrict__ d) {
+    constexpr int TY = 8;
+    using MG = MarchGeom<TY>;
+    constexpr int NF = PAIR ? 8 : 4;
+    __shared__ T win[5 * NF * MG::P];
+    const int EX = g.nx + 4, EY = g.ny + 4, EZ = g.nz + 4;
+    const long long ne = (long long)EX * EY * EZ;
+    const int tx = threadIdx.x % kMTX, ty = threadIdx.x / kMTX;
+    const int xe = blockIdx.x * kMTX + tx, ye = blockIdx.y * TY + ty;
+    const int ze0 = blockIdx.z * kZC, ze1 = min(ze0 + kZC, EZ);
+    const bool mine = xe < EX && ye < EY;
+    // region origin: grid point (xe0 - 2) - 2 along x, likewise y
+    const int xa = blockIdx.x * kMTX - 4, ya = blockIdx.y * TY - 4;
+    const T e = PAIR ? T(eps_dev ? *eps_dev : eps_in) : T(0);
+    Stager<T, NF, TY, 256, 4, true> st;
+    // planes z - 2 .. z + 1 of the first point z = ze0 - 2, then z + 2 in flight
+    for (int k = 0; k < 4; ++k) {
+        st.load(g, u, v, xa, ya, ze0 - 4 + k);
+        st.store(win + k * NF * MG::P);
     }
-    const T trw = (SW[0] + SW[1] + SW[2]) / T(3), trv = (SV[0] + SV[1] + SV[2]) / T(3);
-    const long long ne = (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4);
+    st.load(g, u, v, xa, ya, ze0);
+    for (int ze = ze0; ze < ze1; ++ze) {
+        const int z = ze - 2;
+        const int r0 = ze - ze0;                 // ring slot of plane z - 2
+        st.store(win + ((r0 + 4) % 5) * NF * MG::P);
+        __syncthreads();
+        if (ze + 1 < ze1) st.load(g, u, v, xa, ya, z + 3);
+        if (mine) {
+            Win<T, TY> w;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const T dw = k < 3 ? SW[k] - trw : SW[k];
-        const T dv = k < 3 ? SV[k] - trv : SV[k];
-        d[k * ne + i] = T(2) * dnu * dw + T(2) * nua * dv;
-    }
+            for (int k = 0; k < 5; ++k) w.slot[k] = win + ((r0 + k) % 5) * NF * MG::P;
+            w.c = (ty + 2) * MG::SX + tx + 2;
+            const long long i = ((long long)ze * EY + ye) * EX + xe;
+            if (!PAIR) {
+                T S[6], th[3];
+                strain_win<T, TY>(g, w, 0, S, th);
+                T nu, kth;
+                closure3(g, frob3(S, S), nu, kth);
+                const T third = (S[0] + S[1] + S[2]) / T(3);
+                d[0 * ne + i] = T(2) * nu * (S[0] - third);
+                d[1 * ne + i] = T(2) * nu * (S[1] - third);
+                d[2 * ne + i] = T(2) * nu * (S[2] - third);
+                d[3 * ne + i] = T(2) * nu * S[3];
+                d[4 * ne + i] = T(2) * nu * S[4];
+                d[5 * ne + i] = T(2) * nu * S[5];
+                d[6 * ne + i] = kth * th[0];
+                d[7 * ne + i] = kth * th[1];
+                d[8 * ne + i] = kth * th[2];
+            } else {
+                T SU[6], SV[6], tU[3], tV[3];
+                strain_win<T, TY>(g, w, 0, SU, tU);
+                strain_win<T, TY>(g, w, 4, SV, tV);
+                T nua, ktha;
+                closure3(g, frob3(SU, SU), nua, ktha);
+                T SW[6];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) d[(6 + j) * ne + i] = dkth * (tU[j] + e * tV[j]) + ktha * tV[j];
-}
-
-// pass 2 of Jv: 2v/dt - [F(u + e v) - F(u)]/e with bilinear terms expanded
-template <typename T>
-__global__ __launch_bounds__(256) void k3_jv(Geo g, const T* __restrict__ u, const T* __restrict__ v,
-                                             double eps_in, const double* __restrict__ eps_dev,
-                                             const T* __restrict__ d, T* __restrict__ out) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= g.npts) return;
-    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    const long long np = g.npts;
-    const T e = T(eps_dev ? *eps_dev : eps_in);
-    T A[5], B[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        A[k] = u[k * np + i];
-        B[k] = v[k * np + i];
-    }
-    T dF[5] = {0, 0, 0, 0, 0};
-    if (g.convection) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int ex = j == 0, ey = j == 1, ez = j == 2;
-            const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
-            const int ox[4] = {-2, -1, 1, 2};
-            T au[4], bv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                au[q] = ld(g, u, j, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
-                bv[q] = ld(g, v, j, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
-            }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                T pa[4], pbv[4], pr[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    pa[q] = ld(g, u, k, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
-                    pbv[q] = ld(g, v, k, x + ox[q] * ex, y + ox[q] * ey, z + ox[q] * ez);
-                    pr[q] = au[q] * pbv[q] + bv[q] * (pa[q] + e * pbv[q]);
+                for (int k = 0; k < 6; ++k) SW[k] = SU[k] + e * SV[k];
+                T dnu = T(0), dkth = T(0);
+                if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+                    const T den = sqrt(frob3(SU, SU)) + sqrt(frob3(SW, SW));
+                    const T num = T(2) * frob3(SU, SV) + e * frob3(SV, SV);
+                    dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+                    dkth = dnu * T(g.inv_pr);
                 }
-                const T flux = d5(pr[0], pr[1], pr[2], pr[3], ih);
-                const T dA = d5(pa[0], pa[1], pa[2], pa[3], ih), dB = d5(pbv[0], pbv[1], pbv[2], pbv[3], ih);
-                const T adv = A[j] * dB + B[j] * (dA + e * dB);
-                dF[k] -= T(0.5) * (flux + adv);
+                const T trw = (SW[0] + SW[1] + SW[2]) / T(3), trv = (SV[0] + SV[1] + SV[2]) / T(3);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const T dw = k < 3 ? SW[k] - trw : SW[k];
+                    const T dv = k < 3 ? SV[k] - trv : SV[k];
+                    d[k * ne + i] = T(2) * dnu * dw + T(2) * nua * dv;
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j) d[(6 + j) * ne + i] = dkth * (tU[j] + e * tV[j]) + ktha * tV[j];
             }
         }
+        __syncthreads();
     }
-    const T th0 = T(g.theta0);
-    T divA = T(0), divB = T(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        dF[c] -= th0 * dfield(g, v, 3, c, x, y, z);
-        divA += dfield(g, u, c, c, x, y, z);
-        divB += dfield(g, v, c, c, x, y, z);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) dF[c] += dext(g, d, tix(c, j), j, x, y, z);
+}
+
+// In-plane derived components staged per plane: xx, yy, xy, xz, yz, qx, qy
+// (slots 0..6); the z-derivatives take xz, yz, zz, qz from a per-thread queue.
+__device__ __forceinline__ int dplane_slot(int comp) {
+    return comp == 0 ? 0 : comp == 1 ? 1 : comp == 3 ? 2 : comp == 4 ? 3 : comp == 5 ? 4 : comp == 6 ? 5 : 6;
+}
+// five consecutive planes of one value, oldest first
+template <typename T> struct Q5 {
+    T m2, m1, c0, p1, p2;
+    __device__ __forceinline__ void push(T x) {
+        m2 = m1;
+        m1 = c0;
+        c0 = p1;
+        p1 = p2;
+        p2 = x;
     }
-    dF[2] += T(g.g_theta0) * B[4];
-    const T* pb = Bg<T>::pbar(g);
-    const T* dpb = Bg<T>::dpbar(g);
-    if (g.energy_test)
-        dF[3] -= T(g.kappa_cp) * divB;
-    else
-        dF[3] -= B[2] * dpb[z] + T(g.kappa) * ((pb[z] + A[3]) * divB + B[3] * divA + e * B[3] * divB);
+};
+constexpr int kDPlane[7] = {0, 1, 3, 4, 5, 6, 7};
+constexpr int kDQueue[4] = {4, 5, 2, 8};
+
+// Pass 2 (per grid point).  MODE 0: out = F (what 0), 2u/dt + F (1) or
+// 2u/dt - F - f (2) of state u; MODE 1: Jv = 2v/dt - [F(u + e v) - F(u)]/e with
+// the bilinear terms expanded (d holds the derived differences).
+template <typename T, int MODE, int TY>
+__global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                                 double eps_in, const double* __restrict__ eps_dev,
+                                                 const T* __restrict__ d, const T* __restrict__ f,
+                                                 T* __restrict__ out, int what) {
+    using MG = MarchGeom<TY>;
+    constexpr int NF = MODE == 1 ? 10 : 5;
+    __shared__ T win[5 * NF * MG::P];
+    __shared__ T dpl[7 * MG::P];
+    const int EX = g.nx + 4, EY = g.ny + 4;
+    const long long ne = (long long)EX * EY * (g.nz + 4);
+    const long long np = g.npts;
+    constexpr int NTHR = kMTX * TY;
+    const int tx = threadIdx.x % kMTX, ty = threadIdx.x / kMTX;
+    const int x = blockIdx.x * kMTX + tx, y = blockIdx.y * TY + ty;
+    const int z0 = blockIdx.z * kZC, z1 = min(z0 + kZC, g.nz);
+    const bool mine = x < g.nx && y < g.ny;
+    const int xa = blockIdx.x * kMTX - 2, ya = blockIdx.y * TY - 2;
+    const T e = MODE == 1 ? T(eps_dev ? *eps_dev : eps_in) : T(0);
+    const T ih[3] = {T(g.idx), T(g.idy), T(g.idz)};
+    // clamped ext-grid columns (points outside the grid never read them)
+    auto dcol = [&](int xx, int yy) {
+        return (long long)min(max(yy + 2, 0), EY - 1) * EX + min(max(xx + 2, 0), EX - 1);
+    };
+    const long long pe = (long long)EX * EY;
+    const long long mycol = dcol(x, y);
+    // in-plane derived components of one plane over the region, one plane ahead
+    constexpr int DN = 7 * MG::P, DIT = (DN + NTHR - 1) / NTHR;
+    T dr[DIT];
+    auto dload = [&](int zz) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) dF[4] += dext(g, d, 6 + j, j, x, y, z);
-    dF[4] -= T(g.beta) * B[2];
-    const T tdt = T(g.two_dt);
+        for (int it = 0; it < DIT; ++it) {
+            const int idx = (int)threadIdx.x + it * NTHR;
+            if (idx < DN) {
+                const int sl = idx / MG::P, rr = idx - sl * MG::P;
+                const int ly = rr / MG::SX, lx = rr - ly * MG::SX;
+                dr[it] = d[kDPlane[sl] * ne + (zz + 2) * pe + dcol(xa + lx, ya + ly)];
+            }
+        }
+    };
+    // z queue of xz, yz, zz, qz at z - 2 .. z + 2 (named registers), the next
+    // plane in qn
+    Q5<T> q[4];
+    T qn[4];
+    auto qload = [&](int zz) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) out[k * np + i] = tdt * B[k] - dF[k];
+        for (int c = 0; c < 4; ++c) qn[c] = d[kDQueue[c] * ne + (zz + 2) * pe + mycol];
+    };
+    Stager<T, NF, TY, NTHR, 5, false> st;
+    for (int k = 0; k < 4; ++k) {
+        st.load(g, u, v, xa, ya, z0 - 2 + k);
+        st.store(win + k * NF * MG::P);
+        qload(z0 - 2 + k);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[c].push(qn[c]);
+    }
+    st.load(g, u, v, xa, ya, z0 + 2);
+    dload(z0);
+    qload(z0 + 2);
+    for (int z = z0; z < z1; ++z) {
+        const int r0 = z - z0;
+        st.store(win + ((r0 + 4) % 5) * NF * MG::P);
+#pragma unroll
+        for (int it = 0; it < DIT; ++it) {
+            const int idx = (int)threadIdx.x + it * NTHR;
+            if (idx < DN) dpl[idx] = dr[it];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[c].push(qn[c]);
+        __syncthreads();
+        if (z + 1 < z1) {
+            st.load(g, u, v, xa, ya, z + 3);
+            dload(z + 1);
+            qload(z + 3);
+        }
+        if (mine) {
+            Win<T, TY> wa, wb;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                wa.slot[k] = win + ((r0 + k) % 5) * NF * MG::P;
+                wb.slot[k] = wa.slot[k] + 5 * MG::P;
+            }
+            wa.c = wb.c = (ty + 2) * MG::SX + tx + 2;
+            // derivative of derived component comp along axis j at the point
+            auto dd = [&](int comp, int j) -> T {
+                if (j == 2) {
+                    const Q5<T>& qq = comp == 4 ? q[0] : comp == 5 ? q[1] : comp == 2 ? q[2] : q[3];
+                    return d5(qq.m2, qq.m1, qq.p1, qq.p2, ih[2]);
+                }
+                const T* pl = dpl + dplane_slot(comp) * MG::P + wa.c;
+                const int st = j == 0 ? 1 : MG::SX;
+                return d5(pl[-2 * st], pl[-st], pl[st], pl[2 * st], ih[j]);
+            };
+            const long long i = ((long long)z * g.ny + y) * g.nx + x;
+            const T th0 = T(g.theta0);
+            const T* pb = Bg<T>::pbar(g);
+            const T* dpb = Bg<T>::dpbar(g);
+            if (MODE == 0) {
+                T val[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) val[k] = wa.at(k, 0, 0, 0);
+                T Fv[5] = {0, 0, 0, 0, 0};
+                if (g.convection) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int ex = j == 0, ey = j == 1, ez = j == 2;
+                        const T am2 = wa.at(j, -2 * ex, -2 * ey, -2 * ez), am1 = wa.at(j, -ex, -ey, -ez);
+                        const T ap1 = wa.at(j, ex, ey, ez), ap2 = wa.at(j, 2 * ex, 2 * ey, 2 * ez);
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            const T pm2 = wa.at(k, -2 * ex, -2 * ey, -2 * ez), pm1 = wa.at(k, -ex, -ey, -ez);
+                            const T pp1 = wa.at(k, ex, ey, ez), pp2 = wa.at(k, 2 * ex, 2 * ey, 2 * ez);
+                            const T flux = d5(am2 * pm2, am1 * pm1, ap1 * pp1, ap2 * pp2, ih[j]);
+                            const T adv = val[j] * d5(pm2, pm1, pp1, pp2, ih[j]);
+                            Fv[k] -= T(0.5) * (flux + adv);
+                        }
+                    }
+                }
+                T div = T(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Fv[c] -= th0 * wa.d(3, c, ih[c]);
+                    div += wa.d(c, c, ih[c]);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Fv[c] += dd(tix(c, j), j);
+                }
+                Fv[2] += T(g.g_theta0) * val[4];
+                if (g.energy_test)
+                    Fv[3] -= T(g.kappa_cp) * div;
+                else
+                    Fv[3] -= val[2] * dpb[z] + T(g.kappa) * (pb[z] + val[3]) * div;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Fv[4] += dd(6 + j, j);
+                Fv[4] -= T(g.beta) * val[2];
+                if (z == 0 && !g.energy_test) Fv[4] += Bg<T>::sflux(g)[(long long)y * g.nx + x];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    T r;
+                    if (what == 0) r = Fv[k];
+                    else if (what == 1) r = T(g.two_dt) * val[k] + Fv[k];
+                    else r = T(g.two_dt) * val[k] - Fv[k] - (f ? f[k * np + i] : T(0));
+                    out[k * np + i] = r;
+                }
+            } else {
+                T A[5], B[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    A[k] = wa.at(k, 0, 0, 0);
+                    B[k] = wb.at(k, 0, 0, 0);
+                }
+                T dF[5] = {0, 0, 0, 0, 0};
+                if (g.convection) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int ex = j == 0, ey = j == 1, ez = j == 2;
+                        const int ox[4] = {-2, -1, 1, 2};
+                        T au[4], bv[4];
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) {
+                            au[qq] = wa.at(j, ox[qq] * ex, ox[qq] * ey, ox[qq] * ez);
+                            bv[qq] = wb.at(j, ox[qq] * ex, ox[qq] * ey, ox[qq] * ez);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            T pa[4], pbv[4], pr[4];
+#pragma unroll
+                            for (int qq = 0; qq < 4; ++qq) {
+                                pa[qq] = wa.at(k, ox[qq] * ex, ox[qq] * ey, ox[qq] * ez);
+                                pbv[qq] = wb.at(k, ox[qq] * ex, ox[qq] * ey, ox[qq] * ez);
+                                pr[qq] = au[qq] * pbv[qq] + bv[qq] * (pa[qq] + e * pbv[qq]);
+                            }
+                            const T flux = d5(pr[0], pr[1], pr[2], pr[3], ih[j]);
+                            const T dA = d5(pa[0], pa[1], pa[2], pa[3], ih[j]);
+                            const T dB = d5(pbv[0], pbv[1], pbv[2], pbv[3], ih[j]);
+                            const T adv = A[j] * dB + B[j] * (dA + e * dB);
+                            dF[k] -= T(0.5) * (flux + adv);
+                        }
+                    }
+                }
+                T divA = T(0), divB = T(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dF[c] -= th0 * wb.d(3, c, ih[c]);
+                    divA += wa.d(c, c, ih[c]);
+                    divB += wb.d(c, c, ih[c]);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) dF[c] += dd(tix(c, j), j);
+                }
+                dF[2] += T(g.g_theta0) * B[4];
+                if (g.energy_test)
+                    dF[3] -= T(g.kappa_cp) * divB;
+                else
+                    dF[3] -= B[2] * dpb[z] + T(g.kappa) * ((pb[z] + A[3]) * divB + B[3] * divA + e * B[3] * divB);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dF[4] += dd(6 + j, j);
+                dF[4] -= T(g.beta) * B[2];
+                const T tdt = T(g.two_dt);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) out[k * np + i] = tdt * B[k] - dF[k];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // frozen eddy viscosity on the ring-2 extended grid
@@ -466,22 +683,35 @@ inline long long next3(const Geo& g) { return (long long)(g.nx + 4) * (g.ny + 4)
 
 }  // namespace
 
-template <typename T>
-hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, T* dbuf, hipStream_t s) {
-    hipLaunchKernelGGL((k3_derived<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, dbuf);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k3_apply_F<T>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, (const T*)dbuf, f, out, what);
-    return hipGetLastError();
+inline dim3 march_grid(int nx, int ny, int nz, int ty) {
+    return dim3((nx + kMTX - 1) / kMTX, (ny + ty - 1) / ty, (nz + kZC - 1) / kZC);
 }
 
 template <typename T>
-hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
-                      hipStream_t s) {
-    hipLaunchKernelGGL((k3_jv_derived<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, v, eps, eps_dev, dbuf);
+hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, T* dbuf, hipStream_t s) {
+    hipLaunchKernelGGL((k3m_derived<T, false>), march_grid(g.nx + 4, g.ny + 4, g.nz + 4, 8), dim3(256), 0, s, g, u,
+                       (const T*)nullptr, 0.0, (const double*)nullptr, dbuf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k3_jv<T>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, v, eps, eps_dev, (const T*)dbuf, out);
+    hipLaunchKernelGGL((k3m_point<T, 0, 8>), march_grid(g.nx, g.ny, g.nz, 8), dim3(256), 0, s, g, u,
+                       (const T*)nullptr, 0.0, (const double*)nullptr, (const T*)dbuf, f, out, what);
+    return hipGetLastError();
+}
+
+// FP64 Jv points use 32 x 4 columns (LDS)
+template <typename T>
+hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k3m_derived<T, true>), march_grid(g.nx + 4, g.ny + 4, g.nz + 4, 8), dim3(256), 0, s, g, u, v,
+                       eps, eps_dev, dbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k3m_point<T, 1, 4>), march_grid(g.nx, g.ny, g.nz, 4), dim3(128), 0, s, g, u, v, eps,
+                           eps_dev, (const T*)dbuf, (const T*)nullptr, out, 0);
+    else
+        hipLaunchKernelGGL((k3m_point<T, 1, 8>), march_grid(g.nx, g.ny, g.nz, 8), dim3(256), 0, s, g, u, v, eps,
+                           eps_dev, (const T*)dbuf, (const T*)nullptr, out, 0);
     return hipGetLastError();
 }
 
