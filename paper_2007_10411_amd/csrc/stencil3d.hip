@@ -162,46 +162,70 @@ template <int TY> struct MarchGeom {
 };
 
 // Register-staged copy of one plane of NF fields over the window region whose
-// (0, 0) is grid point (xa, ya): load() issues every global load of the plane
-// (reflected ghosts via the parity mapping, signs kept as bits), store() writes
-// them to LDS.  Issued one plane ahead, the loads run under the compute of the
-// current plane.  Fields 0..NS-1 come from state a, NS..2NS-1 from state b;
-// with SKIP_P the pressure is left out (field k is state field k < 3 ? k : 4).
+// (0, 0) is grid point (xa, ya).  Each thread owns fixed in-plane positions of
+// the region (idx = threadIdx.x + p NTHR), so their reflected source offsets and
+// the x/y parity signs are computed once (init); per plane only the z mapping
+// changes.  load() issues every global load of a plane, store() writes it to
+// LDS as [field][position]; issued one plane ahead, the loads run under the
+// compute of the current plane.  Fields 0..NS-1 come from state a, NS..2NS-1
+// from state b; with SKIP_P the pressure is left out (field k is state field
+// k < 3 ? k : 4).
 template <typename T, int NF, int TY, int NTHR, int NS, bool SKIP_P>
 struct Stager {
     using MG = MarchGeom<TY>;
-    static constexpr int N = NF * MG::P;
-    static constexpr int IT = (N + NTHR - 1) / NTHR;
-    static_assert(IT <= 32, "sign bits");
-    T r[IT];
-    unsigned neg;
-    __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ a, const T* __restrict__ b, int xa,
-                                         int ya, int z) {
+    static constexpr int POS = (MG::P + NTHR - 1) / NTHR;
+    static_assert(NF <= 32, "sign bits");
+    int off[POS];          // in-plane source index (0 for positions past the region)
+    unsigned xyneg[POS];   // fields negated by the x/y reflection
+    unsigned zneg;         // fields negated by the z reflection of the loaded plane
+    T r[POS][NF];
+    __device__ __forceinline__ static int sfield(int f) {
+        const int k = f < NS ? f : f - NS;
+        return SKIP_P && k == 3 ? 4 : k;
+    }
+    __device__ __forceinline__ void init(const Geo& g, int xa, int ya) {
         const bool lat = g.bcl == JFNK_BC_PERIODIC;
-        int sz;
-        const int mz = map3(z, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
-        neg = 0u;
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int idx = (int)threadIdx.x + it * NTHR;
-            if (idx < N) {
-                const int f = idx / MG::P, rr = idx - f * MG::P;
-                const int ly = rr / MG::SX, lx = rr - ly * MG::SX;
-                const int k = f < NS ? f : f - NS;
-                const int sf = SKIP_P && k == 3 ? 4 : k;
+        for (int p = 0; p < POS; ++p) {
+            const int idx = (int)threadIdx.x + p * NTHR;
+            off[p] = 0;
+            xyneg[p] = 0u;
+            if (idx < MG::P) {
+                const int ly = idx / MG::SX, lx = idx - ly * MG::SX;
                 int sx, sy;
                 const int mx = map3(xa + lx, g.nx, lat, sx), my = map3(ya + ly, g.ny, lat, sy);
-                const T* src = f < NS ? a : b;
-                r[it] = src[(long long)sf * g.npts + ((long long)mz * g.ny + my) * g.nx + mx];
-                if (odd3(sf, sx, sy, sz, g.bcv)) neg |= 1u << it;
+                off[p] = my * g.nx + mx;
+                unsigned m = 0u;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    if (odd3(sfield(f), sx, sy, 0, g.bcv)) m |= 1u << f;
+                xyneg[p] = m;
             }
         }
     }
+    __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ a, const T* __restrict__ b, int z) {
+        int sz;
+        const int mz = map3(z, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+        const long long pl = (long long)mz * g.nx * g.ny;
+        unsigned m = 0u;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (odd3(sfield(f), 0, 0, sz, g.bcv)) m |= 1u << f;
+            const T* base = (f < NS ? a : b) + (long long)sfield(f) * g.npts + pl;
+#pragma unroll
+            for (int p = 0; p < POS; ++p) r[p][f] = base[off[p]];
+        }
+        zneg = m;
+    }
     __device__ __forceinline__ void store(T* dst) const {
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int idx = (int)threadIdx.x + it * NTHR;
-            if (idx < N) dst[idx] = (neg >> it) & 1u ? -r[it] : r[it];
+        for (int p = 0; p < POS; ++p) {
+            const int idx = (int)threadIdx.x + p * NTHR;
+            if (idx < MG::P) {
+                const unsigned m = xyneg[p] ^ zneg;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) dst[f * MG::P + idx] = (m >> f) & 1u ? -r[p][f] : r[p][f];
+            }
         }
     }
 };
@@ -262,18 +286,19 @@ __global__ __launch_bounds__(256) void k3m_derived(Geo g, const T* __restrict__ 
     const int xa = blockIdx.x * kMTX - 4, ya = blockIdx.y * TY - 4;
     const T e = PAIR ? T(eps_dev ? *eps_dev : eps_in) : T(0);
     Stager<T, NF, TY, 256, 4, true> st;
+    st.init(g, xa, ya);
     // planes z - 2 .. z + 1 of the first point z = ze0 - 2, then z + 2 in flight
     for (int k = 0; k < 4; ++k) {
-        st.load(g, u, v, xa, ya, ze0 - 4 + k);
+        st.load(g, u, v, ze0 - 4 + k);
         st.store(win + k * NF * MG::P);
     }
-    st.load(g, u, v, xa, ya, ze0);
+    st.load(g, u, v, ze0);
     for (int ze = ze0; ze < ze1; ++ze) {
         const int z = ze - 2;
         const int r0 = ze - ze0;                 // ring slot of plane z - 2
         st.store(win + ((r0 + 4) % 5) * NF * MG::P);
         __syncthreads();
-        if (ze + 1 < ze1) st.load(g, u, v, xa, ya, z + 3);
+        if (ze + 1 < ze1) st.load(g, u, v, z + 3);
         if (mine) {
             Win<T, TY> w;
 #pragma unroll
@@ -375,17 +400,22 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
     const long long pe = (long long)EX * EY;
     const long long mycol = dcol(x, y);
     // in-plane derived components of one plane over the region, one plane ahead
-    constexpr int DN = 7 * MG::P, DIT = (DN + NTHR - 1) / NTHR;
-    T dr[DIT];
+    // (fixed positions per thread as in Stager)
+    constexpr int DPOS = (MG::P + NTHR - 1) / NTHR;
+    int doff[DPOS];
+#pragma unroll
+    for (int p = 0; p < DPOS; ++p) {
+        const int idx = min((int)threadIdx.x + p * NTHR, MG::P - 1);
+        const int ly = idx / MG::SX, lx = idx - ly * MG::SX;
+        doff[p] = (int)dcol(xa + lx, ya + ly);
+    }
+    T dr[DPOS][7];
     auto dload = [&](int zz) {
 #pragma unroll
-        for (int it = 0; it < DIT; ++it) {
-            const int idx = (int)threadIdx.x + it * NTHR;
-            if (idx < DN) {
-                const int sl = idx / MG::P, rr = idx - sl * MG::P;
-                const int ly = rr / MG::SX, lx = rr - ly * MG::SX;
-                dr[it] = d[kDPlane[sl] * ne + (zz + 2) * pe + dcol(xa + lx, ya + ly)];
-            }
+        for (int sl = 0; sl < 7; ++sl) {
+            const T* base = d + kDPlane[sl] * ne + (zz + 2) * pe;
+#pragma unroll
+            for (int p = 0; p < DPOS; ++p) dr[p][sl] = base[doff[p]];
         }
     };
     // z queue of xz, yz, zz, qz at z - 2 .. z + 2 (named registers), the next
@@ -397,29 +427,33 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
         for (int c = 0; c < 4; ++c) qn[c] = d[kDQueue[c] * ne + (zz + 2) * pe + mycol];
     };
     Stager<T, NF, TY, NTHR, 5, false> st;
+    st.init(g, xa, ya);
     for (int k = 0; k < 4; ++k) {
-        st.load(g, u, v, xa, ya, z0 - 2 + k);
+        st.load(g, u, v, z0 - 2 + k);
         st.store(win + k * NF * MG::P);
         qload(z0 - 2 + k);
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[c].push(qn[c]);
     }
-    st.load(g, u, v, xa, ya, z0 + 2);
+    st.load(g, u, v, z0 + 2);
     dload(z0);
     qload(z0 + 2);
     for (int z = z0; z < z1; ++z) {
         const int r0 = z - z0;
         st.store(win + ((r0 + 4) % 5) * NF * MG::P);
 #pragma unroll
-        for (int it = 0; it < DIT; ++it) {
-            const int idx = (int)threadIdx.x + it * NTHR;
-            if (idx < DN) dpl[idx] = dr[it];
+        for (int p = 0; p < DPOS; ++p) {
+            const int idx = (int)threadIdx.x + p * NTHR;
+            if (idx < MG::P) {
+#pragma unroll
+                for (int sl = 0; sl < 7; ++sl) dpl[sl * MG::P + idx] = dr[p][sl];
+            }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[c].push(qn[c]);
         __syncthreads();
         if (z + 1 < z1) {
-            st.load(g, u, v, xa, ya, z + 3);
+            st.load(g, u, v, z + 3);
             dload(z + 1);
             qload(z + 3);
         }
