@@ -119,24 +119,62 @@ __device__ __forceinline__ T dz_prod(const T* a, const T* b, int z, int x, T ih)
     return dtaps<W>([&](int o) { return ra[o * S] * rb[o * S]; }, ih);
 }
 
+// Threads per tile workgroup (every tile kernel is launched with this many).
+constexpr int kTileThreads = 256;
+
+// Copy of the n-field state (field stride np) with halo H, held in registers
+// between load() and store(): load() issues all global loads of the tile (the
+// reflected ghosts by the parity mapping) before any LDS store, so their
+// latencies overlap; store() writes LDS s[f][SZ][SX].
+template <typename T, int TX, int TZ, int NFL, int H>
+struct TileStage {
+    static constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H, N = SZ * SX;
+    static constexpr int IT = (N + kTileThreads - 1) / kTileThreads;
+    static constexpr int NW = (IT * NFL + 31) / 32;
+    T r[IT][NFL];
+    unsigned neg[NW];   // sign bits, bit (it NFL + f)
+    __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ u, int x0, int z0, int f_first) {
+        const long long np = g.npts;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) neg[w] = 0u;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = min((int)threadIdx.x + it * kTileThreads, N - 1);
+            const int lz = idx / SX, lx = idx - lz * SX;
+            int sx, sz;
+            const int gx = map_axis(x0 + lx - H, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
+            const int gz = map_axis(z0 + lz - H, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+            const long long off = (long long)gz * g.nx + gx;
+#pragma unroll
+            for (int f = 0; f < NFL; ++f) {
+                r[it][f] = u[(long long)(f_first + f) * np + off];
+                const int b = it * NFL + f;
+                if (sign2d(f_first + f, sx, sz, g.bcv) < 0) neg[b / 32] |= 1u << (b % 32);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T* s) const {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + it * kTileThreads;
+            if (idx < N) {
+#pragma unroll
+                for (int f = 0; f < NFL; ++f) {
+                    const int b = it * NFL + f;
+                    s[f * N + idx] = (neg[b / 32] >> (b % 32)) & 1u ? -r[it][f] : r[it][f];
+                }
+            }
+        }
+    }
+};
+
 // Stage the n-field state (field stride np) with halo H into LDS s[f][SZ][SX].
 template <typename T, int TX, int TZ, int NFL, int H = kHalo>
 __device__ __forceinline__ void stage_fields(const Geo& g, const T* __restrict__ u, T* s, int x0, int z0,
                                              int f_first) {
-    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
-    const long long np = g.npts;
-    for (int idx = threadIdx.x; idx < SZ * SX; idx += blockDim.x) {
-        const int lz = idx / SX, lx = idx - (idx / SX) * SX;
-        int sx, sz;
-        const int gx = map_axis(x0 + lx - H, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
-        const int gz = map_axis(z0 + lz - H, g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
-        const long long off = (long long)gz * g.nx + gx;
-#pragma unroll
-        for (int f = 0; f < NFL; ++f) {
-            const T v = u[(long long)(f_first + f) * np + off];
-            s[f * SZ * SX + idx] = sign2d(f_first + f, sx, sz, g.bcv) < 0 ? -v : v;
-        }
-    }
+    TileStage<T, TX, TZ, NFL, H> st;
+    st.load(g, u, x0, z0, f_first);
+    st.store(s);
 }
 
 template <typename T>
@@ -268,8 +306,13 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
     const T ihx = T(g.idx), ihz = T(g.idz);
     const T e = T(eps_dev ? *eps_dev : eps_in);
 
-    stage_fields<T, TX, TZ, 4, H>(g, u, sa, x0, z0, 0);
-    stage_fields<T, TX, TZ, 4, H>(g, v, sb, x0, z0, 0);
+    {
+        TileStage<T, TX, TZ, 4, H> st_a, st_b;
+        st_a.load(g, u, x0, z0, 0);
+        st_b.load(g, v, x0, z0, 0);
+        st_a.store(sa);
+        st_b.store(sb);
+    }
     __syncthreads();
 
     const T *ua = sa, *wa = sa + PS, *pa = sa + 2 * PS, *ta = sa + 3 * PS;
@@ -471,19 +514,39 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
     const T ihx = T(g.idx), ihz = T(g.idz);
     const long long np = g.npts;
 
-    stage_fields<T, TX, TZ, 4, H>(g, zin, sz_, x0, z0, 0);
-    for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
-        const int lz = idx / DX, lx = idx - (idx / DX) * DX;
-        int sx, szd;
-        const int gx = map_axis(x0 + lx - W, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
-        const int gz = map_axis(z0 + lz - W, g.nz, g.bcv == JFNK_BC_PERIODIC, szd);
-        const long long off = (long long)gz * g.nx + gx;
-        const T a0 = u[off], a1 = u[np + off];
-        sv[idx] = sign2d(0, sx, szd, g.bcv) < 0 ? -a0 : a0;
-        sv[DS + idx] = sign2d(1, sx, szd, g.bcv) < 0 ? -a1 : a1;
-        // extended viscosity: row gz + W of the (nz + 2W) x (nx + 2W) ring-W grid
-        const int ex = min(max(x0 + lx, 0), g.nx + 2 * W - 1), ez = min(max(z0 + lz, 0), g.nz + 2 * W - 1);
-        sn[idx] = nu[(long long)ez * (g.nx + 2 * W) + ex];
+    {
+        // every global load of the tile issued before the LDS stores
+        TileStage<T, TX, TZ, 4, H> st;
+        st.load(g, zin, x0, z0, 0);
+        constexpr int DIT = (DS + kTileThreads - 1) / kTileThreads;
+        T a0[DIT], a1[DIT], nn[DIT];
+        unsigned sgn = 0u;
+#pragma unroll
+        for (int it = 0; it < DIT; ++it) {
+            const int idx = min((int)threadIdx.x + it * kTileThreads, DS - 1);
+            const int lz = idx / DX, lx = idx - lz * DX;
+            int sx, szd;
+            const int gx = map_axis(x0 + lx - W, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
+            const int gz = map_axis(z0 + lz - W, g.nz, g.bcv == JFNK_BC_PERIODIC, szd);
+            const long long off = (long long)gz * g.nx + gx;
+            a0[it] = u[off];
+            a1[it] = u[np + off];
+            if (sign2d(0, sx, szd, g.bcv) < 0) sgn |= 1u << (2 * it);
+            if (sign2d(1, sx, szd, g.bcv) < 0) sgn |= 1u << (2 * it + 1);
+            // extended viscosity: row gz + W of the (nz + 2W) x (nx + 2W) ring-W grid
+            const int ex = min(max(x0 + lx, 0), g.nx + 2 * W - 1), ez = min(max(z0 + lz, 0), g.nz + 2 * W - 1);
+            nn[it] = nu[(long long)ez * (g.nx + 2 * W) + ex];
+        }
+        st.store(sz_);
+#pragma unroll
+        for (int it = 0; it < DIT; ++it) {
+            const int idx = (int)threadIdx.x + it * kTileThreads;
+            if (idx < DS) {
+                sv[idx] = (sgn >> (2 * it)) & 1u ? -a0[it] : a0[it];
+                sv[DS + idx] = (sgn >> (2 * it + 1)) & 1u ? -a1[it] : a1[it];
+                sn[idx] = nn[it];
+            }
+        }
     }
     __syncthreads();
 
