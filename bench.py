@@ -228,6 +228,13 @@ def synth_state(torch, prob, seed=0):
     return U.reshape(-1)
 
 
+def jv_kernel_name(rows):
+    """Name of the FP32 Jv kernel of an autotuned launch shape (rows per workgroup)."""
+    if rows >= 32:
+        return f"k_march_2d<float, W, true> ({rows}-row chunks of 64-column strips)"
+    return f"k_jv_2d<float, 64, {rows}>"
+
+
 def kernel_micro(torch, I, L, Context, reps):
     """Residual and Jv kernels alone at sizes beyond the Infinity Cache."""
     out = {}
@@ -235,6 +242,7 @@ def kernel_micro(torch, I, L, Context, reps):
              ("2d_8192x8192_p3", I.thermal_stable_2d(8192, 8192).replace(dd_p=3))]
     for name, prob in cases:
         ctx = Context(prob, max_m=1)
+        shapes = ctx.tune()
         u64 = synth_state(torch, prob)
         g = torch.Generator(device="cuda")
         g.manual_seed(1)
@@ -265,6 +273,7 @@ def kernel_micro(torch, I, L, Context, reps):
                 res[f"{kname}_{dt}"] = {"avg_launch_us": per, "bytes_per_launch": by, "GBps": gbs,
                                         "frac": gbs / HBM_PEAK_GBS,
                                         "gpts": prob.npts / (per * 1e-6) / 1e9}
+        res["launch_shapes"] = shapes
         out[name] = res
         del ctx, u64, v64
         torch.cuda.empty_cache()
@@ -329,6 +338,8 @@ def main():
     prob = I.thermal_stable_2d(args.nx, args.nz)
     U0 = I.bubble_state(prob)
     ctx = Context(prob, max_m=30)
+    shapes = ctx.tune()                 # launch shapes of the stencil stages (setup, untimed)
+    log(f"autotuned launch shapes (rows per workgroup): {shapes}")
     common = dict(rtol=1e-8, m=30, max_restarts=20)
     opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics"),
             "plain": dict(common, inner="f64", pc="physics"),
@@ -370,6 +381,7 @@ def main():
         # the same workload with the 9-point (p = 3) derivative
         prob3 = prob.replace(dd_p=3)
         ctx3 = Context(prob3, max_m=30)
+        ctx3.tune()
         u3 = torch.from_numpy(U0).cuda()
         log("mixed steps with the 9-point stencil")
         run_steps(ctx3, u3, args.warmup, torch, **opts["mixed"])
@@ -396,7 +408,7 @@ def main():
 
     kernels = {"arnoldi": "k_cgs<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
                "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner)",
-               "jv": "k_jv_2d<float> (stable finite-difference Jv)"}
+               "jv": f"{jv_kernel_name(shapes['f32_jv'])} (stable finite-difference Jv)"}
     traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_stable_1024x512",
                     "pc": "pc_f32_counters_thermal_stable_1024x512",
                     "jv": "jv_f32_counters_thermal_stable_1024x512"}
@@ -434,6 +446,7 @@ def main():
             "learned_256x128": small,
             "jv_kernel_gpts": npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0,
             "kernel_ms_per_step": {k: v[0] / steps["mixed"] for k, v in tm.items()},
+            "launch_shapes": shapes,
         },
         "roofline": roof("mixed", dominant, kernels[dominant], traffic=traffic_of(dominant)),
         "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=traffic_of("jv")),
@@ -449,7 +462,8 @@ def main():
         micro = kernel_micro(torch, I, L, Context, args.micro_reps)
         out["kernel_micro"] = micro
         best = micro["2d_8192x8192"]["jv_f32"]
-        out["roofline_jv_micro"] = {"kernel": "k_jv_2d<float> at 8192x8192 (vectors beyond the Infinity Cache)",
+        jk = jv_kernel_name(micro["2d_8192x8192"]["launch_shapes"]["f32_jv"])
+        out["roofline_jv_micro"] = {"kernel": f"{jk} at 8192x8192 (vectors beyond the Infinity Cache)",
                                     "bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS,
                                     "unit": "GB/s", "frac": best["frac"],
                                     "traffic": counter_traffic("jv_f32_counters_8192x8192"),

@@ -191,12 +191,22 @@ int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
 int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* out);
 
 /* Autotuner: times every compiled tile shape (64 x 4, 64 x 8, 64 x 16 points)
- * of the residual, Jv and preconditioner-sweep kernels in both precisions on
- * this context's grid (HIP events, one warm-up and five timed launches each) and
- * keeps the fastest for the context; tile_rows (HOST, 6 entries, may be NULL)
- * receives the chosen tile heights for (F64 residual, F32 residual, F64 Jv,
+ * of the residual, Jv and preconditioner-sweep kernels, and the row-marching
+ * residual and Jv (a 64-column strip walking down 32, 64 or 256 rows), in both
+ * precisions on this context's grid (HIP events, one warm-up and five timed
+ * launches each) and keeps the fastest for the context; tile_rows (HOST, 6
+ * entries, may be NULL) receives the rows per workgroup of the choices (4, 8,
+ * 16: tiles; 32, 64, 256: marching) for (F64 residual, F32 residual, F64 Jv,
  * F32 Jv, F64 sweep, F32 sweep).  Overwrites the Krylov workspace; synchronises. */
 int jfnk_tune(jfnk_ctx* ctx, int32_t* tile_rows);
+
+/* Pins the launch shape of one stencil stage (what the autotuner would choose):
+ * stage 0 residual / F, 1 Jv, 2 preconditioner sweep; dtype JFNK_F64 or
+ * JFNK_F32; variant 0, 1, 2 = tiles of 64 x 4, 64 x 8, 64 x 16 points, 3, 4, 5 =
+ * row marching over 32, 64, 256 rows (residual and Jv only).  The FP64 Jv has
+ * no 64 x 16 tile (its LDS would exceed a CU's).  The 3D kernels ignore it.
+ * Returns JFNK_ERR_ARG for anything else.                                       */
+int jfnk_set_variant(jfnk_ctx* ctx, int32_t stage, int32_t dtype, int32_t variant);
 
 /* Kernel timing with HIP events recorded on the context stream around each
  * launch (resolved lazily, no synchronisation per launch).  Kernel classes:

@@ -23,7 +23,7 @@ EXPORTS = ["jfnk_create", "jfnk_destroy", "jfnk_last_error", "jfnk_set_stream", 
            "jfnk_residual", "jfnk_apply_F", "jfnk_jv", "jfnk_precond_apply", "jfnk_gmres",
            "jfnk_newton_step", "jfnk_norm", "jfnk_timing_enable", "jfnk_timing_read",
            "jfnk_net_init", "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_apply",
-           "jfnk_nlpc_residual", "jfnk_nlpc_step", "jfnk_net_set_loss", "jfnk_net_loss_grad", "jfnk_net_train_step", "jfnk_tune",
+           "jfnk_nlpc_residual", "jfnk_nlpc_step", "jfnk_net_set_loss", "jfnk_net_loss_grad", "jfnk_net_train_step", "jfnk_tune", "jfnk_set_variant",
            "jfnk_batch_create", "jfnk_batch_destroy", "jfnk_batch_size", "jfnk_batch_apply_F",
            "jfnk_batch_newton_step", "jfnk_batch_tune"]
 
@@ -103,6 +103,7 @@ def load():
     L.jfnk_net_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]
     L.jfnk_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.POINTER(C.c_double)]
     L.jfnk_tune.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.jfnk_set_variant.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.jfnk_batch_create.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, vp, C.POINTER(vp)]
     L.jfnk_batch_destroy.argtypes = [vp]
     L.jfnk_batch_size.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]

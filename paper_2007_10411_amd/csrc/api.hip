@@ -487,7 +487,8 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
 }
 
 // Autotuner: every compiled tile height (4, 8, 16 rows of 64 points) of the
-// three stencil stages in both precisions is timed with HIP events on this
+// three stencil stages, and the row-marching residual and Jv over chunks of 32,
+// 64 and 256 rows, in both precisions, are timed with HIP events on this
 // context's grid (one warm-up and five timed launches on the workspace
 // vectors); the fastest is kept for the context.
 template <typename T>
@@ -502,7 +503,9 @@ int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
     for (int stage = 0; stage < 3; ++stage) {
         float best = 1e30f;
         int bestv = 1;
-        for (int var = 0; var < 3; ++var) {
+        // tiles 64 x 4/8/16 (variants 0-2); row marching over 32/64/256 rows (3-5) for F and Jv
+        const int nvar = stage < 2 ? 6 : 3;
+        for (int var = 0; var < nvar; ++var) {
             if (stage == 1 && sizeof(T) == 8 && var == 2) continue;   // exceeds the LDS of a CU
             auto launch = [&]() -> hipError_t {
                 if (stage == 0) return launch_apply_F<T>(c->geo, V, nullptr, Z, 0, s, var);
@@ -1056,6 +1059,20 @@ int jfnk_nlpc_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newton_
     inf.res_final = rn;
     if (info) *info = inf;
     return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+int jfnk_set_variant(jfnk_ctx* c, int32_t stage, int32_t dtype, int32_t variant) {
+    if (!c) {
+        set_error("null context");
+        return JFNK_ERR_ARG;
+    }
+    if (stage < 0 || stage > 2 || (dtype != JFNK_F64 && dtype != JFNK_F32) || variant < 0 ||
+        variant > (stage < 2 ? 5 : 2) || (stage == 1 && dtype == JFNK_F64 && variant == 2)) {
+        set_error("invalid stage, dtype or variant");
+        return JFNK_ERR_ARG;
+    }
+    c->tune[stage * 2 + (dtype == JFNK_F32 ? 1 : 0)] = variant;
+    return JFNK_OK;
 }
 
 int jfnk_tune(jfnk_ctx* c, int32_t* tile_rows) {

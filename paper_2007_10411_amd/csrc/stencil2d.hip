@@ -50,6 +50,183 @@ __global__ __launch_bounds__(256) void k_pc_sweep_2d(Geo g, const T* __restrict_
     if (ea.partials) partial_eps(ea, acc, red);
 }
 
+// ---------------------------------------------------------------------------
+// Row-marching residual and Jv.  A workgroup owns a strip of kMX columns and
+// walks down a chunk of zc rows, kRB rows per step.  Primitive rows (halo 2W
+// in x) live in a ring of kRB + 3W LDS rows, the stress and heat flux of the
+// rows in a ring of kRB + 2W, so each row is fetched from HBM once per chunk
+// (the tile kernels fetch the 2W-row halo of every tile again).  The next
+// step's rows are loaded to registers while the current step computes.
+// ---------------------------------------------------------------------------
+constexpr int kMX = 64, kRB = 4;
+
+// One group of kRB primitive rows of NF fields (fields 4.. from the second
+// state), columns x0 - 2W .. x0 + kMX + 2W - 1: fixed positions per thread, so
+// the reflected source columns and their x-parity signs are set once.
+template <typename T, int W, int NF>
+struct RowStage {
+    static constexpr int SX = kMX + 4 * W, N = kRB * SX;
+    static constexpr int POS = (N + 255) / 256;
+    int col[POS];
+    int lrow[POS];
+    unsigned xneg[POS];
+    unsigned neg[POS];
+    T r[POS][NF];
+    __device__ __forceinline__ void init(const Geo& g, int x0) {
+#pragma unroll
+        for (int p = 0; p < POS; ++p) {
+            const int idx = min((int)threadIdx.x + p * 256, N - 1);
+            const int lr = idx / SX, lx = idx - lr * SX;
+            int sx;
+            col[p] = map_axis(x0 + lx - 2 * W, g.nx, g.bcl == JFNK_BC_PERIODIC, sx);
+            lrow[p] = lr;
+            unsigned m = 0u;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (sign2d(f & 3, sx, 0, g.bcv) < 0) m |= 1u << f;
+            xneg[p] = m;
+        }
+    }
+    // rows rbase .. rbase + kRB - 1 (reflected at the walls)
+    __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ a, const T* __restrict__ b, int rbase) {
+        const long long np = g.npts;
+#pragma unroll
+        for (int p = 0; p < POS; ++p) {
+            int sz;
+            const int row = map_axis(rbase + lrow[p], g.nz, g.bcv == JFNK_BC_PERIODIC, sz);
+            const long long off = (long long)row * g.nx + col[p];
+            unsigned m = xneg[p];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                r[p][f] = (f < 4 ? a : b)[(long long)(f & 3) * np + off];
+                if (sign2d(f & 3, 0, sz, g.bcv) < 0) m ^= 1u << f;
+            }
+            neg[p] = m;
+        }
+    }
+    // into ring [f][NA][SX]; slot0 is the ring slot of row rbase
+    template <int NA>
+    __device__ __forceinline__ void store(T* dst, int slot0) const {
+#pragma unroll
+        for (int p = 0; p < POS; ++p) {
+            const int idx = (int)threadIdx.x + p * 256;
+            if (idx < N) {
+                const int lx = idx - lrow[p] * SX;
+                T* d = dst + ((slot0 + lrow[p]) % NA) * SX + lx;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) d[f * NA * SX] = (neg[p] >> f) & 1u ? -r[p][f] : r[p][f];
+            }
+        }
+    }
+};
+
+template <typename T, int W, bool JV>
+__global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __restrict__ u, const T* __restrict__ v,
+                                                  double eps_in, const double* __restrict__ eps_dev,
+                                                  const T* __restrict__ f, T* __restrict__ out, int what) {
+    constexpr int H = 2 * W, SX = kMX + 2 * H, DX = kMX + 2 * W;
+    constexpr int NF = JV ? 8 : 4;
+    constexpr int NA = kRB + 3 * W, NB = kRB + 2 * W;
+    constexpr int AFS = NA * SX, BFS = NB * DX;   // field strides of the rings
+    static_assert(4 * W <= NA, "prologue rows fit the ring");
+    __shared__ T sa[NF * AFS];
+    __shared__ T sd[5 * BFS];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * kMX, z0 = blockIdx.y * zc, z1 = min(z0 + zc, g.nz);
+    const int ra0 = z0 - H;   // primitive row in ring slot 0
+    const int rd0 = z0 - W;   // derived row in ring slot 0
+    const T ihx = T(g.idx), ihz = T(g.idz);
+    const T e = JV ? T(eps_dev ? *eps_dev : eps_in) : T(0);
+    auto slotA = [&](int r) { return (r - ra0) % NA; };
+    auto slotD = [&](int d) { return (d - rd0) % NB; };
+    auto prim = [&](int row, int c) {   // accessor of the primitives at (row, LDS column c)
+        RingAcc<T, AFS, W> P;
+#pragma unroll
+        for (int k = 0; k <= 2 * W; ++k) P.r[k] = sa + slotA(row + k - W) * SX + c;
+        return P;
+    };
+    // stress and heat flux (or their differences) of derived rows d0 .. d0 + nrows - 1
+    auto derive = [&](int d0, int nrows) {
+        for (int idx = tid; idx < nrows * DX; idx += 256) {
+            const int lr = idx / DX, lx = idx - lr * DX;
+            const int d = d0 + lr;
+            const RingAcc<T, AFS, W> PA = prim(d, lx + W);
+            T dd[5];
+            if constexpr (JV) {
+                RingAcc<T, AFS, W> PB;
+#pragma unroll
+                for (int k = 0; k <= 2 * W; ++k) PB.r[k] = PA.r[k] + 4 * AFS;
+                derived_jv_pt<W>(g, PA, PB, e, ihx, ihz, dd);
+            } else {
+                derived_F_pt<W>(g, PA, ihx, ihz, dd);
+            }
+            T* o = sd + slotD(d) * DX + lx;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) o[k * BFS] = dd[k];
+        }
+    };
+
+    RowStage<T, W, NF> st;
+    st.init(g, x0);
+    // prologue: primitive rows z0 - 2W .. z0 + 2W - 1, derived rows z0 - W .. z0 + W - 1
+    for (int rb = z0 - H; rb < z0 + H; rb += kRB) {
+        st.load(g, u, v, rb);
+        st.template store<NA>(sa, slotA(rb));
+    }
+    __syncthreads();
+    derive(z0 - W, 2 * W);
+    __syncthreads();
+    const int nsteps = (z1 - z0 + kRB - 1) / kRB;
+    st.load(g, u, v, z0 + H);
+    const int ty = tid / kMX, tx = tid - ty * kMX;
+    for (int k = 0; k < nsteps; ++k) {
+        const int rb = z0 + k * kRB;
+        st.template store<NA>(sa, slotA(rb + H));
+        __syncthreads();
+        if (k + 1 < nsteps) st.load(g, u, v, rb + kRB + H);
+        derive(rb + W, kRB);
+        __syncthreads();
+        const int gz = rb + ty, gx = x0 + tx;
+        if (gz < z1 && gx < g.nx) {
+            const RingAcc<T, AFS, W> PA = prim(gz, tx + H);
+            RingAcc<T, BFS, W> D;
+#pragma unroll
+            for (int q = 0; q <= 2 * W; ++q) D.r[q] = sd + slotD(gz + q - W) * DX + tx + W;
+            if constexpr (JV) {
+                RingAcc<T, AFS, W> PB;
+#pragma unroll
+                for (int q = 0; q <= 2 * W; ++q) PB.r[q] = PA.r[q] + 4 * AFS;
+                T o[4];
+                point_jv_pt<W>(g, PA, PB, D, gz, e, ihx, ihz, o);
+                const long long np = g.npts, off = (long long)gz * g.nx + gx;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) out[q * np + off] = o[q];
+            } else {
+                T Fv[4];
+                point_F_pt<W>(g, PA, D, gz, ihx, ihz, Fv);
+                const T uv[4] = {PA.at(0, 0, 0), PA.at(1, 0, 0), PA.at(2, 0, 0), PA.at(3, 0, 0)};
+                write_F(g, f, out, gz, gx, uv, Fv, what);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// rows per marching workgroup of variants 3, 4, 5
+inline int march_rows(int var) { return var == 3 ? 32 : (var == 4 ? 64 : 256); }
+
+template <typename T, bool JV>
+hipError_t launch_march(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, const T* f, T* out,
+                        int what, hipStream_t s, int var) {
+    const int zc = march_rows(var);
+    const dim3 grid((g.nx + kMX - 1) / kMX, (g.nz + zc - 1) / zc);
+    if (g.W == 4)
+        hipLaunchKernelGGL((k_march_2d<T, 4, JV>), grid, dim3(256), 0, s, g, zc, u, v, eps, eps_dev, f, out, what);
+    else
+        hipLaunchKernelGGL((k_march_2d<T, 2, JV>), grid, dim3(256), 0, s, g, zc, u, v, eps, eps_dev, f, out, what);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // tile height variants (TX = 64); variant index v -> TZ = 4 << v
@@ -79,10 +256,14 @@ inline dim3 tile_grid(const Geo& g, int tz) { return dim3((g.nx + kTX - 1) / kTX
     } while (0)
 #define JFNK_NO_CAP(tz, w) (tz)
 
-int tile_tz(int variant) { return variant == 0 ? 4 : (variant == 2 ? 16 : 8); }
+int tile_tz(int variant) {
+    if (variant >= 3) return march_rows(variant);
+    return variant == 0 ? 4 : (variant == 2 ? 16 : 8);
+}
 
 template <typename T>
 hipError_t launch_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, hipStream_t s, int var) {
+    if (var >= 3) return launch_march<T, false>(g, u, nullptr, 0.0, nullptr, f, out, what, s, var);
     JFNK_TZ_DISPATCH(var, k_apply_F_2d, T, JFNK_NO_CAP, g, u, f, out, what);
     return hipGetLastError();
 }
@@ -99,6 +280,7 @@ __global__ __launch_bounds__(256) void k_jv_2d(Geo g, const T* __restrict__ u, c
 template <typename T>
 hipError_t launch_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* jv,
                      hipStream_t s, int var) {
+    if (var >= 3) return launch_march<T, true>(g, u, v, eps, eps_dev, nullptr, jv, 0, s, var);
 #define JFNK_JV_CAP(tz, w) ((w) == 4 ? jv_tz<T, tz, 4>() : jv_tz<T, tz, 2>())
     JFNK_TZ_DISPATCH(var, k_jv_2d, T, JFNK_JV_CAP, g, u, v, eps, eps_dev, jv);
 #undef JFNK_JV_CAP

@@ -39,8 +39,12 @@ constexpr int kHalo = 4;
 __device__ __forceinline__ int map_axis(int e, int n, bool periodic, int& side) {
     side = 0;
     if (periodic) {
-        int r = e % n;
-        return r < 0 ? r + n : r;
+        int r = e < 0 ? e + n : (e >= n ? e - n : e);
+        if (r < 0 || r >= n) {
+            r = e % n;
+            r = r < 0 ? r + n : r;
+        }
+        return r;
     }
     if (e < 0) {
         side = 1;
@@ -192,105 +196,227 @@ __device__ __forceinline__ void closure_coeffs(const Geo& g, T s2, T& nu, T& kth
 }
 
 // ---------------------------------------------------------------------------
-// F(u) and the residual
+// Point bodies of F and Jv over LDS accessors.  An accessor returns field f at
+// row offset oz and column offset ox from the point; the tile kernels read
+// contiguous rows, the row-marching kernels rows held in the slots of a ring.
+// ---------------------------------------------------------------------------
+template <typename T, int FS, int RS>
+struct TileAcc {      // rows contiguous with stride RS, fields FS apart
+    const T* p;       // field 0 at the point
+    __device__ __forceinline__ T at(int f, int oz, int ox) const { return p[f * FS + oz * RS + ox]; }
+};
+template <typename T, int FS, int W>
+struct RingAcc {      // rows z-W..z+W in ring slots, fields FS apart
+    const T* r[2 * W + 1];   // field 0 of each row at the point's column
+    __device__ __forceinline__ T at(int f, int oz, int ox) const { return r[oz + W][f * FS + ox]; }
+};
+
+template <int W, typename T, typename A>
+__device__ __forceinline__ T acc_dx(const A& a, int f, T ih) {
+    return dtaps<W>([&](int o) { return a.at(f, 0, o); }, ih);
+}
+template <int W, typename T, typename A>
+__device__ __forceinline__ T acc_dz(const A& a, int f, T ih) {
+    return dtaps<W>([&](int o) { return a.at(f, o, 0); }, ih);
+}
+
+// Stress and heat flux (txx, txz, tzz, qx, qz) of the state held in P
+// (fields u 0, w 1, theta 3).
+template <int W, typename T, typename A>
+__device__ __forceinline__ void derived_F_pt(const Geo& g, const A& P, T ihx, T ihz, T d[5]) {
+    const T ux = acc_dx<W>(P, 0, ihx), uz = acc_dz<W>(P, 0, ihz);
+    const T wx = acc_dx<W>(P, 1, ihx), wz = acc_dz<W>(P, 1, ihz);
+    const T tx = acc_dx<W>(P, 3, ihx), tz = acc_dz<W>(P, 3, ihz);
+    const T sxz = T(0.5) * (uz + wx);
+    const T div = ux + wz;
+    const T s2 = ux * ux + wz * wz + T(2) * sxz * sxz;
+    T nu, kth;
+    closure_coeffs(g, s2, nu, kth);
+    const T third = div / T(3);
+    d[0] = T(2) * nu * (ux - third);
+    d[1] = T(2) * nu * sxz;
+    d[2] = T(2) * nu * (wz - third);
+    d[3] = kth * tx;
+    d[4] = kth * tz;
+}
+
+// F at a point from the primitives P and the derived quantities D (txx 0,
+// txz 1, tzz 2, qx 3, qz 4) at grid row gz.
+template <int W, typename T, typename A, typename AD>
+__device__ __forceinline__ void point_F_pt(const Geo& g, const A& P, const AD& D, int gz, T ihx, T ihz, T Fv[4]) {
+    const T* pb = Bg<T>::pbar(g);
+    const T* dpb = Bg<T>::dpbar(g);
+    const T uu = P.at(0, 0, 0), ww = P.at(1, 0, 0), pp = P.at(2, 0, 0), th = P.at(3, 0, 0);
+    const T ux = acc_dx<W>(P, 0, ihx), wz = acc_dz<W>(P, 1, ihz);
+    const T div = ux + wz;
+    T cu = 0, cw = 0, cp = 0, ct = 0;
+    if (g.convection) {
+        const T uz = acc_dz<W>(P, 0, ihz), wx = acc_dx<W>(P, 1, ihx);
+        const T px = acc_dx<W>(P, 2, ihx), pz = acc_dz<W>(P, 2, ihz);
+        const T tx = acc_dx<W>(P, 3, ihx), tz = acc_dz<W>(P, 3, ihz);
+        auto dxp = [&](int fa, int fb) { return dtaps<W>([&](int o) { return P.at(fa, 0, o) * P.at(fb, 0, o); }, ihx); };
+        auto dzp = [&](int fa, int fb) { return dtaps<W>([&](int o) { return P.at(fa, o, 0) * P.at(fb, o, 0); }, ihz); };
+        cu = T(0.5) * (dxp(0, 0) + dzp(1, 0) + uu * ux + ww * uz);
+        cw = T(0.5) * (dxp(0, 1) + dzp(1, 1) + uu * wx + ww * wz);
+        cp = T(0.5) * (dxp(0, 2) + dzp(1, 2) + uu * px + ww * pz);
+        ct = T(0.5) * (dxp(0, 3) + dzp(1, 3) + uu * tx + ww * tz);
+    }
+    const T th0 = T(g.theta0);
+    Fv[0] = -th0 * acc_dx<W>(P, 2, ihx) + acc_dx<W>(D, 0, ihx) + acc_dz<W>(D, 1, ihz) - cu;
+    Fv[1] = -th0 * acc_dz<W>(P, 2, ihz) + acc_dx<W>(D, 1, ihx) + acc_dz<W>(D, 2, ihz) - cw + T(g.g_theta0) * th;
+    if (g.energy_test)
+        Fv[2] = -cp - T(g.kappa_cp) * div;
+    else
+        Fv[2] = -cp - ww * dpb[gz] - T(g.kappa) * (pb[gz] + pp) * div;
+    Fv[3] = acc_dx<W>(D, 3, ihx) + acc_dz<W>(D, 4, ihz) - ct - T(g.beta) * ww;
+}
+
+// Jv (stable finite-difference form):
+//   [B(a + e b, c + e d) - B(a, c)] / e = B(a, d) + B(b, c) + e B(b, d)
+//   nu difference: (cs Delta)^2 sqrt2 (2 S:T + e T:T) / (|S + e T| + |S|)
+// Derived differences of the pair (PA = u, PB = v).
+template <int W, typename T, typename A>
+__device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PA, const A& PB, T e, T ihx, T ihz, T d[5]) {
+    const T uxa = acc_dx<W>(PA, 0, ihx), uza = acc_dz<W>(PA, 0, ihz);
+    const T wxa = acc_dx<W>(PA, 1, ihx), wza = acc_dz<W>(PA, 1, ihz);
+    const T uxb = acc_dx<W>(PB, 0, ihx), uzb = acc_dz<W>(PB, 0, ihz);
+    const T wxb = acc_dx<W>(PB, 1, ihx), wzb = acc_dz<W>(PB, 1, ihz);
+    const T txa = acc_dx<W>(PA, 3, ihx), tza = acc_dz<W>(PA, 3, ihz);
+    const T txb = acc_dx<W>(PB, 3, ihx), tzb = acc_dz<W>(PB, 3, ihz);
+    // strain of u (a) and of v (b)
+    const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
+    const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
+    T nua, ktha, dnu, dkth;
+    const T s2a = axx * axx + azz * azz + T(2) * axz * axz;
+    closure_coeffs(g, s2a, nua, ktha);
+    // strain of u + e v
+    const T cxx = axx + e * bxx, czz = azz + e * bzz, cxz = axz + e * bxz;
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+        const T sab = axx * bxx + azz * bzz + T(2) * axz * bxz;
+        const T sbb = bxx * bxx + bzz * bzz + T(2) * bxz * bxz;
+        const T s2c = cxx * cxx + czz * czz + T(2) * cxz * cxz;
+        const T den = sqrt(s2a) + sqrt(s2c);
+        const T num = T(2) * sab + e * sbb;
+        dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+        dkth = dnu * T(g.inv_pr);
+    } else {
+        dnu = T(0);
+        dkth = T(0);
+    }
+    const T trc = (cxx + czz) / T(3), trb = (bxx + bzz) / T(3);
+    d[0] = T(2) * dnu * (cxx - trc) + T(2) * nua * (bxx - trb);
+    d[1] = T(2) * dnu * cxz + T(2) * nua * bxz;
+    d[2] = T(2) * dnu * (czz - trc) + T(2) * nua * (bzz - trb);
+    d[3] = dkth * (txa + e * txb) + ktha * txb;
+    d[4] = dkth * (tza + e * tzb) + ktha * tzb;
+}
+
+// Jv at a point: out = 2v/dt - dF with dF from the pair and the derived differences.
+template <int W, typename T, typename A, typename AD>
+__device__ __forceinline__ void point_jv_pt(const Geo& g, const A& PA, const A& PB, const AD& D, int gz, T e, T ihx,
+                                            T ihz, T o[4]) {
+    const T* pbar = Bg<T>::pbar(g);
+    const T* dpb = Bg<T>::dpbar(g);
+    const T uA = PA.at(0, 0, 0), wA = PA.at(1, 0, 0), pA = PA.at(2, 0, 0);
+    const T uB = PB.at(0, 0, 0), wB = PB.at(1, 0, 0), pB = PB.at(2, 0, 0), tB = PB.at(3, 0, 0);
+    const T divA = acc_dx<W>(PA, 0, ihx) + acc_dz<W>(PA, 1, ihz);
+    const T divB = acc_dx<W>(PB, 0, ihx) + acc_dz<W>(PB, 1, ihz);
+    T cc[4] = {0, 0, 0, 0};
+    if (g.convection) {
+        // 1/2 [ D_j(a_j phi_b + b_j phi_a + e b_j phi_b) + a_j D_j phi_b + b_j D_j phi_a + e b_j D_j phi_b ]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            auto px = [&](int q) {
+                return PA.at(0, 0, q) * PB.at(k, 0, q) + PB.at(0, 0, q) * (PA.at(k, 0, q) + e * PB.at(k, 0, q));
+            };
+            auto pz = [&](int q) {
+                return PA.at(1, q, 0) * PB.at(k, q, 0) + PB.at(1, q, 0) * (PA.at(k, q, 0) + e * PB.at(k, q, 0));
+            };
+            const T fx = dtaps<W>(px, ihx);
+            const T fz = dtaps<W>(pz, ihz);
+            const T dAx = acc_dx<W>(PA, k, ihx), dAz = acc_dz<W>(PA, k, ihz);
+            const T dBx = acc_dx<W>(PB, k, ihx), dBz = acc_dz<W>(PB, k, ihz);
+            const T ad = uA * dBx + wA * dBz + uB * (dAx + e * dBx) + wB * (dAz + e * dBz);
+            cc[k] = T(0.5) * (fx + fz + ad);
+        }
+    }
+    const T th0 = T(g.theta0);
+    const T dFu = -th0 * acc_dx<W>(PB, 2, ihx) + acc_dx<W>(D, 0, ihx) + acc_dz<W>(D, 1, ihz) - cc[0];
+    const T dFw = -th0 * acc_dz<W>(PB, 2, ihz) + acc_dx<W>(D, 1, ihx) + acc_dz<W>(D, 2, ihz) - cc[1] +
+                  T(g.g_theta0) * tB;
+    T dFp;
+    if (g.energy_test)
+        dFp = -cc[2] - T(g.kappa_cp) * divB;
+    else
+        dFp = -cc[2] - wB * dpb[gz] - T(g.kappa) * ((pbar[gz] + pA) * divB + pB * divA + e * pB * divB);
+    const T dFt = acc_dx<W>(D, 3, ihx) + acc_dz<W>(D, 4, ihz) - cc[3] - T(g.beta) * wB;
+    const T tdt = T(g.two_dt);
+    o[0] = tdt * uB - dFu;
+    o[1] = tdt * wB - dFw;
+    o[2] = tdt * pB - dFp;
+    o[3] = tdt * tB - dFt;
+}
+
+// out = F (what 0), 2u/dt + F (1) or 2u/dt - F - f (2) at grid point (gz, gx)
+template <typename T>
+__device__ __forceinline__ void write_F(const Geo& g, const T* __restrict__ f, T* __restrict__ out, int gz, int gx,
+                                        const T uv[4], const T Fv[4], int what) {
+    const long long np = g.npts;
+    const long long off = (long long)gz * g.nx + gx;
+    T Fs[4] = {Fv[0], Fv[1], Fv[2], Fv[3]};
+    if (gz == 0 && !g.energy_test) Fs[3] += Bg<T>::sflux(g)[gx];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T r;
+        if (what == 0) r = Fs[k];
+        else if (what == 1) r = T(g.two_dt) * uv[k] + Fs[k];
+        else r = T(g.two_dt) * uv[k] - Fs[k] - (f ? f[k * np + off] : T(0));
+        out[k * np + off] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// F(u) and the residual: one TX x TZ tile
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TZ, int W = 2>
 __device__ __forceinline__ void apply_F_tile(const Geo& g, int x0, int z0, const T* __restrict__ u,
                                              const T* __restrict__ f, T* __restrict__ out, int what) {
     constexpr int H = 2 * W;
-    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
-    constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W;
-    __shared__ T sp[4 * SZ * SX];
-    __shared__ T sd[5 * DZ * DX];
+    constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H, PS = SZ * SX;
+    constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W, DS = DZ * DX;
+    __shared__ T sp[4 * PS];
+    __shared__ T sd[5 * DS];
     const T ihx = T(g.idx), ihz = T(g.idz);
 
     stage_fields<T, TX, TZ, 4, H>(g, u, sp, x0, z0, 0);
     __syncthreads();
 
-    const T* su = sp;
-    const T* sw = sp + SZ * SX;
-    const T* spp = sp + 2 * SZ * SX;
-    const T* sth = sp + 3 * SZ * SX;
-
     // stress and heat flux on the ring-W extended tile
-    for (int idx = threadIdx.x; idx < DZ * DX; idx += blockDim.x) {
-        const int dzi = idx / DX, dxi = idx - (idx / DX) * DX;
-        const int z = dzi + W, x = dxi + W;
-        const T ux = dx_s<T, SX, W>(su, z, x, ihx), uz = dz_s<T, SX, W>(su, z, x, ihz);
-        const T wx = dx_s<T, SX, W>(sw, z, x, ihx), wz = dz_s<T, SX, W>(sw, z, x, ihz);
-        const T tx = dx_s<T, SX, W>(sth, z, x, ihx), tz = dz_s<T, SX, W>(sth, z, x, ihz);
-        const T sxz = T(0.5) * (uz + wx);
-        const T div = ux + wz;
-        const T s2 = ux * ux + wz * wz + T(2) * sxz * sxz;
-        T nu, kth;
-        closure_coeffs(g, s2, nu, kth);
-        const T third = div / T(3);
-        sd[0 * DZ * DX + idx] = T(2) * nu * (ux - third);
-        sd[1 * DZ * DX + idx] = T(2) * nu * sxz;
-        sd[2 * DZ * DX + idx] = T(2) * nu * (wz - third);
-        sd[3 * DZ * DX + idx] = kth * tx;
-        sd[4 * DZ * DX + idx] = kth * tz;
+    for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
+        const int z = idx / DX + W, x = idx - (idx / DX) * DX + W;
+        const TileAcc<T, PS, SX> P{sp + z * SX + x};
+        T d[5];
+        derived_F_pt<W>(g, P, ihx, ihz, d);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sd[k * DS + idx] = d[k];
     }
     __syncthreads();
 
-    const long long np = g.npts;
-    const T* pb = Bg<T>::pbar(g);
-    const T* dpb = Bg<T>::dpbar(g);
-    const T* sfl = Bg<T>::sflux(g);
-    const bool conv = g.convection != 0;
     for (int idx = threadIdx.x; idx < TZ * TX; idx += blockDim.x) {
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= g.nx || gz >= g.nz) continue;
-        const int z = lz + H, x = lx + H;              // primitive coordinates
-        const int dz_ = lz + W, dx_ = lx + W;          // derived coordinates
-        const T uu = su[z * SX + x], ww = sw[z * SX + x], pp = spp[z * SX + x], th = sth[z * SX + x];
-        const T ux = dx_s<T, SX, W>(su, z, x, ihx), wz = dz_s<T, SX, W>(sw, z, x, ihz);
-        const T div = ux + wz;
-        T cu = 0, cw = 0, cp = 0, ct = 0;
-        if (conv) {
-            const T uz = dz_s<T, SX, W>(su, z, x, ihz), wx = dx_s<T, SX, W>(sw, z, x, ihx);
-            const T px = dx_s<T, SX, W>(spp, z, x, ihx), pz = dz_s<T, SX, W>(spp, z, x, ihz);
-            const T tx = dx_s<T, SX, W>(sth, z, x, ihx), tz = dz_s<T, SX, W>(sth, z, x, ihz);
-            cu = T(0.5) * (dx_prod<T, SX, W>(su, su, z, x, ihx) + dz_prod<T, SX, W>(sw, su, z, x, ihz) + uu * ux + ww * uz);
-            cw = T(0.5) * (dx_prod<T, SX, W>(su, sw, z, x, ihx) + dz_prod<T, SX, W>(sw, sw, z, x, ihz) + uu * wx + ww * wz);
-            cp = T(0.5) * (dx_prod<T, SX, W>(su, spp, z, x, ihx) + dz_prod<T, SX, W>(sw, spp, z, x, ihz) + uu * px + ww * pz);
-            ct = T(0.5) * (dx_prod<T, SX, W>(su, sth, z, x, ihx) + dz_prod<T, SX, W>(sw, sth, z, x, ihz) + uu * tx + ww * tz);
-        }
-        const T* txx = sd;
-        const T* txz = sd + DZ * DX;
-        const T* tzz = sd + 2 * DZ * DX;
-        const T* qx = sd + 3 * DZ * DX;
-        const T* qz = sd + 4 * DZ * DX;
-        const T th0 = T(g.theta0);
-        T Fu = -th0 * dx_s<T, SX, W>(spp, z, x, ihx) + dx_s<T, DX, W>(txx, dz_, dx_, ihx) + dz_s<T, DX, W>(txz, dz_, dx_, ihz) - cu;
-        T Fw = -th0 * dz_s<T, SX, W>(spp, z, x, ihz) + dx_s<T, DX, W>(txz, dz_, dx_, ihx) + dz_s<T, DX, W>(tzz, dz_, dx_, ihz) - cw +
-               T(g.g_theta0) * th;
-        T Fp;
-        if (g.energy_test)
-            Fp = -cp - T(g.kappa_cp) * div;
-        else
-            Fp = -cp - ww * dpb[gz] - T(g.kappa) * (pb[gz] + pp) * div;
-        T Ft = dx_s<T, DX, W>(qx, dz_, dx_, ihx) + dz_s<T, DX, W>(qz, dz_, dx_, ihz) - ct - T(g.beta) * ww;
-        if (gz == 0 && !g.energy_test) Ft += sfl[gx];
-        const long long off = (long long)gz * g.nx + gx;
-        T Fv[4] = {Fu, Fw, Fp, Ft};
-        const T uv[4] = {uu, ww, pp, th};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            T r;
-            if (what == 0) r = Fv[k];
-            else if (what == 1) r = T(g.two_dt) * uv[k] + Fv[k];
-            else r = T(g.two_dt) * uv[k] - Fv[k] - (f ? f[k * np + off] : T(0));
-            out[k * np + off] = r;
-        }
+        const TileAcc<T, PS, SX> P{sp + (lz + H) * SX + lx + H};
+        const TileAcc<T, DS, DX> D{sd + (lz + W) * DX + lx + W};
+        T Fv[4];
+        point_F_pt<W>(g, P, D, gz, ihx, ihz, Fv);
+        const T uv[4] = {P.at(0, 0, 0), P.at(1, 0, 0), P.at(2, 0, 0), P.at(3, 0, 0)};
+        write_F(g, f, out, gz, gx, uv, Fv, what);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Jacobian-vector product, stable finite-difference form
-//   [B(a + e b, c + e d) - B(a, c)] / e = B(a, d) + B(b, c) + e B(b, d)
-//   nu difference: (cs Delta)^2 sqrt2 (2 S:T + e T:T) / (|S + e T| + |S|)
+// Jacobian-vector product: one TX x TZ tile
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TZ, int W = 2>
 __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* __restrict__ u,
@@ -315,103 +441,29 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
     }
     __syncthreads();
 
-    const T *ua = sa, *wa = sa + PS, *pa = sa + 2 * PS, *ta = sa + 3 * PS;
-    const T *ub = sb, *wb = sb + PS, *pbv = sb + 2 * PS, *tb = sb + 3 * PS;
-
     for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
         const int z = idx / DX + W, x = idx - (idx / DX) * DX + W;
-        const T uxa = dx_s<T, SX, W>(ua, z, x, ihx), uza = dz_s<T, SX, W>(ua, z, x, ihz);
-        const T wxa = dx_s<T, SX, W>(wa, z, x, ihx), wza = dz_s<T, SX, W>(wa, z, x, ihz);
-        const T uxb = dx_s<T, SX, W>(ub, z, x, ihx), uzb = dz_s<T, SX, W>(ub, z, x, ihz);
-        const T wxb = dx_s<T, SX, W>(wb, z, x, ihx), wzb = dz_s<T, SX, W>(wb, z, x, ihz);
-        const T txa = dx_s<T, SX, W>(ta, z, x, ihx), tza = dz_s<T, SX, W>(ta, z, x, ihz);
-        const T txb = dx_s<T, SX, W>(tb, z, x, ihx), tzb = dz_s<T, SX, W>(tb, z, x, ihz);
-        // strain of u (a) and of v (b)
-        const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
-        const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
-        T nua, ktha, dnu, dkth;
-        const T s2a = axx * axx + azz * azz + T(2) * axz * axz;
-        closure_coeffs(g, s2a, nua, ktha);
-        // strain of u + e v
-        const T cxx = axx + e * bxx, czz = azz + e * bzz, cxz = axz + e * bxz;
-        if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-            const T sab = axx * bxx + azz * bzz + T(2) * axz * bxz;
-            const T sbb = bxx * bxx + bzz * bzz + T(2) * bxz * bxz;
-            const T s2c = cxx * cxx + czz * czz + T(2) * cxz * cxz;
-            const T den = sqrt(s2a) + sqrt(s2c);
-            const T num = T(2) * sab + e * sbb;
-            dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
-            dkth = dnu * T(g.inv_pr);
-        } else {
-            dnu = T(0);
-            dkth = T(0);
-        }
-        const T trc = (cxx + czz) / T(3), trb = (bxx + bzz) / T(3);
-        sd[0 * DS + idx] = T(2) * dnu * (cxx - trc) + T(2) * nua * (bxx - trb);
-        sd[1 * DS + idx] = T(2) * dnu * cxz + T(2) * nua * bxz;
-        sd[2 * DS + idx] = T(2) * dnu * (czz - trc) + T(2) * nua * (bzz - trb);
-        sd[3 * DS + idx] = dkth * (txa + e * txb) + ktha * txb;
-        sd[4 * DS + idx] = dkth * (tza + e * tzb) + ktha * tzb;
+        const TileAcc<T, PS, SX> PA{sa + z * SX + x}, PB{sb + z * SX + x};
+        T d[5];
+        derived_jv_pt<W>(g, PA, PB, e, ihx, ihz, d);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sd[k * DS + idx] = d[k];
     }
     __syncthreads();
 
     const long long np = g.npts;
-    const T* pbar = Bg<T>::pbar(g);
-    const T* dpb = Bg<T>::dpbar(g);
-    const bool conv = g.convection != 0;
     for (int idx = threadIdx.x; idx < TZ * TX; idx += blockDim.x) {
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= g.nx || gz >= g.nz) continue;
-        const int z = lz + H, x = lx + H;
-        const int dz_ = lz + W, dx_ = lx + W;
-        const int c = z * SX + x;
-        const T uA = ua[c], wA = wa[c], pA = pa[c];
-        const T uB = ub[c], wB = wb[c], pB = pbv[c], tB = tb[c];
-        const T divA = dx_s<T, SX, W>(ua, z, x, ihx) + dz_s<T, SX, W>(wa, z, x, ihz);
-        const T divB = dx_s<T, SX, W>(ub, z, x, ihx) + dz_s<T, SX, W>(wb, z, x, ihz);
-        T cu = 0, cw = 0, cp = 0, ct = 0;
-        if (conv) {
-            // 1/2 [ D_j(a_j phi_b + b_j phi_a + e b_j phi_b) + a_j D_j phi_b + b_j D_j phi_a + e b_j D_j phi_b ]
-            const T* fa[4] = {ua, wa, pa, ta};
-            const T* fb[4] = {ub, wb, pbv, tb};
-            T cc[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const T* A = fa[k];
-                const T* B = fb[k];
-                auto px = [&](int o) { return ua[c + o] * B[c + o] + ub[c + o] * (A[c + o] + e * B[c + o]); };
-                auto pz = [&](int o) { return wa[c + o] * B[c + o] + wb[c + o] * (A[c + o] + e * B[c + o]); };
-                const T fx = dtaps<W>(px, ihx);
-                const T fz = dtaps<W>([&](int o) { return pz(o * SX); }, ihz);
-                const T dAx = dx_s<T, SX, W>(A, z, x, ihx), dAz = dz_s<T, SX, W>(A, z, x, ihz);
-                const T dBx = dx_s<T, SX, W>(B, z, x, ihx), dBz = dz_s<T, SX, W>(B, z, x, ihz);
-                const T ad = uA * dBx + wA * dBz + uB * (dAx + e * dBx) + wB * (dAz + e * dBz);
-                cc[k] = T(0.5) * (fx + fz + ad);
-            }
-            cu = cc[0];
-            cw = cc[1];
-            cp = cc[2];
-            ct = cc[3];
-        }
-        const T *txx = sd, *txz = sd + DS, *tzz = sd + 2 * DS, *qx = sd + 3 * DS, *qz = sd + 4 * DS;
-        const T th0 = T(g.theta0);
-        const T dFu = -th0 * dx_s<T, SX, W>(pbv, z, x, ihx) + dx_s<T, DX, W>(txx, dz_, dx_, ihx) +
-                      dz_s<T, DX, W>(txz, dz_, dx_, ihz) - cu;
-        const T dFw = -th0 * dz_s<T, SX, W>(pbv, z, x, ihz) + dx_s<T, DX, W>(txz, dz_, dx_, ihx) +
-                      dz_s<T, DX, W>(tzz, dz_, dx_, ihz) - cw + T(g.g_theta0) * tB;
-        T dFp;
-        if (g.energy_test)
-            dFp = -cp - T(g.kappa_cp) * divB;
-        else
-            dFp = -cp - wB * dpb[gz] - T(g.kappa) * ((pbar[gz] + pA) * divB + pB * divA + e * pB * divB);
-        const T dFt = dx_s<T, DX, W>(qx, dz_, dx_, ihx) + dz_s<T, DX, W>(qz, dz_, dx_, ihz) - ct - T(g.beta) * wB;
+        const int c = (lz + H) * SX + lx + H;
+        const TileAcc<T, PS, SX> PA{sa + c}, PB{sb + c};
+        const TileAcc<T, DS, DX> D{sd + (lz + W) * DX + lx + W};
+        T o[4];
+        point_jv_pt<W>(g, PA, PB, D, gz, e, ihx, ihz, o);
         const long long off = (long long)gz * g.nx + gx;
-        const T tdt = T(g.two_dt);
-        out[off] = tdt * uB - dFu;
-        out[np + off] = tdt * wB - dFw;
-        out[2 * np + off] = tdt * pB - dFp;
-        out[3 * np + off] = tdt * tB - dFt;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k * np + off] = o[k];
     }
 }
 

@@ -250,6 +250,14 @@ class Context:
         keys = ["f64_residual", "f32_residual", "f64_jv", "f32_jv", "f64_pc_sweep", "f32_pc_sweep"]
         return dict(zip(keys, list(rows)))
 
+    def set_variant(self, stage, dtype, variant):
+        """Pin a stencil launch shape: stage "residual" / "jv" / "pc_sweep",
+        dtype "f64" / "f32", variant 0-2 (tiles 64 x 4/8/16) or 3-5 (row marching
+        over 32/64/256 rows; residual and Jv)."""
+        st = {"residual": 0, "jv": 1, "pc_sweep": 2}[stage]
+        dt = {"f64": L.F64, "f32": L.F32}[dtype]
+        L.check(self.lib.jfnk_set_variant(self.h, st, dt, int(variant)), "jfnk_set_variant", soft_ok=False)
+
     # -- timing ----------------------------------------------------------------
     def timing(self, on):
         """Start (clearing the counters) or stop HIP-event timing: True records

@@ -217,11 +217,61 @@ def test_newton_mixed_precision_error_vs_fp64_oracle():
         assert e2 * nr <= 1e-5 * max(step[k], 1e-30) + 1e-12 * nr, (k, e2, step[k])
 
 
-def test_full_size_residual_and_jv_stable_thermal():
+MARCH_CASES = ["neutral-130x70", "island-noslip-260x36", "constK-periodic-72x24", "energy-test-64x16",
+               "minimal-8x8", "inviscid-lin-33x9", "stable-p3-200x100", "island-noslip-p3-130x36",
+               "constK-periodic-p3-72x24", "minimal-p3-8x9"]
+
+
+@pytest.mark.parametrize("variant", [3, 4, 5])
+@pytest.mark.parametrize("name", MARCH_CASES)
+def test_row_marching_residual_and_jv(name, variant):
+    """The row-marching kernels (64-column strips over 32, 64 or 256 rows, 4 rows
+    per step; ragged strips, chunks and steps) against the oracle: F and the
+    residual in FP64 and FP32, the stable Jv in FP64 and FP32."""
+    prob, seed = CASES[name]
+    U = _state(prob, seed)
+    Un = I.smooth_flow_state(prob, seed=seed + 100)
+    V = I.random_vector(prob, seed=seed + 7)
+    c = _ctx(prob)
+    for dt in ("f64", "f32"):
+        c.set_variant("residual", dt, variant)
+        c.set_variant("jv", dt, variant)
+    f = M.rhs(prob, Un)
+    out = dev(np.zeros(prob.shape))
+    c.apply_F(dev(U), out, what=0)
+    assert_fields_close(host(out), M.F(prob, U), F64_TOL, f"{name} v{variant} F")
+    c.residual(dev(U), dev(f), out)
+    assert_fields_close(host(out), M.residual(prob, U, f), F64_TOL, f"{name} v{variant} residual")
+    c.jv(dev(U), dev(V), out, mode="stable")
+    assert_fields_close(host(out), M.jv(prob, U, V, M.fd_eps(prob, U, V)), F64_TOL, f"{name} v{variant} jv")
+    U32 = U.astype(np.float32).astype(np.float64)
+    V32 = V.astype(np.float32).astype(np.float64)
+    out32 = dev(np.zeros(prob.shape), "f32")
+    c.apply_F(dev(U32, "f32"), out32, what=0)
+    assert_fields_close(host(out32), M.F(prob, U32), F32_TOL, f"{name} v{variant} F32")
+    e32 = M.fd_eps(prob, U32, V32, eps_mach=2.0 ** -23)
+    c.jv(dev(U32, "f32"), dev(V32, "f32"), out32, mode="stable", eps=e32)
+    assert_fields_close(host(out32), M.jv(prob, U32, V32, e32), F32_TOL, f"{name} v{variant} jv f32")
+
+
+def test_set_variant_rejects_invalid_shapes():
+    from paper_2007_10411_amd._lib import JfnkError
+    c = _ctx(I.thermal_stable_2d(64, 32))
+    for args in [("pc_sweep", "f32", 3), ("jv", "f64", 2), ("residual", "f64", 6), ("jv", "f32", -1)]:
+        with pytest.raises(JfnkError):
+            c.set_variant(*args)
+
+
+@pytest.mark.parametrize("variant", [1, 4])
+def test_full_size_residual_and_jv_stable_thermal(variant):
+    """Tile (64 x 8) and row-marching (64 rows) kernels on the whole 1024 x 512 grid."""
     prob = I.thermal_stable_2d()          # 1024 x 512
     U = _state(prob, 31)
     V = I.random_vector(prob, seed=32)
     c = _ctx(prob, max_m=4)
+    for dt in ("f64", "f32"):
+        c.set_variant("residual", dt, variant)
+        c.set_variant("jv", dt, variant)
     out = dev(np.zeros(prob.shape))
     f = M.rhs(prob, I.bubble_state(prob))
     c.residual(dev(U), dev(f), out)
