@@ -235,6 +235,67 @@ def stress(S, nu):
             for i in range(nd)]
 
 
+# --------------------------------------------------------------------------- #
+# Anisotropic exchange coefficients (section 2.3, Eq. 7, after Deardorff)
+# --------------------------------------------------------------------------- #
+def deardorff_coefficients(prob, S):
+    """Eq. 7: K_m = C_s^(4/3) eps^(1/3) (dx dy)^(2/3), K_M = C_s^(4/3) eps^(1/3) dz^(4/3)
+    with eps = nu_tau S_ij S_ij, nu_tau the Smagorinsky coefficient; the heat
+    coefficients K_h = (1 + 2 l / sqrt(dx dy)) K_m and K_H = (1 + 2 l / dz) K_M.
+    Readings: dy = dx in 2D; l from ``mixing_length``.  Returns (K_m, K_M, K_h, K_H)."""
+    dx, dy, dz = spacings(prob)
+    dh2 = dx * dy if prob.dim == 3 else dx * dx
+    SS = _frob(S, S)
+    nu = (prob.cs * les_width(prob)) ** 2 * np.sqrt(2.0 * SS)
+    eps = nu * SS
+    e13 = eps ** (1.0 / 3.0)
+    c43 = prob.cs ** (4.0 / 3.0)
+    Km = c43 * e13 * dh2 ** (2.0 / 3.0)
+    KM = c43 * e13 * dz ** (4.0 / 3.0)
+    l = mixing_length(prob, eps)
+    Kh = (1.0 + 2.0 * l / math.sqrt(dh2)) * Km
+    KH = (1.0 + 2.0 * l / dz) * KM
+    return Km, KM, Kh, KH
+
+
+def mixing_length(prob, eps):
+    """l = 0.75 sqrt(tau_kk) / N.  Readings: tau_kk is twice the subgrid kinetic
+    energy e of local equilibrium, eps = e^(3/2) / Delta (so e = (eps Delta)^(2/3));
+    N is the background Brunt-Vaisala frequency; l is capped at the filter width
+    Delta, which is also its value at N = 0 (Deardorff's limit for neutral and
+    unstable layers)."""
+    delta = les_width(prob)
+    if prob.n_bv <= 0.0:
+        return np.full(np.shape(eps), delta)
+    e = (eps * delta) ** (2.0 / 3.0)
+    return np.minimum(0.75 * np.sqrt(2.0 * e) / prob.n_bv, delta)
+
+
+def exchange_coefficients(prob, S, shape):
+    """(momentum, heat) coefficients as (horizontal, vertical) pairs on the
+    extended grid; the isotropic closures give the same array both ways."""
+    if prob.closure == 3:
+        Km, KM, Kh, KH = deardorff_coefficients(prob, S)
+        return (Km, KM), (Kh, KH)
+    nu, kth = eddy_viscosity(prob, S, shape)
+    return (nu, nu), (kth, kth)
+
+
+def stress_aniso(S, Kmom):
+    """tau_ij = 2 K_ij (S_ij - delta_ij tr S / 3) with K_ij the vertical coefficient
+    when i or j is the vertical axis and the horizontal one otherwise (reading of
+    Eq. 7: the vertical exchange coefficient carries every flux through or along z)."""
+    nd = len(S)
+    tr = _trace(S)
+    Kh, Kv = Kmom
+    return [[2.0 * (Kv if (i == nd - 1 or j == nd - 1) else Kh) * (S[i][j] - (tr / 3.0 if i == j else 0.0))
+             for j in range(nd)] for i in range(nd)]
+
+
+def _axis_coeff(K, j, nd):
+    return K[1] if j == nd - 1 else K[0]
+
+
 def _zcol(prob, prof):
     """Broadcast a (nz,) cell-centre profile against interior arrays."""
     return prof[:, None, None]
@@ -249,8 +310,8 @@ def F(prob, U):
     nd = prob.dim
     vel, p, th = _ext_state(prob, U)
     S = strain(ops, vel)
-    nu, kth = eddy_viscosity(prob, S, p.shape)
-    tau = stress(S, nu)
+    Kmom, Kheat = exchange_coefficients(prob, S, p.shape)
+    tau = stress_aniso(S, Kmom)
     div = _trace(S)
     conv_on = prob.convection != 0
     out = np.zeros(U.shape, dtype=U.dtype)
@@ -279,7 +340,7 @@ def F(prob, U):
     # potential temperature (eq. 3)
     tt = 0.0
     for j in range(nd):
-        tt = tt + ops.D(kth * ops.D(th, j), j)
+        tt = tt + ops.D(_axis_coeff(Kheat, j, nd) * ops.D(th, j), j)
     if conv_on:
         tt = tt - convection(ops, vel, th)
     tt = I(tt) - beta(prob) * U[nd - 1]
@@ -338,25 +399,31 @@ def F_difference(prob, U, V, eps):
     I = lambda x: interior(prob, x)
     shape = pU.shape
     # eddy coefficients at u and their difference quotient
-    nuU, kthU = eddy_viscosity(prob, SU, shape)
-    if prob.closure == 1:
-        c = (prob.cs * les_width(prob)) ** 2 * math.sqrt(2.0)
-        SW = [[SU[i][j] + eps * SV[i][j] for j in range(nd)] for i in range(nd)]
+    KmomU, KheatU = exchange_coefficients(prob, SU, shape)
+    SW = [[SU[i][j] + eps * SV[i][j] for j in range(nd)] for i in range(nd)]
+    if prob.closure in (1, 3):
         magU = np.sqrt(_frob(SU, SU))
         magW = np.sqrt(_frob(SW, SW))
         num = 2.0 * _frob(SU, SV) + eps * _frob(SV, SV)
         den = magU + magW
         with np.errstate(invalid="ignore", divide="ignore"):
+            dmag = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)   # (|S_W| - |S_U|) / eps
+        dmag = np.where(np.isnan(den), np.nan, dmag)
+    if prob.closure == 1:
+        c = (prob.cs * les_width(prob)) ** 2 * math.sqrt(2.0)
+        with np.errstate(invalid="ignore", divide="ignore"):
             dnu = np.where(den > 0, c * num / np.where(den > 0, den, 1.0), 0.0)
         dnu = np.where(np.isnan(den), np.nan, dnu)
         dkth = dnu / prob.pr_t
+        dKmom, dKheat = (dnu, dnu), (dkth, dkth)
+    elif prob.closure == 3:
+        dKmom, dKheat = _deardorff_difference(prob, magU, dmag, eps)
     else:
-        SW = [[SU[i][j] + eps * SV[i][j] for j in range(nd)] for i in range(nd)]
-        dnu = np.zeros(shape)
-        dkth = np.zeros(shape)
-    # d tau / eps = 2 dnu S_dev(u + eps v) + 2 nu(u) S_dev(v)
-    tW = stress(SW, dnu)
-    tV = stress(SV, nuU)
+        z = np.zeros(shape)
+        dKmom, dKheat = (z, z), (z, z)
+    # d tau / eps = 2 dK S_dev(u + eps v) + 2 K(u) S_dev(v)
+    tW = stress_aniso(SW, dKmom)
+    tV = stress_aniso(SV, KmomU)
     dtau = [[tW[i][j] + tV[i][j] for j in range(nd)] for i in range(nd)]
     conv_on = prob.convection != 0
 
@@ -389,11 +456,47 @@ def F_difference(prob, U, V, eps):
     thW = thU + eps * thV
     tt = 0.0
     for j in range(nd):
-        tt = tt + ops.D(dkth * ops.D(thW, j) + kthU * ops.D(thV, j), j)
+        tt = tt + ops.D(_axis_coeff(dKheat, j, nd) * ops.D(thW, j) + _axis_coeff(KheatU, j, nd) * ops.D(thV, j), j)
     if conv_on:
         tt = tt - dconv(thU, thV)
     out[nd + 1] = I(tt) - beta(prob) * V[nd - 1]
     return out
+
+
+def _deardorff_difference(prob, magU, dmag, eps):
+    """[K(u + eps v) - K(u)] / eps of the four Eq. 7 coefficients without
+    subtracting nearly equal values.  With eps^(1/3) = (C_s Delta)^(2/3) 2^(1/6) |S|
+    (|S| = sqrt(S:S)) every coefficient is linear in |S| up to the mixing length:
+    K_m = a_h |S|, K_M = a_v |S|, l = min(b |S|, Delta) (b = 0.75 2^(2/3) (C_s Delta)^(2/3)
+    Delta^(1/3) / N), K_h = K_m + (2 a_h / sqrt(dx dy)) l |S|, and likewise K_H.
+    dmag = (|S_W| - |S_U|) / eps is formed stably by the caller."""
+    dx, dy, dz = spacings(prob)
+    dh = math.sqrt(dx * dy if prob.dim == 3 else dx * dx)
+    delta = les_width(prob)
+    g = (prob.cs * delta) ** (2.0 / 3.0) * 2.0 ** (1.0 / 6.0)
+    c43 = prob.cs ** (4.0 / 3.0)
+    a_h = c43 * g * dh ** (4.0 / 3.0)
+    a_v = c43 * g * dz ** (4.0 / 3.0)
+    if prob.n_bv <= 0.0:
+        lU = np.full(magU.shape, delta)
+        dl = np.zeros(magU.shape)
+    else:
+        b = 0.75 * 2.0 ** (2.0 / 3.0) * (prob.cs * delta) ** (2.0 / 3.0) * delta ** (1.0 / 3.0) / prob.n_bv
+        xU = b * magU
+        lU = np.minimum(xU, delta)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            if eps == 0.0:
+                dl = np.where(xU < delta, b * dmag, np.where(xU > delta, 0.0, np.minimum(b * dmag, 0.0)))
+            else:
+                dl = np.where(xU >= delta, np.minimum((xU - delta) / eps + b * dmag, 0.0),
+                              np.minimum(b * dmag, (delta - xU) / eps))
+    lW = lU + eps * dl
+    dlS = lW * dmag + magU * dl           # (l_W |S_W| - l_U |S_U|) / eps
+    dKm = a_h * dmag
+    dKM = a_v * dmag
+    dKh = dKm + 2.0 * a_h / dh * dlS
+    dKH = dKM + 2.0 * a_v / dz * dlS
+    return (dKm, dKM), (dKh, dKH)
 
 
 def jv(prob, U, V, eps):

@@ -28,34 +28,36 @@ from .stencil import stencil
 
 
 def frozen_coefficients(prob, U):
-    """Extended frozen velocity and (nu, K_theta) of the state U."""
+    """Extended frozen velocity and the (horizontal, vertical) momentum and heat
+    coefficients of the state U (one array both ways for isotropic closures)."""
     ops = M._Ops(prob)
     vel, p, th = M._ext_state(prob, U)
     S = M.strain(ops, vel)
-    nu, kth = M.eddy_viscosity(prob, S, p.shape)
-    return vel, nu, kth
+    Kmom, Kheat = M.exchange_coefficients(prob, S, p.shape)
+    return vel, Kmom, Kheat
 
 
-def _block_coeff(prob, name, nu, kth):
+def _block_coeff(prob, name, Kmom, Kheat):
     if name == "p":
-        return np.zeros(nu.shape)
+        z = np.zeros(Kmom[0].shape)
+        return z, z
     if name == "theta":
-        return kth
-    return nu
+        return Kheat
+    return Kmom
 
 
 def apply_blocks(prob, U, Z, frozen=None):
     """P(u) z for all fields (block-diagonal operator)."""
-    vel, nu, kth = frozen if frozen is not None else frozen_coefficients(prob, U)
+    vel, Kmom, Kheat = frozen if frozen is not None else frozen_coefficients(prob, U)
     ops = M._Ops(prob)
     names = M.field_names(prob)
     out = np.zeros(Z.shape)
     for k, name in enumerate(names):
         z = M.extend(prob, Z[k], name)
-        K = _block_coeff(prob, name, nu, kth)
+        K = _block_coeff(prob, name, Kmom, Kheat)
         t = 0.0
         for j in range(prob.dim):
-            t = t - ops.D(K * ops.D(z, j), j)
+            t = t - ops.D((K[1] if j == prob.dim - 1 else K[0]) * ops.D(z, j), j)
         if prob.convection:
             t = t + M.convection(ops, vel, z)
         out[k] = 2.0 * Z[k] / prob.dt + M.interior(prob, t)
@@ -63,16 +65,20 @@ def apply_blocks(prob, U, Z, frozen=None):
 
 
 def diagonal(prob, U, frozen=None):
-    vel, nu, kth = frozen if frozen is not None else frozen_coefficients(prob, U)
+    vel, Kmom, Kheat = frozen if frozen is not None else frozen_coefficients(prob, U)
     _, c = stencil(prob.dd_p)
     cD = float(np.sum(c * c))
     dx, dy, dz = M.spacings(prob)
+    inv_hh = 1.0 / dx ** 2 + (1.0 / dy ** 2 if prob.dim == 3 else 0.0)
     inv_h2 = 1.0 / dx ** 2 + 1.0 / dz ** 2 + (1.0 / dy ** 2 if prob.dim == 3 else 0.0)
     names = M.field_names(prob)
     d = np.zeros((prob.nf,) + (prob.nz, prob.ny, prob.nx))
     for k, name in enumerate(names):
-        K = M.interior(prob, _block_coeff(prob, name, nu, kth))
-        d[k] = 2.0 / prob.dt + cD * K * inv_h2
+        Kh, Kv = _block_coeff(prob, name, Kmom, Kheat)
+        if Kh is Kv:                      # isotropic: K sum_j 1/h_j^2
+            d[k] = 2.0 / prob.dt + cD * M.interior(prob, Kh) * inv_h2
+        else:                             # sum_j K_j / h_j^2
+            d[k] = 2.0 / prob.dt + cD * (M.interior(prob, Kh) * inv_hh + M.interior(prob, Kv) / dz ** 2)
     return d
 
 

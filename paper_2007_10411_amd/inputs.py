@@ -31,6 +31,7 @@ import numpy as np
 CLOSURE_CONST_K = 0
 CLOSURE_SMAGORINSKY = 1
 CLOSURE_NONE = 2
+CLOSURE_DEARDORFF = 3              # anisotropic coefficients of Eq. 7
 # boundary kinds
 BC_FREE_SLIP = 0
 BC_NO_SLIP_BOTTOM = 1

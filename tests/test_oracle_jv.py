@@ -20,6 +20,11 @@ def _cases():
         ("3d", I.thermal_neutral_3d(12, 10, 8)),
         ("stable-smag-p3", I.thermal_stable_2d(24, 16).replace(dd_p=3)),
         ("island-noslip-p3", I.heat_island_2d(32, 12, h0=400.0, width=8000.0).replace(dd_p=3)),
+        # anisotropic Eq. 7 coefficients: mixing length below the cap (N = 0.01) and at it (N = 0)
+        ("deardorff-stable", I.thermal_stable_2d(24, 16).replace(closure=I.CLOSURE_DEARDORFF)),
+        ("deardorff-neutral", I.thermal_neutral_2d(24, 16).replace(closure=I.CLOSURE_DEARDORFF)),
+        ("deardorff-island-noslip", I.heat_island_2d(32, 12, h0=400.0, width=8000.0)
+         .replace(closure=I.CLOSURE_DEARDORFF)),
     ]
 
 
