@@ -12,6 +12,8 @@ Legs, all from the same state after the warm-up steps:
             the network is trained first on pairs the solver generates on this
             workload (training time reported, not timed with the steps)
   mixed_p3  the mixed leg with the 9-point (p = 3) derivative
+  mixed_deardorff  the mixed leg with the anisotropic exchange coefficients (Eq. 7)
+Each context is autotuned (tile or row-marching launch shapes) before its steps.
 A second learned comparison runs on the same thermal at 256 x 128, where the
 acoustic CFL number is a quarter of the full grid's.
 
@@ -62,7 +64,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,learned,p3")
+    ap.add_argument("--legs", default="mixed,plain,learned,p3,deardorff")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
@@ -387,6 +389,17 @@ def main():
         run_steps(ctx3, u3, args.warmup, torch, **opts["mixed"])
         legs["mixed_p3"] = timed_leg(ctx3, u3, args.plain_steps, torch, L, classes["mixed"], **opts["mixed"])
         del ctx3
+    if "deardorff" in legs_wanted:
+        # the same workload with the anisotropic exchange coefficients of Eq. 7
+        probd = prob.replace(closure=I.CLOSURE_DEARDORFF)
+        ctxd = Context(probd, max_m=30)
+        ctxd.tune()
+        ud = torch.from_numpy(U0).cuda()
+        log("mixed steps with the anisotropic (Eq. 7) closure")
+        run_steps(ctxd, ud, args.warmup, torch, **opts["mixed"])
+        legs["mixed_deardorff"] = timed_leg(ctxd, ud, args.plain_steps, torch, L, classes["mixed"],
+                                            **opts["mixed"])
+        del ctxd
 
     T = legs["mixed"]
     tm = T["tm"]

@@ -60,7 +60,12 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_PHYSICS = 1, JFNK_PC_LEARNED = 2 } jfnk
  *         literal quotient in exact arithmetic, no cancellation);
  * LITERAL: the quotient evaluated as written;  ANALYTIC: the eps -> 0 limit.   */
 typedef enum { JFNK_JV_STABLE = 0, JFNK_JV_LITERAL = 1, JFNK_JV_ANALYTIC = 2 } jfnk_jv_mode;
-typedef enum { JFNK_CLOSURE_CONST_K = 0, JFNK_CLOSURE_SMAGORINSKY = 1, JFNK_CLOSURE_NONE = 2 } jfnk_closure;
+typedef enum {
+    JFNK_CLOSURE_CONST_K = 0,
+    JFNK_CLOSURE_SMAGORINSKY = 1,
+    JFNK_CLOSURE_NONE = 2,
+    JFNK_CLOSURE_DEARDORFF = 3
+} jfnk_closure;
 typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIODIC = 2 } jfnk_bc;
 
 /* Physical problem (equations 1-3 with the constants of section 2.1).
@@ -68,7 +73,13 @@ typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIOD
  * background p_bar with dp_bar/dz = -g/theta_bar and p_bar(0) = cp.  kappa_div is
  * the coefficient of (p_bar + p') div u in the Exner equation (<= 0: R/cv).
  * Closure (section 2.4): Smagorinsky nu = (cs Delta)^2 sqrt(2 S:S), Delta the
- * geometric mean spacing, heat diffusivity nu/pr_t; or constant k_m, k_h.
+ * geometric mean spacing, heat diffusivity nu/pr_t; or constant k_m, k_h; or
+ * (2D problems outside a batch) the anisotropic coefficients of Eq. 7:
+ * K_m = cs^(4/3) eps^(1/3) dx^(4/3), K_M = cs^(4/3) eps^(1/3) dz^(4/3) with
+ * eps = nu S:S, K_h = (1 + 2l/dx) K_m, K_H = (1 + 2l/dz) K_M, the mixing length
+ * l = min(0.75 sqrt(2e) / n_bv, Delta) with e = (eps Delta)^(2/3) (l = Delta for
+ * n_bv = 0); the vertical coefficient carries every stress component with a z
+ * index and the vertical heat flux.
  * Surface heat flux (section 3.2): h0 [W m^-2] over a strip of width strip_width
  * centred at x = strip_center, top-hat (strip_shape 0) or tanh profile (1, with
  * half-width units and steepness strip_xi); converted with rho0 = p_ref/(R theta0)

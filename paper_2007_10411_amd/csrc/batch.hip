@@ -741,8 +741,8 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
     for (int i = 0; i < ninst; ++i) {
         const jfnk_problem& p = probs[i];
         std::string why;
-        if (p.dim != 2 || p.ny != 1 || p.nx < 8 || p.nz < 8 || !(p.dt > 0) || p.dd_p != 2 ||
-            (p.closure == JFNK_CLOSURE_SMAGORINSKY && !(p.pr_t > 0))) {
+        if (p.dim != 2 || p.ny != 1 || p.nx < 8 || p.nz < 8 || !(p.dt > 0) || p.dd_p != 2 || p.closure < 0 ||
+            p.closure > 2 || (p.closure == JFNK_CLOSURE_SMAGORINSKY && !(p.pr_t > 0))) {
             set_error("batch instance " + std::to_string(i) + ": unsupported or invalid problem");
             return fail(JFNK_ERR_ARG);
         }

@@ -28,6 +28,10 @@ struct Geo {
     double smag;                // (cs * Delta)^2
     double inv_pr;              // 1 / Pr_t
     double k_m, k_h;
+    // anisotropic coefficients (closure 3, 2D): K_m = dd_ah |S|, K_M = dd_av |S|,
+    // l = min(dd_b |S|, dd_delta) (dd_b = 0: l = dd_delta), K_h = K_m + dd_ch l |S|,
+    // K_H = K_M + dd_cv l |S|; |S| = nu_tau * dd_inv_nu
+    double dd_ah, dd_av, dd_ch, dd_cv, dd_b, dd_delta, dd_inv_nu;
     int convection, energy_test;
     const double* pbar64;       // p_bar(z), [nz]
     const double* dpbar64;      // dp_bar/dz(z), [nz]

@@ -181,9 +181,11 @@ __device__ __forceinline__ void stage_fields(const Geo& g, const T* __restrict__
     st.store(s);
 }
 
+// Isotropic coefficients (nu, K_theta) of S:S = s2; for the anisotropic closure
+// nu is the Smagorinsky viscosity from which its coefficients derive.
 template <typename T>
 __device__ __forceinline__ void closure_coeffs(const Geo& g, T s2, T& nu, T& kth) {
-    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
         nu = T(g.smag) * sqrt(T(2) * s2);
         kth = nu * T(g.inv_pr);
     } else if (g.closure == JFNK_CLOSURE_CONST_K) {
@@ -193,6 +195,50 @@ __device__ __forceinline__ void closure_coeffs(const Geo& g, T s2, T& nu, T& kth
         nu = T(0);
         kth = T(0);
     }
+}
+
+// Momentum and heat exchange coefficients, horizontal and vertical.
+template <typename T> struct Coef {
+    T mh, mv, hh, hv;
+};
+
+// Eq. 7 coefficients from |S| = sqrt(S:S): each is linear in |S| below the
+// mixing-length cap (the constants are set on the host).
+template <typename T>
+__device__ __forceinline__ Coef<T> deardorff_coef(const Geo& g, T mag) {
+    const T l = g.dd_b > 0 ? min(T(g.dd_b) * mag, T(g.dd_delta)) : T(g.dd_delta);
+    const T km = T(g.dd_ah) * mag, kM = T(g.dd_av) * mag;
+    return {km, kM, km + T(g.dd_ch) * l * mag, kM + T(g.dd_cv) * l * mag};
+}
+
+template <typename T>
+__device__ __forceinline__ Coef<T> closure_coef(const Geo& g, T s2) {
+    if (g.closure == JFNK_CLOSURE_DEARDORFF) return deardorff_coef(g, T(sqrt(s2)));
+    T nu, kth;
+    closure_coeffs(g, s2, nu, kth);
+    return {nu, nu, kth, kth};
+}
+
+// [K(S + e T) - K(S)] / e of the Eq. 7 coefficients at |S| = magA, with
+// dmag = (|S + e T| - |S|) / e formed stably; the mixing-length difference
+// takes the side of the cap that S is on (no two nearly equal values are
+// subtracted).  e = 0 gives the derivative.
+template <typename T>
+__device__ __forceinline__ Coef<T> deardorff_diff(const Geo& g, T magA, T dmag, T e) {
+    const T delta = T(g.dd_delta);
+    T lA = delta, dl = T(0);
+    if (g.dd_b > 0) {
+        const T b = T(g.dd_b), xA = b * magA;
+        lA = min(xA, delta);
+        if (e == T(0))
+            dl = xA < delta ? b * dmag : (xA > delta ? T(0) : min(b * dmag, T(0)));
+        else
+            dl = xA >= delta ? min((xA - delta) / e + b * dmag, T(0)) : min(b * dmag, (delta - xA) / e);
+    }
+    const T lW = lA + e * dl;
+    const T dlS = lW * dmag + magA * dl;   // (l_W |S_W| - l_A |S_A|) / e
+    const T dkm = T(g.dd_ah) * dmag, dkM = T(g.dd_av) * dmag;
+    return {dkm, dkM, dkm + T(g.dd_ch) * dlS, dkM + T(g.dd_cv) * dlS};
 }
 
 // ---------------------------------------------------------------------------
@@ -230,14 +276,13 @@ __device__ __forceinline__ void derived_F_pt(const Geo& g, const A& P, T ihx, T 
     const T sxz = T(0.5) * (uz + wx);
     const T div = ux + wz;
     const T s2 = ux * ux + wz * wz + T(2) * sxz * sxz;
-    T nu, kth;
-    closure_coeffs(g, s2, nu, kth);
+    const Coef<T> k = closure_coef(g, s2);
     const T third = div / T(3);
-    d[0] = T(2) * nu * (ux - third);
-    d[1] = T(2) * nu * sxz;
-    d[2] = T(2) * nu * (wz - third);
-    d[3] = kth * tx;
-    d[4] = kth * tz;
+    d[0] = T(2) * k.mh * (ux - third);
+    d[1] = T(2) * k.mv * sxz;
+    d[2] = T(2) * k.mv * (wz - third);
+    d[3] = k.hh * tx;
+    d[4] = k.hv * tz;
 }
 
 // F at a point from the primitives P and the derived quantities D (txx 0,
@@ -286,29 +331,31 @@ __device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PA, const A
     // strain of u (a) and of v (b)
     const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
     const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
-    T nua, ktha, dnu, dkth;
     const T s2a = axx * axx + azz * azz + T(2) * axz * axz;
-    closure_coeffs(g, s2a, nua, ktha);
+    const Coef<T> ka = closure_coef(g, s2a);
+    Coef<T> dk = {T(0), T(0), T(0), T(0)};
     // strain of u + e v
     const T cxx = axx + e * bxx, czz = azz + e * bzz, cxz = axz + e * bxz;
-    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
         const T sab = axx * bxx + azz * bzz + T(2) * axz * bxz;
         const T sbb = bxx * bxx + bzz * bzz + T(2) * bxz * bxz;
         const T s2c = cxx * cxx + czz * czz + T(2) * cxz * cxz;
         const T den = sqrt(s2a) + sqrt(s2c);
         const T num = T(2) * sab + e * sbb;
-        dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
-        dkth = dnu * T(g.inv_pr);
-    } else {
-        dnu = T(0);
-        dkth = T(0);
+        if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+            const T dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+            const T dkth = dnu * T(g.inv_pr);
+            dk = {dnu, dnu, dkth, dkth};
+        } else {
+            dk = deardorff_diff(g, T(sqrt(s2a)), den > T(0) ? num / den : T(0), e);
+        }
     }
     const T trc = (cxx + czz) / T(3), trb = (bxx + bzz) / T(3);
-    d[0] = T(2) * dnu * (cxx - trc) + T(2) * nua * (bxx - trb);
-    d[1] = T(2) * dnu * cxz + T(2) * nua * bxz;
-    d[2] = T(2) * dnu * (czz - trc) + T(2) * nua * (bzz - trb);
-    d[3] = dkth * (txa + e * txb) + ktha * txb;
-    d[4] = dkth * (tza + e * tzb) + ktha * tzb;
+    d[0] = T(2) * dk.mh * (cxx - trc) + T(2) * ka.mh * (bxx - trb);
+    d[1] = T(2) * dk.mv * cxz + T(2) * ka.mv * bxz;
+    d[2] = T(2) * dk.mv * (czz - trc) + T(2) * ka.mv * (bzz - trb);
+    d[3] = dk.hh * (txa + e * txb) + ka.hh * txb;
+    d[4] = dk.hv * (tza + e * tzb) + ka.hv * tzb;
 }
 
 // Jv at a point: out = 2v/dt - dF with dF from the pair and the derived differences.
@@ -500,20 +547,26 @@ __device__ __forceinline__ void frozen_nu_point(const Geo& g, long long i, const
     nu[i] = n;
 }
 
-// Diagonal of the field block: 2/dt + 2 sum_m c_m^2 K (1/dx^2 + 1/dz^2) (65/72
-// for the 5-point stencil).
+// Frozen coefficients of the preconditioner from the frozen viscosity nu_pt
+// (for the anisotropic closure the Smagorinsky nu, |S| = nu dd_inv_nu).
 template <typename T>
-__device__ __forceinline__ void pc_coeffs(const Geo& g, T nu_pt, T& kmom, T& kth) {
+__device__ __forceinline__ Coef<T> pc_coef(const Geo& g, T nu_pt) {
     if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-        kmom = nu_pt;
-        kth = nu_pt * T(g.inv_pr);
-    } else if (g.closure == JFNK_CLOSURE_CONST_K) {
-        kmom = T(g.k_m);
-        kth = T(g.k_h);
-    } else {
-        kmom = T(0);
-        kth = T(0);
+        const T kth = nu_pt * T(g.inv_pr);
+        return {nu_pt, nu_pt, kth, kth};
     }
+    if (g.closure == JFNK_CLOSURE_CONST_K) return {T(g.k_m), T(g.k_m), T(g.k_h), T(g.k_h)};
+    if (g.closure == JFNK_CLOSURE_DEARDORFF) return deardorff_coef(g, nu_pt * T(g.dd_inv_nu));
+    return {T(0), T(0), T(0), T(0)};
+}
+
+// Diagonal of a field block: 2/dt + 2 sum_m c_m^2 (K_h/dx^2 + K_v/dz^2) (65/72 for
+// the 5-point stencil); one K times (1/dx^2 + 1/dz^2) for isotropic closures.
+template <typename T, int W>
+__device__ __forceinline__ T pc_block_diag(const Geo& g, T kh, T kv) {
+    const T cD = T(DW<W>::sumsq2);
+    if (g.closure == JFNK_CLOSURE_DEARDORFF) return T(g.two_dt) + cD * (kh * T(g.idx * g.idx) + kv * T(g.idz * g.idz));
+    return T(g.two_dt) + cD * kh * T(g.idx * g.idx + g.idz * g.idz);
 }
 
 // Start of the Jacobi iteration, z0 = v / d, fused with the normalisation of
@@ -527,12 +580,9 @@ __device__ __forceinline__ double pc_diag_point(const Geo& g, long long i, const
     double acc = 0.0;
     if (i < g.npts) {
         const long long ie = (i / g.nx + W) * (long long)(g.nx + 2 * W) + (i % g.nx) + W;
-        T km, kt;
-        pc_coeffs(g, nu[ie], km, kt);
-        const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
-        const T cD = T(DW<W>::sumsq2);
-        const T dd[4] = {T(g.two_dt) + cD * km * ih2, T(g.two_dt) + cD * km * ih2, T(g.two_dt),
-                         T(g.two_dt) + cD * kt * ih2};
+        const Coef<T> k = pc_coef(g, nu[ie]);
+        const T dm = pc_block_diag<T, W>(g, k.mh, k.mv);
+        const T dd[4] = {dm, dm, T(g.two_dt), pc_block_diag<T, W>(g, k.hh, k.hv)};
         const long long np = g.npts;
         const double dv = div ? *div : 1.0;
 #pragma unroll
@@ -604,23 +654,20 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
 
     for (int idx = threadIdx.x; idx < DS; idx += blockDim.x) {
         const int z = idx / DX + W, x = idx - (idx / DX) * DX + W;
-        T km, kt;
-        pc_coeffs(g, sn[idx], km, kt);
+        const Coef<T> k = pc_coef(g, sn[idx]);
         const T* zu = sz_;
         const T* zw = sz_ + PS;
         const T* zt = sz_ + 3 * PS;
-        sf[0 * DS + idx] = km * dx_s<T, SX, W>(zu, z, x, ihx);
-        sf[1 * DS + idx] = km * dz_s<T, SX, W>(zu, z, x, ihz);
-        sf[2 * DS + idx] = km * dx_s<T, SX, W>(zw, z, x, ihx);
-        sf[3 * DS + idx] = km * dz_s<T, SX, W>(zw, z, x, ihz);
-        sf[4 * DS + idx] = kt * dx_s<T, SX, W>(zt, z, x, ihx);
-        sf[5 * DS + idx] = kt * dz_s<T, SX, W>(zt, z, x, ihz);
+        sf[0 * DS + idx] = k.mh * dx_s<T, SX, W>(zu, z, x, ihx);
+        sf[1 * DS + idx] = k.mv * dz_s<T, SX, W>(zu, z, x, ihz);
+        sf[2 * DS + idx] = k.mh * dx_s<T, SX, W>(zw, z, x, ihx);
+        sf[3 * DS + idx] = k.mv * dz_s<T, SX, W>(zw, z, x, ihz);
+        sf[4 * DS + idx] = k.hh * dx_s<T, SX, W>(zt, z, x, ihx);
+        sf[5 * DS + idx] = k.hv * dz_s<T, SX, W>(zt, z, x, ihz);
     }
     __syncthreads();
 
     const bool conv = g.convection != 0;
-    const T ih2 = T(g.idx * g.idx + g.idz * g.idz);
-    const T cD = T(DW<W>::sumsq2);
     for (int idx = threadIdx.x; idx < TZ * TX; idx += blockDim.x) {
         const int lz = idx / TX, lx = idx - (idx / TX) * TX;
         const int gx = x0 + lx, gz = z0 + lz;
@@ -629,15 +676,14 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
         const int dzi = lz + W, dxi = lx + W;
         const int dc = dzi * DX + dxi;
         const T a = sv[dc], w = sv[DS + dc];
-        T km, kt;
-        pc_coeffs(g, sn[dc], km, kt);
+        const Coef<T> kc = pc_coef(g, sn[dc]);
+        const T dmom = pc_block_diag<T, W>(g, kc.mh, kc.mv), dth = pc_block_diag<T, W>(g, kc.hh, kc.hv);
         const long long off = (long long)gz * g.nx + gx;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const T* Z = sz_ + k * PS;
             const T zc = Z[z * SX + x];
             T diff = T(0);
-            T kk = (k == 2) ? T(0) : (k == 3 ? kt : km);
             if (k != 2) {
                 const int fi = (k == 3) ? 4 : 2 * k;
                 diff = dx_s<T, DX, W>(sf + fi * DS, dzi, dxi, ihx) + dz_s<T, DX, W>(sf + (fi + 1) * DS, dzi, dxi, ihz);
@@ -654,7 +700,7 @@ __device__ __forceinline__ double pc_sweep_tile(const Geo& g, int x0, int z0, co
                 cv = T(0.5) * (fx + fz + a * dx_s<T, SX, W>(Z, z, x, ihx) + w * dz_s<T, SX, W>(Z, z, x, ihz));
             }
             const T Pz = T(g.two_dt) * zc + (cv - diff);
-            const T d = T(g.two_dt) + cD * kk * ih2;
+            const T d = k == 2 ? T(g.two_dt) : (k == 3 ? dth : dmom);
             const T zn = zc + (r[k * np + off] - Pz) / d;
             zout[k * np + off] = zn;
             zacc += (double)zn * (double)zn;
