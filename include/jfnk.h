@@ -205,7 +205,8 @@ int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* ou
  * of the residual, Jv and preconditioner-sweep kernels, and the row-marching
  * residual and Jv (a 64-column strip walking down 32, 64 or 256 rows), in both
  * precisions on this context's grid (HIP events, one warm-up and five timed
- * launches each) and keeps the fastest for the context; tile_rows (HOST, 6
+ * launches each on a deterministic non-zero fill of the Krylov workspace) and
+ * keeps the fastest for the context; tile_rows (HOST, 6
  * entries, may be NULL) receives the rows per workgroup of the choices (4, 8,
  * 16: tiles; 32, 64, 256: marching) for (F64 residual, F32 residual, F64 Jv,
  * F32 Jv, F64 sweep, F32 sweep).  Overwrites the Krylov workspace; synchronises. */

@@ -138,6 +138,19 @@ void resolve_timing(jfnk_ctx* c) {
     }
 }
 
+// Deterministic non-zero fill of the autotuner's operands (strain, closure and
+// mixing-length branches all active): x_i = 0.01 (h(i) / 2^32 - 1/2), h an integer hash.
+template <typename T>
+__global__ void k_tune_fill(T* x, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned h = (unsigned)i * 2654435761u;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    x[i] = T(0.01 * ((double)h * (1.0 / 4294967296.0) - 0.5));
+}
+
 // ---- background and surface flux set-up (section 2.1, section 3.2) ----
 __global__ void k_background(Geo g, jfnk_problem p, double* pbar, double* dpbar, double* sflux, float* pbar32,
                              float* dpbar32, float* sflux32) {
@@ -490,14 +503,16 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
 // three stencil stages, and the row-marching residual and Jv over chunks of 32,
 // 64 and 256 rows, in both precisions, are timed with HIP events on this
 // context's grid (one warm-up and five timed launches on the workspace
-// vectors); the fastest is kept for the context.
+// vectors, filled first with a deterministic non-zero pattern); the fastest is
+// kept for the context.
 template <typename T>
 int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
     T* V = Vb<T>(c);
     T* Z = Zb<T>(c);
     const long long n = c->n;
     hipStream_t s = c->stream;
-    JFNK_HIP(hipMemsetAsync(V, 0, 2 * n * sizeof(T), s));
+    hipLaunchKernelGGL((k_tune_fill<T>), dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, V, 2 * n);
+    JFNK_HIP(hipGetLastError());
     JFNK_HIP(launch_frozen_nu<T>(c->geo, V, NUb<T>(c), s));
     EpsArgs none;
     for (int stage = 0; stage < 3; ++stage) {

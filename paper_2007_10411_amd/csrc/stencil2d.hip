@@ -139,10 +139,17 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
     const T e = JV ? T(eps_dev ? *eps_dev : eps_in) : T(0);
     auto slotA = [&](int r) { return (r - ra0) % NA; };
     auto slotD = [&](int d) { return (d - rd0) % NB; };
+    // ring pointers of 2W + 1 consecutive rows from the slot of the first
+    auto rows = [](const T* base, int s, int stride, int n_slots, const T** r) {
+#pragma unroll
+        for (int k = 0; k <= 2 * W; ++k) {
+            r[k] = base + s * stride;
+            s = s + 1 == n_slots ? 0 : s + 1;
+        }
+    };
     auto prim = [&](int row, int c) {   // accessor of the primitives at (row, LDS column c)
         RingAcc<T, AFS, W> P;
-#pragma unroll
-        for (int k = 0; k <= 2 * W; ++k) P.r[k] = sa + slotA(row + k - W) * SX + c;
+        rows(sa + c, slotA(row - W), SX, NA, P.r);
         return P;
     };
     // stress and heat flux (or their differences) of derived rows d0 .. d0 + nrows - 1
@@ -190,8 +197,7 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
         if (gz < z1 && gx < g.nx) {
             const RingAcc<T, AFS, W> PA = prim(gz, tx + H);
             RingAcc<T, BFS, W> D;
-#pragma unroll
-            for (int q = 0; q <= 2 * W; ++q) D.r[q] = sd + slotD(gz + q - W) * DX + tx + W;
+            rows(sd + tx + W, slotD(gz - W), DX, NB, D.r);
             if constexpr (JV) {
                 RingAcc<T, AFS, W> PB;
 #pragma unroll

@@ -55,7 +55,8 @@ __device__ __forceinline__ bool odd3(int f, int sx, int sy, int sz, int bcv) {
 
 template <typename T>
 __device__ __forceinline__ T d5(T m2, T m1, T p1, T p2, T ih) {
-    return (T(2.0 / 3.0) * (p1 - m1) - T(1.0 / 12.0) * (p2 - m2)) * ih;
+    // weights scaled by 1/h once (shared by every derivative along the axis)
+    return (T(2.0 / 3.0) * ih) * (p1 - m1) - (T(1.0 / 12.0) * ih) * (p2 - m2);
 }
 
 // field f of a state at (possibly ghost) position (x, y, z)
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void k3m_derived(Geo g, const T* __restrict__ 
                 strain_win<T, TY>(g, w, 0, S, th);
                 T nu, kth;
                 closure3(g, frob3(S, S), nu, kth);
-                const T third = (S[0] + S[1] + S[2]) / T(3);
+                const T third = (S[0] + S[1] + S[2]) * T(1.0 / 3.0);
                 d[0 * ne + i] = T(2) * nu * (S[0] - third);
                 d[1 * ne + i] = T(2) * nu * (S[1] - third);
                 d[2 * ne + i] = T(2) * nu * (S[2] - third);
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(256) void k3m_derived(Geo g, const T* __restrict__ 
                     dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
                     dkth = dnu * T(g.inv_pr);
                 }
-                const T trw = (SW[0] + SW[1] + SW[2]) / T(3), trv = (SV[0] + SV[1] + SV[2]) / T(3);
+                const T trw = (SW[0] + SW[1] + SW[2]) * T(1.0 / 3.0), trv = (SV[0] + SV[1] + SV[2]) * T(1.0 / 3.0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const T dw = k < 3 ? SW[k] - trw : SW[k];
