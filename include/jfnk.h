@@ -204,8 +204,9 @@ int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* ou
 /* Autotuner: times every compiled tile shape (64 x 4, 64 x 8, 64 x 16 points)
  * of the residual, Jv and preconditioner-sweep kernels, and the row-marching
  * residual and Jv (a 64-column strip walking down 32, 64 or 256 rows), in both
- * precisions on this context's grid (HIP events, one warm-up and five timed
- * launches each on a deterministic non-zero fill of the Krylov workspace) and
+ * precisions on this context's grid (HIP events: one warm-up launch, then the
+ * fastest of three groups of five timed launches, on a deterministic non-zero
+ * fill of the Krylov workspace) and
  * keeps the fastest for the context; tile_rows (HOST, 6
  * entries, may be NULL) receives the rows per workgroup of the choices (4, 8,
  * 16: tiles; 32, 64, 256: marching) for (F64 residual, F32 residual, F64 Jv,
