@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--copy-probe", type=float, default=0.0)
     ap.add_argument("--micro-only", action="store_true")
+    ap.add_argument("--pin", default="", help="launch shapes pinned over the autotuner on the timed "
+                    "context, e.g. 'f32_jv=8,f32_pc_sweep=4' (rows per workgroup)")
+    ap.add_argument("--micro-pin", default="", help="the same for the 2D micro-benchmark contexts")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--micro-reps", type=int, default=20)
     return ap.parse_args()
@@ -164,10 +167,11 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
-def counter_traffic(name):
+def counter_traffic(name, shapes=None):
     """HBM bytes per launch of a kernel class from the committed hardware-counter
     summary profiles/<name>.md (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
-    factor), or None if there is none or the kernel sources changed since."""
+    factor), or None if there is none, the kernel sources changed since, or the
+    launch shapes it was measured with differ from this run's."""
     path = os.path.join(ROOT, "profiles", name + ".md")
     if not os.path.exists(path):
         return None
@@ -179,7 +183,34 @@ def counter_traffic(name):
         return None
     if sources_sha256(m_src.group(1).split()) != m_sha.group(1):
         return None
+    m_shape = re.search(r"^launch_shapes: (.+)$", text, re.M)
+    if m_shape:
+        want = parse_shapes(m_shape.group(1))
+        if shapes is None or any(shapes.get(k) != v for k, v in want.items()):
+            return None
     return float(m_val.group(1))
+
+
+# rows per workgroup of a launch shape -> jfnk_set_variant variant
+SHAPE_VARIANT = {4: 0, 8: 1, 16: 2, 32: 3, 64: 4, 256: 5}
+
+
+def parse_shapes(text):
+    """'f32_jv=8,f32_pc_sweep=4' -> {'f32_jv': 8, 'f32_pc_sweep': 4}"""
+    out = {}
+    for item in filter(None, (x.strip() for x in text.split(","))):
+        k, v = item.split("=")
+        out[k.strip()] = int(v)
+    return out
+
+
+def pin_shapes(ctx, shapes, pins):
+    """Pin launch shapes (rows per workgroup) over the autotuner's choices."""
+    for key, rows in pins.items():
+        dtype, stage = key.split("_", 1)
+        ctx.set_variant(stage, dtype, SHAPE_VARIANT[rows])
+        shapes[key] = rows
+    return shapes
 
 
 def copy_probe(gib):
@@ -237,7 +268,7 @@ def jv_kernel_name(rows):
     return f"k_jv_2d<float, 64, {rows}>"
 
 
-def kernel_micro(torch, I, L, Context, reps):
+def kernel_micro(torch, I, L, Context, reps, pins=None):
     """Residual and Jv kernels alone at sizes beyond the Infinity Cache."""
     out = {}
     cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d()),
@@ -245,6 +276,8 @@ def kernel_micro(torch, I, L, Context, reps):
     for name, prob in cases:
         ctx = Context(prob, max_m=1)
         shapes = ctx.tune()
+        if prob.dim == 2 and pins:
+            shapes = pin_shapes(ctx, shapes, pins)
         u64 = synth_state(torch, prob)
         g = torch.Generator(device="cuda")
         g.manual_seed(1)
@@ -321,7 +354,8 @@ def main():
         from paper_2007_10411_amd import inputs as I
         from paper_2007_10411_amd.jfnk import Context
         torch.cuda.set_device(0)
-        print(json.dumps({"kernel_micro": kernel_micro(torch, I, L, Context, args.micro_reps)}), flush=True)
+        print(json.dumps({"kernel_micro": kernel_micro(torch, I, L, Context, args.micro_reps,
+                                                       parse_shapes(args.micro_pin))}), flush=True)
         return
     import numpy as np
     import torch
@@ -341,7 +375,8 @@ def main():
     U0 = I.bubble_state(prob)
     ctx = Context(prob, max_m=30)
     shapes = ctx.tune()                 # launch shapes of the stencil stages (setup, untimed)
-    log(f"autotuned launch shapes (rows per workgroup): {shapes}")
+    shapes = pin_shapes(ctx, shapes, parse_shapes(args.pin))
+    log(f"launch shapes (rows per workgroup): {shapes}")
     common = dict(rtol=1e-8, m=30, max_restarts=20)
     opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics"),
             "plain": dict(common, inner="f64", pc="physics"),
@@ -429,7 +464,7 @@ def main():
     full = (prob.nx, prob.nz) == (1024, 512)
 
     def traffic_of(k):
-        return counter_traffic(traffic_name[k]) if full else None
+        return counter_traffic(traffic_name[k], shapes) if full else None
 
     jv_ms, jv_launches, _ = tm["jv"]
     value = npts * jv_launches / T["wall"] / 1e9
@@ -472,14 +507,15 @@ def main():
         del legs
         torch.cuda.empty_cache()
         log("kernel micro-benchmark (2D 8192x8192, 3D 256x256x128)")
-        micro = kernel_micro(torch, I, L, Context, args.micro_reps)
+        micro = kernel_micro(torch, I, L, Context, args.micro_reps, parse_shapes(args.micro_pin))
         out["kernel_micro"] = micro
         best = micro["2d_8192x8192"]["jv_f32"]
         jk = jv_kernel_name(micro["2d_8192x8192"]["launch_shapes"]["f32_jv"])
         out["roofline_jv_micro"] = {"kernel": f"{jk} at 8192x8192 (vectors beyond the Infinity Cache)",
                                     "bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS,
                                     "unit": "GB/s", "frac": best["frac"],
-                                    "traffic": counter_traffic("jv_f32_counters_8192x8192"),
+                                    "traffic": counter_traffic("jv_f32_counters_8192x8192",
+                                                               micro["2d_8192x8192"]["launch_shapes"]),
                                     "bytes_per_launch": best["bytes_per_launch"],
                                     "avg_launch_us": best["avg_launch_us"]}
     if not args.no_cpu:

@@ -207,7 +207,8 @@ int jfnk_norm(jfnk_ctx* ctx, jfnk_dtype dt, const void* x, int64_t n, double* ou
  * precisions on this context's grid (HIP events: one warm-up launch, then the
  * fastest of three groups of five timed launches, on a deterministic non-zero
  * fill of the Krylov workspace) and
- * keeps the fastest for the context; tile_rows (HOST, 6
+ * keeps the fastest for the context (near-ties within 3% go to the 64 x 8 tile,
+ * then to the lowest variant); tile_rows (HOST, 6
  * entries, may be NULL) receives the rows per workgroup of the choices (4, 8,
  * 16: tiles; 32, 64, 256: marching) for (F64 residual, F32 residual, F64 Jv,
  * F32 Jv, F64 sweep, F32 sweep).  Overwrites the Krylov workspace; synchronises. */

@@ -504,7 +504,8 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
 // 64 and 256 rows, in both precisions, are timed with HIP events on this
 // context's grid (one warm-up launch, then the fastest of three groups of five
 // timed launches, on the workspace vectors filled first with a deterministic
-// non-zero pattern); the fastest candidate is kept for the context.
+// non-zero pattern); the fastest candidate is kept for the context, the
+// default 64 x 8 tile or else the lowest variant when within 3% of it.
 template <typename T>
 int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
     T* V = Vb<T>(c);
@@ -516,11 +517,11 @@ int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
     JFNK_HIP(launch_frozen_nu<T>(c->geo, V, NUb<T>(c), s));
     EpsArgs none;
     for (int stage = 0; stage < 3; ++stage) {
-        float best = 1e30f;
-        int bestv = 1;
+        float tvar[6];
         // tiles 64 x 4/8/16 (variants 0-2); row marching over 32/64/256 rows (3-5) for F and Jv
         const int nvar = stage < 2 ? 6 : 3;
         for (int var = 0; var < nvar; ++var) {
+            tvar[var] = 1e30f;
             if (stage == 1 && sizeof(T) == 8 && var == 2) continue;   // exceeds the LDS of a CU
             auto launch = [&]() -> hipError_t {
                 if (stage == 0) return launch_apply_F<T>(c->geo, V, nullptr, Z, 0, s, var);
@@ -538,11 +539,19 @@ int tune_precision(jfnk_ctx* c, hipEvent_t e0, hipEvent_t e1) {
                 JFNK_HIP(hipEventElapsedTime(&t, e0, e1));
                 ms = t < ms ? t : ms;
             }
-            if (ms < best) {
-                best = ms;
-                bestv = var;
-            }
+            tvar[var] = ms;
         }
+        // near-ties (within 3%) go to the default 64 x 8 tile, then to the lowest
+        // variant, so that timing noise does not flip the choice between runs
+        float best = 1e30f;
+        for (int var = 0; var < nvar; ++var) best = tvar[var] < best ? tvar[var] : best;
+        int bestv = 1;
+        if (tvar[1] > 1.03f * best)
+            for (int var = 0; var < nvar; ++var)
+                if (tvar[var] <= 1.03f * best) {
+                    bestv = var;
+                    break;
+                }
         c->tune[stage * 2 + is32<T>()] = bestv;
     }
     return JFNK_OK;
