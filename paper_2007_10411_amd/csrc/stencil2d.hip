@@ -132,7 +132,18 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
     __shared__ T sa[NF * AFS];
     __shared__ T sd[5 * BFS];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * kMX, z0 = blockIdx.y * zc, z1 = min(z0 + zc, g.nz);
+    // Workgroups go round-robin to the 8 XCDs; give each XCD a contiguous run of
+    // the strip-fastest order so that neighbouring strips, which share their
+    // halo cache lines, run at the same time under the same L2.
+    int bx, by;
+    {
+        const int nb = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+        const int q = nb / 8, r = nb % 8, xcd = lin % 8, k = lin / 8;
+        const int logical = xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+        bx = logical % gridDim.x;
+        by = logical / gridDim.x;
+    }
+    const int x0 = bx * kMX, z0 = by * zc, z1 = min(z0 + zc, g.nz);
     const int ra0 = z0 - H;   // primitive row in ring slot 0
     const int rd0 = z0 - W;   // derived row in ring slot 0
     const T ihx = T(g.idx), ihz = T(g.idz);
