@@ -13,6 +13,7 @@ Legs, all from the same state after the warm-up steps:
             workload (training time reported, not timed with the steps)
   mixed_p3  the mixed leg with the 9-point (p = 3) derivative
   mixed_deardorff  the mixed leg with the anisotropic exchange coefficients (Eq. 7)
+  mixed_3d_256x256x128  the mixed leg on the 3D neutral thermal (20 x 20 x 10 km, dt = 2 s)
 Each context is autotuned (tile or row-marching launch shapes) before its steps.
 A second learned comparison runs on the same thermal at 256 x 128, where the
 acoustic CFL number is a quarter of the full grid's.
@@ -64,7 +65,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,learned,p3,deardorff")
+    ap.add_argument("--legs", default="mixed,plain,learned,p3,deardorff,3d")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
@@ -118,7 +119,8 @@ def per_step(leg):
     return {"ms_per_step": leg["wall"] / k * 1e3,
             "newton_iters_per_step": sum(r.newton_iters for r in leg["infos"]) / k,
             "gmres_iters_per_step": sum(r.gmres_iters_total for r in leg["infos"]) / k,
-            "fallbacks": sum(r.fallbacks for r in leg["infos"])}
+            "fallbacks": sum(r.fallbacks for r in leg["infos"]),
+            "kernel_ms_per_step": {c: v[0] / k for c, v in leg["tm"].items()}}
 
 
 def cpu_baseline(prob, U0, seconds):
@@ -435,6 +437,17 @@ def main():
         legs["mixed_deardorff"] = timed_leg(ctxd, ud, args.plain_steps, torch, L, classes["mixed"],
                                             **opts["mixed"])
         del ctxd
+    if "3d" in legs_wanted:
+        # the 3D neutral thermal at 256 x 256 x 128 (20 x 20 x 10 km, dt = 2 s), mixed precision
+        prob3d = I.thermal_neutral_3d()
+        ctx3d = Context(prob3d, max_m=30)
+        u3d = torch.from_numpy(I.bubble_state(prob3d)).cuda()
+        log("mixed steps of the 3D thermal 256x256x128")
+        run_steps(ctx3d, u3d, 1, torch, **opts["mixed"])
+        legs["mixed_3d_256x256x128"] = timed_leg(ctx3d, u3d, args.plain_steps, torch, L, classes["mixed"],
+                                                 **opts["mixed"])
+        del ctx3d, u3d
+        torch.cuda.empty_cache()
 
     T = legs["mixed"]
     tm = T["tm"]

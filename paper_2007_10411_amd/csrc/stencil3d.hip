@@ -158,8 +158,8 @@ __device__ __forceinline__ int tix(int i, int j) {
 constexpr int kMTX = 32;       // points per workgroup along x
 constexpr int kZC = 16;        // planes per workgroup
 
-template <int TY> struct MarchGeom {
-    static constexpr int SX = kMTX + 4, SY = TY + 4, P = SX * SY;
+template <int TY, int H = 2> struct MarchGeom {   // window region: the columns grown by H
+    static constexpr int SX = kMTX + 2 * H, SY = TY + 2 * H, P = SX * SY;
 };
 
 // Register-staged copy of one plane of NF fields over the window region whose
@@ -171,9 +171,9 @@ template <int TY> struct MarchGeom {
 // compute of the current plane.  Fields 0..NS-1 come from state a, NS..2NS-1
 // from state b; with SKIP_P the pressure is left out (field k is state field
 // k < 3 ? k : 4).
-template <typename T, int NF, int TY, int NTHR, int NS, bool SKIP_P>
+template <typename T, int NF, int TY, int NTHR, int NS, bool SKIP_P, int H = 2>
 struct Stager {
-    using MG = MarchGeom<TY>;
+    using MG = MarchGeom<TY, H>;
     static constexpr int POS = (MG::P + NTHR - 1) / NTHR;
     static_assert(NF <= 32, "sign bits");
     int off[POS];          // in-plane source index (0 for positions past the region)
@@ -588,19 +588,6 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
     }
 }
 
-// frozen eddy viscosity on the ring-2 extended grid
-template <typename T>
-__global__ __launch_bounds__(256) void k3_frozen_nu(Geo g, const T* __restrict__ u, T* __restrict__ nu) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    int x, y, z;
-    if (!ext_point(g, i, x, y, z)) return;
-    T S[6], th[3];
-    strain3(g, u, x, y, z, S, th);
-    T n, k;
-    closure3(g, frob3(S, S), n, k);
-    nu[i] = n;
-}
-
 template <typename T>
 __device__ __forceinline__ void pc_k3(const Geo& g, T nu_pt, T& kmom, T& kth) {
     if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
@@ -619,6 +606,190 @@ template <typename T>
 __device__ __forceinline__ T nuext(const Geo& g, const T* __restrict__ nu, int x, int y, int z) {
     const long long ex = g.nx + 4, ey = g.ny + 4;
     return nu[((long long)(z + 2) * ey + (y + 2)) * ex + (x + 2)];
+}
+
+// Shift a register queue one place towards the front and append v.
+template <typename T, int N>
+__device__ __forceinline__ void qpush(T (&q)[N], T v) {
+#pragma unroll
+    for (int i = 0; i + 1 < N; ++i) q[i] = q[i + 1];
+    q[N - 1] = v;
+}
+
+// ---------------------------------------------------------------------------
+// z-marching Jacobi sweep of the 3D field-block preconditioner.  A workgroup
+// owns 32 x 8 columns and walks a chunk of kZC planes.  In-plane neighbours
+// come from LDS: the iterate with a halo of 4 (for K D z at +-2), the horizontal
+// velocity and the frozen viscosity with a halo of 2; the fluxes K D_x z and
+// K D_y z of the plane are formed once in LDS.  Along z every thread keeps its
+// own column in registers: the iterate over 7 planes (z-2 .. z+4), w over 5 and
+// the fluxes K D_z z over 5.  Same arithmetic as the per-point sweep it replaces.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__ u, const T* __restrict__ nu,
+                                                    const T* __restrict__ r, const T* __restrict__ zin,
+                                                    T* __restrict__ zout, EpsArgs ea) {
+    constexpr int TY = 8, NTHR = kMTX * TY;
+    using ZG = MarchGeom<TY, 4>;              // iterate plane, halo 4
+    using AG = MarchGeom<TY, 2>;              // velocity and viscosity plane, halo 2
+    constexpr int FXN = AG::SX * TY, FYN = kMTX * AG::SY;
+    __shared__ T sz[5 * ZG::P];
+    __shared__ T sa[2 * AG::P];
+    __shared__ T sk[AG::P];
+    __shared__ T fx[4 * FXN];                 // K D_x z, columns x0-2 .. x0+33, rows of the tile
+    __shared__ T fy[4 * FYN];                 // K D_y z, rows y0-2 .. y0+TY+1
+    __shared__ double red[4];
+    const int tx = threadIdx.x % kMTX, ty = threadIdx.x / kMTX;
+    const int x0 = blockIdx.x * kMTX, y0 = blockIdx.y * TY;
+    const int x = x0 + tx, y = y0 + ty;
+    const int z0 = blockIdx.z * kZC, z1 = min(z0 + kZC, g.nz);
+    const bool mine = x < g.nx && y < g.ny;
+    const long long np = g.npts, nxy = (long long)g.nx * g.ny;
+    const bool vper = g.bcv == JFNK_BC_PERIODIC;
+    const T ihx = T(g.idx), ihy = T(g.idy), ihz = T(g.idz);
+    const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
+    const T cD = T(65.0 / 72.0);
+    const int cx = min(x, g.nx - 1), cy = min(y, g.ny - 1);   // own column (clamped: unused outside)
+    const long long col = (long long)cy * g.nx + cx;
+    // column value of field k of a state at plane zz (z reflection only)
+    auto colv = [&](const T* __restrict__ a, int k, int zz) {
+        int sz_;
+        const int mz = map3(zz, g.nz, vper, sz_);
+        const T v = a[(long long)k * np + mz * nxy + col];
+        return odd3(k, 0, 0, sz_, g.bcv) ? -v : v;
+    };
+    // coefficient of flux slot f (0 u, 1 v, 2 w, 3 theta) from a frozen viscosity
+    auto kof = [&](T nuv, int f) {
+        T km, kt;
+        pc_k3(g, nuv, km, kt);
+        return f == 3 ? kt : km;
+    };
+    // column queues
+    T zq[5][7], wq[5], fq[4][5];
+    auto flux_z = [&](int zc_) {             // K D_z z at plane zc_ from zq planes zc_-2 .. zc_+2
+        const T nuv = nuext(g, nu, cx, cy, zc_);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int k = f < 3 ? f : 4;
+            qpush(fq[f], kof(nuv, f) * d5(zq[k][2], zq[k][3], zq[k][5], zq[k][6], ihz));
+        }
+    };
+#pragma unroll
+    for (int it = 0; it < 10; ++it) {         // planes z0-6 .. z0+3; fluxes at z0-2 .. z0+1
+        const int n = z0 - 6 + it;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qpush(zq[k], colv(zin, k, n));
+        if (it >= 6) flux_z(n - 2);
+        if (it >= 6) qpush(wq, colv(u, 2, n - 2));
+    }
+    // in-plane staging: fixed positions per thread, reflected offsets set once
+    Stager<T, 5, TY, NTHR, 5, false, 4> stz;
+    Stager<T, 2, TY, NTHR, 2, false, 2> sta;
+    stz.init(g, x0 - 4, y0 - 4);
+    sta.init(g, x0 - 2, y0 - 2);
+    constexpr int KPOS = (AG::P + NTHR - 1) / NTHR;
+    int koff[KPOS];
+    const long long ex = g.nx + 4, ey = g.ny + 4;
+#pragma unroll
+    for (int p = 0; p < KPOS; ++p) {
+        const int idx = min((int)threadIdx.x + p * NTHR, AG::P - 1);
+        const int ly = idx / AG::SX, lx = idx - ly * AG::SX;
+        const int xe = min(max(x0 - 2 + lx + 2, 0), (int)ex - 1), ye = min(max(y0 - 2 + ly + 2, 0), (int)ey - 1);
+        koff[p] = ye * (int)ex + xe;
+    }
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        // column: iterate at z+4, w at z+2, flux K D_z z at z+2
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qpush(zq[k], colv(zin, k, z + 4));
+        qpush(wq, colv(u, 2, z + 2));
+        flux_z(z + 2);
+        // plane z
+        stz.load(g, zin, zin, z);
+        sta.load(g, u, u, z);
+        T kv[KPOS];
+#pragma unroll
+        for (int p = 0; p < KPOS; ++p) kv[p] = nu[(long long)(z + 2) * ex * ey + koff[p]];
+        stz.store(sz);
+        sta.store(sa);
+#pragma unroll
+        for (int p = 0; p < KPOS; ++p) {
+            const int idx = (int)threadIdx.x + p * NTHR;
+            if (idx < AG::P) sk[idx] = kv[p];
+        }
+        __syncthreads();
+        // in-plane fluxes
+        for (int idx = threadIdx.x; idx < 4 * FXN; idx += NTHR) {
+            const int f = idx / FXN, rr = idx - f * FXN;
+            const int row = rr / AG::SX, c = rr - row * AG::SX;
+            const T* zp = sz + (f < 3 ? f : 4) * ZG::P + (row + 4) * ZG::SX + c + 2;
+            fx[idx] = kof(sk[(row + 2) * AG::SX + c], f) * d5(zp[-2], zp[-1], zp[1], zp[2], ihx);
+        }
+        for (int idx = threadIdx.x; idx < 4 * FYN; idx += NTHR) {
+            const int f = idx / FYN, rr = idx - f * FYN;
+            const int row = rr / kMTX, c = rr - row * kMTX;
+            const T* zp = sz + (f < 3 ? f : 4) * ZG::P + (row + 2) * ZG::SX + c + 4;
+            fy[idx] = kof(sk[row * AG::SX + c + 2], f) *
+                      d5(zp[-2 * ZG::SX], zp[-ZG::SX], zp[ZG::SX], zp[2 * ZG::SX], ihy);
+        }
+        __syncthreads();
+        if (mine) {
+            const long long i = (long long)z * nxy + col;
+            T km0, kt0;
+            pc_k3(g, sk[(ty + 2) * AG::SX + tx + 2], km0, kt0);
+            const T* ua = sa + (ty + 2) * AG::SX + tx + 2;
+            const T* va = ua + AG::P;
+            const T a[3] = {ua[0], va[0], wq[2]};
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const T* zp = sz + k * ZG::P + (ty + 4) * ZG::SX + tx + 4;
+                const T zc = zp[0];
+                T diff = T(0), cv = T(0);
+                if (k != 3) {
+                    const int f = k < 3 ? k : 3;
+                    const T* fxp = fx + f * FXN + ty * AG::SX + tx + 2;
+                    const T* fyp = fy + f * FYN + (ty + 2) * kMTX + tx;
+                    diff += d5(fxp[-2], fxp[-1], fxp[1], fxp[2], ihx);
+                    diff += d5(fyp[-2 * kMTX], fyp[-kMTX], fyp[kMTX], fyp[2 * kMTX], ihy);
+                    diff += d5(fq[f][0], fq[f][1], fq[f][3], fq[f][4], ihz);
+                }
+                if (g.convection) {
+                    cv += T(0.5) * (d5(ua[-2] * zp[-2], ua[-1] * zp[-1], ua[1] * zp[1], ua[2] * zp[2], ihx) +
+                                    a[0] * d5(zp[-2], zp[-1], zp[1], zp[2], ihx));
+                    constexpr int AS = AG::SX, ZS = ZG::SX;
+                    cv += T(0.5) * (d5(va[-2 * AS] * zp[-2 * ZS], va[-AS] * zp[-ZS], va[AS] * zp[ZS],
+                                       va[2 * AS] * zp[2 * ZS], ihy) +
+                                    a[1] * d5(zp[-2 * ZS], zp[-ZS], zp[ZS], zp[2 * ZS], ihy));
+                    cv += T(0.5) * (d5(wq[0] * zq[k][0], wq[1] * zq[k][1], wq[3] * zq[k][3], wq[4] * zq[k][4], ihz) +
+                                    a[2] * d5(zq[k][0], zq[k][1], zq[k][3], zq[k][4], ihz));
+                }
+                const T kk = k == 3 ? T(0) : (k == 4 ? kt0 : km0);
+                const T Pz = T(g.two_dt) * zc + (cv - diff);
+                const T dd = T(g.two_dt) + cD * kk * ih2;
+                const T zn = zc + (r[k * np + i] - Pz) / dd;
+                zout[k * np + i] = zn;
+                acc += (double)zn * (double)zn;
+            }
+        }
+        __syncthreads();
+    }
+    if (ea.partials) {
+        const double t = block_sum256(acc, red);
+        if (threadIdx.x == 0) ea.partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// frozen eddy viscosity on the ring-2 extended grid
+template <typename T>
+__global__ __launch_bounds__(256) void k3_frozen_nu(Geo g, const T* __restrict__ u, T* __restrict__ nu) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_point(g, i, x, y, z)) return;
+    T S[6], th[3];
+    strain3(g, u, x, y, z, S, th);
+    T n, k;
+    closure3(g, frob3(S, S), n, k);
+    nu[i] = n;
 }
 
 // z0 = v / d (v = V_j / div written back); returns the thread's ||z||^2
@@ -648,66 +819,6 @@ __global__ __launch_bounds__(256) void k3_pc_diag(Geo g, const T* __restrict__ n
             const T zv = vv / dd[k];
             z[k * np + i] = zv;
             acc += (double)zv * (double)zv;
-        }
-    }
-    if (ea.partials) partial_eps(ea, acc, red);
-}
-
-// one Jacobi sweep of the field-block preconditioner
-template <typename T>
-__global__ __launch_bounds__(256) void k3_pc_sweep(Geo g, const T* __restrict__ u, const T* __restrict__ nu,
-                                                   const T* __restrict__ r, const T* __restrict__ zin,
-                                                   T* __restrict__ zout, EpsArgs ea) {
-    __shared__ double red[4];
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    double acc = 0.0;
-    if (i < g.npts) {
-        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-        const long long np = g.npts;
-        T km0, kt0;
-        pc_k3(g, nuext(g, nu, x, y, z), km0, kt0);
-        const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
-        const T cD = T(65.0 / 72.0);
-        const T a[3] = {u[i], u[np + i], u[2 * np + i]};
-        const int ox[4] = {-2, -1, 1, 2};
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const T zc = zin[k * np + i];
-            T diff = T(0), cv = T(0);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int ex = j == 0, ey = j == 1, ez = j == 2;
-                const T ih = T(j == 0 ? g.idx : (j == 1 ? g.idy : g.idz));
-                if (k != 3) {
-                    // D_j(K D_j z): fluxes at the four neighbours along j
-                    T fl[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int xq = x + ox[q] * ex, yq = y + ox[q] * ey, zq = z + ox[q] * ez;
-                        T kmq, ktq;
-                        pc_k3(g, nuext(g, nu, xq, yq, zq), kmq, ktq);
-                        fl[q] = (k == 4 ? ktq : kmq) * dfield(g, zin, k, j, xq, yq, zq);
-                    }
-                    diff += d5(fl[0], fl[1], fl[2], fl[3], ih);
-                }
-                if (g.convection) {
-                    T pa[4], pz[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int xq = x + ox[q] * ex, yq = y + ox[q] * ey, zq = z + ox[q] * ez;
-                        pa[q] = ld(g, u, j, xq, yq, zq);
-                        pz[q] = ld(g, zin, k, xq, yq, zq);
-                    }
-                    cv += T(0.5) * (d5(pa[0] * pz[0], pa[1] * pz[1], pa[2] * pz[2], pa[3] * pz[3], ih) +
-                                    a[j] * d5(pz[0], pz[1], pz[2], pz[3], ih));
-                }
-            }
-            const T kk = k == 3 ? T(0) : (k == 4 ? kt0 : km0);
-            const T Pz = T(g.two_dt) * zc + (cv - diff);
-            const T dd = T(g.two_dt) + cD * kk * ih2;
-            const T zn = zc + (r[k * np + i] - Pz) / dd;
-            zout[k * np + i] = zn;
-            acc += (double)zn * (double)zn;
         }
     }
     if (ea.partials) partial_eps(ea, acc, red);
@@ -769,11 +880,11 @@ hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, 
 template <typename T>
 hipError_t launch3_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
                             const EpsArgs& ea, hipStream_t s) {
-    const int nb = blocks(g.npts);
-    hipLaunchKernelGGL((k3_pc_sweep<T>), dim3(nb), dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
+    const dim3 grid = march_grid(g.nx, g.ny, g.nz, 8);
+    hipLaunchKernelGGL((k3m_pc_sweep<T>), grid, dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ea.partials) return e;
-    return launch_eps_finish(nb, ea, s);
+    return launch_eps_finish((int)(grid.x * grid.y * grid.z), ea, s);
 }
 
 #define JFNK_INST3(T)                                                                                          \

@@ -76,6 +76,29 @@ def test_physics_pc_3d(name, sweeps):
     assert_fields_close(host(z), PC.physics_pc(prob, U, R, sweeps=sweeps), F64_TOL, f"{name} pc{sweeps}")
 
 
+@pytest.mark.parametrize("name", ["neutral-70x20x37", "noslip-stable-45x17x21", "periodic-constK-40x9x18"])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_physics_pc_3d_multiblock(name, sweeps):
+    """The z-marching sweep across several 32 x 8 column blocks and 16-plane
+    chunks with ragged edges in every direction, FP64 and FP32."""
+    prob = {"neutral-70x20x37": I.thermal_neutral_3d(70, 20, 37),
+            "noslip-stable-45x17x21": I.Problem(dim=3, nx=45, ny=17, nz=21, lx=9000.0, ly=6000.0, lz=4000.0,
+                                                dt=2.0, n_bv=0.01, bc_vertical=1),
+            "periodic-constK-40x9x18": I.Problem(dim=3, nx=40, ny=9, nz=18, ly=15000.0, closure=0, bc_lateral=2,
+                                                 bc_vertical=2, n_bv=0.01)}[name]
+    U = I.smooth_flow_state(prob, seed=9)
+    R = I.random_vector(prob, seed=10)
+    c = _ctx(prob)
+    z = dev(np.zeros(prob.shape))
+    c.precond_apply(dev(U), dev(R), z, pc="physics", sweeps=sweeps)
+    assert_fields_close(host(z), PC.physics_pc(prob, U, R, sweeps=sweeps), F64_TOL, f"{name} pc{sweeps}")
+    U32 = U.astype(np.float32).astype(np.float64)
+    R32 = R.astype(np.float32).astype(np.float64)
+    z32 = dev(np.zeros(prob.shape), "f32")
+    c.precond_apply(dev(U32, "f32"), dev(R32, "f32"), z32, pc="physics", sweeps=sweeps)
+    assert_fields_close(host(z32), PC.physics_pc(prob, U32, R32, sweeps=sweeps), F32_TOL, f"{name} pc{sweeps} f32")
+
+
 def test_gmres_fixed_iterations_3d():
     prob = CASES3["neutral-3d-20x12x10"]
     U = I.smooth_flow_state(prob, seed=9)
