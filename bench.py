@@ -27,10 +27,12 @@ Printed JSON line:
                  roofline_jv for the Jv kernel, roofline_net for the network
   cpu_baseline   the FP64 oracle on a bounded sample of the same workload
 
-kernel_micro   the residual and Jv kernels alone on grids whose vectors exceed the
-               256 MB Infinity Cache (2D 8192 x 8192, 3D 256 x 256 x 128), FP32
-               and FP64: per-launch HIP-event time, algorithmic bytes (read u and
-               v or f, write the result: 3 n_f w per point) and the HBM fraction
+kernel_micro   the residual, Jv and physics-preconditioner kernels alone on grids
+               whose vectors exceed the 256 MB Infinity Cache (2D 8192 x 8192, p = 2
+               and 3, 3D 256 x 256 x 128), FP32 and FP64: per-launch HIP-event time,
+               algorithmic bytes (residual and Jv: read u and v or f, write the
+               result, 3 n_f w per point; preconditioner: the library's per-launch
+               count of its diagonal start and sweeps) and the HBM fraction
 
 --copy-probe GIB runs only a device-to-device copy of GIB GiB (the calibration
 kernel for the hardware byte counters) and prints its size and time.
@@ -271,7 +273,8 @@ def jv_kernel_name(rows):
 
 
 def kernel_micro(torch, I, L, Context, reps, pins=None):
-    """Residual and Jv kernels alone at sizes beyond the Infinity Cache."""
+    """Residual, Jv and physics-preconditioner kernels alone at sizes beyond the
+    Infinity Cache."""
     out = {}
     cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d()),
              ("2d_8192x8192_p3", I.thermal_stable_2d(8192, 8192).replace(dd_p=3))]
@@ -292,20 +295,25 @@ def kernel_micro(torch, I, L, Context, reps, pins=None):
             f = torch.zeros_like(u)
             o = torch.empty_like(u)
             w = u.element_size()
+            z = torch.empty_like(u)
             for _ in range(3):
                 ctx.jv(u, v, o, mode="stable", eps=1e-3)
                 ctx.apply_F(u, o, what=2, f=f)
+                ctx.precond_apply(u, v, z, pc="physics", sweeps=2)
             torch.cuda.synchronize()
+            # pc: one launch = the diagonal start or one Jacobi sweep (3 per application);
+            # its algorithmic bytes are the library's own per-launch accounting
             for kname, call, cls in [("jv", lambda: ctx.jv(u, v, o, mode="stable", eps=1e-3), L.KC_JV),
-                                     ("residual", lambda: ctx.apply_F(u, o, what=2, f=f), L.KC_RESIDUAL)]:
+                                     ("residual", lambda: ctx.apply_F(u, o, what=2, f=f), L.KC_RESIDUAL),
+                                     ("pc", lambda: ctx.precond_apply(u, v, z, pc="physics", sweeps=2), L.KC_PC)]:
                 ctx.timing(1 << cls)
                 for _ in range(reps):
                     call()
                 torch.cuda.synchronize()
-                ms, launches, _ = ctx.timing_read(cls)
+                ms, launches, amount = ctx.timing_read(cls)
                 ctx.timing(0)
                 per = ms / launches * 1e3
-                by = 3.0 * prob.n * w
+                by = amount / launches if kname == "pc" else 3.0 * prob.n * w
                 gbs = by / (per * 1e-6) / 1e9
                 res[f"{kname}_{dt}"] = {"avg_launch_us": per, "bytes_per_launch": by, "GBps": gbs,
                                         "frac": gbs / HBM_PEAK_GBS,
