@@ -1,6 +1,7 @@
-// Single-grid 2D stencil kernels: one workgroup per TX x TZ tile of the grid.
-// The bodies live in stencil2d_impl.hpp; TZ is chosen per stage by the
-// autotuner among the compiled variants 4, 8 and 16.
+// Single-grid 2D stencil kernels.  Tiles: one workgroup per TX x TZ tile of the
+// grid, bodies in stencil2d_impl.hpp, TZ 4, 8 or 16.  Row marching (residual and
+// Jv): one workgroup per 64-column strip walking down 32, 64 or 256 rows.  The
+// autotuner picks the shape per stage and precision.
 
 #include "stencil2d_impl.hpp"
 

@@ -10,9 +10,9 @@
 //           ring of 2, written to an HBM buffer [9][nz+4][ny+4][nx+4];
 //   pass 2  per grid point: convection, pressure gradient, divergence, buoyancy
 //           and the divergences of tau and q.
-// Both passes march along z through LDS windows of 5 planes (k3m_*).  The
-// preconditioner kernels load their neighbour values through the caches with
-// the parity mapping, one thread per point, x fastest (coalesced rows).
+// Both passes march along z through LDS windows of 5 planes (k3m_*), and so
+// does the Jacobi sweep of the preconditioner (k3m_pc_sweep); the frozen
+// viscosity and the diagonal start run one thread per point, x fastest.
 
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
