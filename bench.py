@@ -24,7 +24,10 @@ Printed JSON line:
   ms_per_step    wall time per implicit step of the timed leg
   roofline       the dominant kernel class of the timed leg (algorithmic bytes over
                  the summed HIP-event time of its launches) against 8 TB/s HBM;
-                 roofline_jv for the Jv kernel, roofline_net for the network
+                 roofline_jv for the Jv kernel, roofline_net for the network.
+                 Each leg runs its steps twice from the same state: the wall time
+                 above comes from the run without instrumentation, the per-class
+                 HIP events from the second run (their packets add ~20% to a step)
   cpu_baseline   the FP64 oracle on a bounded sample of the same workload
 
 kernel_micro   the residual, Jv and physics-preconditioner kernels alone on grids
@@ -100,20 +103,30 @@ def run_steps(ctx, u, k, torch, **opts):
 
 
 def timed_leg(ctx, u0, k, torch, L, classes, **opts):
-    """k steps from u0; HIP events record the launches of the given classes."""
+    """k steps from u0, twice: the wall time comes from a run without
+    instrumentation; a second run of the same steps from the same state records
+    HIP events around every launch of the given kernel classes (the event
+    packets themselves cost about a fifth of the step time at 1024 x 512)."""
     u = u0.clone()
-    mask = 0
-    for c in classes.values():
-        mask |= 1 << c
     torch.cuda.synchronize()
-    ctx.timing(mask)
     t0 = time.perf_counter()
     infos = run_steps(ctx, u, k, torch, **opts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    mask = 0
+    for c in classes.values():
+        mask |= 1 << c
+    ui = u0.clone()
+    torch.cuda.synchronize()
+    ctx.timing(mask)
+    t0 = time.perf_counter()
+    run_steps(ctx, ui, k, torch, **opts)
+    torch.cuda.synchronize()
+    wall_i = time.perf_counter() - t0
     tm = {name: ctx.timing_read(c) for name, c in classes.items()}    # (ms, launches, bytes or flops)
     ctx.timing(0)
-    return {"wall": wall, "infos": infos, "tm": tm, "u": u}
+    del ui
+    return {"wall": wall, "wall_instrumented": wall_i, "infos": infos, "tm": tm, "u": u}
 
 
 def per_step(leg):
@@ -122,6 +135,7 @@ def per_step(leg):
             "newton_iters_per_step": sum(r.newton_iters for r in leg["infos"]) / k,
             "gmres_iters_per_step": sum(r.gmres_iters_total for r in leg["infos"]) / k,
             "fallbacks": sum(r.fallbacks for r in leg["infos"]),
+            "ms_per_step_instrumented": leg["wall_instrumented"] / k * 1e3,
             "kernel_ms_per_step": {c: v[0] / k for c, v in leg["tm"].items()}}
 
 
