@@ -570,8 +570,8 @@ bool valid_problem(const jfnk_problem* p, std::string& why) {
         return why = "bc_lateral must be free-slip or periodic", false;
     if (p->bc_vertical < 0 || p->bc_vertical > 2) return why = "invalid bc_vertical", false;
     if (p->closure < 0 || p->closure > 3) return why = "invalid closure", false;
-    if (p->closure == JFNK_CLOSURE_DEARDORFF && (p->dim != 2 || !(p->cs >= 0) || !(p->n_bv >= 0)))
-        return why = "the anisotropic closure needs a 2D problem, cs >= 0 and n_bv >= 0", false;
+    if (p->closure == JFNK_CLOSURE_DEARDORFF && (!(p->cs >= 0) || !(p->n_bv >= 0)))
+        return why = "the anisotropic closure needs cs >= 0 and n_bv >= 0", false;
     if (p->closure == JFNK_CLOSURE_SMAGORINSKY && !(p->pr_t > 0)) return why = "pr_t must be positive", false;
     return true;
 }
@@ -640,12 +640,13 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     g.inv_pr = p->pr_t > 0 ? 1.0 / p->pr_t : 0.0;
     if (p->closure == JFNK_CLOSURE_DEARDORFF) {
         // eps^(1/3) = (cs Delta)^(2/3) 2^(1/6) |S|, so every coefficient is linear in |S|
-        // below the mixing-length cap; dy = dx in 2D
+        // below the mixing-length cap; the horizontal scale sqrt(dx dy) (dy = dx in 2D)
         const double gm = std::cbrt((p->cs * delta) * (p->cs * delta)) * std::pow(2.0, 1.0 / 6.0);
         const double c43 = std::pow(p->cs, 4.0 / 3.0);
-        g.dd_ah = c43 * gm * std::pow(g.dx, 4.0 / 3.0);
+        const double dh = p->dim == 3 ? std::sqrt(g.dx * g.dy) : g.dx;
+        g.dd_ah = c43 * gm * std::pow(dh, 4.0 / 3.0);
         g.dd_av = c43 * gm * std::pow(g.dz, 4.0 / 3.0);
-        g.dd_ch = 2.0 * g.dd_ah / g.dx;
+        g.dd_ch = 2.0 * g.dd_ah / dh;
         g.dd_cv = 2.0 * g.dd_av / g.dz;
         g.dd_delta = delta;
         g.dd_b = p->n_bv > 0 ? 0.75 * std::pow(2.0, 2.0 / 3.0) * std::cbrt((p->cs * delta) * (p->cs * delta)) *

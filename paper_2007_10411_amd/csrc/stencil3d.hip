@@ -16,6 +16,7 @@
 
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
+#include "exchange.hpp"
 
 namespace jfnk {
 
@@ -94,9 +95,11 @@ __device__ __forceinline__ T dext(const Geo& g, const T* __restrict__ d, int c, 
               ldx(g, d, c, x + ex, y + ey, z + ez), ldx(g, d, c, x + 2 * ex, y + 2 * ey, z + 2 * ez), ih);
 }
 
+// Isotropic (nu, K_theta) of S:S = s2; for the anisotropic closure nu is the
+// Smagorinsky viscosity from which its coefficients derive.
 template <typename T>
 __device__ __forceinline__ void closure3(const Geo& g, T s2, T& nu, T& kth) {
-    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
         nu = T(g.smag) * sqrt(T(2) * s2);
         kth = nu * T(g.inv_pr);
     } else if (g.closure == JFNK_CLOSURE_CONST_K) {
@@ -131,6 +134,19 @@ template <typename T>
 __device__ __forceinline__ T frob3(const T a[6], const T b[6]) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + T(2) * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]);
 }
+
+// exchange coefficients (horizontal, vertical) of S:S = s2
+template <typename T>
+__device__ __forceinline__ Coef<T> closure3c(const Geo& g, T s2) {
+    if (g.closure == JFNK_CLOSURE_DEARDORFF) return deardorff_coef(g, T(sqrt(s2)));
+    T nu, kth;
+    closure3(g, s2, nu, kth);
+    return {nu, nu, kth, kth};
+}
+
+// stress components xx, yy, zz, xy, xz, yz: the ones with a z index take the
+// vertical coefficient
+__device__ __forceinline__ bool vert3(int comp) { return comp == 2 || comp == 4 || comp == 5; }
 
 __device__ __forceinline__ bool ext_point(const Geo& g, long long i, int& x, int& y, int& z) {
     const long long ex = g.nx + 4, ey = g.ny + 4, ez = g.nz + 4;
@@ -309,43 +325,47 @@ __global__ __launch_bounds__(256) void k3m_derived(Geo g, const T* __restrict__ 
             if (!PAIR) {
                 T S[6], th[3];
                 strain_win<T, TY>(g, w, 0, S, th);
-                T nu, kth;
-                closure3(g, frob3(S, S), nu, kth);
+                const Coef<T> k = closure3c(g, frob3(S, S));
                 const T third = (S[0] + S[1] + S[2]) * T(1.0 / 3.0);
-                d[0 * ne + i] = T(2) * nu * (S[0] - third);
-                d[1 * ne + i] = T(2) * nu * (S[1] - third);
-                d[2 * ne + i] = T(2) * nu * (S[2] - third);
-                d[3 * ne + i] = T(2) * nu * S[3];
-                d[4 * ne + i] = T(2) * nu * S[4];
-                d[5 * ne + i] = T(2) * nu * S[5];
-                d[6 * ne + i] = kth * th[0];
-                d[7 * ne + i] = kth * th[1];
-                d[8 * ne + i] = kth * th[2];
+                d[0 * ne + i] = T(2) * k.mh * (S[0] - third);
+                d[1 * ne + i] = T(2) * k.mh * (S[1] - third);
+                d[2 * ne + i] = T(2) * k.mv * (S[2] - third);
+                d[3 * ne + i] = T(2) * k.mh * S[3];
+                d[4 * ne + i] = T(2) * k.mv * S[4];
+                d[5 * ne + i] = T(2) * k.mv * S[5];
+                d[6 * ne + i] = k.hh * th[0];
+                d[7 * ne + i] = k.hh * th[1];
+                d[8 * ne + i] = k.hv * th[2];
             } else {
                 T SU[6], SV[6], tU[3], tV[3];
                 strain_win<T, TY>(g, w, 0, SU, tU);
                 strain_win<T, TY>(g, w, 4, SV, tV);
-                T nua, ktha;
-                closure3(g, frob3(SU, SU), nua, ktha);
+                const Coef<T> ka = closure3c(g, frob3(SU, SU));
                 T SW[6];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) SW[k] = SU[k] + e * SV[k];
-                T dnu = T(0), dkth = T(0);
-                if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+                Coef<T> dk = {T(0), T(0), T(0), T(0)};
+                if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
                     const T den = sqrt(frob3(SU, SU)) + sqrt(frob3(SW, SW));
                     const T num = T(2) * frob3(SU, SV) + e * frob3(SV, SV);
-                    dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
-                    dkth = dnu * T(g.inv_pr);
+                    if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+                        const T dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+                        const T dkth = dnu * T(g.inv_pr);
+                        dk = {dnu, dnu, dkth, dkth};
+                    } else {
+                        dk = deardorff_diff(g, T(sqrt(frob3(SU, SU))), den > T(0) ? num / den : T(0), e);
+                    }
                 }
                 const T trw = (SW[0] + SW[1] + SW[2]) * T(1.0 / 3.0), trv = (SV[0] + SV[1] + SV[2]) * T(1.0 / 3.0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const T dw = k < 3 ? SW[k] - trw : SW[k];
                     const T dv = k < 3 ? SV[k] - trv : SV[k];
-                    d[k * ne + i] = T(2) * dnu * dw + T(2) * nua * dv;
+                    d[k * ne + i] = T(2) * (vert3(k) ? dk.mv : dk.mh) * dw + T(2) * (vert3(k) ? ka.mv : ka.mh) * dv;
                 }
 #pragma unroll
-                for (int j = 0; j < 3; ++j) d[(6 + j) * ne + i] = dkth * (tU[j] + e * tV[j]) + ktha * tV[j];
+                for (int j = 0; j < 3; ++j)
+                    d[(6 + j) * ne + i] = (j == 2 ? dk.hv : dk.hh) * (tU[j] + e * tV[j]) + (j == 2 ? ka.hv : ka.hh) * tV[j];
             }
         }
         __syncthreads();
@@ -588,18 +608,27 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
     }
 }
 
+// frozen coefficients of the preconditioner from the frozen viscosity (for the
+// anisotropic closure the Smagorinsky nu, |S| = nu dd_inv_nu)
 template <typename T>
-__device__ __forceinline__ void pc_k3(const Geo& g, T nu_pt, T& kmom, T& kth) {
+__device__ __forceinline__ Coef<T> pc_k3(const Geo& g, T nu_pt) {
     if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-        kmom = nu_pt;
-        kth = nu_pt * T(g.inv_pr);
-    } else if (g.closure == JFNK_CLOSURE_CONST_K) {
-        kmom = T(g.k_m);
-        kth = T(g.k_h);
-    } else {
-        kmom = T(0);
-        kth = T(0);
+        const T kth = nu_pt * T(g.inv_pr);
+        return {nu_pt, nu_pt, kth, kth};
     }
+    if (g.closure == JFNK_CLOSURE_CONST_K) return {T(g.k_m), T(g.k_m), T(g.k_h), T(g.k_h)};
+    if (g.closure == JFNK_CLOSURE_DEARDORFF) return deardorff_coef(g, nu_pt * T(g.dd_inv_nu));
+    return {T(0), T(0), T(0), T(0)};
+}
+
+// diagonal of a field block: 2/dt + 2 sum c^2 (K_h (1/dx^2 + 1/dy^2) + K_v/dz^2); one K
+// times sum 1/h^2 for the isotropic closures
+template <typename T>
+__device__ __forceinline__ T pc_diag3(const Geo& g, T kh, T kv) {
+    const T cD = T(65.0 / 72.0);
+    if (g.closure == JFNK_CLOSURE_DEARDORFF)
+        return T(g.two_dt) + cD * (kh * T(g.idx * g.idx + g.idy * g.idy) + kv * T(g.idz * g.idz));
+    return T(g.two_dt) + cD * kh * T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
 }
 
 template <typename T>
@@ -647,8 +676,6 @@ __global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__
     const long long np = g.npts, nxy = (long long)g.nx * g.ny;
     const bool vper = g.bcv == JFNK_BC_PERIODIC;
     const T ihx = T(g.idx), ihy = T(g.idy), ihz = T(g.idz);
-    const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
-    const T cD = T(65.0 / 72.0);
     const int cx = min(x, g.nx - 1), cy = min(y, g.ny - 1);   // own column (clamped: unused outside)
     const long long col = (long long)cy * g.nx + cx;
     // column value of field k of a state at plane zz (z reflection only)
@@ -658,11 +685,11 @@ __global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__
         const T v = a[(long long)k * np + mz * nxy + col];
         return odd3(k, 0, 0, sz_, g.bcv) ? -v : v;
     };
-    // coefficient of flux slot f (0 u, 1 v, 2 w, 3 theta) from a frozen viscosity
-    auto kof = [&](T nuv, int f) {
-        T km, kt;
-        pc_k3(g, nuv, km, kt);
-        return f == 3 ? kt : km;
+    // coefficient of flux slot f (0 u, 1 v, 2 w, 3 theta) along a horizontal (or the
+    // vertical) axis from a frozen viscosity
+    auto kof = [&](T nuv, int f, bool vertical) {
+        const Coef<T> kc = pc_k3(g, nuv);
+        return f == 3 ? (vertical ? kc.hv : kc.hh) : (vertical ? kc.mv : kc.mh);
     };
     // column queues
     T zq[5][7], wq[5], fq[4][5];
@@ -671,7 +698,7 @@ __global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int k = f < 3 ? f : 4;
-            qpush(fq[f], kof(nuv, f) * d5(zq[k][2], zq[k][3], zq[k][5], zq[k][6], ihz));
+            qpush(fq[f], kof(nuv, f, true) * d5(zq[k][2], zq[k][3], zq[k][5], zq[k][6], ihz));
         }
     };
 #pragma unroll
@@ -723,20 +750,20 @@ __global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__
             const int f = idx / FXN, rr = idx - f * FXN;
             const int row = rr / AG::SX, c = rr - row * AG::SX;
             const T* zp = sz + (f < 3 ? f : 4) * ZG::P + (row + 4) * ZG::SX + c + 2;
-            fx[idx] = kof(sk[(row + 2) * AG::SX + c], f) * d5(zp[-2], zp[-1], zp[1], zp[2], ihx);
+            fx[idx] = kof(sk[(row + 2) * AG::SX + c], f, false) * d5(zp[-2], zp[-1], zp[1], zp[2], ihx);
         }
         for (int idx = threadIdx.x; idx < 4 * FYN; idx += NTHR) {
             const int f = idx / FYN, rr = idx - f * FYN;
             const int row = rr / kMTX, c = rr - row * kMTX;
             const T* zp = sz + (f < 3 ? f : 4) * ZG::P + (row + 2) * ZG::SX + c + 4;
-            fy[idx] = kof(sk[row * AG::SX + c + 2], f) *
+            fy[idx] = kof(sk[row * AG::SX + c + 2], f, false) *
                       d5(zp[-2 * ZG::SX], zp[-ZG::SX], zp[ZG::SX], zp[2 * ZG::SX], ihy);
         }
         __syncthreads();
         if (mine) {
             const long long i = (long long)z * nxy + col;
-            T km0, kt0;
-            pc_k3(g, sk[(ty + 2) * AG::SX + tx + 2], km0, kt0);
+            const Coef<T> kc0 = pc_k3(g, sk[(ty + 2) * AG::SX + tx + 2]);
+            const T dmom = pc_diag3(g, kc0.mh, kc0.mv), dth = pc_diag3(g, kc0.hh, kc0.hv);
             const T* ua = sa + (ty + 2) * AG::SX + tx + 2;
             const T* va = ua + AG::P;
             const T a[3] = {ua[0], va[0], wq[2]};
@@ -763,9 +790,8 @@ __global__ __launch_bounds__(256) void k3m_pc_sweep(Geo g, const T* __restrict__
                     cv += T(0.5) * (d5(wq[0] * zq[k][0], wq[1] * zq[k][1], wq[3] * zq[k][3], wq[4] * zq[k][4], ihz) +
                                     a[2] * d5(zq[k][0], zq[k][1], zq[k][3], zq[k][4], ihz));
                 }
-                const T kk = k == 3 ? T(0) : (k == 4 ? kt0 : km0);
                 const T Pz = T(g.two_dt) * zc + (cv - diff);
-                const T dd = T(g.two_dt) + cD * kk * ih2;
+                const T dd = k == 3 ? T(g.two_dt) : (k == 4 ? dth : dmom);
                 const T zn = zc + (r[k * np + i] - Pz) / dd;
                 zout[k * np + i] = zn;
                 acc += (double)zn * (double)zn;
@@ -801,11 +827,8 @@ __global__ __launch_bounds__(256) void k3_pc_diag(Geo g, const T* __restrict__ n
     double acc = 0.0;
     if (i < g.npts) {
         const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zz = (int)(i / ((long long)g.nx * g.ny));
-        T km, kt;
-        pc_k3(g, nuext(g, nu, x, y, zz), km, kt);
-        const T ih2 = T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
-        const T cD = T(65.0 / 72.0);
-        const T dm = T(g.two_dt) + cD * km * ih2, dt_ = T(g.two_dt) + cD * kt * ih2;
+        const Coef<T> kc = pc_k3(g, nuext(g, nu, x, y, zz));
+        const T dm = pc_diag3(g, kc.mh, kc.mv), dt_ = pc_diag3(g, kc.hh, kc.hv);
         const T dd[5] = {dm, dm, dm, T(g.two_dt), dt_};
         const double dv = div ? *div : 1.0;
         const long long np = g.npts;

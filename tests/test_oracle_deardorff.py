@@ -34,6 +34,16 @@ def test_equal_spacing_reduces_to_scaled_smagorinsky():
     np.testing.assert_allclose(KM, Km, rtol=1e-13, atol=0)
 
 
+def test_equal_spacing_3d_reduces_to_scaled_smagorinsky():
+    # 20 x 20 x 10 km on 32 x 32 x 16: dx = dy = dz = 625 m
+    prob = I.thermal_neutral_3d(32, 32, 16).replace(closure=I.CLOSURE_DEARDORFF, n_bv=0.01)
+    S, shape = _strain(prob, 7)
+    Km, KM, _, _ = M.deardorff_coefficients(prob, S)
+    nu, _ = M.eddy_viscosity(prob.replace(closure=I.CLOSURE_SMAGORINSKY), S, shape)
+    np.testing.assert_allclose(Km, 2.0 ** (-1.0 / 3.0) * nu, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(KM, Km, rtol=1e-13, atol=0)
+
+
 def test_vertical_over_horizontal_is_spacing_ratio_to_four_thirds():
     prob = I.thermal_stable_2d(48, 40).replace(closure=I.CLOSURE_DEARDORFF)   # dx 417 m, dz 250 m
     S, _ = _strain(prob, 2)

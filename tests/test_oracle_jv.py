@@ -25,6 +25,7 @@ def _cases():
         ("deardorff-neutral", I.thermal_neutral_2d(24, 16).replace(closure=I.CLOSURE_DEARDORFF)),
         ("deardorff-island-noslip", I.heat_island_2d(32, 12, h0=400.0, width=8000.0)
          .replace(closure=I.CLOSURE_DEARDORFF)),
+        ("deardorff-3d", I.thermal_neutral_3d(12, 10, 8).replace(closure=I.CLOSURE_DEARDORFF, n_bv=0.01)),
     ]
 
 
