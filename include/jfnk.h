@@ -74,7 +74,7 @@ typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIOD
  * the coefficient of (p_bar + p') div u in the Exner equation (<= 0: R/cv).
  * Closure (section 2.4): Smagorinsky nu = (cs Delta)^2 sqrt(2 S:S), Delta the
  * geometric mean spacing, heat diffusivity nu/pr_t; or constant k_m, k_h; or
- * (outside a batch) the anisotropic coefficients of Eq. 7:
+ * the anisotropic coefficients of Eq. 7:
  * K_m = cs^(4/3) eps^(1/3) (dx dy)^(2/3), K_M = cs^(4/3) eps^(1/3) dz^(4/3) with
  * eps = nu S:S, K_h = (1 + 2l/sqrt(dx dy)) K_m, K_H = (1 + 2l/dz) K_M (dy = dx in
  * 2D), the mixing length

@@ -578,6 +578,55 @@ bool valid_problem(const jfnk_problem* p, std::string& why) {
 
 }  // namespace
 
+// Device geometry and coefficients of a problem (grid, boundary kinds, physical
+// constants, closure constants).
+void fill_geo(const jfnk_problem& p, Geo& g) {
+    g.dim = p.dim;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.nz = p.nz;
+    g.npts = (long long)p.nx * p.ny * p.nz;
+    g.bcl = p.bc_lateral;
+    g.bcv = p.bc_vertical;
+    g.W = p.dd_p == 3 ? 4 : 2;
+    g.dx = p.lx / p.nx;
+    g.dy = p.ly / p.ny;
+    g.dz = p.lz / p.nz;
+    g.idx = 1.0 / g.dx;
+    g.idy = 1.0 / g.dy;
+    g.idz = 1.0 / g.dz;
+    g.two_dt = 2.0 / p.dt;
+    g.theta0 = p.theta0;
+    g.g_theta0 = p.g / p.theta0;
+    g.kappa = p.kappa_div > 0 ? p.kappa_div : p.rgas / p.cv;
+    g.kappa_cp = g.kappa * p.cp;
+    g.beta = p.n_bv * p.n_bv * p.theta0 / p.g;
+    g.closure = p.closure;
+    const double delta = p.dim == 2 ? std::sqrt(g.dx * g.dz) : std::cbrt(g.dx * g.dy * g.dz);
+    g.smag = (p.cs * delta) * (p.cs * delta);
+    g.inv_pr = p.pr_t > 0 ? 1.0 / p.pr_t : 0.0;
+    if (p.closure == JFNK_CLOSURE_DEARDORFF) {
+        // eps^(1/3) = (cs Delta)^(2/3) 2^(1/6) |S|, so every coefficient is linear in |S|
+        // below the mixing-length cap; the horizontal scale sqrt(dx dy) (dy = dx in 2D)
+        const double gm = std::cbrt((p.cs * delta) * (p.cs * delta)) * std::pow(2.0, 1.0 / 6.0);
+        const double c43 = std::pow(p.cs, 4.0 / 3.0);
+        const double dh = p.dim == 3 ? std::sqrt(g.dx * g.dy) : g.dx;
+        g.dd_ah = c43 * gm * std::pow(dh, 4.0 / 3.0);
+        g.dd_av = c43 * gm * std::pow(g.dz, 4.0 / 3.0);
+        g.dd_ch = 2.0 * g.dd_ah / dh;
+        g.dd_cv = 2.0 * g.dd_av / g.dz;
+        g.dd_delta = delta;
+        g.dd_b = p.n_bv > 0 ? 0.75 * std::pow(2.0, 2.0 / 3.0) * std::cbrt((p.cs * delta) * (p.cs * delta)) *
+                                   std::cbrt(delta) / p.n_bv
+                             : 0.0;
+        g.dd_inv_nu = g.smag > 0 ? 1.0 / (g.smag * std::sqrt(2.0)) : 0.0;
+    }
+    g.k_m = p.k_m;
+    g.k_h = p.k_h;
+    g.convection = p.convection;
+    g.energy_test = p.energy_test;
+}
+
 void set_error(const std::string& msg) { g_err = msg; }
 
 int hip_fail(hipError_t e, const char* what) {
@@ -613,51 +662,8 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     c->stream = (hipStream_t)stream;
     c->max_m = max_m;
     JFNK_HIP(hipGetDevice(&c->device));
+    fill_geo(*p, c->geo);
     Geo& g = c->geo;
-    g.dim = p->dim;
-    g.nx = p->nx;
-    g.ny = p->ny;
-    g.nz = p->nz;
-    g.npts = (long long)p->nx * p->ny * p->nz;
-    g.bcl = p->bc_lateral;
-    g.bcv = p->bc_vertical;
-    g.W = p->dd_p == 3 ? 4 : 2;
-    g.dx = p->lx / p->nx;
-    g.dy = p->ly / p->ny;
-    g.dz = p->lz / p->nz;
-    g.idx = 1.0 / g.dx;
-    g.idy = 1.0 / g.dy;
-    g.idz = 1.0 / g.dz;
-    g.two_dt = 2.0 / p->dt;
-    g.theta0 = p->theta0;
-    g.g_theta0 = p->g / p->theta0;
-    g.kappa = p->kappa_div > 0 ? p->kappa_div : p->rgas / p->cv;
-    g.kappa_cp = g.kappa * p->cp;
-    g.beta = p->n_bv * p->n_bv * p->theta0 / p->g;
-    g.closure = p->closure;
-    const double delta = p->dim == 2 ? std::sqrt(g.dx * g.dz) : std::cbrt(g.dx * g.dy * g.dz);
-    g.smag = (p->cs * delta) * (p->cs * delta);
-    g.inv_pr = p->pr_t > 0 ? 1.0 / p->pr_t : 0.0;
-    if (p->closure == JFNK_CLOSURE_DEARDORFF) {
-        // eps^(1/3) = (cs Delta)^(2/3) 2^(1/6) |S|, so every coefficient is linear in |S|
-        // below the mixing-length cap; the horizontal scale sqrt(dx dy) (dy = dx in 2D)
-        const double gm = std::cbrt((p->cs * delta) * (p->cs * delta)) * std::pow(2.0, 1.0 / 6.0);
-        const double c43 = std::pow(p->cs, 4.0 / 3.0);
-        const double dh = p->dim == 3 ? std::sqrt(g.dx * g.dy) : g.dx;
-        g.dd_ah = c43 * gm * std::pow(dh, 4.0 / 3.0);
-        g.dd_av = c43 * gm * std::pow(g.dz, 4.0 / 3.0);
-        g.dd_ch = 2.0 * g.dd_ah / dh;
-        g.dd_cv = 2.0 * g.dd_av / g.dz;
-        g.dd_delta = delta;
-        g.dd_b = p->n_bv > 0 ? 0.75 * std::pow(2.0, 2.0 / 3.0) * std::cbrt((p->cs * delta) * (p->cs * delta)) *
-                                   std::cbrt(delta) / p->n_bv
-                             : 0.0;
-        g.dd_inv_nu = g.smag > 0 ? 1.0 / (g.smag * std::sqrt(2.0)) : 0.0;
-    }
-    g.k_m = p->k_m;
-    g.k_h = p->k_h;
-    g.convection = p->convection;
-    g.energy_test = p->energy_test;
     c->nf = p->dim == 2 ? 4 : 5;
     c->n = c->nf * g.npts;
     const long long n = c->n;

@@ -742,39 +742,14 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
         const jfnk_problem& p = probs[i];
         std::string why;
         if (p.dim != 2 || p.ny != 1 || p.nx < 8 || p.nz < 8 || !(p.dt > 0) || p.dd_p != 2 || p.closure < 0 ||
-            p.closure > 2 || (p.closure == JFNK_CLOSURE_SMAGORINSKY && !(p.pr_t > 0))) {
+            p.closure > 3 || (p.closure == JFNK_CLOSURE_SMAGORINSKY && !(p.pr_t > 0)) ||
+            (p.closure == JFNK_CLOSURE_DEARDORFF && (!(p.cs >= 0) || !(p.n_bv >= 0)))) {
             set_error("batch instance " + std::to_string(i) + ": unsupported or invalid problem");
             return fail(JFNK_ERR_ARG);
         }
         b->probs.push_back(p);
         Geo g{};
-        g.dim = 2;
-        g.nx = p.nx;
-        g.ny = 1;
-        g.nz = p.nz;
-        g.npts = (long long)p.nx * p.nz;
-        g.bcl = p.bc_lateral;
-        g.bcv = p.bc_vertical;
-        g.dx = p.lx / p.nx;
-        g.dy = 1.0;
-        g.dz = p.lz / p.nz;
-        g.idx = 1.0 / g.dx;
-        g.idy = 1.0;
-        g.idz = 1.0 / g.dz;
-        g.two_dt = 2.0 / p.dt;
-        g.theta0 = p.theta0;
-        g.g_theta0 = p.g / p.theta0;
-        g.kappa = p.kappa_div > 0 ? p.kappa_div : p.rgas / p.cv;
-        g.kappa_cp = g.kappa * p.cp;
-        g.beta = p.n_bv * p.n_bv * p.theta0 / p.g;
-        g.closure = p.closure;
-        const double delta = std::sqrt(g.dx * g.dz);
-        g.smag = (p.cs * delta) * (p.cs * delta);
-        g.inv_pr = p.pr_t > 0 ? 1.0 / p.pr_t : 0.0;
-        g.k_m = p.k_m;
-        g.k_h = p.k_h;
-        g.convection = p.convection;
-        g.energy_test = p.energy_test;
+        fill_geo(p, g);
         b->geos.push_back(g);
         const long long n = 4 * g.npts;
         b->voff.push_back(b->voff.back() + n);

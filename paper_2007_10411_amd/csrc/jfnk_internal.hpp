@@ -226,6 +226,8 @@ int hip_fail(hipError_t e, const char* what);
 // out = F(u) (what 0), 2u/dt + F(u) (what 1), 2u/dt - F(u) - f (what 2)
 // var: tile variant chosen by the autotuner (tile height 4 << var)
 int tile_tz(int variant);
+// device geometry and coefficients of a problem (grid, boundaries, constants, closure)
+void fill_geo(const jfnk_problem& p, Geo& g);
 template <typename T>
 hipError_t launch_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, hipStream_t s, int var = 1);
 // Jv = 2v/dt - [F(u + eps v) - F(u)]/eps, expanded; eps read from *eps_dev if non-null

@@ -1,7 +1,8 @@
 """Batched ensemble (one launch per stage over all instances) against the FP64
 oracle per instance: residuals to 1e-11, a mixed-precision implicit step of
-uneven instances against the oracle's step, the 64-instance heat-island
-ensemble, and the autotuner's choice not changing results."""
+uneven instances (one with the anisotropic coefficients of Eq. 7) against the
+oracle's step, the 64-instance heat-island ensemble, and the autotuner's choice
+not changing results."""
 import time
 
 import numpy as np
@@ -18,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 def _small_ensemble():
     return [I.heat_island_2d(64, 16, h0=300.0, width=6000.0),
+            I.thermal_stable_2d(80, 32).replace(closure=I.CLOSURE_DEARDORFF),
             I.thermal_stable_2d(96, 40),
             I.heat_island_2d(130, 24, h0=80.0, width=3000.0, n_bv=0.015),
             I.thermal_neutral_2d(72, 36),

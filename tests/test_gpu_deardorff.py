@@ -170,10 +170,3 @@ def test_newton_step_3d_f64_matches_oracle():
     r = c.newton_step(un, u, rtol=1e-13)
     assert r.converged
     assert_fields_close(host(u), ref, F64_TOL, "newton 3d f64")
-
-
-def test_rejected_in_the_ensemble():
-    from paper_2007_10411_amd._lib import JfnkError
-    from paper_2007_10411_amd.jfnk import Batch
-    with pytest.raises(JfnkError):
-        Batch([I.thermal_stable_2d(64, 32).replace(closure=D)], max_m=8)
