@@ -174,7 +174,8 @@ __global__ __launch_bounds__(kB) void kb_finish(BTab t, const double* __restrict
 }
 
 // Gram-Schmidt passes, one chunk per block, basis vectors j of all instances at
-// V + j * ntot (modes as in the single-problem pass)
+// V + j * ntot (modes as in the single-problem pass); basis staged in LDS, used
+// beyond 32 basis vectors (kb_cgs_reg below up to 32)
 template <typename T, int NV>
 __global__ __launch_bounds__(kB) void kb_cgs(BTab t, const T* __restrict__ V, long long ntot, int nv,
                                              const double* __restrict__ hin, T* __restrict__ w,
@@ -247,6 +248,61 @@ __global__ __launch_bounds__(kB) void kb_cgs(BTab t, const T* __restrict__ V, lo
             if (lane == 0) partials[(long long)v * nchunks + blockIdx.x] = s;
         }
     }
+}
+
+// The same passes with the basis held in registers (as the single-problem
+// k_cgs_reg): one element per thread and step, all NV basis loads of the
+// element issued before its arithmetic (rows nv..NV-1 re-read row nv-1 with a
+// zero coefficient), FP64 dots per thread reduced once per block.
+template <typename T, int NV, int MODE>
+__global__ __launch_bounds__(kB) void kb_cgs_reg(BTab t, const T* __restrict__ V, long long ntot, int nv,
+                                                 const double* __restrict__ hin, T* __restrict__ w,
+                                                 double* __restrict__ partials, int nchunks) {
+    constexpr bool kDots = MODE != CGS_UPD_NORM;
+    constexpr bool kUpd = MODE != CGS_DOT;
+    __shared__ double red[4][kDots ? NV : 1];
+    const Chunk c = chunk_of(t);
+    if (inactive(t, c.inst)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double h[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) h[v] = (kUpd && v < nv) ? hin[(long long)c.inst * M + v] : 0.0;
+    double acc[kDots ? NV : 1];
+#pragma unroll
+    for (int v = 0; v < (kDots ? NV : 1); ++v) acc[v] = 0.0;
+    double nacc = 0.0;
+    for (long long i = c.b + tid; i < c.e; i += kB) {
+        T wv = w[i];
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < nv ? v : nv - 1) * ntot + i];
+        __builtin_amdgcn_sched_barrier(0);   // all loads of the element ahead of its arithmetic
+        if (kUpd) {
+            double sacc = (double)wv;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sacc -= h[v] * (double)x[v];
+            wv = (T)sacc;
+            w[i] = wv;
+        }
+        if (kDots) {
+            const double wd = (double)wv;
+#pragma unroll
+            for (int v = 0; v < (kDots ? NV : 1); ++v) acc[v] += (double)x[v] * wd;
+        } else {
+            nacc += (double)wv * (double)wv;
+        }
+    }
+    if (!kDots) {
+        const double s = block_sum256(nacc, &red[0][0]);
+        if (tid == 0) partials[blockIdx.x] = s;
+        return;
+    }
+    constexpr int kSpan = 64 / NV;
+    const double s = wave_sum_scatter<kDots ? NV : 1>(acc, lane);
+    if (lane % kSpan == 0) red[wid][lane / kSpan] = s;
+    __syncthreads();
+    if (tid < nv)
+        partials[(long long)tid * nchunks + blockIdx.x] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // block (i, v): hout[i][v] = sum over instance i's chunks; after the last pass
@@ -484,20 +540,38 @@ int b_norm2(jfnk_batch* b, const T* x, double* out, int stride, int mode, bool m
     return JFNK_OK;
 }
 
+template <typename T, int NV>
+hipError_t launch_kb_cgs_reg_nv(const BTab& t, const T* V, long long ntot, int nv, const double* hin, T* w,
+                                double* partials, int nchunks, int mode, hipStream_t s) {
+    const dim3 grid(nchunks);
+    if (mode == CGS_DOT)
+        hipLaunchKernelGGL((kb_cgs_reg<T, NV, CGS_DOT>), grid, dim3(kB), 0, s, t, V, ntot, nv, hin, w, partials,
+                           nchunks);
+    else if (mode == CGS_UPD_DOT)
+        hipLaunchKernelGGL((kb_cgs_reg<T, NV, CGS_UPD_DOT>), grid, dim3(kB), 0, s, t, V, ntot, nv, hin, w, partials,
+                           nchunks);
+    else
+        hipLaunchKernelGGL((kb_cgs_reg<T, NV, CGS_UPD_NORM>), grid, dim3(kB), 0, s, t, V, ntot, nv, hin, w,
+                           partials, nchunks);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_kb_cgs_reg(const BTab& t, const T* V, long long ntot, int nv, const double* hin, T* w,
+                             double* partials, int nchunks, int mode, hipStream_t s) {
+    if (nv <= 8) return launch_kb_cgs_reg_nv<T, 8>(t, V, ntot, nv, hin, w, partials, nchunks, mode, s);
+    if (nv <= 16) return launch_kb_cgs_reg_nv<T, 16>(t, V, ntot, nv, hin, w, partials, nchunks, mode, s);
+    return launch_kb_cgs_reg_nv<T, 32>(t, V, ntot, nv, hin, w, partials, nchunks, mode, s);
+}
+
 template <typename T>
 int b_cgs(jfnk_batch* b, int nv, int mode, const double* hin, T* w, double* hout, int j, int m) {
     const BTab t = tab(b, 1, true);
     const long long ntot = b->ntot;
     const dim3 grid(b->nchunks);
-    if (nv <= 8)
-        hipLaunchKernelGGL((kb_cgs<T, 8>), grid, dim3(kB), 0, b->stream, t, (const T*)b->V32, ntot, nv, hin, w,
-                           b->partials, b->nchunks, mode);
-    else if (nv <= 16)
-        hipLaunchKernelGGL((kb_cgs<T, 16>), grid, dim3(kB), 0, b->stream, t, (const T*)b->V32, ntot, nv, hin, w,
-                           b->partials, b->nchunks, mode);
-    else if (nv <= 32)
-        hipLaunchKernelGGL((kb_cgs<T, 32>), grid, dim3(kB), 0, b->stream, t, (const T*)b->V32, ntot, nv, hin, w,
-                           b->partials, b->nchunks, mode);
+    if (nv <= 32)
+        JFNK_HIP(launch_kb_cgs_reg<T>(t, (const T*)b->V32, ntot, nv, hin, w, b->partials, b->nchunks, mode,
+                                      b->stream));
     else
         hipLaunchKernelGGL((kb_cgs<T, 64>), grid, dim3(kB), 0, b->stream, t, (const T*)b->V32, ntot, nv, hin, w,
                            b->partials, b->nchunks, mode);

@@ -15,6 +15,30 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
+// Sums a[0..NV) over the 64 lanes of a wavefront by recursive halving: each
+// exchange step hands half of the values held to the partner lane, so NV
+// values cost NV - 1 + log2(64 / NV) shuffles instead of 6 NV.  On return the
+// lane holds the wavefront total of value lane / (64 / NV).
+template <int NV>
+__device__ __forceinline__ double wave_sum_scatter(double (&a)[NV], int lane) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two up to 64");
+    int d = 32;
+#pragma unroll
+    for (int K = NV; K > 1; K >>= 1, d >>= 1) {
+        const int half = K >> 1;
+        const bool up = (lane & d) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double lo = a[k], hi = a[k + half];
+            const double recv = __shfl_xor(up ? lo : hi, d, 64);
+            a[k] = (up ? hi : lo) + recv;
+        }
+    }
+    double s = a[0];
+    for (; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    return s;
+}
+
 // Sum of one value per thread of a 256-thread block; valid in thread 0.
 __device__ __forceinline__ double block_sum256(double v, double* red4) {
     v = wave_sum64(v);

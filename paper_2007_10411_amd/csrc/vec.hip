@@ -253,11 +253,14 @@ __global__ void k_set_start(const double* beta2, double* g, double* beta, int m)
 //   CGS_DOT       hout = V^T w
 //   CGS_UPD_DOT   w <- w - V hin, hout = V^T w          (basis values reused from registers)
 //   CGS_UPD_NORM  w <- w - V hin, ||w||^2, then the Givens step of column j
-// Partial sums per block are finished by the last block of the same launch.
+// Each block writes its partial sums; k_cgs_finish adds them in a fixed order.
+// Up to 32 basis vectors the passes run in k_cgs_reg (basis in registers),
+// beyond that in k_cgs (basis staged in LDS).
 // ---------------------------------------------------------------------------
-// Chunks of kChunk consecutive elements: V_0..V_{nv-1} of the chunk are staged
-// in LDS once; each thread updates its own element of w, then wavefront k forms
-// the dots of basis vectors k, k+4, ... with the chunk of w (FP64 accumulation).
+// k_cgs: chunks of kChunk consecutive elements; V_0..V_{nv-1} of the chunk are
+// staged in LDS once; each thread updates its own element of w, then wavefront
+// k forms the dots of basis vectors k, k+4, ... with the chunk of w (FP64
+// accumulation).
 constexpr int kChunk = 256;
 
 template <typename T, int NV>
@@ -333,6 +336,66 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const T* __restrict__ V, long lo
             if (lane == 0) partials[(long long)v * gridDim.x + blockIdx.x] = t;
         }
     }
+}
+
+// The same three passes with the basis held in registers instead of LDS: one
+// element of w per thread and step, all NV basis loads of the element issued
+// before any arithmetic (rows nv..NV-1 re-read row nv-1; their update
+// coefficient is zero and their dots are never stored), the dots kept per
+// thread in FP64 and reduced once per block.  No barrier inside the element
+// loop, so the loads of one wavefront overlap the arithmetic of the others.
+// A wavefront-uniform branch per row instead of the clamped re-read makes the
+// compiler wait for each load before issuing the next.
+template <typename T, int NV, int MODE>
+__global__ __launch_bounds__(kBlock) void k_cgs_reg(const T* __restrict__ V, int n, int nv,
+                                                    const double* __restrict__ hin, T* __restrict__ w,
+                                                    double* __restrict__ partials) {
+    constexpr bool kDots = MODE != CGS_UPD_NORM;
+    constexpr bool kUpd = MODE != CGS_DOT;
+    __shared__ double red[4][kDots ? NV : 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double h[NV];                              // update coefficients (wavefront-uniform)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) h[v] = (kUpd && v < nv) ? hin[v] : 0.0;
+    double acc[kDots ? NV : 1];
+#pragma unroll
+    for (int v = 0; v < (kDots ? NV : 1); ++v) acc[v] = 0.0;
+    double nacc = 0.0;
+    const int step = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + tid; i < n; i += step) {
+        T wv = w[i];
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < nv ? v : nv - 1) * n + i];
+        // keep every load of the element ahead of its arithmetic (left alone, the
+        // scheduler of the dot-only pass interleaves them and keeps ~5 in flight)
+        __builtin_amdgcn_sched_barrier(0);
+        if (kUpd) {
+            double sacc = (double)wv;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sacc -= h[v] * (double)x[v];
+            wv = (T)sacc;
+            w[i] = wv;
+        }
+        if (kDots) {
+            const double wd = (double)wv;
+#pragma unroll
+            for (int v = 0; v < (kDots ? NV : 1); ++v) acc[v] += (double)x[v] * wd;
+        } else {
+            nacc += (double)wv * (double)wv;
+        }
+    }
+    if (!kDots) {
+        const double t = block_sum256(nacc, &red[0][0]);
+        if (tid == 0) partials[blockIdx.x] = t;
+        return;
+    }
+    constexpr int kSpan = 64 / NV;             // lanes sharing one value after the scatter
+    const double t = wave_sum_scatter<kDots ? NV : 1>(acc, lane);
+    if (lane % kSpan == 0) red[wid][lane / kSpan] = t;
+    __syncthreads();
+    if (tid < nv)
+        partials[(long long)tid * gridDim.x + blockIdx.x] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // Block v: hout[v] = sum of the pass partials (fixed order).  The last pass has
@@ -513,11 +576,37 @@ int cgs_blocks(long long n) {
     return (int)b;
 }
 
+template <typename T, int NV, int MODE>
+hipError_t launch_cgs_reg_mode(const T* V, int n, int nv, const double* hin, T* w, double* partials, int nb,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((k_cgs_reg<T, NV, MODE>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials);
+    return hipGetLastError();
+}
+
+template <typename T, int NV>
+hipError_t launch_cgs_reg_nv(const T* V, int n, int nv, const double* hin, T* w, double* partials, int mode,
+                             int nb, hipStream_t s) {
+    if (mode == CGS_DOT) return launch_cgs_reg_mode<T, NV, CGS_DOT>(V, n, nv, hin, w, partials, nb, s);
+    if (mode == CGS_UPD_DOT) return launch_cgs_reg_mode<T, NV, CGS_UPD_DOT>(V, n, nv, hin, w, partials, nb, s);
+    return launch_cgs_reg_mode<T, NV, CGS_UPD_NORM>(V, n, nv, hin, w, partials, nb, s);
+}
+
+template <typename T>
+hipError_t launch_cgs_reg(const T* V, int n, int nv, const double* hin, T* w, double* partials, int mode, int nb,
+                          hipStream_t s) {
+    if (nv <= 8) return launch_cgs_reg_nv<T, 8>(V, n, nv, hin, w, partials, mode, nb, s);
+    if (nv <= 16) return launch_cgs_reg_nv<T, 16>(V, n, nv, hin, w, partials, mode, nb, s);
+    return launch_cgs_reg_nv<T, 32>(V, n, nv, hin, w, partials, mode, nb, s);
+}
+
 template <typename T>
 hipError_t launch_cgs(const T* V, long long n, int nv, const double* hin, T* w, double* partials,
                       double* hout, int mode, const GivensArgs& ga, hipStream_t s) {
     const int nb = cgs_blocks(n);
-    if (nv <= 8)
+    if (nv <= 32 && n < (1LL << 30)) {   // int element index with room for the grid stride
+        const hipError_t e = launch_cgs_reg<T>(V, (int)n, nv, hin, w, partials, mode, nb, s);
+        if (e != hipSuccess) return e;
+    } else if (nv <= 8)
         hipLaunchKernelGGL((k_cgs<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
     else if (nv <= 16)
         hipLaunchKernelGGL((k_cgs<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, n, nv, hin, w, partials, mode);
