@@ -489,7 +489,7 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_launch": per, "avg_launch_us": ms / max(launches, 1) * 1e3, "launches": launches}
 
-    kernels = {"arnoldi": "k_cgs<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
+    kernels = {"arnoldi": "k_cgs_reg<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
                "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner)",
                "jv": f"{jv_kernel_name(shapes['f32_jv'])} (stable finite-difference Jv)"}
     traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_stable_1024x512",
