@@ -123,7 +123,7 @@ struct NetBuffers {
     float* g0 = nullptr;             // 16 x npts gradients
     float* g1 = nullptr;
     float* wpart = nullptr;          // per-tile weight-gradient partials
-    unsigned short* abf = nullptr;   // 2 x 16 x npts bf16 activations
+    unsigned short* abf = nullptr;   // 2 x npts x 16 bf16 activations, pixel-major (channel innermost)
     int nparam = 0;
     int adam_t = 0;
     int dil[4] = {1, 1, 1, 1};       // per-layer dilation of the 3x3 kernels

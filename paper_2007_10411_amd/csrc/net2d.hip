@@ -7,7 +7,9 @@
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one 3x3 tap per instruction);
 // training (forward, backward, Adam on FP32 master weights) runs in FP32.
 //
-// Activations are channel-major [c][nz][nx] like the state vectors.  Parameters
+// The FP32 training activations are channel-major [c][nz][nx] like the state
+// vectors; the BF16 inference activations are pixel-major [pixel][16], so one
+// pixel's channels are one 32-byte row.  Parameters
 // are one flat FP32 vector: per layer W[co][ci][kz][kx] (tap offsets kz-1, kx-1)
 // followed by b[co].
 
@@ -153,20 +155,43 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
                                                    unsigned short* __restrict__ post, const float* __restrict__ r,
                                                    const float* __restrict__ s, float half_dt,
                                                    float* __restrict__ z, int dil) {
-    __shared__ unsigned short sin_[kSZ][kSX][kHid];   // pixel-major, channel-innermost
+    __shared__ __align__(16) unsigned short sin_[kSZ][kSX][kHid];   // pixel-major, channel-innermost
     const long long np = (long long)nx * nz;
     const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
     const int SZ = kTZ + 2 * dil, SX = kTX + 2 * dil;   // staged region for this dilation
-    for (int idx = threadIdx.x; idx < kHid * SZ * SX; idx += 256) {
-        const int c = idx / (SZ * SX), rem = idx - c * (SZ * SX);
-        const int lz = rem / SX, lx = rem - lz * SX;
-        const int gx = x0 + lx - dil, gz = z0 + lz - dil;
-        unsigned short v = 0;
-        if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz) {
-            const long long o = (long long)c * np + (long long)gz * nx + gx;
-            v = (MODE == L_FIRST) ? f2bf(r[o] / s[c]) : in[o];
+    if (MODE == L_FIRST) {
+        // the state vector r: channel-major FP32, scaled by s and rounded to BF16
+        for (int idx = threadIdx.x; idx < kHid * SZ * SX; idx += 256) {
+            const int c = idx / (SZ * SX), rem = idx - c * (SZ * SX);
+            const int lz = rem / SX, lx = rem - lz * SX;
+            const int gx = x0 + lx - dil, gz = z0 + lz - dil;
+            unsigned short v = 0;
+            if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz)
+                v = f2bf(r[(long long)c * np + (long long)gz * nx + gx] / s[c]);
+            sin_[lz][lx][c] = v;
         }
-        sin_[lz][lx][c] = v;
+    } else {
+        // hidden activations: pixel-major BF16, 32 bytes per pixel, copied as two
+        // 16-byte halves (four loads in flight per thread before their stores)
+        const int nh = SZ * SX * 2;
+        for (int i0 = threadIdx.x; i0 < nh; i0 += 4 * 256) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * 256, p = idx >> 1;
+                const int lz = p / SX, lx = p - lz * SX;
+                const int gx = x0 + lx - dil, gz = z0 + lz - dil;
+                v[u] = uint4{0u, 0u, 0u, 0u};
+                if (idx < nh && gx >= 0 && gx < nx && gz >= 0 && gz < nz)
+                    v[u] = reinterpret_cast<const uint4*>(in + ((long long)gz * nx + gx) * kHid)[idx & 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * 256, p = idx >> 1;
+                const int lz = p / SX, lx = p - lz * SX;
+                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[lz][lx][8 * (idx & 1)]) = v[u];
+            }
+        }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;          // k group of 4 channels
@@ -188,8 +213,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int dz = (t / 3) * dil, dx = (t % 3) * dil;
-            const unsigned short* ap = &sin_[wv + dz][px + dx][4 * kg];
-            const bf16x4_t a = bf16x4_t{(short)ap[0], (short)ap[1], (short)ap[2], (short)ap[3]};
+            const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&sin_[wv + dz][px + dx][4 * kg]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
         }
         // D: rows (pixels) 4 kg + i, column (output channel) col
@@ -198,12 +222,13 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
         for (int i = 0; i < 4; ++i) {
             const int gx = x0 + st * 16 + 4 * kg + i;
             if (gx >= nx) continue;
-            const long long o = (long long)col * np + (long long)gz * nx + gx;
             const float h = acc[i] + bias;
-            if (MODE == L_LAST)
+            if (MODE == L_LAST) {
+                const long long o = (long long)col * np + (long long)gz * nx + gx;
                 z[o] = half_dt * r[o] + s[col] * h;
-            else
-                post[o] = f2bf(gelu(h));
+            } else {
+                post[((long long)gz * nx + gx) * kHid + col] = f2bf(gelu(h));   // pixel-major
+            }
         }
     }
 }

@@ -6,7 +6,8 @@
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one tap per instruction, 27
 // per 16-point subtile); training (forward, backward, Adam) runs in FP32.
 //
-// Activations are channel-major [c][nz][ny][nx] like the state vectors.
+// The FP32 training activations are channel-major [c][nz][ny][nx] like the
+// state vectors; the BF16 inference activations are pixel-major [point][16].
 // Parameters: one flat FP32 vector, per layer W[co][ci][kz][ky][kx] then b[co].
 
 #include "jfnk_internal.hpp"
@@ -120,21 +121,46 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
                                                     unsigned short* __restrict__ post, const float* __restrict__ r,
                                                     const float* __restrict__ s, float half_dt,
                                                     float* __restrict__ z) {
-    __shared__ unsigned short sin_[kSZ][kSY][kSX][kHid];
+    __shared__ __align__(16) unsigned short sin_[kSZ][kSY][kSX][kHid];   // pixel-major, channel-innermost
     const long long np = (long long)nx * ny * nz;
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, gz = blockIdx.z;
     constexpr int plane = kSZ * kSY * kSX;
-    for (int idx = threadIdx.x; idx < kHid * plane; idx += 256) {
-        const int c = idx / plane, rem = idx - c * plane;
-        const int lz = rem / (kSY * kSX), rem2 = rem - lz * (kSY * kSX);
-        const int ly = rem2 / kSX, lx = rem2 - ly * kSX;
-        const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
-        unsigned short v = 0;
-        if (c < cin && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz) {
-            const long long o = (long long)c * np + ((long long)zz * ny + gy) * nx + gx;
-            v = (MODE == L_FIRST) ? f2bf(r[o] / s[c]) : in[o];
+    if (MODE == L_FIRST) {
+        // the state vector r: channel-major FP32, scaled by s and rounded to BF16
+        for (int idx = threadIdx.x; idx < kHid * plane; idx += 256) {
+            const int c = idx / plane, rem = idx - c * plane;
+            const int lz = rem / (kSY * kSX), rem2 = rem - lz * (kSY * kSX);
+            const int ly = rem2 / kSX, lx = rem2 - ly * kSX;
+            const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
+            unsigned short v = 0;
+            if (c < cin && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz)
+                v = f2bf(r[(long long)c * np + ((long long)zz * ny + gy) * nx + gx] / s[c]);
+            sin_[lz][ly][lx][c] = v;
         }
-        sin_[lz][ly][lx][c] = v;
+    } else {
+        // hidden activations: pixel-major BF16, 32 bytes per point, copied as two
+        // 16-byte halves (four loads in flight per thread before their stores)
+        constexpr int nh = plane * 2;
+        for (int i0 = threadIdx.x; i0 < nh; i0 += 4 * 256) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * 256, p = idx >> 1;
+                const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
+                const int ly = rem / kSX, lx = rem - ly * kSX;
+                const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
+                v[u] = uint4{0u, 0u, 0u, 0u};
+                if (idx < nh && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz)
+                    v[u] = reinterpret_cast<const uint4*>(in + (((long long)zz * ny + gy) * nx + gx) * kHid)[idx & 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * 256, p = idx >> 1;
+                const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
+                const int ly = rem / kSX, lx = rem - ly * kSX;
+                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][8 * (idx & 1)]) = v[u];
+            }
+        }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
@@ -155,8 +181,7 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) {
             const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const unsigned short* ap = &sin_[dz][wv + dy][px + dx][4 * kg];
-            const bf16x4_t a = bf16x4_t{(short)ap[0], (short)ap[1], (short)ap[2], (short)ap[3]};
+            const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
         }
         if (col >= cout) continue;
@@ -164,12 +189,12 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
         for (int i = 0; i < 4; ++i) {
             const int gx = x0 + st * 16 + 4 * kg + i;
             if (gx >= nx) continue;
-            const long long o = (long long)col * np + ((long long)gz * ny + gy) * nx + gx;
+            const long long pt = ((long long)gz * ny + gy) * nx + gx;
             const float h = acc[i] + bias;
             if (MODE == L_LAST)
-                z[o] = half_dt * r[o] + s[col] * h;
+                z[(long long)col * np + pt] = half_dt * r[(long long)col * np + pt] + s[col] * h;
             else
-                post[o] = f2bf(gelu(h));
+                post[pt * kHid + col] = f2bf(gelu(h));   // pixel-major
         }
     }
 }
