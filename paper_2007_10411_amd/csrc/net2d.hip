@@ -31,6 +31,7 @@ constexpr int kSX = kTX + 2 * kMaxDil, kSZ = kTZ + 2 * kMaxDil;   // input tile 
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
     unsigned u = __float_as_uint(x);
@@ -142,10 +143,11 @@ __global__ __launch_bounds__(256) void k_conv_f32(int nx, int nz, const float* _
 // ---------------------------------------------------------------------------
 // BF16 MFMA convolution for inference.  Wave w of the block computes output row
 // z0 + w, 64 pixels as four 16-pixel MFMA tiles; per tile 9 instructions
-// (one per tap), A = 16 pixels x 16 input channels, B = 16 input x 16 output
-// channels, FP32 accumulation.  Operand layout of v_mfma_f32_16x16x16_bf16:
-// lane l holds A[row l%16][k 4(l/16)..+3], B[k 4(l/16)..+3][col l%16] and
-// D[row 4(l/16)..+3][col l%16].
+// (one per tap), A = 16 output x 16 input channels (the weights), B = 16 input
+// channels x 16 pixels, FP32 accumulation.  Operand layout of
+// v_mfma_f32_16x16x16_bf16: lane l holds A[row l%16][k 4(l/16)..+3],
+// B[k 4(l/16)..+3][col l%16] and D[row 4(l/16)..+3][col l%16], so each lane
+// ends with four consecutive output channels of one pixel: one 8-byte store.
 // Wf: bf16 weights [tap][co][ci] padded to 16 x 16.
 // ---------------------------------------------------------------------------
 template <int MODE>
@@ -155,7 +157,9 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
                                                    unsigned short* __restrict__ post, const float* __restrict__ r,
                                                    const float* __restrict__ s, float half_dt,
                                                    float* __restrict__ z, int dil) {
-    __shared__ __align__(16) unsigned short sin_[kSZ][kSX][kHid];   // pixel-major, channel-innermost
+    // staged input tile, pixel-major with the channels innermost; sized by the
+    // launch for this layer's dilation ((kTZ + 2 dil) x (kTX + 2 dil) pixels)
+    extern __shared__ __align__(16) unsigned short sin_[];
     const long long np = (long long)nx * nz;
     const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
     const int SZ = kTZ + 2 * dil, SX = kTX + 2 * dil;   // staged region for this dilation
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
             unsigned short v = 0;
             if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz)
                 v = f2bf(r[(long long)c * np + (long long)gz * nx + gx] / s[c]);
-            sin_[lz][lx][c] = v;
+            sin_[(lz * SX + lx) * kHid + c] = v;
         }
     } else {
         // hidden activations: pixel-major BF16, 32 bytes per pixel, copied as two
@@ -189,46 +193,51 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * 256, p = idx >> 1;
                 const int lz = p / SX, lx = p - lz * SX;
-                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[lz][lx][8 * (idx & 1)]) = v[u];
+                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[(lz * SX + lx) * kHid + 8 * (idx & 1)]) = v[u];
             }
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;          // k group of 4 channels
-    // B fragments of the 9 taps: W[t][co = col][ci = 4 kg .. 4 kg + 3]
-    bf16x4_t bfrag[9];
+    // A fragments of the 9 taps (weights): W[t][co = col][ci = 4 kg .. 4 kg + 3]
+    bf16x4_t wfrag[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
-        bfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
+        wfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
     }
-    const float bias = col < cout ? b[col] : 0.0f;
+    float bias[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[i] = 4 * kg + i < cout ? b[4 * kg + i] : 0.0f;
     __syncthreads();
     const int gz = z0 + wv;
     if (gz >= nz) return;
 #pragma unroll
     for (int st = 0; st < kTX / 16; ++st) {
         f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int px = st * 16 + col;                   // A row: pixel of this lane
+        const int px = st * 16 + col;                   // B column: pixel of this lane
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int dz = (t / 3) * dil, dx = (t % 3) * dil;
-            const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&sin_[wv + dz][px + dx][4 * kg]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
+            const bf16x4_t xv =
+                *reinterpret_cast<const bf16x4_t*>(&sin_[((wv + dz) * SX + px + dx) * kHid + 4 * kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
         }
-        // D: rows (pixels) 4 kg + i, column (output channel) col
-        if (col >= cout) continue;
+        // D[co = 4 kg + i][pixel = col]: four consecutive output channels of one pixel
+        const int gx = x0 + px;
+        if (gx >= nx) continue;
+        const long long pt = (long long)gz * nx + gx;
+        if (MODE == L_LAST) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int gx = x0 + st * 16 + 4 * kg + i;
-            if (gx >= nx) continue;
-            const float h = acc[i] + bias;
-            if (MODE == L_LAST) {
-                const long long o = (long long)col * np + (long long)gz * nx + gx;
-                z[o] = half_dt * r[o] + s[col] * h;
-            } else {
-                post[((long long)gz * nx + gx) * kHid + col] = f2bf(gelu(h));   // pixel-major
+            for (int i = 0; i < 4; ++i) {
+                const int co = 4 * kg + i;
+                if (co < cout) z[co * np + pt] = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
             }
+        } else {
+            u16x4_t o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
+            *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
         }
     }
 }
@@ -504,18 +513,20 @@ hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt
     if (bf16) {
         unsigned short* a0 = nb.abf;
         unsigned short* a1 = nb.abf + kHid * np;
-        hipLaunchKernelGGL((k_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)nullptr,
-                           L[0].cin, nb.wbf + 0 * 9 * kHid * kHid, nb.theta + L[0].boff, L[0].cout, a0, r, nb.s,
-                           half_dt, (float*)nullptr, nb.dil[0]);
-        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[1].cin,
-                           nb.wbf + 1 * 9 * kHid * kHid, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
-                           (float*)nullptr, nb.dil[1]);
-        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a1, L[2].cin,
-                           nb.wbf + 2 * 9 * kHid * kHid, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
-                           (float*)nullptr, nb.dil[2]);
-        hipLaunchKernelGGL((k_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, nz, (const unsigned short*)a0, L[3].cin,
-                           nb.wbf + 3 * 9 * kHid * kHid, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
-                           nb.s, half_dt, z, nb.dil[3]);
+        auto lds = [](int d) { return (size_t)(kTZ + 2 * d) * (kTX + 2 * d) * kHid * sizeof(unsigned short); };
+        constexpr int wl = 9 * kHid * kHid;   // bf16 weights per layer
+        hipLaunchKernelGGL((k_conv_mfma<L_FIRST>), grid, dim3(256), lds(nb.dil[0]), st, nx, nz,
+                           (const unsigned short*)nullptr, L[0].cin, nb.wbf + 0 * wl, nb.theta + L[0].boff, L[0].cout,
+                           a0, r, nb.s, half_dt, (float*)nullptr, nb.dil[0]);
+        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), lds(nb.dil[1]), st, nx, nz,
+                           (const unsigned short*)a0, L[1].cin, nb.wbf + 1 * wl, nb.theta + L[1].boff, L[1].cout, a1,
+                           r, nb.s, half_dt, (float*)nullptr, nb.dil[1]);
+        hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), lds(nb.dil[2]), st, nx, nz,
+                           (const unsigned short*)a1, L[2].cin, nb.wbf + 2 * wl, nb.theta + L[2].boff, L[2].cout, a0,
+                           r, nb.s, half_dt, (float*)nullptr, nb.dil[2]);
+        hipLaunchKernelGGL((k_conv_mfma<L_LAST>), grid, dim3(256), lds(nb.dil[3]), st, nx, nz,
+                           (const unsigned short*)a0, L[3].cin, nb.wbf + 3 * wl, nb.theta + L[3].boff, L[3].cout,
+                           (unsigned short*)nullptr, r, nb.s, half_dt, z, nb.dil[3]);
         return hipGetLastError();
     }
     float* a0 = nb.act;                 // reuse the training buffers

@@ -27,6 +27,7 @@ constexpr int kSX = kTX + 2, kSY = kTY + 2, kSZ = 3;
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
     unsigned u = __float_as_uint(x);
@@ -113,7 +114,9 @@ __global__ __launch_bounds__(256) void k3_conv_f32(int nx, int ny, int nz, const
 
 // BF16 MFMA convolution for inference.  Block: 64 x 4 points of one z plane,
 // wavefront w computes row y0 + w as four 16-point subtiles; the input (3 x 6 x
-// 66 points, 16 channels, channel innermost) is staged in LDS once.
+// 66 points, 16 channels, channel innermost) is staged in LDS once.  A = the
+// weights (output x input channels), B = input channels x 16 points, so each
+// lane ends with four consecutive output channels of one point.
 template <int MODE>
 __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, const unsigned short* __restrict__ in,
                                                     int cin, const unsigned short* __restrict__ Wf,
@@ -164,37 +167,43 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
-    bf16x4_t bfrag[kTaps];
+    bf16x4_t wfrag[kTaps];                           // A fragments (weights): W[t][co = col][ci = 4 kg ..]
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) {
         const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
-        bfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
+        wfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
     }
-    const float bias = col < cout ? b[col] : 0.0f;
+    float bias[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[i] = 4 * kg + i < cout ? b[4 * kg + i] : 0.0f;
     __syncthreads();
     const int gy = y0 + wv;
     if (gy >= ny) return;
 #pragma unroll
     for (int st = 0; st < kTX / 16; ++st) {
         f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int px = st * 16 + col;
+        const int px = st * 16 + col;                   // B column: point of this lane
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) {
             const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfrag[t], acc, 0, 0, 0);
+            const bf16x4_t xv = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
         }
-        if (col >= cout) continue;
+        // D[co = 4 kg + i][point = col]: four consecutive output channels of one point
+        const int gx = x0 + px;
+        if (gx >= nx) continue;
+        const long long pt = ((long long)gz * ny + gy) * nx + gx;
+        if (MODE == L_LAST) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int gx = x0 + st * 16 + 4 * kg + i;
-            if (gx >= nx) continue;
-            const long long pt = ((long long)gz * ny + gy) * nx + gx;
-            const float h = acc[i] + bias;
-            if (MODE == L_LAST)
-                z[(long long)col * np + pt] = half_dt * r[(long long)col * np + pt] + s[col] * h;
-            else
-                post[pt * kHid + col] = f2bf(gelu(h));   // pixel-major
+            for (int i = 0; i < 4; ++i) {
+                const int co = 4 * kg + i;
+                if (co < cout) z[co * np + pt] = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
+            }
+        } else {
+            u16x4_t o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
+            *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
         }
     }
 }
