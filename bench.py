@@ -5,9 +5,16 @@ over 20 x 10 km, N = 0.01 1/s, +2 K bubble, dt = 1 s, Smagorinsky closure.  One
 step = one trapezoidal implicit step solved by inexact Newton (Eisenstat-Walker
 forcing) to a relative residual of 1e-8, FGMRES(30).
 
+The physics-based preconditioner of the timed legs applies its field-block
+diagonal with --pc-sweeps Jacobi sweeps (default 0): on this workload the GMRES
+iteration count is the same for 0 to 8 sweeps (the acoustic coupling between
+fields, which no field block holds, sets it), so each sweep only adds time.
+
 Legs, all from the same state after the warm-up steps:
   mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton   (timed leg)
   plain     FP64 everywhere, physics-based preconditioner
+  mixed_pc_sweeps2  the mixed leg with two preconditioner sweeps (the source of
+            roofline_pc, whose kernels the timed legs launch without sweeps)
   learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
             the network is trained first on pairs the solver generates on this
             workload (training time reported, not timed with the steps)
@@ -24,7 +31,8 @@ Printed JSON line:
   ms_per_step    wall time per implicit step of the timed leg
   roofline       the dominant kernel class of the timed leg (algorithmic bytes over
                  the summed HIP-event time of its launches) against 8 TB/s HBM;
-                 roofline_jv for the Jv kernel, roofline_net for the network.
+                 roofline_jv for the Jv kernel, roofline_pc for the preconditioner
+                 (from mixed_pc_sweeps2), roofline_net for the network.
                  Each leg runs its steps twice from the same state: the wall time
                  above comes from the run without instrumentation, the per-class
                  HIP events from the second run (their packets add ~20% to a step)
@@ -70,7 +78,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,learned,p3,deardorff,3d")
+    ap.add_argument("--legs", default="mixed,plain,sweeps2,learned,p3,deardorff,3d")
+    ap.add_argument("--pc-sweeps", type=int, default=0,
+                    help="Jacobi sweeps of the physics preconditioner in the timed legs (0: its field-block "
+                         "diagonal alone; the sweeps2 leg repeats the timed configuration with 2)")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=512)
@@ -139,7 +150,7 @@ def per_step(leg):
             "kernel_ms_per_step": {c: v[0] / k for c, v in leg["tm"].items()}}
 
 
-def cpu_baseline(prob, U0, seconds):
+def cpu_baseline(prob, U0, seconds, sweeps):
     """Oracle (FP64 numpy) on a bounded sample of the same workload: GMRES
     iterations of the first Newton iteration of the first step (physics
     preconditioner, stable-FD Jv, CGS2 Arnoldi), stopped after `seconds`."""
@@ -165,7 +176,7 @@ def cpu_baseline(prob, U0, seconds):
             calls[0] += 1
             return M.jv(prob, U0, v, M.fd_eps(prob, U0, v, 2.0 ** -52))
 
-        pc = lambda r: PC.physics_pc(prob, U0, r, 2, fr)
+        pc = lambda r: PC.physics_pc(prob, U0, r, sweeps, fr)
         try:
             K.fgmres(mv, pc, -R, m=30, tol=1e-12, max_iters=10 ** 6, true_residual=False)
         except Stop:
@@ -173,7 +184,7 @@ def cpu_baseline(prob, U0, seconds):
         el = time.perf_counter() - t0
     gpts = prob.npts * calls[0] / el / 1e9
     return {"value": gpts, "unit": "Gpoint-residuals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{calls[0]} FP64 GMRES iterations (PC + Jv + CGS2) of the first Newton "
+            "sample": f"{calls[0]} FP64 GMRES iterations (PC with {sweeps} sweeps + Jv + CGS2) of the first Newton "
                       f"iteration of step 1 on the same {prob.nx}x{prob.nz} grid, {el:.1f} s, 1 thread"}
 
 
@@ -339,9 +350,10 @@ def kernel_micro(torch, I, L, Context, reps, pins=None):
     return out
 
 
-def learned_small(torch, I, LRN, Context, train_iters):
-    """Trained network vs the physics preconditioner vs the untrained form on the
-    stable thermal at 256 x 128 (two steps each from the same state)."""
+def learned_small(torch, I, LRN, Context, train_iters, sweeps):
+    """Trained network vs the physics preconditioner (with the timed legs' sweep
+    count and with two sweeps) vs the untrained form on the stable thermal at
+    256 x 128 (two steps each from the same state)."""
     import numpy as np
     prob = I.thermal_stable_2d(256, 128)
     ctx = Context(prob, max_m=30)
@@ -352,12 +364,13 @@ def learned_small(torch, I, LRN, Context, train_iters):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0])}
-    for name, pc, params in [("physics", "physics", None), ("learned", "learned", theta),
-                             ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32))]:
+    for name, pc, params, sw in [("physics", "physics", None, sweeps), ("physics_sweeps2", "physics", None, 2),
+                                 ("learned", "learned", theta, 0),
+                                 ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32), 0)]:
         if params is not None:
             ctx.net_set_params(params)
         leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner="f32",
-                        eta_floor=1e-4, pc=pc)
+                        eta_floor=1e-4, pc=pc, sweeps=sw)
         out[name] = per_step(leg)
     return out
 
@@ -402,8 +415,8 @@ def main():
     shapes = pin_shapes(ctx, shapes, parse_shapes(args.pin))
     log(f"launch shapes (rows per workgroup): {shapes}")
     common = dict(rtol=1e-8, m=30, max_restarts=20)
-    opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics"),
-            "plain": dict(common, inner="f64", pc="physics"),
+    opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics", sweeps=args.pc_sweeps),
+            "plain": dict(common, inner="f64", pc="physics", sweeps=args.pc_sweeps),
             "learned": dict(common, inner="f32", eta_floor=1e-4, pc="learned")}
     steps = {"mixed": args.steps, "plain": args.plain_steps, "learned": args.learned_steps}
     classes = {"mixed": {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI},
@@ -419,6 +432,11 @@ def main():
     if "plain" in legs_wanted:
         log(f"timing {steps['plain']} plain FP64 steps")
         legs["plain"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["plain"], **opts["plain"])
+    if "sweeps2" in legs_wanted:
+        # the timed configuration with two Jacobi sweeps in the physics preconditioner
+        log(f"timing {steps['plain']} mixed steps with two preconditioner sweeps")
+        legs["mixed_pc_sweeps2"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["mixed"],
+                                             **dict(opts["mixed"], sweeps=2))
     train_info = None
     small = None
     if "learned" in legs_wanted:
@@ -437,7 +455,7 @@ def main():
         log(f"timing {steps['learned']} learned steps")
         legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
         log("learned vs physics preconditioner at 256 x 128")
-        small = learned_small(torch, I, LRN, Context, args.train_iters)
+        small = learned_small(torch, I, LRN, Context, args.train_iters, args.pc_sweeps)
     if "p3" in legs_wanted:
         # the same workload with the 9-point (p = 3) derivative
         prob3 = prob.replace(dd_p=3)
@@ -490,7 +508,9 @@ def main():
                 "bytes_per_launch": per, "avg_launch_us": ms / max(launches, 1) * 1e3, "launches": launches}
 
     kernels = {"arnoldi": "k_cgs_reg<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
-               "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner)",
+               "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner with two sweeps, "
+                     "mixed_pc_sweeps2 leg)" if "mixed_pc_sweeps2" in legs else
+                     f"k_pc_diag_2d<float> + {args.pc_sweeps} x k_pc_sweep_2d<float> (physics preconditioner)",
                "jv": f"{jv_kernel_name(shapes['f32_jv'])} (stable finite-difference Jv)"}
     traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_stable_1024x512",
                     "pc": "pc_f32_counters_thermal_stable_1024x512",
@@ -519,8 +539,10 @@ def main():
         "config": {
             "workload": f"stable 2D dry thermal {prob.nx}x{prob.nz} (20x10 km, N=0.01/s, +2 K bubble, "
                         f"dt={prob.dt} s, Smagorinsky), mixed-precision JFNK with the physics-based "
-                        f"preconditioner: FGMRES(30), Newton rtol 1e-8",
+                        f"preconditioner (field-block diagonal, {args.pc_sweeps} Jacobi sweeps): FGMRES(30), "
+                        f"Newton rtol 1e-8",
             "grid": [prob.nx, prob.nz],
+            "pc_sweeps": args.pc_sweeps,
             "timed_leg": "mixed",
             "legs": {k: per_step(v) for k, v in legs.items()},
             "plain_over_mixed_time": (per_step(legs["plain"])["ms_per_step"] / per_step(T)["ms_per_step"]
@@ -533,7 +555,8 @@ def main():
         },
         "roofline": roof("mixed", dominant, kernels[dominant], traffic=traffic_of(dominant)),
         "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=traffic_of("jv")),
-        "roofline_pc": roof("mixed", "pc", kernels["pc"], traffic=traffic_of("pc")),
+        "roofline_pc": roof("mixed_pc_sweeps2" if "mixed_pc_sweeps2" in legs else "mixed", "pc", kernels["pc"],
+                            traffic=traffic_of("pc")),
     }
     if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
         out["roofline_net"] = roof("learned", "net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)",
@@ -555,7 +578,7 @@ def main():
                                     "avg_launch_us": best["avg_launch_us"]}
     if not args.no_cpu:
         log(f"cpu baseline ({args.cpu_seconds} s)")
-        out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds, args.pc_sweeps)
     print(json.dumps(out), flush=True)
 
 
