@@ -172,6 +172,26 @@ def test_gmres_fixed_iterations_f64(pc, p):
     assert abs(r.res_est - io.res_est) <= 1e-9 * io.res_est
 
 
+def test_gmres_basis_beyond_32_vectors_f64():
+    """One cycle of 36 iterations: the Gram-Schmidt passes run with the basis in
+    registers up to 32 vectors (8-, 16- and 32-row forms) and staged in LDS
+    beyond; the Hessenberg matrix matches the oracle's CGS2 column by column."""
+    prob = I.thermal_stable_2d(96, 40)
+    U = _state(prob, 25)
+    b = I.random_vector(prob, seed=26)
+    mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
+    m = iters = 36
+    xo, io = K.fgmres(mv, lambda r: r, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
+    c = _ctx(prob, max_m=40)
+    x = dev(np.zeros(prob.shape))
+    r = c.gmres(dev(U), dev(b), x, m=40, max_restarts=1, tol=0.0, pc="none", max_iters=iters, want_H=True)
+    assert r.iters == iters and r.restarts == 0
+    assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
+    k = io.H.shape[1]
+    assert k == iters
+    assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
+
+
 def test_gmres_converges_and_estimate_is_true_residual():
     prob = I.thermal_neutral_2d(128, 64)
     U = _state(prob, 23)
