@@ -52,10 +52,22 @@ __device__ __forceinline__ double block_sum256(double v, double* red4) {
 __device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
 __device__ __forceinline__ int grid_blocks() { return gridDim.x * gridDim.y; }
 
-// Fixed-order sum of partials[b * stride + k] over b < nblk by one block.
+// Fixed-order sum of partials[b * stride + k] over b < nblk by one block.  Each
+// thread adds its partials b = tid, tid + 256, ... in ascending order; the
+// loads are issued eight at a time before the adds (one at a time, each
+// waits a full memory round trip, which is most of a finishing launch).
 __device__ __forceinline__ double sum_partials(const double* partials, int nblk, int stride, int k, double* red4) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) acc += partials[(long long)b * stride + k];
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * 256) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * 256;
+            x[u] = b < nblk ? partials[(long long)b * stride + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += x[u];
+    }
     return block_sum256(acc, red4);
 }
 

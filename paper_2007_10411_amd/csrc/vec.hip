@@ -52,9 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
                                                             int accumulate) {
     __shared__ double red[4];
     const int k = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partials[(long long)b * stride + k];
-    const double s = block_sum(acc, red);
+    const double s = sum_partials(partials, nblk, stride, k, red);
     if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
 }
 
