@@ -60,6 +60,17 @@ typedef enum { JFNK_PC_NONE = 0, JFNK_PC_PHYSICS = 1, JFNK_PC_LEARNED = 2 } jfnk
  *         literal quotient in exact arithmetic, no cancellation);
  * LITERAL: the quotient evaluated as written;  ANALYTIC: the eps -> 0 limit.   */
 typedef enum { JFNK_JV_STABLE = 0, JFNK_JV_LITERAL = 1, JFNK_JV_ANALYTIC = 2 } jfnk_jv_mode;
+/* Gram-Schmidt form of the Arnoldi step of jfnk_gmres (the GMRES of Saad and
+ * Schultz that section 2.5.1 relies on; the paper does not fix the form).
+ * CGS2: classical Gram-Schmidt applied twice, three passes over the basis and
+ *       three reductions per iteration.
+ * ONE_REDUCTION: the second projection and the normalization of each basis
+ *       vector are delayed to the next iteration, whose single reduction
+ *       provides them (two passes over the basis per iteration); a column of
+ *       the Hessenberg matrix is final one iteration later.  Equal to CGS2 in
+ *       exact arithmetic.  Used when m < 32 and the vectors hold fewer than
+ *       2^30 values; CGS2 otherwise.  The ensemble path always uses CGS2.     */
+typedef enum { JFNK_ORTHO_CGS2 = 0, JFNK_ORTHO_ONE_REDUCTION = 1 } jfnk_ortho;
 typedef enum {
     JFNK_CLOSURE_CONST_K = 0,
     JFNK_CLOSURE_SMAGORINSKY = 1,
@@ -116,6 +127,7 @@ typedef struct {
     int32_t jv;                /* jfnk_jv_mode                                           */
     int32_t sweeps;            /* physics preconditioner Jacobi sweeps (>= 0)            */
     int32_t max_iters;         /* hard cap on iterations (<= 0: m * max_restarts)        */
+    int32_t ortho;             /* jfnk_ortho: Gram-Schmidt form of the Arnoldi step      */
 } jfnk_gmres_opts;
 
 typedef struct {
@@ -188,7 +200,7 @@ int jfnk_precond_apply(jfnk_ctx* ctx, jfnk_pc_kind pc, jfnk_dtype dt, const void
                        const void* r, void* z, int32_t sweeps);
 
 /* Right-preconditioned flexible restarted GMRES(m) (Saad and Schultz) for
- * J(u) x = rhs with x0 = 0, classical Gram-Schmidt applied twice, Givens
+ * J(u) x = rhs with x0 = 0, the Arnoldi step of o->ortho (jfnk_ortho), Givens
  * rotations and back substitution in FP64.  x is output only.                    */
 int jfnk_gmres(jfnk_ctx* ctx, jfnk_dtype dt, const void* u, const void* rhs, void* x,
                const jfnk_gmres_opts* opts, jfnk_gmres_info* info);

@@ -16,6 +16,7 @@ JFNK_OK, JFNK_NOT_CONVERGED, JFNK_ERR_ARG, JFNK_ERR_HIP, JFNK_ERR_NONFINITE = 0,
 F64, F32 = 0, 1
 PC_NONE, PC_PHYSICS, PC_LEARNED = 0, 1, 2
 JV_STABLE, JV_LITERAL, JV_ANALYTIC = 0, 1, 2
+ORTHO_CGS2, ORTHO_ONE_REDUCTION = 0, 1
 NET_LOSS_SOLUTION, NET_LOSS_REST_JACOBIAN = 0, 1
 KC_JV, KC_RESIDUAL, KC_PC, KC_ARNOLDI, KC_VEC, KC_NET = range(6)
 
@@ -42,7 +43,7 @@ class Problem(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("max_restarts", C.c_int32), ("tol", C.c_double), ("pc", C.c_int32),
-                ("jv", C.c_int32), ("sweeps", C.c_int32), ("max_iters", C.c_int32)]
+                ("jv", C.c_int32), ("sweeps", C.c_int32), ("max_iters", C.c_int32), ("ortho", C.c_int32)]
 
 
 class GmresInfo(C.Structure):

@@ -27,8 +27,10 @@ constexpr int O_G = O_SN + M;
 constexpr int O_Y = O_G + M + 1;
 constexpr int O_H1 = O_Y + M;
 constexpr int O_H2 = O_H1 + M;
-constexpr int O_S = O_H2 + M;         // misc scalars
-enum { S_UNORM2 = 0, S_VNORM2, S_EPS, S_WNORM2, S_WNORM, S_RES, S_BETA2, S_BETA, S_TMP, S_SLOT0 = 10, S_COUNT = 16 };
+constexpr int O_R = O_H2 + M;         // one-reduction step: norms r_c of the basis vectors before normalization
+constexpr int O_CO = O_R + M;         //   and the update coefficients (a, e, 1/r, c_w)
+constexpr int O_S = O_CO + 2 * M + 2; // misc scalars
+enum { S_UNORM2 = 0, S_VNORM2, S_EPS, S_WNORM2, S_WNORM, S_RES, S_BETA2, S_BETA, S_TMP, S_SLOT0 = 10, S_COUNT = 18 };
 constexpr int kScal = O_S + S_COUNT;
 
 double* ds(jfnk_ctx* c, int off) { return c->dscal + off; }
@@ -356,7 +358,13 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
 }
 
 template <typename T>
+int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o,
+                        jfnk_gmres_info* info);
+
+template <typename T>
 int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o, jfnk_gmres_info* info) {
+    if (o.ortho == JFNK_ORTHO_ONE_REDUCTION && o.m < kDgMaxRows && c->n < (1LL << 30))
+        return gmres_one_reduction<T>(c, u, b, x, o, info);
     const long long n = c->n;
     const int m = o.m;
     const int max_iters = o.max_iters > 0 ? o.max_iters : m * o.max_restarts;
@@ -474,6 +482,151 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
         }
         ++restarts;
         // true residual r = b - J x
+        if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
+        if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
+        JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
+        if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+        JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
+        if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+        if (c->hscal[S_BETA] == 0.0) {
+            converged = true;
+            break;
+        }
+    }
+    if (info) {
+        info->iters = total;
+        info->restarts = restarts;
+        info->converged = converged ? 1 : 0;
+        info->res_est = res_est;
+        if (info->h_out) {
+            JFNK_HIP(hipMemcpyAsync(info->h_out, ds(c, O_HRAW), (size_t)(m + 1) * m * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+        }
+    }
+    JFNK_HIP(hipStreamSynchronize(s));
+    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
+// FGMRES(m) with the one-reduction Arnoldi step (three launches per iteration:
+// the reduction pass, its finishing block and the update pass).  Column c of
+// the Hessenberg matrix is final one iteration later (iteration c + 1 or, for
+// the last column of a cycle, a closing reduction over basis vector c + 1
+// alone).  Iterations run up to two ahead of the host's test; a speculative
+// iteration only writes columns, rotations and basis vectors past the ones the
+// back substitution reads.
+template <typename T>
+int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o,
+                        jfnk_gmres_info* info) {
+    const long long n = c->n;
+    const int m = o.m;
+    const int max_iters = o.max_iters > 0 ? o.max_iters : m * o.max_restarts;
+    T* V = Vb<T>(c);
+    T* Z = Zb<T>(c);
+    hipStream_t s = c->stream;
+    int rc;
+    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, u, NUb<T>(c)));
+    if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
+    JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
+    JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
+    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+    const double bnorm = c->hscal[S_BETA];
+    if (info) {
+        info->res0 = bnorm;
+        info->res_est = bnorm;
+        info->iters = 0;
+        info->restarts = 0;
+        info->converged = 0;
+    }
+    if (!std::isfinite(bnorm)) {
+        set_error("non-finite right-hand side norm");
+        return JFNK_ERR_NONFINITE;
+    }
+    if (bnorm == 0.0) {
+        if (info) info->converged = 1;
+        return JFNK_OK;
+    }
+    const EpsArgs ea = o.jv == JFNK_JV_ANALYTIC ? EpsArgs() : eps_args(c, eps_mach<T>());
+    DgArgs da;
+    da.H = ds(c, O_H);
+    da.Hraw = ds(c, O_HRAW);
+    da.cs = ds(c, O_CS);
+    da.sn = ds(c, O_SN);
+    da.g = ds(c, O_G);
+    da.h1 = ds(c, O_H1);
+    da.rs = ds(c, O_R);
+    da.coef = ds(c, O_CO);
+    da.m = m;
+    int total = 0, restarts = 0;
+    bool converged = false;
+    double res_est = bnorm;
+    auto slot_of = [](int op) { return op & 3; };
+    // iteration j: z_j = M q~_j, w = A z_j, the reduction (closes column j-1), the update
+    auto enqueue_iter = [&](int j) -> int {
+        T* Vj = V + (long long)j * n;
+        T* Vn = V + (long long)(j + 1) * n;
+        T* Zj = Z + (long long)j * n;
+        int r;
+        if ((r = apply_pc<T>(c, o.pc, u, Vj, nullptr, Zj, o.sweeps, Vn, ea))) return r;
+        if ((r = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return r;
+        if (std::is_same<T, float>::value && c->rec_count && *c->rec_count < c->rec_cap) {
+            const long long off = (long long)(*c->rec_count) * n;
+            JFNK_HIP(hipMemcpyAsync(c->rec_r + off, Vn, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+            JFNK_HIP(hipMemcpyAsync(c->rec_du + off, Zj, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+            ++*c->rec_count;
+        }
+        {
+            // the reduction pass reads V_0..V_{j+1}; the update pass reads them and writes two rows
+            TimedLaunch tl(c, KC_ARNOLDI, (2.0 * j + 6.0) * n * sizeof(T));
+            da.host = c->hscal + S_SLOT0 + 2 * slot_of(j);
+            JFNK_HIP(launch_dg_reduce<T>(V, n, j, true, c->partials, da, s));
+            JFNK_HIP(hipEventRecord(c->slot_ev[slot_of(j)], s));
+            JFNK_HIP(launch_dg_update<T>(V, n, j, da.coef, s));
+        }
+        return JFNK_OK;
+    };
+    // closing reduction over q~_k alone: column k-1 becomes final
+    auto enqueue_close = [&](int k) -> int {
+        TimedLaunch tl(c, KC_ARNOLDI, (k + 1.0) * n * sizeof(T));
+        da.host = c->hscal + S_SLOT0 + 2 * slot_of(k);
+        JFNK_HIP(launch_dg_reduce<T>(V, n, k, false, c->partials, da, s));
+        JFNK_HIP(hipEventRecord(c->slot_ev[slot_of(k)], s));
+        return JFNK_OK;
+    };
+    auto enqueue_op = [&](int op, int kmax) -> int { return op < kmax ? enqueue_iter(op) : enqueue_close(op); };
+    while (true) {
+        const int kmax = std::min(m, max_iters - total);    // columns of this cycle
+        int k = 0;
+        bool done = false;
+        if ((rc = enqueue_op(0, kmax))) return rc;
+        if ((rc = enqueue_op(1, kmax))) return rc;
+        for (int col = 0; col < kmax; ++col) {
+            if (col + 2 <= kmax && (rc = enqueue_op(col + 2, kmax))) return rc;
+            // column col is closed by op col + 1
+            const int slot = slot_of(col + 1);
+            JFNK_HIP(hipEventSynchronize(c->slot_ev[slot]));
+            const double rnext = c->hscal[S_SLOT0 + 2 * slot];
+            res_est = c->hscal[S_SLOT0 + 2 * slot + 1];
+            if (!std::isfinite(rnext) || !std::isfinite(res_est)) {
+                set_error("non-finite Krylov norm");
+                return JFNK_ERR_NONFINITE;
+            }
+            ++total;
+            k = col + 1;
+            if (res_est <= o.tol * bnorm || rnext == 0.0 || total >= max_iters) {
+                done = true;
+                break;
+            }
+        }
+        JFNK_HIP(launch_backsolve(ds(c, O_H), ds(c, O_G), k, m, ds(c, O_Y), s));
+        JFNK_HIP(launch_axpy_basis<T>(x, Z, n, k, ds(c, O_Y), s));
+        if (done) {
+            converged = res_est <= o.tol * bnorm;
+            break;
+        }
+        ++restarts;
+        // true residual r = b - J x, the next cycle's (unnormalized) start vector
         if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
         if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
         JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
@@ -717,7 +870,7 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
         // scalars straight to the host
         hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocCoherent);
         if (e != hipSuccess) return fail(e, "hipHostMalloc");
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 4; ++k) {
             e = hipEventCreateWithFlags(&c->slot_ev[k], hipEventDisableTiming);
             if (e != hipSuccess) return fail(e, "hipEventCreate");
         }
@@ -759,7 +912,7 @@ int jfnk_destroy(jfnk_ctx* c) {
             if (q) (void)hipFree(q);
     }
     if (c->hscal) (void)hipHostFree(c->hscal);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 4; ++k)
         if (c->slot_ev[k]) (void)hipEventDestroy(c->slot_ev[k]);
     for (int k = 0; k < KC_COUNT; ++k)
         for (auto e : c->timing.ev[k]) (void)hipEventDestroy(e);
@@ -846,6 +999,10 @@ static bool valid_gmres_opts(jfnk_ctx* c, const jfnk_gmres_opts* o) {
     }
     if (o->pc != JFNK_PC_NONE && o->pc != JFNK_PC_PHYSICS && o->pc != JFNK_PC_LEARNED) {
         set_error("unknown preconditioner kind");
+        return false;
+    }
+    if (o->ortho != JFNK_ORTHO_CGS2 && o->ortho != JFNK_ORTHO_ONE_REDUCTION) {
+        set_error("unknown orthogonalization");
         return false;
     }
     return true;

@@ -197,7 +197,7 @@ struct jfnk_ctx {
     double* epart = nullptr;    // per-block partials of the FD-step norm
     double* dscal = nullptr;    // device scalars (see solver)
     double* hscal = nullptr;    // pinned host mirror
-    hipEvent_t slot_ev[2] = {nullptr, nullptr};  // GMRES result slots in flight
+    hipEvent_t slot_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // GMRES result slots in flight
     jfnk::Timing timing;
     jfnk::NetBuffers net;
     int fallbacks = 0;
@@ -301,6 +301,31 @@ hipError_t launch_cgs(const T* V, long long n, int nv, const double* hin, T* w, 
 hipError_t launch_eps_finish(int nblk, const EpsArgs& ea, hipStream_t s);
 template <typename T>
 hipError_t launch_normalize_copy(T* v, long long n, const double* div, T* z, const EpsArgs& ea, hipStream_t s);
+// One-reduction Arnoldi step (classical Gram-Schmidt whose second projection
+// and normalization of each basis vector are delayed to the next iteration's
+// single reduction).  DgArgs points at the device state the finishing kernel
+// reads and updates; see vec.hip.
+struct DgArgs {
+    double* H = nullptr;        // rotated Hessenberg, row-major (m + 1) x m
+    double* Hraw = nullptr;     // unrotated, each column divided by its direction's scale
+    double* cs = nullptr;
+    double* sn = nullptr;
+    double* g = nullptr;
+    double* h1 = nullptr;       // first-projection coefficients of the newest column
+    double* rs = nullptr;       // r_c, the norm of basis vector c before normalization
+    double* coef = nullptr;     // update coefficients: a[kMaxDots], e[kMaxDots], 1/r, c_w
+    double* host = nullptr;     // pinned (r_j, |g_j|) for the host's test
+    int m = 0;
+};
+// Reduction of iteration j (with_w) or of the closing step of a cycle (!with_w,
+// basis vector j alone): the pass over V and the finishing block.
+template <typename T>
+hipError_t launch_dg_reduce(const T* V, long long n, int j, bool with_w, double* partials, const DgArgs& a,
+                            hipStream_t s);
+// Update pass of iteration j: rows j and j + 1 of V become q_j and q~_{j+1}.
+template <typename T>
+hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s);
+constexpr int kDgMaxRows = 32;          // basis vectors the one-reduction step handles
 hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s);
 hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m, hipStream_t s);
 

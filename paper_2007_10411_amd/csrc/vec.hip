@@ -451,6 +451,215 @@ __global__ __launch_bounds__(kBlock) void k_cgs_finish(const double* __restrict_
     for (int i = threadIdx.x; i <= j + 1; i += kBlock) ga.H[i * m + j] = col[i];
 }
 
+// ---------------------------------------------------------------------------
+// One-reduction Arnoldi step: classical Gram-Schmidt whose second projection
+// and normalization of each basis vector are delayed to the next iteration's
+// single reduction (the low-synchronization Gram-Schmidt of Swirydowicz et al.
+// 2021 and Bielich et al. 2022).  At iteration j, row j of V holds q~_j (basis
+// vector j after one projection, not normalized) and row j + 1 holds w = A z_j,
+// z_j the preconditioned q~_j.  One pass forms per block
+//     s_v = V_v . q~_j,  y_v = V_v . w  (v < j),  alpha = q~_j . q~_j,  beta = q~_j . w;
+// one block adds them up and forms
+//     r_j = sqrt(alpha - s.s)          norm of q~_j projected once more,
+//     column j-1 = its first projection + s, subdiagonal r_j (final: Givens step),
+//     h_j = (y, (beta - s.y) / r_j)    the first projection of w on q_0 .. q_j;
+// a second pass overwrites row j with q_j = (q~_j - V_{<j} s) / r_j and row
+// j + 1 with q~_{j+1} = (w - V_{<j} y - q_j h_jj) / r_j.  Without w (closing a
+// cycle) only s and alpha are formed and column j-1 is finished.  z_j carries
+// the scale r_j of q~_j; the Hessenberg columns keep it (the Arnoldi relation
+// A Z = V H holds for the stored Z): column j-1 = (its first projection
+// + r_{j-1} s, r_{j-1} r_j), the returned raw columns are divided by it.  The
+// division of q~_{j+1} by r_j keeps the scales from compounding over a cycle
+// (they would grow like the product of the subdiagonal, past the FP32 range
+// of the products inside the Jacobian-vector step).
+// ---------------------------------------------------------------------------
+constexpr int kDgBlocks = 256;          // blocks of the reduction pass
+constexpr int kDgSlots = 2 * kDgMaxRows + 2;
+enum { DG_S = 0, DG_Y = kDgMaxRows, DG_ALPHA = 2 * kDgMaxRows, DG_BETA = 2 * kDgMaxRows + 1 };
+constexpr int kDgCoefW = kMaxDots;      // coef layout: a[0..), e[kDgCoefW..), 1/r, c_w at 2 kDgCoefW
+
+template <typename T, int NV, bool W, int NT>
+__global__ __launch_bounds__(NT) void k_dg_dot(const T* __restrict__ V, int n, int j, double* __restrict__ partials) {
+    constexpr int NA = W ? 2 * NV : NV;       // row dots per thread: s, then y
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW][NA + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const T* q = V + (long long)j * n;
+    const T* w = V + (long long)(j + 1) * n;
+    const int last = j > 0 ? j - 1 : 0;        // rows past j - 1 re-read row j - 1 (row 0 when j = 0)
+    double acc[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) acc[v] = 0.0;
+    double aa = 0.0, ab = 0.0;
+    const int step = gridDim.x * NT;
+    for (int i = blockIdx.x * NT + tid; i < n; i += step) {
+        const T qv = q[i];
+        const T wv = W ? w[i] : T(0);
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < j ? v : last) * n + i];
+        __builtin_amdgcn_sched_barrier(0);    // all loads of the element ahead of its arithmetic
+        const double qd = (double)qv, wd = (double)wv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc[v] += (double)x[v] * qd;
+            if (W) acc[NV + v] += (double)x[v] * wd;
+        }
+        aa += qd * qd;
+        if (W) ab += qd * wd;
+    }
+    constexpr int kSpan = 64 / NA;
+    const double t = wave_sum_scatter<NA>(acc, lane);
+    if (lane % kSpan == 0) red[wid][lane / kSpan] = t;
+    const double ta = wave_sum64(aa);
+    const double tb = W ? wave_sum64(ab) : 0.0;
+    if (lane == 0) {
+        red[wid][NA] = ta;
+        red[wid][NA + 1] = tb;
+    }
+    __syncthreads();
+    for (int o = tid; o < NA + 2; o += NT) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) sum += red[k][o];
+        int slot = -1;
+        if (o < NV) {
+            if (o < j) slot = DG_S + o;
+        } else if (o < NA) {
+            if (o - NV < j) slot = DG_Y + (o - NV);
+        } else if (o == NA) {
+            slot = DG_ALPHA;
+        } else if (W) {
+            slot = DG_BETA;
+        }
+        if (slot >= 0) partials[(long long)slot * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
+// One block of 1024 threads: the sums of the pass, then (thread 0, FP64) the
+// closing of column j-1 with its Givens step, and the coefficients of the
+// update pass.
+__global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ partials, int nb, int j, int with_w,
+                                                    DgArgs a) {
+    __shared__ double sums[kDgSlots];
+    __shared__ double hp[kMaxDots + 1], scs[kMaxDots], ssn[kMaxDots];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int o = wid; o < kDgSlots; o += 16) {          // one output per wavefront at a time
+        const bool need = o < DG_Y ? o < j : o < DG_ALPHA ? (with_w && o - DG_Y < j) : (o == DG_ALPHA || with_w);
+        if (!need) continue;
+        double acc = 0.0;
+        for (int b0 = lane; b0 < nb; b0 += 8 * 64) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u * 64;
+                x[u] = b < nb ? partials[(long long)o * nb + b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += x[u];
+        }
+        acc = wave_sum64(acc);
+        if (lane == 0) sums[o] = acc;
+    }
+    for (int i = tid; i < j; i += 1024) {
+        hp[i] = a.h1[i];                                 // first projection of column j-1
+        scs[i] = a.cs[i];
+        ssn[i] = a.sn[i];
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const int m = a.m;
+    double ss = 0.0;
+    for (int v = 0; v < j; ++v) ss += sums[DG_S + v] * sums[DG_S + v];
+    const double r2 = sums[DG_ALPHA] - ss;
+    const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+    double res = 0.0;
+    if (j == 0) {
+        a.g[0] = r;                                      // the start vector is r q_0
+    } else {
+        const int c = j - 1;
+        const double sc = a.rs[c];
+        const double inv_sc = sc > 0.0 ? 1.0 / sc : 0.0;
+        double* col = hp;
+        for (int i = 0; i < j; ++i) col[i] += sc * sums[DG_S + i];
+        col[j] = sc * r;
+        for (int i = 0; i <= j; ++i) a.Hraw[i * m + c] = col[i] * inv_sc;
+        for (int i = 0; i < c; ++i) {
+            const double x = col[i], y = col[i + 1];
+            col[i] = scs[i] * x + ssn[i] * y;
+            col[i + 1] = -ssn[i] * x + scs[i] * y;
+        }
+        const double x = col[c], y = col[c + 1];
+        const double rr = hypot(x, y);
+        double cc = 1.0, sn = 0.0;
+        if (rr > 0.0) {
+            cc = x / rr;
+            sn = y / rr;
+        }
+        a.cs[c] = cc;
+        a.sn[c] = sn;
+        col[c] = rr;
+        col[c + 1] = 0.0;
+        const double gc = a.g[c];
+        a.g[c + 1] = -sn * gc;
+        a.g[c] = cc * gc;
+        res = fabs(sn * gc);
+        for (int i = 0; i <= j; ++i) a.H[i * m + c] = col[i];
+    }
+    a.rs[j] = r;
+    if (with_w) {
+        double sy = 0.0;
+        for (int v = 0; v < j; ++v) sy += sums[DG_S + v] * sums[DG_Y + v];
+        const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
+        const double hjj = (sums[DG_BETA] - sy) * inv_r;
+        const double cw = hjj * inv_r;
+        for (int v = 0; v < j; ++v) {
+            a.h1[v] = sums[DG_Y + v];
+            a.coef[v] = sums[DG_S + v];
+            a.coef[kDgCoefW + v] = sums[DG_Y + v] - cw * sums[DG_S + v];
+        }
+        a.h1[j] = hjj;
+        a.coef[2 * kDgCoefW] = inv_r;
+        a.coef[2 * kDgCoefW + 1] = cw;
+    }
+    if (a.host) {
+        a.host[0] = r;
+        a.host[1] = res;
+    }
+}
+
+// q_j = (q~_j - sum_v a_v V_v) / r_j over row j, and over row j + 1
+// (w - c_w q~_j - sum_v e_v V_v) / r_j  (e_v = y_v - c_w a_v, c_w = h_jj / r_j).
+template <typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const double* __restrict__ coef) {
+    T* q = V + (long long)j * n;
+    T* w = V + (long long)(j + 1) * n;
+    const int last = j > 0 ? j - 1 : 0;
+    double ca[NV], ce[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ca[v] = v < j ? coef[v] : 0.0;
+        ce[v] = v < j ? coef[kDgCoefW + v] : 0.0;
+    }
+    const double inv_r = coef[2 * kDgCoefW], cw = coef[2 * kDgCoefW + 1];
+    const int step = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
+        const T qv = q[i], wv = w[i];
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < j ? v : last) * n + i];
+        __builtin_amdgcn_sched_barrier(0);
+        double sq = (double)qv, sw = (double)wv - cw * (double)qv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            sq -= ca[v] * (double)x[v];
+            sw -= ce[v] * (double)x[v];
+        }
+        q[i] = (T)(sq * inv_r);
+        w[i] = (T)(sw * inv_r);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_eps_finish(int nblk, EpsArgs ea) {
     __shared__ double red[4];
     const double t = sum_partials(ea.partials, nblk, 1, 0, red);
@@ -619,6 +828,51 @@ hipError_t launch_cgs(const T* V, long long n, int nv, const double* hin, T* w, 
     return hipGetLastError();
 }
 
+template <typename T, int NV, bool W, int NT>
+hipError_t launch_dg_dot_nv(const T* V, int n, int j, double* partials, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_dg_dot<T, NV, W, NT>), dim3(nb), dim3(NT), 0, s, V, n, j, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dg_reduce(const T* V, long long n, int j, bool with_w, double* partials, const DgArgs& a,
+                            hipStream_t s) {
+    if (j < 0 || j >= kDgMaxRows || n < 1 || n >= (1LL << 30)) return hipErrorInvalidValue;
+    // threads per block: 1024 while the dots fit 128 registers; 512 for 32 rows
+    // with w, or 32 FP64 rows
+    const int nt = (j > 16 && (with_w || sizeof(T) == 8)) ? 512 : 1024;
+    long long nb = (n + nt - 1) / nt;
+    if (nb > kDgBlocks) nb = kDgBlocks;
+    const int ni = (int)n, b = (int)nb;
+    hipError_t e;
+    if (with_w) {
+        e = j <= 8 ? launch_dg_dot_nv<T, 8, true, 1024>(V, ni, j, partials, b, s)
+          : j <= 16 ? launch_dg_dot_nv<T, 16, true, 1024>(V, ni, j, partials, b, s)
+                    : launch_dg_dot_nv<T, 32, true, 512>(V, ni, j, partials, b, s);
+    } else {
+        constexpr int kNt32 = sizeof(T) == 8 ? 512 : 1024;
+        e = j <= 8 ? launch_dg_dot_nv<T, 8, false, 1024>(V, ni, j, partials, b, s)
+          : j <= 16 ? launch_dg_dot_nv<T, 16, false, 1024>(V, ni, j, partials, b, s)
+                    : launch_dg_dot_nv<T, 32, false, kNt32>(V, ni, j, partials, b, s);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dg_finish, dim3(1), dim3(1024), 0, s, (const double*)partials, b, j, with_w ? 1 : 0, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s) {
+    if (j < 0 || j >= kDgMaxRows || n < 1 || n >= (1LL << 30)) return hipErrorInvalidValue;
+    const int nb = cgs_blocks(n), ni = (int)n;
+    if (j <= 8)
+        hipLaunchKernelGGL((k_dg_update<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+    else if (j <= 16)
+        hipLaunchKernelGGL((k_dg_update<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+    else
+        hipLaunchKernelGGL((k_dg_update<T, 32>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+    return hipGetLastError();
+}
+
 hipError_t launch_eps_finish(int nblk, const EpsArgs& ea, hipStream_t s) {
     hipLaunchKernelGGL(k_eps_finish, dim3(1), dim3(kBlock), 0, s, nblk, ea);
     return hipGetLastError();
@@ -655,7 +909,9 @@ hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m,
     template hipError_t launch_lincomb<T>(T*, const T*, const T*, long long, double, double, hipStream_t); \
     template hipError_t launch_cgs<T>(const T*, long long, int, const double*, T*, double*, double*, int,      \
                                       const GivensArgs&, hipStream_t);                                         \
-    template hipError_t launch_normalize_copy<T>(T*, long long, const double*, T*, const EpsArgs&, hipStream_t);
+    template hipError_t launch_normalize_copy<T>(T*, long long, const double*, T*, const EpsArgs&, hipStream_t); \
+    template hipError_t launch_dg_reduce<T>(const T*, long long, int, bool, double*, const DgArgs&, hipStream_t); \
+    template hipError_t launch_dg_update<T>(T*, long long, int, const double*, hipStream_t);
 JFNK_VINST(double)
 JFNK_VINST(float)
 #undef JFNK_VINST

@@ -16,6 +16,7 @@ from . import _lib as L
 DTYPES = {"f64": L.F64, "f32": L.F32}
 PCS = {"none": L.PC_NONE, "physics": L.PC_PHYSICS, "learned": L.PC_LEARNED}
 JVS = {"stable": L.JV_STABLE, "literal": L.JV_LITERAL, "analytic": L.JV_ANALYTIC}
+ORTHO = {"cgs2": L.ORTHO_CGS2, "one_reduction": L.ORTHO_ONE_REDUCTION}
 
 
 def _torch():
@@ -123,10 +124,10 @@ class Context:
         return z
 
     def gmres(self, u, b, x, m=30, max_restarts=20, tol=1e-6, pc="physics", jv="stable", sweeps=2,
-              max_iters=0, want_H=False):
+              max_iters=0, want_H=False, ortho="cgs2"):
         self._check_size(u, b, x)
         o = L.GmresOpts(m=m, max_restarts=max_restarts, tol=tol, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
-                        max_iters=max_iters)
+                        max_iters=max_iters, ortho=ORTHO[ortho])
         info = L.GmresInfo()
         Hbuf = None
         if want_H:
@@ -139,13 +140,13 @@ class Context:
 
     def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, inner="f64",
                     m=30, max_restarts=20, pc="physics", jv="stable", sweeps=2, forcing="ew", eta=1e-2,
-                    eta_floor=0.0, record=None, record_krylov=False):
+                    eta_floor=0.0, record=None, record_krylov=False, ortho="cgs2"):
         """record: optional (R, DU, count) with R, DU float32 device tensors of
         shape (cap, n) receiving the Newton linear systems; count is a one-element
-        list updated in place."""
+        list updated in place.  ortho: "cgs2" or "one_reduction" (jfnk_ortho)."""
         self._check_size(u_n, u_np1)
         gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
-                         max_iters=0)
+                         max_iters=0, ortho=ORTHO[ortho])
         o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=DTYPES[inner],
                          gm=gm, forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
         cnt = C.c_int32(0)

@@ -148,9 +148,10 @@ def test_physics_pc(name, sweeps):
     assert_fields_close(host(z32), ref32, F32_TOL, f"{name} pc{sweeps} f32")
 
 
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
 @pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("pc", ["physics", "none"])
-def test_gmres_fixed_iterations_f64(pc, p):
+def test_gmres_fixed_iterations_f64(pc, p, ortho):
     prob = I.thermal_stable_2d(96, 40).replace(dd_p=p)
     U = _state(prob, 21)
     b = I.random_vector(prob, seed=22)
@@ -164,12 +165,36 @@ def test_gmres_fixed_iterations_f64(pc, p):
     xo, io = K.fgmres(mv, pcf, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
     c = _ctx(prob, max_m=m)
     x = dev(np.zeros(prob.shape))
-    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=10, tol=0.0, pc=pc, max_iters=iters, want_H=True)
+    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=10, tol=0.0, pc=pc, max_iters=iters, want_H=True,
+                ortho=ortho)
     assert r.iters == iters and r.restarts == io.restarts
     assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
     k = io.H.shape[1]
     assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
     assert abs(r.res_est - io.res_est) <= 1e-9 * io.res_est
+
+
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
+def test_gmres_full_cycle_of_30_f64(ortho):
+    """One full cycle of m = 30: every register form of the Gram-Schmidt passes
+    (up to 31 basis vectors) and the closing reduction against the oracle's CGS2."""
+    prob = I.thermal_stable_2d(96, 40)
+    U = _state(prob, 27)
+    b = I.random_vector(prob, seed=28)
+    mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
+    fr = PC.frozen_coefficients(prob, U)
+    pcf = lambda r: PC.physics_pc(prob, U, r, 2, fr)
+    m = iters = 30
+    xo, io = K.fgmres(mv, pcf, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
+    c = _ctx(prob, max_m=m)
+    x = dev(np.zeros(prob.shape))
+    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=5, tol=0.0, pc="physics", max_iters=iters, want_H=True,
+                ortho=ortho)
+    assert r.iters == iters and r.restarts == io.restarts == 0
+    assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
+    k = io.H.shape[1]
+    assert k == iters
+    assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
 
 
 def test_gmres_basis_beyond_32_vectors_f64():
@@ -192,20 +217,22 @@ def test_gmres_basis_beyond_32_vectors_f64():
     assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
 
 
-def test_gmres_converges_and_estimate_is_true_residual():
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
+def test_gmres_converges_and_estimate_is_true_residual(ortho):
     prob = I.thermal_neutral_2d(128, 64)
     U = _state(prob, 23)
     b = I.random_vector(prob, seed=24)
     c = _ctx(prob)
     x = dev(np.zeros(prob.shape))
-    r = c.gmres(dev(U), dev(b), x, m=30, max_restarts=20, tol=1e-8, pc="physics")
+    r = c.gmres(dev(U), dev(b), x, m=30, max_restarts=20, tol=1e-8, pc="physics", ortho=ortho)
     assert r.converged
     true = np.linalg.norm(M.jv(prob, U, host(x), M.fd_eps(prob, U, host(x))) - b)
     assert true <= 2e-8 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
 @pytest.mark.parametrize("p", [2, 3])
-def test_newton_step_f64_matches_oracle(p):
+def test_newton_step_f64_matches_oracle(p, ortho):
     prob = I.thermal_neutral_2d(128, 64).replace(dd_p=p)
     U0 = I.bubble_state(prob)
     ref, info = K.newton_step(prob, U0, K.NewtonOpts(rtol=1e-13))
@@ -213,12 +240,13 @@ def test_newton_step_f64_matches_oracle(p):
     c = _ctx(prob)
     un = dev(U0)
     u = un.clone()
-    r = c.newton_step(un, u, rtol=1e-13)
+    r = c.newton_step(un, u, rtol=1e-13, ortho=ortho)
     assert r.converged
     assert_fields_close(host(u), ref, F64_TOL, "newton f64")
 
 
-def test_newton_mixed_precision_error_vs_fp64_oracle():
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
+def test_newton_mixed_precision_error_vs_fp64_oracle(ortho):
     """FP32 Krylov/Jv inside the FP64 Newton: converges to the same 1e-8
     tolerance; the per-field error against the FP64 oracle solution is reported
     and stays within what the tolerance allows."""
@@ -228,7 +256,7 @@ def test_newton_mixed_precision_error_vs_fp64_oracle():
     c = _ctx(prob)
     un = dev(U0)
     u = un.clone()
-    r = c.newton_step(un, u, rtol=1e-8, inner="f32", eta_floor=1e-4)
+    r = c.newton_step(un, u, rtol=1e-8, inner="f32", eta_floor=1e-4, ortho=ortho)
     assert r.converged and r.res_final <= 1e-8 * r.res0
     errs = field_errors(host(u), ref)
     step = np.array([np.linalg.norm((ref[k] - U0[k]).ravel()) for k in range(prob.nf)])
