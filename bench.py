@@ -10,11 +10,16 @@ diagonal with --pc-sweeps Jacobi sweeps (default 0): on this workload the GMRES
 iteration count is the same for 0 to 8 sweeps (the acoustic coupling between
 fields, which no field block holds, sets it), so each sweep only adds time.
 
+The Krylov solve of the timed legs uses the one-reduction Arnoldi step
+(--ortho, jfnk_ortho): two passes over the basis per iteration instead of the
+three of classical Gram-Schmidt applied twice, equal to it in exact arithmetic.
+
 Legs, all from the same state after the warm-up steps:
   mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton   (timed leg)
   plain     FP64 everywhere, physics-based preconditioner
   mixed_pc_sweeps2  the mixed leg with two preconditioner sweeps (the source of
             roofline_pc, whose kernels the timed legs launch without sweeps)
+  mixed_cgs2  the mixed leg with the CGS2 Arnoldi step
   learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
             the network is trained first on pairs the solver generates on this
             workload (training time reported, not timed with the steps)
@@ -78,7 +83,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,sweeps2,learned,p3,deardorff,3d")
+    ap.add_argument("--legs", default="mixed,plain,sweeps2,cgs2,learned,p3,deardorff,3d")
+    ap.add_argument("--ortho", default="one_reduction", choices=["one_reduction", "cgs2"],
+                    help="Gram-Schmidt form of the Arnoldi step in the timed legs (the cgs2 leg repeats the timed "
+                         "configuration with CGS2)")
     ap.add_argument("--pc-sweeps", type=int, default=0,
                     help="Jacobi sweeps of the physics preconditioner in the timed legs (0: its field-block "
                          "diagonal alone; the sweeps2 leg repeats the timed configuration with 2)")
@@ -350,7 +358,7 @@ def kernel_micro(torch, I, L, Context, reps, pins=None):
     return out
 
 
-def learned_small(torch, I, LRN, Context, train_iters, sweeps):
+def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
     """Trained network vs the physics preconditioner (with the timed legs' sweep
     count and with two sweeps) vs the untrained form on the stable thermal at
     256 x 128 (two steps each from the same state)."""
@@ -370,7 +378,7 @@ def learned_small(torch, I, LRN, Context, train_iters, sweeps):
         if params is not None:
             ctx.net_set_params(params)
         leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner="f32",
-                        eta_floor=1e-4, pc=pc, sweeps=sw)
+                        eta_floor=1e-4, pc=pc, sweeps=sw, ortho=ortho)
         out[name] = per_step(leg)
     return out
 
@@ -414,7 +422,7 @@ def main():
     shapes = ctx.tune()                 # launch shapes of the stencil stages (setup, untimed)
     shapes = pin_shapes(ctx, shapes, parse_shapes(args.pin))
     log(f"launch shapes (rows per workgroup): {shapes}")
-    common = dict(rtol=1e-8, m=30, max_restarts=20)
+    common = dict(rtol=1e-8, m=30, max_restarts=20, ortho=args.ortho)
     opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics", sweeps=args.pc_sweeps),
             "plain": dict(common, inner="f64", pc="physics", sweeps=args.pc_sweeps),
             "learned": dict(common, inner="f32", eta_floor=1e-4, pc="learned")}
@@ -437,6 +445,11 @@ def main():
         log(f"timing {steps['plain']} mixed steps with two preconditioner sweeps")
         legs["mixed_pc_sweeps2"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["mixed"],
                                              **dict(opts["mixed"], sweeps=2))
+    if "cgs2" in legs_wanted and args.ortho != "cgs2":
+        # the timed configuration with classical Gram-Schmidt applied twice
+        log(f"timing {steps['plain']} mixed steps with the CGS2 Arnoldi step")
+        legs["mixed_cgs2"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["mixed"],
+                                       **dict(opts["mixed"], ortho="cgs2"))
     train_info = None
     small = None
     if "learned" in legs_wanted:
@@ -455,7 +468,7 @@ def main():
         log(f"timing {steps['learned']} learned steps")
         legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
         log("learned vs physics preconditioner at 256 x 128")
-        small = learned_small(torch, I, LRN, Context, args.train_iters, args.pc_sweeps)
+        small = learned_small(torch, I, LRN, Context, args.train_iters, args.pc_sweeps, args.ortho)
     if "p3" in legs_wanted:
         # the same workload with the 9-point (p = 3) derivative
         prob3 = prob.replace(dd_p=3)
@@ -507,12 +520,16 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_launch": per, "avg_launch_us": ms / max(launches, 1) * 1e3, "launches": launches}
 
-    kernels = {"arnoldi": "k_cgs_reg<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES iteration)",
+    kernels = {"arnoldi": ("k_dg_dot<float> + k_dg_finish + k_dg_update<float> (one-reduction Arnoldi step and "
+                           "Givens step of one GMRES iteration)" if args.ortho == "one_reduction" else
+                           "k_cgs_reg<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES "
+                           "iteration)"),
                "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner with two sweeps, "
                      "mixed_pc_sweeps2 leg)" if "mixed_pc_sweeps2" in legs else
                      f"k_pc_diag_2d<float> + {args.pc_sweeps} x k_pc_sweep_2d<float> (physics preconditioner)",
                "jv": f"{jv_kernel_name(shapes['f32_jv'])} (stable finite-difference Jv)"}
-    traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_stable_1024x512",
+    traffic_name = {"arnoldi": ("arnoldi_f32_counters_thermal_stable_1024x512" if args.ortho == "one_reduction"
+                                else "arnoldi_cgs2_f32_counters_thermal_stable_1024x512"),
                     "pc": "pc_f32_counters_thermal_stable_1024x512",
                     "jv": "jv_f32_counters_thermal_stable_1024x512"}
     dominant = max(kernels, key=lambda k: tm[k][0])
@@ -539,10 +556,11 @@ def main():
         "config": {
             "workload": f"stable 2D dry thermal {prob.nx}x{prob.nz} (20x10 km, N=0.01/s, +2 K bubble, "
                         f"dt={prob.dt} s, Smagorinsky), mixed-precision JFNK with the physics-based "
-                        f"preconditioner (field-block diagonal, {args.pc_sweeps} Jacobi sweeps): FGMRES(30), "
-                        f"Newton rtol 1e-8",
+                        f"preconditioner (field-block diagonal, {args.pc_sweeps} Jacobi sweeps): FGMRES(30) "
+                        f"with the {args.ortho} Arnoldi step, Newton rtol 1e-8",
             "grid": [prob.nx, prob.nz],
             "pc_sweeps": args.pc_sweeps,
+            "ortho": args.ortho,
             "timed_leg": "mixed",
             "legs": {k: per_step(v) for k, v in legs.items()},
             "plain_over_mixed_time": (per_step(legs["plain"])["ms_per_step"] / per_step(T)["ms_per_step"]
