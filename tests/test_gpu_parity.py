@@ -377,3 +377,10 @@ def test_invalid_gmres_options_are_rejected():
     with pytest.raises(L.JfnkError) as e:
         c.gmres(z, z, z.clone(), m=11)
     assert e.value.code == L.JFNK_ERR_ARG
+    # an unknown Gram-Schmidt form
+    import ctypes as C
+    o = L.GmresOpts(m=4, max_restarts=2, tol=1e-6, pc=L.PC_NONE, jv=L.JV_STABLE, sweeps=0, max_iters=0, ortho=7)
+    info = L.GmresInfo()
+    code = c.lib.jfnk_gmres(c.h, L.F64, C.c_void_p(z.data_ptr()), C.c_void_p(z.data_ptr()),
+                            C.c_void_p(z.clone().data_ptr()), C.byref(o), C.byref(info))
+    assert code == L.JFNK_ERR_ARG
