@@ -536,13 +536,13 @@ __global__ __launch_bounds__(NT) void k_dg_dot(const T* __restrict__ V, int n, i
     }
 }
 
-// One block of 1024 threads: the sums of the pass, then (thread 0, FP64) the
-// closing of column j-1 with its Givens step, and the coefficients of the
-// update pass.
+// One block of 1024 threads: the sums of the pass; then wavefront 0, one lane
+// per basis vector, the closed column j-1 and the coefficients of the update
+// pass; then thread 0 the Givens step of column j-1 (FP64 throughout).
 __global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ partials, int nb, int j, int with_w,
                                                     DgArgs a) {
     __shared__ double sums[kDgSlots];
-    __shared__ double hp[kMaxDots + 1], scs[kMaxDots], ssn[kMaxDots];
+    __shared__ double hp[kMaxDots + 1], scs[kMaxDots], ssn[kMaxDots], pre[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int o = wid; o < kDgSlots; o += 16) {          // one output per wavefront at a time
         const bool need = o < DG_Y ? o < j : o < DG_ALPHA ? (with_w && o - DG_Y < j) : (o == DG_ALPHA || with_w);
@@ -566,62 +566,86 @@ __global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ p
         scs[i] = a.cs[i];
         ssn[i] = a.sn[i];
     }
+    if (tid == 1023 && j > 0) {                          // the scale of z_{j-1} and g_{j-1}
+        pre[0] = a.rs[j - 1];
+        pre[1] = a.g[j - 1];
+    }
     __syncthreads();
-    if (tid != 0) return;
     const int m = a.m;
-    double ss = 0.0;
-    for (int v = 0; v < j; ++v) ss += sums[DG_S + v] * sums[DG_S + v];
-    const double r2 = sums[DG_ALPHA] - ss;
-    const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+    // wavefront 0, one lane per basis vector (j < 32): s.s and s.y, the closed
+    // column j-1 before its rotations, and the update coefficients
+    if (wid == 0) {
+        const double sv = lane < j ? sums[DG_S + lane] : 0.0;
+        const double yv = (with_w && lane < j) ? sums[DG_Y + lane] : 0.0;
+        double ss = sv * sv, sy = sv * yv;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {               // butterfly: the same sums in every lane
+            ss += __shfl_xor(ss, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+        }
+        const double r2 = sums[DG_ALPHA] - ss;
+        const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+        if (j > 0) {
+            const double sc = pre[0];
+            const double inv_sc = sc > 0.0 ? 1.0 / sc : 0.0;
+            double h = 0.0;
+            if (lane < j) h = hp[lane] + sc * sv;
+            else if (lane == j) h = sc * r;
+            if (lane <= j) {
+                hp[lane] = h;
+                a.Hraw[lane * m + (j - 1)] = h * inv_sc;
+            }
+        }
+        if (with_w) {
+            const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
+            const double hjj = (sums[DG_BETA] - sy) * inv_r;
+            const double cw = hjj * inv_r;
+            if (lane < j) {
+                a.coef[lane] = sv;
+                a.coef[kDgCoefW + lane] = yv - cw * sv;
+            }
+            if (lane == 0) {
+                a.coef[2 * kDgCoefW] = inv_r;
+                a.coef[2 * kDgCoefW + 1] = cw;
+                pre[2] = hjj;
+            }
+        }
+        if (lane == 0) pre[3] = r;
+    }
+    __syncthreads();
+    if (with_w && tid < j) a.h1[tid] = sums[DG_Y + tid];   // after every read of the old h1
+    if (tid != 0) return;
+    const double r = pre[3];
     double res = 0.0;
     if (j == 0) {
         a.g[0] = r;                                      // the start vector is r q_0
     } else {
+        // Givens rotations of column c = j-1, the rotated value carried in a register
         const int c = j - 1;
-        const double sc = a.rs[c];
-        const double inv_sc = sc > 0.0 ? 1.0 / sc : 0.0;
-        double* col = hp;
-        for (int i = 0; i < j; ++i) col[i] += sc * sums[DG_S + i];
-        col[j] = sc * r;
-        for (int i = 0; i <= j; ++i) a.Hraw[i * m + c] = col[i] * inv_sc;
+        double y = hp[0];
         for (int i = 0; i < c; ++i) {
-            const double x = col[i], y = col[i + 1];
-            col[i] = scs[i] * x + ssn[i] * y;
-            col[i + 1] = -ssn[i] * x + scs[i] * y;
+            const double z = hp[i + 1];
+            a.H[i * m + c] = scs[i] * y + ssn[i] * z;
+            y = -ssn[i] * y + scs[i] * z;
         }
-        const double x = col[c], y = col[c + 1];
-        const double rr = hypot(x, y);
+        const double z = hp[c + 1];
+        const double rr = hypot(y, z);
         double cc = 1.0, sn = 0.0;
         if (rr > 0.0) {
-            cc = x / rr;
-            sn = y / rr;
+            cc = y / rr;
+            sn = z / rr;
         }
         a.cs[c] = cc;
         a.sn[c] = sn;
-        col[c] = rr;
-        col[c + 1] = 0.0;
-        const double gc = a.g[c];
+        a.H[c * m + c] = rr;
+        a.H[(c + 1) * m + c] = 0.0;
+        const double gc = pre[1];
         a.g[c + 1] = -sn * gc;
         a.g[c] = cc * gc;
         res = fabs(sn * gc);
-        for (int i = 0; i <= j; ++i) a.H[i * m + c] = col[i];
     }
     a.rs[j] = r;
-    if (with_w) {
-        double sy = 0.0;
-        for (int v = 0; v < j; ++v) sy += sums[DG_S + v] * sums[DG_Y + v];
-        const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
-        const double hjj = (sums[DG_BETA] - sy) * inv_r;
-        const double cw = hjj * inv_r;
-        for (int v = 0; v < j; ++v) {
-            a.h1[v] = sums[DG_Y + v];
-            a.coef[v] = sums[DG_S + v];
-            a.coef[kDgCoefW + v] = sums[DG_Y + v] - cw * sums[DG_S + v];
-        }
-        a.h1[j] = hjj;
-        a.coef[2 * kDgCoefW] = inv_r;
-        a.coef[2 * kDgCoefW + 1] = cw;
-    }
+    if (with_w) a.h1[j] = pre[2];
     if (a.host) {
         a.host[0] = r;
         a.host[1] = res;
