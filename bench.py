@@ -360,8 +360,8 @@ def kernel_micro(torch, I, L, Context, reps, pins=None):
 
 def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
     """Trained network vs the physics preconditioner (with the timed legs' sweep
-    count and with two sweeps) vs the untrained form on the stable thermal at
-    256 x 128 (two steps each from the same state)."""
+    count and with two sweeps; and the plain FP64 solve with it) vs the untrained
+    form on the stable thermal at 256 x 128 (two steps each from the same state)."""
     import numpy as np
     prob = I.thermal_stable_2d(256, 128)
     ctx = Context(prob, max_m=30)
@@ -372,13 +372,16 @@ def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0])}
-    for name, pc, params, sw in [("physics", "physics", None, sweeps), ("physics_sweeps2", "physics", None, 2),
-                                 ("learned", "learned", theta, 0),
-                                 ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32), 0)]:
+    for name, pc, params, sw, inner in [("physics", "physics", None, sweeps, "f32"),
+                                        ("physics_sweeps2", "physics", None, 2, "f32"),
+                                        ("plain_f64_physics", "physics", None, sweeps, "f64"),
+                                        ("learned", "learned", theta, 0, "f32"),
+                                        ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32), 0, "f32")]:
         if params is not None:
             ctx.net_set_params(params)
-        leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner="f32",
-                        eta_floor=1e-4, pc=pc, sweeps=sw, ortho=ortho)
+        extra = dict(eta_floor=1e-4) if inner == "f32" else {}
+        leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner=inner,
+                        pc=pc, sweeps=sw, ortho=ortho, **extra)
         out[name] = per_step(leg)
     return out
 
