@@ -197,6 +197,35 @@ def test_gmres_full_cycle_of_30_f64(ortho):
     assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
 
 
+def test_one_reduction_f32_full_size_matches_cgs2():
+    """FP32 at 1024 x 512, two restarts of 30: the one-reduction step against
+    CGS2 on the same inputs.  Regression test for the scale of the lagged
+    basis vector, which once compounded over a cycle and overflowed the FP32
+    products inside the Jv (non-finite result after 29 iterations)."""
+    import torch
+    prob = I.thermal_stable_2d(1024, 512)
+    U = I.bubble_state(prob)
+    c = _ctx(prob, max_m=30)
+    u64 = dev(U)
+    f = u64.clone()
+    c.rhs(u64, f)
+    R = u64.clone()
+    c.residual(u64, f, R)
+    u32, b32 = u64.float(), (-R).float()
+    out = {}
+    for ortho in ("cgs2", "one_reduction"):
+        x = torch.zeros_like(b32)
+        r = c.gmres(u32, b32, x, m=30, max_restarts=5, tol=0.0, pc="physics", sweeps=0, max_iters=70,
+                    ortho=ortho)
+        assert r.iters == 70 and r.restarts == 2
+        out[ortho] = (host(x), r.res_est)
+    xa, ra = out["cgs2"]
+    xb, rb = out["one_reduction"]
+    assert np.all(np.isfinite(xb))
+    assert np.linalg.norm(xb - xa) <= 1e-5 * np.linalg.norm(xa)
+    assert abs(rb - ra) <= 1e-3 * ra
+
+
 def test_gmres_basis_beyond_32_vectors_f64():
     """One cycle of 36 iterations: the Gram-Schmidt passes run with the basis in
     registers up to 32 vectors (8-, 16- and 32-row forms) and staged in LDS
