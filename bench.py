@@ -20,6 +20,8 @@ Legs, all from the same state after the warm-up steps:
   mixed_pc_sweeps2  the mixed leg with two preconditioner sweeps (the source of
             roofline_pc, whose kernels the timed legs launch without sweeps)
   mixed_cgs2  the mixed leg with the CGS2 Arnoldi step
+  ensemble  one mixed step of the 64-instance heat-island ensemble (3.93 M points,
+            uneven grids), reported in config.ensemble_64_heat_island
   learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
             the network is trained first on pairs the solver generates on this
             workload (training time reported, not timed with the steps)
@@ -83,7 +85,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,sweeps2,cgs2,learned,p3,deardorff,3d")
+    ap.add_argument("--legs", default="mixed,plain,sweeps2,cgs2,learned,p3,deardorff,3d,ensemble")
     ap.add_argument("--ortho", default="one_reduction", choices=["one_reduction", "cgs2"],
                     help="Gram-Schmidt form of the Arnoldi step in the timed legs (the cgs2 leg repeats the timed "
                          "configuration with CGS2)")
@@ -505,6 +507,32 @@ def main():
         del ctx3d, u3d
         torch.cuda.empty_cache()
 
+    ensemble = None
+    if "ensemble" in legs_wanted:
+        # the 64-instance heat-island ensemble (uneven 2D grids, one launch per stage); its
+        # Krylov solves use CGS2 (the ensemble path has no one-reduction step)
+        from paper_2007_10411_amd.jfnk import Batch
+        log("one mixed step of the 64-instance heat-island ensemble")
+        eprobs = I.heat_island_ensemble(64, seed=0)
+        bt = Batch(eprobs, max_m=30)
+        erows = bt.tune()
+        un_e = bt.pack([I.rest_state(p) for p in eprobs])
+        ue = un_e.clone()
+        bt.newton_step(un_e, ue, sweeps=args.pc_sweeps)          # untimed: first launches
+        ue = un_e.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eres = bt.newton_step(un_e, ue, sweeps=args.pc_sweeps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = [r.gmres_iters_total for r in eres]
+        ensemble = {"instances": len(eprobs), "points": int(sum(p.npts for p in eprobs)),
+                    "ms_per_step": el * 1e3, "converged": all(r.converged for r in eres),
+                    "gmres_iters_per_instance": [min(its), max(its)], "gmres_iters_total": sum(its),
+                    "pc_sweeps": args.pc_sweeps, "launch_shapes": erows}
+        del bt, un_e, ue
+        torch.cuda.empty_cache()
+
     T = legs["mixed"]
     tm = T["tm"]
     npts = prob.npts
@@ -570,6 +598,7 @@ def main():
                                       if "plain" in legs else None),
             "training": train_info,
             "learned_256x128": small,
+            "ensemble_64_heat_island": ensemble,
             "jv_kernel_gpts": npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0,
             "kernel_ms_per_step": {k: v[0] / steps["mixed"] for k, v in tm.items()},
             "launch_shapes": shapes,
