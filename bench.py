@@ -509,8 +509,7 @@ def main():
 
     ensemble = None
     if "ensemble" in legs_wanted:
-        # the 64-instance heat-island ensemble (uneven 2D grids, one launch per stage); its
-        # Krylov solves use CGS2 (the ensemble path has no one-reduction step)
+        # the 64-instance heat-island ensemble (uneven 2D grids, one launch per stage)
         from paper_2007_10411_amd.jfnk import Batch
         log("one mixed step of the 64-instance heat-island ensemble")
         eprobs = I.heat_island_ensemble(64, seed=0)
@@ -518,18 +517,18 @@ def main():
         erows = bt.tune()
         un_e = bt.pack([I.rest_state(p) for p in eprobs])
         ue = un_e.clone()
-        bt.newton_step(un_e, ue, sweeps=args.pc_sweeps)          # untimed: first launches
+        bt.newton_step(un_e, ue, sweeps=args.pc_sweeps, ortho=args.ortho)   # untimed: first launches
         ue = un_e.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        eres = bt.newton_step(un_e, ue, sweeps=args.pc_sweeps)
+        eres = bt.newton_step(un_e, ue, sweeps=args.pc_sweeps, ortho=args.ortho)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         its = [r.gmres_iters_total for r in eres]
         ensemble = {"instances": len(eprobs), "points": int(sum(p.npts for p in eprobs)),
                     "ms_per_step": el * 1e3, "converged": all(r.converged for r in eres),
                     "gmres_iters_per_instance": [min(its), max(its)], "gmres_iters_total": sum(its),
-                    "pc_sweeps": args.pc_sweeps, "launch_shapes": erows}
+                    "pc_sweeps": args.pc_sweeps, "ortho": args.ortho, "launch_shapes": erows}
         del bt, un_e, ue
         torch.cuda.empty_cache()
 

@@ -69,7 +69,7 @@ typedef enum { JFNK_JV_STABLE = 0, JFNK_JV_LITERAL = 1, JFNK_JV_ANALYTIC = 2 } j
  *       provides them (two passes over the basis per iteration); a column of
  *       the Hessenberg matrix is final one iteration later.  Equal to CGS2 in
  *       exact arithmetic.  Used when m < 32 and the vectors hold fewer than
- *       2^30 values; CGS2 otherwise.  The ensemble path always uses CGS2.     */
+ *       2^30 values (for the ensemble: m < 32); CGS2 otherwise.               */
 typedef enum { JFNK_ORTHO_CGS2 = 0, JFNK_ORTHO_ONE_REDUCTION = 1 } jfnk_ortho;
 typedef enum {
     JFNK_CLOSURE_CONST_K = 0,

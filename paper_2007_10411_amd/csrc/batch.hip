@@ -305,6 +305,232 @@ __global__ __launch_bounds__(kB) void kb_cgs_reg(BTab t, const T* __restrict__ V
         partials[(long long)tid * nchunks + blockIdx.x] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
+// ---------------------------------------------------------------------------
+// One-reduction Arnoldi step over the instances (the single-problem k_dg_*
+// kernels, per chunk and per instance): the reduction pass writes per chunk
+// the partial dots s (slots 0..), y (slots kDgMaxRows..), alpha and beta; one
+// 1024-thread block per instance adds its chunks, closes column j-1 with its
+// Givens step and forms the update coefficients; the update pass writes q_j
+// and q~_{j+1} = (w - V y - q_j h_jj) / r_j.
+// ---------------------------------------------------------------------------
+enum { BD_S = 0, BD_Y = kDgMaxRows, BD_ALPHA = 2 * kDgMaxRows, BD_BETA = 2 * kDgMaxRows + 1,
+       BD_SLOTS = 2 * kDgMaxRows + 2 };
+constexpr int kBdCoef = 2 * M + 2;       // per instance: a[M], e[M], 1/r, c_w
+
+template <typename T, int NV, bool W>
+__global__ __launch_bounds__(kB) void kb_dg_dot(BTab t, const T* __restrict__ V, long long ntot, int j,
+                                                double* __restrict__ partials, int nchunks) {
+    constexpr int NA = W ? 2 * NV : NV;
+    __shared__ double red[4][NA + 2];
+    const Chunk c = chunk_of(t);
+    if (inactive(t, c.inst)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const T* q = V + (long long)j * ntot;
+    const T* w = V + (long long)(j + 1) * ntot;
+    const int last = j > 0 ? j - 1 : 0;      // rows past j - 1 re-read row j - 1 (row 0 when j = 0)
+    double acc[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) acc[v] = 0.0;
+    double aa = 0.0, ab = 0.0;
+    for (long long i = c.b + tid; i < c.e; i += kB) {
+        const T qv = q[i];
+        const T wv = W ? w[i] : T(0);
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < j ? v : last) * ntot + i];
+        __builtin_amdgcn_sched_barrier(0);
+        const double qd = (double)qv, wd = (double)wv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc[v] += (double)x[v] * qd;
+            if (W) acc[NV + v] += (double)x[v] * wd;
+        }
+        aa += qd * qd;
+        if (W) ab += qd * wd;
+    }
+    constexpr int kSpan = 64 / NA;
+    const double tsum = wave_sum_scatter<NA>(acc, lane);
+    if (lane % kSpan == 0) red[wid][lane / kSpan] = tsum;
+    const double ta = wave_sum64(aa);
+    const double tb = W ? wave_sum64(ab) : 0.0;
+    if (lane == 0) {
+        red[wid][NA] = ta;
+        red[wid][NA + 1] = tb;
+    }
+    __syncthreads();
+    for (int o = tid; o < NA + 2; o += kB) {
+        const double sum = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+        int slot = -1;
+        if (o < NV) {
+            if (o < j) slot = BD_S + o;
+        } else if (o < NA) {
+            if (o - NV < j) slot = BD_Y + (o - NV);
+        } else if (o == NA) {
+            slot = BD_ALPHA;
+        } else if (W) {
+            slot = BD_BETA;
+        }
+        if (slot >= 0) partials[(long long)slot * nchunks + blockIdx.x] = sum;
+    }
+}
+
+struct BdArgs {
+    double* H;
+    double* Hraw;
+    double* cs;
+    double* sn;
+    double* g;
+    double* h1;
+    double* rs;       // per instance: r_c, the norm of basis vector c before normalization
+    double* coef;     // per instance: kBdCoef update coefficients
+    double* scal;     // per instance: SB_WNORM <- r_j, SB_RES <- |g_j| after the Givens step
+    int m;
+};
+
+__global__ __launch_bounds__(1024) void kb_dg_finish(BTab t, const double* __restrict__ partials, int nchunks, int j,
+                                                     int with_w, BdArgs a) {
+    const int inst = blockIdx.x;
+    if (inactive(t, inst)) return;
+    __shared__ double sums[BD_SLOTS];
+    __shared__ double hp[M + 1], scs[M], ssn[M], pre[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int c0 = t.chunk_off[inst], c1 = t.chunk_off[inst + 1];
+    for (int o = wid; o < BD_SLOTS; o += 16) {
+        const bool need = o < BD_Y ? o < j : o < BD_ALPHA ? (with_w && o - BD_Y < j) : (o == BD_ALPHA || with_w);
+        if (!need) continue;
+        double acc = 0.0;
+        for (int b = c0 + lane; b < c1; b += 64) acc += partials[(long long)o * nchunks + b];
+        acc = wave_sum64(acc);
+        if (lane == 0) sums[o] = acc;
+    }
+    const int m = a.m;
+    double* H = a.H + (long long)inst * (M + 1) * M;
+    double* Hraw = a.Hraw + (long long)inst * (M + 1) * M;
+    double* cs = a.cs + (long long)inst * M;
+    double* sn = a.sn + (long long)inst * M;
+    double* g = a.g + (long long)inst * (M + 1);
+    double* h1 = a.h1 + (long long)inst * M;
+    double* rs = a.rs + (long long)inst * M;
+    double* coef = a.coef + (long long)inst * kBdCoef;
+    double* sc = a.scal + (long long)inst * S_STRIDE;
+    for (int r = tid; r < j; r += 1024) {
+        hp[r] = h1[r];
+        scs[r] = cs[r];
+        ssn[r] = sn[r];
+    }
+    if (tid == 1023 && j > 0) {
+        pre[0] = rs[j - 1];
+        pre[1] = g[j - 1];
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const double sv = lane < j ? sums[BD_S + lane] : 0.0;
+        const double yv = (with_w && lane < j) ? sums[BD_Y + lane] : 0.0;
+        double ss = sv * sv, sy = sv * yv;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            ss += __shfl_xor(ss, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+        }
+        const double r2 = sums[BD_ALPHA] - ss;
+        const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+        if (j > 0) {
+            const double scl = pre[0];
+            const double inv_scl = scl > 0.0 ? 1.0 / scl : 0.0;
+            double h = 0.0;
+            if (lane < j) h = hp[lane] + scl * sv;
+            else if (lane == j) h = scl * r;
+            if (lane <= j) {
+                hp[lane] = h;
+                Hraw[lane * m + (j - 1)] = h * inv_scl;
+            }
+        }
+        if (with_w) {
+            const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
+            const double hjj = (sums[BD_BETA] - sy) * inv_r;
+            const double cw = hjj * inv_r;
+            if (lane < j) {
+                coef[lane] = sv;
+                coef[M + lane] = yv - cw * sv;
+            }
+            if (lane == 0) {
+                coef[2 * M] = inv_r;
+                coef[2 * M + 1] = cw;
+                pre[2] = hjj;
+            }
+        }
+        if (lane == 0) pre[3] = r;
+    }
+    __syncthreads();
+    if (with_w && tid < j) h1[tid] = sums[BD_Y + tid];
+    if (tid != 0) return;
+    const double r = pre[3];
+    double res = 0.0;
+    if (j == 0) {
+        g[0] = r;
+    } else {
+        const int c = j - 1;
+        double y = hp[0];
+        for (int k = 0; k < c; ++k) {
+            const double z = hp[k + 1];
+            H[k * m + c] = scs[k] * y + ssn[k] * z;
+            y = -ssn[k] * y + scs[k] * z;
+        }
+        const double z = hp[c + 1];
+        const double rr = hypot(y, z);
+        double cc = 1.0, snn = 0.0;
+        if (rr > 0.0) {
+            cc = y / rr;
+            snn = z / rr;
+        }
+        cs[c] = cc;
+        sn[c] = snn;
+        H[c * m + c] = rr;
+        H[(c + 1) * m + c] = 0.0;
+        const double gc = pre[1];
+        g[c + 1] = -snn * gc;
+        g[c] = cc * gc;
+        res = fabs(snn * gc);
+    }
+    rs[j] = r;
+    if (with_w) h1[j] = pre[2];
+    sc[SB_WNORM] = r;
+    sc[SB_RES] = res;
+}
+
+template <typename T, int NV>
+__global__ __launch_bounds__(kB) void kb_dg_update(BTab t, T* V, long long ntot, int j,
+                                                   const double* __restrict__ coefs) {
+    const Chunk c = chunk_of(t);
+    if (inactive(t, c.inst)) return;
+    const double* coef = coefs + (long long)c.inst * kBdCoef;
+    T* q = V + (long long)j * ntot;
+    T* w = V + (long long)(j + 1) * ntot;
+    const int last = j > 0 ? j - 1 : 0;
+    double ca[NV], ce[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ca[v] = v < j ? coef[v] : 0.0;
+        ce[v] = v < j ? coef[M + v] : 0.0;
+    }
+    const double inv_r = coef[2 * M], cw = coef[2 * M + 1];
+    for (long long i = c.b + threadIdx.x; i < c.e; i += kB) {
+        const T qv = q[i], wv = w[i];
+        T x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < j ? v : last) * ntot + i];
+        __builtin_amdgcn_sched_barrier(0);
+        double sq = (double)qv, sw = (double)wv - cw * (double)qv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            sq -= ca[v] * (double)x[v];
+            sw -= ce[v] * (double)x[v];
+        }
+        q[i] = (T)(sq * inv_r);
+        w[i] = (T)(sw * inv_r);
+    }
+}
+
 // block (i, v): hout[i][v] = sum over instance i's chunks; after the last pass
 // the Givens step of column j for instance i (one thread)
 __global__ __launch_bounds__(kB) void kb_cgs_finish(BTab t, const double* __restrict__ partials, int nchunks,
@@ -414,6 +640,10 @@ __global__ __launch_bounds__(kB) void kb_normalize_copy(BTab t, T* __restrict__ 
                                                         int which, T* __restrict__ z) {
     const Chunk c = chunk_of(t);
     if (inactive(t, c.inst)) return;
+    if (which < 0) {                      // copy only (the one-reduction step keeps V_j as it is)
+        for (long long e = c.b + threadIdx.x; e < c.e; e += kB) z[e] = v[e];
+        return;
+    }
     const double d = scal[(long long)c.inst * S_STRIDE + which];
     for (long long e = c.b + threadIdx.x; e < c.e; e += kB) {
         const T o = (T)((double)v[e] / d);
@@ -471,6 +701,7 @@ struct jfnk_batch {
     // per-instance scalars
     double *H = nullptr, *Hraw = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h1 = nullptr,
            *h2 = nullptr, *scal = nullptr, *outv = nullptr;
+    double* coef = nullptr;     // one-reduction step: update coefficients per instance
     double* partials = nullptr;
     double* hscal = nullptr;    // pinned: ninst * S_STRIDE
     int* hflags = nullptr;      // pinned: ninst
@@ -606,11 +837,227 @@ int b_set_kcnt(jfnk_batch* b, const std::vector<int>& k) {
     return JFNK_OK;
 }
 
+template <typename T>
+hipError_t launch_kb_dg_dot(jfnk_batch* b, const BTab& t, int j, bool with_w) {
+    const dim3 grid(b->nchunks);
+    const float* V = (const float*)b->V32;
+    if (with_w) {
+        if (j <= 8)
+            hipLaunchKernelGGL((kb_dg_dot<T, 8, true>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j, b->partials,
+                               b->nchunks);
+        else if (j <= 16)
+            hipLaunchKernelGGL((kb_dg_dot<T, 16, true>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j, b->partials,
+                               b->nchunks);
+        else
+            hipLaunchKernelGGL((kb_dg_dot<T, 32, true>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j, b->partials,
+                               b->nchunks);
+    } else {
+        if (j <= 8)
+            hipLaunchKernelGGL((kb_dg_dot<T, 8, false>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j, b->partials,
+                               b->nchunks);
+        else if (j <= 16)
+            hipLaunchKernelGGL((kb_dg_dot<T, 16, false>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j,
+                               b->partials, b->nchunks);
+        else
+            hipLaunchKernelGGL((kb_dg_dot<T, 32, false>), grid, dim3(kB), 0, b->stream, t, V, b->ntot, j,
+                               b->partials, b->nchunks);
+    }
+    return hipGetLastError();
+}
+
+// reduction (and, with w, the update) of the one-reduction step j for the
+// active instances; r_j and |g_j| land in scal (SB_WNORM, SB_RES)
+int b_dg(jfnk_batch* b, int j, bool with_w, int m) {
+    if (j < 0 || j >= kDgMaxRows) {
+        set_error("the one-reduction step handles fewer than 32 basis vectors");
+        return JFNK_ERR_ARG;
+    }
+    const BTab t = tab(b, 1, true);
+    JFNK_HIP(launch_kb_dg_dot<float>(b, t, j, with_w));
+    BdArgs a;
+    a.H = b->H;
+    a.Hraw = b->Hraw;
+    a.cs = b->cs;
+    a.sn = b->sn;
+    a.g = b->g;
+    a.h1 = b->h1;
+    a.rs = b->h2;             // CGS2's second-pass coefficients are unused here
+    a.coef = b->coef;
+    a.scal = b->scal;
+    a.m = m;
+    hipLaunchKernelGGL(kb_dg_finish, dim3(b->ninst), dim3(1024), 0, b->stream, t, (const double*)b->partials,
+                       b->nchunks, j, with_w ? 1 : 0, a);
+    JFNK_HIP(hipGetLastError());
+    if (!with_w) return JFNK_OK;
+    float* V = b->V32;
+    if (j <= 8)
+        hipLaunchKernelGGL((kb_dg_update<float, 8>), dim3(b->nchunks), dim3(kB), 0, b->stream, t, V, b->ntot, j,
+                           (const double*)b->coef);
+    else if (j <= 16)
+        hipLaunchKernelGGL((kb_dg_update<float, 16>), dim3(b->nchunks), dim3(kB), 0, b->stream, t, V, b->ntot, j,
+                           (const double*)b->coef);
+    else
+        hipLaunchKernelGGL((kb_dg_update<float, 32>), dim3(b->nchunks), dim3(kB), 0, b->stream, t, V, b->ntot, j,
+                           (const double*)b->coef);
+    JFNK_HIP(hipGetLastError());
+    return JFNK_OK;
+}
+
+// b_gmres with the one-reduction Arnoldi step: column j-1 of an instance is
+// closed at iteration j (or by the closing reduction at the end of a cycle),
+// so its convergence is known one iteration later; the basis vectors stay
+// unnormalized until then.
+int b_gmres_one_reduction(jfnk_batch* b, const float* u, const float* rhs, float* x, const std::vector<int>& act0,
+                          const std::vector<double>& tol, const jfnk_gmres_opts& o, std::vector<int>& iters,
+                          std::vector<int>& conv) {
+    const int ni = b->ninst, m = o.m;
+    const long long ntot = b->ntot;
+    const int max_iters = o.max_iters > 0 ? o.max_iters : m * o.max_restarts;
+    const double sqrt_eps = std::sqrt(1.1920928955078125e-07);
+    hipStream_t s = b->stream;
+    std::vector<int> act = act0;
+    iters.assign(ni, 0);
+    conv.assign(ni, 0);
+    int rc;
+    if ((rc = b_set_active(b, act))) return rc;
+    {
+        const BTab t = tab(b, 1, false);
+        hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
+        JFNK_HIP(hipGetLastError());
+        if (o.pc == JFNK_PC_PHYSICS) {
+            const BTab ta = tab(b, 1, true);
+            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
+            JFNK_HIP(hipGetLastError());
+        }
+    }
+    if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
+    JFNK_HIP(hipMemcpyAsync(b->V32, rhs, ntot * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+    if ((rc = b_read_scal(b))) return rc;
+    std::vector<double> bnorm(ni, 0.0), res(ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        if (!act[i]) continue;
+        bnorm[i] = b->hscal[(long long)i * S_STRIDE + SB_BETA];
+        if (!std::isfinite(bnorm[i])) {
+            set_error("non-finite right-hand side norm in the batch");
+            return JFNK_ERR_NONFINITE;
+        }
+        res[i] = bnorm[i];
+        if (bnorm[i] == 0.0) {
+            act[i] = 0;
+            conv[i] = 1;
+        }
+    }
+    const BTab tall = tab(b, 1, false);
+    // after the reduction that closed column `col` of every active instance:
+    // count it and stop the instances that are done
+    auto close_column = [&](int col, std::vector<int>& kcnt, bool& any) -> int {
+        if ((rc = b_read_scal(b))) return rc;
+        any = false;
+        for (int i = 0; i < ni; ++i) {
+            if (!act[i]) continue;
+            const double r = b->hscal[(long long)i * S_STRIDE + SB_WNORM];
+            res[i] = b->hscal[(long long)i * S_STRIDE + SB_RES];
+            if (!std::isfinite(r) || !std::isfinite(res[i])) {
+                set_error("non-finite Krylov norm in the batch");
+                return JFNK_ERR_NONFINITE;
+            }
+            kcnt[i] = col + 1;
+            iters[i]++;
+            if (res[i] <= tol[i] * bnorm[i] || r == 0.0 || iters[i] >= max_iters || col + 1 == m) {
+                act[i] = 0;
+                conv[i] = res[i] <= tol[i] * bnorm[i] ? 1 : 0;
+            } else {
+                any = true;
+            }
+        }
+        return JFNK_OK;
+    };
+    while (true) {
+        if (std::none_of(act.begin(), act.end(), [](int a) { return a; })) break;
+        if ((rc = b_set_active(b, act))) return rc;
+        const BTab ta = tab(b, 1, true);
+        hipLaunchKernelGGL(kb_set_start, dim3((ni + 255) / 256), dim3(256), 0, s, ta, b->g, (const double*)b->scal, m);
+        JFNK_HIP(hipGetLastError());
+        std::vector<int> kcnt(ni, 0);
+        const std::vector<int> in_cycle = act;
+        bool closed_last = false;
+        for (int j = 0; j < m; ++j) {
+            float* Vj = b->V32 + (long long)j * ntot;
+            float* Vn = b->V32 + (long long)(j + 1) * ntot;
+            float* Zj = b->Z32 + (long long)j * ntot;
+            // z_j = M^-1 q~_j (q~_j not normalized)
+            if (o.pc == JFNK_PC_PHYSICS) {
+                float* bufs[2] = {Zj, b->t32};
+                int cur = (o.sweeps % 2 == 0) ? 0 : 1;
+                hipLaunchKernelGGL((kb_pc_diag<float>), dim3(b->pblk_off[ni]), dim3(kB), 0, s, ta,
+                                   (const float*)b->nu32, Vj, (const double*)nullptr, bufs[cur]);
+                JFNK_HIP(hipGetLastError());
+                for (int sw = 0; sw < o.sweeps; ++sw) {
+                    JFNK_HIP(b_pc_sweep<float>(b, u, b->nu32, Vj, bufs[cur], bufs[1 - cur], b->tune[2 * 2 + 1]));
+                    cur = 1 - cur;
+                }
+            } else {
+                hipLaunchKernelGGL((kb_normalize_copy<float>), dim3(b->nchunks), dim3(kB), 0, s, ta, Vj,
+                                   (const double*)b->scal, -1, Zj);
+                JFNK_HIP(hipGetLastError());
+            }
+            if ((rc = b_norm2<float>(b, Zj, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
+            JFNK_HIP(b_jv<float>(b, u, Zj, b->scal + SB_EPS, Vn, b->tune[1 * 2 + 1]));
+            if ((rc = b_dg(b, j, true, m))) return rc;
+            if (j == 0) continue;                       // no column closed yet
+            bool any = false;
+            if ((rc = close_column(j - 1, kcnt, any))) return rc;
+            if (!any) {
+                closed_last = true;
+                break;
+            }
+            if ((rc = b_set_active(b, act))) return rc;
+        }
+        if (!closed_last) {
+            // column m-1 of the instances still working: closing reduction over q~_m
+            if ((rc = b_set_active(b, act))) return rc;
+            if ((rc = b_dg(b, m, false, m))) return rc;
+            bool any = false;
+            if ((rc = close_column(m - 1, kcnt, any))) return rc;
+        }
+        // solution update of every instance that worked in this cycle
+        if ((rc = b_set_kcnt(b, kcnt))) return rc;
+        hipLaunchKernelGGL(kb_backsolve, dim3((ni + 63) / 64), dim3(64), 0, s, tall, (const double*)b->H,
+                           (const double*)b->g, (const int*)b->d_kcnt, m, b->y);
+        JFNK_HIP(hipGetLastError());
+        hipLaunchKernelGGL((kb_axpy_basis<float>), dim3(b->nchunks), dim3(kB), 0, s, tall, x, (const float*)b->Z32,
+                           ntot, (const int*)b->d_kcnt, (const double*)b->y);
+        JFNK_HIP(hipGetLastError());
+        // instances that ended the cycle unconverged with iterations left restart from the true residual
+        for (int i = 0; i < ni; ++i)
+            if (in_cycle[i] && !conv[i] && iters[i] < max_iters && kcnt[i] == m) act[i] = 1;
+        if (std::none_of(act.begin(), act.end(), [](int a) { return a; })) break;
+        if ((rc = b_set_active(b, act))) return rc;
+        const BTab tr = tab(b, 1, true);
+        if ((rc = b_norm2<float>(b, x, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
+        JFNK_HIP(b_jv<float>(b, u, x, b->scal + SB_EPS, b->V32, b->tune[1 * 2 + 1]));
+        hipLaunchKernelGGL((kb_lincomb<float>), dim3(b->nchunks), dim3(kB), 0, s, tr, b->V32, rhs, b->V32, 1.0, -1.0);
+        JFNK_HIP(hipGetLastError());
+        if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+        if ((rc = b_read_scal(b))) return rc;
+        for (int i = 0; i < ni; ++i)
+            if (act[i] && b->hscal[(long long)i * S_STRIDE + SB_BETA] == 0.0) {
+                act[i] = 0;
+                conv[i] = 1;
+            }
+    }
+    JFNK_HIP(hipStreamSynchronize(s));
+    return JFNK_OK;
+}
+
 // Lockstep flexible GMRES(m) in FP32 over the instances with act[i] = 1:
 // J_i x_i = b_i to relative tolerance tol[i]; x of the others is left at zero.
 int b_gmres(jfnk_batch* b, const float* u, const float* rhs, float* x, const std::vector<int>& act0,
             const std::vector<double>& tol, const jfnk_gmres_opts& o, std::vector<int>& iters,
             std::vector<int>& conv) {
+    if (o.ortho == JFNK_ORTHO_ONE_REDUCTION && o.m < kDgMaxRows)
+        return b_gmres_one_reduction(b, u, rhs, x, act0, tol, o, iters, conv);
     const int ni = b->ninst, m = o.m;
     const long long ntot = b->ntot;
     const int max_iters = o.max_iters > 0 ? o.max_iters : m * o.max_restarts;
@@ -781,7 +1228,7 @@ int jfnk_batch_destroy(jfnk_batch* b) {
                     b->d_tiles_x[0], b->d_tiles_x[1], b->d_tiles_x[2], b->d_pblk_off, b->d_eblk_off, b->d_chunk_off,
                     b->d_active, b->d_kcnt, b->V32, b->Z32, b->u32, b->b32, b->x32, b->t32, b->nu32, b->f64, b->R64,
                     b->bg64, b->bg32, b->H, b->Hraw, b->cs, b->sn, b->g, b->y, b->h1, b->h2, b->scal, b->outv,
-                    b->partials};
+                    b->partials, b->coef};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->hscal) (void)hipHostFree(b->hscal);
@@ -887,7 +1334,8 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
     BALLOC(b->h2, (size_t)ninst * M);
     BALLOC(b->scal, (size_t)ninst * S_STRIDE);
     BALLOC(b->outv, (size_t)ninst);
-    BALLOC(b->partials, (size_t)b->nchunks * kMaxDots);
+    BALLOC(b->partials, (size_t)b->nchunks * (kMaxDots + 2));   // the one-reduction pass uses 2 kDgMaxRows + 2
+    BALLOC(b->coef, (size_t)ninst * kBdCoef);
 #undef BALLOC
     if (hipHostMalloc((void**)&b->hscal, (size_t)ninst * S_STRIDE * sizeof(double), hipHostMallocDefault) !=
             hipSuccess ||
@@ -961,8 +1409,10 @@ int jfnk_batch_apply_F(jfnk_batch* b, int32_t what, const double* u, const doubl
 int jfnk_batch_newton_step(jfnk_batch* b, const double* u_n, double* u, const jfnk_newton_opts* o,
                            jfnk_newton_info* infos) {
     if (!b || !u_n || !u || !o || o->inner != JFNK_F32 || o->gm.m < 1 || o->gm.m > b->max_m ||
-        (o->gm.pc != JFNK_PC_PHYSICS && o->gm.pc != JFNK_PC_NONE) || o->max_newton < 0) {
-        set_error("invalid argument to jfnk_batch_newton_step (FP32 inner solve, physics or no preconditioner)");
+        (o->gm.pc != JFNK_PC_PHYSICS && o->gm.pc != JFNK_PC_NONE) || o->max_newton < 0 ||
+        (o->gm.ortho != JFNK_ORTHO_CGS2 && o->gm.ortho != JFNK_ORTHO_ONE_REDUCTION)) {
+        set_error("invalid argument to jfnk_batch_newton_step (FP32 inner solve, physics or no preconditioner, "
+                  "a known Gram-Schmidt form)");
         return JFNK_ERR_ARG;
     }
     const int ni = b->ninst;

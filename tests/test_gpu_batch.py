@@ -44,14 +44,16 @@ def test_batched_residual_matches_oracle():
         assert_fields_close(got[i], ref, 1e-11, f"batch residual {i}")
 
 
-def test_batched_step_matches_oracle_steps():
+@pytest.mark.parametrize("ortho,m", [("cgs2", 30), ("one_reduction", 30), ("one_reduction", 6)])
+def test_batched_step_matches_oracle_steps(ortho, m):
+    """m = 6 forces restarts (and closing reductions) inside the lockstep loop."""
     from paper_2007_10411_amd.jfnk import Batch
     probs = _small_ensemble()[:4]
     b = Batch(probs, max_m=30)
     U0 = [I.bubble_state(p) if p.h0 == 0 else I.rest_state(p) for p in probs]
     un = b.pack(U0)
     u = un.clone()
-    res = b.newton_step(un, u, rtol=1e-10)
+    res = b.newton_step(un, u, rtol=1e-10, ortho=ortho, m=m, max_restarts=100)
     assert all(r.converged for r in res), res
     got = b.unpack(u)
     for i, p in enumerate(probs):
