@@ -332,7 +332,8 @@ int jfnk_batch_size(jfnk_batch* batch, int64_t* total, int64_t* offsets);
 /* F / rhs / residual of every instance (what as in jfnk_apply_F), FP64.          */
 int jfnk_batch_apply_F(jfnk_batch* batch, int32_t what, const double* u, const double* f, double* out);
 /* One trapezoidal step of every instance (opts->inner must be JFNK_F32; the
- * recording fields are ignored); infos: HOST array of ninst results.            */
+ * recording fields are ignored; opts->gm.ortho selects the Arnoldi step as in
+ * jfnk_gmres); infos: HOST array of ninst results.                              */
 int jfnk_batch_newton_step(jfnk_batch* batch, const double* u_n, double* u_np1, const jfnk_newton_opts* opts,
                            jfnk_newton_info* infos);
 /* Autotuner of the batched residual, Jv and sweep kernels (tile heights 4, 8,

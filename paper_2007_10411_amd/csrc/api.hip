@@ -357,6 +357,73 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
     return JFNK_OK;
 }
 
+// Start of both GMRES forms: frozen coefficients, ||u||^2, x = 0, V_0 = rhs and
+// beta = ||rhs|| (g = beta e_1, beta also on the host).  bnorm = 0: nothing
+// to solve (info says converged).
+template <typename T>
+int gmres_begin(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o, jfnk_gmres_info* info,
+                double& bnorm) {
+    const long long n = c->n;
+    T* V = Vb<T>(c);
+    hipStream_t s = c->stream;
+    int rc;
+    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, u, NUb<T>(c)));
+    if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
+    JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
+    JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), o.m, s));
+    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+    bnorm = c->hscal[S_BETA];
+    if (info) {
+        info->res0 = bnorm;
+        info->res_est = bnorm;
+        info->iters = 0;
+        info->restarts = 0;
+        info->converged = bnorm == 0.0 ? 1 : 0;
+    }
+    if (!std::isfinite(bnorm)) {
+        set_error("non-finite right-hand side norm");
+        return JFNK_ERR_NONFINITE;
+    }
+    return JFNK_OK;
+}
+
+// Restart: the true residual r = rhs - J x into V_0, beta = ||r||, g = beta e_1;
+// zero when r = 0.
+template <typename T>
+int gmres_restart(jfnk_ctx* c, const T* u, const T* b, const T* x, const jfnk_gmres_opts& o, bool& zero) {
+    const long long n = c->n;
+    T* V = Vb<T>(c);
+    hipStream_t s = c->stream;
+    int rc;
+    if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
+    if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
+    JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
+    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
+    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), o.m, s));
+    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
+    zero = c->hscal[S_BETA] == 0.0;
+    return JFNK_OK;
+}
+
+// End of both GMRES forms: the result fields (and the raw Hessenberg matrix of
+// the last cycle when asked for), after the stream has drained.
+int gmres_end(jfnk_ctx* c, jfnk_gmres_info* info, int m, int total, int restarts, bool converged, double res_est) {
+    if (info) {
+        info->iters = total;
+        info->restarts = restarts;
+        info->converged = converged ? 1 : 0;
+        info->res_est = res_est;
+        if (info->h_out) {
+            JFNK_HIP(hipMemcpyAsync(info->h_out, ds(c, O_HRAW), (size_t)(m + 1) * m * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    JFNK_HIP(hipStreamSynchronize(c->stream));
+    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+}
+
 template <typename T>
 int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts& o,
                         jfnk_gmres_info* info);
@@ -372,29 +439,9 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
     T* Z = Zb<T>(c);
     hipStream_t s = c->stream;
     int rc;
-    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, u, NUb<T>(c)));
-    if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
-    JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
-    JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
-    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
-    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
-    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
-    const double bnorm = c->hscal[S_BETA];
-    if (info) {
-        info->res0 = bnorm;
-        info->res_est = bnorm;
-        info->iters = 0;
-        info->restarts = 0;
-        info->converged = 0;
-    }
-    if (!std::isfinite(bnorm)) {
-        set_error("non-finite right-hand side norm");
-        return JFNK_ERR_NONFINITE;
-    }
-    if (bnorm == 0.0) {
-        if (info) info->converged = 1;
-        return JFNK_OK;
-    }
+    double bnorm = 0.0;
+    if ((rc = gmres_begin<T>(c, u, b, x, o, info, bnorm))) return rc;
+    if (bnorm == 0.0) return JFNK_OK;
     const EpsArgs ea = o.jv == JFNK_JV_ANALYTIC ? EpsArgs() : eps_args(c, eps_mach<T>());
     GivensArgs ga;
     ga.H = ds(c, O_H);
@@ -482,29 +529,14 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
         }
         ++restarts;
         // true residual r = b - J x
-        if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
-        if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
-        JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
-        if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
-        JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
-        if ((rc = read_scalars(c, S_BETA, 1))) return rc;
-        if (c->hscal[S_BETA] == 0.0) {
+        bool zero = false;
+        if ((rc = gmres_restart<T>(c, u, b, x, o, zero))) return rc;
+        if (zero) {
             converged = true;
             break;
         }
     }
-    if (info) {
-        info->iters = total;
-        info->restarts = restarts;
-        info->converged = converged ? 1 : 0;
-        info->res_est = res_est;
-        if (info->h_out) {
-            JFNK_HIP(hipMemcpyAsync(info->h_out, ds(c, O_HRAW), (size_t)(m + 1) * m * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-        }
-    }
-    JFNK_HIP(hipStreamSynchronize(s));
-    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+    return gmres_end(c, info, m, total, restarts, converged, res_est);
 }
 
 // FGMRES(m) with the one-reduction Arnoldi step (three launches per iteration:
@@ -524,29 +556,9 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
     T* Z = Zb<T>(c);
     hipStream_t s = c->stream;
     int rc;
-    if (o.pc == JFNK_PC_PHYSICS) JFNK_HIP(op_frozen_nu<T>(c, u, NUb<T>(c)));
-    if ((rc = norm2_to<T>(c, u, n, sc(c, S_UNORM2)))) return rc;
-    JFNK_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
-    JFNK_HIP(hipMemcpyAsync(V, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
-    if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
-    JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
-    if ((rc = read_scalars(c, S_BETA, 1))) return rc;
-    const double bnorm = c->hscal[S_BETA];
-    if (info) {
-        info->res0 = bnorm;
-        info->res_est = bnorm;
-        info->iters = 0;
-        info->restarts = 0;
-        info->converged = 0;
-    }
-    if (!std::isfinite(bnorm)) {
-        set_error("non-finite right-hand side norm");
-        return JFNK_ERR_NONFINITE;
-    }
-    if (bnorm == 0.0) {
-        if (info) info->converged = 1;
-        return JFNK_OK;
-    }
+    double bnorm = 0.0;
+    if ((rc = gmres_begin<T>(c, u, b, x, o, info, bnorm))) return rc;
+    if (bnorm == 0.0) return JFNK_OK;
     const EpsArgs ea = o.jv == JFNK_JV_ANALYTIC ? EpsArgs() : eps_args(c, eps_mach<T>());
     DgArgs da;
     da.H = ds(c, O_H);
@@ -627,29 +639,14 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
         }
         ++restarts;
         // true residual r = b - J x, the next cycle's (unnormalized) start vector
-        if (o.jv != JFNK_JV_ANALYTIC && (rc = fd_eps_dev<T>(c, x))) return rc;
-        if ((rc = apply_jv<T>(c, o.jv, u, x, sc(c, S_EPS), 0.0, V))) return rc;
-        JFNK_HIP(launch_lincomb<T>(V, b, V, n, 1.0, -1.0, s));
-        if ((rc = norm2_to<T>(c, V, n, sc(c, S_BETA2)))) return rc;
-        JFNK_HIP(launch_set_start(sc(c, S_BETA2), ds(c, O_G), sc(c, S_BETA), m, s));
-        if ((rc = read_scalars(c, S_BETA, 1))) return rc;
-        if (c->hscal[S_BETA] == 0.0) {
+        bool zero = false;
+        if ((rc = gmres_restart<T>(c, u, b, x, o, zero))) return rc;
+        if (zero) {
             converged = true;
             break;
         }
     }
-    if (info) {
-        info->iters = total;
-        info->restarts = restarts;
-        info->converged = converged ? 1 : 0;
-        info->res_est = res_est;
-        if (info->h_out) {
-            JFNK_HIP(hipMemcpyAsync(info->h_out, ds(c, O_HRAW), (size_t)(m + 1) * m * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-        }
-    }
-    JFNK_HIP(hipStreamSynchronize(s));
-    return converged ? JFNK_OK : JFNK_NOT_CONVERGED;
+    return gmres_end(c, info, m, total, restarts, converged, res_est);
 }
 
 // Autotuner: every compiled tile height (4, 8, 16 rows of 64 points) of the

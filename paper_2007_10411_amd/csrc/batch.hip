@@ -837,6 +837,70 @@ int b_set_kcnt(jfnk_batch* b, const std::vector<int>& k) {
     return JFNK_OK;
 }
 
+// Start of both ensemble GMRES forms over the instances with act[i] = 1: x = 0,
+// frozen coefficients, ||u_i||^2, V_0 = rhs and beta_i = ||rhs_i|| (bnorm, res);
+// instances with beta_i = 0 are done (converged).
+int b_gmres_begin(jfnk_batch* b, const float* u, const float* rhs, float* x, const jfnk_gmres_opts& o,
+                  std::vector<int>& act, std::vector<int>& conv, std::vector<double>& bnorm,
+                  std::vector<double>& res) {
+    const int ni = b->ninst;
+    hipStream_t s = b->stream;
+    int rc;
+    if ((rc = b_set_active(b, act))) return rc;
+    {
+        const BTab t = tab(b, 1, false);
+        hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
+        JFNK_HIP(hipGetLastError());
+        if (o.pc == JFNK_PC_PHYSICS) {
+            const BTab ta = tab(b, 1, true);
+            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
+            JFNK_HIP(hipGetLastError());
+        }
+    }
+    if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
+    JFNK_HIP(hipMemcpyAsync(b->V32, rhs, b->ntot * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+    if ((rc = b_read_scal(b))) return rc;
+    bnorm.assign(ni, 0.0);
+    res.assign(ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        if (!act[i]) continue;
+        bnorm[i] = b->hscal[(long long)i * S_STRIDE + SB_BETA];
+        if (!std::isfinite(bnorm[i])) {
+            set_error("non-finite right-hand side norm in the batch");
+            return JFNK_ERR_NONFINITE;
+        }
+        res[i] = bnorm[i];
+        if (bnorm[i] == 0.0) {
+            act[i] = 0;
+            conv[i] = 1;
+        }
+    }
+    return JFNK_OK;
+}
+
+// Restart of the active instances (d_active set): the true residual
+// r_i = rhs_i - J_i x_i into V_0 and beta_i = ||r_i||; r_i = 0 ends instance i.
+int b_restart_residual(jfnk_batch* b, const float* u, const float* rhs, const float* x, std::vector<int>& act,
+                       std::vector<int>& conv) {
+    const double sqrt_eps = std::sqrt(1.1920928955078125e-07);
+    hipStream_t s = b->stream;
+    int rc;
+    const BTab tr = tab(b, 1, true);
+    if ((rc = b_norm2<float>(b, x, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
+    JFNK_HIP(b_jv<float>(b, u, x, b->scal + SB_EPS, b->V32, b->tune[1 * 2 + 1]));
+    hipLaunchKernelGGL((kb_lincomb<float>), dim3(b->nchunks), dim3(kB), 0, s, tr, b->V32, rhs, b->V32, 1.0, -1.0);
+    JFNK_HIP(hipGetLastError());
+    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+    if ((rc = b_read_scal(b))) return rc;
+    for (int i = 0; i < b->ninst; ++i)
+        if (act[i] && b->hscal[(long long)i * S_STRIDE + SB_BETA] == 0.0) {
+            act[i] = 0;
+            conv[i] = 1;
+        }
+    return JFNK_OK;
+}
+
 template <typename T>
 hipError_t launch_kb_dg_dot(jfnk_batch* b, const BTab& t, int j, bool with_w) {
     const dim3 grid(b->nchunks);
@@ -919,35 +983,8 @@ int b_gmres_one_reduction(jfnk_batch* b, const float* u, const float* rhs, float
     iters.assign(ni, 0);
     conv.assign(ni, 0);
     int rc;
-    if ((rc = b_set_active(b, act))) return rc;
-    {
-        const BTab t = tab(b, 1, false);
-        hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
-        JFNK_HIP(hipGetLastError());
-        if (o.pc == JFNK_PC_PHYSICS) {
-            const BTab ta = tab(b, 1, true);
-            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
-            JFNK_HIP(hipGetLastError());
-        }
-    }
-    if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
-    JFNK_HIP(hipMemcpyAsync(b->V32, rhs, ntot * sizeof(float), hipMemcpyDeviceToDevice, s));
-    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
-    if ((rc = b_read_scal(b))) return rc;
-    std::vector<double> bnorm(ni, 0.0), res(ni, 0.0);
-    for (int i = 0; i < ni; ++i) {
-        if (!act[i]) continue;
-        bnorm[i] = b->hscal[(long long)i * S_STRIDE + SB_BETA];
-        if (!std::isfinite(bnorm[i])) {
-            set_error("non-finite right-hand side norm in the batch");
-            return JFNK_ERR_NONFINITE;
-        }
-        res[i] = bnorm[i];
-        if (bnorm[i] == 0.0) {
-            act[i] = 0;
-            conv[i] = 1;
-        }
-    }
+    std::vector<double> bnorm, res;
+    if ((rc = b_gmres_begin(b, u, rhs, x, o, act, conv, bnorm, res))) return rc;
     const BTab tall = tab(b, 1, false);
     // after the reduction that closed column `col` of every active instance:
     // count it and stop the instances that are done
@@ -1034,18 +1071,7 @@ int b_gmres_one_reduction(jfnk_batch* b, const float* u, const float* rhs, float
             if (in_cycle[i] && !conv[i] && iters[i] < max_iters && kcnt[i] == m) act[i] = 1;
         if (std::none_of(act.begin(), act.end(), [](int a) { return a; })) break;
         if ((rc = b_set_active(b, act))) return rc;
-        const BTab tr = tab(b, 1, true);
-        if ((rc = b_norm2<float>(b, x, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
-        JFNK_HIP(b_jv<float>(b, u, x, b->scal + SB_EPS, b->V32, b->tune[1 * 2 + 1]));
-        hipLaunchKernelGGL((kb_lincomb<float>), dim3(b->nchunks), dim3(kB), 0, s, tr, b->V32, rhs, b->V32, 1.0, -1.0);
-        JFNK_HIP(hipGetLastError());
-        if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
-        if ((rc = b_read_scal(b))) return rc;
-        for (int i = 0; i < ni; ++i)
-            if (act[i] && b->hscal[(long long)i * S_STRIDE + SB_BETA] == 0.0) {
-                act[i] = 0;
-                conv[i] = 1;
-            }
+        if ((rc = b_restart_residual(b, u, rhs, x, act, conv))) return rc;
     }
     JFNK_HIP(hipStreamSynchronize(s));
     return JFNK_OK;
@@ -1067,35 +1093,8 @@ int b_gmres(jfnk_batch* b, const float* u, const float* rhs, float* x, const std
     iters.assign(ni, 0);
     conv.assign(ni, 0);
     int rc;
-    if ((rc = b_set_active(b, act))) return rc;
-    {
-        const BTab t = tab(b, 1, false);
-        hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
-        JFNK_HIP(hipGetLastError());
-        if (o.pc == JFNK_PC_PHYSICS) {
-            const BTab ta = tab(b, 1, true);
-            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
-            JFNK_HIP(hipGetLastError());
-        }
-    }
-    if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
-    JFNK_HIP(hipMemcpyAsync(b->V32, rhs, ntot * sizeof(float), hipMemcpyDeviceToDevice, s));
-    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
-    if ((rc = b_read_scal(b))) return rc;
-    std::vector<double> bnorm(ni, 0.0), res(ni, 0.0);
-    for (int i = 0; i < ni; ++i) {
-        if (!act[i]) continue;
-        bnorm[i] = b->hscal[(long long)i * S_STRIDE + SB_BETA];
-        if (!std::isfinite(bnorm[i])) {
-            set_error("non-finite right-hand side norm in the batch");
-            return JFNK_ERR_NONFINITE;
-        }
-        res[i] = bnorm[i];
-        if (bnorm[i] == 0.0) {
-            act[i] = 0;
-            conv[i] = 1;
-        }
-    }
+    std::vector<double> bnorm, res;
+    if ((rc = b_gmres_begin(b, u, rhs, x, o, act, conv, bnorm, res))) return rc;
     const BTab tall = tab(b, 1, false);
     while (true) {
         if (std::none_of(act.begin(), act.end(), [](int a) { return a; })) break;
@@ -1166,18 +1165,7 @@ int b_gmres(jfnk_batch* b, const float* u, const float* rhs, float* x, const std
         // instances still active restart from the true residual
         if (std::none_of(act.begin(), act.end(), [](int a) { return a; })) break;
         if ((rc = b_set_active(b, act))) return rc;
-        const BTab tr = tab(b, 1, true);
-        if ((rc = b_norm2<float>(b, x, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
-        JFNK_HIP(b_jv<float>(b, u, x, b->scal + SB_EPS, b->V32, b->tune[1 * 2 + 1]));
-        hipLaunchKernelGGL((kb_lincomb<float>), dim3(b->nchunks), dim3(kB), 0, s, tr, b->V32, rhs, b->V32, 1.0, -1.0);
-        JFNK_HIP(hipGetLastError());
-        if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
-        if ((rc = b_read_scal(b))) return rc;
-        for (int i = 0; i < ni; ++i)
-            if (act[i] && b->hscal[(long long)i * S_STRIDE + SB_BETA] == 0.0) {
-                act[i] = 0;
-                conv[i] = 1;
-            }
+        if ((rc = b_restart_residual(b, u, rhs, x, act, conv))) return rc;
     }
     JFNK_HIP(hipStreamSynchronize(s));
     return JFNK_OK;
