@@ -150,23 +150,26 @@ def test_physics_pc(name, sweeps):
 
 @pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
 @pytest.mark.parametrize("p", [2, 3])
-@pytest.mark.parametrize("pc", ["physics", "none"])
+@pytest.mark.parametrize("pc", ["physics", "physics0", "none"])
 def test_gmres_fixed_iterations_f64(pc, p, ortho):
+    """physics0: the preconditioner's diagonal alone (no sweeps), which the
+    one-reduction form applies inside its update pass."""
     prob = I.thermal_stable_2d(96, 40).replace(dd_p=p)
     U = _state(prob, 21)
     b = I.random_vector(prob, seed=22)
     mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
-    if pc == "physics":
+    sweeps = 0 if pc == "physics0" else 2
+    if pc.startswith("physics"):
         fr = PC.frozen_coefficients(prob, U)
-        pcf = lambda r: PC.physics_pc(prob, U, r, 2, fr)
+        pcf = lambda r: PC.physics_pc(prob, U, r, sweeps, fr)
     else:
         pcf = lambda r: r
     m, iters = 8, 19                      # two restarts and a partial cycle
     xo, io = K.fgmres(mv, pcf, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
     c = _ctx(prob, max_m=m)
     x = dev(np.zeros(prob.shape))
-    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=10, tol=0.0, pc=pc, max_iters=iters, want_H=True,
-                ortho=ortho)
+    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=10, tol=0.0, pc=pc[:7] if pc != "none" else pc,
+                sweeps=sweeps, max_iters=iters, want_H=True, ortho=ortho)
     assert r.iters == iters and r.restarts == io.restarts
     assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
     k = io.H.shape[1]

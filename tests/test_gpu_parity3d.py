@@ -99,18 +99,20 @@ def test_physics_pc_3d_multiblock(name, sweeps):
     assert_fields_close(host(z32), PC.physics_pc(prob, U32, R32, sweeps=sweeps), F32_TOL, f"{name} pc{sweeps} f32")
 
 
+@pytest.mark.parametrize("sweeps", [2, 0])
 @pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
-def test_gmres_fixed_iterations_3d(ortho):
+def test_gmres_fixed_iterations_3d(ortho, sweeps):
     prob = CASES3["neutral-3d-20x12x10"]
     U = I.smooth_flow_state(prob, seed=9)
     b = I.random_vector(prob, seed=10)
     mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
     fr = PC.frozen_coefficients(prob, U)
-    xo, io = K.fgmres(mv, lambda r: PC.physics_pc(prob, U, r, 2, fr), b, m=6, tol=0.0, max_iters=11, ortho="cgs2")
+    xo, io = K.fgmres(mv, lambda r: PC.physics_pc(prob, U, r, sweeps, fr), b, m=6, tol=0.0, max_iters=11,
+                      ortho="cgs2")
     c = _ctx(prob, max_m=6)
     x = dev(np.zeros(prob.shape))
-    r = c.gmres(dev(U), dev(b), x, m=6, max_restarts=5, tol=0.0, pc="physics", max_iters=11, want_H=True,
-                ortho=ortho)
+    r = c.gmres(dev(U), dev(b), x, m=6, max_restarts=5, tol=0.0, pc="physics", sweeps=sweeps, max_iters=11,
+                want_H=True, ortho=ortho)
     assert r.iters == 11
     assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
 
