@@ -143,6 +143,19 @@ struct TileStage {
         const long long np = g.npts;
 #pragma unroll
         for (int w = 0; w < NW; ++w) neg[w] = 0u;
+        if (x0 >= H && z0 >= H && x0 + TX + H <= g.nx && z0 + TZ + H <= g.nz) {
+            // the tile and its halo lie inside the grid: no wrap, no reflection
+            const long long base = (long long)(z0 - H) * g.nx + (x0 - H);
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int idx = min((int)threadIdx.x + it * kTileThreads, N - 1);
+                const int lz = idx / SX, lx = idx - lz * SX;
+                const long long off = base + (long long)lz * g.nx + lx;
+#pragma unroll
+                for (int f = 0; f < NFL; ++f) r[it][f] = u[(long long)(f_first + f) * np + off];
+            }
+            return;
+        }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int idx = min((int)threadIdx.x + it * kTileThreads, N - 1);
