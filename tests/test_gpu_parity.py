@@ -178,6 +178,28 @@ def test_gmres_fixed_iterations_f64(pc, p, ortho):
 
 
 @pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
+@pytest.mark.parametrize("m", [1, 2])
+def test_gmres_short_cycles_f64(m, ortho):
+    """Restart lengths of one and two vectors: every cycle closes after one or two
+    columns, so each iteration of the one-reduction form is followed at once by
+    the cycle's closing reduction."""
+    prob = I.thermal_stable_2d(96, 40)
+    U = _state(prob, 23)
+    b = I.random_vector(prob, seed=24)
+    mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v))
+    fr = PC.frozen_coefficients(prob, U)
+    pcf = lambda r: PC.physics_pc(prob, U, r, 2, fr)
+    iters = 3 * m + 1
+    xo, io = K.fgmres(mv, pcf, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
+    c = _ctx(prob, max_m=m)
+    x = dev(np.zeros(prob.shape))
+    r = c.gmres(dev(U), dev(b), x, m=m, max_restarts=20, tol=0.0, pc="physics", max_iters=iters, ortho=ortho)
+    assert r.iters == iters and r.restarts == io.restarts
+    assert np.linalg.norm(host(x) - xo) <= F64_TOL * np.linalg.norm(xo)
+    assert abs(r.res_est - io.res_est) <= 1e-9 * io.res_est
+
+
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
 def test_gmres_full_cycle_of_30_f64(ortho):
     """One full cycle of m = 30: every register form of the Gram-Schmidt passes
     (up to 31 basis vectors) and the closing reduction against the oracle's CGS2."""
