@@ -7,7 +7,7 @@
  * F the spatially discrete operator of equations 1-3 (eq. 4).  Newton solves
  * J(u) du = -R(u), R(u) = L(u) - f (eq. 8), by GMRES with the Jacobian applied
  * matrix-free as the Frechet derivative of R (eq. 9), right-preconditioned by the
- * physics-based field-block preconditioner (section 2.5.1).
+ * physics-based field-block preconditioner (section 2.5.2).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -136,6 +136,10 @@ typedef struct {
     double* h_out;             /* optional HOST buffer of (m+1)*m doubles, row-major:
                                   receives the Hessenberg of the last cycle before the
                                   Givens rotations (NULL: not returned)                  */
+    int32_t fallback;          /* 1: the physics-based preconditioner produced x although
+                                  the learned one was asked for (see jfnk_gmres)         */
+    double res_true;           /* ||rhs - J x|| of the returned x (jfnk_gmres only; -1
+                                  where not computed)                                    */
 } jfnk_gmres_info;
 
 typedef struct {
@@ -178,7 +182,7 @@ int jfnk_set_stream(jfnk_ctx* ctx, void* hip_stream);
 /* f = 2 u^n / dt + F(u^n)   (equation 5, right-hand side).  FP64.               */
 int jfnk_rhs(jfnk_ctx* ctx, const double* u_n, double* f);
 
-/* R = 2 u / dt - F(u) - f   (section 2.5.1, R = L(u) - f).  FP64.  f may be NULL
+/* R = 2 u / dt - F(u) - f   (sections 2.5 and 2.5.1, R = L(u) - f).  FP64.  f may be NULL
  * (treated as zero).                                                             */
 int jfnk_residual(jfnk_ctx* ctx, const double* u, const double* f, double* R);
 
@@ -192,7 +196,7 @@ int jfnk_apply_F(jfnk_ctx* ctx, jfnk_dtype dt, int32_t what, const void* u, cons
 int jfnk_jv(jfnk_ctx* ctx, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v,
             double eps, void* Jv);
 
-/* z ~ P(u)^{-1} r, the physics-based preconditioner (section 2.5.1): field-block
+/* z ~ P(u)^{-1} r, the physics-based preconditioner (section 2.5.2): field-block
  * diagonal of L with u frozen, 2/dt + C(u; .) - D.(K D .), applied by Jacobi
  * sweeps (z0 = r/d, z <- z + (r - P z)/d).  JFNK_PC_NONE copies r.  u, r, z share
  * the dtype; r and z must not alias.                                             */
@@ -201,13 +205,25 @@ int jfnk_precond_apply(jfnk_ctx* ctx, jfnk_pc_kind pc, jfnk_dtype dt, const void
 
 /* Right-preconditioned flexible restarted GMRES(m) (Saad and Schultz) for
  * J(u) x = rhs with x0 = 0, the Arnoldi step of o->ortho (jfnk_ortho), Givens
- * rotations and back substitution in FP64.  x is output only.                    */
+ * rotations and back substitution in FP64.  x is output only.  info->res_true
+ * receives the true residual of x (one more Jv).
+ * The learned preconditioner (FP32 only, parameters set) is judged by the
+ * physics-based one (section 2.5.2): it runs only when a physics-preconditioned
+ * solve of this context is on record and stops at the end of the first cycle
+ * whose mean log residual reduction per iteration falls short of that solve's;
+ * the system is then solved with the physics-based preconditioner, as it is when
+ * no record exists or the learned solve does not converge (info->fallback = 1).
+ * Every converged physics-preconditioned solve (here or inside
+ * jfnk_newton_step) updates the record.                                          */
 int jfnk_gmres(jfnk_ctx* ctx, jfnk_dtype dt, const void* u, const void* rhs, void* x,
                const jfnk_gmres_opts* opts, jfnk_gmres_info* info);
 
 /* One trapezoidal step by inexact Newton (equation 8): u_np1 holds the initial
  * guess on entry (usually a copy of u_n) and the solution on return.  FP64 outer
- * residual, update and norms; inner Krylov solve in opts->inner.                  */
+ * residual, update and norms; inner Krylov solve in opts->inner, each judged as in
+ * jfnk_gmres when the learned preconditioner is asked for (info->fallbacks counts
+ * the solves the physics-based one took over; the learned attempts' iterations
+ * count in gmres_iters_total).                                                    */
 int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
                      const jfnk_newton_opts* opts, jfnk_newton_info* info);
 
@@ -249,7 +265,7 @@ int jfnk_timing_enable(jfnk_ctx* ctx, int32_t enable);
 int jfnk_timing_read(jfnk_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches,
                      double* bytes);
 
-/* ---- nonlinear physics-based preconditioning (section 2.5.1) ----------------
+/* ---- nonlinear physics-based preconditioning (section 2.5.2) ----------------
  * The preconditioned system R~(u) = u - P^{-1}(u)[f - L(u) + P(u)u], with the
  * preconditioning operator acting on u inside the bracket, is
  * R~(u) = P^{-1}(u) R(u): P^{-1}(u) is the physics-based field-block
@@ -276,7 +292,7 @@ int jfnk_nlpc_step(jfnk_ctx* ctx, const double* u_n, double* u_np1, const jfnk_n
  * conv(16->n_f), zero padding, exact (erf) GELU.  2D: 3x3 kernels with a
  * dilation d_l per layer (taps at d_l (-1, 0, 1); dilations 1, 2, 4, 8 give a
  * dense 31 x 31 receptive field).  3D: 3x3x3 kernels, dilation 1.  An approximate
- * inverse of J in the spirit of the paper's cheap preconditioners (section 2.5.1);
+ * inverse of J in the spirit of the paper's cheap preconditioners (section 2.5.2);
  * nonlinear in r, hence used inside the flexible GMRES.  Parameters: one flat
  * FP32 vector, per layer W[co][ci][kz][kx] (2D) or W[co][ci][kz][ky][kx] (3D),
  * tap offset (kz-1, ...), then b[co].
@@ -310,9 +326,15 @@ int jfnk_net_set_loss(jfnk_ctx* ctx, int32_t kind);
 int jfnk_net_loss_grad(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, double* loss,
                        float* grad_host);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on that loss;
- * loss receives the loss before the step (host double, may be NULL).            */
-int jfnk_net_train_step(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, float lr,
-                        double* loss);
+ * loss receives the loss before the step (host double, may be NULL).
+ * crop_dims (HOST, 3 entries nx, ny, nz, or NULL for the context's grid): the
+ * pairs are crops of that size, each vector [n_f][nz][ny][nx] (a convolution does
+ * not depend on the domain it slides over, so a network trained on crops applies
+ * to the full grid); every entry must be within the context's grid (ny = 1 in
+ * 2D) and at least 1, and crops take the solution-space loss only.  Errors:
+ * JFNK_ERR_ARG.                                                                  */
+int jfnk_net_train_step(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, const int32_t* crop_dims,
+                        float lr, double* loss);
 
 /* ---- batched ensemble (2D) ------------------------------------------------
  * Independent problems of uneven grid sizes solved together: every stage of the

@@ -9,7 +9,7 @@ library: the two share no code.  Inputs reach both from the seeded generators in
 Modules:
   stencil  - Deslauriers-Dubuc derivative stencil from the refinement relation (section 2.3)
   model    - F(u), R(u), f(u^n), Jv (equations 1-5 and 9, sections 2.2-2.5)
-  precond  - physics-based field-block preconditioner (section 2.5.1)
+  precond  - physics-based field-block preconditioner (section 2.5.2)
   krylov   - flexible restarted GMRES and inexact Newton (section 2.5.1, equation 8)
   net      - the learned convolutional preconditioner, forward and backward, FP64
 """

@@ -236,7 +236,7 @@ def stress(S, nu):
 
 
 # --------------------------------------------------------------------------- #
-# Anisotropic exchange coefficients (section 2.3, Eq. 7, after Deardorff)
+# Anisotropic exchange coefficients (section 2.4, Eq. 7, after Deardorff)
 # --------------------------------------------------------------------------- #
 def deardorff_coefficients(prob, S):
     """Eq. 7: K_m = C_s^(4/3) eps^(1/3) (dx dy)^(2/3), K_M = C_s^(4/3) eps^(1/3) dz^(4/3)

@@ -4,7 +4,7 @@ network, its exact gradient and one Adam step, in FP64.
 ORACLE - test infrastructure only.  Plain numpy loops over the 3 x 3 (2D) or
 3 x 3 x 3 (3D) taps.
 
-The paper's preconditioning discussion (section 2.5.1) motivates approximating
+The paper's preconditioning discussion (section 2.5.2) motivates approximating
 J^{-1} cheaply; the network form follows the design of this project:
 
     z = (dt/2) r + s N(r / s),       s = RMS of r over all fields and points

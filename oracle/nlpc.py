@@ -1,4 +1,4 @@
-"""Physics-based nonlinear preconditioning (section 2.5.1).
+"""Physics-based nonlinear preconditioning (section 2.5.2).
 
 ORACLE - test infrastructure only.  Plain FP64 numpy on top of the model, the
 physics-based preconditioner and the GMRES of this package.

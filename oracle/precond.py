@@ -1,4 +1,4 @@
-"""Physics-based preconditioner (section 2.5.1): keep each field's own diagonal
+"""Physics-based preconditioner (section 2.5.2): keep each field's own diagonal
 block of L(u) = 2u/dt - F(u) and drop the coupling between fields.
 
 ORACLE - test infrastructure only.

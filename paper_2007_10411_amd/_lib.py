@@ -48,7 +48,8 @@ class GmresOpts(C.Structure):
 
 class GmresInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
-                ("res0", C.c_double), ("res_est", C.c_double), ("h_out", C.POINTER(C.c_double))]
+                ("res0", C.c_double), ("res_est", C.c_double), ("h_out", C.POINTER(C.c_double)),
+                ("fallback", C.c_int32), ("res_true", C.c_double)]
 
 
 class NewtonOpts(C.Structure):
@@ -102,7 +103,7 @@ def load():
     L.jfnk_nlpc_residual.argtypes = [vp, vp, vp, vp, C.c_int32]
     L.jfnk_nlpc_step.argtypes = [vp, vp, vp, C.POINTER(NewtonOpts), C.c_int32, C.POINTER(NewtonInfo)]
     L.jfnk_net_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]
-    L.jfnk_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.POINTER(C.c_double)]
+    L.jfnk_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_int32), C.c_float, C.POINTER(C.c_double)]
     L.jfnk_tune.argtypes = [vp, C.POINTER(C.c_int32)]
     L.jfnk_set_variant.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.jfnk_batch_create.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, vp, C.POINTER(vp)]

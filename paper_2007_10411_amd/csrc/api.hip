@@ -357,6 +357,20 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
     return JFNK_OK;
 }
 
+// Judge of a learned-preconditioner solve (c->judge_active < 0 while one runs):
+// at the end of a cycle that has not converged, the mean log reduction of the
+// residual estimate per iteration so far must reach the physics-based
+// preconditioner's (section 2.5.2) on record; a solve that falls short stops
+// there (c->judged_out) so that the caller can hand the system to the physics-based
+// preconditioner after at most one cycle.
+bool judged_short(jfnk_ctx* c, double res_est, double bnorm, int total) {
+    if (!(c->judge_active < 0.0) || total < 1 || !(bnorm > 0.0)) return false;
+    const double rate = res_est > 0.0 ? std::log(res_est / bnorm) / total : -INFINITY;
+    if (rate <= c->judge_active) return false;
+    c->judged_out = true;
+    return true;
+}
+
 // Start of both GMRES forms: frozen coefficients, ||u||^2, x = 0, V_0 = rhs and
 // beta = ||rhs|| (g = beta e_1, beta also on the host).  bnorm = 0: nothing
 // to solve (info says converged).
@@ -527,6 +541,7 @@ int gmres_impl(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gmres_opts&
             converged = res_est <= o.tol * bnorm;
             break;
         }
+        if (judged_short(c, res_est, bnorm, total)) break;
         ++restarts;
         // true residual r = b - J x
         bool zero = false;
@@ -637,6 +652,7 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
             converged = res_est <= o.tol * bnorm;
             break;
         }
+        if (judged_short(c, res_est, bnorm, total)) break;
         ++restarts;
         // true residual r = b - J x, the next cycle's (unnormalized) start vector
         bool zero = false;
@@ -647,6 +663,39 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
         }
     }
     return gmres_end(c, info, m, total, restarts, converged, res_est);
+}
+
+// Krylov solve of J(u) x = b with the preconditioner of go.pc.  The learned
+// preconditioner is judged by the physics-based one (section 2.5.2): it runs
+// only when a physics-preconditioned solve of this context is on record, and
+// stops at the end of the first cycle whose mean log residual reduction per
+// iteration falls short of that solve's; the system is then solved again with
+// the physics-based preconditioner, as it is when no record exists or the
+// learned solve does not converge (gi->fallback = 1, the learned attempt's
+// iterations added to *spent).  Every physics-preconditioned solve that
+// converges updates the record.
+template <typename T>
+int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, jfnk_gmres_info* gi, int* spent) {
+    gi->fallback = 0;
+    gi->res_true = -1.0;
+    if (go.pc == JFNK_PC_LEARNED) {
+        if (c->judge_rate < 0.0) {
+            c->judge_active = c->judge_rate;
+            c->judged_out = false;
+            const int rc = gmres_impl<T>(c, u, b, x, go, gi);
+            c->judge_active = 0.0;
+            if (rc < 0 || (rc == JFNK_OK && !c->judged_out)) return rc;
+            if (spent) *spent += gi->iters;
+        }
+        gi->fallback = 1;
+        go.pc = JFNK_PC_PHYSICS;
+    }
+    const int fb = gi->fallback;
+    const int rc = gmres_impl<T>(c, u, b, x, go, gi);
+    gi->fallback = fb;
+    if (rc == JFNK_OK && go.pc == JFNK_PC_PHYSICS && gi->iters > 0 && gi->res0 > 0.0 && gi->res_est > 0.0)
+        c->judge_rate = std::log(gi->res_est / gi->res0) / gi->iters;
+    return rc;
 }
 
 // Autotuner: every compiled tile height (4, 8, 16 rows of 64 points) of the
@@ -1011,10 +1060,30 @@ int jfnk_gmres(jfnk_ctx* c, jfnk_dtype dt, const void* u, const void* rhs, void*
         if (c && o) set_error(std::string("invalid argument to jfnk_gmres: ") + jfnk_last_error());
         return JFNK_ERR_ARG;
     }
-    if (dt == JFNK_F64) return gmres_impl<double>(c, (const double*)u, (const double*)rhs, (double*)x, *o, info);
-    if (dt == JFNK_F32) return gmres_impl<float>(c, (const float*)u, (const float*)rhs, (float*)x, *o, info);
-    set_error("invalid dtype");
-    return JFNK_ERR_ARG;
+    if (dt != JFNK_F64 && dt != JFNK_F32) {
+        set_error("invalid dtype");
+        return JFNK_ERR_ARG;
+    }
+    if (o->pc == JFNK_PC_LEARNED && (dt != JFNK_F32 || !c->net.ready)) {
+        set_error("the learned preconditioner needs FP32 and parameters set (jfnk_net_set_params)");
+        return JFNK_ERR_ARG;
+    }
+    jfnk_gmres_info local{};
+    jfnk_gmres_info* gi = info ? info : &local;
+    // the true residual ||rhs - J x|| of the returned x (the same Jv as the solve)
+    auto finish = [&](auto zero_t, int rc) -> int {
+        using T = decltype(zero_t);
+        if (rc < 0) return rc;
+        bool zero = false;
+        int r2 = gmres_restart<T>(c, (const T*)u, (const T*)rhs, (const T*)x, *o, zero);
+        if (r2) return r2;
+        gi->res_true = c->hscal[S_BETA];
+        return rc;
+    };
+    if (dt == JFNK_F64)
+        return finish(double(0), krylov_solve<double>(c, (const double*)u, (const double*)rhs, (double*)x, *o, gi,
+                                                      nullptr));
+    return finish(float(0), krylov_solve<float>(c, (const float*)u, (const float*)rhs, (float*)x, *o, gi, nullptr));
 }
 
 int jfnk_norm(jfnk_ctx* c, jfnk_dtype dt, const void* x, int64_t n, double* out) {
@@ -1111,7 +1180,7 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
         jfnk_gmres_info gi{};
         if (o->inner == JFNK_F64) {
             JFNK_HIP(launch_cast<double, double>(c->b64, c->R64, n, -1.0, s));
-            rc = gmres_impl<double>(c, u, c->b64, c->x64, go, &gi);
+            rc = krylov_solve<double>(c, u, c->b64, c->x64, go, &gi, nullptr);
             if (rc < 0) return rc;
             if (rec_sys && *o->rec_count < o->rec_cap) {
                 const long long off = (long long)(*o->rec_count) * n;
@@ -1123,14 +1192,8 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
         } else {
             JFNK_HIP(launch_cast<float, double>(c->u32, u, n, 1.0, s));
             JFNK_HIP(launch_cast<float, double>(c->b32, c->R64, n, -1.0, s));
-            rc = gmres_impl<float>(c, c->u32, c->b32, c->x32, go, &gi);
-            if (go.pc == JFNK_PC_LEARNED && rc != JFNK_OK) {
-                // the learned preconditioner failed this solve: redo it with the physics-based one
-                inf.fallbacks++;
-                inf.gmres_iters_total += gi.iters;
-                go.pc = JFNK_PC_PHYSICS;
-                rc = gmres_impl<float>(c, c->u32, c->b32, c->x32, go, &gi);
-            }
+            rc = krylov_solve<float>(c, c->u32, c->b32, c->x32, go, &gi, &inf.gmres_iters_total);
+            if (go.pc == JFNK_PC_LEARNED && gi.fallback) inf.fallbacks++;
             if (rc < 0) return rc;
             if (rec_sys && *o->rec_count < o->rec_cap) {
                 const long long off = (long long)(*o->rec_count) * n;
@@ -1433,18 +1496,20 @@ int jfnk_net_apply(jfnk_ctx* c, int32_t bf16, const float* r, float* z) {
     return JFNK_OK;
 }
 
-static int net_batch_grad(jfnk_ctx* c, const float* r, const float* du, int32_t batch, double* loss) {
+// Loss and gradient over a batch of pairs on the grid nx x ny x nz (the context's
+// or a crop of it, see jfnk_net_train_step).
+static int net_batch_grad(jfnk_ctx* c, const float* r, const float* du, int32_t batch, double* loss, int nx, int ny,
+                          int nz) {
     NetBuffers& nb = c->net;
     const float hdt = (float)(0.5 * c->prob.dt);
+    const long long nvec = (long long)c->nf * nx * ny * nz;
     for (int b = 0; b < batch; ++b) {
-        const float* rb = r + (long long)b * c->n;
-        const float* db = du + (long long)b * c->n;
+        const float* rb = r + (long long)b * nvec;
+        const float* db = du + (long long)b * nvec;
         if (nb.dim == 3)
-            JFNK_HIP(net3_pair_grad(nb, c->geo.nx, c->geo.ny, c->geo.nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0,
-                                    c->stream));
+            JFNK_HIP(net3_pair_grad(nb, nx, ny, nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0, c->stream));
         else
-            JFNK_HIP(net_pair_grad(nb, c->geo.nx, c->geo.nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0, c->geo,
-                                   c->stream));
+            JFNK_HIP(net_pair_grad(nb, nx, nz, c->nf, hdt, rb, db, 1.0 / batch, b == 0, c->geo, c->stream));
     }
     if (loss) {
         JFNK_HIP(hipMemcpyAsync(loss, nb.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1471,7 +1536,7 @@ int jfnk_net_loss_grad(jfnk_ctx* c, const float* r, const float* du, int32_t bat
         set_error("invalid argument to jfnk_net_loss_grad");
         return JFNK_ERR_ARG;
     }
-    int rc = net_batch_grad(c, r, du, batch, loss);
+    int rc = net_batch_grad(c, r, du, batch, loss, c->geo.nx, c->geo.ny, c->geo.nz);
     if (rc) return rc;
     if (grad) {
         JFNK_HIP(hipMemcpyAsync(grad, c->net.grad, c->net.nparam * sizeof(float), hipMemcpyDeviceToHost, c->stream));
@@ -1480,12 +1545,25 @@ int jfnk_net_loss_grad(jfnk_ctx* c, const float* r, const float* du, int32_t bat
     return JFNK_OK;
 }
 
-int jfnk_net_train_step(jfnk_ctx* c, const float* r, const float* du, int32_t batch, float lr, double* loss) {
+int jfnk_net_train_step(jfnk_ctx* c, const float* r, const float* du, int32_t batch, const int32_t* crop_dims,
+                        float lr, double* loss) {
     if (!net_ok(c) || !r || !du || batch < 1 || !(lr > 0) || !c->net.ready) {
         set_error("invalid argument to jfnk_net_train_step");
         return JFNK_ERR_ARG;
     }
-    int rc = net_batch_grad(c, r, du, batch, loss);
+    int nx = c->geo.nx, ny = c->geo.ny, nz = c->geo.nz;
+    if (crop_dims) {
+        nx = crop_dims[0];
+        ny = crop_dims[1];
+        nz = crop_dims[2];
+        const bool whole = nx == c->geo.nx && ny == c->geo.ny && nz == c->geo.nz;
+        if (nx < 1 || ny < 1 || nz < 1 || nx > c->geo.nx || ny > c->geo.ny || nz > c->geo.nz ||
+            (c->prob.dim == 2 && ny != 1) || (!whole && c->net.loss_kind != NET_LOSS_SOLUTION)) {
+            set_error("invalid crop_dims for jfnk_net_train_step (within the grid, ny = 1 in 2D, solution loss)");
+            return JFNK_ERR_ARG;
+        }
+    }
+    int rc = net_batch_grad(c, r, du, batch, loss, nx, ny, nz);
     if (rc) return rc;
     c->net.adam_t++;
     JFNK_HIP(net_adam(c->net, c->net.nparam, c->net.adam_t, lr, c->stream));

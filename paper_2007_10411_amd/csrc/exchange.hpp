@@ -1,4 +1,4 @@
-// Anisotropic exchange coefficients (section 2.3, Eq. 7) shared by the 2D and
+// Anisotropic exchange coefficients (section 2.4, Eq. 7) shared by the 2D and
 // 3D stencil kernels.  With eps^(1/3) = (cs Delta)^(2/3) 2^(1/6) |S| every
 // coefficient is linear in |S| = sqrt(S:S) below the mixing-length cap:
 //   K_m = dd_ah |S|, K_M = dd_av |S|, l = min(dd_b |S|, dd_delta),

@@ -201,6 +201,13 @@ struct jfnk_ctx {
     jfnk::Timing timing;
     jfnk::NetBuffers net;
     int fallbacks = 0;
+    // physics-based preconditioner as the judge of the learned one: mean log
+    // residual reduction per Krylov iteration of the last physics-preconditioned
+    // solve of this context (0: none on record), the bound a running learned
+    // solve is held to (0: none) and whether it fell short
+    double judge_rate = 0.0;
+    double judge_active = 0.0;
+    bool judged_out = false;
     // tile variant per stencil stage, chosen by jfnk_tune (index: stage * 2 + (FP32 ? 1 : 0);
     // stages 0 residual / F, 1 Jv, 2 preconditioner sweep)
     int tune[6] = {1, 1, 1, 1, 1, 1};

@@ -49,6 +49,8 @@ class GmresResult:
     res0: float
     res_est: float
     H: np.ndarray = None
+    fallback: bool = False
+    res_true: float = -1.0
 
 
 @dataclass
@@ -136,7 +138,8 @@ class Context:
         L.check(self.lib.jfnk_gmres(self.h, _dcode(u), _ptr(u), _ptr(b), _ptr(x), C.byref(o), C.byref(info)),
                 "jfnk_gmres")
         H = np.ctypeslib.as_array(Hbuf).reshape(m + 1, m).copy() if want_H else None
-        return GmresResult(info.iters, info.restarts, bool(info.converged), info.res0, info.res_est, H)
+        return GmresResult(info.iters, info.restarts, bool(info.converged), info.res0, info.res_est, H,
+                           bool(info.fallback), info.res_true)
 
     def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, inner="f64",
                     m=30, max_restarts=20, pc="physics", jv="stable", sweeps=2, forcing="ew", eta=1e-2,
@@ -237,10 +240,14 @@ class Context:
                 "jfnk_net_loss_grad", soft_ok=False)
         return loss.value, g
 
-    def net_train_step(self, R, DU, lr):
-        batch = R.numel() // self.n
+    def net_train_step(self, R, DU, lr, crop=None):
+        """One Adam step on the pairs (R, DU); crop = (nx, ny, nz) when they are
+        crops of that size rather than vectors of the context's grid."""
+        nvec = self.n if crop is None else self.prob.nf * int(crop[0]) * int(crop[1]) * int(crop[2])
+        batch = R.numel() // nvec
         loss = C.c_double()
-        L.check(self.lib.jfnk_net_train_step(self.h, _ptr(R), _ptr(DU), batch, float(lr), C.byref(loss)),
+        cd = None if crop is None else (C.c_int32 * 3)(*[int(x) for x in crop])
+        L.check(self.lib.jfnk_net_train_step(self.h, _ptr(R), _ptr(DU), batch, cd, float(lr), C.byref(loss)),
                 "jfnk_net_train_step", soft_ok=False)
         return loss.value
 

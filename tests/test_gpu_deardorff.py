@@ -1,4 +1,4 @@
-"""GPU parity of the anisotropic exchange coefficients (section 2.3, Eq. 7)
+"""GPU parity of the anisotropic exchange coefficients (section 2.4, Eq. 7)
 against the FP64 oracle: F and the residual, the stable and analytic Jv, the
 physics preconditioner with the frozen anisotropic coefficients, a GMRES run
 and a Newton step; 2D tile and row-marching kernels and the 3D z-marching

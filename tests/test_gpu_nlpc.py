@@ -1,4 +1,4 @@
-"""Nonlinear physics-based preconditioning (section 2.5.1) on the GPU against the
+"""Nonlinear physics-based preconditioning (section 2.5.2) on the GPU against the
 FP64 oracle: R~ = P^{-1}(u) R(u) per field, Newton-Krylov on R~ reaching the
 oracle's solution, the fixed-point iteration iterate for iterate, and a timed
 comparison with the plain Newton step."""

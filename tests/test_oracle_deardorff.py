@@ -1,4 +1,4 @@
-"""Pins of the oracle's anisotropic exchange coefficients (section 2.3, Eq. 7).
+"""Pins of the oracle's anisotropic exchange coefficients (section 2.4, Eq. 7).
 
 Closed forms the formula must reduce to: on a grid with equal spacings the
 coefficients are a fixed multiple of the Smagorinsky viscosity (the exponents

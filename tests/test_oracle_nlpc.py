@@ -1,4 +1,4 @@
-"""Pins of the nonlinear physics-based preconditioning (section 2.5.1): R~ has
+"""Pins of the nonlinear physics-based preconditioning (section 2.5.2): R~ has
 the roots of R, Newton-Krylov on R~ reaches the plain Newton solution, for a
 linear operator without closure R~ is (dt/2) R exactly (the block preconditioner
 is then (dt/2) I) and its finite-difference Jacobian is (dt/2) J, and the fixed

@@ -1,7 +1,7 @@
 """Pins of the oracle's GMRES, Newton and physics preconditioner: full GMRES
 against a dense LU solve, residual estimates against true residuals, MGS against
 CGS2, quadratic Newton convergence with exact Jacobian solves, and the
-block-diagonal structure of the preconditioner (section 2.5.1)."""
+block-diagonal structure of the preconditioner (section 2.5.2)."""
 import numpy as np
 import pytest
 
