@@ -1,56 +1,47 @@
 """Benchmark of the JFNK hot path on one MI355X.
 
-Workload: the 2D dry thermal in a stably stratified atmosphere, 1024 x 512 grid
-over 20 x 10 km, N = 0.01 1/s, +2 K bubble, dt = 1 s, Smagorinsky closure.  One
-step = one trapezoidal implicit step solved by inexact Newton (Eisenstat-Walker
-forcing) to a relative residual of 1e-8, FGMRES(30).
+Headline workload: the 3D neutral dry thermal, 256 x 256 x 128 points over
+20 x 20 x 10 km (78.125 m spacing), +2 K cosine-squared bubble of radius 2 km
+at (10, 10, 2) km, dt = 2 s, Smagorinsky closure, free-slip walls.  One step =
+one trapezoidal implicit step solved by inexact Newton (Eisenstat-Walker
+forcing) to a relative residual of 1e-8 with FGMRES(30).
 
-The physics-based preconditioner of the timed legs applies its field-block
-diagonal with --pc-sweeps Jacobi sweeps (default 0): on this workload the GMRES
-iteration count is the same for 0 to 8 sweeps (the acoustic coupling between
-fields, which no field block holds, sets it), so each sweep only adds time.
-
-The Krylov solve of the timed legs uses the one-reduction Arnoldi step
-(--ortho, jfnk_ortho): two passes over the basis per iteration instead of the
-three of classical Gram-Schmidt applied twice, equal to it in exact arithmetic.
-
-Legs, all from the same state after the warm-up steps:
+Legs at that size, each from the same state after the warm-up steps:
   mixed     FP32 Krylov / Jv, physics-based preconditioner, FP64 Newton   (timed leg)
   plain     FP64 everywhere, physics-based preconditioner
-  mixed_pc_sweeps2  the mixed leg with two preconditioner sweeps (the source of
-            roofline_pc, whose kernels the timed legs launch without sweeps)
-  mixed_cgs2  the mixed leg with the CGS2 Arnoldi step
-  ensemble  one mixed step of the 64-instance heat-island ensemble (3.93 M points,
-            uneven grids), reported in config.ensemble_64_heat_island
-  learned   FP32 Krylov / Jv, learned BF16-MFMA right preconditioner, FP64 Newton;
-            the network is trained first on pairs the solver generates on this
-            workload (training time reported, not timed with the steps)
-  mixed_p3  the mixed leg with the 9-point (p = 3) derivative
-  mixed_deardorff  the mixed leg with the anisotropic exchange coefficients (Eq. 7)
-  mixed_3d_256x256x128  the mixed leg on the 3D neutral thermal (20 x 20 x 10 km, dt = 2 s)
-Each context is autotuned (tile or row-marching launch shapes) before its steps.
-A second learned comparison runs on the same thermal at 256 x 128, where the
-acoustic CFL number is a quarter of the full grid's.
+  learned   FP32 Krylov / Jv, learned BF16-MFMA 3x3x3 right preconditioner judged
+            by the physics-based one, FP64 Newton; the network is trained first on
+            crops of solver pairs from this workload and from the 2D thermal at the
+            same spacing and time step (training reported, not timed with the steps)
+The physics-based preconditioner applies its field-block diagonal with
+--pc-sweeps Jacobi sweeps (default 0: on these workloads the sweeps leave the
+GMRES iteration count unchanged).  The Krylov solves use the one-reduction
+Arnoldi step (--ortho).
+
+Further legs (config.legs_2d, config.learned_256x128, config.ensemble_64_heat_island):
+the 2D stable thermal at 1024 x 512 (mixed and plain), the trained 2D network
+against the physics preconditioner at 256 x 128, and one mixed step of the
+64-instance heat-island ensemble.
 
 Printed JSON line:
-  value          whole-job Jv throughput of the timed leg: grid points x Jv
-                 evaluations / wall time of the timed steps [Gpoint-residuals/s]
+  value          Jv throughput of the timed leg: grid points x Jv evaluations /
+                 summed Jv kernel time (HIP events on the context stream around
+                 every Jv launch of the steps) [Gpoint-residuals/s]
   ms_per_step    wall time per implicit step of the timed leg
   roofline       the dominant kernel class of the timed leg (algorithmic bytes over
                  the summed HIP-event time of its launches) against 8 TB/s HBM;
-                 roofline_jv for the Jv kernel, roofline_pc for the preconditioner
-                 (from mixed_pc_sweeps2), roofline_net for the network.
-                 Each leg runs its steps twice from the same state: the wall time
-                 above comes from the run without instrumentation, the per-class
-                 HIP events from the second run (their packets add ~20% to a step)
-  cpu_baseline   the FP64 oracle on a bounded sample of the same workload
+                 roofline_jv for the Jv kernel, roofline_pc for the preconditioner,
+                 roofline_net for the network.  Each leg runs its steps twice from
+                 the same state: the wall time comes from the run without events,
+                 the kernel-class times from the second run.
+  cpu_baseline   the FP64 oracle's Jv on a bounded sample of the same workload (the
+                 lowest planes of the grid), on all host cores (one process per
+                 core) and on one
 
-kernel_micro   the residual, Jv and physics-preconditioner kernels alone on grids
-               whose vectors exceed the 256 MB Infinity Cache (2D 8192 x 8192, p = 2
-               and 3, 3D 256 x 256 x 128), FP32 and FP64: per-launch HIP-event time,
-               algorithmic bytes (residual and Jv: read u and v or f, write the
-               result, 3 n_f w per point; preconditioner: the library's per-launch
-               count of its diagonal start and sweeps) and the HBM fraction
+kernel_micro   the residual, Jv and physics-preconditioner kernels alone (3D
+               256 x 256 x 128 and 2D 8192 x 8192, vectors beyond the Infinity Cache),
+               FP32 and FP64: per-launch HIP-event time, algorithmic bytes and
+               the HBM fraction
 
 --copy-probe GIB runs only a device-to-device copy of GIB GiB (the calibration
 kernel for the hardware byte counters) and prints its size and time.
@@ -73,6 +64,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+ALL_LEGS = "mixed,plain,learned,2d,learned2d,ensemble"
 
 
 def parse():
@@ -81,24 +73,22 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--learned-steps", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--learned-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--legs", default="mixed,plain,sweeps2,cgs2,learned,p3,deardorff,3d,ensemble")
+    ap.add_argument("--legs", default=ALL_LEGS)
     ap.add_argument("--ortho", default="one_reduction", choices=["one_reduction", "cgs2"],
-                    help="Gram-Schmidt form of the Arnoldi step in the timed legs (the cgs2 leg repeats the timed "
-                         "configuration with CGS2)")
+                    help="Gram-Schmidt form of the Arnoldi step in the timed legs")
     ap.add_argument("--pc-sweeps", type=int, default=0,
                     help="Jacobi sweeps of the physics preconditioner in the timed legs (0: its field-block "
-                         "diagonal alone; the sweeps2 leg repeats the timed configuration with 2)")
-    ap.add_argument("--train-iters", type=int, default=1500)
-    ap.add_argument("--nx", type=int, default=1024)
-    ap.add_argument("--nz", type=int, default=512)
+                         "diagonal alone)")
+    ap.add_argument("--train-iters", type=int, default=600)
+    ap.add_argument("--train-iters-2d", type=int, default=1500)
     ap.add_argument("--copy-probe", type=float, default=0.0)
     ap.add_argument("--micro-only", action="store_true")
-    ap.add_argument("--pin", default="", help="launch shapes pinned over the autotuner on the timed "
-                    "context, e.g. 'f32_jv=8,f32_pc_sweep=4' (rows per workgroup)")
+    ap.add_argument("--pin", default="", help="launch shapes pinned over the autotuner on the 2D "
+                    "contexts, e.g. 'f32_jv=8,f32_pc_sweep=4' (rows per workgroup)")
     ap.add_argument("--micro-pin", default="", help="the same for the 2D micro-benchmark contexts")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--micro-reps", type=int, default=20)
@@ -126,8 +116,7 @@ def run_steps(ctx, u, k, torch, **opts):
 def timed_leg(ctx, u0, k, torch, L, classes, **opts):
     """k steps from u0, twice: the wall time comes from a run without
     instrumentation; a second run of the same steps from the same state records
-    HIP events around every launch of the given kernel classes (the event
-    packets themselves cost about a fifth of the step time at 1024 x 512)."""
+    HIP events around every launch of the given kernel classes."""
     u = u0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -141,61 +130,96 @@ def timed_leg(ctx, u0, k, torch, L, classes, **opts):
     torch.cuda.synchronize()
     ctx.timing(mask)
     t0 = time.perf_counter()
-    run_steps(ctx, ui, k, torch, **opts)
+    infos_i = run_steps(ctx, ui, k, torch, **opts)
     torch.cuda.synchronize()
     wall_i = time.perf_counter() - t0
     tm = {name: ctx.timing_read(c) for name, c in classes.items()}    # (ms, launches, bytes or flops)
     ctx.timing(0)
     del ui
-    return {"wall": wall, "wall_instrumented": wall_i, "infos": infos, "tm": tm, "u": u}
+    return {"wall": wall, "wall_instrumented": wall_i, "infos": infos, "infos_instrumented": infos_i, "tm": tm,
+            "u": u}
 
 
-def per_step(leg):
+def per_step(leg, npts=None):
     k = len(leg["infos"])
-    return {"ms_per_step": leg["wall"] / k * 1e3,
-            "newton_iters_per_step": sum(r.newton_iters for r in leg["infos"]) / k,
-            "gmres_iters_per_step": sum(r.gmres_iters_total for r in leg["infos"]) / k,
-            "fallbacks": sum(r.fallbacks for r in leg["infos"]),
-            "ms_per_step_instrumented": leg["wall_instrumented"] / k * 1e3,
-            "kernel_ms_per_step": {c: v[0] / k for c, v in leg["tm"].items()}}
+    nn = sum(r.newton_iters for r in leg["infos"])
+    ng = sum(r.gmres_iters_total for r in leg["infos"])
+    out = {"ms_per_step": leg["wall"] / k * 1e3,
+           "newton_iters_per_step": nn / k,
+           "gmres_iters_per_step": ng / k,
+           "gmres_iters_per_newton_iter": ng / max(nn, 1),
+           "fallbacks": sum(r.fallbacks for r in leg["infos"]),
+           "ms_per_step_instrumented": leg["wall_instrumented"] / k * 1e3,
+           "kernel_ms_per_step": {c: v[0] / k for c, v in leg["tm"].items()}}
+    if npts is not None and "jv" in leg["tm"] and leg["tm"]["jv"][0] > 0:
+        ms, launches, _ = leg["tm"]["jv"]
+        out["jv_kernel_gpts"] = npts * launches / (ms / 1e3) / 1e9
+    return out
 
 
-def cpu_baseline(prob, U0, seconds, sweeps):
-    """Oracle (FP64 numpy) on a bounded sample of the same workload: GMRES
-    iterations of the first Newton iteration of the first step (physics
-    preconditioner, stable-FD Jv, CGS2 Arnoldi), stopped after `seconds`."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_jv_worker(args):
+    """One process: the oracle's FP64 stable-FD Jv on the sample, repeated until
+    `seconds` have passed, with one BLAS / OpenMP thread.  Returns (calls, points
+    per call, seconds)."""
+    nz_s, seconds = args
     from threadpoolctl import threadpool_limits
 
-    from oracle import krylov as K
+    import numpy as np
+
     from oracle import model as M
-    from oracle import precond as PC
-
+    from paper_2007_10411_amd import inputs as I
+    full = I.thermal_neutral_3d()
+    prob = full.replace(nz=nz_s, lz=full.lz * nz_s / full.nz)
+    U = I.bubble_state(prob, center=(full.lx / 2, full.ly / 2, 2000.0))
+    V = I.random_vector(prob, seed=1)
+    calls = 0
     with threadpool_limits(limits=1):
-        f = M.rhs(prob, U0)
-        R = M.residual(prob, U0, f)
-        fr = PC.frozen_coefficients(prob, U0)
-        calls = [0]
+        eps = M.fd_eps(prob, U, V, 2.0 ** -52)
         t0 = time.perf_counter()
+        while True:
+            M.jv(prob, U, V, eps)
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    return calls, prob.npts, el
 
-        class Stop(Exception):
-            pass
 
-        def mv(v):
-            if time.perf_counter() - t0 > seconds:
-                raise Stop
-            calls[0] += 1
-            return M.jv(prob, U0, v, M.fd_eps(prob, U0, v, 2.0 ** -52))
-
-        pc = lambda r: PC.physics_pc(prob, U0, r, sweeps, fr)
-        try:
-            K.fgmres(mv, pc, -R, m=30, tol=1e-12, max_iters=10 ** 6, true_residual=False)
-        except Stop:
-            pass
-        el = time.perf_counter() - t0
-    gpts = prob.npts * calls[0] / el / 1e9
-    return {"value": gpts, "unit": "Gpoint-residuals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{calls[0]} FP64 GMRES iterations (PC with {sweeps} sweeps + Jv + CGS2) of the first Newton "
-                      f"iteration of step 1 on the same {prob.nx}x{prob.nz} grid, {el:.1f} s, 1 thread"}
+def cpu_baseline(seconds, nz_s=16):
+    """FP64 oracle on a bounded sample of the workload: its Jv on the lowest
+    nz_s planes of the 256 x 256 x 128 grid (same spacing, bubble state, unit
+    random direction), on one core and then on every core of the host's share
+    (one single-threaded process per core, all at once)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    c1, npts, el1 = _oracle_jv_worker((nz_s, seconds))
+    one = npts * c1 / el1 / 1e9
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_jv_worker, [(nz_s, seconds)] * cores)
+    wall = time.perf_counter() - t0
+    pts = sum(c * n for c, n, _ in res)
+    span = max(e for _, _, e in res)
+    allv = pts / span / 1e9
+    return {"value": allv, "unit": "Gpoint-residuals/s", "cores": cores, "kind": "oracle",
+            "sample": f"the FP64 oracle's stable-FD Jv on the lowest {nz_s} planes of the 256x256x128 grid "
+                      f"({npts} points, bubble state, unit random direction): {cores} single-threaded "
+                      f"processes at once, {sum(c for c, _, _ in res)} evaluations in {span:.1f} s "
+                      f"(pool wall {wall:.1f} s); one process alone: {c1} evaluations in {el1:.1f} s",
+            "value_1core": one, "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cores": len(os.sched_getaffinity(0))}
 
 
 def sources_sha256(paths):
@@ -300,6 +324,11 @@ def synth_state(torch, prob, seed=0):
     return U.reshape(-1)
 
 
+# kernels of the 3D operators (256 x 256 x 128)
+JV3_KERNEL = "k3m_derived<float, true> + k3m_point<float, 1, 8>"
+RES3_KERNEL = "k3m_derived<double, false> + k3m_point<double, 0, 8>"
+
+
 def jv_kernel_name(rows):
     """Name of the FP32 Jv kernel of an autotuned launch shape (rows per workgroup)."""
     if rows >= 32:
@@ -311,7 +340,7 @@ def kernel_micro(torch, I, L, Context, reps, pins=None):
     """Residual, Jv and physics-preconditioner kernels alone at sizes beyond the
     Infinity Cache."""
     out = {}
-    cases = [("2d_8192x8192", I.thermal_stable_2d(8192, 8192)), ("3d_256x256x128", I.thermal_neutral_3d()),
+    cases = [("3d_256x256x128", I.thermal_neutral_3d()), ("2d_8192x8192", I.thermal_stable_2d(8192, 8192)),
              ("2d_8192x8192_p3", I.thermal_stable_2d(8192, 8192).replace(dd_p=3))]
     for name, prob in cases:
         ctx = Context(prob, max_m=1)
@@ -374,18 +403,55 @@ def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0])}
-    for name, pc, params, sw, inner in [("physics", "physics", None, sweeps, "f32"),
-                                        ("physics_sweeps2", "physics", None, 2, "f32"),
-                                        ("plain_f64_physics", "physics", None, sweeps, "f64"),
-                                        ("learned", "learned", theta, 0, "f32"),
-                                        ("untrained_form", "learned", np.zeros(ctx.n_params, np.float32), 0, "f32")]:
+    zero = np.zeros(ctx.n_params, np.float32)
+    # learned: judged by the physics-based preconditioner (the library's behaviour);
+    # *_unjudged: the network's own iteration counts
+    for name, pc, params, sw, inner, judge in [("physics", "physics", None, sweeps, "f32", True),
+                                               ("physics_sweeps2", "physics", None, 2, "f32", True),
+                                               ("plain_f64_physics", "physics", None, sweeps, "f64", True),
+                                               ("learned", "learned", theta, 0, "f32", True),
+                                               ("learned_unjudged", "learned", theta, 0, "f32", False),
+                                               ("untrained_form_unjudged", "learned", zero, 0, "f32", False)]:
         if params is not None:
             ctx.net_set_params(params)
         extra = dict(eta_floor=1e-4) if inner == "f32" else {}
         leg = timed_leg(ctx, u_end, 2, torch, None, {}, rtol=1e-8, m=30, max_restarts=20, inner=inner,
-                        pc=pc, sweeps=sw, ortho=ortho, **extra)
+                        pc=pc, sweeps=sw, ortho=ortho, judge=judge, **extra)
         out[name] = per_step(leg)
     return out
+
+
+def train_learned_3d(torch, I, LRN, Context, ctx, u, iters, sweeps):
+    """Train the 3x3x3 network of the 256 x 256 x 128 context on crops of solver
+    pairs: Krylov directions and their images from one physics-preconditioned
+    step of this workload (64 x 64 x 32 crops), the same from the 2D neutral
+    thermal at the same spacing and time step (256 x 128, embedded as y-invariant
+    3D fields, 128 x 16 x 64 crops), and noise directions through this
+    context's Jv (64 x 64 x 32 crops)."""
+    t0 = time.perf_counter()
+    p3 = ctx.prob
+    R3, DU3, _ = LRN.collect_pairs(ctx, u, steps=1, cap=24, sweeps=sweeps)
+    p2 = I.thermal_neutral_2d(256, 128)
+    ctx2 = Context(p2, max_m=30)
+    u2 = torch.from_numpy(I.bubble_state(p2)).cuda()
+    R2, DU2, _ = LRN.collect_pairs(ctx2, u2, steps=3, cap=64, sweeps=sweeps)
+    ny2 = 16
+    R2e, DU2e = LRN.embed_2d(R2, p2.nx, p2.nz, ny2), LRN.embed_2d(DU2, p2.nx, p2.nz, ny2)
+    del ctx2, R2, DU2
+    t1 = time.perf_counter()
+    crop3 = (64, 64, 32)
+    sources = [(R3, DU3, (p3.nf, p3.nz, p3.ny, p3.nx), crop3),
+               (R2e, DU2e, (5, p2.nz, ny2, p2.nx), (128, ny2, 64))]
+    noise = (LRN.NoisePairs(ctx, u, LRN.field_rms(DU3, p3.nf), seed=1), crop3)
+    theta, losses = LRN.train_3d_crops(ctx, sources, iters=iters, lr=2e-3, batch=4, noise=noise)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"pairs_3d": int(R3.shape[0]), "pairs_2d": int(R2e.shape[0]), "crop_3d": list(crop3),
+            "crop_2d_embedded": [128, ny2, 64], "collect_s": t1 - t0, "train_s": t2 - t1, "adam_steps": iters,
+            "loss_first": float(losses[0]), "loss_last": float(sum(losses[-30:]) / min(30, len(losses)))}
+    del R3, DU3, R2e, DU2e
+    torch.cuda.empty_cache()
+    return theta, info
 
 
 def main():
@@ -416,28 +482,25 @@ def main():
     from paper_2007_10411_amd.jfnk import Context
 
     legs_wanted = [x for x in args.legs.split(",") if x]
-    if args.no_learned and "learned" in legs_wanted:
-        legs_wanted.remove("learned")
+    if args.no_learned:
+        legs_wanted = [x for x in legs_wanted if x not in ("learned", "learned2d")]
     if "mixed" not in legs_wanted:
         legs_wanted.insert(0, "mixed")
     torch.cuda.set_device(0)
-    prob = I.thermal_stable_2d(args.nx, args.nz)
-    U0 = I.bubble_state(prob)
+    prob = I.thermal_neutral_3d()
+    npts = prob.npts
     ctx = Context(prob, max_m=30)
-    shapes = ctx.tune()                 # launch shapes of the stencil stages (setup, untimed)
-    shapes = pin_shapes(ctx, shapes, parse_shapes(args.pin))
-    log(f"launch shapes (rows per workgroup): {shapes}")
+    shapes = ctx.tune()
     common = dict(rtol=1e-8, m=30, max_restarts=20, ortho=args.ortho)
     opts = {"mixed": dict(common, inner="f32", eta_floor=1e-4, pc="physics", sweeps=args.pc_sweeps),
             "plain": dict(common, inner="f64", pc="physics", sweeps=args.pc_sweeps),
-            "learned": dict(common, inner="f32", eta_floor=1e-4, pc="learned")}
+            "learned": dict(common, inner="f32", eta_floor=1e-4, pc="learned", sweeps=args.pc_sweeps)}
     steps = {"mixed": args.steps, "plain": args.plain_steps, "learned": args.learned_steps}
-    classes = {"mixed": {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI},
-               "plain": {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI},
-               "learned": {"jv": L.KC_JV, "arnoldi": L.KC_ARNOLDI, "net": L.KC_NET}}
+    cls = {"jv": L.KC_JV, "pc": L.KC_PC, "arnoldi": L.KC_ARNOLDI, "residual": L.KC_RESIDUAL}
+    classes = {"mixed": cls, "plain": cls, "learned": dict(cls, net=L.KC_NET)}
 
-    u = torch.from_numpy(U0).cuda()
-    log(f"warmup {args.warmup} mixed steps")
+    u = torch.from_numpy(I.bubble_state(prob)).cuda()
+    log(f"3D thermal 256x256x128: warmup {args.warmup} mixed steps")
     run_steps(ctx, u, args.warmup, torch, **opts["mixed"])
     legs = {}
     log(f"timing {steps['mixed']} mixed steps")
@@ -445,71 +508,38 @@ def main():
     if "plain" in legs_wanted:
         log(f"timing {steps['plain']} plain FP64 steps")
         legs["plain"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["plain"], **opts["plain"])
-    if "sweeps2" in legs_wanted:
-        # the timed configuration with two Jacobi sweeps in the physics preconditioner
-        log(f"timing {steps['plain']} mixed steps with two preconditioner sweeps")
-        legs["mixed_pc_sweeps2"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["mixed"],
-                                             **dict(opts["mixed"], sweeps=2))
-    if "cgs2" in legs_wanted and args.ortho != "cgs2":
-        # the timed configuration with classical Gram-Schmidt applied twice
-        log(f"timing {steps['plain']} mixed steps with the CGS2 Arnoldi step")
-        legs["mixed_cgs2"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["mixed"],
-                                       **dict(opts["mixed"], ortho="cgs2"))
     train_info = None
-    small = None
     if "learned" in legs_wanted:
-        log("recording solver pairs and training the learned preconditioner")
-        t0 = time.perf_counter()
-        R, DU, u_tr = LRN.collect_pairs(ctx, u, steps=2, cap=96)
-        t1 = time.perf_counter()
-        theta, losses = LRN.train_mixed(ctx, R, DU, u_tr, iters=args.train_iters, lr=2e-3, batch=8)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        train_info = {"pairs": int(R.shape[0]), "collect_s": t1 - t0, "train_s": t2 - t1,
-                      "adam_steps": args.train_iters, "dilations": list(LRN.DILATIONS),
-                      "loss_first": losses[0], "loss_last": float(np.mean(losses[-20:]))}
-        del R, DU
-        torch.cuda.empty_cache()
+        log("recording solver pairs and training the 3D network")
+        theta, train_info = train_learned_3d(torch, I, LRN, Context, ctx, u, args.train_iters, args.pc_sweeps)
+        # the judge's record: one physics-preconditioned step of the timed configuration
+        run_steps(ctx, u.clone(), 1, torch, **opts["mixed"])
         log(f"timing {steps['learned']} learned steps")
         legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
-        log("learned vs physics preconditioner at 256 x 128")
-        small = learned_small(torch, I, LRN, Context, args.train_iters, args.pc_sweeps, args.ortho)
-    if "p3" in legs_wanted:
-        # the same workload with the 9-point (p = 3) derivative
-        prob3 = prob.replace(dd_p=3)
-        ctx3 = Context(prob3, max_m=30)
-        ctx3.tune()
-        u3 = torch.from_numpy(U0).cuda()
-        log("mixed steps with the 9-point stencil")
-        run_steps(ctx3, u3, args.warmup, torch, **opts["mixed"])
-        legs["mixed_p3"] = timed_leg(ctx3, u3, args.plain_steps, torch, L, classes["mixed"], **opts["mixed"])
-        del ctx3
-    if "deardorff" in legs_wanted:
-        # the same workload with the anisotropic exchange coefficients of Eq. 7
-        probd = prob.replace(closure=I.CLOSURE_DEARDORFF)
-        ctxd = Context(probd, max_m=30)
-        ctxd.tune()
-        ud = torch.from_numpy(U0).cuda()
-        log("mixed steps with the anisotropic (Eq. 7) closure")
-        run_steps(ctxd, ud, args.warmup, torch, **opts["mixed"])
-        legs["mixed_deardorff"] = timed_leg(ctxd, ud, args.plain_steps, torch, L, classes["mixed"],
-                                            **opts["mixed"])
-        del ctxd
-    if "3d" in legs_wanted:
-        # the 3D neutral thermal at 256 x 256 x 128 (20 x 20 x 10 km, dt = 2 s), mixed precision
-        prob3d = I.thermal_neutral_3d()
-        ctx3d = Context(prob3d, max_m=30)
-        u3d = torch.from_numpy(I.bubble_state(prob3d)).cuda()
-        log("mixed steps of the 3D thermal 256x256x128")
-        run_steps(ctx3d, u3d, 1, torch, **opts["mixed"])
-        legs["mixed_3d_256x256x128"] = timed_leg(ctx3d, u3d, args.plain_steps, torch, L, classes["mixed"],
-                                                 **opts["mixed"])
-        del ctx3d, u3d
-        torch.cuda.empty_cache()
+    del ctx
+    torch.cuda.empty_cache()
 
+    legs_2d = None
+    if "2d" in legs_wanted:
+        # the 2D stable thermal at 1024 x 512 (N = 0.01 1/s, dt = 1 s), mixed and plain
+        p2 = I.thermal_stable_2d(1024, 512)
+        c2 = Context(p2, max_m=30)
+        sh2 = pin_shapes(c2, c2.tune(), parse_shapes(args.pin))
+        u2 = torch.from_numpy(I.bubble_state(p2)).cuda()
+        log("2D stable thermal 1024x512: mixed and plain legs")
+        run_steps(c2, u2, args.warmup, torch, **opts["mixed"])
+        legs_2d = {"workload": "stable 2D dry thermal 1024x512 (20x10 km, N=0.01/s, dt=1 s)", "launch_shapes": sh2}
+        for name in ("mixed", "plain"):
+            k = steps["mixed"] if name == "mixed" else steps["plain"]
+            legs_2d[name] = per_step(timed_leg(c2, u2, k, torch, L, cls, **opts[name]), p2.npts)
+        del c2, u2
+        torch.cuda.empty_cache()
+    small = None
+    if "learned2d" in legs_wanted:
+        log("learned vs physics preconditioner, 2D stable thermal 256 x 128")
+        small = learned_small(torch, I, LRN, Context, args.train_iters_2d, args.pc_sweeps, args.ortho)
     ensemble = None
     if "ensemble" in legs_wanted:
-        # the 64-instance heat-island ensemble (uneven 2D grids, one launch per stage)
         from paper_2007_10411_amd.jfnk import Batch
         log("one mixed step of the 64-instance heat-island ensemble")
         eprobs = I.heat_island_ensemble(64, seed=0)
@@ -534,7 +564,6 @@ def main():
 
     T = legs["mixed"]
     tm = T["tm"]
-    npts = prob.npts
 
     def roof(leg, name, kernel, bound="hbm", traffic=None):
         ms, launches, amount = legs[leg]["tm"][name]
@@ -554,22 +583,18 @@ def main():
                            "Givens step of one GMRES iteration)" if args.ortho == "one_reduction" else
                            "k_cgs_reg<float> x3 + k_cgs_finish x3 (CGS2 passes and Givens step of one GMRES "
                            "iteration)"),
-               "pc": "k_pc_diag_2d<float> + 2 x k_pc_sweep_2d<float> (physics preconditioner with two sweeps, "
-                     "mixed_pc_sweeps2 leg)" if "mixed_pc_sweeps2" in legs else
-                     f"k_pc_diag_2d<float> + {args.pc_sweeps} x k_pc_sweep_2d<float> (physics preconditioner)",
-               "jv": f"{jv_kernel_name(shapes['f32_jv'])} (stable finite-difference Jv)"}
-    traffic_name = {"arnoldi": ("arnoldi_f32_counters_thermal_stable_1024x512" if args.ortho == "one_reduction"
-                                else "arnoldi_cgs2_f32_counters_thermal_stable_1024x512"),
-                    "pc": "pc_f32_counters_thermal_stable_1024x512",
-                    "jv": "jv_f32_counters_thermal_stable_1024x512"}
-    dominant = max(kernels, key=lambda k: tm[k][0])
-    full = (prob.nx, prob.nz) == (1024, 512)
-
-    def traffic_of(k):
-        return counter_traffic(traffic_name[k], shapes) if full else None
-
+               "pc": f"k3_pc_diag<float> + {args.pc_sweeps} x k3m_pc_sweep<float> (physics preconditioner)",
+               "jv": JV3_KERNEL + " (stable finite-difference Jv, FP32)",
+               "residual": RES3_KERNEL + " (FP64 residual)"}
+    traffic_name = {"arnoldi": "arnoldi_f32_counters_thermal_3d_256x256x128",
+                    "pc": "pc_f32_counters_thermal_3d_256x256x128",
+                    "jv": "jv_f32_counters_thermal_3d_256x256x128",
+                    "residual": "residual_f64_counters_thermal_3d_256x256x128"}
+    dominant = max(("arnoldi", "jv", "pc"), key=lambda k: tm[k][0])
     jv_ms, jv_launches, _ = tm["jv"]
-    value = npts * jv_launches / T["wall"] / 1e9
+    value = npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0
+    leg_summary = {k: per_step(v, npts) for k, v in legs.items()}
+    mixed_ms = leg_summary["mixed"]["ms_per_step"]
     out = {
         "metric": "Gpoint-residuals/s (Jv) and ms per implicit step at 1e-8 Newton tol, plain vs learned",
         "value": value,
@@ -577,57 +602,50 @@ def main():
         "n_gpus": 1,
         "steps": steps["mixed"],
         "warmup": args.warmup,
-        "ms_per_step": T["wall"] / steps["mixed"] * 1e3,
+        "ms_per_step": mixed_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 Krylov/Jv, f64 Newton",
         "data": "synthetic",
         "config": {
-            "workload": f"stable 2D dry thermal {prob.nx}x{prob.nz} (20x10 km, N=0.01/s, +2 K bubble, "
-                        f"dt={prob.dt} s, Smagorinsky), mixed-precision JFNK with the physics-based "
+            "workload": f"3D neutral dry thermal 256x256x128 (20x20x10 km, +2 K bubble r=2 km at (10,10,2) km, "
+                        f"dt={prob.dt} s, Smagorinsky, free-slip), mixed-precision JFNK with the physics-based "
                         f"preconditioner (field-block diagonal, {args.pc_sweeps} Jacobi sweeps): FGMRES(30) "
                         f"with the {args.ortho} Arnoldi step, Newton rtol 1e-8",
-            "grid": [prob.nx, prob.nz],
+            "grid": [prob.nx, prob.ny, prob.nz],
             "pc_sweeps": args.pc_sweeps,
             "ortho": args.ortho,
             "timed_leg": "mixed",
-            "legs": {k: per_step(v) for k, v in legs.items()},
-            "plain_over_mixed_time": (per_step(legs["plain"])["ms_per_step"] / per_step(T)["ms_per_step"]
-                                      if "plain" in legs else None),
-            "training": train_info,
+            "value_definition": "grid points x Jv evaluations / summed Jv kernel time (HIP events) of the timed leg",
+            "jv_wall_gpts": npts * jv_launches / T["wall"] / 1e9 * len(T["infos"]) / len(T["infos_instrumented"]),
+            "legs": leg_summary,
+            "plain_ms_over_mixed_ms": (leg_summary["plain"]["ms_per_step"] / mixed_ms if "plain" in legs else None),
+            "plain_ms_over_learned_ms": (leg_summary["plain"]["ms_per_step"] / leg_summary["learned"]["ms_per_step"]
+                                         if "plain" in legs and "learned" in legs else None),
+            "training_3d": train_info,
+            "legs_2d": legs_2d,
             "learned_256x128": small,
             "ensemble_64_heat_island": ensemble,
-            "jv_kernel_gpts": npts * jv_launches / (jv_ms / 1e3) / 1e9 if jv_ms > 0 else 0.0,
             "kernel_ms_per_step": {k: v[0] / steps["mixed"] for k, v in tm.items()},
             "launch_shapes": shapes,
         },
-        "roofline": roof("mixed", dominant, kernels[dominant], traffic=traffic_of(dominant)),
-        "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=traffic_of("jv")),
-        "roofline_pc": roof("mixed_pc_sweeps2" if "mixed_pc_sweeps2" in legs else "mixed", "pc", kernels["pc"],
-                            traffic=traffic_of("pc")),
+        "roofline": roof("mixed", dominant, kernels[dominant], traffic=counter_traffic(traffic_name[dominant])),
+        "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=counter_traffic(traffic_name["jv"])),
+        "roofline_pc": roof("mixed", "pc", kernels["pc"], traffic=counter_traffic(traffic_name["pc"])),
     }
     if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
-        out["roofline_net"] = roof("learned", "net", "k_conv_mfma x4 (BF16 3x3 conv layers of the learned PC)",
+        out["roofline_net"] = roof("learned", "net", "k3_conv_mfma x4 (BF16 3x3x3 conv layers of the learned PC)",
                                    "mfma")
     if not args.no_micro:
         del legs
         torch.cuda.empty_cache()
-        log("kernel micro-benchmark (2D 8192x8192, 3D 256x256x128)")
+        log("kernel micro-benchmark (3D 256x256x128, 2D 8192x8192)")
         micro = kernel_micro(torch, I, L, Context, args.micro_reps, parse_shapes(args.micro_pin))
         out["kernel_micro"] = micro
-        best = micro["2d_8192x8192"]["jv_f32"]
-        jk = jv_kernel_name(micro["2d_8192x8192"]["launch_shapes"]["f32_jv"])
-        out["roofline_jv_micro"] = {"kernel": f"{jk} at 8192x8192 (vectors beyond the Infinity Cache)",
-                                    "bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS,
-                                    "unit": "GB/s", "frac": best["frac"],
-                                    "traffic": counter_traffic("jv_f32_counters_8192x8192",
-                                                               micro["2d_8192x8192"]["launch_shapes"]),
-                                    "bytes_per_launch": best["bytes_per_launch"],
-                                    "avg_launch_us": best["avg_launch_us"]}
     if not args.no_cpu:
-        log(f"cpu baseline ({args.cpu_seconds} s)")
-        out["cpu_baseline"] = cpu_baseline(prob, U0, args.cpu_seconds, args.pc_sweeps)
+        log(f"cpu baseline ({args.cpu_seconds} s per process)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

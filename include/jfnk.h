@@ -128,6 +128,9 @@ typedef struct {
     int32_t sweeps;            /* physics preconditioner Jacobi sweeps (>= 0)            */
     int32_t max_iters;         /* hard cap on iterations (<= 0: m * max_restarts)        */
     int32_t ortho;             /* jfnk_ortho: Gram-Schmidt form of the Arnoldi step      */
+    int32_t no_judge;          /* 1: a learned-preconditioner solve is not judged by the
+                                  physics-based one (it runs to its iteration budget and
+                                  falls back only when it does not converge)             */
 } jfnk_gmres_opts;
 
 typedef struct {
@@ -247,7 +250,10 @@ int jfnk_tune(jfnk_ctx* ctx, int32_t* tile_rows);
  * stage 0 residual / F, 1 Jv, 2 preconditioner sweep; dtype JFNK_F64 or
  * JFNK_F32; variant 0, 1, 2 = tiles of 64 x 4, 64 x 8, 64 x 16 points, 3, 4, 5 =
  * row marching over 32, 64, 256 rows (residual and Jv only).  The FP64 Jv has
- * no 64 x 16 tile (its LDS would exceed a CU's).  The 3D kernels ignore it.
+ * no 64 x 16 tile (its LDS would exceed a CU's).  3D contexts take only the
+ * FP32 Jv (stage 1): variant 7 = one z-marching launch that keeps the stress and
+ * heat-flux differences in LDS and registers (the default), 6 = two launches
+ * with those differences in an HBM buffer between them.
  * Returns JFNK_ERR_ARG for anything else.                                       */
 int jfnk_set_variant(jfnk_ctx* ctx, int32_t stage, int32_t dtype, int32_t variant);
 

@@ -43,7 +43,8 @@ class Problem(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("max_restarts", C.c_int32), ("tol", C.c_double), ("pc", C.c_int32),
-                ("jv", C.c_int32), ("sweeps", C.c_int32), ("max_iters", C.c_int32), ("ortho", C.c_int32)]
+                ("jv", C.c_int32), ("sweeps", C.c_int32), ("max_iters", C.c_int32), ("ortho", C.c_int32),
+                ("no_judge", C.c_int32)]
 
 
 class GmresInfo(C.Structure):

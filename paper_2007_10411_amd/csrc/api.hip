@@ -66,7 +66,11 @@ hipError_t op_F(jfnk_ctx* c, const T* u, const T* f, T* out, int what) {
 }
 template <typename T>
 hipError_t op_jv(jfnk_ctx* c, const T* u, const T* v, double eps, const double* eps_dev, T* out) {
-    if (c->geo.dim == 3) return launch3_jv<T>(c->geo, u, v, eps, eps_dev, out, DB<T>(c), c->stream);
+    if (c->geo.dim == 3) {
+        if constexpr (std::is_same<T, float>::value)
+            if (c->jv3_single && c->geo.W == 2) return launch3_jv_fused(c->geo, u, v, eps, eps_dev, out, c->stream);
+        return launch3_jv<T>(c->geo, u, v, eps, eps_dev, out, DB<T>(c), c->stream);
+    }
     return launch_jv<T>(c->geo, u, v, eps, eps_dev, out, c->stream, tv(c, 1, is32<T>()));
 }
 template <typename T>
@@ -672,15 +676,16 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
 // iteration falls short of that solve's; the system is then solved again with
 // the physics-based preconditioner, as it is when no record exists or the
 // learned solve does not converge (gi->fallback = 1, the learned attempt's
-// iterations added to *spent).  Every physics-preconditioned solve that
-// converges updates the record.
+// iterations added to *spent).  go.no_judge runs the learned solve unjudged,
+// falling back only when it does not converge.  Every physics-preconditioned
+// solve that converges updates the record.
 template <typename T>
 int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, jfnk_gmres_info* gi, int* spent) {
     gi->fallback = 0;
     gi->res_true = -1.0;
     if (go.pc == JFNK_PC_LEARNED) {
-        if (c->judge_rate < 0.0) {
-            c->judge_active = c->judge_rate;
+        if (go.no_judge || c->judge_rate < 0.0) {
+            c->judge_active = go.no_judge ? 0.0 : c->judge_rate;
             c->judged_out = false;
             const int rc = gmres_impl<T>(c, u, b, x, go, gi);
             c->judge_active = 0.0;
@@ -1334,6 +1339,15 @@ int jfnk_set_variant(jfnk_ctx* c, int32_t stage, int32_t dtype, int32_t variant)
     if (!c) {
         set_error("null context");
         return JFNK_ERR_ARG;
+    }
+    if (c->geo.dim == 3) {
+        // 3D: only the FP32 Jv has two forms
+        if (stage != 1 || dtype != JFNK_F32 || (variant != 6 && variant != 7)) {
+            set_error("3D contexts take variant 6 (two-pass) or 7 (single-pass) of the FP32 Jv");
+            return JFNK_ERR_ARG;
+        }
+        c->jv3_single = variant == 7 ? 1 : 0;
+        return JFNK_OK;
     }
     if (stage < 0 || stage > 2 || (dtype != JFNK_F64 && dtype != JFNK_F32) || variant < 0 ||
         variant > (stage < 2 ? 5 : 2) || (stage == 1 && dtype == JFNK_F64 && variant == 2)) {

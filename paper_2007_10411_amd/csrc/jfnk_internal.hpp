@@ -211,6 +211,9 @@ struct jfnk_ctx {
     // tile variant per stencil stage, chosen by jfnk_tune (index: stage * 2 + (FP32 ? 1 : 0);
     // stages 0 residual / F, 1 Jv, 2 preconditioner sweep)
     int tune[6] = {1, 1, 1, 1, 1, 1};
+    // 3D FP32 Jv: the single-pass kernel (1) or the two-pass form with the
+    // stress / heat-flux buffer (0)
+    int jv3_single = 1;
     // Krylov-pair recording (J z_j, z_j) during FP32 solves
     float* rec_r = nullptr;
     float* rec_du = nullptr;
@@ -261,6 +264,9 @@ hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int wha
 template <typename T>
 hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
                       hipStream_t s);
+// the FP32 Jv in one z-marching launch (no intermediate buffer)
+hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double eps, const double* eps_dev,
+                            float* out, hipStream_t s);
 template <typename T>
 hipError_t launch3_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s);
 template <typename T>

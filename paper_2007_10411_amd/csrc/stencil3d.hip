@@ -14,6 +14,8 @@
 // does the Jacobi sweep of the preconditioner (k3m_pc_sweep); the frozen
 // viscosity and the diagonal start run one thread per point, x fastest.
 
+#include <algorithm>
+
 #include "jfnk_internal.hpp"
 #include "reduce.hpp"
 #include "exchange.hpp"
@@ -608,6 +610,447 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-launch 3D Jv (the stable finite-difference quotient of Eq. 9, FP32).
+// A workgroup owns 32 x TY columns and marches along z; at step s it forms the
+// differences of the stress and heat flux (the derived quantities) at plane
+// s + 2 over the columns grown by 2, and Jv at plane s:
+//  - the primitives of A = u and B = v reach a step through per-column
+//    register queues, filled one plane ahead: the own column holds planes
+//    s-2 .. s+4 (p: s-2 .. s+2), each column of the ring of 2 around the tile
+//    planes s .. s+4;
+//  - in-plane neighbours come from LDS: plane s+2 over the columns grown by 4
+//    (gradients of the derived stage) and plane s over the columns grown by 2
+//    (convection, pressure gradient, divergence);
+//  - the in-plane derived components (xx, yy, xy, xz, yz, qx, qy) of planes
+//    s .. s+2 live in an LDS ring of three planes, the own column's vertical
+//    ones (xz, yz, zz, qz) of planes s-2 .. s+2 in a register queue.
+// Every state value comes from HBM once per workgroup (plus the halos) and Jv
+// is the only array written: 3 n_f values per point against the two-pass
+// form's 9 extra components written and read back.
+// ---------------------------------------------------------------------------
+template <int TY> struct FusedGeom {
+    static constexpr int TX = 32, NT = TX * TY;
+    static constexpr int SX2 = TX + 4, SY2 = TY + 4, P2 = SX2 * SY2;   // the columns grown by 2
+    static constexpr int SX4 = TX + 8, SY4 = TY + 8, P4 = SX4 * SY4;   // grown by 4
+    static constexpr int NRIM2 = P2 - NT, NRIM4 = P4 - P2;
+};
+
+// r-th column of the ring of 2 around the tile, in the coordinates of the
+// columns grown by 2: two full rows below, two above, then two columns each side
+template <int TY>
+__device__ __forceinline__ void fused_rim2(int r, int& lx, int& ly) {
+    using FG = FusedGeom<TY>;
+    constexpr int row2 = 2 * FG::SX2;
+    if (r < row2) {
+        ly = r / FG::SX2;
+        lx = r - ly * FG::SX2;
+    } else if (r < 2 * row2) {
+        r -= row2;
+        ly = TY + 2 + r / FG::SX2;
+        lx = r - (ly - TY - 2) * FG::SX2;
+    } else {
+        r -= 2 * row2;
+        ly = 2 + (r >> 2);
+        const int c = r & 3;
+        lx = c < 2 ? c : FG::TX + c;
+    }
+}
+
+// r-th column of the ring between the columns grown by 2 and by 4, in the
+// coordinates of the columns grown by 4
+template <int TY>
+__device__ __forceinline__ void fused_rim4(int r, int& lx, int& ly) {
+    using FG = FusedGeom<TY>;
+    constexpr int row2 = 2 * FG::SX4;
+    if (r < row2) {
+        ly = r / FG::SX4;
+        lx = r - ly * FG::SX4;
+    } else if (r < 2 * row2) {
+        r -= row2;
+        ly = FG::SY4 - 2 + r / FG::SX4;
+        lx = r - (ly - FG::SY4 + 2) * FG::SX4;
+    } else {
+        r -= 2 * row2;
+        ly = 2 + (r >> 2);
+        const int c = r & 3;
+        lx = c < 2 ? c : FG::SX4 - 4 + c;
+    }
+}
+
+// fields of the derived stage: (u, v, w, theta) of A, then of B; state indices
+__device__ __forceinline__ constexpr int fused_sf(int k) { return k == 3 ? 4 : k; }
+
+// Derived quantities of the pair (A, B) at one column of plane za: the stable
+// differences [tau(A + e B) - tau(A)] / e and [q(A + e B) - q(A)] / e (as in
+// k3m_derived).  L points at the column in the LDS plane za over the columns
+// grown by 4 (fields A u, v, w, theta, B u, v, w, theta); q[Q0 .. Q0+4] are
+// the column's values at planes za-2 .. za+2.  out: xx, yy, zz, xy, xz, yz,
+// qx, qy, qz.
+template <int TY, int Q0, int N>
+__device__ __forceinline__ void fused_derived(const Geo& g, const float* __restrict__ L, const float (&q)[N][8], float e,
+                                              float ihx, float ihy, float ihz, float out[9]) {
+    using FG = FusedGeom<TY>;
+    constexpr int P = FG::P4, S = FG::SX4;
+    float gA[3][3], gB[3][3], tA[3], tB[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = i + 4 * h;
+            const float* c = L + f * P;
+            const float dx = d5(c[-2], c[-1], c[1], c[2], ihx);
+            const float dy = d5(c[-2 * S], c[-S], c[S], c[2 * S], ihy);
+            const float dz = d5(q[Q0][f], q[Q0 + 1][f], q[Q0 + 3][f], q[Q0 + 4][f], ihz);
+            float* gr = i < 3 ? (h ? gB[i] : gA[i]) : (h ? tB : tA);
+            gr[0] = dx;
+            gr[1] = dy;
+            gr[2] = dz;
+        }
+    }
+    float SA[6], SB[6], SW[6];
+    SA[0] = gA[0][0], SA[1] = gA[1][1], SA[2] = gA[2][2];
+    SA[3] = 0.5f * (gA[0][1] + gA[1][0]), SA[4] = 0.5f * (gA[0][2] + gA[2][0]), SA[5] = 0.5f * (gA[1][2] + gA[2][1]);
+    SB[0] = gB[0][0], SB[1] = gB[1][1], SB[2] = gB[2][2];
+    SB[3] = 0.5f * (gB[0][1] + gB[1][0]), SB[4] = 0.5f * (gB[0][2] + gB[2][0]), SB[5] = 0.5f * (gB[1][2] + gB[2][1]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) SW[k] = SA[k] + e * SB[k];
+    Coef<float> ka = {0.f, 0.f, 0.f, 0.f}, dk = {0.f, 0.f, 0.f, 0.f};
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
+        const float ma = sqrtf(frob3(SA, SA)), mw = sqrtf(frob3(SW, SW));
+        const float den = ma + mw;
+        const float num = 2.f * frob3(SA, SB) + e * frob3(SB, SB);
+        if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+            const float c = float(g.smag) * 1.4142135623730951f;
+            const float nu = c * ma, dnu = den > 0.f ? c * num / den : 0.f;
+            const float ip = float(g.inv_pr);
+            ka = {nu, nu, nu * ip, nu * ip};
+            dk = {dnu, dnu, dnu * ip, dnu * ip};
+        } else {
+            ka = deardorff_coef(g, ma);
+            dk = deardorff_diff(g, ma, den > 0.f ? num / den : 0.f, e);
+        }
+    } else if (g.closure == JFNK_CLOSURE_CONST_K) {
+        ka = {float(g.k_m), float(g.k_m), float(g.k_h), float(g.k_h)};
+    }
+    const float trw = (SW[0] + SW[1] + SW[2]) * (1.f / 3.f), trb = (SB[0] + SB[1] + SB[2]) * (1.f / 3.f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float dw = k < 3 ? SW[k] - trw : SW[k];
+        const float db = k < 3 ? SB[k] - trb : SB[k];
+        out[k] = 2.f * ((vert3(k) ? dk.mv : dk.mh) * dw + (vert3(k) ? ka.mv : ka.mh) * db);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        out[6 + j] = (j == 2 ? dk.hv : dk.hh) * (tA[j] + e * tB[j]) + (j == 2 ? ka.hv : ka.hh) * tB[j];
+}
+
+template <int TY>
+__global__ __launch_bounds__(32 * TY, 2) void k3f_jv(Geo g, const float* __restrict__ u, const float* __restrict__ v,
+                                                     double eps_in, const double* __restrict__ eps_dev,
+                                                     float* __restrict__ out, int kzc) {
+    using FG = FusedGeom<TY>;
+    __shared__ float L4[8 * FG::P4];        // plane s+2 over the columns grown by 4
+    __shared__ float L2[10 * FG::P2];       // plane s over the columns grown by 2 (A then B, state order)
+    __shared__ float RG[3 * 7 * FG::P2];    // in-plane derived components of planes s .. s+2
+    const int tid = threadIdx.x;
+    const int tx = tid & 31, ty = tid >> 5;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * kzc, z1 = min(z0 + kzc, g.nz);
+    const bool lat = g.bcl == JFNK_BC_PERIODIC, vper = g.bcv == JFNK_BC_PERIODIC;
+    const long long np = g.npts, nxy = (long long)g.nx * g.ny;
+    const float e = (float)(eps_dev ? *eps_dev : eps_in);
+    const float ihx = (float)g.idx, ihy = (float)g.idy, ihz = (float)g.idz;
+
+    // in-plane source offset and x/y reflection signs (bit f: state field f) of a column
+    auto setup = [&](int gx, int gy, int& off, unsigned& neg) {
+        int sx, sy;
+        const int mx = map3(gx, g.nx, lat, sx), my = map3(gy, g.ny, lat, sy);
+        off = my * g.nx + mx;
+        unsigned m = 0u;
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+            if (odd3(f, sx, sy, 0, g.bcv)) m |= 1u << f;
+        neg = m;
+    };
+    // plane offset and z reflection signs of plane z
+    auto zmap = [&](int z, long long& pl, unsigned& neg) {
+        int sz;
+        const int mz = map3(z, g.nz, vper, sz);
+        pl = (long long)mz * nxy;
+        unsigned m = 0u;
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+            if (odd3(f, 0, 0, sz, g.bcv)) m |= 1u << f;
+        neg = m;
+    };
+    auto sgn = [](float x, unsigned neg, int f) { return (neg >> f) & 1u ? -x : x; };
+    auto ld8 = [&](int off, long long pl, float (&r)[8]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r[k] = u[fused_sf(k) * np + pl + off];
+            r[4 + k] = v[fused_sf(k) * np + pl + off];
+        }
+    };
+    auto ldp = [&](int off, long long pl, float (&r)[2]) {
+        r[0] = u[3 * np + pl + off];
+        r[1] = v[3 * np + pl + off];
+    };
+    auto fix8 = [&](float (&r)[8], unsigned neg) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r[k] = sgn(r[k], neg, fused_sf(k & 3));
+    };
+    auto fixp = [&](float (&r)[2], unsigned neg) {
+        r[0] = sgn(r[0], neg, 3);
+        r[1] = sgn(r[1], neg, 3);
+    };
+
+    // the own column, a column of the ring of 2 and one of the ring between 2 and 4
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool mine = gx < g.nx && gy < g.ny;
+    int off0, off1, off4;
+    unsigned neg0, neg1, neg4;
+    setup(gx, gy, off0, neg0);
+    const int c2o = (ty + 2) * FG::SX2 + tx + 2, c4o = (ty + 4) * FG::SX4 + tx + 4;
+    const bool has1 = tid < FG::NRIM2, has4 = tid < FG::NRIM4;
+    int lx1 = 0, ly1 = 0, lx4 = 0, ly4 = 0;
+    if (has1) fused_rim2<TY>(tid, lx1, ly1);
+    if (has4) fused_rim4<TY>(tid, lx4, ly4);
+    setup(x0 - 2 + lx1, y0 - 2 + ly1, off1, neg1);
+    setup(x0 - 4 + lx4, y0 - 4 + ly4, off4, neg4);
+    const int c2r = ly1 * FG::SX2 + lx1, c4r = (ly1 + 2) * FG::SX4 + lx1 + 2, c4x = ly4 * FG::SX4 + lx4;
+
+    // queues (slot 0 oldest)
+    float q0[7][8];   // own column, planes s-2 .. s+4
+    float p0[5][2];   // own column p of A and B, planes s-2 .. s+2
+    float q1[5][8];   // ring-of-2 column, planes s .. s+4
+    float p1[2];      // its p at plane s
+    float r4[8];      // ring-of-4 column at plane s+2
+    float tq[5][4];   // own column xz, yz, zz, qz at planes s-2 .. s+2
+    const int sb = z0 - 4;   // first step: the derived stage starts at plane z0 - 2
+    {
+        long long pl;
+        unsigned nz_;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            zmap(sb - 2 + k, pl, nz_);
+            ld8(off0, pl, q0[k]);
+            fix8(q0[k], neg0 ^ nz_);
+            if (k < 5) {
+                ldp(off0, pl, p0[k]);
+                fixp(p0[k], neg0 ^ nz_);
+            }
+            if (k >= 2) {
+                ld8(off1, pl, q1[k - 2]);
+                fix8(q1[k - 2], neg1 ^ nz_);
+            }
+            if (k == 2) {
+                ldp(off1, pl, p1);
+                fixp(p1, neg1 ^ nz_);
+            }
+            if (k == 4) {
+                ld8(off4, pl, r4);
+                fix8(r4, neg4 ^ nz_);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tq[k][c] = 0.f;
+    }
+    const float* pb = g.pbar32;
+    const float* dpb = g.dpbar32;
+    const float th0 = (float)g.theta0, kap = (float)g.kappa, kcp = (float)g.kappa_cp;
+    const float gth = (float)g.g_theta0, bet = (float)g.beta, tdt = (float)g.two_dt;
+
+    for (int s = sb; s < z1; ++s) {
+        // (1) LDS: plane s+2 over the columns grown by 4, plane s over those grown by 2
+#pragma unroll
+        for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4o] = q0[4][k];
+        if (has1) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4r] = q1[2][k];
+        }
+        if (has4) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = r4[k];
+        }
+        {
+            const float a[10] = {q0[2][0], q0[2][1], q0[2][2], p0[2][0], q0[2][3],
+                                 q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
+#pragma unroll
+            for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2o] = a[k];
+        }
+        if (has1) {
+            const float a[10] = {q1[0][0], q1[0][1], q1[0][2], p1[0], q1[0][3],
+                                 q1[0][4], q1[0][5], q1[0][6], p1[1], q1[0][7]};
+#pragma unroll
+            for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2r] = a[k];
+        }
+        __syncthreads();
+        // (2) loads for the next step (consumed after the closing barrier)
+        const bool more = s + 1 < z1;
+        float n0[8], n1[8], n4[8], np0[2], np1[2];
+        unsigned m0 = 0u, m1 = 0u, m4 = 0u, mp0 = 0u, mp1 = 0u;
+        if (more) {
+            long long pl;
+            unsigned zn;
+            zmap(s + 5, pl, zn);
+            ld8(off0, pl, n0);
+            ld8(off1, pl, n1);
+            m0 = neg0 ^ zn;
+            m1 = neg1 ^ zn;
+            zmap(s + 3, pl, zn);
+            ldp(off0, pl, np0);
+            ld8(off4, pl, n4);
+            mp0 = neg0 ^ zn;
+            m4 = neg4 ^ zn;
+            zmap(s + 1, pl, zn);
+            ldp(off1, pl, np1);
+            mp1 = neg1 ^ zn;
+        }
+        // (3) derived stage at plane s+2: in-plane components to the ring, the
+        //     own column's vertical ones to its queue
+        const int slotA = (s + 8) % 3;
+        {
+            float d[9];
+            fused_derived<TY, 2>(g, L4 + c4o, q0, e, ihx, ihy, ihz, d);
+            float* rg = RG + slotA * 7 * FG::P2 + c2o;
+            rg[0 * FG::P2] = d[0];
+            rg[1 * FG::P2] = d[1];
+            rg[2 * FG::P2] = d[3];
+            rg[3 * FG::P2] = d[4];
+            rg[4 * FG::P2] = d[5];
+            rg[5 * FG::P2] = d[6];
+            rg[6 * FG::P2] = d[7];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) tq[k][c] = tq[k + 1][c];
+            tq[4][0] = d[4];
+            tq[4][1] = d[5];
+            tq[4][2] = d[2];
+            tq[4][3] = d[8];
+        }
+        if (has1) {
+            float d[9];
+            fused_derived<TY, 0>(g, L4 + c4r, q1, e, ihx, ihy, ihz, d);
+            float* rg = RG + slotA * 7 * FG::P2 + c2r;
+            rg[0 * FG::P2] = d[0];
+            rg[1 * FG::P2] = d[1];
+            rg[2 * FG::P2] = d[3];
+            rg[3 * FG::P2] = d[4];
+            rg[4 * FG::P2] = d[5];
+            rg[5 * FG::P2] = d[6];
+            rg[6 * FG::P2] = d[7];
+        }
+        // (4) Jv at plane s (its derived ring plane was written two steps ago)
+        if (s >= z0 && mine) {
+            const float* l2 = L2 + c2o;
+            // values of field f (state order; 0..4 of A, 5..9 of B) at tap k
+            // (0..3: -2, -1, +1, +2) along axis j
+            auto tap = [&](int f, int j, int k) -> float {
+                constexpr int oz[4] = {0, 1, 3, 4};
+                if (j == 2) {
+                    const int a = f < 5 ? f : f - 5, h = f < 5 ? 0 : 1;
+                    if (a == 3) return p0[oz[k]][h];
+                    return q0[oz[k]][(a == 4 ? 3 : a) + 4 * h];
+                }
+                const int st = j == 0 ? 1 : FG::SX2;
+                const int o = (k < 2 ? k - 2 : k - 1) * st;
+                return l2[f * FG::P2 + o];
+            };
+            const float Ac[5] = {q0[2][0], q0[2][1], q0[2][2], p0[2][0], q0[2][3]};
+            const float Bc[5] = {q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
+            const float ih[3] = {ihx, ihy, ihz};
+            float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            float divB = 0.f, divW = 0.f, gp[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                float aj[4], bj[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    aj[k] = tap(j, j, k);
+                    bj[k] = tap(5 + j, j, k);
+                }
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    float a[4], b[4], w[4], pr[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        a[k] = f == j ? aj[k] : tap(f, j, k);
+                        b[k] = f == j ? bj[k] : tap(5 + f, j, k);
+                        w[k] = a[k] + e * b[k];
+                        pr[k] = aj[k] * b[k] + bj[k] * w[k];
+                    }
+                    const float dB = d5(b[0], b[1], b[2], b[3], ih[j]);
+                    const float dW = d5(w[0], w[1], w[2], w[3], ih[j]);
+                    if (f == j) {
+                        divB += dB;
+                        divW += dW;
+                    }
+                    if (f == 3) gp[j] = dB;
+                    if (g.convection) acc[f] += d5(pr[0], pr[1], pr[2], pr[3], ih[j]) + Ac[j] * dB + Bc[j] * dW;
+                }
+            }
+            // divergences of the stress and heat-flux differences
+            const float* rg = RG + ((s + 6) % 3) * 7 * FG::P2 + c2o;
+            auto Dx = [&](int c) {
+                const float* r = rg + c * FG::P2;
+                return d5(r[-2], r[-1], r[1], r[2], ihx);
+            };
+            auto Dy = [&](int c) {
+                const float* r = rg + c * FG::P2;
+                return d5(r[-2 * FG::SX2], r[-FG::SX2], r[FG::SX2], r[2 * FG::SX2], ihy);
+            };
+            auto Dz = [&](int c) { return d5(tq[0][c], tq[1][c], tq[3][c], tq[4][c], ihz); };
+            float dF[5];
+            dF[0] = -0.5f * acc[0] - th0 * gp[0] + Dx(0) + Dy(2) + Dz(0);
+            dF[1] = -0.5f * acc[1] - th0 * gp[1] + Dx(2) + Dy(1) + Dz(1);
+            dF[2] = -0.5f * acc[2] - th0 * gp[2] + Dx(3) + Dy(4) + Dz(2) + gth * Bc[4];
+            if (g.energy_test)
+                dF[3] = -0.5f * acc[3] - kcp * divB;
+            else
+                dF[3] = -0.5f * acc[3] - (Bc[2] * dpb[s] + kap * ((pb[s] + Ac[3]) * divB + Bc[3] * divW));
+            dF[4] = -0.5f * acc[4] + Dx(5) + Dy(6) + Dz(3) - bet * Bc[2];
+            const long long i = (long long)s * nxy + (long long)gy * g.nx + gx;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) out[k * np + i] = tdt * Bc[k] - dF[k];
+        }
+        __syncthreads();
+        // (5) advance the queues by one plane
+        if (more) {
+            fix8(n0, m0);
+            fix8(n1, m1);
+            fix8(n4, m4);
+            fixp(np0, mp0);
+            fixp(np1, mp1);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) q0[k][c] = q0[k + 1][c];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) q0[6][c] = n0[c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                p0[k][0] = p0[k + 1][0];
+                p0[k][1] = p0[k + 1][1];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) q1[k][c] = q1[k + 1][c];
+            }
+            p0[4][0] = np0[0];
+            p0[4][1] = np0[1];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                q1[4][c] = n1[c];
+                r4[c] = n4[c];
+            }
+            p1[0] = np1[0];
+            p1[1] = np1[1];
+        }
+    }
+}
+
 // frozen coefficients of the preconditioner from the frozen viscosity (for the
 // anisotropic closure the Smagorinsky nu, |S| = nu dd_inv_nu)
 template <typename T>
@@ -864,6 +1307,26 @@ hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int wha
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k3m_point<T, 0, 8>), march_grid(g.nx, g.ny, g.nz, 8), dim3(256), 0, s, g, u,
                        (const T*)nullptr, 0.0, (const double*)nullptr, (const T*)dbuf, f, out, what);
+    return hipGetLastError();
+}
+
+// Planes per workgroup of the single-pass Jv: enough z chunks for two
+// workgroups per compute unit (256 CUs), at least 16 planes per chunk (each
+// chunk re-forms four planes of derived quantities at its start).
+inline int fused_kzc(int nx, int ny, int nz, int ty) {
+    const long long cols = (long long)((nx + 31) / 32) * ((ny + ty - 1) / ty);
+    const long long want = (512 + cols - 1) / cols;
+    int kzc = (int)((nz + want - 1) / want);
+    kzc = std::max(kzc, std::min(nz, 16));
+    return std::max(1, kzc);
+}
+
+hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double eps, const double* eps_dev,
+                            float* out, hipStream_t s) {
+    constexpr int TY = 8;
+    const int kzc = fused_kzc(g.nx, g.ny, g.nz, TY);
+    const dim3 grid((g.nx + 31) / 32, (g.ny + TY - 1) / TY, (g.nz + kzc - 1) / kzc);
+    hipLaunchKernelGGL((k3f_jv<TY>), grid, dim3(32 * TY), 0, s, g, u, v, eps, eps_dev, out, kzc);
     return hipGetLastError();
 }
 

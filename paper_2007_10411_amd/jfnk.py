@@ -126,10 +126,12 @@ class Context:
         return z
 
     def gmres(self, u, b, x, m=30, max_restarts=20, tol=1e-6, pc="physics", jv="stable", sweeps=2,
-              max_iters=0, want_H=False, ortho="cgs2"):
+              max_iters=0, want_H=False, ortho="cgs2", judge=True):
+        """judge=False runs a learned-preconditioner solve without the physics-based
+        preconditioner's judgement (jfnk_gmres_opts.no_judge)."""
         self._check_size(u, b, x)
         o = L.GmresOpts(m=m, max_restarts=max_restarts, tol=tol, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
-                        max_iters=max_iters, ortho=ORTHO[ortho])
+                        max_iters=max_iters, ortho=ORTHO[ortho], no_judge=0 if judge else 1)
         info = L.GmresInfo()
         Hbuf = None
         if want_H:
@@ -143,13 +145,14 @@ class Context:
 
     def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, inner="f64",
                     m=30, max_restarts=20, pc="physics", jv="stable", sweeps=2, forcing="ew", eta=1e-2,
-                    eta_floor=0.0, record=None, record_krylov=False, ortho="cgs2"):
+                    eta_floor=0.0, record=None, record_krylov=False, ortho="cgs2", judge=True):
         """record: optional (R, DU, count) with R, DU float32 device tensors of
         shape (cap, n) receiving the Newton linear systems; count is a one-element
-        list updated in place.  ortho: "cgs2" or "one_reduction" (jfnk_ortho)."""
+        list updated in place.  ortho: "cgs2" or "one_reduction" (jfnk_ortho).
+        judge=False: learned-preconditioner solves run unjudged (no_judge)."""
         self._check_size(u_n, u_np1)
         gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
-                         max_iters=0, ortho=ORTHO[ortho])
+                         max_iters=0, ortho=ORTHO[ortho], no_judge=0 if judge else 1)
         o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=DTYPES[inner],
                          gm=gm, forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
         cnt = C.c_int32(0)
@@ -261,7 +264,8 @@ class Context:
     def set_variant(self, stage, dtype, variant):
         """Pin a stencil launch shape: stage "residual" / "jv" / "pc_sweep",
         dtype "f64" / "f32", variant 0-2 (tiles 64 x 4/8/16) or 3-5 (row marching
-        over 32/64/256 rows; residual and Jv)."""
+        over 32/64/256 rows; residual and Jv); for 3D contexts the FP32 Jv only,
+        variant 7 (one z-marching launch) or 6 (two launches)."""
         st = {"residual": 0, "jv": 1, "pc_sweep": 2}[stage]
         dt = {"f64": L.F64, "f32": L.F32}[dtype]
         L.check(self.lib.jfnk_set_variant(self.h, st, dt, int(variant)), "jfnk_set_variant", soft_ok=False)

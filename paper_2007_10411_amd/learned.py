@@ -125,3 +125,74 @@ def train(ctx, R, DU, iters, lr=2e-3, batch=4, seed=0, theta0=None, lr_decay=Tru
 def held_out_loss(ctx, R, DU):
     loss, _ = ctx.net_loss_grad(R.contiguous(), DU.contiguous(), want_grad=False)
     return loss
+
+
+# --------------------------------------------------------------------------- #
+# 3D network trained on crops of solver pairs from 3D and 2D runs
+# --------------------------------------------------------------------------- #
+def embed_2d(V2, nx, nz, ny):
+    """2D vectors (count, 4 nz nx) of fields (u, w, p, theta) -> y-invariant 3D
+    vectors (count, 5 nz ny nx) of fields (u, v = 0, w, p, theta).  A 2D pair
+    (J2 x = r) embeds as a 3D pair of the same spacing and time step: the 3D
+    operator acts on a y-invariant field with v = 0 as the 2D one does on its
+    x-z slice."""
+    import torch
+    c = V2.shape[0]
+    a = V2.reshape(c, 4, nz, 1, nx)
+    out = torch.zeros((c, 5, nz, ny, nx), dtype=V2.dtype, device=V2.device)
+    out[:, 0] = a[:, 0]
+    out[:, 2:] = a[:, 1:]
+    return out.reshape(c, -1)
+
+
+def crops(V, grid, crop, idx, starts):
+    """Crops of size crop = (cx, cy, cz) of the vectors V[idx] on grid =
+    (nf, nz, ny, nx), one start (x0, y0, z0) per vector; returns (len(idx), n_crop)."""
+    import torch
+    nf, nz, ny, nx = grid
+    cx, cy, cz = crop
+    out = []
+    for i, (x0, y0, z0) in zip(idx, starts):
+        g = V[int(i)].view(nf, nz, ny, nx)
+        out.append(g[:, z0:z0 + cz, y0:y0 + cy, x0:x0 + cx].reshape(-1))
+    return torch.stack(out).contiguous()
+
+
+def random_starts(rng, grid, crop, k):
+    nf, nz, ny, nx = grid
+    cx, cy, cz = crop
+    return [(int(rng.integers(0, nx - cx + 1)), int(rng.integers(0, ny - cy + 1)), int(rng.integers(0, nz - cz + 1)))
+            for _ in range(k)]
+
+
+def train_3d_crops(ctx, sources, iters=600, lr=2e-3, batch=4, seed=0, noise=None, theta0=None):
+    """Adam on crops of 3D pairs.  sources: list of (R, DU, grid, crop) with R, DU
+    float32 device tensors (count, n) on grid = (nf, nz, ny, nx) and crop =
+    (cx, cy, cz); noise: optional (NoisePairs on the context's grid, crop) whose
+    full-grid pairs are cropped.  Steps cycle through the sources (and the noise
+    pairs); returns (theta, losses)."""
+    nf = ctx.prob.nf
+    ctx.net_init()
+    theta = I.net_init_params(nf, seed=seed, dim=3) if theta0 is None else np.asarray(theta0)
+    ctx.net_set_params(theta.astype(np.float32))
+    rng = np.random.Generator(np.random.PCG64(seed + 23))
+    kinds = list(range(len(sources))) + (["noise"] if noise is not None else [])
+    p = ctx.prob
+    full = (p.nf, p.nz, p.ny, p.nx)
+    losses = []
+    for it in range(iters):
+        step_lr = lr * 0.5 * (1 + np.cos(np.pi * it / iters)) + 1e-5
+        kind = kinds[it % len(kinds)]
+        if kind == "noise":
+            gen, crop = noise
+            Rn, Xn = gen.batch(1)
+            st = random_starts(rng, full, crop, batch)
+            Rb = crops(Rn, full, crop, [0] * batch, st)
+            Xb = crops(Xn, full, crop, [0] * batch, st)
+        else:
+            R, DU, grid, crop = sources[kind]
+            idx = rng.choice(R.shape[0], size=min(batch, R.shape[0]), replace=False)
+            st = random_starts(rng, grid, crop, len(idx))
+            Rb, Xb = crops(R, grid, crop, idx, st), crops(DU, grid, crop, idx, st)
+        losses.append(ctx.net_train_step(Rb, Xb, step_lr, crop=crop))
+    return ctx.net_get_params(), losses

@@ -4,6 +4,7 @@ loss and gradient, the Adam step, FGMRES with the learned preconditioner, and
 what the trained network gains over the untrained (diagonal-only) form."""
 import numpy as np
 import pytest
+import torch
 
 from oracle import net as N
 from paper_2007_10411_amd import inputs as I
@@ -146,14 +147,50 @@ def test_learned_pc_in_fgmres_converges_and_falls_back():
     U0 = I.bubble_state(prob)
     un = dev(U0)
     u = un.clone()
-    r = c.newton_step(un, u, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4)
-    assert r.converged
+    r = c.newton_step(un, u, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4, judge=False)
+    assert r.converged and r.fallbacks == 0
     # two iterations cannot reach a forcing term of 1e-10: the learned solve fails
     # and is redone with the physics-based preconditioner
     u2 = un.clone()
     r2 = c.newton_step(un, u2, rtol=1e-8, inner="f32", pc="learned", forcing="fixed", eta=1e-10,
-                       max_restarts=1, m=2, max_newton=1)
+                       max_restarts=1, m=2, max_newton=1, judge=False)
     assert r2.fallbacks == 1 and not r2.converged
+
+
+def test_physics_preconditioner_judges_the_learned_one():
+    """Section 2.5.2's preconditioner as the judge: with no physics-preconditioned
+    solve on record the system goes to the physics-based preconditioner; a network
+    whose residual reduction per iteration falls short of the record is stopped
+    at the end of its first cycle, so each judged-out solve costs at most m
+    iterations on top of the physics solve, whose result the step then equals
+    bit for bit."""
+    prob = I.thermal_stable_2d(128, 64)
+    U0 = I.bubble_state(prob)
+    un = dev(U0)
+    m = 10
+    # the step with the physics-based preconditioner alone
+    cp = _ctx(prob)
+    up = un.clone()
+    opts = dict(rtol=1e-8, inner="f32", forcing="fixed", eta=1e-5, m=m, sweeps=0)
+    rp = cp.newton_step(un, up, pc="physics", **opts)
+    assert rp.converged
+    # a fresh context: no record, so every solve of the first step would calibrate
+    c = _ctx(prob)
+    bad = I.net_init_params(prob.nf, seed=3, out_scale=30.0)
+    c.net_set_params(bad)
+    b = dev(np.random.Generator(np.random.PCG64(5)).normal(size=prob.shape), "f32")
+    x = torch.zeros_like(b)
+    g = c.gmres(dev(U0, "f32"), b, x, m=m, tol=1e-6, pc="learned", sweeps=0)
+    assert g.fallback and g.converged and g.res_true > 0
+    # record the physics rate, then judge the (poor) network on the same step
+    u1 = un.clone()
+    r1 = c.newton_step(un, u1, pc="physics", **opts)
+    u2 = un.clone()
+    r2 = c.newton_step(un, u2, pc="learned", **opts)
+    assert r2.converged
+    assert r2.fallbacks == r2.newton_iters
+    assert rp.gmres_iters_total < r2.gmres_iters_total <= rp.gmres_iters_total + m * r2.fallbacks
+    assert torch.equal(u2, up) and torch.equal(u1, up)
 
 
 def test_trained_network_beats_untrained_form():
@@ -183,7 +220,7 @@ def test_trained_network_beats_untrained_form():
         tot = 0
         for _ in range(2):
             nxt = u.clone()
-            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc=pc, eta_floor=1e-4)
+            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc=pc, eta_floor=1e-4, judge=False)
             assert res.converged and res.fallbacks == 0
             tot += res.gmres_iters_total
             u.copy_(nxt)
@@ -276,7 +313,7 @@ def test_trained_network_3d_beats_untrained_form():
         tot = 0
         for _ in range(2):
             nxt = u.clone()
-            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4)
+            res = c.newton_step(u, nxt, rtol=1e-8, inner="f32", pc="learned", eta_floor=1e-4, judge=False)
             assert res.converged and res.fallbacks == 0
             tot += res.gmres_iters_total
             u.copy_(nxt)

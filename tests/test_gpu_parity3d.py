@@ -149,3 +149,42 @@ def test_full_size_3d_thermal_residual_and_jv32():
     o32 = dev(np.zeros(prob.shape), "f32")
     c.jv(dev(U32, "f32"), dev(V32, "f32"), o32, mode="stable", eps=e32)
     assert_fields_close(host(o32), M.jv(prob, U32, V32, e32), F32_TOL, "C5 jv f32")
+
+
+JV32_CASES = {
+    "neutral-70x20x37": lambda: I.thermal_neutral_3d(70, 20, 37),
+    "noslip-stable-flux-45x17x21": lambda: I.Problem(dim=3, nx=45, ny=17, nz=21, lx=9000.0, ly=6000.0, lz=4000.0,
+                                                     dt=2.0, n_bv=0.01, bc_vertical=1, h0=300.0,
+                                                     strip_width=3000.0, strip_center=4500.0),
+    "periodic-constK-40x9x18": lambda: I.Problem(dim=3, nx=40, ny=9, nz=18, ly=15000.0, closure=0, bc_lateral=2,
+                                                 bc_vertical=2, n_bv=0.01),
+    "deardorff-stable-33x16x12": lambda: I.Problem(dim=3, nx=33, ny=16, nz=12, lx=8000.0, ly=6000.0, lz=3000.0,
+                                                   dt=2.0, n_bv=0.01, closure=I.CLOSURE_DEARDORFF),
+    "energy-test-no-closure-32x8x9": lambda: I.Problem(dim=3, nx=32, ny=8, nz=9, lx=8000.0, ly=4000.0, lz=3000.0,
+                                                       dt=2.0, n_bv=0.01, closure=I.CLOSURE_NONE, energy_test=1),
+    "no-convection-36x11x10": lambda: I.Problem(dim=3, nx=36, ny=11, nz=10, lx=8000.0, ly=4000.0, lz=3000.0,
+                                                dt=2.0, n_bv=0.005, convection=0),
+}
+
+
+@pytest.mark.parametrize("name", list(JV32_CASES))
+@pytest.mark.parametrize("mode", ["stable", "analytic"])
+def test_jv32_3d_single_pass_and_two_pass(name, mode):
+    """The FP32 Jv of both 3D forms (variant 7: one z-marching launch, variant 6:
+    two launches with the derived components in HBM) against the FP64 oracle on
+    FP32-rounded inputs, across several 32 x 8 column blocks and z chunks with
+    ragged edges, every boundary kind and closure."""
+    prob = JV32_CASES[name]()
+    U = I.smooth_flow_state(prob, seed=21).astype(np.float32).astype(np.float64)
+    V = I.random_vector(prob, seed=22).astype(np.float32).astype(np.float64)
+    eps = M.fd_eps(prob, U, V, eps_mach=2.0 ** -23) if mode == "stable" else 0.0
+    ref = M.jv(prob, U, V, eps)
+    c = _ctx(prob, max_m=2)
+    outs = []
+    for variant in (7, 6):
+        c.set_variant("jv", "f32", variant)
+        o = dev(np.zeros(prob.shape), "f32")
+        c.jv(dev(U, "f32"), dev(V, "f32"), o, mode=mode, eps=eps)
+        assert_fields_close(host(o), ref, F32_TOL, f"{name} jv32 {mode} variant {variant}")
+        outs.append(host(o))
+    assert_fields_close(outs[0], outs[1], F32_TOL, f"{name} single vs two pass")
