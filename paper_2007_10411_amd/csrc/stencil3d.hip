@@ -717,12 +717,13 @@ __device__ __forceinline__ void fused_derived(const Geo& g, const float* __restr
     for (int k = 0; k < 6; ++k) SW[k] = SA[k] + e * SB[k];
     Coef<float> ka = {0.f, 0.f, 0.f, 0.f}, dk = {0.f, 0.f, 0.f, 0.f};
     if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
-        const float ma = sqrtf(frob3(SA, SA)), mw = sqrtf(frob3(SW, SW));
+        // hardware square root and reciprocal (1 ulp): well inside the FP32 parity bar
+        const float ma = __builtin_amdgcn_sqrtf(frob3(SA, SA)), mw = __builtin_amdgcn_sqrtf(frob3(SW, SW));
         const float den = ma + mw;
         const float num = 2.f * frob3(SA, SB) + e * frob3(SB, SB);
         if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
             const float c = float(g.smag) * 1.4142135623730951f;
-            const float nu = c * ma, dnu = den > 0.f ? c * num / den : 0.f;
+            const float nu = c * ma, dnu = den > 0.f ? c * num * __builtin_amdgcn_rcpf(den) : 0.f;
             const float ip = float(g.inv_pr);
             ka = {nu, nu, nu * ip, nu * ip};
             dk = {dnu, dnu, dnu * ip, dnu * ip};
@@ -746,7 +747,7 @@ __device__ __forceinline__ void fused_derived(const Geo& g, const float* __restr
 }
 
 template <int TY>
-__global__ __launch_bounds__(32 * TY, 2) void k3f_jv(Geo g, const float* __restrict__ u, const float* __restrict__ v,
+__global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict__ u, const float* __restrict__ v,
                                                      double eps_in, const double* __restrict__ eps_dev,
                                                      float* __restrict__ out, int kzc) {
     using FG = FusedGeom<TY>;
@@ -1310,12 +1311,13 @@ hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int wha
     return hipGetLastError();
 }
 
-// Planes per workgroup of the single-pass Jv: enough z chunks for two
-// workgroups per compute unit (256 CUs), at least 16 planes per chunk (each
-// chunk re-forms four planes of derived quantities at its start).
+// Planes per workgroup of the single-pass Jv: enough z chunks for one
+// workgroup per compute unit (256 CUs; a 32 x 16 workgroup holds 120 KB of
+// LDS), at least 16 planes per chunk (each chunk re-forms four planes of
+// derived quantities at its start).
 inline int fused_kzc(int nx, int ny, int nz, int ty) {
     const long long cols = (long long)((nx + 31) / 32) * ((ny + ty - 1) / ty);
-    const long long want = (512 + cols - 1) / cols;
+    const long long want = (256 + cols - 1) / cols;
     int kzc = (int)((nz + want - 1) / want);
     kzc = std::max(kzc, std::min(nz, 16));
     return std::max(1, kzc);
@@ -1323,7 +1325,7 @@ inline int fused_kzc(int nx, int ny, int nz, int ty) {
 
 hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double eps, const double* eps_dev,
                             float* out, hipStream_t s) {
-    constexpr int TY = 8;
+    constexpr int TY = 16;
     const int kzc = fused_kzc(g.nx, g.ny, g.nz, TY);
     const dim3 grid((g.nx + 31) / 32, (g.ny + TY - 1) / TY, (g.nz + kzc - 1) / kzc);
     hipLaunchKernelGGL((k3f_jv<TY>), grid, dim3(32 * TY), 0, s, g, u, v, eps, eps_dev, out, kzc);
