@@ -368,6 +368,22 @@ int jfnk_batch_newton_step(jfnk_batch* batch, const double* u_n, double* u_np1, 
  * 16); tile_rows (HOST, 3 entries, may be NULL) receives the choices.           */
 int jfnk_batch_tune(jfnk_batch* batch, int32_t* tile_rows);
 
+/* ---- Jv without a context, allocating nothing -------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same product as
+ * jfnk_jv (STABLE or ANALYTIC mode, the context-free default launch shape) for
+ * the problem *prob, enqueued on hip_stream (NULL: the null stream) without
+ * creating a context: u, v and Jv are the caller's device arrays; the
+ * background profiles and the reductions of the automatic step (eps <= 0) use
+ * a fixed per-GPU array of the library (about 115 KB, held until the process
+ * ends) and no call allocates or frees memory.  Limits: nz <= 4096; 3D problems
+ * in FP32 with dd_p = 2 only.  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams or host threads) race; calls
+ * enqueued on one stream are ordered.  Errors: JFNK_ERR_ARG (invalid argument
+ * or a limit exceeded), JFNK_ERR_HIP.                                          */
+int jfnk_jv_noalloc(const jfnk_problem* prob, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v,
+                    double eps, void* Jv, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTS = ["jfnk_create", "jfnk_destroy", "jfnk_last_error", "jfnk_set_stream", 
            "jfnk_net_init", "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_apply",
            "jfnk_nlpc_residual", "jfnk_nlpc_step", "jfnk_net_set_loss", "jfnk_net_loss_grad", "jfnk_net_train_step", "jfnk_tune", "jfnk_set_variant",
            "jfnk_batch_create", "jfnk_batch_destroy", "jfnk_batch_size", "jfnk_batch_apply_F",
-           "jfnk_batch_newton_step", "jfnk_batch_tune"]
+           "jfnk_batch_newton_step", "jfnk_batch_tune", "jfnk_jv_noalloc"]
 
 
 class Problem(C.Structure):
@@ -113,6 +113,7 @@ def load():
     L.jfnk_batch_apply_F.argtypes = [vp, C.c_int32, vp, vp, vp]
     L.jfnk_batch_newton_step.argtypes = [vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)]
     L.jfnk_batch_tune.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.jfnk_jv_noalloc.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, vp, vp, C.c_double, vp, vp]
     for name in EXPORTS:
         if name != "jfnk_last_error":
             getattr(L, name).restype = C.c_int

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -176,7 +177,7 @@ __global__ void k_background(Geo g, jfnk_problem p, double* pbar, double* dpbar,
         dpbar32[t] = (float)dpb;
     }
     const int nxy = g.nx * g.ny;
-    if (t < nxy) {
+    if (sflux && t < nxy) {
         // the cell centre is rounded on its own, as the strip definition reads
         // (no multiply-add fused into the strip test, whose edges can fall
         // exactly on a centre)
@@ -1586,3 +1587,107 @@ int jfnk_net_train_step(jfnk_ctx* c, const float* r, const float* du, int32_t ba
 }
 
 }  // extern "C"
+
+// ---- Jv without a context, allocating nothing ------------------------------
+// The device memory this entry point needs beyond its inputs and output (the
+// background profiles p_bar, dp_bar/dz of both precisions, the partial sums and
+// scalars of the finite-difference step) is a fixed file-scope array, one copy
+// per GPU, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's name
+// in host code is not a device address).
+constexpr int kNoAllocMaxNz = 4096;
+constexpr int kNoAllocScalars = 8;
+constexpr long long kNoAllocDoubles =
+    2LL * kNoAllocMaxNz + kNoAllocMaxNz /* two float profiles */ + kMaxPartials + kNoAllocScalars;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch array (looked up once per device)
+int scratch_ptr(double** out) {
+    int dev = 0;
+    JFNK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index out of range for the no-allocation scratch table");
+        return JFNK_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        JFNK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned no address for the scratch array");
+            return JFNK_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return JFNK_OK;
+}
+}  // namespace
+
+extern "C" int jfnk_jv_noalloc(const jfnk_problem* p, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v,
+                               double eps, void* Jv, void* hip_stream) {
+    std::string why;
+    if (!p || !u || !v || !Jv || (mode != JFNK_JV_STABLE && mode != JFNK_JV_ANALYTIC) ||
+        (dt != JFNK_F64 && dt != JFNK_F32) || !valid_problem(p, why)) {
+        set_error("invalid argument to jfnk_jv_noalloc" + (why.empty() ? std::string() : ": " + why));
+        return JFNK_ERR_ARG;
+    }
+    if (p->nz > kNoAllocMaxNz) {
+        set_error("jfnk_jv_noalloc: nz exceeds " + std::to_string(kNoAllocMaxNz));
+        return JFNK_ERR_ARG;
+    }
+    if (p->dim == 3 && (dt != JFNK_F32 || p->dd_p != 2)) {
+        set_error("jfnk_jv_noalloc: 3D problems take the FP32 single-pass Jv (dd_p = 2) only");
+        return JFNK_ERR_ARG;
+    }
+    double* sp = nullptr;
+    int rc = scratch_ptr(&sp);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Geo g;
+    fill_geo(*p, g);
+    double* pb64 = sp;
+    double* dpb64 = sp + kNoAllocMaxNz;
+    float* pb32 = (float*)(sp + 2 * kNoAllocMaxNz);
+    float* dpb32 = pb32 + kNoAllocMaxNz;
+    double* partials = sp + 3 * kNoAllocMaxNz;
+    double* scal = partials + kMaxPartials;   // ||u||^2, ||v||^2, eps
+    g.pbar64 = pb64;
+    g.dpbar64 = dpb64;
+    g.sflux64 = nullptr;                      // the surface source does not enter Jv
+    g.pbar32 = pb32;
+    g.dpbar32 = dpb32;
+    g.sflux32 = nullptr;
+    hipLaunchKernelGGL(k_background, dim3((g.nz + 255) / 256), dim3(256), 0, st, g, *p, pb64, dpb64, (double*)nullptr,
+                       pb32, dpb32, (float*)nullptr);
+    JFNK_HIP(hipGetLastError());
+    const long long n = (long long)(p->dim == 3 ? 5 : 4) * g.npts;
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        const double* edev = nullptr;
+        if (mode == JFNK_JV_STABLE && !(eps > 0)) {
+            const int nb = red_blocks(n);
+            JFNK_HIP(launch_norm2_partial<T>((const T*)u, n, partials, nb, st));
+            JFNK_HIP(launch_reduce_partials(partials, nb, 1, 1, scal, 0, st));
+            JFNK_HIP(launch_norm2_partial<T>((const T*)v, n, partials, nb, st));
+            JFNK_HIP(launch_reduce_partials(partials, nb, 1, 1, scal + 1, 0, st));
+            JFNK_HIP(launch_fd_eps(scal, scal + 1, std::sqrt(eps_mach<T>()), std::sqrt((double)n), scal + 2, st));
+            edev = scal + 2;
+        }
+        const double e = mode == JFNK_JV_ANALYTIC ? 0.0 : eps;
+        if constexpr (std::is_same<T, float>::value) {
+            if (g.dim == 3) {
+                JFNK_HIP(launch3_jv_fused(g, (const float*)u, (const float*)v, e, edev, (float*)Jv, st));
+                return JFNK_OK;
+            }
+        }
+        JFNK_HIP(launch_jv<T>(g, (const T*)u, (const T*)v, e, edev, (T*)Jv, st, 1));
+        return JFNK_OK;
+    };
+    return dt == JFNK_F64 ? run(double(0)) : run(float(0));
+}

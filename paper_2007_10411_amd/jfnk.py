@@ -63,6 +63,23 @@ class NewtonResult:
     fallbacks: int = 0
 
 
+def jv_noalloc(prob, u, v, out, mode="stable", eps=0.0, stream=None):
+    """``jfnk_jv_noalloc``: Jv of ``prob`` without a context; no device memory is
+    allocated (the library's fixed per-GPU scratch array holds the background
+    profiles and reductions)."""
+    torch = _torch()
+    lib = L.load()
+    n = prob.n
+    for t in (u, v, out):
+        if t.numel() != n:
+            raise ValueError(f"expected {n} elements, got {t.numel()}")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ps = L.problem_struct(prob)
+    L.check(lib.jfnk_jv_noalloc(C.byref(ps), _dcode(u), JVS[mode], _ptr(u), _ptr(v), float(eps), _ptr(out),
+                                C.c_void_p(s.cuda_stream)), "jfnk_jv_noalloc", soft_ok=False)
+    return out
+
+
 class Context:
     """One problem on the current device (``jfnk_create`` / ``jfnk_destroy``)."""
 
