@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--micro-pin", default="", help="the same for the 2D micro-benchmark contexts")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--micro-reps", type=int, default=20)
+    ap.add_argument("--micro-cases", default="3d_256x256x128,2d_8192x8192,2d_8192x8192_p3",
+                    help="kernel micro-benchmark cases to run")
     return ap.parse_args()
 
 
@@ -336,12 +338,14 @@ def jv_kernel_name(rows):
     return f"k_jv_2d<float, 64, {rows}>"
 
 
-def kernel_micro(torch, I, L, Context, reps, pins=None):
+def kernel_micro(torch, I, L, Context, reps, pins=None, names=None):
     """Residual, Jv and physics-preconditioner kernels alone at sizes beyond the
     Infinity Cache."""
     out = {}
     cases = [("3d_256x256x128", I.thermal_neutral_3d()), ("2d_8192x8192", I.thermal_stable_2d(8192, 8192)),
              ("2d_8192x8192_p3", I.thermal_stable_2d(8192, 8192).replace(dd_p=3))]
+    if names:
+        cases = [c for c in cases if c[0] in names]
     for name, prob in cases:
         ctx = Context(prob, max_m=1)
         shapes = ctx.tune()
@@ -448,7 +452,8 @@ def train_learned_3d(torch, I, LRN, Context, ctx, u, iters, sweeps):
     t2 = time.perf_counter()
     info = {"pairs_3d": int(R3.shape[0]), "pairs_2d": int(R2e.shape[0]), "crop_3d": list(crop3),
             "crop_2d_embedded": [128, ny2, 64], "collect_s": t1 - t0, "train_s": t2 - t1, "adam_steps": iters,
-            "loss_first": float(losses[0]), "loss_last": float(sum(losses[-30:]) / min(30, len(losses)))}
+            "loss_first": float(losses[0]), "loss_last": float(sum(losses[-30:]) / min(30, len(losses))),
+            "loss_every_100": [float(x) for x in losses[::100]]}
     del R3, DU3, R2e, DU2e
     torch.cuda.empty_cache()
     return theta, info
@@ -471,7 +476,8 @@ def main():
         from paper_2007_10411_amd.jfnk import Context
         torch.cuda.set_device(0)
         print(json.dumps({"kernel_micro": kernel_micro(torch, I, L, Context, args.micro_reps,
-                                                       parse_shapes(args.micro_pin))}), flush=True)
+                                                       parse_shapes(args.micro_pin),
+                                                       args.micro_cases.split(","))}), flush=True)
         return
     import numpy as np
     import torch
@@ -509,13 +515,18 @@ def main():
         log(f"timing {steps['plain']} plain FP64 steps")
         legs["plain"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["plain"], **opts["plain"])
     train_info = None
+    learned_error = None
     if "learned" in legs_wanted:
         log("recording solver pairs and training the 3D network")
         theta, train_info = train_learned_3d(torch, I, LRN, Context, ctx, u, args.train_iters, args.pc_sweeps)
         # the judge's record: one physics-preconditioned step of the timed configuration
         run_steps(ctx, u.clone(), 1, torch, **opts["mixed"])
         log(f"timing {steps['learned']} learned steps")
-        legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
+        try:
+            legs["learned"] = timed_leg(ctx, u, steps["learned"], torch, L, classes["learned"], **opts["learned"])
+        except RuntimeError as ex:            # reported in the line, not hidden
+            learned_error = str(ex)
+            log(f"learned leg failed: {ex}")
     del ctx
     torch.cuda.empty_cache()
 
@@ -624,6 +635,7 @@ def main():
             "plain_ms_over_learned_ms": (leg_summary["plain"]["ms_per_step"] / leg_summary["learned"]["ms_per_step"]
                                          if "plain" in legs and "learned" in legs else None),
             "training_3d": train_info,
+            "learned_error": learned_error,
             "legs_2d": legs_2d,
             "learned_256x128": small,
             "ensemble_64_heat_island": ensemble,
@@ -641,7 +653,8 @@ def main():
         del legs
         torch.cuda.empty_cache()
         log("kernel micro-benchmark (3D 256x256x128, 2D 8192x8192)")
-        micro = kernel_micro(torch, I, L, Context, args.micro_reps, parse_shapes(args.micro_pin))
+        micro = kernel_micro(torch, I, L, Context, args.micro_reps, parse_shapes(args.micro_pin),
+                             args.micro_cases.split(","))
         out["kernel_micro"] = micro
     if not args.no_cpu:
         log(f"cpu baseline ({args.cpu_seconds} s per process)")

@@ -99,8 +99,8 @@ typedef enum { JFNK_BC_FREE_SLIP = 0, JFNK_BC_NO_SLIP_BOTTOM = 1, JFNK_BC_PERIOD
  * convection = 0 drops the convective terms; energy_test = 1 replaces
  * kappa (p_bar + p') by kappa cp and drops w dp_bar/dz (a frozen-coefficient
  * operator that conserves a quadratic energy).  dd_p is the order parameter of
- * the Deslauriers-Dubuc derivative (section 2.3): 2 (5 points) or, for 2D
- * problems outside a batch, 3 (9 points; halos twice as deep).                  */
+ * the Deslauriers-Dubuc derivative (section 2.3): 2 (5 points) or, outside a
+ * batch, 3 (9 points; halos twice as deep).                                     */
 typedef struct {
     int32_t dim, nx, ny, nz;          /* 2 or 3; grid points per direction (ny = 1 in 2D) */
     double lx, ly, lz, dt;            /* domain [m], time step [s]                       */
@@ -215,18 +215,20 @@ int jfnk_precond_apply(jfnk_ctx* ctx, jfnk_pc_kind pc, jfnk_dtype dt, const void
  * solve of this context is on record and stops at the end of the first cycle
  * whose mean log residual reduction per iteration falls short of that solve's;
  * the system is then solved with the physics-based preconditioner, as it is when
- * no record exists or the learned solve does not converge (info->fallback = 1).
- * Every converged physics-preconditioned solve (here or inside
- * jfnk_newton_step) updates the record.                                          */
+ * no record exists or the learned solve does not converge or breaks down (a
+ * non-finite Krylov vector or solution) (info->fallback = 1).  Every converged
+ * physics-preconditioned solve (here or inside jfnk_newton_step) updates the
+ * record.                                                                         */
 int jfnk_gmres(jfnk_ctx* ctx, jfnk_dtype dt, const void* u, const void* rhs, void* x,
                const jfnk_gmres_opts* opts, jfnk_gmres_info* info);
 
 /* One trapezoidal step by inexact Newton (equation 8): u_np1 holds the initial
  * guess on entry (usually a copy of u_n) and the solution on return.  FP64 outer
  * residual, update and norms; inner Krylov solve in opts->inner, each judged as in
- * jfnk_gmres when the learned preconditioner is asked for (info->fallbacks counts
- * the solves the physics-based one took over; the learned attempts' iterations
- * count in gmres_iters_total).                                                    */
+ * jfnk_gmres when the learned preconditioner is asked for; after a solve in which
+ * the learned preconditioner fell back, the remaining solves of the step use the
+ * physics-based one (info->fallbacks counts the solves it took over; the learned
+ * attempts' iterations count in gmres_iters_total).                               */
 int jfnk_newton_step(jfnk_ctx* ctx, const double* u_n, double* u_np1,
                      const jfnk_newton_opts* opts, jfnk_newton_info* info);
 
@@ -328,7 +330,8 @@ typedef enum { JFNK_NET_LOSS_SOLUTION = 0, JFNK_NET_LOSS_REST_JACOBIAN = 1 } jfn
 int jfnk_net_set_loss(jfnk_ctx* ctx, int32_t kind);
 /* Mean over a batch of pairs (r_b, du_b) (batch consecutive state vectors) of the
  * selected loss (to a host double) and its gradient (to a HOST float array of
- * n_params, or NULL), FP32 forward and backward.                                 */
+ * n_params, or NULL), FP32 forward and backward.  A pair with du = 0 (nothing
+ * to be relative to) contributes zero loss and gradient.                        */
 int jfnk_net_loss_grad(jfnk_ctx* ctx, const float* r, const float* du, int32_t batch, double* loss,
                        float* grad_host);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on that loss;

@@ -676,22 +676,35 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
 // stops at the end of the first cycle whose mean log residual reduction per
 // iteration falls short of that solve's; the system is then solved again with
 // the physics-based preconditioner, as it is when no record exists or the
-// learned solve does not converge (gi->fallback = 1, the learned attempt's
-// iterations added to *spent).  go.no_judge runs the learned solve unjudged,
-// falling back only when it does not converge.  Every physics-preconditioned
-// solve that converges updates the record.
+// learned solve does not converge or breaks down (gi->fallback = 1, the learned
+// attempt's iterations added to *spent).  Once a judged learned solve has
+// fallen back, *benched (when given) keeps the remaining solves of the caller's
+// step on the physics-based preconditioner.  go.no_judge runs the learned solve
+// unjudged, falling back only when it does not converge.  Every
+// physics-preconditioned solve that converges updates the record.
 template <typename T>
-int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, jfnk_gmres_info* gi, int* spent) {
+int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, jfnk_gmres_info* gi, int* spent,
+                 bool* benched = nullptr) {
     gi->fallback = 0;
     gi->res_true = -1.0;
     if (go.pc == JFNK_PC_LEARNED) {
-        if (go.no_judge || c->judge_rate < 0.0) {
+        if (go.no_judge || (c->judge_rate < 0.0 && !(benched && *benched))) {
             c->judge_active = go.no_judge ? 0.0 : c->judge_rate;
             c->judged_out = false;
-            const int rc = gmres_impl<T>(c, u, b, x, go, gi);
+            int rc = gmres_impl<T>(c, u, b, x, go, gi);
             c->judge_active = 0.0;
-            if (rc < 0 || (rc == JFNK_OK && !c->judged_out)) return rc;
+            if (rc < 0 && rc != JFNK_ERR_NONFINITE) return rc;   // a non-finite learned solve falls back
+            if (rc == JFNK_OK && !c->judged_out) {
+                // a nonlinear preconditioner can break the Arnoldi process down
+                // (a direction with a vanishing image): accept only a finite x
+                double x2 = 0.0;
+                if ((rc = norm2_to<T>(c, x, c->n, sc(c, S_TMP)))) return rc;
+                if ((rc = read_scalars(c, S_TMP, 1))) return rc;
+                x2 = c->hscal[S_TMP];
+                if (std::isfinite(x2)) return JFNK_OK;
+            }
             if (spent) *spent += gi->iters;
+            if (benched && !go.no_judge) *benched = true;
         }
         gi->fallback = 1;
         go.pc = JFNK_PC_PHYSICS;
@@ -769,8 +782,7 @@ bool valid_problem(const jfnk_problem* p, std::string& why) {
         return why = "grid below 8 points in a direction (or ny != 1 in 2D)", false;
     if (p->dim == 3 && !(p->ly > 0)) return why = "non-positive domain size", false;
     if (!(p->dt > 0) || !(p->lx > 0) || !(p->lz > 0)) return why = "non-positive dt or domain size", false;
-    if (p->dd_p != 2 && !(p->dd_p == 3 && p->dim == 2))
-        return why = "dd_p must be 2 (or 3 for 2D problems)", false;
+    if (p->dd_p != 2 && p->dd_p != 3) return why = "dd_p must be 2 or 3", false;
     if (p->bc_lateral != JFNK_BC_FREE_SLIP && p->bc_lateral != JFNK_BC_PERIODIC)
         return why = "bc_lateral must be free-slip or periodic", false;
     if (p->bc_vertical < 0 || p->bc_vertical > 2) return why = "invalid bc_vertical", false;
@@ -894,7 +906,7 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     ALLOC(c->t64b, nb64);
     ALLOC(c->b64, nb64);
     ALLOC(c->x64, nb64);
-    const size_t next = (size_t)(g.nx + 2 * g.W) * (g.nz + 2 * g.W) * (g.dim == 3 ? (g.ny + 4) : 1);
+    const size_t next = (size_t)(g.nx + 2 * g.W) * (g.nz + 2 * g.W) * (g.dim == 3 ? (g.ny + 2 * g.W) : 1);
     ALLOC(c->nu64, next * sizeof(double));
     ALLOC(c->u32, nb32);
     ALLOC(c->b32, nb32);
@@ -1154,6 +1166,7 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
     }
     double rprev = r0, eta = 0.5;
     bool converged = false;
+    bool benched = false;   // the learned preconditioner fell short earlier in this step
     int k = 0;
     for (;; ++k) {
         if (!std::isfinite(rn)) {
@@ -1198,7 +1211,7 @@ int jfnk_newton_step(jfnk_ctx* c, const double* u_n, double* u, const jfnk_newto
         } else {
             JFNK_HIP(launch_cast<float, double>(c->u32, u, n, 1.0, s));
             JFNK_HIP(launch_cast<float, double>(c->b32, c->R64, n, -1.0, s));
-            rc = krylov_solve<float>(c, c->u32, c->b32, c->x32, go, &gi, &inf.gmres_iters_total);
+            rc = krylov_solve<float>(c, c->u32, c->b32, c->x32, go, &gi, &inf.gmres_iters_total, &benched);
             if (go.pc == JFNK_PC_LEARNED && gi.fallback) inf.fallbacks++;
             if (rc < 0) return rc;
             if (rec_sys && *o->rec_count < o->rec_cap) {

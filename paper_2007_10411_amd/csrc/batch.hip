@@ -433,7 +433,7 @@ __global__ __launch_bounds__(1024) void kb_dg_finish(BTab t, const double* __res
             sy += __shfl_xor(sy, o, 64);
         }
         const double r2 = sums[BD_ALPHA] - ss;
-        const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+        const double r = r2 > 0.0 ? sqrt(r2) : (r2 != r2 ? r2 : 0.0);
         if (j > 0) {
             const double scl = pre[0];
             const double inv_scl = scl > 0.0 ? 1.0 / scl : 0.0;

@@ -245,13 +245,15 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-// g = 2 (z - du) s / (||du||^2 B), and the partial loss sum (z - du)^2 / ||du||^2
+// g = 2 (z - du) s / (||du||^2 B), and the partial loss sum (z - du)^2 / ||du||^2;
+// a pair with du = 0 has no relative error and contributes nothing
 __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ z, const float* __restrict__ du,
                                                    long long npts, int nf, const float* __restrict__ s,
                                                    const double* __restrict__ du2, double inv_batch,
                                                    float* __restrict__ g, double* __restrict__ partials) {
     __shared__ double red[4];
-    const double nd = *du2;
+    const double nd2 = *du2;
+    const double nd = nd2 > 0.0 ? nd2 : INFINITY;
     const long long n = npts * nf;
     double acc = 0.0;
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {

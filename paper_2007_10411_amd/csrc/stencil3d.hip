@@ -1291,6 +1291,320 @@ __global__ __launch_bounds__(256) void k3_pc_diag(Geo g, const T* __restrict__ n
     if (ea.partials) partial_eps(ea, acc, red);
 }
 
+// ---------------------------------------------------------------------------
+// Per-point 3D kernels for any stencil half-width W (W = 4: the 9-point
+// derivative of order parameter p = 3, section 2.3).  The same operators as the
+// z-marching kernels, with every neighbour a global load through the mirror
+// mapping (reach 2W for the composite D(K D .) and D(tau(D u)) stencils): the
+// derived quantities and the frozen viscosity live on the grid grown by a ring
+// of W, [9][nz+2W][ny+2W][nx+2W] and [nz+2W][ny+2W][nx+2W].
+// ---------------------------------------------------------------------------
+template <int W> struct Dc;
+template <> struct Dc<2> {
+    static constexpr double c[2] = {2.0 / 3.0, -1.0 / 12.0};
+    static constexpr double sumsq2 = 65.0 / 72.0;
+};
+template <> struct Dc<4> {
+    static constexpr double c[4] = {272.0 / 365.0, -53.0 / 365.0, 16.0 / 1095.0, 1.0 / 2920.0};
+    static constexpr double sumsq2 = 2.0 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3]);
+};
+
+// sum_m c_m (f(m) - f(-m)) ih for a tap functor f(offset)
+template <int W, typename T, typename F>
+__device__ __forceinline__ T dW(F f, T ih) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < W; ++m) acc += (T(Dc<W>::c[m]) * ih) * (f(m + 1) - f(-m - 1));
+    return acc;
+}
+
+__device__ __forceinline__ double ihg(const Geo& g, int a) { return a == 0 ? g.idx : (a == 1 ? g.idy : g.idz); }
+
+// derivative of state field f along axis a at (possibly ghost) (x, y, z)
+template <int W, typename T>
+__device__ __forceinline__ T dfW(const Geo& g, const T* __restrict__ u, int f, int a, int x, int y, int z) {
+    const int ex = a == 0, ey = a == 1, ez = a == 2;
+    return dW<W>([&](int o) { return ld(g, u, f, x + o * ex, y + o * ey, z + o * ez); }, T(ihg(g, a)));
+}
+
+// index on the grid grown by a ring of W
+template <int W>
+__device__ __forceinline__ long long extW(const Geo& g, int x, int y, int z) {
+    return ((long long)(z + W) * (g.ny + 2 * W) + (y + W)) * (g.nx + 2 * W) + (x + W);
+}
+template <int W>
+__device__ __forceinline__ long long next3W(const Geo& g) {
+    return (long long)(g.nx + 2 * W) * (g.ny + 2 * W) * (g.nz + 2 * W);
+}
+template <int W>
+__device__ __forceinline__ bool ext_pointW(const Geo& g, long long i, int& x, int& y, int& z) {
+    const long long ex = g.nx + 2 * W, ey = g.ny + 2 * W, ez = g.nz + 2 * W;
+    if (i >= ex * ey * ez) return false;
+    x = (int)(i % ex) - W;
+    y = (int)((i / ex) % ey) - W;
+    z = (int)(i / (ex * ey)) - W;
+    return true;
+}
+
+template <int W, typename T>
+__device__ __forceinline__ void strainW(const Geo& g, const T* __restrict__ u, int x, int y, int z, T S[6], T th[3]) {
+    T gr[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] = dfW<W>(g, u, i, j, x, y, z);
+    S[0] = gr[0][0];
+    S[1] = gr[1][1];
+    S[2] = gr[2][2];
+    S[3] = T(0.5) * (gr[0][1] + gr[1][0]);
+    S[4] = T(0.5) * (gr[0][2] + gr[2][0]);
+    S[5] = T(0.5) * (gr[1][2] + gr[2][1]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) th[j] = dfW<W>(g, u, 4, j, x, y, z);
+}
+
+// stress / heat flux (or, with PAIR, their stable FD differences) on the grid
+// grown by W, one thread per point
+template <int W, typename T, bool PAIR>
+__global__ __launch_bounds__(256) void k3g_derived(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                                   double eps_in, const double* __restrict__ eps_dev,
+                                                   T* __restrict__ d) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_pointW<W>(g, i, x, y, z)) return;
+    const long long ne = next3W<W>(g);
+    if (!PAIR) {
+        T S[6], th[3];
+        strainW<W>(g, u, x, y, z, S, th);
+        const Coef<T> k = closure3c(g, frob3(S, S));
+        const T third = (S[0] + S[1] + S[2]) * T(1.0 / 3.0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d[c * ne + i] = T(2) * (vert3(c) ? k.mv : k.mh) * (c < 3 ? S[c] - third : S[c]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) d[(6 + j) * ne + i] = (j == 2 ? k.hv : k.hh) * th[j];
+        return;
+    }
+    const T e = T(eps_dev ? *eps_dev : eps_in);
+    T SU[6], SV[6], tU[3], tV[3], SW[6];
+    strainW<W>(g, u, x, y, z, SU, tU);
+    strainW<W>(g, v, x, y, z, SV, tV);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) SW[c] = SU[c] + e * SV[c];
+    const Coef<T> ka = closure3c(g, frob3(SU, SU));
+    Coef<T> dk = {T(0), T(0), T(0), T(0)};
+    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
+        const T den = sqrt(frob3(SU, SU)) + sqrt(frob3(SW, SW));
+        const T num = T(2) * frob3(SU, SV) + e * frob3(SV, SV);
+        if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+            const T dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+            dk = {dnu, dnu, dnu * T(g.inv_pr), dnu * T(g.inv_pr)};
+        } else {
+            dk = deardorff_diff(g, T(sqrt(frob3(SU, SU))), den > T(0) ? num / den : T(0), e);
+        }
+    }
+    const T trw = (SW[0] + SW[1] + SW[2]) * T(1.0 / 3.0), trv = (SV[0] + SV[1] + SV[2]) * T(1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const T dw = c < 3 ? SW[c] - trw : SW[c];
+        const T dv = c < 3 ? SV[c] - trv : SV[c];
+        d[c * ne + i] = T(2) * (vert3(c) ? dk.mv : dk.mh) * dw + T(2) * (vert3(c) ? ka.mv : ka.mh) * dv;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        d[(6 + j) * ne + i] = (j == 2 ? dk.hv : dk.hh) * (tU[j] + e * tV[j]) + (j == 2 ? ka.hv : ka.hh) * tV[j];
+}
+
+// the operator per grid point: MODE 0 out = F (what 0), 2u/dt + F (1),
+// 2u/dt - F - f (2); MODE 1 Jv = 2v/dt - [F(u + e v) - F(u)]/e expanded
+template <int W, typename T, int MODE>
+__global__ __launch_bounds__(256) void k3g_point(Geo g, const T* __restrict__ u, const T* __restrict__ v,
+                                                 double eps_in, const double* __restrict__ eps_dev,
+                                                 const T* __restrict__ d, const T* __restrict__ f,
+                                                 T* __restrict__ out, int what) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.npts) return;
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+    const long long np = g.npts, ne = next3W<W>(g);
+    const T e = MODE == 1 ? T(eps_dev ? *eps_dev : eps_in) : T(0);
+    const T th0 = T(g.theta0);
+    const T* pb = Bg<T>::pbar(g);
+    const T* dpb = Bg<T>::dpbar(g);
+    // divergence of derived component c along axis j
+    auto dd = [&](int c, int j) -> T {
+        const int ex = j == 0, ey = j == 1, ez = j == 2;
+        return dW<W>([&](int o) { return d[c * ne + extW<W>(g, x + o * ex, y + o * ey, z + o * ez)]; },
+                     T(ihg(g, j)));
+    };
+    T A[5], B[5], dF[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        A[k] = u[k * np + i];
+        B[k] = MODE == 1 ? v[k * np + i] : T(0);
+    }
+    T divA = T(0), divB = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int ex = j == 0, ey = j == 1, ez = j == 2;
+        const T ih = T(ihg(g, j));
+        for (int k = 0; k < 5; ++k) {
+            auto a = [&](int o) { return ld(g, u, k, x + o * ex, y + o * ey, z + o * ez); };
+            auto aj = [&](int o) { return ld(g, u, j, x + o * ex, y + o * ey, z + o * ez); };
+            if (MODE == 0) {
+                if (g.convection) {
+                    const T flux = dW<W>([&](int o) { return aj(o) * a(o); }, ih);
+                    dF[k] -= T(0.5) * (flux + A[j] * dW<W>(a, ih));
+                }
+                if (k == j) divA += dW<W>(a, ih);
+            } else {
+                auto b = [&](int o) { return ld(g, v, k, x + o * ex, y + o * ey, z + o * ez); };
+                auto bj = [&](int o) { return ld(g, v, j, x + o * ex, y + o * ey, z + o * ez); };
+                const T dA = dW<W>(a, ih), dB = dW<W>(b, ih);
+                if (g.convection) {
+                    const T flux = dW<W>([&](int o) { return aj(o) * b(o) + bj(o) * (a(o) + e * b(o)); }, ih);
+                    dF[k] -= T(0.5) * (flux + A[j] * dB + B[j] * (dA + e * dB));
+                }
+                if (k == j) {
+                    divA += dA;
+                    divB += dB;
+                }
+            }
+        }
+    }
+    const T* P = MODE == 1 ? v : u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dF[c] -= th0 * dfW<W>(g, P, 3, c, x, y, z);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dF[c] += dd(tix(c, j), j);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dF[4] += dd(6 + j, j);
+    if (MODE == 0) {
+        dF[2] += T(g.g_theta0) * A[4];
+        if (g.energy_test)
+            dF[3] -= T(g.kappa_cp) * divA;
+        else
+            dF[3] -= A[2] * dpb[z] + T(g.kappa) * (pb[z] + A[3]) * divA;
+        dF[4] -= T(g.beta) * A[2];
+        if (z == 0 && !g.energy_test) dF[4] += Bg<T>::sflux(g)[(long long)y * g.nx + x];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            T r;
+            if (what == 0) r = dF[k];
+            else if (what == 1) r = T(g.two_dt) * A[k] + dF[k];
+            else r = T(g.two_dt) * A[k] - dF[k] - (f ? f[k * np + i] : T(0));
+            out[k * np + i] = r;
+        }
+    } else {
+        dF[2] += T(g.g_theta0) * B[4];
+        if (g.energy_test)
+            dF[3] -= T(g.kappa_cp) * divB;
+        else
+            dF[3] -= B[2] * dpb[z] + T(g.kappa) * ((pb[z] + A[3]) * divB + B[3] * divA + e * B[3] * divB);
+        dF[4] -= T(g.beta) * B[2];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) out[k * np + i] = T(g.two_dt) * B[k] - dF[k];
+    }
+}
+
+// frozen eddy viscosity on the grid grown by W
+template <int W, typename T>
+__global__ __launch_bounds__(256) void k3g_frozen_nu(Geo g, const T* __restrict__ u, T* __restrict__ nu) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    int x, y, z;
+    if (!ext_pointW<W>(g, i, x, y, z)) return;
+    T S[6], th[3];
+    strainW<W>(g, u, x, y, z, S, th);
+    T n, k;
+    closure3(g, frob3(S, S), n, k);
+    nu[i] = n;
+}
+
+template <int W, typename T>
+__device__ __forceinline__ T pc_diagW(const Geo& g, T kh, T kv) {
+    const T cD = T(Dc<W>::sumsq2);
+    if (g.closure == JFNK_CLOSURE_DEARDORFF)
+        return T(g.two_dt) + cD * (kh * T(g.idx * g.idx + g.idy * g.idy) + kv * T(g.idz * g.idz));
+    return T(g.two_dt) + cD * kh * T(g.idx * g.idx + g.idy * g.idy + g.idz * g.idz);
+}
+
+// z0 = v / d (v = V_j / div written back); the thread's ||z||^2 to the partials
+template <int W, typename T>
+__global__ __launch_bounds__(256) void k3g_pc_diag(Geo g, const T* __restrict__ nu, T* __restrict__ vj,
+                                                   const double* __restrict__ div, T* __restrict__ z, EpsArgs ea) {
+    __shared__ double red[4];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (i < g.npts) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zz = (int)(i / ((long long)g.nx * g.ny));
+        const Coef<T> kc = pc_k3(g, nu[extW<W>(g, x, y, zz)]);
+        const T dm = pc_diagW<W>(g, kc.mh, kc.mv), dt_ = pc_diagW<W>(g, kc.hh, kc.hv);
+        const T dg[5] = {dm, dm, dm, T(g.two_dt), dt_};
+        const double dv = div ? *div : 1.0;
+        const long long np = g.npts;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            T vv = vj[k * np + i];
+            if (div) {
+                vv = (T)((double)vv / dv);
+                vj[k * np + i] = vv;
+            }
+            const T zv = vv / dg[k];
+            z[k * np + i] = zv;
+            acc += (double)zv * (double)zv;
+        }
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
+}
+
+// one Jacobi sweep of the field-block preconditioner, one thread per point:
+// zout = zin + (r - P zin)/d with P z = (2/dt) z + C(a(u); z) - sum_j D_j(K D_j z)
+template <int W, typename T>
+__global__ __launch_bounds__(256) void k3g_pc_sweep(Geo g, const T* __restrict__ u, const T* __restrict__ nu,
+                                                    const T* __restrict__ r, const T* __restrict__ zin,
+                                                    T* __restrict__ zout, EpsArgs ea) {
+    __shared__ double red[4];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (i < g.npts) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+        const long long np = g.npts;
+        const Coef<T> kc0 = pc_k3(g, nu[extW<W>(g, x, y, z)]);
+        const T dmom = pc_diagW<W>(g, kc0.mh, kc0.mv), dth = pc_diagW<W>(g, kc0.hh, kc0.hv);
+        for (int k = 0; k < 5; ++k) {
+            const T zc = zin[k * np + i];
+            T t = T(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int ex = j == 0, ey = j == 1, ez = j == 2;
+                const T ih = T(ihg(g, j));
+                auto zz = [&](int o) { return ld(g, zin, k, x + o * ex, y + o * ey, z + o * ez); };
+                if (k != 3) {
+                    // D_j (K D_j z): K frozen on the grid grown by W
+                    auto flux = [&](int o) {
+                        const int xo = x + o * ex, yo = y + o * ey, zo = z + o * ez;
+                        const Coef<T> kc = pc_k3(g, nu[extW<W>(g, xo, yo, zo)]);
+                        const T K = k == 4 ? (j == 2 ? kc.hv : kc.hh) : (j == 2 ? kc.mv : kc.mh);
+                        return K * dW<W>([&](int q) { return ld(g, zin, k, xo + q * ex, yo + q * ey, zo + q * ez); },
+                                         ih);
+                    };
+                    t -= dW<W>(flux, ih);
+                }
+                if (g.convection) {
+                    auto aj = [&](int o) { return ld(g, u, j, x + o * ex, y + o * ey, z + o * ez); };
+                    t += T(0.5) * (dW<W>([&](int o) { return aj(o) * zz(o); }, ih) + u[j * np + i] * dW<W>(zz, ih));
+                }
+            }
+            const T Pz = T(g.two_dt) * zc + t;
+            const T dd = k == 3 ? T(g.two_dt) : (k == 4 ? dth : dmom);
+            const T zn = zc + (r[k * np + i] - Pz) / dd;
+            zout[k * np + i] = zn;
+            acc += (double)zn * (double)zn;
+        }
+    }
+    if (ea.partials) partial_eps(ea, acc, red);
+}
+
 inline int blocks(long long n) { return (int)((n + 255) / 256); }
 inline long long next3(const Geo& g) { return (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4); }
 
@@ -1300,8 +1614,22 @@ inline dim3 march_grid(int nx, int ny, int nz, int ty) {
     return dim3((nx + kMTX - 1) / kMTX, (ny + ty - 1) / ty, (nz + kZC - 1) / kZC);
 }
 
+template <int W>
+inline long long next3W_host(const Geo& g) {
+    return (long long)(g.nx + 2 * W) * (g.ny + 2 * W) * (g.nz + 2 * W);
+}
+
 template <typename T>
 hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int what, T* dbuf, hipStream_t s) {
+    if (g.W == 4) {
+        hipLaunchKernelGGL((k3g_derived<4, T, false>), dim3(blocks(next3W_host<4>(g))), dim3(256), 0, s, g, u,
+                           (const T*)nullptr, 0.0, (const double*)nullptr, dbuf);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k3g_point<4, T, 0>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, (const T*)nullptr, 0.0,
+                           (const double*)nullptr, (const T*)dbuf, f, out, what);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k3m_derived<T, false>), march_grid(g.nx + 4, g.ny + 4, g.nz + 4, 8), dim3(256), 0, s, g, u,
                        (const T*)nullptr, 0.0, (const double*)nullptr, dbuf);
     hipError_t e = hipGetLastError();
@@ -1336,6 +1664,15 @@ hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double
 template <typename T>
 hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, T* out, T* dbuf,
                       hipStream_t s) {
+    if (g.W == 4) {
+        hipLaunchKernelGGL((k3g_derived<4, T, true>), dim3(blocks(next3W_host<4>(g))), dim3(256), 0, s, g, u, v, eps,
+                           eps_dev, dbuf);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k3g_point<4, T, 1>), dim3(blocks(g.npts)), dim3(256), 0, s, g, u, v, eps, eps_dev,
+                           (const T*)dbuf, (const T*)nullptr, out, 0);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k3m_derived<T, true>), march_grid(g.nx + 4, g.ny + 4, g.nz + 4, 8), dim3(256), 0, s, g, u, v,
                        eps, eps_dev, dbuf);
     hipError_t e = hipGetLastError();
@@ -1351,6 +1688,10 @@ hipError_t launch3_jv(const Geo& g, const T* u, const T* v, double eps, const do
 
 template <typename T>
 hipError_t launch3_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s) {
+    if (g.W == 4) {
+        hipLaunchKernelGGL((k3g_frozen_nu<4, T>), dim3(blocks(next3W_host<4>(g))), dim3(256), 0, s, g, u, nu);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k3_frozen_nu<T>), dim3(blocks(next3(g))), dim3(256), 0, s, g, u, nu);
     return hipGetLastError();
 }
@@ -1359,7 +1700,10 @@ template <typename T>
 hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
                            hipStream_t s) {
     const int nb = blocks(g.npts);
-    hipLaunchKernelGGL((k3_pc_diag<T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
+    if (g.W == 4)
+        hipLaunchKernelGGL((k3g_pc_diag<4, T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
+    else
+        hipLaunchKernelGGL((k3_pc_diag<T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ea.partials) return e;
     return launch_eps_finish(nb, ea, s);
@@ -1368,6 +1712,13 @@ hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, 
 template <typename T>
 hipError_t launch3_pc_sweep(const Geo& g, const T* u, const T* nu, const T* r, const T* zin, T* zout,
                             const EpsArgs& ea, hipStream_t s) {
+    if (g.W == 4) {
+        const int nb = blocks(g.npts);
+        hipLaunchKernelGGL((k3g_pc_sweep<4, T>), dim3(nb), dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !ea.partials) return e;
+        return launch_eps_finish(nb, ea, s);
+    }
     const dim3 grid = march_grid(g.nx, g.ny, g.nz, 8);
     hipLaunchKernelGGL((k3m_pc_sweep<T>), grid, dim3(256), 0, s, g, u, nu, r, zin, zout, ea);
     hipError_t e = hipGetLastError();

@@ -584,7 +584,8 @@ __global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ p
             sy += __shfl_xor(sy, o, 64);
         }
         const double r2 = sums[DG_ALPHA] - ss;
-        const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+        // a NaN (a non-finite Krylov vector) stays NaN for the host's test
+        const double r = r2 > 0.0 ? sqrt(r2) : (r2 != r2 ? r2 : 0.0);
         if (j > 0) {
             const double sc = pre[0];
             const double inv_sc = sc > 0.0 ? 1.0 / sc : 0.0;

@@ -158,11 +158,35 @@ def crops(V, grid, crop, idx, starts):
     return torch.stack(out).contiguous()
 
 
-def random_starts(rng, grid, crop, k):
+def random_starts(rng, grid, crop, k, centers=None):
+    """Crop starts: uniform over the grid, or around the given centres (x, y, z)
+    with a jitter of a quarter crop, clamped to the grid."""
     nf, nz, ny, nx = grid
     cx, cy, cz = crop
-    return [(int(rng.integers(0, nx - cx + 1)), int(rng.integers(0, ny - cy + 1)), int(rng.integers(0, nz - cz + 1)))
-            for _ in range(k)]
+    out = []
+    for q in range(k):
+        if centers is None:
+            out.append((int(rng.integers(0, nx - cx + 1)), int(rng.integers(0, ny - cy + 1)),
+                        int(rng.integers(0, nz - cz + 1))))
+            continue
+        c = centers[q]
+        st = []
+        for ci, cn, n in zip(c, (cx, cy, cz), (nx, ny, nz)):
+            j = cn // 4
+            s0 = ci - cn // 2 + int(rng.integers(-j, j + 1))
+            st.append(int(min(max(s0, 0), n - cn)))
+        out.append(tuple(st))
+    return out
+
+
+def support_centers(V, grid):
+    """Grid point (x, y, z) of the largest summed field magnitude of each vector:
+    Krylov directions started from a localised residual vanish far from it, and a
+    crop must hold some of the direction to carry a relative loss."""
+    nf, nz, ny, nx = grid
+    a = V.view(V.shape[0], nf, nz * ny * nx).abs().sum(dim=1)
+    idx = a.argmax(dim=1).cpu().numpy()
+    return [(int(i % nx), int((i // nx) % ny), int(i // (nx * ny))) for i in idx]
 
 
 def train_3d_crops(ctx, sources, iters=600, lr=2e-3, batch=4, seed=0, noise=None, theta0=None):
@@ -177,6 +201,7 @@ def train_3d_crops(ctx, sources, iters=600, lr=2e-3, batch=4, seed=0, noise=None
     ctx.net_set_params(theta.astype(np.float32))
     rng = np.random.Generator(np.random.PCG64(seed + 23))
     kinds = list(range(len(sources))) + (["noise"] if noise is not None else [])
+    centers = [support_centers(DU, grid) for (R, DU, grid, crop) in sources]
     p = ctx.prob
     full = (p.nf, p.nz, p.ny, p.nx)
     losses = []
@@ -192,7 +217,7 @@ def train_3d_crops(ctx, sources, iters=600, lr=2e-3, batch=4, seed=0, noise=None
         else:
             R, DU, grid, crop = sources[kind]
             idx = rng.choice(R.shape[0], size=min(batch, R.shape[0]), replace=False)
-            st = random_starts(rng, grid, crop, len(idx))
+            st = random_starts(rng, grid, crop, len(idx), [centers[kind][i] for i in idx])
             Rb, Xb = crops(R, grid, crop, idx, st), crops(DU, grid, crop, idx, st)
         losses.append(ctx.net_train_step(Rb, Xb, step_lr, crop=crop))
     return ctx.net_get_params(), losses

@@ -161,9 +161,9 @@ def test_physics_preconditioner_judges_the_learned_one():
     """Section 2.5.2's preconditioner as the judge: with no physics-preconditioned
     solve on record the system goes to the physics-based preconditioner; a network
     whose residual reduction per iteration falls short of the record is stopped
-    at the end of its first cycle, so each judged-out solve costs at most m
-    iterations on top of the physics solve, whose result the step then equals
-    bit for bit."""
+    at the end of its first cycle and the rest of the step stays on the physics
+    preconditioner, so the step costs at most m iterations more than the physics
+    step, whose result it then equals bit for bit."""
     prob = I.thermal_stable_2d(128, 64)
     U0 = I.bubble_state(prob)
     un = dev(U0)
@@ -189,7 +189,9 @@ def test_physics_preconditioner_judges_the_learned_one():
     r2 = c.newton_step(un, u2, pc="learned", **opts)
     assert r2.converged
     assert r2.fallbacks == r2.newton_iters
-    assert rp.gmres_iters_total < r2.gmres_iters_total <= rp.gmres_iters_total + m * r2.fallbacks
+    # the first judged-out solve costs at most one cycle; the rest of the step
+    # stays on the physics-based preconditioner
+    assert rp.gmres_iters_total < r2.gmres_iters_total <= rp.gmres_iters_total + m
     assert torch.equal(u2, up) and torch.equal(u1, up)
 
 

@@ -188,3 +188,63 @@ def test_jv32_3d_single_pass_and_two_pass(name, mode):
         assert_fields_close(host(o), ref, F32_TOL, f"{name} jv32 {mode} variant {variant}")
         outs.append(host(o))
     assert_fields_close(outs[0], outs[1], F32_TOL, f"{name} single vs two pass")
+
+
+P3_CASES = {
+    "neutral-p3-20x12x10": lambda: I.thermal_neutral_3d(20, 12, 10).replace(dd_p=3),
+    "noslip-stable-flux-p3-17x9x11": lambda: CASES3["stable-noslip-3d-17x9x11"].replace(dd_p=3),
+    "periodic-constK-p3-12x10x8": lambda: CASES3["constK-periodic-3d-12x10x8"].replace(dd_p=3),
+    "deardorff-p3-16x9x10": lambda: I.Problem(dim=3, nx=16, ny=9, nz=10, lx=8000.0, ly=5000.0, lz=3000.0, dt=2.0,
+                                              n_bv=0.01, closure=I.CLOSURE_DEARDORFF, dd_p=3),
+}
+
+
+@pytest.mark.parametrize("name", list(P3_CASES))
+def test_p3_residual_jv_pc_3d(name):
+    """The 9-point derivative (p = 3, halos of 8) in 3D: residual and F (FP64,
+    FP32), stable and analytic Jv (FP64, FP32) and the physics preconditioner
+    with 0 and 2 sweeps against the oracle."""
+    prob = P3_CASES[name]()
+    U = I.smooth_flow_state(prob, seed=13)
+    Un = I.smooth_flow_state(prob, seed=14)
+    f = M.rhs(prob, Un)
+    c = _ctx(prob)
+    out = dev(np.zeros(prob.shape))
+    c.rhs(dev(Un), out)
+    assert_fields_close(host(out), f, F64_TOL, name + " rhs")
+    c.residual(dev(U), dev(f), out)
+    assert_fields_close(host(out), M.residual(prob, U, f), F64_TOL, name + " residual")
+    U32 = U.astype(np.float32).astype(np.float64)
+    o32 = dev(np.zeros(prob.shape), "f32")
+    c.apply_F(dev(U32, "f32"), o32, what=0)
+    assert_fields_close(host(o32), M.F(prob, U32), F32_TOL, name + " F32")
+    V = I.random_vector(prob, seed=15)
+    V32 = V.astype(np.float32).astype(np.float64)
+    for mode in ("stable", "analytic"):
+        eps = M.fd_eps(prob, U, V) if mode == "stable" else 0.0
+        c.jv(dev(U), dev(V), out, mode=mode)
+        assert_fields_close(host(out), M.jv(prob, U, V, eps), F64_TOL, f"{name} jv {mode}")
+        e32 = M.fd_eps(prob, U32, V32, eps_mach=2.0 ** -23) if mode == "stable" else 0.0
+        c.jv(dev(U32, "f32"), dev(V32, "f32"), o32, mode=mode, eps=e32)
+        assert_fields_close(host(o32), M.jv(prob, U32, V32, e32), F32_TOL, f"{name} jv32 {mode}")
+    R = I.random_vector(prob, seed=16)
+    for sweeps in (0, 2):
+        z = dev(np.zeros(prob.shape))
+        c.precond_apply(dev(U), dev(R), z, pc="physics", sweeps=sweeps)
+        assert_fields_close(host(z), PC.physics_pc(prob, U, R, sweeps=sweeps), F64_TOL, f"{name} pc{sweeps}")
+
+
+def test_p3_newton_step_3d():
+    prob = I.thermal_neutral_3d(16, 12, 10).replace(dd_p=3)
+    U0 = I.bubble_state(prob)
+    ref, info = K.newton_step(prob, U0, K.NewtonOpts(rtol=1e-13))
+    c = _ctx(prob)
+    un = dev(U0)
+    u = un.clone()
+    assert c.newton_step(un, u, rtol=1e-13).converged
+    assert_fields_close(host(u), ref, F64_TOL, "newton 3d p3")
+    u2 = un.clone()
+    r2 = c.newton_step(un, u2, rtol=1e-8, inner="f32", eta_floor=1e-4)
+    assert r2.converged
+    d = np.linalg.norm((host(u2) - ref).ravel()) / np.linalg.norm((ref - U0).ravel())
+    assert d < 1e-6
