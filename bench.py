@@ -557,19 +557,24 @@ def main():
         bt = Batch(eprobs, max_m=30)
         erows = bt.tune()
         un_e = bt.pack([I.rest_state(p) for p in eprobs])
-        ue = un_e.clone()
-        bt.newton_step(un_e, ue, sweeps=args.pc_sweeps, ortho=args.ortho)   # untimed: first launches
-        ue = un_e.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        eres = bt.newton_step(un_e, ue, sweeps=args.pc_sweeps, ortho=args.ortho)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        eopts = dict(sweeps=args.pc_sweeps, ortho=args.ortho)
+        ens_ms = {}
+        for mode, graph in (("graph", True), ("host", False)):
+            ue = un_e.clone()
+            bt.newton_step(un_e, ue, use_graph=graph, **eopts)   # untimed: first launches, graph capture
+            ue = un_e.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eres = bt.newton_step(un_e, ue, use_graph=graph, **eopts)
+            torch.cuda.synchronize()
+            ens_ms[mode] = (time.perf_counter() - t0) * 1e3
         its = [r.gmres_iters_total for r in eres]
         ensemble = {"instances": len(eprobs), "points": int(sum(p.npts for p in eprobs)),
-                    "ms_per_step": el * 1e3, "converged": all(r.converged for r in eres),
+                    "ms_per_step": ens_ms["graph"], "ms_per_step_host_decided": ens_ms["host"],
+                    "converged": all(r.converged for r in eres),
                     "gmres_iters_per_instance": [min(its), max(its)], "gmres_iters_total": sum(its),
-                    "pc_sweeps": args.pc_sweeps, "ortho": args.ortho, "launch_shapes": erows}
+                    "pc_sweeps": args.pc_sweeps, "ortho": args.ortho, "launch_shapes": erows,
+                    "cycle": "one captured HIP graph per restart cycle, decisions on the device"}
         del bt, un_e, ue
         torch.cuda.empty_cache()
 

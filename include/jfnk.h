@@ -364,9 +364,17 @@ int jfnk_batch_size(jfnk_batch* batch, int64_t* total, int64_t* offsets);
 int jfnk_batch_apply_F(jfnk_batch* batch, int32_t what, const double* u, const double* f, double* out);
 /* One trapezoidal step of every instance (opts->inner must be JFNK_F32; the
  * recording fields are ignored; opts->gm.ortho selects the Arnoldi step as in
- * jfnk_gmres); infos: HOST array of ninst results.                              */
+ * jfnk_gmres); infos: HOST array of ninst results.
+ * use_graph = 1 keeps every decision of a restart cycle on the device (per
+ * instance: which instances work, their iteration counts, convergence against
+ * the forcing term, the columns of the least-squares update, who restarts) and
+ * replays each cycle as one captured HIP graph, captured on the first call (and
+ * again when m, the sweeps, the preconditioner, the Gram-Schmidt form or the
+ * iteration limit change); the host waits once per cycle instead of twice per
+ * Krylov iteration.  use_graph = 0 takes those decisions on the host.  Both give
+ * the same results.                                                             */
 int jfnk_batch_newton_step(jfnk_batch* batch, const double* u_n, double* u_np1, const jfnk_newton_opts* opts,
-                           jfnk_newton_info* infos);
+                           jfnk_newton_info* infos, int32_t use_graph);
 /* Autotuner of the batched residual, Jv and sweep kernels (tile heights 4, 8,
  * 16); tile_rows (HOST, 3 entries, may be NULL) receives the choices.           */
 int jfnk_batch_tune(jfnk_batch* batch, int32_t* tile_rows);

@@ -111,7 +111,7 @@ def load():
     L.jfnk_batch_destroy.argtypes = [vp]
     L.jfnk_batch_size.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.jfnk_batch_apply_F.argtypes = [vp, C.c_int32, vp, vp, vp]
-    L.jfnk_batch_newton_step.argtypes = [vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)]
+    L.jfnk_batch_newton_step.argtypes = [vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo), C.c_int32]
     L.jfnk_batch_tune.argtypes = [vp, C.POINTER(C.c_int32)]
     L.jfnk_jv_noalloc.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, vp, vp, C.c_double, vp, vp]
     for name in EXPORTS:

@@ -667,6 +667,108 @@ __global__ __launch_bounds__(kB) void kb_zero(BTab t, T* __restrict__ x) {
     for (long long e = c.b + threadIdx.x; e < c.e; e += kB) x[e] = T(0);
 }
 
+// ---- per-instance decisions on the device (the captured-graph cycle) ----
+// Instance state of a lockstep GMRES solve kept in device memory so that a
+// whole restart cycle runs without the host: act (working), in_cycle (worked
+// in this cycle), conv, iters, kcnt (columns of this cycle), tol and bnorm
+// (relative tolerance and ||rhs||), flags[0] = any instance active after the
+// cycle, flags[1] = a non-finite norm was met.
+struct BDev {
+    int* act;
+    int* in_cycle;
+    int* conv;
+    int* iters;
+    int* kcnt;
+    const double* tol;
+    double* bnorm;
+    int* flags;
+};
+
+// start of a solve: iteration counts and convergence cleared, ||rhs|| taken
+// from the cycle-start norm; a zero right-hand side is solved, a non-finite
+// one flagged
+__global__ void kb_dev_begin(int ni, BDev d, const double* __restrict__ scal) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) d.flags[1] = 0;
+    if (i >= ni) return;
+    d.conv[i] = 0;
+    d.iters[i] = 0;
+    d.kcnt[i] = 0;
+    if (!d.act[i]) return;
+    const double b = scal[(long long)i * S_STRIDE + SB_BETA];
+    d.bnorm[i] = b;
+    if (!isfinite(b)) {
+        d.flags[1] = 1;
+        d.act[i] = 0;
+    } else if (b == 0.0) {
+        d.act[i] = 0;
+        d.conv[i] = 1;
+    }
+}
+
+__global__ void kb_dev_cycle_begin(int ni, BDev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    d.in_cycle[i] = d.act[i];
+    d.kcnt[i] = 0;
+}
+
+// column col of every working instance is final: count it and stop the
+// instances that are done (converged, exact, out of iterations or, with
+// last_col, at the end of the cycle)
+__global__ void kb_dev_close(int ni, BDev d, const double* __restrict__ scal, int col, int max_iters, int last_col) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni || !d.act[i]) return;
+    const double r = scal[(long long)i * S_STRIDE + SB_WNORM];
+    const double res = scal[(long long)i * S_STRIDE + SB_RES];
+    if (!isfinite(r) || !isfinite(res)) {
+        d.flags[1] = 1;
+        d.act[i] = 0;
+        return;
+    }
+    d.kcnt[i] = col + 1;
+    const int it = d.iters[i] + 1;
+    d.iters[i] = it;
+    const bool ok = res <= d.tol[i] * d.bnorm[i];
+    if (ok || r == 0.0 || it >= max_iters || (last_col && col + 1 == last_col)) {
+        d.act[i] = 0;
+        d.conv[i] = ok ? 1 : 0;
+    }
+}
+
+// after a one-reduction cycle: the instances that ended it unconverged with
+// iterations left restart
+__global__ void kb_dev_restart_select(int ni, BDev d, int m, int max_iters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    d.act[i] = (d.in_cycle[i] && !d.conv[i] && d.iters[i] < max_iters && d.kcnt[i] == m) ? 1 : 0;
+}
+
+// after the restart residual: r = 0 ends an instance
+__global__ void kb_dev_beta_zero(int ni, BDev d, const double* __restrict__ scal) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni || !d.act[i]) return;
+    const double b = scal[(long long)i * S_STRIDE + SB_BETA];
+    if (!isfinite(b)) {
+        d.flags[1] = 1;
+        d.act[i] = 0;
+    } else if (b == 0.0) {
+        d.act[i] = 0;
+        d.conv[i] = 1;
+    }
+}
+
+// flags[0] = some instance still works (one block)
+__global__ __launch_bounds__(256) void kb_dev_any(int ni, BDev d) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ni; i += 256)
+        if (d.act[i]) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) d.flags[0] = any;
+}
+
 }  // namespace
 }  // namespace jfnk
 
@@ -705,6 +807,15 @@ struct jfnk_batch {
     double* partials = nullptr;
     double* hscal = nullptr;    // pinned: ninst * S_STRIDE
     int* hflags = nullptr;      // pinned: ninst
+    // device-side instance state of the captured cycle (see BDev)
+    int *d_incycle = nullptr, *d_conv = nullptr, *d_iters = nullptr, *d_dflags = nullptr;
+    double *d_tol = nullptr, *d_bnorm = nullptr;
+    int* hdflags = nullptr;     // pinned: 2 (any, non-finite) per cycle
+    double* htol = nullptr;     // pinned: ninst
+    int* hres = nullptr;        // pinned: 2 ninst (iters, conv)
+    hipStream_t cap_stream = nullptr;   // capture stream (a graph cannot be captured on the null stream)
+    hipGraphExec_t cycle_exec = nullptr;
+    int cyc_key[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // the options the captured cycle was built for
 };
 
 namespace {
@@ -1077,6 +1188,169 @@ int b_gmres_one_reduction(jfnk_batch* b, const float* u, const float* rhs, float
     return JFNK_OK;
 }
 
+BDev bdev(jfnk_batch* b) {
+    return {b->d_active, b->d_incycle, b->d_conv, b->d_iters, b->d_kcnt, b->d_tol, b->d_bnorm, b->d_dflags};
+}
+
+// One restart cycle of the lockstep FGMRES(m) with every decision on the
+// device: m iterations of the preconditioner, Jv and Arnoldi step (each launch
+// masked by the instances still working), column closes, the solution update
+// over the columns each instance counted, the choice of the instances that
+// restart, their true residual, and the flags the host reads after the cycle.
+// Nothing here synchronises, allocates or clears memory with a memset, so the
+// sequence can be captured as a graph and replayed.
+int b_enqueue_cycle(jfnk_batch* b, const float* u, const float* rhs, float* x, const jfnk_gmres_opts& o,
+                    int max_iters) {
+    const int ni = b->ninst, m = o.m;
+    const long long ntot = b->ntot;
+    const double sqrt_eps = std::sqrt(1.1920928955078125e-07);
+    const bool onered = o.ortho == JFNK_ORTHO_ONE_REDUCTION && m < kDgMaxRows;
+    hipStream_t s = b->stream;
+    const BDev d = bdev(b);
+    const dim3 g1((ni + 255) / 256), b1(256);
+    int rc;
+    const BTab ta = tab(b, 1, true), tall = tab(b, 1, false);
+    hipLaunchKernelGGL(kb_set_start, g1, b1, 0, s, ta, b->g, (const double*)b->scal, m);
+    hipLaunchKernelGGL(kb_dev_cycle_begin, g1, b1, 0, s, ni, d);
+    JFNK_HIP(hipGetLastError());
+    for (int j = 0; j < m; ++j) {
+        float* Vj = b->V32 + (long long)j * ntot;
+        float* Vn = b->V32 + (long long)(j + 1) * ntot;
+        float* Zj = b->Z32 + (long long)j * ntot;
+        const int which = onered ? -1 : (j == 0 ? SB_BETA : SB_WNORM);
+        if (o.pc == JFNK_PC_PHYSICS) {
+            float* bufs[2] = {Zj, b->t32};
+            int cur = (o.sweeps % 2 == 0) ? 0 : 1;
+            hipLaunchKernelGGL((kb_pc_diag<float>), dim3(b->pblk_off[ni]), dim3(kB), 0, s, ta, (const float*)b->nu32,
+                               Vj, onered ? (const double*)nullptr : (const double*)(b->scal + which), bufs[cur]);
+            JFNK_HIP(hipGetLastError());
+            for (int sw = 0; sw < o.sweeps; ++sw) {
+                JFNK_HIP(b_pc_sweep<float>(b, u, b->nu32, Vj, bufs[cur], bufs[1 - cur], b->tune[2 * 2 + 1]));
+                cur = 1 - cur;
+            }
+        } else {
+            hipLaunchKernelGGL((kb_normalize_copy<float>), dim3(b->nchunks), dim3(kB), 0, s, ta, Vj,
+                               (const double*)b->scal, which, Zj);
+            JFNK_HIP(hipGetLastError());
+        }
+        if ((rc = b_norm2<float>(b, Zj, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
+        JFNK_HIP(b_jv<float>(b, u, Zj, b->scal + SB_EPS, Vn, b->tune[1 * 2 + 1]));
+        if (onered) {
+            if ((rc = b_dg(b, j, true, m))) return rc;
+            if (j > 0) hipLaunchKernelGGL(kb_dev_close, g1, b1, 0, s, ni, d, (const double*)b->scal, j - 1, max_iters, m);
+        } else {
+            if ((rc = b_cgs<float>(b, j + 1, CGS_DOT, nullptr, Vn, b->h1, j, m))) return rc;
+            if ((rc = b_cgs<float>(b, j + 1, CGS_UPD_DOT, b->h1, Vn, b->h2, j, m))) return rc;
+            if ((rc = b_cgs<float>(b, j + 1, CGS_UPD_NORM, b->h2, Vn, b->outv, j, m))) return rc;
+            hipLaunchKernelGGL(kb_dev_close, g1, b1, 0, s, ni, d, (const double*)b->scal, j, max_iters, 0);
+        }
+        JFNK_HIP(hipGetLastError());
+    }
+    if (onered) {
+        // column m-1 of the instances still working: closing reduction over q~_m
+        if ((rc = b_dg(b, m, false, m))) return rc;
+        hipLaunchKernelGGL(kb_dev_close, g1, b1, 0, s, ni, d, (const double*)b->scal, m - 1, max_iters, m);
+        JFNK_HIP(hipGetLastError());
+    }
+    // solution update of every instance that worked in this cycle
+    hipLaunchKernelGGL(kb_backsolve, dim3((ni + 63) / 64), dim3(64), 0, s, tall, (const double*)b->H,
+                       (const double*)b->g, (const int*)b->d_kcnt, m, b->y);
+    hipLaunchKernelGGL((kb_axpy_basis<float>), dim3(b->nchunks), dim3(kB), 0, s, tall, x, (const float*)b->Z32, ntot,
+                       (const int*)b->d_kcnt, (const double*)b->y);
+    JFNK_HIP(hipGetLastError());
+    if (onered) hipLaunchKernelGGL(kb_dev_restart_select, g1, b1, 0, s, ni, d, m, max_iters);
+    // restart of the instances still working: true residual r = rhs - J x into V_0
+    const BTab tr = tab(b, 1, true);
+    if ((rc = b_norm2<float>(b, x, b->scal + SB_VNORM2, S_STRIDE, FIN_EPS, true, sqrt_eps))) return rc;
+    JFNK_HIP(b_jv<float>(b, u, x, b->scal + SB_EPS, b->V32, b->tune[1 * 2 + 1]));
+    hipLaunchKernelGGL((kb_lincomb<float>), dim3(b->nchunks), dim3(kB), 0, s, tr, b->V32, rhs, b->V32, 1.0, -1.0);
+    JFNK_HIP(hipGetLastError());
+    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+    hipLaunchKernelGGL(kb_dev_beta_zero, g1, b1, 0, s, ni, d, (const double*)b->scal);
+    hipLaunchKernelGGL(kb_dev_any, dim3(1), dim3(256), 0, s, ni, d);
+    JFNK_HIP(hipGetLastError());
+    JFNK_HIP(hipMemcpyAsync(b->hdflags, b->d_dflags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    return JFNK_OK;
+}
+
+// Lockstep FGMRES(m) with device-side decisions: one captured graph per
+// restart cycle, replayed until no instance works; the host synchronises once
+// per cycle (to read whether any instance is left) instead of twice per
+// iteration.  Same arithmetic and results as b_gmres.
+int b_gmres_graph(jfnk_batch* b, const float* u, const float* rhs, float* x, const std::vector<int>& act0,
+                  const std::vector<double>& tol, const jfnk_gmres_opts& o, std::vector<int>& iters,
+                  std::vector<int>& conv) {
+    const int ni = b->ninst;
+    const int max_iters = o.max_iters > 0 ? o.max_iters : o.m * o.max_restarts;
+    hipStream_t s = b->stream;
+    int rc;
+    // start: activity and tolerances in, x = 0, frozen coefficients, ||u||, V_0 = rhs, beta
+    for (int i = 0; i < ni; ++i) {
+        b->hflags[i] = act0[i];
+        b->htol[i] = tol[i];
+    }
+    JFNK_HIP(hipMemcpyAsync(b->d_active, b->hflags, ni * sizeof(int), hipMemcpyHostToDevice, s));
+    JFNK_HIP(hipMemcpyAsync(b->d_tol, b->htol, ni * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+        const BTab t = tab(b, 1, false), ta = tab(b, 1, true);
+        hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
+        if (o.pc == JFNK_PC_PHYSICS)
+            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
+        JFNK_HIP(hipGetLastError());
+    }
+    if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
+    JFNK_HIP(hipMemcpyAsync(b->V32, rhs, b->ntot * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if ((rc = b_norm2<float>(b, b->V32, b->outv, 1, FIN_BETA, true))) return rc;
+    const BDev d = bdev(b);
+    hipLaunchKernelGGL(kb_dev_begin, dim3((ni + 255) / 256), dim3(256), 0, s, ni, d, (const double*)b->scal);
+    JFNK_HIP(hipGetLastError());
+    // the cycle graph, captured once per set of options
+    const int key[8] = {o.m, o.sweeps, o.pc, o.ortho, max_iters, b->tune[3], b->tune[5], 1};
+    if (!b->cycle_exec || !std::equal(key, key + 8, b->cyc_key)) {
+        if (b->cycle_exec) {
+            JFNK_HIP(hipGraphExecDestroy(b->cycle_exec));
+            b->cycle_exec = nullptr;
+        }
+        JFNK_HIP(hipStreamSynchronize(s));
+        hipGraph_t graph = nullptr;
+        b->stream = b->cap_stream;
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = b_enqueue_cycle(b, u, rhs, x, o, max_iters);
+            hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+            if (!rc && e2 != hipSuccess) e = e2;
+        }
+        b->stream = s;
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "capture of the ensemble cycle");
+        e = hipGraphInstantiate(&b->cycle_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->cycle_exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        std::copy(key, key + 8, b->cyc_key);
+    }
+    while (true) {
+        JFNK_HIP(hipGraphLaunch(b->cycle_exec, s));
+        JFNK_HIP(hipStreamSynchronize(s));
+        if (b->hdflags[1]) {
+            set_error("non-finite Krylov norm in the batch");
+            return JFNK_ERR_NONFINITE;
+        }
+        if (!b->hdflags[0]) break;
+    }
+    JFNK_HIP(hipMemcpyAsync(b->hres, b->d_iters, ni * sizeof(int), hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipMemcpyAsync(b->hres + ni, b->d_conv, ni * sizeof(int), hipMemcpyDeviceToHost, s));
+    JFNK_HIP(hipStreamSynchronize(s));
+    iters.assign(b->hres, b->hres + ni);
+    conv.assign(b->hres + ni, b->hres + 2 * ni);
+    return JFNK_OK;
+}
+
 // Lockstep flexible GMRES(m) in FP32 over the instances with act[i] = 1:
 // J_i x_i = b_i to relative tolerance tol[i]; x of the others is left at zero.
 int b_gmres(jfnk_batch* b, const float* u, const float* rhs, float* x, const std::vector<int>& act0,
@@ -1216,11 +1490,16 @@ int jfnk_batch_destroy(jfnk_batch* b) {
                     b->d_tiles_x[0], b->d_tiles_x[1], b->d_tiles_x[2], b->d_pblk_off, b->d_eblk_off, b->d_chunk_off,
                     b->d_active, b->d_kcnt, b->V32, b->Z32, b->u32, b->b32, b->x32, b->t32, b->nu32, b->f64, b->R64,
                     b->bg64, b->bg32, b->H, b->Hraw, b->cs, b->sn, b->g, b->y, b->h1, b->h2, b->scal, b->outv,
-                    b->partials, b->coef};
+                    b->partials, b->coef, b->d_incycle, b->d_conv, b->d_iters, b->d_dflags, b->d_tol, b->d_bnorm};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->hscal) (void)hipHostFree(b->hscal);
     if (b->hflags) (void)hipHostFree(b->hflags);
+    if (b->hdflags) (void)hipHostFree(b->hdflags);
+    if (b->htol) (void)hipHostFree(b->htol);
+    if (b->hres) (void)hipHostFree(b->hres);
+    if (b->cycle_exec) (void)hipGraphExecDestroy(b->cycle_exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return JFNK_OK;
 }
@@ -1324,10 +1603,20 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
     BALLOC(b->outv, (size_t)ninst);
     BALLOC(b->partials, (size_t)b->nchunks * (kMaxDots + 2));   // the one-reduction pass uses 2 kDgMaxRows + 2
     BALLOC(b->coef, (size_t)ninst * kBdCoef);
+    BALLOC(b->d_incycle, ninst);
+    BALLOC(b->d_conv, ninst);
+    BALLOC(b->d_iters, ninst);
+    BALLOC(b->d_dflags, 2);
+    BALLOC(b->d_tol, ninst);
+    BALLOC(b->d_bnorm, ninst);
 #undef BALLOC
     if (hipHostMalloc((void**)&b->hscal, (size_t)ninst * S_STRIDE * sizeof(double), hipHostMallocDefault) !=
             hipSuccess ||
-        hipHostMalloc((void**)&b->hflags, (size_t)ninst * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&b->hflags, (size_t)ninst * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->hdflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->htol, (size_t)ninst * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->hres, (size_t)2 * ninst * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         set_error("hipHostMalloc failed");
         return fail(JFNK_ERR_HIP);
     }
@@ -1395,7 +1684,7 @@ int jfnk_batch_apply_F(jfnk_batch* b, int32_t what, const double* u, const doubl
 }
 
 int jfnk_batch_newton_step(jfnk_batch* b, const double* u_n, double* u, const jfnk_newton_opts* o,
-                           jfnk_newton_info* infos) {
+                           jfnk_newton_info* infos, int32_t use_graph) {
     if (!b || !u_n || !u || !o || o->inner != JFNK_F32 || o->gm.m < 1 || o->gm.m > b->max_m ||
         (o->gm.pc != JFNK_PC_PHYSICS && o->gm.pc != JFNK_PC_NONE) || o->max_newton < 0 ||
         (o->gm.ortho != JFNK_ORTHO_CGS2 && o->gm.ortho != JFNK_ORTHO_ONE_REDUCTION)) {
@@ -1460,7 +1749,9 @@ int jfnk_batch_newton_step(jfnk_batch* b, const double* u_n, double* u, const jf
         JFNK_HIP(launch_cast<float, double>(b->u32, u, ntot, 1.0, s));
         JFNK_HIP(launch_cast<float, double>(b->b32, b->R64, ntot, -1.0, s));
         std::vector<int> gi, gc;
-        if ((rc = b_gmres(b, b->u32, b->b32, b->x32, act, gt, o->gm, gi, gc))) return rc;
+        rc = use_graph ? b_gmres_graph(b, b->u32, b->b32, b->x32, act, gt, o->gm, gi, gc)
+                       : b_gmres(b, b->u32, b->b32, b->x32, act, gt, o->gm, gi, gc);
+        if (rc) return rc;
         JFNK_HIP(launch_add_to64<float>(u, b->x32, ntot, s));     // x = 0 for finished instances
         for (int i = 0; i < ni; ++i)
             if (act[i]) {

@@ -356,13 +356,15 @@ class Batch:
         return dict(zip(["f64_residual", "f32_jv", "f32_pc_sweep"], list(rows)))
 
     def newton_step(self, u_n, u_np1, rtol=1e-8, atol_factor=1e-13, max_newton=20, m=30, max_restarts=20,
-                    pc="physics", sweeps=2, forcing="ew", eta=1e-2, eta_floor=1e-4, ortho="cgs2"):
+                    pc="physics", sweeps=2, forcing="ew", eta=1e-2, eta_floor=1e-4, ortho="cgs2", use_graph=False):
+        """use_graph: each restart cycle as one captured HIP graph with the
+        per-instance decisions on the device (jfnk_batch_newton_step)."""
         gm = L.GmresOpts(m=m, max_restarts=max_restarts, tol=0.0, pc=PCS[pc], jv=L.JV_STABLE, sweeps=sweeps,
                          max_iters=0, ortho=ORTHO[ortho])
         o = L.NewtonOpts(rtol=rtol, atol_factor=atol_factor, max_newton=max_newton, inner=L.F32, gm=gm,
                          forcing=0 if forcing == "ew" else 1, eta=eta, eta_floor=eta_floor)
         infos = (L.NewtonInfo * len(self.probs))()
-        L.check(self.lib.jfnk_batch_newton_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), infos),
-                "jfnk_batch_newton_step")
+        L.check(self.lib.jfnk_batch_newton_step(self.h, _ptr(u_n), _ptr(u_np1), C.byref(o), infos,
+                                                1 if use_graph else 0), "jfnk_batch_newton_step")
         return [NewtonResult(i.newton_iters, i.gmres_iters_total, bool(i.converged), i.res0, i.res_final,
                              i.fallbacks) for i in infos]
