@@ -327,7 +327,7 @@ def synth_state(torch, prob, seed=0):
 
 
 # kernels of the 3D operators (256 x 256 x 128)
-JV3_KERNEL = "k3m_derived<float, true> + k3m_point<float, 1, 8>"
+JV3_KERNEL = "k3f_jv<16> (single z-marching launch, 32 x 16 columns)"
 RES3_KERNEL = "k3m_derived<double, false> + k3m_point<double, 0, 8>"
 
 

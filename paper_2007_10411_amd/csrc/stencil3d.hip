@@ -615,10 +615,10 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
 // A workgroup owns 32 x TY columns and marches along z; at step s it forms the
 // differences of the stress and heat flux (the derived quantities) at plane
 // s + 2 over the columns grown by 2, and Jv at plane s:
-//  - the primitives of A = u and B = v reach a step through per-column
-//    register queues, filled one plane ahead: the own column holds planes
-//    s-2 .. s+4 (p: s-2 .. s+2), each column of the ring of 2 around the tile
-//    planes s .. s+4;
+//  - the primitives of A = u and B = v reach a step one plane ahead: the own
+//    column's planes s-2 .. s+4 (p: s-2 .. s+2) in a register queue, each
+//    column of the ring of 2 around the tile planes s .. s+4 in an LDS ring of
+//    five planes that only its own thread touches;
 //  - in-plane neighbours come from LDS: plane s+2 over the columns grown by 4
 //    (gradients of the derived stage) and plane s over the columns grown by 2
 //    (convection, pressure gradient, divergence);
@@ -684,11 +684,10 @@ __device__ __forceinline__ constexpr int fused_sf(int k) { return k == 3 ? 4 : k
 // Derived quantities of the pair (A, B) at one column of plane za: the stable
 // differences [tau(A + e B) - tau(A)] / e and [q(A + e B) - q(A)] / e (as in
 // k3m_derived).  L points at the column in the LDS plane za over the columns
-// grown by 4 (fields A u, v, w, theta, B u, v, w, theta); q[Q0 .. Q0+4] are
-// the column's values at planes za-2 .. za+2.  out: xx, yy, zz, xy, xz, yz,
-// qx, qy, qz.
-template <int TY, int Q0, int N>
-__device__ __forceinline__ void fused_derived(const Geo& g, const float* __restrict__ L, const float (&q)[N][8], float e,
+// grown by 4 (fields A u, v, w, theta, B u, v, w, theta); q(k, f) is field f of
+// the column at plane za - 2 + k.  out: xx, yy, zz, xy, xz, yz, qx, qy, qz.
+template <int TY, typename ZQ>
+__device__ __forceinline__ void fused_derived(const Geo& g, const float* __restrict__ L, ZQ q, float e,
                                               float ihx, float ihy, float ihz, float out[9]) {
     using FG = FusedGeom<TY>;
     constexpr int P = FG::P4, S = FG::SX4;
@@ -701,7 +700,7 @@ __device__ __forceinline__ void fused_derived(const Geo& g, const float* __restr
             const float* c = L + f * P;
             const float dx = d5(c[-2], c[-1], c[1], c[2], ihx);
             const float dy = d5(c[-2 * S], c[-S], c[S], c[2 * S], ihy);
-            const float dz = d5(q[Q0][f], q[Q0 + 1][f], q[Q0 + 3][f], q[Q0 + 4][f], ihz);
+            const float dz = d5(q(0, f), q(1, f), q(3, f), q(4, f), ihz);
             float* gr = i < 3 ? (h ? gB[i] : gA[i]) : (h ? tB : tA);
             gr[0] = dx;
             gr[1] = dy;
@@ -754,10 +753,19 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     __shared__ float L4[8 * FG::P4];        // plane s+2 over the columns grown by 4
     __shared__ float L2[10 * FG::P2];       // plane s over the columns grown by 2 (A then B, state order)
     __shared__ float RG[3 * 7 * FG::P2];    // in-plane derived components of planes s .. s+2
+    __shared__ float RQ[5 * 8 * FG::NRIM2]; // ring-of-2 columns, planes s .. s+4 (slot = plane mod 5)
     const int tid = threadIdx.x;
     const int tx = tid & 31, ty = tid >> 5;
-    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * TY;
-    const int z0 = blockIdx.z * kzc, z1 = min(z0 + kzc, g.nz);
+    // Workgroups go to the 8 XCDs in turn; give each XCD a contiguous run of
+    // tiles (x fastest, then y, then z chunks) so that the halo rows and
+    // columns neighbouring tiles share are fetched once into that XCD's L2.
+    const int gx = (g.nx + 31) / 32, gy = (g.ny + TY - 1) / TY;
+    const int nblk = (int)gridDim.x;
+    int t = (int)blockIdx.x;
+    if (nblk % 8 == 0) t = (t % 8) * (nblk / 8) + t / 8;
+    const int bx = t % gx, by = (t / gx) % gy, bz = t / (gx * gy);
+    const int x0 = bx * 32, y0 = by * TY;
+    const int z0 = bz * kzc, z1 = min(z0 + kzc, g.nz);
     const bool lat = g.bcl == JFNK_BC_PERIODIC, vper = g.bcv == JFNK_BC_PERIODIC;
     const long long np = g.npts, nxy = (long long)g.nx * g.ny;
     const float e = (float)(eps_dev ? *eps_dev : eps_in);
@@ -807,11 +815,11 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     };
 
     // the own column, a column of the ring of 2 and one of the ring between 2 and 4
-    const int gx = x0 + tx, gy = y0 + ty;
-    const bool mine = gx < g.nx && gy < g.ny;
+    const int px = x0 + tx, py = y0 + ty;
+    const bool mine = px < g.nx && py < g.ny;
     int off0, off1, off4;
     unsigned neg0, neg1, neg4;
-    setup(gx, gy, off0, neg0);
+    setup(px, py, off0, neg0);
     const int c2o = (ty + 2) * FG::SX2 + tx + 2, c4o = (ty + 4) * FG::SX4 + tx + 4;
     const bool has1 = tid < FG::NRIM2, has4 = tid < FG::NRIM4;
     int lx1 = 0, ly1 = 0, lx4 = 0, ly4 = 0;
@@ -824,8 +832,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     // queues (slot 0 oldest)
     float q0[7][8];   // own column, planes s-2 .. s+4
     float p0[5][2];   // own column p of A and B, planes s-2 .. s+2
-    float q1[5][8];   // ring-of-2 column, planes s .. s+4
-    float p1[2];      // its p at plane s
+    float p1[2];      // the ring-of-2 column's p at plane s
     float r4[8];      // ring-of-4 column at plane s+2
     float tq[5][4];   // own column xz, yz, zz, qz at planes s-2 .. s+2
     const int sb = z0 - 4;   // first step: the derived stage starts at plane z0 - 2
@@ -841,9 +848,13 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                 ldp(off0, pl, p0[k]);
                 fixp(p0[k], neg0 ^ nz_);
             }
-            if (k >= 2) {
-                ld8(off1, pl, q1[k - 2]);
-                fix8(q1[k - 2], neg1 ^ nz_);
+            if (k >= 2 && has1) {
+                float r[8];
+                ld8(off1, pl, r);
+                fix8(r, neg1 ^ nz_);
+                const int slot = (sb - 2 + k + 10) % 5;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) RQ[(slot * 8 + c) * FG::NRIM2 + tid] = r[c];
             }
             if (k == 2) {
                 ldp(off1, pl, p1);
@@ -868,9 +879,10 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         // (1) LDS: plane s+2 over the columns grown by 4, plane s over those grown by 2
 #pragma unroll
         for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4o] = q0[4][k];
+        const int rq2 = ((s + 12) % 5) * 8 * FG::NRIM2 + tid, rq0 = ((s + 10) % 5) * 8 * FG::NRIM2 + tid;
         if (has1) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4r] = q1[2][k];
+            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4r] = RQ[rq2 + k * FG::NRIM2];
         }
         if (has4) {
 #pragma unroll
@@ -883,8 +895,10 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2o] = a[k];
         }
         if (has1) {
-            const float a[10] = {q1[0][0], q1[0][1], q1[0][2], p1[0], q1[0][3],
-                                 q1[0][4], q1[0][5], q1[0][6], p1[1], q1[0][7]};
+            float q[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) q[k] = RQ[rq0 + k * FG::NRIM2];
+            const float a[10] = {q[0], q[1], q[2], p1[0], q[3], q[4], q[5], q[6], p1[1], q[7]};
 #pragma unroll
             for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2r] = a[k];
         }
@@ -915,7 +929,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         const int slotA = (s + 8) % 3;
         {
             float d[9];
-            fused_derived<TY, 2>(g, L4 + c4o, q0, e, ihx, ihy, ihz, d);
+            fused_derived<TY>(g, L4 + c4o, [&](int k, int f) { return q0[2 + k][f]; }, e, ihx, ihy, ihz, d);
             float* rg = RG + slotA * 7 * FG::P2 + c2o;
             rg[0 * FG::P2] = d[0];
             rg[1 * FG::P2] = d[1];
@@ -935,7 +949,11 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         }
         if (has1) {
             float d[9];
-            fused_derived<TY, 0>(g, L4 + c4r, q1, e, ihx, ihy, ihz, d);
+            int sl[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sl[k] = ((s + k + 10) % 5) * 8 * FG::NRIM2 + tid;
+            fused_derived<TY>(g, L4 + c4r, [&](int k, int f) { return RQ[sl[k] + f * FG::NRIM2]; }, e, ihx, ihy,
+                              ihz, d);
             float* rg = RG + slotA * 7 * FG::P2 + c2r;
             rg[0 * FG::P2] = d[0];
             rg[1 * FG::P2] = d[1];
@@ -1014,7 +1032,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             else
                 dF[3] = -0.5f * acc[3] - (Bc[2] * dpb[s] + kap * ((pb[s] + Ac[3]) * divB + Bc[3] * divW));
             dF[4] = -0.5f * acc[4] + Dx(5) + Dy(6) + Dz(3) - bet * Bc[2];
-            const long long i = (long long)s * nxy + (long long)gy * g.nx + gx;
+            const long long i = (long long)s * nxy + (long long)py * g.nx + px;
 #pragma unroll
             for (int k = 0; k < 5; ++k) out[k * np + i] = tdt * Bc[k] - dF[k];
         }
@@ -1036,16 +1054,16 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             for (int k = 0; k < 4; ++k) {
                 p0[k][0] = p0[k + 1][0];
                 p0[k][1] = p0[k + 1][1];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) q1[k][c] = q1[k + 1][c];
             }
             p0[4][0] = np0[0];
             p0[4][1] = np0[1];
+            if (has1) {
+                const int slot = ((s + 15) % 5) * 8 * FG::NRIM2 + tid;   // plane s + 5 replaces plane s
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                q1[4][c] = n1[c];
-                r4[c] = n4[c];
+                for (int c = 0; c < 8; ++c) RQ[slot + c * FG::NRIM2] = n1[c];
             }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) r4[c] = n4[c];
             p1[0] = np1[0];
             p1[1] = np1[1];
         }
@@ -1655,8 +1673,8 @@ hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double
                             float* out, hipStream_t s) {
     constexpr int TY = 16;
     const int kzc = fused_kzc(g.nx, g.ny, g.nz, TY);
-    const dim3 grid((g.nx + 31) / 32, (g.ny + TY - 1) / TY, (g.nz + kzc - 1) / kzc);
-    hipLaunchKernelGGL((k3f_jv<TY>), grid, dim3(32 * TY), 0, s, g, u, v, eps, eps_dev, out, kzc);
+    const int nblk = ((g.nx + 31) / 32) * ((g.ny + TY - 1) / TY) * ((g.nz + kzc - 1) / kzc);
+    hipLaunchKernelGGL((k3f_jv<TY>), dim3(nblk), dim3(32 * TY), 0, s, g, u, v, eps, eps_dev, out, kzc);
     return hipGetLastError();
 }
 

@@ -26,8 +26,14 @@ def field_errors(x, ref):
     return out
 
 
+# per-field errors of every parity check of the session (printed as a table at
+# the end of the run by conftest.py)
+RECORDS = []
+
+
 def assert_fields_close(x, ref, tol, what="", abs_floor=0.0):
     errs = field_errors(x, ref)
+    RECORDS.append((what, tol, [e2 for e2, _, _ in errs], [em for _, em, _ in errs]))
     for k, (e2, em, r) in enumerate(errs):
         if r <= abs_floor:
             assert np.abs(x[k] - ref[k]).max() <= max(abs_floor, 1e-300), (what, k, "abs", np.abs(x[k] - ref[k]).max())

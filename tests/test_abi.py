@@ -36,7 +36,7 @@ def test_invalid_problem_is_rejected_without_a_gpu():
     assert lib.jfnk_create(C.byref(bad), 30, None, C.byref(h)) == L.JFNK_ERR_ARG
     assert b"8 points" in lib.jfnk_last_error()
     assert lib.jfnk_create(None, 30, None, C.byref(h)) == L.JFNK_ERR_ARG
-    # the 9-point stencil (dd_p = 3) is built for 2D problems only
-    bad3 = L.problem_struct(I.thermal_neutral_3d(16, 16, 16).replace(dd_p=3))
+    # the derivative order parameter is 2 or 3
+    bad3 = L.problem_struct(I.thermal_neutral_3d(16, 16, 16).replace(dd_p=4))
     assert lib.jfnk_create(C.byref(bad3), 30, None, C.byref(h)) == L.JFNK_ERR_ARG
     assert b"dd_p" in lib.jfnk_last_error()

@@ -222,6 +222,32 @@ def test_gmres_full_cycle_of_30_f64(ortho):
     assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F64_TOL * np.abs(io.H).max()
 
 
+@pytest.mark.parametrize("ortho", ["one_reduction", "cgs2"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gmres_fixed_iterations_f32_vs_oracle(dim, ortho):
+    """The FP32 Krylov solve of the timed configuration (preconditioner diagonal,
+    FP32 Jv with its FD step) against the oracle's FP64 CGS2 FGMRES on the same
+    FP32-rounded inputs, at a fixed count of 8 iterations in one cycle: the
+    solution and the Hessenberg matrix per field and entry, to the FP32 bar."""
+    prob = I.thermal_stable_2d(96, 40) if dim == 2 else I.thermal_neutral_3d(40, 20, 18)
+    U = I.smooth_flow_state(prob, seed=25).astype(np.float32).astype(np.float64)
+    b = I.random_vector(prob, seed=26).astype(np.float32).astype(np.float64)
+    mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v, eps_mach=2.0 ** -23))
+    fr = PC.frozen_coefficients(prob, U)
+    pcf = lambda r: PC.physics_pc(prob, U, r, 0, fr)
+    m = iters = 8
+    xo, io = K.fgmres(mv, pcf, b, m=m, tol=0.0, max_iters=iters, ortho="cgs2")
+    c = _ctx(prob, max_m=m)
+    x = dev(np.zeros(prob.shape), "f32")
+    r = c.gmres(dev(U, "f32"), dev(b, "f32"), x, m=m, max_restarts=1, tol=0.0, pc="physics", sweeps=0,
+                max_iters=iters, want_H=True, ortho=ortho)
+    assert r.iters == iters
+    assert_fields_close(host(x), xo, F32_TOL, f"gmres f32 {dim}d {ortho} x")
+    k = io.H.shape[1]
+    assert np.abs(r.H[: k + 1, :k] - io.H).max() <= F32_TOL * np.abs(io.H).max()
+    assert abs(r.res_true - np.linalg.norm(b - mv(host(x)))) <= 1e-4 * r.res0
+
+
 def test_one_reduction_f32_full_size_matches_cgs2():
     """FP32 at 1024 x 512, two restarts of 30: the one-reduction step against
     CGS2 on the same inputs.  Regression test for the scale of the lagged
