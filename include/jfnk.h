@@ -130,7 +130,9 @@ typedef struct {
     int32_t ortho;             /* jfnk_ortho: Gram-Schmidt form of the Arnoldi step      */
     int32_t no_judge;          /* 1: a learned-preconditioner solve is not judged by the
                                   physics-based one (it runs to its iteration budget and
-                                  falls back only when it does not converge)             */
+                                  falls back only when it does not converge); 2: nor does
+                                  it fall back (x and info are the learned solve's, e.g.
+                                  after a fixed iteration count)                         */
 } jfnk_gmres_opts;
 
 typedef struct {

@@ -68,8 +68,9 @@ hipError_t op_F(jfnk_ctx* c, const T* u, const T* f, T* out, int what) {
 template <typename T>
 hipError_t op_jv(jfnk_ctx* c, const T* u, const T* v, double eps, const double* eps_dev, T* out) {
     if (c->geo.dim == 3) {
-        if constexpr (std::is_same<T, float>::value)
+        if constexpr (std::is_same<T, float>::value) {
             if (c->jv3_single && c->geo.W == 2) return launch3_jv_fused(c->geo, u, v, eps, eps_dev, out, c->stream);
+        }
         return launch3_jv<T>(c->geo, u, v, eps, eps_dev, out, DB<T>(c), c->stream);
     }
     return launch_jv<T>(c->geo, u, v, eps, eps_dev, out, c->stream, tv(c, 1, is32<T>()));
@@ -126,11 +127,13 @@ struct TimedLaunch {
 };
 
 // learned preconditioner of the context's dimension
-hipError_t net_run(jfnk_ctx* c, const float* r, float* z, bool bf16) {
+hipError_t net_run(jfnk_ctx* c, const float* r, float* z, bool bf16, const EpsArgs* ea = nullptr,
+                   const double* rpart = nullptr, int rnblk = 0) {
     const float hdt = (float)(0.5 * c->prob.dt);
     if (c->net.dim == 3)
-        return net3_apply(c->net, c->geo.nx, c->geo.ny, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream);
-    return net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream);
+        return net3_apply(c->net, c->geo.nx, c->geo.ny, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream, ea, rpart,
+                          rnblk);
+    return net_apply(c->net, c->geo.nx, c->geo.nz, c->nf, hdt, r, z, bf16, c->stream, ea, rpart, rnblk);
 }
 
 void resolve_timing(jfnk_ctx* c) {
@@ -218,7 +221,7 @@ int read_scalars(jfnk_ctx* c, int first, int count) {
 
 template <typename T>
 int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, int sweeps, T* scratch,
-             const EpsArgs& ea);
+             const EpsArgs& ea, const double* vpart = nullptr);
 
 // Internal Jv mode of the nonlinear preconditioning: the finite-difference
 // Jacobian of R~(u) = P^{-1}(u) R(u), [R~(u + eps v) - R~(u)] / eps, with R~(u)
@@ -314,9 +317,12 @@ EpsArgs eps_args(jfnk_ctx* c, double eps_mach_v) {
 // z = P^{-1} v by the physics preconditioner (nu frozen beforehand) or z = v,
 // where v = V_j / *div is first written back into V_j (div may be null).  When
 // ea.partials is set, the FD step for direction z is formed on the way.
+// vpart (may be null): the per-block partial sums of v^2 that the Arnoldi
+// update pass left when it wrote v, from which the learned preconditioner
+// takes its input scale.
 template <typename T>
 int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, int sweeps, T* scratch,
-             const EpsArgs& ea) {
+             const EpsArgs& ea, const double* vpart) {
     if (pc == JFNK_PC_NONE) {
         TimedLaunch tl(c, KC_PC);
         JFNK_HIP(launch_normalize_copy<T>(vj, c->n, div, z, ea, c->stream));
@@ -329,14 +335,11 @@ int apply_pc(jfnk_ctx* c, int pc, const T* u, T* vj, const double* div, T* z, in
         }
         if (div) JFNK_HIP(launch_scale<T>(vj, c->n, div, c->stream));
         {
-            // counted in flops: 2 multiply-adds per weight and point
+            // counted in flops: 2 multiply-adds per weight and point; the last
+            // layer leaves the partial sums of ||z||^2 for the FD step
             TimedLaunch tl(c, KC_NET, 2.0 * (c->net.nparam) * c->geo.npts);
-            JFNK_HIP(net_run(c, (const float*)vj, (float*)z, true));
-        }
-        if (ea.partials) {
-            int r = norm2_to<T>(c, z, c->n, sc(c, S_VNORM2));
-            if (r) return r;
-            JFNK_HIP(launch_fd_eps(sc(c, S_UNORM2), sc(c, S_VNORM2), ea.sqrt_eps, ea.sqrt_n, sc(c, S_EPS), c->stream));
+            JFNK_HIP(net_run(c, (const float*)vj, (float*)z, true, ea.partials ? &ea : nullptr,
+                             div ? nullptr : vpart, cgs_blocks(c->n)));
         }
         return JFNK_OK;
     }
@@ -594,13 +597,17 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
     bool converged = false;
     double res_est = bnorm;
     auto slot_of = [](int op) { return op & 3; };
+    // the learned preconditioner takes the scale of q~_j from the partial sums
+    // of its squares that the update pass of iteration j - 1 leaves
+    const bool learned = o.pc == JFNK_PC_LEARNED && std::is_same<T, float>::value;
     // iteration j: z_j = M q~_j, w = A z_j, the reduction (closes column j-1), the update
     auto enqueue_iter = [&](int j) -> int {
         T* Vj = V + (long long)j * n;
         T* Vn = V + (long long)(j + 1) * n;
         T* Zj = Z + (long long)j * n;
         int r;
-        if ((r = apply_pc<T>(c, o.pc, u, Vj, nullptr, Zj, o.sweeps, Vn, ea))) return r;
+        if ((r = apply_pc<T>(c, o.pc, u, Vj, nullptr, Zj, o.sweeps, Vn, ea, learned && j > 0 ? c->qpart : nullptr)))
+            return r;
         if ((r = apply_jv<T>(c, o.jv, u, Zj, sc(c, S_EPS), 0.0, Vn))) return r;
         if (std::is_same<T, float>::value && c->rec_count && *c->rec_count < c->rec_cap) {
             const long long off = (long long)(*c->rec_count) * n;
@@ -614,7 +621,7 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
             da.host = c->hscal + S_SLOT0 + 2 * slot_of(j);
             JFNK_HIP(launch_dg_reduce<T>(V, n, j, true, c->partials, da, s));
             JFNK_HIP(hipEventRecord(c->slot_ev[slot_of(j)], s));
-            JFNK_HIP(launch_dg_update<T>(V, n, j, da.coef, s));
+            JFNK_HIP(launch_dg_update<T>(V, n, j, da.coef, s, learned ? c->qpart : nullptr));
         }
         return JFNK_OK;
     };
@@ -679,8 +686,9 @@ int gmres_one_reduction(jfnk_ctx* c, const T* u, const T* b, T* x, const jfnk_gm
 // learned solve does not converge or breaks down (gi->fallback = 1, the learned
 // attempt's iterations added to *spent).  Once a judged learned solve has
 // fallen back, *benched (when given) keeps the remaining solves of the caller's
-// step on the physics-based preconditioner.  go.no_judge runs the learned solve
-// unjudged, falling back only when it does not converge.  Every
+// step on the physics-based preconditioner.  go.no_judge = 1 runs the learned
+// solve unjudged, falling back only when it does not converge; 2 returns the
+// learned solve's outcome as it is (no fallback).  Every
 // physics-preconditioned solve that converges updates the record.
 template <typename T>
 int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, jfnk_gmres_info* gi, int* spent,
@@ -693,6 +701,7 @@ int krylov_solve(jfnk_ctx* c, const T* u, const T* b, T* x, jfnk_gmres_opts go, 
             c->judged_out = false;
             int rc = gmres_impl<T>(c, u, b, x, go, gi);
             c->judge_active = 0.0;
+            if (go.no_judge == 2) return rc;   // the learned solve's own outcome, no fallback
             if (rc < 0 && rc != JFNK_ERR_NONFINITE) return rc;   // a non-finite learned solve falls back
             if (rc == JFNK_OK && !c->judged_out) {
                 // a nonlinear preconditioner can break the Arnoldi process down
@@ -925,8 +934,12 @@ int jfnk_create(const jfnk_problem* p, int32_t max_m, void* stream, jfnk_ctx** o
     ALLOC(c->dscal, kScal * sizeof(double));
     {
         const long long tiles = (long long)((g.nx + 63) / 64) * ((g.nz + 7) / 8) * (g.dim == 3 ? g.ny : 1);
-        const long long ne = std::max(tiles, (g.npts + 255) / 256) + 1024;
+        // the network's last layer: one partial per 64 x 4 tile (per plane in 3D)
+        const long long conv = (long long)((g.nx + 63) / 64) *
+                               (g.dim == 3 ? (long long)((g.ny + 3) / 4) * g.nz : (long long)((g.nz + 3) / 4));
+        const long long ne = std::max(std::max(tiles, conv), (g.npts + 255) / 256) + 1024;
         ALLOC(c->epart, (size_t)ne * sizeof(double));
+        ALLOC(c->qpart, (size_t)1024 * sizeof(double));   // one per block of the update pass (at most 1024)
     }
 #undef ALLOC
     {
@@ -965,7 +978,7 @@ int jfnk_destroy(jfnk_ctx* c) {
     if (!c) return JFNK_OK;
     (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->V64, c->Z64, c->V32, c->Z32, c->f64, c->R64, c->nl64, c->nls64, c->t64a, c->t64b, c->b64, c->x64, c->nu64, c->d64, c->d32, c->u32, c->b32,
-                    c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal, c->epart};
+                    c->x32, c->t32a, c->t32b, c->nu32, c->bg64, c->bg32, c->partials, c->dscal, c->epart, c->qpart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     {

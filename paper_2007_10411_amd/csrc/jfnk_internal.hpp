@@ -135,12 +135,19 @@ enum { NET_LOSS_SOLUTION = 0, NET_LOSS_REST_JACOBIAN = 1 };
 
 int net_param_count(int nf);
 hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s);
+// BF16 path only, may be null: ea, the FD step of the next Jv formed from z;
+// rpart, rnblk partial sums of r^2 over all fields left by r's producer
 hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r, float* z,
-                     bool bf16, hipStream_t st);
+                     bool bf16, hipStream_t st, const EpsArgs* ea = nullptr, const double* rpart = nullptr,
+                     int rnblk = 0);
 hipError_t net_pair_grad(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r,
                          const float* du, double inv_batch, bool first_pair, const Geo& geo, hipStream_t st);
 hipError_t net_adam(const NetBuffers& nb, int n, int t, float lr, hipStream_t st);
 hipError_t net_field_scale(const float* r, long long np, int nf, double* partials, float* s, hipStream_t st);
+hipError_t net_field_sumsq(const float* r, long long np, int nf, double* partials, hipStream_t st);
+int net_sumsq_blocks(long long np);
+hipError_t net_scale_source(const float* r, long long np, int nf, const double* rpart, int rnblk, double* partials,
+                            float* s, int fuse_limit, const double** part, int* nblk, int* nsets, hipStream_t st);
 hipError_t net_solution_loss(const NetBuffers& nb, long long np, int nf, const float* du, double inv_batch,
                              bool first_pair, hipStream_t st);
 hipError_t net_cast_scaled(const float* r, long long np, int nf, const float* s, float* out, hipStream_t st);
@@ -150,7 +157,8 @@ int net3_param_count(int nf);
 long long net3_wgrad_tiles(int nx, int ny, int nz);
 hipError_t net3_prep_weights(const NetBuffers& nb, int nf, hipStream_t s);
 hipError_t net3_apply(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r, float* z,
-                      bool bf16, hipStream_t st);
+                      bool bf16, hipStream_t st, const EpsArgs* ea = nullptr, const double* rpart = nullptr,
+                      int rnblk = 0);
 hipError_t net3_pair_grad(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r,
                           const float* du, double inv_batch, bool first_pair, hipStream_t st);
 
@@ -195,6 +203,7 @@ struct jfnk_ctx {
     // reductions and small device state
     double* partials = nullptr; // kMaxPartials * kMaxDots
     double* epart = nullptr;    // per-block partials of the FD-step norm
+    double* qpart = nullptr;    // per-block partials of ||q~_{j+1}||^2 from the Arnoldi update pass
     double* dscal = nullptr;    // device scalars (see solver)
     double* hscal = nullptr;    // pinned host mirror
     hipEvent_t slot_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // GMRES result slots in flight
@@ -337,7 +346,8 @@ hipError_t launch_dg_reduce(const T* V, long long n, int j, bool with_w, double*
                             hipStream_t s);
 // Update pass of iteration j: rows j and j + 1 of V become q_j and q~_{j+1}.
 template <typename T>
-hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s);
+// sq (may be null): per-block partial sums of the squares of the new row q~_{j+1}
+hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s, double* sq = nullptr);
 constexpr int kDgMaxRows = 32;          // basis vectors the one-reduction step handles
 hipError_t launch_backsolve(const double* H, const double* g, int k, int m, double* y, hipStream_t s);
 hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m, hipStream_t s);

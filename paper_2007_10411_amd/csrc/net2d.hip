@@ -27,6 +27,9 @@ namespace {
 constexpr int kHid = 16;
 constexpr int kTX = 64, kTZ = 4;            // output tile per 256-thread block
 constexpr int kMaxDil = 8;
+// the first layer finishes the input scale itself when k_field_sumsq leaves at
+// most this many partial sums (a few per thread), saving a launch on small grids
+constexpr int kFuseScalePartials = 1024;
 constexpr int kSX = kTX + 2 * kMaxDil, kSZ = kTZ + 2 * kMaxDil;   // input tile with the largest halo
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
@@ -64,13 +67,15 @@ __global__ __launch_bounds__(256) void k_field_sumsq(const float* __restrict__ r
     if (threadIdx.x == 0) partials[(long long)f * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void k_field_scale(const double* __restrict__ partials, int nblk, long long npts,
-                                                     int nf, float* __restrict__ s) {
+// partials: nsets sets of nblk per-block sums of squares (one set per field
+// from k_field_sumsq, or one set over all fields); s[0..nf) = sqrt(sum / count)
+__global__ __launch_bounds__(256) void k_field_scale(const double* __restrict__ partials, int nblk, int nsets,
+                                                     double count, int nf, float* __restrict__ s) {
     __shared__ double red[4];
     double tot = 0.0;
-    for (int f = 0; f < nf; ++f) tot += sum_partials(partials + (long long)f * nblk, nblk, 1, 0, red);
+    for (int f = 0; f < nsets; ++f) tot += sum_partials(partials + (long long)f * nblk, nblk, 1, 0, red);
     if (threadIdx.x == 0) {
-        const double v = sqrt(tot / ((double)npts * nf));
+        const double v = sqrt(tot / count);
         for (int f = 0; f < nf; ++f) s[f] = v > 0.0 ? (float)v : 1.0f;
     }
 }
@@ -150,33 +155,71 @@ __global__ __launch_bounds__(256) void k_conv_f32(int nx, int nz, const float* _
 // ends with four consecutive output channels of one pixel: one 8-byte store.
 // Wf: bf16 weights [tap][co][ci] padded to 16 x 16.
 // ---------------------------------------------------------------------------
+// Scale of the input, s = sqrt(mean r^2) over all fields (1 if r = 0), from
+// per-block partial sums of squares (nsets sets of nblk), in the order
+// k_field_scale adds them; every thread of the block gets it.
+__device__ __forceinline__ float finish_scale(const double* __restrict__ partials, int nblk, int nsets, double count,
+                                              double* red4, float* sh) {
+    double tot = 0.0;
+    for (int f = 0; f < nsets; ++f) tot += sum_partials(partials + (long long)f * nblk, nblk, 1, 0, red4);
+    if (threadIdx.x == 0) {
+        const double v = sqrt(tot / count);
+        *sh = v > 0.0 ? (float)v : 1.0f;
+    }
+    __syncthreads();
+    return *sh;
+}
+
+// Input scale per channel for the first layer: finished here from spart
+// (block 0 stores it in s for the last layer) or read from s.
+__device__ __forceinline__ void first_layer_scale(int cin, long long np, float* __restrict__ s,
+                                                  const double* __restrict__ spart, int snblk, int snsets,
+                                                  double* red, float* s_sh, float (&sc)[kHid]) {
+    if (spart) {
+        const float sv = finish_scale(spart, snblk, snsets, (double)np * cin, red, s_sh);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < cin) s[threadIdx.x] = sv;
+#pragma unroll
+        for (int c = 0; c < kHid; ++c) sc[c] = sv;
+    } else {
+#pragma unroll
+        for (int c = 0; c < kHid; ++c) sc[c] = c < cin ? s[c] : 1.0f;
+    }
+}
+
+// Input tile of a layer, pixel-major with the channels innermost: rows
+// z0 - h .. z0 + kTZ + h - 1 and columns x0 - h .. x0 + kTX + h - 1, zero
+// outside the grid.  FIRST: the state vector r (channel-major FP32) divided by
+// the scale and rounded to BF16, one pixel per thread and pass, its 16-channel
+// row (zeros beyond cin) stored as two 16-byte halves; MID and LAST: hidden
+// activations (pixel-major BF16, 32 bytes per pixel) copied as two 16-byte
+// halves, four loads in flight per thread before their stores.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigned short* __restrict__ in, int cin,
-                                                   const unsigned short* __restrict__ Wf,
-                                                   const float* __restrict__ b, int cout,
-                                                   unsigned short* __restrict__ post, const float* __restrict__ r,
-                                                   const float* __restrict__ s, float half_dt,
-                                                   float* __restrict__ z, int dil) {
-    // staged input tile, pixel-major with the channels innermost; sized by the
-    // launch for this layer's dilation ((kTZ + 2 dil) x (kTX + 2 dil) pixels)
-    extern __shared__ __align__(16) unsigned short sin_[];
+__device__ __forceinline__ void stage_input(int nx, int nz, int x0, int z0, int h,
+                                            const unsigned short* __restrict__ in, int cin,
+                                            const float* __restrict__ r, const float (&sc)[kHid],
+                                            unsigned short* __restrict__ dst) {
     const long long np = (long long)nx * nz;
-    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
-    const int SZ = kTZ + 2 * dil, SX = kTX + 2 * dil;   // staged region for this dilation
+    const int SZ = kTZ + 2 * h, SX = kTX + 2 * h;
     if (MODE == L_FIRST) {
-        // the state vector r: channel-major FP32, scaled by s and rounded to BF16
-        for (int idx = threadIdx.x; idx < kHid * SZ * SX; idx += 256) {
-            const int c = idx / (SZ * SX), rem = idx - c * (SZ * SX);
-            const int lz = rem / SX, lx = rem - lz * SX;
-            const int gx = x0 + lx - dil, gz = z0 + lz - dil;
-            unsigned short v = 0;
-            if (c < cin && gx >= 0 && gx < nx && gz >= 0 && gz < nz)
-                v = f2bf(r[(long long)c * np + (long long)gz * nx + gx] / s[c]);
-            sin_[(lz * SX + lx) * kHid + c] = v;
+        for (int p = threadIdx.x; p < SZ * SX; p += 256) {
+            const int lz = p / SX, lx = p - lz * SX;
+            const int gx = x0 + lx - h, gz = z0 + lz - h;
+            const bool inside = gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+            unsigned short hv[kHid];
+#pragma unroll
+            for (int c = 0; c < kHid; ++c) {
+                hv[c] = 0;
+                if (c < cin && inside) hv[c] = f2bf(r[(long long)c * np + (long long)gz * nx + gx] / sc[c]);
+            }
+            uint4 lo, hi;
+            lo.x = hv[0] | ((unsigned)hv[1] << 16), lo.y = hv[2] | ((unsigned)hv[3] << 16);
+            lo.z = hv[4] | ((unsigned)hv[5] << 16), lo.w = hv[6] | ((unsigned)hv[7] << 16);
+            hi.x = hv[8] | ((unsigned)hv[9] << 16), hi.y = hv[10] | ((unsigned)hv[11] << 16);
+            hi.z = hv[12] | ((unsigned)hv[13] << 16), hi.w = hv[14] | ((unsigned)hv[15] << 16);
+            *reinterpret_cast<uint4*>(&dst[p * kHid]) = lo;
+            *reinterpret_cast<uint4*>(&dst[p * kHid + 8]) = hi;
         }
     } else {
-        // hidden activations: pixel-major BF16, 32 bytes per pixel, copied as two
-        // 16-byte halves (four loads in flight per thread before their stores)
         const int nh = SZ * SX * 2;
         for (int i0 = threadIdx.x; i0 < nh; i0 += 4 * 256) {
             uint4 v[4];
@@ -184,7 +227,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * 256, p = idx >> 1;
                 const int lz = p / SX, lx = p - lz * SX;
-                const int gx = x0 + lx - dil, gz = z0 + lz - dil;
+                const int gx = x0 + lx - h, gz = z0 + lz - h;
                 v[u] = uint4{0u, 0u, 0u, 0u};
                 if (idx < nh && gx >= 0 && gx < nx && gz >= 0 && gz < nz)
                     v[u] = reinterpret_cast<const uint4*>(in + ((long long)gz * nx + gx) * kHid)[idx & 1];
@@ -193,52 +236,107 @@ __global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigne
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * 256, p = idx >> 1;
                 const int lz = p / SX, lx = p - lz * SX;
-                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[(lz * SX + lx) * kHid + 8 * (idx & 1)]) = v[u];
+                if (idx < nh) *reinterpret_cast<uint4*>(&dst[(lz * SX + lx) * kHid + 8 * (idx & 1)]) = v[u];
             }
         }
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int col = lane & 15, kg = lane >> 4;          // k group of 4 channels
-    // A fragments of the 9 taps (weights): W[t][co = col][ci = 4 kg .. 4 kg + 3]
-    bf16x4_t wfrag[9];
+}
+
+// A fragments of the 9 taps (weights): W[t][co = col][ci = 4 kg .. 4 kg + 3]
+__device__ __forceinline__ void load_wfrag(const unsigned short* __restrict__ Wf, int col, int kg, bf16x4_t (&w)[9]) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
-        wfrag[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
+        w[t] = bf16x4_t{(short)wp[0], (short)wp[1], (short)wp[2], (short)wp[3]};
     }
+}
+
+// One 16-pixel subtile: the 9 dilated taps of a tile whose output pixel (row,
+// px) sits at (row + dil, px + dil) of the staged input (stride SX pixels).
+__device__ __forceinline__ f32x4_t conv_taps(const unsigned short* __restrict__ tile, int SX, int row, int px,
+                                             int dil, const bf16x4_t (&w)[9], int kg) {
+    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int dz = (t / 3) * dil, dx = (t % 3) * dil;
+        const bf16x4_t xv = *reinterpret_cast<const bf16x4_t*>(&tile[((row + dz) * SX + px + dx) * kHid + 4 * kg]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], xv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Output of one subtile at grid pixel pt: D[co = 4 kg + i][pixel = col] holds
+// four consecutive output channels of one pixel.  MID: GELU, BF16, one 8-byte
+// store (pixel-major); LAST: z = (dt/2) r + s (out), and z^2 added to zz.
+template <int MODE>
+__device__ __forceinline__ void layer_out(const f32x4_t& acc, const float (&bias)[4], int kg, int cout, long long np,
+                                          long long pt, unsigned short* __restrict__ post,
+                                          const float* __restrict__ r, const float* __restrict__ s, float half_dt,
+                                          float* __restrict__ z, double& zz) {
+    if (MODE == L_LAST) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = 4 * kg + i;
+            if (co < cout) {
+                const float zv = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
+                z[co * np + pt] = zv;
+                zz += (double)zv * zv;
+            }
+        }
+    } else {
+        u16x4_t o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
+        *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;
+    }
+}
+
+// Optional fusions of the inference launches: with spart set, the first layer
+// finishes the scale itself from per-block partial sums of r^2 (block 0 stores
+// it in s for the last layer); with zpart set, the last layer leaves the
+// block's partial sum of z^2 (the norm of the direction for the FD step of the
+// next Jv) in zpart[block].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_mfma(int nx, int nz, const unsigned short* __restrict__ in, int cin,
+                                                   const unsigned short* __restrict__ Wf,
+                                                   const float* __restrict__ b, int cout,
+                                                   unsigned short* __restrict__ post, const float* __restrict__ r,
+                                                   float* __restrict__ s, float half_dt,
+                                                   float* __restrict__ z, int dil, const double* __restrict__ spart,
+                                                   int snblk, int snsets, double* __restrict__ zpart) {
+    // staged input tile ((kTZ + 2 dil) x (kTX + 2 dil) pixels, sized by the launch)
+    extern __shared__ __align__(16) unsigned short sin_[];
+    __shared__ double red[4];
+    __shared__ float s_sh;
+    const long long np = (long long)nx * nz;
+    const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+    const int SX = kTX + 2 * dil;
+    float sc[kHid];
+    if (MODE == L_FIRST) first_layer_scale(cin, np, s, spart, snblk, snsets, red, &s_sh, sc);
+    stage_input<MODE>(nx, nz, x0, z0, dil, in, cin, r, sc, sin_);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;          // k group of 4 channels
+    bf16x4_t wfrag[9];
+    load_wfrag(Wf, col, kg, wfrag);
     float bias[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) bias[i] = 4 * kg + i < cout ? b[4 * kg + i] : 0.0f;
     __syncthreads();
     const int gz = z0 + wv;
-    if (gz >= nz) return;
+    double zz = 0.0;
+    if (gz < nz) {
 #pragma unroll
-    for (int st = 0; st < kTX / 16; ++st) {
-        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int px = st * 16 + col;                   // B column: pixel of this lane
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dz = (t / 3) * dil, dx = (t % 3) * dil;
-            const bf16x4_t xv =
-                *reinterpret_cast<const bf16x4_t*>(&sin_[((wv + dz) * SX + px + dx) * kHid + 4 * kg]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
+        for (int st = 0; st < kTX / 16; ++st) {
+            const int px = st * 16 + col;                   // B column: pixel of this lane
+            const f32x4_t acc = conv_taps(sin_, SX, wv, px, dil, wfrag, kg);
+            const int gx = x0 + px;
+            if (gx >= nx) continue;
+            layer_out<MODE>(acc, bias, kg, cout, np, (long long)gz * nx + gx, post, r, s, half_dt, z, zz);
         }
-        // D[co = 4 kg + i][pixel = col]: four consecutive output channels of one pixel
-        const int gx = x0 + px;
-        if (gx >= nx) continue;
-        const long long pt = (long long)gz * nx + gx;
-        if (MODE == L_LAST) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = 4 * kg + i;
-                if (co < cout) z[co * np + pt] = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
-            }
-        } else {
-            u16x4_t o;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
-            *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
-        }
+    }
+    if (MODE == L_LAST && zpart) {
+        const double t = block_sum256(zz, red);
+        if (threadIdx.x == 0) zpart[block_linear_id()] = t;
     }
 }
 
@@ -493,44 +591,89 @@ hipError_t net_prep_weights(const NetBuffers& nb, int nf, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t net_field_scale(const float* r, long long np, int nf, double* partials, float* s, hipStream_t st) {
-    int nblk = (int)std::min<long long>(512, (np + 1023) / 1024);
-    if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_field_sumsq, dim3(nblk, nf), dim3(256), 0, st, r, np, partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_field_scale, dim3(1), dim3(256), 0, st, partials, nblk, np, nf, s);
+int net_sumsq_blocks(long long np) {
+    const int nblk = (int)std::min<long long>(512, (np + 1023) / 1024);
+    return nblk < 1 ? 1 : nblk;
+}
+
+hipError_t net_field_sumsq(const float* r, long long np, int nf, double* partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_field_sumsq, dim3(net_sumsq_blocks(np), nf), dim3(256), 0, st, r, np, partials);
     return hipGetLastError();
 }
 
-// inference: z = (dt/2) r + s N(r/s), BF16 MFMA (bf16 = true) or FP32
+hipError_t net_field_scale(const float* r, long long np, int nf, double* partials, float* s, hipStream_t st) {
+    hipError_t e = net_field_sumsq(r, np, nf, partials, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_field_scale, dim3(1), dim3(256), 0, st, (const double*)partials, net_sumsq_blocks(np), nf,
+                       (double)np * nf, nf, s);
+    return hipGetLastError();
+}
+
+// The input scale for inference: from rpart (rnblk partial sums of r^2 over
+// all fields, left by the producer of r) or from a pass over r.  Returns in
+// (*part, *nblk, *nsets) the partials the first layer finishes itself, or
+// part = null when a one-block launch has already written s.
+hipError_t net_scale_source(const float* r, long long np, int nf, const double* rpart, int rnblk, double* partials,
+                            float* s, int fuse_limit, const double** part, int* nblk, int* nsets, hipStream_t st) {
+    *part = nullptr;
+    if (rpart) {
+        *nblk = rnblk;
+        *nsets = 1;
+    } else {
+        hipError_t e = net_field_sumsq(r, np, nf, partials, st);
+        if (e != hipSuccess) return e;
+        *nblk = net_sumsq_blocks(np);
+        *nsets = nf;
+        rpart = partials;
+    }
+    if ((long long)(*nblk) * (*nsets) <= fuse_limit) {
+        *part = rpart;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_field_scale, dim3(1), dim3(256), 0, st, rpart, *nblk, *nsets, (double)np * nf, nf, s);
+    return hipGetLastError();
+}
+
+// inference: z = (dt/2) r + s N(r/s), BF16 MFMA (bf16 = true) or FP32.  In
+// BF16 a problem with few scale partials has the scale finished inside the
+// first layer; with ea set the last layer leaves the partial sums of ||z||^2
+// and one finishing block forms the FD step of the next Jv.
 hipError_t net_apply(const NetBuffers& nb, int nx, int nz, int nf, float half_dt, const float* r, float* z,
-                     bool bf16, hipStream_t st) {
+                     bool bf16, hipStream_t st, const EpsArgs* ea, const double* rpart, int rnblk) {
     NetLayer L[4];
     layers_of(nf, L);
-    hipError_t e = net_field_scale(r, (long long)nx * nz, nf, nb.partials, nb.s, st);
-    if (e != hipSuccess) return e;
     const dim3 grid = tiles(nx, nz);
     const long long np = (long long)nx * nz;
     if (bf16) {
+        const double* spart = nullptr;
+        int snblk = 0, snsets = 0;
+        hipError_t e = net_scale_source(r, np, nf, rpart, rnblk, nb.partials, nb.s, kFuseScalePartials, &spart,
+                                        &snblk, &snsets, st);
+        if (e != hipSuccess) return e;
         unsigned short* a0 = nb.abf;
         unsigned short* a1 = nb.abf + kHid * np;
         auto lds = [](int d) { return (size_t)(kTZ + 2 * d) * (kTX + 2 * d) * kHid * sizeof(unsigned short); };
         constexpr int wl = 9 * kHid * kHid;   // bf16 weights per layer
+        const double* none = nullptr;
         hipLaunchKernelGGL((k_conv_mfma<L_FIRST>), grid, dim3(256), lds(nb.dil[0]), st, nx, nz,
                            (const unsigned short*)nullptr, L[0].cin, nb.wbf + 0 * wl, nb.theta + L[0].boff, L[0].cout,
-                           a0, r, nb.s, half_dt, (float*)nullptr, nb.dil[0]);
+                           a0, r, nb.s, half_dt, (float*)nullptr, nb.dil[0], spart, snblk, snsets, (double*)nullptr);
         hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), lds(nb.dil[1]), st, nx, nz,
                            (const unsigned short*)a0, L[1].cin, nb.wbf + 1 * wl, nb.theta + L[1].boff, L[1].cout, a1,
-                           r, nb.s, half_dt, (float*)nullptr, nb.dil[1]);
+                           r, nb.s, half_dt, (float*)nullptr, nb.dil[1], none, 0, 0, (double*)nullptr);
         hipLaunchKernelGGL((k_conv_mfma<L_MID>), grid, dim3(256), lds(nb.dil[2]), st, nx, nz,
                            (const unsigned short*)a1, L[2].cin, nb.wbf + 2 * wl, nb.theta + L[2].boff, L[2].cout, a0,
-                           r, nb.s, half_dt, (float*)nullptr, nb.dil[2]);
+                           r, nb.s, half_dt, (float*)nullptr, nb.dil[2], none, 0, 0, (double*)nullptr);
         hipLaunchKernelGGL((k_conv_mfma<L_LAST>), grid, dim3(256), lds(nb.dil[3]), st, nx, nz,
                            (const unsigned short*)a0, L[3].cin, nb.wbf + 3 * wl, nb.theta + L[3].boff, L[3].cout,
-                           (unsigned short*)nullptr, r, nb.s, half_dt, z, nb.dil[3]);
-        return hipGetLastError();
+                           (unsigned short*)nullptr, r, nb.s, half_dt, z, nb.dil[3], none, 0, 0,
+                           ea ? ea->partials : (double*)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return ea ? launch_eps_finish((int)(grid.x * grid.y), *ea, st) : hipSuccess;
     }
+    if (ea || rpart) return hipErrorInvalidValue;   // BF16 path only
+    hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
     float* a0 = nb.act;                 // reuse the training buffers
     float* a1 = nb.act + kHid * np;
     hipLaunchKernelGGL((k_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, nz, (const float*)nullptr, L[0].cin,

@@ -11,6 +11,7 @@
 // Parameters: one flat FP32 vector, per layer W[co][ci][kz][ky][kx] then b[co].
 
 #include "jfnk_internal.hpp"
+#include "reduce.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -24,6 +25,8 @@ constexpr int kTaps = 27;
 constexpr int kTX = 64, kTY = 4;      // output points per 256-thread block (one z plane)
 constexpr int kWZ = 4;                // z planes per weight-gradient block
 constexpr int kSX = kTX + 2, kSY = kTY + 2, kSZ = 3;
+// the first layer finishes the input scale itself below this many partials
+constexpr int kFuseScalePartials3 = 1024;
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -117,28 +120,62 @@ __global__ __launch_bounds__(256) void k3_conv_f32(int nx, int ny, int nz, const
 // 66 points, 16 channels, channel innermost) is staged in LDS once.  A = the
 // weights (output x input channels), B = input channels x 16 points, so each
 // lane ends with four consecutive output channels of one point.
+// Optional fusions of the inference launches, as in the 2D network: spart
+// (the first layer finishes the scale from k_field_sumsq's partials, block 0
+// stores it in s) and zpart (the last layer's per-block partial sum of z^2).
 template <int MODE>
 __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, const unsigned short* __restrict__ in,
                                                     int cin, const unsigned short* __restrict__ Wf,
                                                     const float* __restrict__ b, int cout,
                                                     unsigned short* __restrict__ post, const float* __restrict__ r,
-                                                    const float* __restrict__ s, float half_dt,
-                                                    float* __restrict__ z) {
+                                                    float* __restrict__ s, float half_dt,
+                                                    float* __restrict__ z, const double* __restrict__ spart,
+                                                    int snblk, int snsets, double* __restrict__ zpart) {
     __shared__ __align__(16) unsigned short sin_[kSZ][kSY][kSX][kHid];   // pixel-major, channel-innermost
+    __shared__ double red[4];
+    __shared__ float s_sh;
     const long long np = (long long)nx * ny * nz;
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, gz = blockIdx.z;
     constexpr int plane = kSZ * kSY * kSX;
     if (MODE == L_FIRST) {
-        // the state vector r: channel-major FP32, scaled by s and rounded to BF16
-        for (int idx = threadIdx.x; idx < kHid * plane; idx += 256) {
-            const int c = idx / plane, rem = idx - c * plane;
-            const int lz = rem / (kSY * kSX), rem2 = rem - lz * (kSY * kSX);
-            const int ly = rem2 / kSX, lx = rem2 - ly * kSX;
+        // the state vector r: channel-major FP32, scaled by s and rounded to
+        // BF16; one point per thread and pass, its 16-channel row (zeros beyond
+        // cin) stored as two 16-byte halves
+        float sc[kHid];
+        if (spart) {
+            double tot = 0.0;
+            for (int f = 0; f < snsets; ++f) tot += sum_partials(spart + (long long)f * snblk, snblk, 1, 0, red);
+            if (threadIdx.x == 0) {
+                const double v = sqrt(tot / ((double)np * cin));
+                s_sh = v > 0.0 ? (float)v : 1.0f;
+            }
+            __syncthreads();
+            const float sv = s_sh;
+            if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < cin) s[threadIdx.x] = sv;
+#pragma unroll
+            for (int c = 0; c < kHid; ++c) sc[c] = sv;
+        } else {
+#pragma unroll
+            for (int c = 0; c < kHid; ++c) sc[c] = c < cin ? s[c] : 1.0f;
+        }
+        for (int p = threadIdx.x; p < plane; p += 256) {
+            const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
+            const int ly = rem / kSX, lx = rem - ly * kSX;
             const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
-            unsigned short v = 0;
-            if (c < cin && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz)
-                v = f2bf(r[(long long)c * np + ((long long)zz * ny + gy) * nx + gx] / s[c]);
-            sin_[lz][ly][lx][c] = v;
+            const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz;
+            unsigned short h[kHid];
+#pragma unroll
+            for (int c = 0; c < kHid; ++c) {
+                h[c] = 0;
+                if (c < cin && inside) h[c] = f2bf(r[(long long)c * np + ((long long)zz * ny + gy) * nx + gx] / sc[c]);
+            }
+            uint4 lo, hi;
+            lo.x = h[0] | ((unsigned)h[1] << 16), lo.y = h[2] | ((unsigned)h[3] << 16);
+            lo.z = h[4] | ((unsigned)h[5] << 16), lo.w = h[6] | ((unsigned)h[7] << 16);
+            hi.x = h[8] | ((unsigned)h[9] << 16), hi.y = h[10] | ((unsigned)h[11] << 16);
+            hi.z = h[12] | ((unsigned)h[13] << 16), hi.w = h[14] | ((unsigned)h[15] << 16);
+            *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][0]) = lo;
+            *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][8]) = hi;
         }
     } else {
         // hidden activations: pixel-major BF16, 32 bytes per point, copied as two
@@ -178,33 +215,44 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
     for (int i = 0; i < 4; ++i) bias[i] = 4 * kg + i < cout ? b[4 * kg + i] : 0.0f;
     __syncthreads();
     const int gy = y0 + wv;
-    if (gy >= ny) return;
+    double zz2 = 0.0;
+    if (gy < ny) {
 #pragma unroll
-    for (int st = 0; st < kTX / 16; ++st) {
-        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int px = st * 16 + col;                   // B column: point of this lane
+        for (int st = 0; st < kTX / 16; ++st) {
+            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int px = st * 16 + col;                   // B column: point of this lane
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const bf16x4_t xv = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
-        }
-        // D[co = 4 kg + i][point = col]: four consecutive output channels of one point
-        const int gx = x0 + px;
-        if (gx >= nx) continue;
-        const long long pt = ((long long)gz * ny + gy) * nx + gx;
-        if (MODE == L_LAST) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = 4 * kg + i;
-                if (co < cout) z[co * np + pt] = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
+            for (int t = 0; t < kTaps; ++t) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                const bf16x4_t xv = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
             }
-        } else {
-            u16x4_t o;
+            // D[co = 4 kg + i][point = col]: four consecutive output channels of one point
+            const int gx = x0 + px;
+            if (gx >= nx) continue;
+            const long long pt = ((long long)gz * ny + gy) * nx + gx;
+            if (MODE == L_LAST) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
-            *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
+                for (int i = 0; i < 4; ++i) {
+                    const int co = 4 * kg + i;
+                    if (co < cout) {
+                        const float zv = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
+                        z[co * np + pt] = zv;
+                        zz2 += (double)zv * zv;
+                    }
+                }
+            } else {
+                u16x4_t o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
+                *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
+            }
         }
+    }
+    if (MODE == L_LAST && zpart) {
+        const double t = block_sum256(zz2, red);
+        if (threadIdx.x == 0)
+            zpart[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -326,31 +374,42 @@ hipError_t net3_prep_weights(const NetBuffers& nb, int nf, hipStream_t s) {
 }
 
 hipError_t net3_apply(const NetBuffers& nb, int nx, int ny, int nz, int nf, float half_dt, const float* r, float* z,
-                      bool bf16, hipStream_t st) {
+                      bool bf16, hipStream_t st, const EpsArgs* ea, const double* rpart, int rnblk) {
     Layer3 L[4];
     layers3(nf, L);
     const long long np = (long long)nx * ny * nz;
     const dim3 grid = grid3(nx, ny, nz);
-    hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
-    if (e != hipSuccess) return e;
     if (bf16) {
+        // the scale is finished inside the first layer on small grids (few
+        // partials); with ea set the last layer leaves the partial sums of
+        // ||z||^2 and one finishing block forms the FD step of the next Jv
+        const double* spart = nullptr;
+        int snblk = 0, snsets = 0;
+        hipError_t e = net_scale_source(r, np, nf, rpart, rnblk, nb.partials, nb.s, kFuseScalePartials3, &spart,
+                                        &snblk, &snsets, st);
+        if (e != hipSuccess) return e;
         unsigned short* a0 = nb.abf;
         unsigned short* a1 = nb.abf + kHid * np;
         const int wl = kTaps * kHid * kHid;
+        const double* none = nullptr;
         hipLaunchKernelGGL((k3_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz,
                            (const unsigned short*)nullptr, L[0].cin, nb.wbf + 0 * wl, nb.theta + L[0].boff, L[0].cout,
-                           a0, r, nb.s, half_dt, (float*)nullptr);
+                           a0, r, nb.s, half_dt, (float*)nullptr, spart, snblk, snsets, (double*)nullptr);
         hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
                            L[1].cin, nb.wbf + 1 * wl, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
-                           (float*)nullptr);
+                           (float*)nullptr, none, 0, 0, (double*)nullptr);
         hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a1,
                            L[2].cin, nb.wbf + 2 * wl, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
-                           (float*)nullptr);
+                           (float*)nullptr, none, 0, 0, (double*)nullptr);
         hipLaunchKernelGGL((k3_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
                            L[3].cin, nb.wbf + 3 * wl, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
-                           nb.s, half_dt, z);
-        return hipGetLastError();
+                           nb.s, half_dt, z, none, 0, 0, ea ? ea->partials : (double*)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return ea ? launch_eps_finish((int)(grid.x * grid.y * grid.z), *ea, st) : hipSuccess;
     }
+    if (ea || rpart) return hipErrorInvalidValue;   // BF16 path only
+    hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
+    if (e != hipSuccess) return e;
     float* a0 = nb.act;
     float* a1 = nb.act + kHid * np;
     hipLaunchKernelGGL((k3_conv_f32<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz, (const float*)nullptr, L[0].cin,

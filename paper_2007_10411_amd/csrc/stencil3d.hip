@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
 //    five planes that only its own thread touches;
 //  - in-plane neighbours come from LDS: plane s+2 over the columns grown by 4
 //    (gradients of the derived stage) and plane s over the columns grown by 2
-//    (convection, pressure gradient, divergence);
+//    as W = A + e B and B (convection, pressure gradient, divergence);
 //  - the in-plane derived components (xx, yy, xy, xz, yz, qx, qy) of planes
 //    s .. s+2 live in an LDS ring of three planes, the own column's vertical
 //    ones (xz, yz, zz, qz) of planes s-2 .. s+2 in a register queue.
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                                                      float* __restrict__ out, int kzc) {
     using FG = FusedGeom<TY>;
     __shared__ float L4[8 * FG::P4];        // plane s+2 over the columns grown by 4
-    __shared__ float L2[10 * FG::P2];       // plane s over the columns grown by 2 (A then B, state order)
+    __shared__ float L2[10 * FG::P2];       // plane s over the columns grown by 2: W = A + e B, then B (state order)
     __shared__ float RG[3 * 7 * FG::P2];    // in-plane derived components of planes s .. s+2
     __shared__ float RQ[5 * 8 * FG::NRIM2]; // ring-of-2 columns, planes s .. s+4 (slot = plane mod 5)
     const int tid = threadIdx.x;
@@ -784,6 +784,11 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     };
     // plane offset and z reflection signs of plane z
     auto zmap = [&](int z, long long& pl, unsigned& neg) {
+        if (z >= 0 && z < g.nz) {   // interior plane: no reflection
+            pl = (long long)z * nxy;
+            neg = 0u;
+            return;
+        }
         int sz;
         const int mz = map3(z, g.nz, vper, sz);
         pl = (long long)mz * nxy;
@@ -875,11 +880,16 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     const float th0 = (float)g.theta0, kap = (float)g.kappa, kcp = (float)g.kappa_cp;
     const float gth = (float)g.g_theta0, bet = (float)g.beta, tdt = (float)g.two_dt;
 
+    // ring slots of plane s (mod 5 for the rim queue, mod 3 for the derived
+    // ring), advanced once per step
+    int r5 = (sb + 10) % 5, r3 = (sb + 6) % 3;
+    auto m5 = [](int a) { return a >= 5 ? a - 5 : a; };
+    auto m3 = [](int a) { return a >= 3 ? a - 3 : a; };
     for (int s = sb; s < z1; ++s) {
         // (1) LDS: plane s+2 over the columns grown by 4, plane s over those grown by 2
 #pragma unroll
         for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4o] = q0[4][k];
-        const int rq2 = ((s + 12) % 5) * 8 * FG::NRIM2 + tid, rq0 = ((s + 10) % 5) * 8 * FG::NRIM2 + tid;
+        const int rq2 = m5(r5 + 2) * 8 * FG::NRIM2 + tid, rq0 = r5 * 8 * FG::NRIM2 + tid;
         if (has1) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4r] = RQ[rq2 + k * FG::NRIM2];
@@ -889,7 +899,8 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = r4[k];
         }
         {
-            const float a[10] = {q0[2][0], q0[2][1], q0[2][2], p0[2][0], q0[2][3],
+            const float a[10] = {q0[2][0] + e * q0[2][4], q0[2][1] + e * q0[2][5], q0[2][2] + e * q0[2][6],
+                                 p0[2][0] + e * p0[2][1], q0[2][3] + e * q0[2][7],
                                  q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
 #pragma unroll
             for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2o] = a[k];
@@ -898,7 +909,8 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             float q[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) q[k] = RQ[rq0 + k * FG::NRIM2];
-            const float a[10] = {q[0], q[1], q[2], p1[0], q[3], q[4], q[5], q[6], p1[1], q[7]};
+            const float a[10] = {q[0] + e * q[4], q[1] + e * q[5], q[2] + e * q[6], p1[0] + e * p1[1],
+                                 q[3] + e * q[7], q[4], q[5], q[6], p1[1], q[7]};
 #pragma unroll
             for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2r] = a[k];
         }
@@ -926,7 +938,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         }
         // (3) derived stage at plane s+2: in-plane components to the ring, the
         //     own column's vertical ones to its queue
-        const int slotA = (s + 8) % 3;
+        const int slotA = m3(r3 + 2);
         {
             float d[9];
             fused_derived<TY>(g, L4 + c4o, [&](int k, int f) { return q0[2 + k][f]; }, e, ihx, ihy, ihz, d);
@@ -951,7 +963,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             float d[9];
             int sl[5];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sl[k] = ((s + k + 10) % 5) * 8 * FG::NRIM2 + tid;
+            for (int k = 0; k < 5; ++k) sl[k] = m5(r5 + k) * 8 * FG::NRIM2 + tid;
             fused_derived<TY>(g, L4 + c4r, [&](int k, int f) { return RQ[sl[k] + f * FG::NRIM2]; }, e, ihx, ihy,
                               ihz, d);
             float* rg = RG + slotA * 7 * FG::P2 + c2r;
@@ -966,40 +978,32 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         // (4) Jv at plane s (its derived ring plane was written two steps ago)
         if (s >= z0 && mine) {
             const float* l2 = L2 + c2o;
-            // values of field f (state order; 0..4 of A, 5..9 of B) at tap k
-            // (0..3: -2, -1, +1, +2) along axis j
-            auto tap = [&](int f, int j, int k) -> float {
-                constexpr int oz[4] = {0, 1, 3, 4};
-                if (j == 2) {
-                    const int a = f < 5 ? f : f - 5, h = f < 5 ? 0 : 1;
-                    if (a == 3) return p0[oz[k]][h];
-                    return q0[oz[k]][(a == 4 ? 3 : a) + 4 * h];
-                }
-                const int st = j == 0 ? 1 : FG::SX2;
-                const int o = (k < 2 ? k - 2 : k - 1) * st;
-                return l2[f * FG::P2 + o];
-            };
             const float Ac[5] = {q0[2][0], q0[2][1], q0[2][2], p0[2][0], q0[2][3]};
             const float Bc[5] = {q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
-            const float ih[3] = {ihx, ihy, ihz};
+            const float ih[2] = {ihx, ihy};
             float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
             float divB = 0.f, divW = 0.f, gp[3];
+            // x and y: W = A + e B and B at the taps from LDS; the flux
+            // difference A_j B_f + B_j W_f with A_j = W_j - e B_j formed once
+            // per tap for all fields
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
+            for (int j = 0; j < 2; ++j) {
+                const int st = j == 0 ? 1 : FG::SX2;
+                auto tw = [&](int f, int k) { return l2[f * FG::P2 + (k < 2 ? k - 2 : k - 1) * st]; };
+                auto tb = [&](int f, int k) { return l2[(5 + f) * FG::P2 + (k < 2 ? k - 2 : k - 1) * st]; };
                 float aj[4], bj[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    aj[k] = tap(j, j, k);
-                    bj[k] = tap(5 + j, j, k);
+                    bj[k] = tb(j, k);
+                    aj[k] = tw(j, k) - e * bj[k];
                 }
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
-                    float a[4], b[4], w[4], pr[4];
+                    float w[4], b[4], pr[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        a[k] = f == j ? aj[k] : tap(f, j, k);
-                        b[k] = f == j ? bj[k] : tap(5 + f, j, k);
-                        w[k] = a[k] + e * b[k];
+                        w[k] = tw(f, k);
+                        b[k] = f == j ? bj[k] : tb(f, k);
                         pr[k] = aj[k] * b[k] + bj[k] * w[k];
                     }
                     const float dB = d5(b[0], b[1], b[2], b[3], ih[j]);
@@ -1012,8 +1016,39 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                     if (g.convection) acc[f] += d5(pr[0], pr[1], pr[2], pr[3], ih[j]) + Ac[j] * dB + Bc[j] * dW;
                 }
             }
+            // z: the own column's queue at planes s-2, s-1, s+1, s+2; the flux
+            // difference written as W_z B_f + B_z A_f with W_z formed once per tap
+            {
+                constexpr int oz[4] = {0, 1, 3, 4};
+                auto za = [&](int f, int k) { return f == 3 ? p0[oz[k]][0] : q0[oz[k]][f == 4 ? 3 : f]; };
+                auto zb = [&](int f, int k) { return f == 3 ? p0[oz[k]][1] : q0[oz[k]][(f == 4 ? 3 : f) + 4]; };
+                float wz[4], bz[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bz[k] = zb(2, k);
+                    wz[k] = za(2, k) + e * bz[k];
+                }
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    float a[4], b[4], pr[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        a[k] = za(f, k);
+                        b[k] = zb(f, k);
+                        pr[k] = wz[k] * b[k] + bz[k] * a[k];
+                    }
+                    const float dB = d5(b[0], b[1], b[2], b[3], ihz);
+                    const float dW = d5(a[0], a[1], a[2], a[3], ihz) + e * dB;
+                    if (f == 2) {
+                        divB += dB;
+                        divW += dW;
+                    }
+                    if (f == 3) gp[2] = dB;
+                    if (g.convection) acc[f] += d5(pr[0], pr[1], pr[2], pr[3], ihz) + Ac[2] * dB + Bc[2] * dW;
+                }
+            }
             // divergences of the stress and heat-flux differences
-            const float* rg = RG + ((s + 6) % 3) * 7 * FG::P2 + c2o;
+            const float* rg = RG + r3 * 7 * FG::P2 + c2o;
             auto Dx = [&](int c) {
                 const float* r = rg + c * FG::P2;
                 return d5(r[-2], r[-1], r[1], r[2], ihx);
@@ -1058,7 +1093,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             p0[4][0] = np0[0];
             p0[4][1] = np0[1];
             if (has1) {
-                const int slot = ((s + 15) % 5) * 8 * FG::NRIM2 + tid;   // plane s + 5 replaces plane s
+                const int slot = r5 * 8 * FG::NRIM2 + tid;   // plane s + 5 replaces plane s
 #pragma unroll
                 for (int c = 0; c < 8; ++c) RQ[slot + c * FG::NRIM2] = n1[c];
             }
@@ -1067,6 +1102,8 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             p1[0] = np1[0];
             p1[1] = np1[1];
         }
+        r5 = r5 == 4 ? 0 : r5 + 1;
+        r3 = r3 == 2 ? 0 : r3 + 1;
     }
 }
 
@@ -1658,7 +1695,7 @@ hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int wha
 }
 
 // Planes per workgroup of the single-pass Jv: enough z chunks for one
-// workgroup per compute unit (256 CUs; a 32 x 16 workgroup holds 120 KB of
+// workgroup per compute unit (256 CUs; a 32 x 16 workgroup holds 150 KB of
 // LDS), at least 16 planes per chunk (each chunk re-forms four planes of
 // derived quantities at its start).
 inline int fused_kzc(int nx, int ny, int nz, int ty) {

@@ -655,8 +655,14 @@ __global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ p
 
 // q_j = (q~_j - sum_v a_v V_v) / r_j over row j, and over row j + 1
 // (w - c_w q~_j - sum_v e_v V_v) / r_j  (e_v = y_v - c_w a_v, c_w = h_jj / r_j).
+//
+// With sq set, each block also leaves the partial sum of the new row's squares
+// in sq[block]: the learned preconditioner, which acts on that row next, takes
+// its input scale from them instead of another pass over the row.
 template <typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const double* __restrict__ coef) {
+__global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const double* __restrict__ coef,
+                                                      double* __restrict__ sq) {
+    __shared__ double red[4];
     T* q = V + (long long)j * n;
     T* w = V + (long long)(j + 1) * n;
     const int last = j > 0 ? j - 1 : 0;
@@ -668,20 +674,27 @@ __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const 
     }
     const double inv_r = coef[2 * kDgCoefW], cw = coef[2 * kDgCoefW + 1];
     const int step = gridDim.x * kBlock;
+    double acc = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
         const T qv = q[i], wv = w[i];
         T x[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) x[v] = V[(long long)(v < j ? v : last) * n + i];
         __builtin_amdgcn_sched_barrier(0);
-        double sq = (double)qv, sw = (double)wv - cw * (double)qv;
+        double sqv = (double)qv, sw = (double)wv - cw * (double)qv;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            sq -= ca[v] * (double)x[v];
+            sqv -= ca[v] * (double)x[v];
             sw -= ce[v] * (double)x[v];
         }
-        q[i] = (T)(sq * inv_r);
-        w[i] = (T)(sw * inv_r);
+        q[i] = (T)(sqv * inv_r);
+        const T wn = (T)(sw * inv_r);
+        w[i] = wn;
+        acc += (double)wn * (double)wn;
+    }
+    if (sq) {
+        const double t = block_sum256(acc, red);
+        if (threadIdx.x == 0) sq[blockIdx.x] = t;
     }
 }
 
@@ -886,15 +899,15 @@ hipError_t launch_dg_reduce(const T* V, long long n, int j, bool with_w, double*
 }
 
 template <typename T>
-hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s) {
+hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s, double* sq) {
     if (j < 0 || j >= kDgMaxRows || n < 1 || n >= (1LL << 30)) return hipErrorInvalidValue;
     const int nb = cgs_blocks(n), ni = (int)n;
     if (j <= 8)
-        hipLaunchKernelGGL((k_dg_update<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+        hipLaunchKernelGGL((k_dg_update<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
     else if (j <= 16)
-        hipLaunchKernelGGL((k_dg_update<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+        hipLaunchKernelGGL((k_dg_update<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
     else
-        hipLaunchKernelGGL((k_dg_update<T, 32>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef);
+        hipLaunchKernelGGL((k_dg_update<T, 32>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
     return hipGetLastError();
 }
 
@@ -936,7 +949,7 @@ hipError_t launch_set_start(const double* beta2, double* g, double* beta, int m,
                                       const GivensArgs&, hipStream_t);                                         \
     template hipError_t launch_normalize_copy<T>(T*, long long, const double*, T*, const EpsArgs&, hipStream_t); \
     template hipError_t launch_dg_reduce<T>(const T*, long long, int, bool, double*, const DgArgs&, hipStream_t); \
-    template hipError_t launch_dg_update<T>(T*, long long, int, const double*, hipStream_t);
+    template hipError_t launch_dg_update<T>(T*, long long, int, const double*, hipStream_t, double*);
 JFNK_VINST(double)
 JFNK_VINST(float)
 #undef JFNK_VINST

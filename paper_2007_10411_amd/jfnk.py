@@ -143,12 +143,15 @@ class Context:
         return z
 
     def gmres(self, u, b, x, m=30, max_restarts=20, tol=1e-6, pc="physics", jv="stable", sweeps=2,
-              max_iters=0, want_H=False, ortho="cgs2", judge=True):
+              max_iters=0, want_H=False, ortho="cgs2", judge=True, fallback=True):
         """judge=False runs a learned-preconditioner solve without the physics-based
-        preconditioner's judgement (jfnk_gmres_opts.no_judge)."""
+        preconditioner's judgement (jfnk_gmres_opts.no_judge = 1); with
+        fallback=False as well, its result is returned even when it has not
+        converged (no_judge = 2)."""
         self._check_size(u, b, x)
+        nj = 0 if judge else (1 if fallback else 2)
         o = L.GmresOpts(m=m, max_restarts=max_restarts, tol=tol, pc=PCS[pc], jv=JVS[jv], sweeps=sweeps,
-                        max_iters=max_iters, ortho=ORTHO[ortho], no_judge=0 if judge else 1)
+                        max_iters=max_iters, ortho=ORTHO[ortho], no_judge=nj)
         info = L.GmresInfo()
         Hbuf = None
         if want_H:

@@ -57,6 +57,25 @@ def test_net_forward_f32_and_bf16(nx, nz, dils):
         assert e < 3e-2, ("bf16", k, e)
 
 
+def test_net_forward_bf16_with_a_separate_scale_launch():
+    """Above about 260 K points the input scale is finished by its own launch
+    instead of inside the first layer (more partial sums than the first
+    layer's blocks add themselves): the BF16 forward there against the oracle."""
+    prob = I.thermal_stable_2d(600, 480)
+    dils = (1, 2, 4, 8)
+    c = _ctx(prob, dils=dils)
+    th = _theta(prob.nf, seed=4)
+    c.net_set_params(th)
+    r = _r(prob, 8)
+    netpart = N.forward(th, r, prob.dt, dils=dils) - 0.5 * prob.dt * r
+    z = dev(np.zeros(prob.shape), "f32")
+    c.net_apply(dev(r, "f32"), z, bf16=True)
+    gp = host(z) - 0.5 * prob.dt * r
+    for k in range(prob.nf):
+        e = np.linalg.norm(gp[k] - netpart[k]) / np.linalg.norm(netpart[k])
+        assert e < 3e-2, ("bf16", k, e)
+
+
 @pytest.mark.parametrize("dils", [(1, 1, 1, 1), (1, 2, 4, 8), (8, 3, 1, 2)])
 def test_net_loss_gradient_matches_oracle(dils):
     prob = I.thermal_stable_2d(70, 20)
@@ -155,6 +174,40 @@ def test_learned_pc_in_fgmres_converges_and_falls_back():
     r2 = c.newton_step(un, u2, rtol=1e-8, inner="f32", pc="learned", forcing="fixed", eta=1e-10,
                        max_restarts=1, m=2, max_newton=1, judge=False)
     assert r2.fallbacks == 1 and not r2.converged
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("ortho", ["one_reduction", "cgs2"])
+def test_learned_fgmres_fixed_iterations_vs_oracle(dim, ortho):
+    """FGMRES with the learned preconditioner (BF16 network, unjudged) against
+    the oracle's FGMRES with its FP64 network at a fixed 8 iterations: x per
+    field within 1e-1.  The one-reduction form hands the network the input
+    scale from the Arnoldi update pass's partial sums, CGS2 from its own pass;
+    both form the FD step from the last layer's partial sums of ||z||^2.  A
+    scale 1.5 times off moves x by about 0.3 here, BF16 rounding by about 0.01."""
+    from oracle import krylov as K
+    from oracle import model as M
+    if dim == 2:
+        prob, dils = I.thermal_stable_2d(96, 40), (1, 2, 4, 8)
+        th = _theta(prob.nf)
+    else:
+        prob, dils = I.thermal_neutral_3d(40, 20, 18), (1, 1, 1, 1)
+        th = _theta3(prob.nf)
+    U = I.smooth_flow_state(prob, seed=25).astype(np.float32).astype(np.float64)
+    b = I.random_vector(prob, seed=26).astype(np.float32).astype(np.float64)
+    mv = lambda v: M.jv(prob, U, v, M.fd_eps(prob, U, v, eps_mach=2.0 ** -23))
+    pcf = lambda r: N.forward(th, r, prob.dt, dils=dils)
+    xo, io = K.fgmres(mv, pcf, b, m=8, tol=0.0, max_iters=8, ortho="cgs2")
+    c = _ctx(prob, max_m=8, dils=dils)
+    c.net_set_params(th)
+    x = dev(np.zeros(prob.shape), "f32")
+    r = c.gmres(dev(U, "f32"), dev(b, "f32"), x, m=8, max_restarts=1, tol=0.0, pc="learned", max_iters=8,
+                ortho=ortho, judge=False, fallback=False)
+    assert r.iters == 8 and not r.fallback
+    got = host(x)
+    for k in range(prob.nf):
+        e = np.linalg.norm(got[k] - xo[k]) / np.linalg.norm(xo[k])
+        assert e < 1e-1, (k, e)
 
 
 def test_physics_preconditioner_judges_the_learned_one():
