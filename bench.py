@@ -36,12 +36,11 @@ Printed JSON line:
                  the kernel-class times from the second run.
   cpu_baseline   the FP64 oracle's Jv on a bounded sample of the same workload (the
                  lowest planes of the grid), on all host cores (one process per
-                 core) and on one
-
-kernel_micro   the residual, Jv and physics-preconditioner kernels alone (3D
-               256 x 256 x 128 and 2D 8192 x 8192, vectors beyond the Infinity Cache),
-               FP32 and FP64: per-launch HIP-event time, algorithmic bytes and
-               the HBM fraction
+                 core) and on one core (value_1core), with nproc and the CPU model
+  kernel_micro   the residual, Jv and physics-preconditioner kernels alone (3D
+                 256 x 256 x 128 and 2D 8192 x 8192, vectors beyond the Infinity
+                 Cache), FP32 and FP64: per-launch HIP-event time, algorithmic bytes
+                 and the HBM fraction
 
 --copy-probe GIB runs only a device-to-device copy of GIB GiB (the calibration
 kernel for the hardware byte counters) and prints its size and time.
@@ -327,7 +326,7 @@ def synth_state(torch, prob, seed=0):
 
 
 # kernels of the 3D operators (256 x 256 x 128)
-JV3_KERNEL = "k3f_jv<16> (single z-marching launch, 32 x 16 columns)"
+JV3_KERNEL = "k3f_jv<16> (single z-marching launch, 32 x 16 columns, ring columns on waves of their own)"
 RES3_KERNEL = "k3m_derived<double, false> + k3m_point<double, 0, 8>"
 
 

@@ -831,6 +831,7 @@ void fill_geo(const jfnk_problem& p, Geo& g) {
     const double delta = p.dim == 2 ? std::sqrt(g.dx * g.dz) : std::cbrt(g.dx * g.dy * g.dz);
     g.smag = (p.cs * delta) * (p.cs * delta);
     g.inv_pr = p.pr_t > 0 ? 1.0 / p.pr_t : 0.0;
+    g.dd_ah = g.dd_av = g.dd_ch = g.dd_cv = g.dd_b = g.dd_delta = g.dd_inv_nu = 0.0;
     if (p.closure == JFNK_CLOSURE_DEARDORFF) {
         // eps^(1/3) = (cs Delta)^(2/3) 2^(1/6) |S|, so every coefficient is linear in |S|
         // below the mixing-length cap; the horizontal scale sqrt(dx dy) (dy = dx in 2D)
@@ -851,6 +852,24 @@ void fill_geo(const jfnk_problem& p, Geo& g) {
     g.k_h = p.k_h;
     g.convection = p.convection;
     g.energy_test = p.energy_test;
+    GeoF& f = g.f;
+    f.idx = (float)g.idx;
+    f.idy = (float)g.idy;
+    f.idz = (float)g.idz;
+    f.two_dt = (float)g.two_dt;
+    f.theta0 = (float)g.theta0;
+    f.g_theta0 = (float)g.g_theta0;
+    f.kappa = (float)g.kappa;
+    f.kappa_cp = (float)g.kappa_cp;
+    f.beta = (float)g.beta;
+    f.smag_s2 = (float)g.smag * 1.4142135623730951f;
+    f.inv_pr = (float)g.inv_pr;
+    f.dd_ah = (float)g.dd_ah;
+    f.dd_av = (float)g.dd_av;
+    f.dd_ch = (float)g.dd_ch;
+    f.dd_cv = (float)g.dd_cv;
+    f.dd_b = (float)g.dd_b;
+    f.dd_delta = (float)g.dd_delta;
 }
 
 void set_error(const std::string& msg) { g_err = msg; }

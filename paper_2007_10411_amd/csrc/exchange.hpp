@@ -16,13 +16,36 @@ template <typename T> struct Coef {
     T mh, mv, hh, hv;
 };
 
+// The constants in the arithmetic of T (FP32: the host-rounded copies, the
+// same values as a conversion on the device).
+template <typename T> struct DdK;
+template <> struct DdK<double> {
+    const Geo& g;
+    __device__ __forceinline__ double ah() const { return g.dd_ah; }
+    __device__ __forceinline__ double av() const { return g.dd_av; }
+    __device__ __forceinline__ double ch() const { return g.dd_ch; }
+    __device__ __forceinline__ double cv() const { return g.dd_cv; }
+    __device__ __forceinline__ double b() const { return g.dd_b; }
+    __device__ __forceinline__ double delta() const { return g.dd_delta; }
+};
+template <> struct DdK<float> {
+    const Geo& g;
+    __device__ __forceinline__ float ah() const { return g.f.dd_ah; }
+    __device__ __forceinline__ float av() const { return g.f.dd_av; }
+    __device__ __forceinline__ float ch() const { return g.f.dd_ch; }
+    __device__ __forceinline__ float cv() const { return g.f.dd_cv; }
+    __device__ __forceinline__ float b() const { return g.f.dd_b; }
+    __device__ __forceinline__ float delta() const { return g.f.dd_delta; }
+};
+
 // Eq. 7 coefficients from |S| = sqrt(S:S): each is linear in |S| below the
 // mixing-length cap (the constants are set on the host).
 template <typename T>
 __device__ __forceinline__ Coef<T> deardorff_coef(const Geo& g, T mag) {
-    const T l = g.dd_b > 0 ? min(T(g.dd_b) * mag, T(g.dd_delta)) : T(g.dd_delta);
-    const T km = T(g.dd_ah) * mag, kM = T(g.dd_av) * mag;
-    return {km, kM, km + T(g.dd_ch) * l * mag, kM + T(g.dd_cv) * l * mag};
+    const DdK<T> k{g};
+    const T l = g.dd_b > 0 ? min(k.b() * mag, k.delta()) : k.delta();
+    const T km = k.ah() * mag, kM = k.av() * mag;
+    return {km, kM, km + k.ch() * l * mag, kM + k.cv() * l * mag};
 }
 
 // [K(S + e T) - K(S)] / e of the Eq. 7 coefficients at |S| = magA, with
@@ -31,10 +54,11 @@ __device__ __forceinline__ Coef<T> deardorff_coef(const Geo& g, T mag) {
 // subtracted).  e = 0 gives the derivative.
 template <typename T>
 __device__ __forceinline__ Coef<T> deardorff_diff(const Geo& g, T magA, T dmag, T e) {
-    const T delta = T(g.dd_delta);
+    const DdK<T> k{g};
+    const T delta = k.delta();
     T lA = delta, dl = T(0);
     if (g.dd_b > 0) {
-        const T b = T(g.dd_b), xA = b * magA;
+        const T b = k.b(), xA = b * magA;
         lA = min(xA, delta);
         if (e == T(0))
             dl = xA < delta ? b * dmag : (xA > delta ? T(0) : min(b * dmag, T(0)));
@@ -43,8 +67,8 @@ __device__ __forceinline__ Coef<T> deardorff_diff(const Geo& g, T magA, T dmag, 
     }
     const T lW = lA + e * dl;
     const T dlS = lW * dmag + magA * dl;   // (l_W |S_W| - l_A |S_A|) / e
-    const T dkm = T(g.dd_ah) * dmag, dkM = T(g.dd_av) * dmag;
-    return {dkm, dkM, dkm + T(g.dd_ch) * dlS, dkM + T(g.dd_cv) * dlS};
+    const T dkm = k.ah() * dmag, dkM = k.av() * dmag;
+    return {dkm, dkM, dkm + k.ch() * dlS, dkM + k.cv() * dlS};
 }
 
 }  // namespace jfnk

@@ -13,6 +13,14 @@
 namespace jfnk {
 
 // Kernel-side view of a problem: constants and device pointers, passed by value.
+// FP32 copies of the constants the FP32 kernels use, rounded once on the host
+// (kernel-argument scalars rather than per-thread conversions)
+struct GeoF {
+    float idx, idy, idz, two_dt, theta0, g_theta0, kappa, kappa_cp, beta;
+    float smag_s2;   // (float)smag * sqrt2, the Smagorinsky nu per unit |S|
+    float inv_pr, dd_ah, dd_av, dd_ch, dd_cv, dd_b, dd_delta;
+};
+
 struct Geo {
     int dim, nx, ny, nz;
     int W = 2;                  // half-width of the derivative stencil (2: p = 2, 4: p = 3)
@@ -39,6 +47,7 @@ struct Geo {
     const float* pbar32;
     const float* dpbar32;
     const float* sflux32;
+    GeoF f;
 };
 
 template <typename T> struct Bg;

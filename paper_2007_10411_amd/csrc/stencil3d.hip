@@ -615,16 +615,19 @@ __global__ __launch_bounds__(256) void k3m_point(Geo g, const T* __restrict__ u,
 // A workgroup owns 32 x TY columns and marches along z; at step s it forms the
 // differences of the stress and heat flux (the derived quantities) at plane
 // s + 2 over the columns grown by 2, and Jv at plane s:
-//  - the primitives of A = u and B = v reach a step one plane ahead: the own
-//    column's planes s-2 .. s+4 (p: s-2 .. s+2) in a register queue, each
-//    column of the ring of 2 around the tile planes s .. s+4 in an LDS ring of
-//    five planes that only its own thread touches;
+//  - 32 x TY own-column threads hold their column's planes s-2 .. s+4 of A = u
+//    and B = v (p: s-2 .. s+2) in registers; 256 ring threads (waves of their
+//    own, so a SIMD runs two own-column waves and one ring wave) hold a
+//    column of the ring of 2 around the tile (planes s .. s+4, p at s) and
+//    one of the ring between 2 and 4 (plane s+2), load them, stage them in
+//    LDS and form the ring's derived quantities;
 //  - in-plane neighbours come from LDS: plane s+2 over the columns grown by 4
 //    (gradients of the derived stage) and plane s over the columns grown by 2
 //    as W = A + e B and B (convection, pressure gradient, divergence);
 //  - the in-plane derived components (xx, yy, xy, xz, yz, qx, qy) of planes
-//    s .. s+2 live in an LDS ring of three planes, the own column's vertical
-//    ones (xz, yz, zz, qz) of planes s-2 .. s+2 in a register queue.
+//    s .. s+2 live in an LDS ring of three planes, the own columns' vertical
+//    ones (xz, yz, zz, qz) of planes s-2 .. s+2 in an LDS ring of five planes
+//    that only the column's thread touches.
 // Every state value comes from HBM once per workgroup (plus the halos) and Jv
 // is the only array written: 3 n_f values per point against the two-pass
 // form's 9 extra components written and read back.
@@ -721,9 +724,9 @@ __device__ __forceinline__ void fused_derived(const Geo& g, const float* __restr
         const float den = ma + mw;
         const float num = 2.f * frob3(SA, SB) + e * frob3(SB, SB);
         if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-            const float c = float(g.smag) * 1.4142135623730951f;
+            const float c = g.f.smag_s2;
             const float nu = c * ma, dnu = den > 0.f ? c * num * __builtin_amdgcn_rcpf(den) : 0.f;
-            const float ip = float(g.inv_pr);
+            const float ip = g.f.inv_pr;
             ka = {nu, nu, nu * ip, nu * ip};
             dk = {dnu, dnu, dnu * ip, dnu * ip};
         } else {
@@ -745,20 +748,22 @@ __device__ __forceinline__ void fused_derived(const Geo& g, const float* __restr
         out[6 + j] = (j == 2 ? dk.hv : dk.hh) * (tA[j] + e * tB[j]) + (j == 2 ? ka.hv : ka.hh) * tB[j];
 }
 
+// The kernel: 32 x TY + 256 threads, roles by wave (own columns first).
 template <int TY>
-__global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict__ u, const float* __restrict__ v,
-                                                     double eps_in, const double* __restrict__ eps_dev,
-                                                     float* __restrict__ out, int kzc) {
+__global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __restrict__ u,
+                                                         const float* __restrict__ v, double eps_in,
+                                                         const double* __restrict__ eps_dev,
+                                                         float* __restrict__ out, int kzc) {
     using FG = FusedGeom<TY>;
+    static_assert(FG::NRIM2 <= 256 && FG::NRIM4 <= 256, "the ring columns exceed the ring threads");
     __shared__ float L4[8 * FG::P4];        // plane s+2 over the columns grown by 4
     __shared__ float L2[10 * FG::P2];       // plane s over the columns grown by 2: W = A + e B, then B (state order)
     __shared__ float RG[3 * 7 * FG::P2];    // in-plane derived components of planes s .. s+2
-    __shared__ float RQ[5 * 8 * FG::NRIM2]; // ring-of-2 columns, planes s .. s+4 (slot = plane mod 5)
+    __shared__ float TQ[5 * 4 * FG::NT];    // own columns: xz, yz, zz, qz of planes s-2 .. s+2 (slot = plane mod 5)
     const int tid = threadIdx.x;
+    const bool own = tid < FG::NT;          // uniform per wave
+    const int rt = tid - FG::NT;            // ring thread index
     const int tx = tid & 31, ty = tid >> 5;
-    // Workgroups go to the 8 XCDs in turn; give each XCD a contiguous run of
-    // tiles (x fastest, then y, then z chunks) so that the halo rows and
-    // columns neighbouring tiles share are fetched once into that XCD's L2.
     const int gx = (g.nx + 31) / 32, gy = (g.ny + TY - 1) / TY;
     const int nblk = (int)gridDim.x;
     int t = (int)blockIdx.x;
@@ -769,9 +774,8 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
     const bool lat = g.bcl == JFNK_BC_PERIODIC, vper = g.bcv == JFNK_BC_PERIODIC;
     const long long np = g.npts, nxy = (long long)g.nx * g.ny;
     const float e = (float)(eps_dev ? *eps_dev : eps_in);
-    const float ihx = (float)g.idx, ihy = (float)g.idy, ihz = (float)g.idz;
+    const float ihx = g.f.idx, ihy = g.f.idy, ihz = g.f.idz;
 
-    // in-plane source offset and x/y reflection signs (bit f: state field f) of a column
     auto setup = [&](int gx, int gy, int& off, unsigned& neg) {
         int sx, sy;
         const int mx = map3(gx, g.nx, lat, sx), my = map3(gy, g.ny, lat, sy);
@@ -782,7 +786,6 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             if (odd3(f, sx, sy, 0, g.bcv)) m |= 1u << f;
         neg = m;
     };
-    // plane offset and z reflection signs of plane z
     auto zmap = [&](int z, long long& pl, unsigned& neg) {
         if (z >= 0 && z < g.nz) {   // interior plane: no reflection
             pl = (long long)z * nxy;
@@ -819,130 +822,127 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         r[1] = sgn(r[1], neg, 3);
     };
 
-    // the own column, a column of the ring of 2 and one of the ring between 2 and 4
+    // own thread: its column; ring thread: a ring-of-2 column (has1) and a
+    // ring-of-4 column (has4)
     const int px = x0 + tx, py = y0 + ty;
-    const bool mine = px < g.nx && py < g.ny;
-    int off0, off1, off4;
-    unsigned neg0, neg1, neg4;
-    setup(px, py, off0, neg0);
-    const int c2o = (ty + 2) * FG::SX2 + tx + 2, c4o = (ty + 4) * FG::SX4 + tx + 4;
-    const bool has1 = tid < FG::NRIM2, has4 = tid < FG::NRIM4;
+    const bool mine = own && px < g.nx && py < g.ny;
+    const bool has1 = !own && rt < FG::NRIM2, has4 = !own && rt < FG::NRIM4;
     int lx1 = 0, ly1 = 0, lx4 = 0, ly4 = 0;
-    if (has1) fused_rim2<TY>(tid, lx1, ly1);
-    if (has4) fused_rim4<TY>(tid, lx4, ly4);
-    setup(x0 - 2 + lx1, y0 - 2 + ly1, off1, neg1);
-    setup(x0 - 4 + lx4, y0 - 4 + ly4, off4, neg4);
-    const int c2r = ly1 * FG::SX2 + lx1, c4r = (ly1 + 2) * FG::SX4 + lx1 + 2, c4x = ly4 * FG::SX4 + lx4;
+    if (has1) fused_rim2<TY>(rt, lx1, ly1);
+    if (has4) fused_rim4<TY>(rt, lx4, ly4);
+    int offA, offB = 0;   // own: the column; ring: the ring-of-2 column (A) and the ring-of-4 column (B)
+    unsigned negA, negB = 0u;
+    if (own)
+        setup(px, py, offA, negA);
+    else {
+        setup(x0 - 2 + lx1, y0 - 2 + ly1, offA, negA);
+        setup(x0 - 4 + lx4, y0 - 4 + ly4, offB, negB);
+    }
+    const int c2 = own ? (ty + 2) * FG::SX2 + tx + 2 : ly1 * FG::SX2 + lx1;
+    const int c4 = own ? (ty + 4) * FG::SX4 + tx + 4 : (ly1 + 2) * FG::SX4 + lx1 + 2;
+    const int c4x = ly4 * FG::SX4 + lx4;
 
-    // queues (slot 0 oldest)
-    float q0[7][8];   // own column, planes s-2 .. s+4
-    float p0[5][2];   // own column p of A and B, planes s-2 .. s+2
-    float p1[2];      // the ring-of-2 column's p at plane s
-    float r4[8];      // ring-of-4 column at plane s+2
-    float tq[5][4];   // own column xz, yz, zz, qz at planes s-2 .. s+2
+    // register queues shared by the two roles (slot 0 oldest)
+    //   own:  Q[0..6] planes s-2 .. s+4, P[0..4] p at s-2 .. s+2
+    //   ring: Q[0..4] ring-of-2 planes s .. s+4, Q[5] ring-of-4 plane s+2,
+    //         Q[6] its next plane in flight, P[0] ring-of-2 p at plane s
+    float Q[7][8];
+    float P[5][2];
     const int sb = z0 - 4;   // first step: the derived stage starts at plane z0 - 2
     {
         long long pl;
         unsigned nz_;
+        if (own) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            zmap(sb - 2 + k, pl, nz_);
-            ld8(off0, pl, q0[k]);
-            fix8(q0[k], neg0 ^ nz_);
-            if (k < 5) {
-                ldp(off0, pl, p0[k]);
-                fixp(p0[k], neg0 ^ nz_);
+            for (int k = 0; k < 7; ++k) {
+                zmap(sb - 2 + k, pl, nz_);
+                ld8(offA, pl, Q[k]);
+                fix8(Q[k], negA ^ nz_);
+                if (k < 5) {
+                    ldp(offA, pl, P[k]);
+                    fixp(P[k], negA ^ nz_);
+                }
             }
-            if (k >= 2 && has1) {
-                float r[8];
-                ld8(off1, pl, r);
-                fix8(r, neg1 ^ nz_);
-                const int slot = (sb - 2 + k + 10) % 5;
+        } else {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) RQ[(slot * 8 + c) * FG::NRIM2 + tid] = r[c];
-            }
-            if (k == 2) {
-                ldp(off1, pl, p1);
-                fixp(p1, neg1 ^ nz_);
-            }
-            if (k == 4) {
-                ld8(off4, pl, r4);
-                fix8(r4, neg4 ^ nz_);
+            for (int k = 0; k < 5; ++k) {
+                zmap(sb + k, pl, nz_);
+                ld8(offA, pl, Q[k]);
+                fix8(Q[k], negA ^ nz_);
+                if (k == 0) {
+                    ldp(offA, pl, P[0]);
+                    fixp(P[0], negA ^ nz_);
+                }
+                if (k == 2) {
+                    ld8(offB, pl, Q[5]);
+                    fix8(Q[5], negB ^ nz_);
+                }
             }
         }
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) tq[k][c] = 0.f;
     }
     const float* pb = g.pbar32;
     const float* dpb = g.dpbar32;
-    const float th0 = (float)g.theta0, kap = (float)g.kappa, kcp = (float)g.kappa_cp;
-    const float gth = (float)g.g_theta0, bet = (float)g.beta, tdt = (float)g.two_dt;
-
-    // ring slots of plane s (mod 5 for the rim queue, mod 3 for the derived
-    // ring), advanced once per step
-    int r5 = (sb + 10) % 5, r3 = (sb + 6) % 3;
+    const float th0 = g.f.theta0, kap = g.f.kappa, kcp = g.f.kappa_cp;
+    const float gth = g.f.g_theta0, bet = g.f.beta, tdt = g.f.two_dt;
+    int r5 = (sb + 10) % 5, r3 = (sb + 6) % 3;   // slots of plane s
     auto m5 = [](int a) { return a >= 5 ? a - 5 : a; };
     auto m3 = [](int a) { return a >= 3 ? a - 3 : a; };
+    float* tq = TQ + tid;   // own column's slot base (stride NT per component, 4 NT per plane)
+
     for (int s = sb; s < z1; ++s) {
         // (1) LDS: plane s+2 over the columns grown by 4, plane s over those grown by 2
-#pragma unroll
-        for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4o] = q0[4][k];
-        const int rq2 = m5(r5 + 2) * 8 * FG::NRIM2 + tid, rq0 = r5 * 8 * FG::NRIM2 + tid;
-        if (has1) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4r] = RQ[rq2 + k * FG::NRIM2];
-        }
-        if (has4) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = r4[k];
-        }
         {
-            const float a[10] = {q0[2][0] + e * q0[2][4], q0[2][1] + e * q0[2][5], q0[2][2] + e * q0[2][6],
-                                 p0[2][0] + e * p0[2][1], q0[2][3] + e * q0[2][7],
-                                 q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
+            // plane s+2 of the column to L4, plane s (W = A + e B and B) to L2
+            auto put = [&](const float (&q2)[8], const float (&q0)[8], const float (&p0)[2]) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2o] = a[k];
-        }
-        if (has1) {
-            float q[8];
+                for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4] = q2[k];
+                const float a[10] = {q0[0] + e * q0[4], q0[1] + e * q0[5], q0[2] + e * q0[6], p0[0] + e * p0[1],
+                                     q0[3] + e * q0[7], q0[4], q0[5], q0[6], p0[1], q0[7]};
 #pragma unroll
-            for (int k = 0; k < 8; ++k) q[k] = RQ[rq0 + k * FG::NRIM2];
-            const float a[10] = {q[0] + e * q[4], q[1] + e * q[5], q[2] + e * q[6], p1[0] + e * p1[1],
-                                 q[3] + e * q[7], q[4], q[5], q[6], p1[1], q[7]};
+                for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2] = a[k];
+            };
+            if (own)
+                put(Q[4], Q[2], P[2]);
+            else if (has1)
+                put(Q[2], Q[0], P[0]);
+            if (has4) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2r] = a[k];
+                for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = Q[5][k];
+            }
         }
         __syncthreads();
         // (2) loads for the next step (consumed after the closing barrier)
         const bool more = s + 1 < z1;
-        float n0[8], n1[8], n4[8], np0[2], np1[2];
-        unsigned m0 = 0u, m1 = 0u, m4 = 0u, mp0 = 0u, mp1 = 0u;
+        float n0[8], np0[2];
+        unsigned m0 = 0u, mp0 = 0u, m4 = 0u;
         if (more) {
             long long pl;
             unsigned zn;
-            zmap(s + 5, pl, zn);
-            ld8(off0, pl, n0);
-            ld8(off1, pl, n1);
-            m0 = neg0 ^ zn;
-            m1 = neg1 ^ zn;
-            zmap(s + 3, pl, zn);
-            ldp(off0, pl, np0);
-            ld8(off4, pl, n4);
-            mp0 = neg0 ^ zn;
-            m4 = neg4 ^ zn;
-            zmap(s + 1, pl, zn);
-            ldp(off1, pl, np1);
-            mp1 = neg1 ^ zn;
+            zmap(s + 5, pl, zn);   // own: plane s+5; ring: ring-of-2 plane s+5
+            if (own || has1) ld8(offA, pl, n0);
+            m0 = negA ^ zn;
+            if (own) {
+                zmap(s + 3, pl, zn);
+                ldp(offA, pl, np0);
+                mp0 = negA ^ zn;
+            } else {
+                zmap(s + 1, pl, zn);
+                if (has1) ldp(offA, pl, np0);
+                mp0 = negA ^ zn;
+                zmap(s + 3, pl, zn);
+                if (has4) ld8(offB, pl, Q[6]);
+                m4 = negB ^ zn;
+            }
         }
-        // (3) derived stage at plane s+2: in-plane components to the ring, the
-        //     own column's vertical ones to its queue
+        // (3) derived stage at plane s+2 (own and ring-of-2 columns)
         const int slotA = m3(r3 + 2);
-        {
+        if (own || has1) {
             float d[9];
-            fused_derived<TY>(g, L4 + c4o, [&](int k, int f) { return q0[2 + k][f]; }, e, ihx, ihy, ihz, d);
-            float* rg = RG + slotA * 7 * FG::P2 + c2o;
+            if (own)
+                fused_derived<TY>(g, L4 + c4, [&](int k, int f) { return Q[2 + k][f]; }, e, ihx, ihy, ihz, d);
+            else
+                fused_derived<TY>(g, L4 + c4, [&](int k, int f) { return Q[k][f]; }, e, ihx, ihy, ihz, d);
+            float* rg = RG + slotA * 7 * FG::P2 + c2;
             rg[0 * FG::P2] = d[0];
             rg[1 * FG::P2] = d[1];
             rg[2 * FG::P2] = d[3];
@@ -950,42 +950,22 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
             rg[4 * FG::P2] = d[5];
             rg[5 * FG::P2] = d[6];
             rg[6 * FG::P2] = d[7];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) tq[k][c] = tq[k + 1][c];
-            tq[4][0] = d[4];
-            tq[4][1] = d[5];
-            tq[4][2] = d[2];
-            tq[4][3] = d[8];
-        }
-        if (has1) {
-            float d[9];
-            int sl[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) sl[k] = m5(r5 + k) * 8 * FG::NRIM2 + tid;
-            fused_derived<TY>(g, L4 + c4r, [&](int k, int f) { return RQ[sl[k] + f * FG::NRIM2]; }, e, ihx, ihy,
-                              ihz, d);
-            float* rg = RG + slotA * 7 * FG::P2 + c2r;
-            rg[0 * FG::P2] = d[0];
-            rg[1 * FG::P2] = d[1];
-            rg[2 * FG::P2] = d[3];
-            rg[3 * FG::P2] = d[4];
-            rg[4 * FG::P2] = d[5];
-            rg[5 * FG::P2] = d[6];
-            rg[6 * FG::P2] = d[7];
+            if (own) {
+                float* w = tq + m5(r5 + 2) * 4 * FG::NT;   // plane s+2
+                w[0 * FG::NT] = d[4];
+                w[1 * FG::NT] = d[5];
+                w[2 * FG::NT] = d[2];
+                w[3 * FG::NT] = d[8];
+            }
         }
         // (4) Jv at plane s (its derived ring plane was written two steps ago)
         if (s >= z0 && mine) {
-            const float* l2 = L2 + c2o;
-            const float Ac[5] = {q0[2][0], q0[2][1], q0[2][2], p0[2][0], q0[2][3]};
-            const float Bc[5] = {q0[2][4], q0[2][5], q0[2][6], p0[2][1], q0[2][7]};
+            const float* l2 = L2 + c2;
+            const float Ac[5] = {Q[2][0], Q[2][1], Q[2][2], P[2][0], Q[2][3]};
+            const float Bc[5] = {Q[2][4], Q[2][5], Q[2][6], P[2][1], Q[2][7]};
             const float ih[2] = {ihx, ihy};
             float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
             float divB = 0.f, divW = 0.f, gp[3];
-            // x and y: W = A + e B and B at the taps from LDS; the flux
-            // difference A_j B_f + B_j W_f with A_j = W_j - e B_j formed once
-            // per tap for all fields
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int st = j == 0 ? 1 : FG::SX2;
@@ -1016,12 +996,10 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                     if (g.convection) acc[f] += d5(pr[0], pr[1], pr[2], pr[3], ih[j]) + Ac[j] * dB + Bc[j] * dW;
                 }
             }
-            // z: the own column's queue at planes s-2, s-1, s+1, s+2; the flux
-            // difference written as W_z B_f + B_z A_f with W_z formed once per tap
             {
                 constexpr int oz[4] = {0, 1, 3, 4};
-                auto za = [&](int f, int k) { return f == 3 ? p0[oz[k]][0] : q0[oz[k]][f == 4 ? 3 : f]; };
-                auto zb = [&](int f, int k) { return f == 3 ? p0[oz[k]][1] : q0[oz[k]][(f == 4 ? 3 : f) + 4]; };
+                auto za = [&](int f, int k) { return f == 3 ? P[oz[k]][0] : Q[oz[k]][f == 4 ? 3 : f]; };
+                auto zb = [&](int f, int k) { return f == 3 ? P[oz[k]][1] : Q[oz[k]][(f == 4 ? 3 : f) + 4]; };
                 float wz[4], bz[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -1048,7 +1026,7 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                 }
             }
             // divergences of the stress and heat-flux differences
-            const float* rg = RG + r3 * 7 * FG::P2 + c2o;
+            const float* rg = RG + r3 * 7 * FG::P2 + c2;
             auto Dx = [&](int c) {
                 const float* r = rg + c * FG::P2;
                 return d5(r[-2], r[-1], r[1], r[2], ihx);
@@ -1057,7 +1035,13 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
                 const float* r = rg + c * FG::P2;
                 return d5(r[-2 * FG::SX2], r[-FG::SX2], r[FG::SX2], r[2 * FG::SX2], ihy);
             };
-            auto Dz = [&](int c) { return d5(tq[0][c], tq[1][c], tq[3][c], tq[4][c], ihz); };
+            const int sl0 = r5 * 4 * FG::NT, slm2 = m5(r5 + 3) * 4 * FG::NT, slm1 = m5(r5 + 4) * 4 * FG::NT,
+                      slp1 = m5(r5 + 1) * 4 * FG::NT, slp2 = m5(r5 + 2) * 4 * FG::NT;
+            (void)sl0;
+            auto Dz = [&](int c) {
+                return d5(tq[slm2 + c * FG::NT], tq[slm1 + c * FG::NT], tq[slp1 + c * FG::NT],
+                          tq[slp2 + c * FG::NT], ihz);
+            };
             float dF[5];
             dF[0] = -0.5f * acc[0] - th0 * gp[0] + Dx(0) + Dy(2) + Dz(0);
             dF[1] = -0.5f * acc[1] - th0 * gp[1] + Dx(2) + Dy(1) + Dz(1);
@@ -1075,32 +1059,35 @@ __global__ __launch_bounds__(32 * TY) void k3f_jv(Geo g, const float* __restrict
         // (5) advance the queues by one plane
         if (more) {
             fix8(n0, m0);
-            fix8(n1, m1);
-            fix8(n4, m4);
             fixp(np0, mp0);
-            fixp(np1, mp1);
+            if (own) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
+                for (int k = 0; k < 6; ++k)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) q0[k][c] = q0[k + 1][c];
+                    for (int c = 0; c < 8; ++c) Q[k][c] = Q[k + 1][c];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) q0[6][c] = n0[c];
+                for (int c = 0; c < 8; ++c) Q[6][c] = n0[c];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                p0[k][0] = p0[k + 1][0];
-                p0[k][1] = p0[k + 1][1];
+                for (int k = 0; k < 4; ++k) {
+                    P[k][0] = P[k + 1][0];
+                    P[k][1] = P[k + 1][1];
+                }
+                P[4][0] = np0[0];
+                P[4][1] = np0[1];
+            } else {
+                fix8(Q[6], m4);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) Q[k][c] = Q[k + 1][c];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    Q[4][c] = n0[c];
+                    Q[5][c] = Q[6][c];
+                }
+                P[0][0] = np0[0];
+                P[0][1] = np0[1];
             }
-            p0[4][0] = np0[0];
-            p0[4][1] = np0[1];
-            if (has1) {
-                const int slot = r5 * 8 * FG::NRIM2 + tid;   // plane s + 5 replaces plane s
-#pragma unroll
-                for (int c = 0; c < 8; ++c) RQ[slot + c * FG::NRIM2] = n1[c];
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) r4[c] = n4[c];
-            p1[0] = np1[0];
-            p1[1] = np1[1];
         }
         r5 = r5 == 4 ? 0 : r5 + 1;
         r3 = r3 == 2 ? 0 : r3 + 1;
@@ -1695,9 +1682,9 @@ hipError_t launch3_apply_F(const Geo& g, const T* u, const T* f, T* out, int wha
 }
 
 // Planes per workgroup of the single-pass Jv: enough z chunks for one
-// workgroup per compute unit (256 CUs; a 32 x 16 workgroup holds 150 KB of
-// LDS), at least 16 planes per chunk (each chunk re-forms four planes of
-// derived quantities at its start).
+// workgroup per compute unit (256 CUs; a workgroup of 32 x 16 columns holds
+// 157 KB of LDS), at least 16 planes per chunk (each chunk re-forms four
+// planes of derived quantities at its start).
 inline int fused_kzc(int nx, int ny, int nz, int ty) {
     const long long cols = (long long)((nx + 31) / 32) * ((ny + ty - 1) / ty);
     const long long want = (256 + cols - 1) / cols;
@@ -1711,7 +1698,7 @@ hipError_t launch3_jv_fused(const Geo& g, const float* u, const float* v, double
     constexpr int TY = 16;
     const int kzc = fused_kzc(g.nx, g.ny, g.nz, TY);
     const int nblk = ((g.nx + 31) / 32) * ((g.ny + TY - 1) / TY) * ((g.nz + kzc - 1) / kzc);
-    hipLaunchKernelGGL((k3f_jv<TY>), dim3(nblk), dim3(32 * TY), 0, s, g, u, v, eps, eps_dev, out, kzc);
+    hipLaunchKernelGGL((k3f_jv<TY>), dim3(nblk), dim3(32 * TY + 256), 0, s, g, u, v, eps, eps_dev, out, kzc);
     return hipGetLastError();
 }
 

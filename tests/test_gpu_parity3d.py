@@ -172,7 +172,7 @@ JV32_CASES = {
 def test_jv32_3d_single_pass_and_two_pass(name, mode):
     """The FP32 Jv of both 3D forms (variant 7: one z-marching launch, variant 6:
     two launches with the derived components in HBM) against the FP64 oracle on
-    FP32-rounded inputs, across several 32 x 8 column blocks and z chunks with
+    FP32-rounded inputs, across several 32 x 16 column blocks and z chunks with
     ragged edges, every boundary kind and closure."""
     prob = JV32_CASES[name]()
     U = I.smooth_flow_state(prob, seed=21).astype(np.float32).astype(np.float64)
