@@ -842,41 +842,33 @@ __global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __re
     const int c4 = own ? (ty + 4) * FG::SX4 + tx + 4 : (ly1 + 2) * FG::SX4 + lx1 + 2;
     const int c4x = ly4 * FG::SX4 + lx4;
 
-    // register queues shared by the two roles (slot 0 oldest)
-    //   own:  Q[0..6] planes s-2 .. s+4, P[0..4] p at s-2 .. s+2
-    //   ring: Q[0..4] ring-of-2 planes s .. s+4, Q[5] ring-of-4 plane s+2,
-    //         Q[6] its next plane in flight, P[0] ring-of-2 p at plane s
+    // register queues, one layout for both roles so that both advance them
+    // the same way (slot 0 oldest): Q[2..6] the column's planes s .. s+4 and
+    // P[2] its p at plane s; own columns also Q[0], Q[1] (planes s-2, s-1)
+    // and P[0], P[1], P[3], P[4] (p at s-2 .. s+2); ring threads keep their
+    // ring-of-4 column's plane s+2 in Q[0] and receive its next plane in Q[1]
+    // and the next p of their ring-of-2 column in P[3] (each moved down one
+    // slot by the advance)
     float Q[7][8];
     float P[5][2];
     const int sb = z0 - 4;   // first step: the derived stage starts at plane z0 - 2
     {
         long long pl;
         unsigned nz_;
-        if (own) {
 #pragma unroll
-            for (int k = 0; k < 7; ++k) {
-                zmap(sb - 2 + k, pl, nz_);
+        for (int k = 0; k < 7; ++k) {
+            zmap(sb - 2 + k, pl, nz_);
+            if (own || k >= 2) {
                 ld8(offA, pl, Q[k]);
                 fix8(Q[k], negA ^ nz_);
-                if (k < 5) {
-                    ldp(offA, pl, P[k]);
-                    fixp(P[k], negA ^ nz_);
-                }
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                zmap(sb + k, pl, nz_);
-                ld8(offA, pl, Q[k]);
-                fix8(Q[k], negA ^ nz_);
-                if (k == 0) {
-                    ldp(offA, pl, P[0]);
-                    fixp(P[0], negA ^ nz_);
-                }
-                if (k == 2) {
-                    ld8(offB, pl, Q[5]);
-                    fix8(Q[5], negB ^ nz_);
-                }
+            if (own ? k < 5 : k == 2) {
+                ldp(offA, pl, P[k]);
+                fixp(P[k], negA ^ nz_);
+            }
+            if (!own && k == 4) {
+                ld8(offB, pl, Q[0]);   // ring-of-4 column, plane sb + 2
+                fix8(Q[0], negB ^ nz_);
             }
         }
     }
@@ -901,24 +893,21 @@ __global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __re
 #pragma unroll
                 for (int k = 0; k < 10; ++k) L2[k * FG::P2 + c2] = a[k];
             };
-            if (own)
-                put(Q[4], Q[2], P[2]);
-            else if (has1)
-                put(Q[2], Q[0], P[0]);
+            if (own || has1) put(Q[4], Q[2], P[2]);
             if (has4) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = Q[5][k];
+                for (int k = 0; k < 8; ++k) L4[k * FG::P4 + c4x] = Q[0][k];
             }
         }
         __syncthreads();
         // (2) loads for the next step (consumed after the closing barrier)
         const bool more = s + 1 < z1;
         float n0[8], np0[2];
-        unsigned m0 = 0u, mp0 = 0u, m4 = 0u;
+        unsigned m0 = 0u, mp0 = 0u, m1 = 0u, m4 = 0u;
         if (more) {
             long long pl;
             unsigned zn;
-            zmap(s + 5, pl, zn);   // own: plane s+5; ring: ring-of-2 plane s+5
+            zmap(s + 5, pl, zn);   // the column's plane s+5
             if (own || has1) ld8(offA, pl, n0);
             m0 = negA ^ zn;
             if (own) {
@@ -927,10 +916,10 @@ __global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __re
                 mp0 = negA ^ zn;
             } else {
                 zmap(s + 1, pl, zn);
-                if (has1) ldp(offA, pl, np0);
-                mp0 = negA ^ zn;
+                if (has1) ldp(offA, pl, P[3]);   // ring-of-2 p at plane s+1
+                m1 = negA ^ zn;
                 zmap(s + 3, pl, zn);
-                if (has4) ld8(offB, pl, Q[6]);
+                if (has4) ld8(offB, pl, Q[1]);   // ring-of-4 plane s+3
                 m4 = negB ^ zn;
             }
         }
@@ -938,10 +927,7 @@ __global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __re
         const int slotA = m3(r3 + 2);
         if (own || has1) {
             float d[9];
-            if (own)
-                fused_derived<TY>(g, L4 + c4, [&](int k, int f) { return Q[2 + k][f]; }, e, ihx, ihy, ihz, d);
-            else
-                fused_derived<TY>(g, L4 + c4, [&](int k, int f) { return Q[k][f]; }, e, ihx, ihy, ihz, d);
+            fused_derived<TY>(g, L4 + c4, [&](int k, int f) { return Q[2 + k][f]; }, e, ihx, ihy, ihz, d);
             float* rg = RG + slotA * 7 * FG::P2 + c2;
             rg[0 * FG::P2] = d[0];
             rg[1 * FG::P2] = d[1];
@@ -1060,34 +1046,23 @@ __global__ __launch_bounds__(32 * TY + 256) void k3f_jv(Geo g, const float* __re
         if (more) {
             fix8(n0, m0);
             fixp(np0, mp0);
-            if (own) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) Q[k][c] = Q[k + 1][c];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) Q[6][c] = n0[c];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    P[k][0] = P[k + 1][0];
-                    P[k][1] = P[k + 1][1];
-                }
-                P[4][0] = np0[0];
-                P[4][1] = np0[1];
-            } else {
-                fix8(Q[6], m4);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) Q[k][c] = Q[k + 1][c];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    Q[4][c] = n0[c];
-                    Q[5][c] = Q[6][c];
-                }
-                P[0][0] = np0[0];
-                P[0][1] = np0[1];
+            if (!own) {
+                fix8(Q[1], m4);
+                fixp(P[3], m1);
             }
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) Q[k][c] = Q[k + 1][c];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) Q[6][c] = n0[c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                P[k][0] = P[k + 1][0];
+                P[k][1] = P[k + 1][1];
+            }
+            P[4][0] = np0[0];
+            P[4][1] = np0[1];
         }
         r5 = r5 == 4 ? 0 : r5 + 1;
         r3 = r3 == 2 ? 0 : r3 + 1;
