@@ -3,9 +3,11 @@
 //     z = (dt/2) r + s N(r / s),     s = RMS of r over all fields (1 if r = 0),
 //     N = conv(nf->16) GELU conv(16->16) GELU conv(16->16) GELU conv(16->nf),
 // 3x3 kernels with a dilation d_l per layer (taps at d_l * (-1, 0, 1), d_l <= 8),
-// zero padding, exact erf GELU.  Inference runs in BF16 on MFMA
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one 3x3 tap per instruction);
-// training (forward, backward, Adam on FP32 master weights) runs in FP32.
+// zero padding, erf GELU.  Inference runs in BF16 on MFMA
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one 3x3 tap per instruction,
+// erf by a rational approximation inside the BF16 rounding); training
+// (forward, backward, Adam on FP32 master weights) runs in FP32 with the
+// exact erf.
 //
 // The FP32 training activations are channel-major [c][nz][nx] like the state
 // vectors; the BF16 inference activations are pixel-major [pixel][16], so one
@@ -45,6 +47,19 @@ __device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest 
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU of the BF16 inference path: erf by the rational approximation 7.1.26 of
+// Abramowitz and Stegun (absolute error below 1.5e-7), written through erfc,
+// 1 + erf(x / sqrt2) = 2 - c or c with c = erfc(|x| / sqrt2), so that the
+// negative tail keeps a relative error below 2e-3, inside the BF16 rounding
+// (2^-8) of the activations.
+__device__ __forceinline__ float gelu_fast(float x) {
+    const float t = fabsf(x) * 0.70710678118654752f;
+    const float k = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * t);
+    const float poly =
+        k * (0.254829592f + k * (-0.284496736f + k * (1.421413741f + k * (-1.453152027f + k * 1.061405429f))));
+    const float c = poly * __expf(-t * t);
+    return 0.5f * x * (x >= 0.0f ? 2.0f - c : c);
+}
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.3989422804014327f;
 }
@@ -286,7 +301,7 @@ __device__ __forceinline__ void layer_out(const f32x4_t& acc, const float (&bias
     } else {
         u16x4_t o;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
+        for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu_fast(acc[i] + bias[i]));
         *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;
     }
 }

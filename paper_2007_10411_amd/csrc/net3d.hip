@@ -2,9 +2,10 @@
 // 3 x 3 x 3 kernels (taps at (-1, 0, 1) along z, y and x, dilation 1):
 //     z = (dt/2) r + s N(r / s),     s = RMS of r over all fields (1 if r = 0),
 //     N = conv(nf->16) GELU conv(16->16) GELU conv(16->16) GELU conv(16->nf),
-// zero padding, exact erf GELU.  Inference runs in BF16 on MFMA
+// zero padding, erf GELU.  Inference runs in BF16 on MFMA
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation, one tap per instruction, 27
-// per 16-point subtile); training (forward, backward, Adam) runs in FP32.
+// per 16-point subtile, erf by a rational approximation inside the BF16
+// rounding); training (forward, backward, Adam) runs in FP32 with the exact erf.
 //
 // The FP32 training activations are channel-major [c][nz][ny][nx] like the
 // state vectors; the BF16 inference activations are pixel-major [point][16].
@@ -40,6 +41,19 @@ __device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest 
 }
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU of the BF16 inference path: erf by the rational approximation 7.1.26 of
+// Abramowitz and Stegun (absolute error below 1.5e-7), written through erfc,
+// 1 + erf(x / sqrt2) = 2 - c or c with c = erfc(|x| / sqrt2), so that the
+// negative tail keeps a relative error below 2e-3, inside the BF16 rounding
+// (2^-8) of the activations.
+__device__ __forceinline__ float gelu_fast(float x) {
+    const float t = fabsf(x) * 0.70710678118654752f;
+    const float k = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * t);
+    const float poly =
+        k * (0.254829592f + k * (-0.284496736f + k * (1.421413741f + k * (-1.453152027f + k * 1.061405429f))));
+    const float c = poly * __expf(-t * t);
+    return 0.5f * x * (x >= 0.0f ? 2.0f - c : c);
+}
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.3989422804014327f;
 }
@@ -115,33 +129,40 @@ __global__ __launch_bounds__(256) void k3_conv_f32(int nx, int ny, int nz, const
     }
 }
 
-// BF16 MFMA convolution for inference.  Block: 64 x 4 points of one z plane,
-// wavefront w computes row y0 + w as four 16-point subtiles; the input (3 x 6 x
-// 66 points, 16 channels, channel innermost) is staged in LDS once.  A = the
-// weights (output x input channels), B = input channels x 16 points, so each
-// lane ends with four consecutive output channels of one point.
-// Optional fusions of the inference launches, as in the 2D network: spart
-// (the first layer finishes the scale from k_field_sumsq's partials, block 0
-// stores it in s) and zpart (the last layer's per-block partial sum of z^2).
+// BF16 3 x 3 x 3 convolution for inference, marching along z: a block of
+// four waves owns 64 x 8 output points over a chunk of planes; the input
+// planes z-1, z, z+1 over the tile grown by one sit in an LDS ring of three
+// (pixel-major, 16 BF16 channels per point), and the next plane is loaded to
+// registers while plane z is computed.  Each wave computes two output rows of
+// four 16-point subtiles; a B fragment of an input row serves the taps of both
+// rows that read it (four rows loaded per (dz, dx) instead of six).
+// v_mfma_f32_16x16x16_bf16 with A = the weights of one tap (output x input
+// channels) and B = input channels x 16 points, FP32 accumulation, so each
+// lane ends with four consecutive output channels of one point.  FIRST: input
+// r / s (channel-major FP32); MID, LAST: pixel-major BF16 activations.
+// Optional fusions, as in the 2D network: spart (the first layer finishes the
+// scale from per-block partial sums of r^2, block 0 stores it in s) and zpart
+// (the last layer's per-block partial sum of z^2).
+constexpr int kMX = 64, kMY = 8;                                    // output points per block and plane
+constexpr int kMSX = kMX + 2, kMSY = kMY + 2, kMPL = kMSX * kMSY;   // staged plane: 660 points
+constexpr int kMPT = (kMPL + 255) / 256;                            // staged points per thread (3)
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, const unsigned short* __restrict__ in,
-                                                    int cin, const unsigned short* __restrict__ Wf,
-                                                    const float* __restrict__ b, int cout,
-                                                    unsigned short* __restrict__ post, const float* __restrict__ r,
-                                                    float* __restrict__ s, float half_dt,
-                                                    float* __restrict__ z, const double* __restrict__ spart,
-                                                    int snblk, int snsets, double* __restrict__ zpart) {
-    __shared__ __align__(16) unsigned short sin_[kSZ][kSY][kSX][kHid];   // pixel-major, channel-innermost
+__global__ __launch_bounds__(256) void k3_conv_march(int nx, int ny, int nz, const unsigned short* __restrict__ in,
+                                                     int cin, const unsigned short* __restrict__ Wf,
+                                                     const float* __restrict__ b, int cout,
+                                                     unsigned short* __restrict__ post, const float* __restrict__ r,
+                                                     float* __restrict__ s, float half_dt, float* __restrict__ z,
+                                                     const double* __restrict__ spart, int snblk, int snsets,
+                                                     double* __restrict__ zpart, int kzc) {
+    __shared__ __align__(16) unsigned short ring[3][kMPL][kHid];
     __shared__ double red[4];
     __shared__ float s_sh;
     const long long np = (long long)nx * ny * nz;
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, gz = blockIdx.z;
-    constexpr int plane = kSZ * kSY * kSX;
+    const int x0 = blockIdx.x * kMX, y0 = blockIdx.y * kMY;
+    const int zc0 = blockIdx.z * kzc, zc1 = min(zc0 + kzc, nz);
+    float sc = 1.0f;   // the input scale (FIRST)
     if (MODE == L_FIRST) {
-        // the state vector r: channel-major FP32, scaled by s and rounded to
-        // BF16; one point per thread and pass, its 16-channel row (zeros beyond
-        // cin) stored as two 16-byte halves
-        float sc[kHid];
         if (spart) {
             double tot = 0.0;
             for (int f = 0; f < snsets; ++f) tot += sum_partials(spart + (long long)f * snblk, snblk, 1, 0, red);
@@ -150,61 +171,70 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
                 s_sh = v > 0.0 ? (float)v : 1.0f;
             }
             __syncthreads();
-            const float sv = s_sh;
-            if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < cin) s[threadIdx.x] = sv;
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) sc[c] = sv;
+            sc = s_sh;
+            if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < cin) s[threadIdx.x] = sc;
         } else {
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) sc[c] = c < cin ? s[c] : 1.0f;
-        }
-        for (int p = threadIdx.x; p < plane; p += 256) {
-            const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
-            const int ly = rem / kSX, lx = rem - ly * kSX;
-            const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
-            const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz;
-            unsigned short h[kHid];
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) {
-                h[c] = 0;
-                if (c < cin && inside) h[c] = f2bf(r[(long long)c * np + ((long long)zz * ny + gy) * nx + gx] / sc[c]);
-            }
-            uint4 lo, hi;
-            lo.x = h[0] | ((unsigned)h[1] << 16), lo.y = h[2] | ((unsigned)h[3] << 16);
-            lo.z = h[4] | ((unsigned)h[5] << 16), lo.w = h[6] | ((unsigned)h[7] << 16);
-            hi.x = h[8] | ((unsigned)h[9] << 16), hi.y = h[10] | ((unsigned)h[11] << 16);
-            hi.z = h[12] | ((unsigned)h[13] << 16), hi.w = h[14] | ((unsigned)h[15] << 16);
-            *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][0]) = lo;
-            *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][8]) = hi;
-        }
-    } else {
-        // hidden activations: pixel-major BF16, 32 bytes per point, copied as two
-        // 16-byte halves (four loads in flight per thread before their stores)
-        constexpr int nh = plane * 2;
-        for (int i0 = threadIdx.x; i0 < nh; i0 += 4 * 256) {
-            uint4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = i0 + u * 256, p = idx >> 1;
-                const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
-                const int ly = rem / kSX, lx = rem - ly * kSX;
-                const int gx = x0 + lx - 1, gy = y0 + ly - 1, zz = gz + lz - 1;
-                v[u] = uint4{0u, 0u, 0u, 0u};
-                if (idx < nh && gx >= 0 && gx < nx && gy >= 0 && gy < ny && zz >= 0 && zz < nz)
-                    v[u] = reinterpret_cast<const uint4*>(in + (((long long)zz * ny + gy) * nx + gx) * kHid)[idx & 1];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = i0 + u * 256, p = idx >> 1;
-                const int lz = p / (kSY * kSX), rem = p - lz * (kSY * kSX);
-                const int ly = rem / kSX, lx = rem - ly * kSX;
-                if (idx < nh) *reinterpret_cast<uint4*>(&sin_[lz][ly][lx][8 * (idx & 1)]) = v[u];
-            }
+            sc = s[0];   // one scale for every field
         }
     }
+    // the staged points of this thread: p = tid + 256 k
+    int soff[kMPT];
+    bool inside[kMPT];
+#pragma unroll
+    for (int k = 0; k < kMPT; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        const int ly = p / kMSX, lx = p - ly * kMSX;
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        inside[k] = p < kMPL && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        soff[k] = inside[k] ? gy * nx + gx : 0;
+    }
+    // one plane's share of this thread into registers (zeros outside the
+    // grid); FIRST keeps the raw FP32 values and converts them at the store,
+    // so that the loads stay in flight under the compute of the plane before
+    constexpr int kMaxIn = 8;   // input fields of the first layer (nf <= 8)
+    uint4 st[kMPT][2];
+    float rv[kMPT][kMaxIn];
+    auto load_plane = [&](int zz) {
+        const bool zin = zz >= 0 && zz < nz;
+#pragma unroll
+        for (int k = 0; k < kMPT; ++k) {
+            const bool ok = zin && inside[k];
+            const long long pt = (long long)zz * nx * ny + soff[k];
+            if (MODE == L_FIRST) {
+#pragma unroll
+                for (int c = 0; c < kMaxIn; ++c) rv[k][c] = ok && c < cin ? r[(long long)c * np + pt] : 0.0f;
+            } else {
+                st[k][0] = uint4{0u, 0u, 0u, 0u};
+                st[k][1] = uint4{0u, 0u, 0u, 0u};
+                if (ok) {
+                    const uint4* src = reinterpret_cast<const uint4*>(in + pt * kHid);
+                    st[k][0] = src[0];
+                    st[k][1] = src[1];
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int slot) {
+#pragma unroll
+        for (int k = 0; k < kMPT; ++k) {
+            const int p = threadIdx.x + 256 * k;
+            if (MODE == L_FIRST) {
+                unsigned short hv[kMaxIn];
+#pragma unroll
+                for (int c = 0; c < kMaxIn; ++c) hv[c] = c < cin ? f2bf(rv[k][c] / sc) : 0;
+                st[k][0] = uint4{hv[0] | ((unsigned)hv[1] << 16), hv[2] | ((unsigned)hv[3] << 16),
+                                 hv[4] | ((unsigned)hv[5] << 16), hv[6] | ((unsigned)hv[7] << 16)};
+                st[k][1] = uint4{0u, 0u, 0u, 0u};
+            }
+            if (p < kMPL) {
+                *reinterpret_cast<uint4*>(&ring[slot][p][0]) = st[k][0];
+                *reinterpret_cast<uint4*>(&ring[slot][p][8]) = st[k][1];
+            }
+        }
+    };
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
-    bf16x4_t wfrag[kTaps];                           // A fragments (weights): W[t][co = col][ci = 4 kg ..]
+    bf16x4_t wfrag[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) {
         const unsigned short* wp = Wf + ((t * kHid + col) * kHid + 4 * kg);
@@ -213,47 +243,106 @@ __global__ __launch_bounds__(256) void k3_conv_mfma(int nx, int ny, int nz, cons
     float bias[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) bias[i] = 4 * kg + i < cout ? b[4 * kg + i] : 0.0f;
+    auto slot_of = [](int zz) { return (zz + 3) % 3; };   // zz >= -1
+#pragma unroll 1
+    for (int zz = zc0 - 1; zz <= zc0 + 1; ++zz) {
+        load_plane(zz);
+        store_plane(slot_of(zz));
+    }
     __syncthreads();
-    const int gy = y0 + wv;
+    const int R0 = 2 * wv;   // this wave's output rows R0, R0 + 1 (staged rows R0 .. R0 + 3)
     double zz2 = 0.0;
-    if (gy < ny) {
+    for (int zo = zc0; zo < zc1; ++zo) {
+        const bool more = zo + 1 < zc1;
+        if (more) load_plane(zo + 2);
+        // LAST: r at this lane's outputs, loaded before the MFMAs
+        float rr[2][4][4];
+        if (MODE == L_LAST) {
 #pragma unroll
-        for (int st = 0; st < kTX / 16; ++st) {
-            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            const int px = st * 16 + col;                   // B column: point of this lane
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int t = 0; t < kTaps; ++t) {
-                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-                const bf16x4_t xv = *reinterpret_cast<const bf16x4_t*>(&sin_[dz][wv + dy][px + dx][4 * kg]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[t], xv, acc, 0, 0, 0);
-            }
-            // D[co = 4 kg + i][point = col]: four consecutive output channels of one point
-            const int gx = x0 + px;
-            if (gx >= nx) continue;
-            const long long pt = ((long long)gz * ny + gy) * nx + gx;
-            if (MODE == L_LAST) {
+                for (int q = 0; q < 4; ++q) {
+                    const int gy = y0 + R0 + h, gx = x0 + q * 16 + col;
+                    const long long pt = ((long long)zo * ny + gy) * nx + gx;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int co = 4 * kg + i;
-                    if (co < cout) {
-                        const float zv = half_dt * r[co * np + pt] + s[co] * (acc[i] + bias[i]);
-                        z[co * np + pt] = zv;
-                        zz2 += (double)zv * zv;
+                    for (int i = 0; i < 4; ++i)
+                        rr[h][q][i] = gy < ny && gx < nx && 4 * kg + i < cout ? r[(4 * kg + i) * np + pt] : 0.0f;
+                }
+        }
+        f32x4_t acc0[4], acc1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc0[q] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+            acc1[q] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            const int sl = slot_of(zo - 1 + dz);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+                for (int yi = 0; yi < 4; ++yi) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bf16x4_t xv =
+                            *reinterpret_cast<const bf16x4_t*>(&ring[sl][(R0 + yi) * kMSX + q * 16 + col + dx][4 * kg]);
+                        if (yi <= 2)
+                            acc0[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[dz * 9 + yi * 3 + dx], xv,
+                                                                                 acc0[q], 0, 0, 0);
+                        if (yi >= 1)
+                            acc1[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wfrag[dz * 9 + (yi - 1) * 3 + dx],
+                                                                                 xv, acc1[q], 0, 0, 0);
                     }
                 }
-            } else {
-                u16x4_t o;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu(acc[i] + bias[i]));
-                *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;   // pixel-major, 8-byte store
             }
         }
+        // D[co = 4 kg + i][point = col]: four consecutive output channels of one point
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gy = y0 + R0 + h;
+            if (gy >= ny) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gx = x0 + q * 16 + col;
+                if (gx >= nx) continue;
+                const f32x4_t& acc = h == 0 ? acc0[q] : acc1[q];
+                const long long pt = ((long long)zo * ny + gy) * nx + gx;
+                if (MODE == L_LAST) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int co = 4 * kg + i;
+                        if (co < cout) {
+                            const float zv = half_dt * rr[h][q][i] + s[co] * (acc[i] + bias[i]);
+                            z[co * np + pt] = zv;
+                            zz2 += (double)zv * zv;
+                        }
+                    }
+                } else {
+                    u16x4_t o;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) o[i] = f2bf(gelu_fast(acc[i] + bias[i]));
+                    *reinterpret_cast<u16x4_t*>(post + pt * kHid + 4 * kg) = o;
+                }
+            }
+        }
+        __syncthreads();   // every wave is done with plane zo - 1
+        if (more) store_plane(slot_of(zo + 2));
+        __syncthreads();
     }
     if (MODE == L_LAST && zpart) {
         const double t = block_sum256(zz2, red);
         if (threadIdx.x == 0)
             zpart[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
     }
+}
+
+// planes per block of the marching convolution: about two blocks per compute
+// unit (256 CUs) at the largest grids, at least one plane
+inline int march_kzc(int nx, int ny, int nz) {
+    const long long cols = (long long)((nx + kMX - 1) / kMX) * ((ny + kMY - 1) / kMY);
+    const long long want = (512 + cols - 1) / cols;
+    const int kzc = (int)((nz + want - 1) / want);
+    return kzc < 1 ? 1 : kzc;
 }
 
 // dW[co][ci][t] and db[co] partial sums over a 64 x 4 x kWZ block of points:
@@ -392,20 +481,22 @@ hipError_t net3_apply(const NetBuffers& nb, int nx, int ny, int nz, int nf, floa
         unsigned short* a1 = nb.abf + kHid * np;
         const int wl = kTaps * kHid * kHid;
         const double* none = nullptr;
-        hipLaunchKernelGGL((k3_conv_mfma<L_FIRST>), grid, dim3(256), 0, st, nx, ny, nz,
+        const int kzc = march_kzc(nx, ny, nz);
+        const dim3 mgrid((nx + kMX - 1) / kMX, (ny + kMY - 1) / kMY, (nz + kzc - 1) / kzc);
+        hipLaunchKernelGGL((k3_conv_march<L_FIRST>), mgrid, dim3(256), 0, st, nx, ny, nz,
                            (const unsigned short*)nullptr, L[0].cin, nb.wbf + 0 * wl, nb.theta + L[0].boff, L[0].cout,
-                           a0, r, nb.s, half_dt, (float*)nullptr, spart, snblk, snsets, (double*)nullptr);
-        hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
+                           a0, r, nb.s, half_dt, (float*)nullptr, spart, snblk, snsets, (double*)nullptr, kzc);
+        hipLaunchKernelGGL((k3_conv_march<L_MID>), mgrid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
                            L[1].cin, nb.wbf + 1 * wl, nb.theta + L[1].boff, L[1].cout, a1, r, nb.s, half_dt,
-                           (float*)nullptr, none, 0, 0, (double*)nullptr);
-        hipLaunchKernelGGL((k3_conv_mfma<L_MID>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a1,
+                           (float*)nullptr, none, 0, 0, (double*)nullptr, kzc);
+        hipLaunchKernelGGL((k3_conv_march<L_MID>), mgrid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a1,
                            L[2].cin, nb.wbf + 2 * wl, nb.theta + L[2].boff, L[2].cout, a0, r, nb.s, half_dt,
-                           (float*)nullptr, none, 0, 0, (double*)nullptr);
-        hipLaunchKernelGGL((k3_conv_mfma<L_LAST>), grid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
+                           (float*)nullptr, none, 0, 0, (double*)nullptr, kzc);
+        hipLaunchKernelGGL((k3_conv_march<L_LAST>), mgrid, dim3(256), 0, st, nx, ny, nz, (const unsigned short*)a0,
                            L[3].cin, nb.wbf + 3 * wl, nb.theta + L[3].boff, L[3].cout, (unsigned short*)nullptr, r,
-                           nb.s, half_dt, z, none, 0, 0, ea ? ea->partials : (double*)nullptr);
+                           nb.s, half_dt, z, none, 0, 0, ea ? ea->partials : (double*)nullptr, kzc);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        return ea ? launch_eps_finish((int)(grid.x * grid.y * grid.z), *ea, st) : hipSuccess;
+        return ea ? launch_eps_finish((int)(mgrid.x * mgrid.y * mgrid.z), *ea, st) : hipSuccess;
     }
     if (ea || rpart) return hipErrorInvalidValue;   // BF16 path only
     hipError_t e = net_field_scale(r, np, nf, nb.partials, nb.s, st);
