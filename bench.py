@@ -651,7 +651,7 @@ def main():
         "roofline_pc": roof("mixed", "pc", kernels["pc"], traffic=counter_traffic(traffic_name["pc"])),
     }
     if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
-        out["roofline_net"] = roof("learned", "net", "k3_conv_mfma x4 (BF16 3x3x3 conv layers of the learned PC)",
+        out["roofline_net"] = roof("learned", "net", "k3_conv_march x4 (BF16 3x3x3 conv layers of the learned PC, z-marching)",
                                    "mfma")
     if not args.no_micro:
         del legs
