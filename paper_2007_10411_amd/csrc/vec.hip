@@ -675,10 +675,10 @@ __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const 
     const double inv_r = coef[2 * kDgCoefW], cw = coef[2 * kDgCoefW + 1];
     const int step = gridDim.x * kBlock;
     double acc = 0.0;
-    // Every value is touched once here and the next pass (a Jv) reads other data,
-    // so the loads and stores take the streaming (non-temporal) path: 4% more
-    // bandwidth at 5 x 8.4 M points than cached accesses.  The reduction pass
-    // keeps cached loads: its rows are read again by this pass.
+    // Every value is touched once here, so the loads and stores take the
+    // streaming (non-temporal) path: 4% more bandwidth than cached accesses at
+    // 5 x 8.4 M points.  The reduction pass keeps cached loads (measured 3%
+    // slower when streamed): this pass reads its rows again right after it.
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
         const T qv = __builtin_nontemporal_load(q + i), wv = __builtin_nontemporal_load(w + i);
         T x[NV];
