@@ -52,21 +52,32 @@ __global__ __launch_bounds__(256) void k_pc_sweep_2d(Geo g, const T* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Row-marching residual and Jv.  A workgroup owns a strip of kMX columns and
-// walks down a chunk of zc rows, kRB rows per step.  Primitive rows (halo 2W
-// in x) live in a ring of kRB + 3W LDS rows, the stress and heat flux of the
-// rows in a ring of kRB + 2W, so each row is fetched from HBM once per chunk
+// Row-marching residual and Jv.  A workgroup owns a strip of MX columns and
+// walks down a chunk of zc rows, RB rows per step.  Primitive rows (halo 2W
+// in x) live in a ring of RB + 3W LDS rows, the stress and heat flux of the
+// rows in a ring of RB + 2W, so each row is fetched from HBM once per chunk
 // (the tile kernels fetch the 2W-row halo of every tile again).  The next
 // step's rows are loaded to registers while the current step computes.
+//
+// Strip shape: a step derives RB rows of MX + 2W columns and finishes RB rows
+// of MX columns on 256 threads.  MX + 2W = 128 with RB = 2, or 64 with RB = 4,
+// is one derived point per thread (64 columns would leave 4 (64 + 2W) points
+// per step, a second pass for 8 W of them).
 // ---------------------------------------------------------------------------
-constexpr int kMX = 64, kRB = 4;
+// FP32 with W = 2: 124 x 2 (LDS 49 KB, three workgroups per CU).  Otherwise
+// (64 - 2W) x 4: the wide strip's LDS (95 KB for FP32 with W = 4, twice that in
+// FP64) would leave one workgroup per CU.
+template <typename T, int W> struct MarchShape {
+    static constexpr bool kWide = sizeof(T) == 4 && W == 2;
+    static constexpr int MX = kWide ? 128 - 2 * W : 64 - 2 * W, RB = kWide ? 2 : 4;
+};
 
-// One group of kRB primitive rows of NF fields (fields 4.. from the second
-// state), columns x0 - 2W .. x0 + kMX + 2W - 1: fixed positions per thread, so
+// One group of RB primitive rows of NF fields (fields 4.. from the second
+// state), columns x0 - 2W .. x0 + MX + 2W - 1: fixed positions per thread, so
 // the reflected source columns and their x-parity signs are set once.
-template <typename T, int W, int NF>
+template <typename T, int W, int NF, int MX, int RB>
 struct RowStage {
-    static constexpr int SX = kMX + 4 * W, N = kRB * SX;
+    static constexpr int SX = MX + 4 * W, N = RB * SX;
     static constexpr int POS = (N + 255) / 256;
     int col[POS];
     int lrow[POS];
@@ -88,7 +99,7 @@ struct RowStage {
             xneg[p] = m;
         }
     }
-    // rows rbase .. rbase + kRB - 1 (reflected at the walls)
+    // rows rbase .. rbase + RB - 1 (reflected at the walls)
     __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ a, const T* __restrict__ b, int rbase) {
         const long long np = g.npts;
 #pragma unroll
@@ -125,11 +136,14 @@ template <typename T, int W, bool JV>
 __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __restrict__ u, const T* __restrict__ v,
                                                   double eps_in, const double* __restrict__ eps_dev,
                                                   const T* __restrict__ f, T* __restrict__ out, int what) {
-    constexpr int H = 2 * W, SX = kMX + 2 * H, DX = kMX + 2 * W;
+    constexpr int MX = MarchShape<T, W>::MX, RB = MarchShape<T, W>::RB;
+    constexpr int H = 2 * W, SX = MX + 2 * H, DX = MX + 2 * W;
     constexpr int NF = JV ? 8 : 4;
-    constexpr int NA = kRB + 3 * W, NB = kRB + 2 * W;
+    // ring rows: RB + 3W in the march, 4W for the prologue's derived rows
+    constexpr int NA = RB + 3 * W > 4 * W ? RB + 3 * W : 4 * W, NB = RB + 2 * W;
     constexpr int AFS = NA * SX, BFS = NB * DX;   // field strides of the rings
-    static_assert(4 * W <= NA, "prologue rows fit the ring");
+    constexpr int PW = (MX + 63) / 64 * 64;       // threads per output row
+    static_assert(RB * PW <= 256 && H % RB == 0, "a step's rows fit the workgroup");
     __shared__ T sa[NF * AFS];
     __shared__ T sd[5 * BFS];
     const int tid = threadIdx.x;
@@ -144,7 +158,7 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
         bx = logical % gridDim.x;
         by = logical / gridDim.x;
     }
-    const int x0 = bx * kMX, z0 = by * zc, z1 = min(z0 + zc, g.nz);
+    const int x0 = bx * MX, z0 = by * zc, z1 = min(z0 + zc, g.nz);
     const int ra0 = z0 - H;   // primitive row in ring slot 0
     const int rd0 = z0 - W;   // derived row in ring slot 0
     const T ihx = T(g.idx), ihz = T(g.idz);
@@ -185,28 +199,29 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
         }
     };
 
-    RowStage<T, W, NF> st;
+    RowStage<T, W, NF, MX, RB> st;
     st.init(g, x0);
     // prologue: primitive rows z0 - 2W .. z0 + 2W - 1, derived rows z0 - W .. z0 + W - 1
-    for (int rb = z0 - H; rb < z0 + H; rb += kRB) {
+    for (int rb = z0 - H; rb < z0 + H; rb += RB) {
         st.load(g, u, v, rb);
         st.template store<NA>(sa, slotA(rb));
     }
     __syncthreads();
     derive(z0 - W, 2 * W);
     __syncthreads();
-    const int nsteps = (z1 - z0 + kRB - 1) / kRB;
+    const int nsteps = (z1 - z0 + RB - 1) / RB;
     st.load(g, u, v, z0 + H);
-    const int ty = tid / kMX, tx = tid - ty * kMX;
+    const int ty = tid / PW, tx = tid - ty * PW;
+    const bool owner = ty < RB && tx < MX;
     for (int k = 0; k < nsteps; ++k) {
-        const int rb = z0 + k * kRB;
+        const int rb = z0 + k * RB;
         st.template store<NA>(sa, slotA(rb + H));
         __syncthreads();
-        if (k + 1 < nsteps) st.load(g, u, v, rb + kRB + H);
-        derive(rb + W, kRB);
+        if (k + 1 < nsteps) st.load(g, u, v, rb + RB + H);
+        derive(rb + W, RB);
         __syncthreads();
         const int gz = rb + ty, gx = x0 + tx;
-        if (gz < z1 && gx < g.nx) {
+        if (owner && gz < z1 && gx < g.nx) {
             const RingAcc<T, AFS, W> PA = prim(gz, tx + H);
             RingAcc<T, BFS, W> D;
             rows(sd + tx + W, slotD(gz - W), DX, NB, D.r);
@@ -237,7 +252,8 @@ template <typename T, bool JV>
 hipError_t launch_march(const Geo& g, const T* u, const T* v, double eps, const double* eps_dev, const T* f, T* out,
                         int what, hipStream_t s, int var) {
     const int zc = march_rows(var);
-    const dim3 grid((g.nx + kMX - 1) / kMX, (g.nz + zc - 1) / zc);
+    const int mx = g.W == 4 ? MarchShape<T, 4>::MX : MarchShape<T, 2>::MX;
+    const dim3 grid((g.nx + mx - 1) / mx, (g.nz + zc - 1) / zc);
     if (g.W == 4)
         hipLaunchKernelGGL((k_march_2d<T, 4, JV>), grid, dim3(256), 0, s, g, zc, u, v, eps, eps_dev, f, out, what);
     else

@@ -311,22 +311,46 @@ __device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PA, const A
     const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
     const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
     const T s2a = axx * axx + azz * azz + T(2) * axz * axz;
-    const Coef<T> ka = closure_coef(g, s2a);
-    Coef<T> dk = {T(0), T(0), T(0), T(0)};
     // strain of u + e v
     const T cxx = axx + e * bxx, czz = azz + e * bzz, cxz = axz + e * bxz;
-    if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
-        const T sab = axx * bxx + azz * bzz + T(2) * axz * bxz;
-        const T sbb = bxx * bxx + bzz * bzz + T(2) * bxz * bxz;
-        const T s2c = cxx * cxx + czz * czz + T(2) * cxz * cxz;
-        const T den = sqrt(s2a) + sqrt(s2c);
-        const T num = T(2) * sab + e * sbb;
-        if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
-            const T dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
-            const T dkth = dnu * T(g.inv_pr);
-            dk = {dnu, dnu, dkth, dkth};
+    Coef<T> ka, dk = {T(0), T(0), T(0), T(0)};
+    if constexpr (std::is_same<T, float>::value) {
+        // FP32: hardware square root and reciprocal (1 ulp, well inside the FP32
+        // parity bar), |S(u)| shared by nu(u) and the nu difference
+        if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
+            const float sab = axx * bxx + azz * bzz + 2.f * axz * bxz;
+            const float sbb = bxx * bxx + bzz * bzz + 2.f * bxz * bxz;
+            const float s2c = cxx * cxx + czz * czz + 2.f * cxz * cxz;
+            const float ma = __builtin_amdgcn_sqrtf(s2a);
+            const float den = ma + __builtin_amdgcn_sqrtf(s2c);
+            const float num = 2.f * sab + e * sbb;
+            if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+                const float c = g.f.smag_s2, ip = g.f.inv_pr;
+                const float nu = c * ma, dnu = den > 0.f ? c * num * __builtin_amdgcn_rcpf(den) : 0.f;
+                ka = {nu, nu, nu * ip, nu * ip};
+                dk = {dnu, dnu, dnu * ip, dnu * ip};
+            } else {
+                ka = deardorff_coef(g, ma);
+                dk = deardorff_diff(g, ma, den > 0.f ? num / den : 0.f, e);
+            }
         } else {
-            dk = deardorff_diff(g, T(sqrt(s2a)), den > T(0) ? num / den : T(0), e);
+            ka = closure_coef(g, s2a);
+        }
+    } else {
+        ka = closure_coef(g, s2a);
+        if (g.closure == JFNK_CLOSURE_SMAGORINSKY || g.closure == JFNK_CLOSURE_DEARDORFF) {
+            const T sab = axx * bxx + azz * bzz + T(2) * axz * bxz;
+            const T sbb = bxx * bxx + bzz * bzz + T(2) * bxz * bxz;
+            const T s2c = cxx * cxx + czz * czz + T(2) * cxz * cxz;
+            const T den = sqrt(s2a) + sqrt(s2c);
+            const T num = T(2) * sab + e * sbb;
+            if (g.closure == JFNK_CLOSURE_SMAGORINSKY) {
+                const T dnu = den > T(0) ? T(g.smag) * T(1.4142135623730951) * num / den : T(0);
+                const T dkth = dnu * T(g.inv_pr);
+                dk = {dnu, dnu, dkth, dkth};
+            } else {
+                dk = deardorff_diff(g, T(sqrt(s2a)), den > T(0) ? num / den : T(0), e);
+            }
         }
     }
     const T trc = (cxx + czz) * T(1.0 / 3.0), trb = (bxx + bzz) * T(1.0 / 3.0);

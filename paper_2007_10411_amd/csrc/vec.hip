@@ -659,7 +659,18 @@ __global__ __launch_bounds__(1024) void k_dg_finish(const double* __restrict__ p
 // With sq set, each block also leaves the partial sum of the new row's squares
 // in sq[block]: the learned preconditioner, which acts on that row next, takes
 // its input scale from them instead of another pass over the row.
-template <typename T, int NV>
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename T, int NV, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const double* __restrict__ coef,
                                                       double* __restrict__ sq) {
     __shared__ double red[4];
@@ -675,15 +686,17 @@ __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const 
     const double inv_r = coef[2 * kDgCoefW], cw = coef[2 * kDgCoefW + 1];
     const int step = gridDim.x * kBlock;
     double acc = 0.0;
-    // Every value is touched once here, so the loads and stores take the
-    // streaming (non-temporal) path: 4% more bandwidth than cached accesses at
-    // 5 x 8.4 M points.  The reduction pass keeps cached loads (measured 3%
-    // slower when streamed): this pass reads its rows again right after it.
+    // NT: every value is touched once here, so on a basis far beyond the
+    // Infinity Cache the loads and stores take the streaming (non-temporal)
+    // path, 4% more bandwidth than cached accesses at 5 x 8.4 M points.  A
+    // basis the cache holds keeps cached accesses (streaming costs 6% there).
+    // The reduction pass keeps cached loads (3% slower when streamed): this
+    // pass reads its rows again right after it.
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
-        const T qv = __builtin_nontemporal_load(q + i), wv = __builtin_nontemporal_load(w + i);
+        const T qv = ld_stream<NT>(q + i), wv = ld_stream<NT>(w + i);
         T x[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) x[v] = __builtin_nontemporal_load(V + (long long)(v < j ? v : last) * n + i);
+        for (int v = 0; v < NV; ++v) x[v] = ld_stream<NT>(V + (long long)(v < j ? v : last) * n + i);
         __builtin_amdgcn_sched_barrier(0);
         double sqv = (double)qv, sw = (double)wv - cw * (double)qv;
 #pragma unroll
@@ -691,9 +704,9 @@ __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const 
             sqv -= ca[v] * (double)x[v];
             sw -= ce[v] * (double)x[v];
         }
-        __builtin_nontemporal_store((T)(sqv * inv_r), q + i);
+        st_stream<NT>((T)(sqv * inv_r), q + i);
         const T wn = (T)(sw * inv_r);
-        __builtin_nontemporal_store(wn, w + i);
+        st_stream<NT>(wn, w + i);
         acc += (double)wn * (double)wn;
     }
     if (sq) {
@@ -906,12 +919,22 @@ template <typename T>
 hipError_t launch_dg_update(T* V, long long n, int j, const double* coef, hipStream_t s, double* sq) {
     if (j < 0 || j >= kDgMaxRows || n < 1 || n >= (1LL << 30)) return hipErrorInvalidValue;
     const int nb = cgs_blocks(n), ni = (int)n;
-    if (j <= 8)
-        hipLaunchKernelGGL((k_dg_update<T, 8>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
-    else if (j <= 16)
-        hipLaunchKernelGGL((k_dg_update<T, 16>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
-    else
-        hipLaunchKernelGGL((k_dg_update<T, 32>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+    // streaming accesses once 8 rows exceed the 256 MB Infinity Cache
+    if (n * (long long)sizeof(T) >= (32LL << 20)) {
+        if (j <= 8)
+            hipLaunchKernelGGL((k_dg_update<T, 8, true>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+        else if (j <= 16)
+            hipLaunchKernelGGL((k_dg_update<T, 16, true>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+        else
+            hipLaunchKernelGGL((k_dg_update<T, 32, true>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+    } else {
+        if (j <= 8)
+            hipLaunchKernelGGL((k_dg_update<T, 8, false>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+        else if (j <= 16)
+            hipLaunchKernelGGL((k_dg_update<T, 16, false>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+        else
+            hipLaunchKernelGGL((k_dg_update<T, 32, false>), dim3(nb), dim3(kBlock), 0, s, V, ni, j, coef, sq);
+    }
     return hipGetLastError();
 }
 

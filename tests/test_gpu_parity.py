@@ -353,8 +353,9 @@ MARCH_CASES = ["neutral-130x70", "island-noslip-260x36", "constK-periodic-72x24"
 @pytest.mark.parametrize("variant", [3, 4, 5])
 @pytest.mark.parametrize("name", MARCH_CASES)
 def test_row_marching_residual_and_jv(name, variant):
-    """The row-marching kernels (64-column strips over 32, 64 or 256 rows, 4 rows
-    per step; ragged strips, chunks and steps) against the oracle: F and the
+    """The row-marching kernels (strips of 124 x 2 rows per step for FP32 with
+    p = 2, (64 - 2W) x 4 otherwise, over chunks of 32, 64 or 256 rows; ragged
+    strips, chunks and steps) against the oracle: F and the
     residual in FP64 and FP32, the stable Jv in FP64 and FP32."""
     prob, seed = CASES[name]
     U = _state(prob, seed)
