@@ -63,6 +63,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+# FP32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane operation per
+# lane and cycle without packed FP32; FP32 FMA counts as one operation here)
+VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 ALL_LEGS = "mixed,plain,learned,2d,learned2d,ensemble"
 
 
@@ -252,6 +255,21 @@ def counter_traffic(name, shapes=None):
         want = parse_shapes(m_shape.group(1))
         if shapes is None or any(shapes.get(k) != v for k, v in want.items()):
             return None
+    return float(m_val.group(1))
+
+
+def counter_value(name, key):
+    """A per-launch figure (line '<key>: <value>') of the committed counter summary
+    profiles/<name>.md, or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"^sources: (.+)$", text, re.M)
+    m_sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    m_val = re.search(r"^" + re.escape(key) + r": ([0-9.eE+]+)$", text, re.M)
+    if not (m_src and m_sha and m_val) or sources_sha256(m_src.group(1).split()) != m_sha.group(1):
+        return None
     return float(m_val.group(1))
 
 
@@ -650,6 +668,14 @@ def main():
         "roofline_jv": roof("mixed", "jv", kernels["jv"], traffic=counter_traffic(traffic_name["jv"])),
         "roofline_pc": roof("mixed", "pc", kernels["pc"], traffic=counter_traffic(traffic_name["pc"])),
     }
+    # the 3D Jv against the vector-ALU issue rate: VALU lane operations per launch from
+    # the committed SQ_INSTS_VALU counter summary (wave instructions x 64 lanes)
+    ops = counter_value("jv3d_f32_sq_counters_256x256x128", "valu_lane_ops_per_launch")
+    if ops is not None:
+        rj = out["roofline_jv"]
+        alu = ops / (rj["avg_launch_us"] * 1e-6) / 1e12
+        rj["valu"] = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TLANEOPS, "unit": "T lane-ops/s",
+                      "frac": alu / VALU_PEAK_TLANEOPS, "lane_ops_per_launch": ops}
     if "learned" in legs and legs["learned"]["tm"]["net"][1] > 0:
         out["roofline_net"] = roof("learned", "net", "k3_conv_march x4 (BF16 3x3x3 conv layers of the learned PC, z-marching)",
                                    "mfma")
