@@ -356,7 +356,9 @@ int jfnk_net_train_step(jfnk_ctx* ctx, const float* r, const float* du, int32_t 
  * single problem).  The inner solve is FP32 FGMRES with the physics-based (or no)
  * preconditioner; the Newton residual, update and norms are FP64.              */
 typedef struct jfnk_batch jfnk_batch;
-/* Allocates the batch workspace for ninst problems (host array).                 */
+/* Allocates the batch workspace for ninst problems (host array): 2D problems with
+ * nx, nz >= 8 and one order parameter dd_p (2 or 3, section 2.3) for all of
+ * them.  Errors: JFNK_ERR_ARG.                                                   */
 int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, void* hip_stream,
                       jfnk_batch** out);
 int jfnk_batch_destroy(jfnk_batch* batch);

@@ -31,7 +31,7 @@ struct BTab {
     const Geo* geos;
     const long long* voff;      // [ninst + 1] element offsets of the instances
     const long long* poff;      // [ninst + 1] grid-point offsets
-    const long long* noff;      // [ninst + 1] offsets of the ring-2 extended grids
+    const long long* noff;      // [ninst + 1] offsets of the ring-W extended grids
     const int* tile_off;        // [ninst + 1] stencil tiles (for the tile height in use)
     const int* tiles_x;         // [ninst] tiles per row
     const int* pblk_off;        // [ninst + 1] blocks of 256 grid points
@@ -55,7 +55,8 @@ __device__ __forceinline__ bool inactive(const BTab& t, int i) { return t.active
 // ---------------------------------------------------------------------------
 // stencil stages
 // ---------------------------------------------------------------------------
-template <typename T, int TZ>
+// W: stencil half-width of every instance (2 for p = 2, 4 for p = 3)
+template <typename T, int TZ, int W>
 __global__ __launch_bounds__(kB) void kb_apply_F(BTab t, const T* __restrict__ u, const T* __restrict__ f,
                                                  T* __restrict__ out, int what) {
     const int i = find_inst(t.tile_off, t.ninst, blockIdx.x);
@@ -64,47 +65,49 @@ __global__ __launch_bounds__(kB) void kb_apply_F(BTab t, const T* __restrict__ u
     const int local = blockIdx.x - t.tile_off[i];
     const int tx = local % t.tiles_x[i], tz = local / t.tiles_x[i];
     const long long o = t.voff[i];
-    s2d::apply_F_tile<T, 64, TZ>(g, tx * 64, tz * TZ, u + o, f ? f + o : nullptr, out + o, what);
+    s2d::apply_F_tile<T, 64, TZ, W>(g, tx * 64, tz * TZ, u + o, f ? f + o : nullptr, out + o, what);
 }
 
-template <typename T, int TZ>
+// FP64 tiles stop at 8 rows (4 for W = 4) for LDS, as in the single-grid kernels
+template <typename T, int TZ, int W>
 __global__ __launch_bounds__(kB) void kb_jv(BTab t, const T* __restrict__ u, const T* __restrict__ v,
                                             const double* __restrict__ eps, T* __restrict__ out) {
-    constexpr int TZC = (sizeof(T) == 8 && TZ > 8) ? 8 : TZ;
+    constexpr int TZC = sizeof(T) == 8 ? (W == 4 ? 4 : (TZ > 8 ? 8 : TZ)) : TZ;
     const int i = find_inst(t.tile_off, t.ninst, blockIdx.x);
     if (inactive(t, i)) return;
     const Geo g = t.geos[i];
     const int local = blockIdx.x - t.tile_off[i];
     const int tx = local % t.tiles_x[i], tz = local / t.tiles_x[i];
     const long long o = t.voff[i];
-    s2d::jv_tile<T, 64, TZC>(g, tx * 64, tz * TZC, u + o, v + o, 0.0, eps ? eps + (long long)i * S_STRIDE : nullptr,
-                             out + o);
+    s2d::jv_tile<T, 64, TZC, W>(g, tx * 64, tz * TZC, u + o, v + o, 0.0,
+                                eps ? eps + (long long)i * S_STRIDE : nullptr, out + o);
 }
 
-template <typename T, int TZ>
+template <typename T, int TZ, int W>
 __global__ __launch_bounds__(kB) void kb_pc_sweep(BTab t, const T* __restrict__ u, const T* __restrict__ nu,
                                                   const T* __restrict__ r, const T* __restrict__ zin,
                                                   T* __restrict__ zout) {
+    static_assert(sizeof(T) == 4 || W == 2 || TZ <= 8, "FP64 sweep tiles with W = 4 stop at 8 rows");
     const int i = find_inst(t.tile_off, t.ninst, blockIdx.x);
     if (inactive(t, i)) return;
     const Geo g = t.geos[i];
     const int local = blockIdx.x - t.tile_off[i];
     const int tx = local % t.tiles_x[i], tz = local / t.tiles_x[i];
     const long long o = t.voff[i];
-    (void)s2d::pc_sweep_tile<T, 64, TZ>(g, tx * 64, tz * TZ, u + o, nu + t.noff[i], r + o, zin + o, zout + o);
+    (void)s2d::pc_sweep_tile<T, 64, TZ, W>(g, tx * 64, tz * TZ, u + o, nu + t.noff[i], r + o, zin + o, zout + o);
 }
 
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(kB) void kb_frozen_nu(BTab t, const T* __restrict__ u, T* __restrict__ nu) {
     const int i = find_inst(t.eblk_off, t.ninst, blockIdx.x);
     if (inactive(t, i)) return;
     const Geo g = t.geos[i];
     const long long k = (long long)(blockIdx.x - t.eblk_off[i]) * kB + threadIdx.x;
-    s2d::frozen_nu_point<T>(g, k, u + t.voff[i], nu + t.noff[i]);
+    s2d::frozen_nu_point<T, W>(g, k, u + t.voff[i], nu + t.noff[i]);
 }
 
 // z = v / d after v = V_j / div[i] is written back into V_j
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(kB) void kb_pc_diag(BTab t, const T* __restrict__ nu, T* __restrict__ vj,
                                                  const double* __restrict__ div, T* __restrict__ z) {
     const int i = find_inst(t.pblk_off, t.ninst, blockIdx.x);
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(kB) void kb_pc_diag(BTab t, const T* __restrict__ n
     const long long k = (long long)(blockIdx.x - t.pblk_off[i]) * kB + threadIdx.x;
     if (k >= g.npts) return;
     const long long o = t.voff[i];
-    (void)s2d::pc_diag_point<T>(g, k, nu + t.noff[i], vj + o, div ? div + (long long)i * S_STRIDE : nullptr,
+    (void)s2d::pc_diag_point<T, W>(g, k, nu + t.noff[i], vj + o, div ? div + (long long)i * S_STRIDE : nullptr,
                                 z + o);
 }
 
@@ -779,6 +782,7 @@ using namespace jfnk;
 
 struct jfnk_batch {
     int ninst = 0, max_m = 0;
+    int W = 2;                  // stencil half-width of every instance (dd_p = 3: 4)
     hipStream_t stream = nullptr;
     std::vector<jfnk_problem> probs;
     std::vector<Geo> geos;
@@ -843,31 +847,67 @@ hipError_t b_apply_F(jfnk_batch* b, const T* u, const T* f, T* out, int what, in
     if (var < 0) var = b->tune[0 * 2 + (sizeof(T) == 4)];
     const BTab t = tab(b, var, false);
     const dim3 grid(ntiles(b, var));
-    if (var == 0) hipLaunchKernelGGL((kb_apply_F<T, 4>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
-    else if (var == 2) hipLaunchKernelGGL((kb_apply_F<T, 16>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
-    else hipLaunchKernelGGL((kb_apply_F<T, 8>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+    if (b->W == 4) {
+        if (var == 0) hipLaunchKernelGGL((kb_apply_F<T, 4, 4>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+        else if (var == 2) hipLaunchKernelGGL((kb_apply_F<T, 16, 4>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+        else hipLaunchKernelGGL((kb_apply_F<T, 8, 4>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+    } else {
+        if (var == 0) hipLaunchKernelGGL((kb_apply_F<T, 4, 2>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+        else if (var == 2) hipLaunchKernelGGL((kb_apply_F<T, 16, 2>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+        else hipLaunchKernelGGL((kb_apply_F<T, 8, 2>), grid, dim3(kB), 0, b->stream, t, u, f, out, what);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t b_jv(jfnk_batch* b, const T* u, const T* v, const double* eps, T* out, int var) {
-    if (sizeof(T) == 8 && var == 2) var = 1;
+    // the tile table of the height the kernel really uses
+    if (sizeof(T) == 8 && b->W == 4) var = 0;
+    else if (sizeof(T) == 8 && var == 2) var = 1;
     const BTab t = tab(b, var, true);
     const dim3 grid(ntiles(b, var));
-    if (var == 0) hipLaunchKernelGGL((kb_jv<T, 4>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
-    else if (var == 2) hipLaunchKernelGGL((kb_jv<T, 16>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
-    else hipLaunchKernelGGL((kb_jv<T, 8>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+    if (b->W == 4) {
+        if (var == 0) hipLaunchKernelGGL((kb_jv<T, 4, 4>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+        else if (var == 2) hipLaunchKernelGGL((kb_jv<T, 16, 4>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+        else hipLaunchKernelGGL((kb_jv<T, 8, 4>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+    } else {
+        if (var == 0) hipLaunchKernelGGL((kb_jv<T, 4, 2>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+        else if (var == 2) hipLaunchKernelGGL((kb_jv<T, 16, 2>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+        else hipLaunchKernelGGL((kb_jv<T, 8, 2>), grid, dim3(kB), 0, b->stream, t, u, v, eps, out);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t b_pc_sweep(jfnk_batch* b, const T* u, const T* nu, const T* r, const T* zin, T* zout, int var) {
+    static_assert(sizeof(T) == 4, "the ensemble's preconditioner sweeps run in FP32");
     const BTab t = tab(b, var, true);
     const dim3 grid(ntiles(b, var));
-    if (var == 0) hipLaunchKernelGGL((kb_pc_sweep<T, 4>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
-    else if (var == 2) hipLaunchKernelGGL((kb_pc_sweep<T, 16>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
-    else hipLaunchKernelGGL((kb_pc_sweep<T, 8>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+    if (b->W == 4) {
+        if (var == 0) hipLaunchKernelGGL((kb_pc_sweep<T, 4, 4>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+        else if (var == 2)
+            hipLaunchKernelGGL((kb_pc_sweep<T, 16, 4>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+        else hipLaunchKernelGGL((kb_pc_sweep<T, 8, 4>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+    } else {
+        if (var == 0) hipLaunchKernelGGL((kb_pc_sweep<T, 4, 2>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+        else if (var == 2)
+            hipLaunchKernelGGL((kb_pc_sweep<T, 16, 2>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+        else hipLaunchKernelGGL((kb_pc_sweep<T, 8, 2>), grid, dim3(kB), 0, b->stream, t, u, nu, r, zin, zout);
+    }
     return hipGetLastError();
+}
+
+// frozen viscosity on every instance's ring-W grid; z = v / d of the active instances
+void b_frozen_nu(jfnk_batch* b, const BTab& t, const float* u) {
+    const dim3 grid(b->eblk_off[b->ninst]);
+    if (b->W == 4) hipLaunchKernelGGL((kb_frozen_nu<float, 4>), grid, dim3(kB), 0, b->stream, t, u, b->nu32);
+    else hipLaunchKernelGGL((kb_frozen_nu<float, 2>), grid, dim3(kB), 0, b->stream, t, u, b->nu32);
+}
+void b_pc_diag(jfnk_batch* b, const BTab& t, float* vj, const double* div, float* z) {
+    const dim3 grid(b->pblk_off[b->ninst]);
+    const float* nu = b->nu32;
+    if (b->W == 4) hipLaunchKernelGGL((kb_pc_diag<float, 4>), grid, dim3(kB), 0, b->stream, t, nu, vj, div, z);
+    else hipLaunchKernelGGL((kb_pc_diag<float, 2>), grid, dim3(kB), 0, b->stream, t, nu, vj, div, z);
 }
 
 // per-instance squared norms of x into out[i * stride], with a finishing mode
@@ -964,7 +1004,7 @@ int b_gmres_begin(jfnk_batch* b, const float* u, const float* rhs, float* x, con
         JFNK_HIP(hipGetLastError());
         if (o.pc == JFNK_PC_PHYSICS) {
             const BTab ta = tab(b, 1, true);
-            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
+            b_frozen_nu(b, ta, u);
             JFNK_HIP(hipGetLastError());
         }
     }
@@ -1138,8 +1178,7 @@ int b_gmres_one_reduction(jfnk_batch* b, const float* u, const float* rhs, float
             if (o.pc == JFNK_PC_PHYSICS) {
                 float* bufs[2] = {Zj, b->t32};
                 int cur = (o.sweeps % 2 == 0) ? 0 : 1;
-                hipLaunchKernelGGL((kb_pc_diag<float>), dim3(b->pblk_off[ni]), dim3(kB), 0, s, ta,
-                                   (const float*)b->nu32, Vj, (const double*)nullptr, bufs[cur]);
+                b_pc_diag(b, ta, Vj, nullptr, bufs[cur]);
                 JFNK_HIP(hipGetLastError());
                 for (int sw = 0; sw < o.sweeps; ++sw) {
                     JFNK_HIP(b_pc_sweep<float>(b, u, b->nu32, Vj, bufs[cur], bufs[1 - cur], b->tune[2 * 2 + 1]));
@@ -1221,8 +1260,7 @@ int b_enqueue_cycle(jfnk_batch* b, const float* u, const float* rhs, float* x, c
         if (o.pc == JFNK_PC_PHYSICS) {
             float* bufs[2] = {Zj, b->t32};
             int cur = (o.sweeps % 2 == 0) ? 0 : 1;
-            hipLaunchKernelGGL((kb_pc_diag<float>), dim3(b->pblk_off[ni]), dim3(kB), 0, s, ta, (const float*)b->nu32,
-                               Vj, onered ? (const double*)nullptr : (const double*)(b->scal + which), bufs[cur]);
+            b_pc_diag(b, ta, Vj, onered ? (const double*)nullptr : (const double*)(b->scal + which), bufs[cur]);
             JFNK_HIP(hipGetLastError());
             for (int sw = 0; sw < o.sweeps; ++sw) {
                 JFNK_HIP(b_pc_sweep<float>(b, u, b->nu32, Vj, bufs[cur], bufs[1 - cur], b->tune[2 * 2 + 1]));
@@ -1295,7 +1333,7 @@ int b_gmres_graph(jfnk_batch* b, const float* u, const float* rhs, float* x, con
         const BTab t = tab(b, 1, false), ta = tab(b, 1, true);
         hipLaunchKernelGGL((kb_zero<float>), dim3(b->nchunks), dim3(kB), 0, s, t, x);
         if (o.pc == JFNK_PC_PHYSICS)
-            hipLaunchKernelGGL((kb_frozen_nu<float>), dim3(b->eblk_off[ni]), dim3(kB), 0, s, ta, u, b->nu32);
+            b_frozen_nu(b, ta, u);
         JFNK_HIP(hipGetLastError());
     }
     if ((rc = b_norm2<float>(b, u, b->scal + SB_UNORM2, S_STRIDE, FIN_STORE, true))) return rc;
@@ -1388,8 +1426,7 @@ int b_gmres(jfnk_batch* b, const float* u, const float* rhs, float* x, const std
             if (o.pc == JFNK_PC_PHYSICS) {
                 float* bufs[2] = {Zj, b->t32};
                 int cur = (o.sweeps % 2 == 0) ? 0 : 1;
-                hipLaunchKernelGGL((kb_pc_diag<float>), dim3(b->pblk_off[ni]), dim3(kB), 0, s, ta,
-                                   (const float*)b->nu32, Vj, (const double*)(b->scal + which), bufs[cur]);
+                b_pc_diag(b, ta, Vj, (const double*)(b->scal + which), bufs[cur]);
                 JFNK_HIP(hipGetLastError());
                 for (int sw = 0; sw < o.sweeps; ++sw) {
                     JFNK_HIP(b_pc_sweep<float>(b, u, b->nu32, Vj, bufs[cur], bufs[1 - cur], b->tune[2 * 2 + 1]));
@@ -1526,13 +1563,17 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
     b->eblk_off.push_back(0);
     b->chunk_off.push_back(0);
     long long nbg = 0;
+    b->W = probs[0].dd_p == 3 ? 4 : 2;
+    const int ew = 2 * b->W;    // ring-W extended grids: (nx + 2W) x (nz + 2W)
     for (int i = 0; i < ninst; ++i) {
         const jfnk_problem& p = probs[i];
         std::string why;
-        if (p.dim != 2 || p.ny != 1 || p.nx < 8 || p.nz < 8 || !(p.dt > 0) || p.dd_p != 2 || p.closure < 0 ||
+        if (p.dim != 2 || p.ny != 1 || p.nx < 8 || p.nz < 8 || !(p.dt > 0) || p.dd_p != probs[0].dd_p ||
+            (p.dd_p != 2 && p.dd_p != 3) || p.closure < 0 ||
             p.closure > 3 || (p.closure == JFNK_CLOSURE_SMAGORINSKY && !(p.pr_t > 0)) ||
             (p.closure == JFNK_CLOSURE_DEARDORFF && (!(p.cs >= 0) || !(p.n_bv >= 0)))) {
-            set_error("batch instance " + std::to_string(i) + ": unsupported or invalid problem");
+            set_error("batch instance " + std::to_string(i) + ": unsupported or invalid problem (2D, nx and nz "
+                      "at least 8, one dd_p of 2 or 3 for every instance)");
             return fail(JFNK_ERR_ARG);
         }
         b->probs.push_back(p);
@@ -1542,7 +1583,7 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
         const long long n = 4 * g.npts;
         b->voff.push_back(b->voff.back() + n);
         b->poff.push_back(b->poff.back() + g.npts);
-        b->noff.push_back(b->noff.back() + (long long)(g.nx + 4) * (g.nz + 4));
+        b->noff.push_back(b->noff.back() + (long long)(g.nx + ew) * (g.nz + ew));
         for (int v = 0; v < 3; ++v) {
             const int tz = tile_tz(v);
             const int tx = (g.nx + 63) / 64;
@@ -1550,7 +1591,7 @@ int jfnk_batch_create(const jfnk_problem* probs, int32_t ninst, int32_t max_m, v
             b->tile_off[v].push_back(b->tile_off[v].back() + tx * ((g.nz + tz - 1) / tz));
         }
         b->pblk_off.push_back(b->pblk_off.back() + (int)((g.npts + kB - 1) / kB));
-        b->eblk_off.push_back(b->eblk_off.back() + (int)(((long long)(g.nx + 4) * (g.nz + 4) + kB - 1) / kB));
+        b->eblk_off.push_back(b->eblk_off.back() + (int)(((long long)(g.nx + ew) * (g.nz + ew) + kB - 1) / kB));
         b->chunk_off.push_back(b->chunk_off.back() + (int)((n + kChunk - 1) / kChunk));
         nbg += 2 * g.nz + g.nx;
     }

@@ -1,8 +1,9 @@
 """Batched ensemble (one launch per stage over all instances) against the FP64
 oracle per instance: residuals to 1e-11, a mixed-precision implicit step of
 uneven instances (one with the anisotropic coefficients of Eq. 7) against the
-oracle's step, the 64-instance heat-island ensemble, and the autotuner's choice
-not changing results."""
+oracle's step, the same with the 9-point derivative (p = 3, section 2.3), the
+64-instance heat-island ensemble, and the autotuner's choice not changing
+results."""
 import time
 
 import numpy as np
@@ -136,3 +137,76 @@ def test_heat_island_ensemble_64_instances():
         d = np.linalg.norm((got[i] - ref).ravel()) / np.linalg.norm((ref - U0[i]).ravel())
         assert d < 1e-6, (i, d)
     print(f"worst relative residual over the 64 instances {worst:.2e}; instances {small} match the oracle's step")
+
+
+def _p3(probs):
+    return [p.replace(dd_p=3) for p in probs]
+
+
+def test_batched_residual_p3_matches_oracle():
+    """p = 3 (stencil half-width 4) in every instance: residual and F per instance
+    against the oracle's 9-point operator; ragged tiles in x and z."""
+    from paper_2007_10411_amd.jfnk import Batch
+    probs = _p3(_small_ensemble())
+    b = Batch(probs, max_m=8)
+    states = [I.smooth_flow_state(p, seed=140 + i) for i, p in enumerate(probs)]
+    prev = [I.smooth_flow_state(p, seed=160 + i) for i, p in enumerate(probs)]
+    u = b.pack(states)
+    un = b.pack(prev)
+    f = un.clone()
+    b.apply_F(un, f, what=1)
+    R = f.clone()
+    b.apply_F(u, R, what=2, f=f)
+    got = b.unpack(R)
+    for i, p in enumerate(probs):
+        ref = M.residual(p, states[i], M.rhs(p, prev[i]))
+        assert_fields_close(got[i], ref, 1e-11, f"batch p3 residual {i}")
+    F = u.clone()
+    b.apply_F(u, F, what=0)
+    for i, (p, g) in enumerate(zip(probs, b.unpack(F))):
+        assert_fields_close(g, M.F(p, states[i]), 1e-11, f"batch p3 F {i}")
+
+
+@pytest.mark.parametrize("ortho,m,sweeps", [("one_reduction", 30, 0), ("one_reduction", 6, 2), ("cgs2", 30, 1)])
+def test_batched_step_p3_matches_oracle_steps(ortho, m, sweeps):
+    """A mixed step of uneven p = 3 instances (heat islands, the Eq. 7 closure, a
+    periodic constant-K case) against the oracle's FP64 step with the same
+    preconditioner sweeps; m = 6 forces restarts."""
+    from paper_2007_10411_amd.jfnk import Batch
+    probs = _p3(_small_ensemble()[:4] + _small_ensemble()[5:])
+    b = Batch(probs, max_m=30)
+    U0 = [I.bubble_state(p) if p.h0 == 0 else I.rest_state(p) for p in probs]
+    un = b.pack(U0)
+    u = un.clone()
+    res = b.newton_step(un, u, rtol=1e-10, ortho=ortho, m=m, max_restarts=100, sweeps=sweeps)
+    assert all(r.converged for r in res), res
+    got = b.unpack(u)
+    for i, p in enumerate(probs):
+        ref, info = K.newton_step(p, U0[i], K.NewtonOpts(rtol=1e-12, sweeps=sweeps))
+        d = np.linalg.norm((got[i] - ref).ravel()) / np.linalg.norm((ref - U0[i]).ravel())
+        assert d < 1e-7, (i, d)
+
+
+def test_graph_cycles_equal_host_decided_cycles_p3():
+    """The captured-cycle step equals the host-decided step bit for bit with p = 3."""
+    import torch
+    from paper_2007_10411_amd.jfnk import Batch
+    probs = _p3(_small_ensemble())
+    b = Batch(probs, max_m=30)
+    U0 = [I.bubble_state(p) if p.h0 == 0 else I.rest_state(p) for p in probs]
+    ua = b.pack(U0)
+    opts = dict(rtol=1e-8, ortho="one_reduction", m=8, max_restarts=100, sweeps=0)
+    na, ng = ua.clone(), ua.clone()
+    ra = b.newton_step(ua, na, use_graph=False, **opts)
+    rg = b.newton_step(ua, ng, use_graph=True, **opts)
+    assert all(r.converged for r in rg), rg
+    assert [(r.newton_iters, r.gmres_iters_total) for r in ra] == [(r.newton_iters, r.gmres_iters_total) for r in rg]
+    assert torch.equal(na, ng)
+
+
+def test_batch_rejects_mixed_orders():
+    """Every instance of a batch takes the same derivative order."""
+    from paper_2007_10411_amd.jfnk import Batch
+    probs = _small_ensemble()[:2]
+    with pytest.raises(Exception, match="dd_p"):
+        Batch([probs[0], probs[1].replace(dd_p=3)], max_m=8)
