@@ -715,6 +715,29 @@ __global__ __launch_bounds__(kBlock) void k_dg_update(T* V, int n, int j, const 
     }
 }
 
+// x += sum_v y_v Z_v for k <= NV basis rows, every row's load of an element
+// issued before the sums (the loop form above keeps one load in flight); rows
+// past k - 1 re-read row k - 1 with a zero coefficient.  The sums run in the
+// loop form's order.  NT: streaming loads of Z as in the Arnoldi update pass.
+template <typename T, int NV, bool NT>
+__global__ __launch_bounds__(kBlock) void k_axpy_basis_reg(T* __restrict__ x, const T* __restrict__ Z, int n, int k,
+                                                           const double* __restrict__ y) {
+    double c[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) c[v] = v < k ? y[v] : 0.0;
+    const int step = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
+        T z[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) z[v] = ld_stream<NT>(Z + (long long)(v < k ? v : k - 1) * n + i);
+        __builtin_amdgcn_sched_barrier(0);
+        double acc = (double)x[i];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc += c[v] * (double)z[v];
+        x[i] = (T)acc;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_eps_finish(int nblk, EpsArgs ea) {
     __shared__ double red[4];
     const double t = sum_partials(ea.partials, nblk, 1, 0, red);
@@ -790,10 +813,26 @@ hipError_t launch_scale(T* x, long long n, const double* d, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int NV, bool NT>
+hipError_t launch_axpy_basis_nv(T* x, const T* Z, int n, int k, const double* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpy_basis_reg<T, NV, NT>), dim3(cgs_blocks(n)), dim3(kBlock), 0, s, x, Z, n, k, y);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_axpy_basis(T* x, const T* Z, long long n, int k, const double* y, hipStream_t s) {
-    hipLaunchKernelGGL((k_axpy_basis<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, Z, n, k, y);
-    return hipGetLastError();
+    if (k < 1 || k > 32 || n >= (1LL << 30)) {
+        hipLaunchKernelGGL((k_axpy_basis<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, Z, n, k, y);
+        return hipGetLastError();
+    }
+    const int ni = (int)n;
+    if (n * (long long)sizeof(T) >= (32LL << 20))
+        return k <= 8 ? launch_axpy_basis_nv<T, 8, true>(x, Z, ni, k, y, s)
+             : k <= 16 ? launch_axpy_basis_nv<T, 16, true>(x, Z, ni, k, y, s)
+                       : launch_axpy_basis_nv<T, 32, true>(x, Z, ni, k, y, s);
+    return k <= 8 ? launch_axpy_basis_nv<T, 8, false>(x, Z, ni, k, y, s)
+         : k <= 16 ? launch_axpy_basis_nv<T, 16, false>(x, Z, ni, k, y, s)
+                   : launch_axpy_basis_nv<T, 32, false>(x, Z, ni, k, y, s);
 }
 
 template <typename Td, typename Ts>
