@@ -86,7 +86,8 @@ def parse():
                     help="Jacobi sweeps of the physics preconditioner in the timed legs (0: its field-block "
                          "diagonal alone)")
     ap.add_argument("--train-iters", type=int, default=600)
-    ap.add_argument("--train-iters-2d", type=int, default=1500)
+    ap.add_argument("--train-iters-2d", type=int, default=3000)
+    ap.add_argument("--train-lr-2d", type=float, default=4e-3)
     ap.add_argument("--copy-probe", type=float, default=0.0)
     ap.add_argument("--micro-only", action="store_true")
     ap.add_argument("--pin", default="", help="launch shapes pinned over the autotuner on the 2D "
@@ -410,7 +411,7 @@ def kernel_micro(torch, I, L, Context, reps, pins=None, names=None):
     return out
 
 
-def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
+def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho, lr=4e-3):
     """Trained network vs the physics preconditioner (with the timed legs' sweep
     count and with two sweeps; and the plain FP64 solve with it) vs the untrained
     form on the stable thermal at 256 x 128 (two steps each from the same state)."""
@@ -420,10 +421,11 @@ def learned_small(torch, I, LRN, Context, train_iters, sweeps, ortho):
     u = torch.from_numpy(I.bubble_state(prob)).cuda()
     R, DU, u_end = LRN.collect_pairs(ctx, u, steps=4, cap=256)
     t0 = time.perf_counter()
-    theta, losses = LRN.train_mixed(ctx, R, DU, u_end, iters=train_iters, lr=2e-3, batch=8)
+    theta, losses = LRN.train_mixed(ctx, R, DU, u_end, iters=train_iters, lr=lr, batch=8)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0])}
+    out = {"grid": [256, 128], "train_s": train_s, "pairs": int(R.shape[0]), "adam_steps": train_iters, "lr": lr,
+           "loss_last": float(np.mean(losses[-50:]))}
     zero = np.zeros(ctx.n_params, np.float32)
     # learned: judged by the physics-based preconditioner (the library's behaviour);
     # *_unjudged: the network's own iteration counts
@@ -565,7 +567,8 @@ def main():
     small = None
     if "learned2d" in legs_wanted:
         log("learned vs physics preconditioner, 2D stable thermal 256 x 128")
-        small = learned_small(torch, I, LRN, Context, args.train_iters_2d, args.pc_sweeps, args.ortho)
+        small = learned_small(torch, I, LRN, Context, args.train_iters_2d, args.pc_sweeps, args.ortho,
+                              args.train_lr_2d)
     ensemble = None
     if "ensemble" in legs_wanted:
         from paper_2007_10411_amd.jfnk import Batch
