@@ -248,3 +248,38 @@ def test_p3_newton_step_3d():
     assert r2.converged
     d = np.linalg.norm((host(u2) - ref).ravel()) / np.linalg.norm((ref - U0).ravel())
     assert d < 1e-6
+
+
+def test_one_reduction_f32_256x256x128_matches_cgs2():
+    """The 3D thermal at 256 x 256 x 128 (rows of 168 MB, where the one-reduction
+    update pass and the cycle-end update x += Z y stream their loads and stores
+    past the caches): 40 FP32 iterations (one restart) of the one-reduction step
+    against CGS2 (cached accesses throughout) on the same inputs, and each
+    solve's true residual ||b - J x|| against its estimate."""
+    import torch
+    prob = I.thermal_neutral_3d()
+    U = I.bubble_state(prob)
+    c = _ctx(prob, max_m=30)
+    u64 = dev(U)
+    f = u64.clone()
+    c.rhs(u64, f)
+    R = u64.clone()
+    c.residual(u64, f, R)
+    u32, b32 = u64.float(), (-R).float()
+    del f, R
+    out = {}
+    for ortho in ("cgs2", "one_reduction"):
+        x = torch.zeros_like(b32)
+        r = c.gmres(u32, b32, x, m=30, max_restarts=5, tol=0.0, pc="physics", sweeps=0, max_iters=40,
+                    ortho=ortho)
+        assert r.iters == 40 and r.restarts == 1
+        # x is assembled from the cycle-end updates: its true residual must match the
+        # Givens estimate to the FP32 Krylov rounding
+        assert r.res_true > 0 and abs(r.res_true - r.res_est) <= 2e-3 * r.res0, (ortho, r)
+        out[ortho] = (x.cpu().double().numpy(), r.res_est)
+        del x
+    xa, ra = out["cgs2"]
+    xb, rb = out["one_reduction"]
+    assert np.all(np.isfinite(xb))
+    assert np.linalg.norm(xb - xa) <= 1e-5 * np.linalg.norm(xa)
+    assert abs(rb - ra) <= 1e-3 * ra
