@@ -481,8 +481,8 @@ def train_learned_3d(torch, I, LRN, Context, ctx, u, iters, sweeps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path (one GPU per "
+              "process; --gpus must be 1).", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
