@@ -1284,24 +1284,29 @@ template <typename T>
 __global__ __launch_bounds__(256) void k3_pc_diag(Geo g, const T* __restrict__ nu, T* __restrict__ vj,
                                                   const double* __restrict__ div, T* __restrict__ z, EpsArgs ea) {
     __shared__ double red[4];
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    // a grid-stride loop over points (32-bit indices: the launcher checks
+    // npts < 2^31), so that the per-launch constants are formed once per thread
+    // and the FD step's finishing block adds at most one partial sum per block
+    const int np = (int)g.npts, nx = g.nx, nxy = g.nx * g.ny;
+    const int ex = g.nx + 4, exy = (g.nx + 4) * (g.ny + 4);
+    const double dv = div ? *div : 1.0;
     double acc = 0.0;
-    if (i < g.npts) {
-        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zz = (int)(i / ((long long)g.nx * g.ny));
-        const Coef<T> kc = pc_k3(g, nuext(g, nu, x, y, zz));
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < np; i += gridDim.x * 256) {
+        const int zz = i / nxy, rem = i - zz * nxy, y = rem / nx, x = rem - y * nx;
+        const Coef<T> kc = pc_k3(g, nu[(zz + 2) * exy + (y + 2) * ex + (x + 2)]);
         const T dm = pc_diag3(g, kc.mh, kc.mv), dt_ = pc_diag3(g, kc.hh, kc.hv);
         const T dd[5] = {dm, dm, dm, T(g.two_dt), dt_};
-        const double dv = div ? *div : 1.0;
-        const long long np = g.npts;
+        T vv[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) vv[k] = vj[(long long)k * np + i];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            T vv = vj[k * np + i];
             if (div) {
-                vv = (T)((double)vv / dv);
-                vj[k * np + i] = vv;
+                vv[k] = (T)((double)vv[k] / dv);
+                vj[(long long)k * np + i] = vv[k];
             }
-            const T zv = vv / dd[k];
-            z[k * np + i] = zv;
+            const T zv = vv[k] / dd[k];
+            z[(long long)k * np + i] = zv;
             acc += (double)zv * (double)zv;
         }
     }
@@ -1713,14 +1718,21 @@ hipError_t launch3_frozen_nu(const Geo& g, const T* u, T* nu, hipStream_t s) {
     return hipGetLastError();
 }
 
+// blocks of the 3D preconditioner diagonal (grid-stride): eight per CU
+constexpr int kPcDiagBlocks = 2048;
+
 template <typename T>
 hipError_t launch3_pc_diag(const Geo& g, const T* nu, T* vj, const double* div, T* z, const EpsArgs& ea,
                            hipStream_t s) {
-    const int nb = blocks(g.npts);
-    if (g.W == 4)
+    int nb = blocks(g.npts);
+    if (g.W == 4) {
         hipLaunchKernelGGL((k3g_pc_diag<4, T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
-    else
+    } else {
+        if (g.npts >= (1LL << 31) || (long long)(g.nx + 4) * (g.ny + 4) * (g.nz + 4) >= (1LL << 31))
+            return hipErrorInvalidValue;
+        nb = nb < kPcDiagBlocks ? nb : kPcDiagBlocks;
         hipLaunchKernelGGL((k3_pc_diag<T>), dim3(nb), dim3(256), 0, s, g, nu, vj, div, z, ea);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ea.partials) return e;
     return launch_eps_finish(nb, ea, s);
