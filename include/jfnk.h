@@ -197,7 +197,8 @@ int jfnk_apply_F(jfnk_ctx* ctx, jfnk_dtype dt, int32_t what, const void* u, cons
 
 /* Jv = J(u) v, the Frechet derivative of R at u in direction v (equation 9).
  * eps <= 0 selects eps = sqrt(eps_mach) max(||u||, sqrt(N)) / ||v|| with eps_mach
- * of the dtype (2^-52 or 2^-23); ignored by ANALYTIC.  u, v, Jv share the dtype.  */
+ * of the dtype (2^-52 or 2^-23); ignored by ANALYTIC.  u, v, Jv share the dtype.
+ * v = 0 gives Jv = 0 in every mode.                                              */
 int jfnk_jv(jfnk_ctx* ctx, jfnk_dtype dt, jfnk_jv_mode mode, const void* u, const void* v,
             double eps, void* Jv);
 

@@ -271,6 +271,10 @@ int apply_jv(jfnk_ctx* c, int mode, const T* u, const T* v, const double* eps_de
             JFNK_HIP(hipStreamSynchronize(c->stream));
             e = c->hscal[S_TMP];
         }
+        if (!(e > 0.0)) {   // v = 0 (the automatic step is 0): J 0 = 0
+            JFNK_HIP(launch_cast<T, T>(out, v, c->n, 0.0, c->stream));
+            return JFNK_OK;
+        }
         T* w1 = TA<T>(c);
         T* w2 = TB<T>(c);
         JFNK_HIP(launch_lincomb<T>(w1, u, v, c->n, 1.0, e, c->stream));

@@ -1,0 +1,91 @@
+"""Degenerate inputs at the boundary: a zero direction (Jv = 0 in every mode, 2D
+and 3D, both precisions), a zero right-hand side (GMRES returns x = 0 after no
+iteration, both Arnoldi forms and precisions), an implicit step that starts at
+its solution (the rest state without forcing, section 2.1: no Newton iteration
+and the state unchanged bit for bit), and a batch in which one instance starts
+at its solution beside instances that do not."""
+import numpy as np
+import pytest
+
+from paper_2007_10411_amd import inputs as I
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(prob, max_m=30):
+    from paper_2007_10411_amd.jfnk import Context
+    return Context(prob, max_m=max_m)
+
+
+PROBS = {2: lambda: I.thermal_stable_2d(72, 40), 3: lambda: I.thermal_neutral_3d(36, 20, 18)}
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("mode", ["stable", "literal", "analytic"])
+def test_jv_of_zero_direction_is_zero(dim, dt, mode):
+    """The automatic step is 0 for v = 0; the stable and analytic forms carry no
+    division by it and the literal form returns 0 instead of 0 / 0."""
+    prob = PROBS[dim]()
+    c = _ctx(prob, max_m=2)
+    U = I.smooth_flow_state(prob, seed=5)
+    u = dev(U, dt)
+    v = dev(np.zeros(prob.shape), dt)
+    out = dev(np.ones(prob.shape), dt)
+    c.jv(u, v, out, mode=mode)
+    got = host(out)
+    assert np.all(np.isfinite(got)) and np.abs(got).max() == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("ortho", ["cgs2", "one_reduction"])
+def test_gmres_zero_rhs_returns_zero(dim, dt, ortho):
+    prob = PROBS[dim]()
+    c = _ctx(prob)
+    u = dev(I.smooth_flow_state(prob, seed=6), dt)
+    b = dev(np.zeros(prob.shape), dt)
+    x = dev(np.ones(prob.shape), dt)
+    r = c.gmres(u, b, x, m=30, max_restarts=2, tol=1e-8, pc="physics", sweeps=0, ortho=ortho)
+    assert r.converged and r.iters == 0 and r.res0 == 0.0
+    assert np.abs(host(x)).max() == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_step_from_the_solution_takes_no_newton_iteration(dim, inner):
+    """The rest state without surface flux is a steady solution: R(u^n) = 0 for
+    u^{n+1} = u^n, so the step stops before its first Krylov solve."""
+    import torch
+    prob = PROBS[dim]()
+    c = _ctx(prob)
+    un = dev(I.rest_state(prob))
+    u = un.clone()
+    extra = dict(eta_floor=1e-4) if inner == "f32" else {}
+    r = c.newton_step(un, u, rtol=1e-8, inner=inner, ortho="one_reduction", sweeps=0, **extra)
+    assert r.converged and r.newton_iters == 0 and r.gmres_iters_total == 0
+    assert torch.equal(u, un)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_with_an_instance_at_its_solution(use_graph):
+    """A neutral thermal at rest (no forcing) beside two heat islands at rest
+    (surface flux): the first instance is done before any iteration and keeps its
+    state bit for bit; the others converge."""
+    import torch
+    from paper_2007_10411_amd.jfnk import Batch
+    probs = [I.thermal_neutral_2d(48, 24), I.heat_island_2d(64, 16, h0=300.0, width=6000.0),
+             I.heat_island_2d(96, 24, h0=150.0, width=4000.0)]
+    b = Batch(probs, max_m=30)
+    U0 = [I.rest_state(p) for p in probs]
+    un = b.pack(U0)
+    u = un.clone()
+    res = b.newton_step(un, u, rtol=1e-8, ortho="one_reduction", sweeps=0, use_graph=use_graph)
+    assert all(r.converged for r in res), res
+    assert res[0].newton_iters == 0 and res[0].gmres_iters_total == 0
+    assert all(r.newton_iters >= 1 for r in res[1:])
+    got = b.unpack(u)
+    assert np.array_equal(got[0], U0[0])
+    assert all(np.abs(g).max() > 0.0 for g in got[1:])
