@@ -89,3 +89,33 @@ def test_batch_with_an_instance_at_its_solution(use_graph):
     got = b.unpack(u)
     assert np.array_equal(got[0], U0[0])
     assert all(np.abs(g).max() > 0.0 for g in got[1:])
+
+
+@pytest.mark.parametrize("change,why", [
+    (dict(dim=1), "dim must be 2 or 3"),
+    (dict(nx=7), "grid below 8 points"),
+    (dict(nz=5), "grid below 8 points"),
+    (dict(ny=2), "ny != 1 in 2D"),
+    (dict(dt=0.0), "non-positive dt"),
+    (dict(dt=float("nan")), "non-positive dt"),
+    (dict(lx=-1.0), "non-positive dt or domain size"),
+    (dict(dd_p=4), "dd_p must be 2 or 3"),
+    (dict(bc_lateral=7), "bc_lateral"),
+    (dict(bc_vertical=3), "bc_vertical"),
+    (dict(closure=4), "invalid closure"),
+    (dict(closure=I.CLOSURE_DEARDORFF, cs=-0.1), "cs >= 0"),
+    (dict(pr_t=0.0), "pr_t must be positive"),
+])
+def test_create_rejects_invalid_problems(change, why):
+    """jfnk_create refuses an invalid problem with JFNK_ERR_ARG and says why,
+    before it allocates anything."""
+    from paper_2007_10411_amd._lib import JfnkError
+    prob = I.thermal_stable_2d(64, 32).replace(**change)
+    with pytest.raises(JfnkError, match=why):
+        _ctx(prob)
+
+
+def test_create_rejects_a_3d_grid_below_8_points():
+    from paper_2007_10411_amd._lib import JfnkError
+    with pytest.raises(JfnkError, match="grid below 8 points"):
+        _ctx(I.thermal_neutral_3d(16, 4, 16))
