@@ -628,15 +628,6 @@ __global__ __launch_bounds__(kB) void kb_axpy_basis(BTab t, T* __restrict__ x, c
     }
 }
 
-// x_i /= scal_i[which] (normalise the start vector of a cycle)
-template <typename T>
-__global__ __launch_bounds__(kB) void kb_scale(BTab t, T* __restrict__ x, const double* __restrict__ scal, int which) {
-    const Chunk c = chunk_of(t);
-    if (inactive(t, c.inst)) return;
-    const double d = scal[(long long)c.inst * S_STRIDE + which];
-    for (long long e = c.b + threadIdx.x; e < c.e; e += kB) x[e] = (T)((double)x[e] / d);
-}
-
 // z = v (no preconditioner), v normalised by div_i first
 template <typename T>
 __global__ __launch_bounds__(kB) void kb_normalize_copy(BTab t, T* __restrict__ v, const double* __restrict__ scal,
