@@ -18,6 +18,10 @@ The physics-based preconditioner applies its field-block diagonal with
 GMRES iteration count unchanged).  The Krylov solves use the one-reduction
 Arnoldi step (--ortho).
 
+config.mixed_vs_fp64: the mixed steps' error per field against the plain FP64
+steps after the plain leg's step count (relative to the FP64 steps' change and to
+the field), the FP64 path being the one that matches the oracle to 1e-11.
+
 Further legs (config.legs_2d, config.learned_256x128, config.ensemble_64_heat_island):
 the 2D stable thermal at 1024 x 512 (mixed and plain), the trained 2D network
 against the physics preconditioner at 256 x 128, and one mixed step of the
@@ -159,6 +163,25 @@ def per_step(leg, npts=None):
     if npts is not None and "jv" in leg["tm"] and leg["tm"]["jv"][0] > 0:
         ms, launches, _ = leg["tm"]["jv"]
         out["jv_kernel_gpts"] = npts * launches / (ms / 1e3) / 1e9
+    return out
+
+
+def field_differences(torch, ctx, u0, u_ref, k, opts, names):
+    """The mixed-precision steps' error per field against the plain FP64 steps
+    (whose FP64 kernels match the oracle to 1e-11): k mixed steps from u0 (not
+    timed), then ||u_mixed - u_fp64|| relative to the FP64 steps' change
+    ||u_fp64 - u0|| and to ||u_fp64||, per field."""
+    u = u0.clone()
+    run_steps(ctx, u, k, torch, **opts)
+    nf = len(names)
+    d = (u - u_ref).reshape(nf, -1).norm(dim=1)
+    ch = (u_ref - u0).reshape(nf, -1).norm(dim=1)
+    nr = u_ref.reshape(nf, -1).norm(dim=1)
+    out = {"steps": k}
+    for i, name in enumerate(names):
+        out[name] = {"rel_to_change": float(d[i] / ch[i]) if ch[i] > 0 else None,
+                     "rel_to_field": float(d[i] / nr[i]) if nr[i] > 0 else None}
+    del u
     return out
 
 
@@ -530,9 +553,12 @@ def main():
     legs = {}
     log(f"timing {steps['mixed']} mixed steps")
     legs["mixed"] = timed_leg(ctx, u, steps["mixed"], torch, L, classes["mixed"], **opts["mixed"])
+    mixed_vs_fp64 = None
     if "plain" in legs_wanted:
         log(f"timing {steps['plain']} plain FP64 steps")
         legs["plain"] = timed_leg(ctx, u, steps["plain"], torch, L, classes["plain"], **opts["plain"])
+        mixed_vs_fp64 = field_differences(torch, ctx, u, legs["plain"]["u"], steps["plain"], opts["mixed"],
+                                          ("u", "v", "w", "p", "theta"))
     train_info = None
     learned_error = None
     if "learned" in legs_wanted:
@@ -659,6 +685,7 @@ def main():
             "plain_ms_over_mixed_ms": (leg_summary["plain"]["ms_per_step"] / mixed_ms if "plain" in legs else None),
             "plain_ms_over_learned_ms": (leg_summary["plain"]["ms_per_step"] / leg_summary["learned"]["ms_per_step"]
                                          if "plain" in legs and "learned" in legs else None),
+            "mixed_vs_fp64": mixed_vs_fp64,
             "training_3d": train_info,
             "learned_error": learned_error,
             "legs_2d": legs_2d,
