@@ -76,6 +76,28 @@ def test_physics_pc_3d(name, sweeps):
     assert_fields_close(host(z), PC.physics_pc(prob, U, R, sweeps=sweeps), F64_TOL, f"{name} pc{sweeps}")
 
 
+@pytest.mark.parametrize("closure", [I.CLOSURE_SMAGORINSKY, I.CLOSURE_DEARDORFF])
+def test_physics_pc_diagonal_3d_grid_stride(closure):
+    """The preconditioner's diagonal start on 96 x 96 x 64 points (more than the
+    2048 blocks x 256 threads of its grid-stride launch, so threads handle two
+    points), FP64 and FP32, against the oracle."""
+    prob = I.thermal_neutral_3d(96, 96, 64).replace(closure=closure, n_bv=0.01)
+    assert prob.npts > 2048 * 256
+    U = I.smooth_flow_state(prob, seed=17)
+    R = I.random_vector(prob, seed=18)
+    ref = PC.physics_pc(prob, U, R, sweeps=0)
+    c = _ctx(prob, max_m=2)
+    z = dev(np.zeros(prob.shape))
+    c.precond_apply(dev(U), dev(R), z, pc="physics", sweeps=0)
+    assert_fields_close(host(z), ref, F64_TOL, f"pc diag grid-stride closure {closure}")
+    U32 = U.astype(np.float32).astype(np.float64)
+    R32 = R.astype(np.float32).astype(np.float64)
+    z32 = dev(np.zeros(prob.shape), "f32")
+    c.precond_apply(dev(U32, "f32"), dev(R32, "f32"), z32, pc="physics", sweeps=0)
+    assert_fields_close(host(z32), PC.physics_pc(prob, U32, R32, sweeps=0), F32_TOL,
+                        f"pc diag grid-stride f32 closure {closure}")
+
+
 @pytest.mark.parametrize("name", ["neutral-70x20x37", "noslip-stable-45x17x21", "periodic-constK-40x9x18"])
 @pytest.mark.parametrize("sweeps", [1, 2])
 def test_physics_pc_3d_multiblock(name, sweeps):
