@@ -305,3 +305,32 @@ def test_one_reduction_f32_256x256x128_matches_cgs2():
     assert np.all(np.isfinite(xb))
     assert np.linalg.norm(xb - xa) <= 1e-5 * np.linalg.norm(xa)
     assert abs(rb - ra) <= 1e-3 * ra
+
+
+def test_one_reduction_f64_streaming_rows_match_cgs2():
+    """FP64 rows of 42 MB (128 x 128 x 64): the one-reduction update pass and the
+    cycle-end update take their streaming path in FP64 too; 40 iterations (one
+    restart) against CGS2 to the FP64 bar, and the true residual against the
+    estimate."""
+    import torch
+    prob = I.thermal_neutral_3d(128, 128, 64)
+    assert prob.n * 8 >= 32 << 20
+    U = I.bubble_state(prob)
+    c = _ctx(prob, max_m=30)
+    u64 = dev(U)
+    f = u64.clone()
+    c.rhs(u64, f)
+    R = u64.clone()
+    c.residual(u64, f, R)
+    b = -R
+    out = {}
+    for ortho in ("cgs2", "one_reduction"):
+        x = torch.zeros_like(b)
+        r = c.gmres(u64, b, x, m=30, max_restarts=5, tol=0.0, pc="physics", sweeps=0, max_iters=40, ortho=ortho)
+        assert r.iters == 40 and r.restarts == 1
+        assert abs(r.res_true - r.res_est) <= 1e-8 * r.res0, (ortho, r)
+        out[ortho] = (host(x), r.res_est)
+    xa, ra = out["cgs2"]
+    xb, rb = out["one_reduction"]
+    assert np.linalg.norm(xb - xa) <= 1e-10 * np.linalg.norm(xa)
+    assert abs(rb - ra) <= 1e-8 * ra
