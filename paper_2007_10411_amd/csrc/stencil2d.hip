@@ -116,9 +116,10 @@ struct RowStage {
             neg[p] = m;
         }
     }
-    // into ring [f][NA][SX]; slot0 is the ring slot of row rbase
+    // into ring [f][NA][SX]; slot0 is the ring slot of row rbase.  With two
+    // states (NF = 8) the first four fields go in as u + e v.
     template <int NA>
-    __device__ __forceinline__ void store(T* dst, int slot0) const {
+    __device__ __forceinline__ void store(T* dst, int slot0, T e) const {
 #pragma unroll
         for (int p = 0; p < POS; ++p) {
             const int idx = (int)threadIdx.x + p * 256;
@@ -126,7 +127,10 @@ struct RowStage {
                 const int lx = idx - lrow[p] * SX;
                 T* d = dst + ((slot0 + lrow[p]) % NA) * SX + lx;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) d[f * NA * SX] = (neg[p] >> f) & 1u ? -r[p][f] : r[p][f];
+                for (int f = 0; f < NF; ++f) {
+                    const T v = (NF == 8 && f < 4) ? r[p][f] + e * r[p][f + 4] : r[p][f];
+                    d[f * NA * SX] = (neg[p] >> f) & 1u ? -v : v;
+                }
             }
         }
     }
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
     // prologue: primitive rows z0 - 2W .. z0 + 2W - 1, derived rows z0 - W .. z0 + W - 1
     for (int rb = z0 - H; rb < z0 + H; rb += RB) {
         st.load(g, u, v, rb);
-        st.template store<NA>(sa, slotA(rb));
+        st.template store<NA>(sa, slotA(rb), e);
     }
     __syncthreads();
     derive(z0 - W, 2 * W);
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(256) void k_march_2d(Geo g, int zc, const T* __rest
     const bool owner = ty < RB && tx < MX;
     for (int k = 0; k < nsteps; ++k) {
         const int rb = z0 + k * RB;
-        st.template store<NA>(sa, slotA(rb + H));
+        st.template store<NA>(sa, slotA(rb + H), e);
         __syncthreads();
         if (k + 1 < nsteps) st.load(g, u, v, rb + RB + H);
         derive(rb + W, RB);

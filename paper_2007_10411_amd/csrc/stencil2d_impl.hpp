@@ -185,6 +185,22 @@ struct TileStage {
             }
         }
     }
+    // this state plus e times state o, staged at the same positions (the same
+    // fields, so the same reflection signs)
+    __device__ __forceinline__ void store_sum(T* s, const TileStage& o, T e) const {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + it * kTileThreads;
+            if (idx < N) {
+#pragma unroll
+                for (int f = 0; f < NFL; ++f) {
+                    const int b = it * NFL + f;
+                    const T v = r[it][f] + e * o.r[it][f];
+                    s[f * N + idx] = (neg[b / 32] >> (b % 32)) & 1u ? -v : v;
+                }
+            }
+        }
+    }
 };
 
 // Stage the n-field state (field stride np) with halo H into LDS s[f][SZ][SX].
@@ -298,21 +314,22 @@ __device__ __forceinline__ void point_F_pt(const Geo& g, const A& P, const AD& D
 // Jv (stable finite-difference form):
 //   [B(a + e b, c + e d) - B(a, c)] / e = B(a, d) + B(b, c) + e B(b, d)
 //   nu difference: (cs Delta)^2 sqrt2 (2 S:T + e T:T) / (|S + e T| + |S|)
-// Derived differences of the pair (PA = u, PB = v).
+// The pair is staged as PW = u + e v and PB = v: derivatives of u + e v are taken
+// directly, those of u as D(u + e v) - e Dv (the derivative is linear).
+// Derived differences of the pair.
 template <int W, typename T, typename A>
-__device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PA, const A& PB, T e, T ihx, T ihz, T d[5]) {
-    const T uxa = acc_dx<W>(PA, 0, ihx), uza = acc_dz<W>(PA, 0, ihz);
-    const T wxa = acc_dx<W>(PA, 1, ihx), wza = acc_dz<W>(PA, 1, ihz);
+__device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PW, const A& PB, T e, T ihx, T ihz, T d[5]) {
+    const T uxw = acc_dx<W>(PW, 0, ihx), uzw = acc_dz<W>(PW, 0, ihz);
+    const T wxw = acc_dx<W>(PW, 1, ihx), wzw = acc_dz<W>(PW, 1, ihz);
     const T uxb = acc_dx<W>(PB, 0, ihx), uzb = acc_dz<W>(PB, 0, ihz);
     const T wxb = acc_dx<W>(PB, 1, ihx), wzb = acc_dz<W>(PB, 1, ihz);
-    const T txa = acc_dx<W>(PA, 3, ihx), tza = acc_dz<W>(PA, 3, ihz);
+    const T txw = acc_dx<W>(PW, 3, ihx), tzw = acc_dz<W>(PW, 3, ihz);
     const T txb = acc_dx<W>(PB, 3, ihx), tzb = acc_dz<W>(PB, 3, ihz);
-    // strain of u (a) and of v (b)
-    const T axx = uxa, azz = wza, axz = T(0.5) * (uza + wxa);
+    // strain of u + e v (c) and of v (b), then of u (a)
+    const T cxx = uxw, czz = wzw, cxz = T(0.5) * (uzw + wxw);
     const T bxx = uxb, bzz = wzb, bxz = T(0.5) * (uzb + wxb);
+    const T axx = cxx - e * bxx, azz = czz - e * bzz, axz = cxz - e * bxz;
     const T s2a = axx * axx + azz * azz + T(2) * axz * axz;
-    // strain of u + e v
-    const T cxx = axx + e * bxx, czz = azz + e * bzz, cxz = axz + e * bxz;
     Coef<T> ka, dk = {T(0), T(0), T(0), T(0)};
     if constexpr (std::is_same<T, float>::value) {
         // FP32: hardware square root and reciprocal (1 ulp, well inside the FP32
@@ -357,36 +374,38 @@ __device__ __forceinline__ void derived_jv_pt(const Geo& g, const A& PA, const A
     d[0] = T(2) * dk.mh * (cxx - trc) + T(2) * ka.mh * (bxx - trb);
     d[1] = T(2) * dk.mv * cxz + T(2) * ka.mv * bxz;
     d[2] = T(2) * dk.mv * (czz - trc) + T(2) * ka.mv * (bzz - trb);
-    d[3] = dk.hh * (txa + e * txb) + ka.hh * txb;
-    d[4] = dk.hv * (tza + e * tzb) + ka.hv * tzb;
+    d[3] = dk.hh * txw + ka.hh * txb;
+    d[4] = dk.hv * tzw + ka.hv * tzb;
 }
 
-// Jv at a point: out = 2v/dt - dF with dF from the pair and the derived differences.
+// Jv at a point: out = 2v/dt - dF with dF from the pair (PW = u + e v, PB = v)
+// and the derived differences.
 template <int W, typename T, typename A, typename AD>
-__device__ __forceinline__ void point_jv_pt(const Geo& g, const A& PA, const A& PB, const AD& D, int gz, T e, T ihx,
+__device__ __forceinline__ void point_jv_pt(const Geo& g, const A& PW, const A& PB, const AD& D, int gz, T e, T ihx,
                                             T ihz, T o[4]) {
     const T* pbar = Bg<T>::pbar(g);
     const T* dpb = Bg<T>::dpbar(g);
-    const T uA = PA.at(0, 0, 0), wA = PA.at(1, 0, 0), pA = PA.at(2, 0, 0);
     const T uB = PB.at(0, 0, 0), wB = PB.at(1, 0, 0), pB = PB.at(2, 0, 0), tB = PB.at(3, 0, 0);
-    const T divA = acc_dx<W>(PA, 0, ihx) + acc_dz<W>(PA, 1, ihz);
+    const T uA = PW.at(0, 0, 0) - e * uB, wA = PW.at(1, 0, 0) - e * wB, pA = PW.at(2, 0, 0) - e * pB;
+    const T divW = acc_dx<W>(PW, 0, ihx) + acc_dz<W>(PW, 1, ihz);
     const T divB = acc_dx<W>(PB, 0, ihx) + acc_dz<W>(PB, 1, ihz);
     T cc[4] = {0, 0, 0, 0};
     if (g.convection) {
-        // 1/2 [ D_j(a_j phi_b + b_j phi_a + e b_j phi_b) + a_j D_j phi_b + b_j D_j phi_a + e b_j D_j phi_b ]
+        // 1/2 [ D_j(a_j phi_b + b_j phi_w) + a_j D_j phi_b + b_j D_j phi_w ],  w = a + e b
+        // (the tap values of a_j are the same for every field)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             auto px = [&](int q) {
-                return PA.at(0, 0, q) * PB.at(k, 0, q) + PB.at(0, 0, q) * (PA.at(k, 0, q) + e * PB.at(k, 0, q));
+                return (PW.at(0, 0, q) - e * PB.at(0, 0, q)) * PB.at(k, 0, q) + PB.at(0, 0, q) * PW.at(k, 0, q);
             };
             auto pz = [&](int q) {
-                return PA.at(1, q, 0) * PB.at(k, q, 0) + PB.at(1, q, 0) * (PA.at(k, q, 0) + e * PB.at(k, q, 0));
+                return (PW.at(1, q, 0) - e * PB.at(1, q, 0)) * PB.at(k, q, 0) + PB.at(1, q, 0) * PW.at(k, q, 0);
             };
             const T fx = dtaps<W>(px, ihx);
             const T fz = dtaps<W>(pz, ihz);
-            const T dAx = acc_dx<W>(PA, k, ihx), dAz = acc_dz<W>(PA, k, ihz);
+            const T dWx = acc_dx<W>(PW, k, ihx), dWz = acc_dz<W>(PW, k, ihz);
             const T dBx = acc_dx<W>(PB, k, ihx), dBz = acc_dz<W>(PB, k, ihz);
-            const T ad = uA * dBx + wA * dBz + uB * (dAx + e * dBx) + wB * (dAz + e * dBz);
+            const T ad = uA * dBx + wA * dBz + uB * dWx + wB * dWz;
             cc[k] = T(0.5) * (fx + fz + ad);
         }
     }
@@ -398,7 +417,7 @@ __device__ __forceinline__ void point_jv_pt(const Geo& g, const A& PA, const A& 
     if (g.energy_test)
         dFp = -cc[2] - T(g.kappa_cp) * divB;
     else
-        dFp = -cc[2] - wB * dpb[gz] - T(g.kappa) * ((pbar[gz] + pA) * divB + pB * divA + e * pB * divB);
+        dFp = -cc[2] - wB * dpb[gz] - T(g.kappa) * ((pbar[gz] + pA) * divB + pB * divW);
     const T dFt = acc_dx<W>(D, 3, ihx) + acc_dz<W>(D, 4, ihz) - cc[3] - T(g.beta) * wB;
     const T tdt = T(g.two_dt);
     o[0] = tdt * uB - dFu;
@@ -476,8 +495,8 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
     constexpr int SX = TX + 2 * H, SZ = TZ + 2 * H;
     constexpr int DX = TX + 2 * W, DZ = TZ + 2 * W;
     constexpr int PS = SZ * SX, DS = DZ * DX;
-    __shared__ T sa[4 * PS];
-    __shared__ T sb[4 * PS];
+    __shared__ T sa[4 * PS];   // u + e v
+    __shared__ T sb[4 * PS];   // v
     __shared__ T sd[5 * DS];
     const T ihx = T(g.idx), ihz = T(g.idz);
     const T e = T(eps_dev ? *eps_dev : eps_in);
@@ -486,7 +505,7 @@ __device__ __forceinline__ void jv_tile(const Geo& g, int x0, int z0, const T* _
         TileStage<T, TX, TZ, 4, H> st_a, st_b;
         st_a.load(g, u, x0, z0, 0);
         st_b.load(g, v, x0, z0, 0);
-        st_a.store(sa);
+        st_a.store_sum(sa, st_b, e);
         st_b.store(sb);
     }
     __syncthreads();
